@@ -1,0 +1,223 @@
+/*
+ * CPU oracle for the conformal Hough transform hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is compiled into a separate shared library that only
+ * the tests, the smoke check and the CPU-baseline leg of the benchmark load.  The product
+ * path (the HIP library) never links, loads or calls it, and the two share no code: each
+ * builds its own binning tables from the rule stated below.
+ *
+ * It is deliberately plain: one event at a time, scalar loops in the order the definitions
+ * are written, no blocking or reordering.  Floating point follows the stated FP32 rule with
+ * explicit fmaf() and is compiled with -ffp-contract=off and without fast-math, so every bin
+ * index is the one the rule defines.
+ *
+ * What is computed, and where it comes from in the paper:
+ *   conformal map (Eq. 1):            u = x/(x^2+y^2), v = y/(x^2+y^2)
+ *   Hough line map (Sec. II):         rho_ij = u_i cos(theta_j) + v_i sin(theta_j)
+ *   uniform discretisation (Sec. II): theta on [0, pi) in n_theta bins, rho on
+ *                                     [rho_min, rho_max) in n_rho bins
+ *   voting (Sec. II, Sec. III):       acc[j][k] += 1 for every hit i whose rho_ij falls in bin k
+ *   peak finding (Sec. II):           threshold plus local-maximum test in the 3x3 neighbourhood
+ *   retention (Sec. I, Sec. II):      a hit is kept when it lies within rho_window rho bins of a
+ *                                     peak at the peak's own theta
+ *
+ * Readings of points the paper leaves open (all fixed here and in the HIP library alike):
+ *   - theta_j is the lower bin edge, theta_j = (j * pi) / n_theta, evaluated in double.
+ *   - A = n_rho / (rho_max - rho_min), B = -rho_min * A (double).  The per-column constants
+ *     are C_j = (float)(A cos theta_j), S_j = (float)(A sin theta_j), Bf = (float)B, each
+ *     rounded once from double (libm cos/sin).
+ *   - a hit is valid iff r2 = fmaf(x, x, y*y) satisfies 0 < r2 <= FLT_MAX; then u = x/r2,
+ *     v = y/r2 (IEEE single division, round to nearest).  Invalid hits cast no votes and are
+ *     never kept.
+ *   - bin rule: w = fmaf(v, S_j, Bf); t = fmaf(u, C_j, w); the vote is in range iff
+ *     t >= 0 and t < n_rho (as float), and then k = (int)t.  Out-of-range votes are dropped.
+ *   - peak (j,k): acc[j][k] >= threshold, and for every 8-neighbour inside the grid,
+ *     acc[j][k] > neighbour if the neighbour precedes (j,k) in raster order (smaller j, or same
+ *     j and smaller k), otherwise acc[j][k] >= neighbour.  No wrap of theta.  Peaks are listed
+ *     in raster order.
+ *   - keep_i iff hit i is valid and some peak (jp,kp) has k_i(jp) in range with
+ *     |k_i(jp) - kp| <= rho_window, k_i(jp) computed with the bin rule above.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_PI 3.14159265358979323846
+
+/* Binning constants for the uniform (theta, rho) grid of Sec. II. */
+int oracle_tables(int n_theta, int n_rho, double rho_min, double rho_max,
+                  float *C, float *S, float *Bf)
+{
+    if (n_theta <= 0 || n_rho <= 0 || !(rho_max > rho_min)) return -1;
+    double A = (double)n_rho / (rho_max - rho_min);
+    double B = -rho_min * A;
+    for (int j = 0; j < n_theta; ++j) {
+        double theta = ((double)j * ORACLE_PI) / (double)n_theta;
+        C[j] = (float)(A * cos(theta));
+        S[j] = (float)(A * sin(theta));
+    }
+    *Bf = (float)B;
+    return 0;
+}
+
+/* Eq. (1): conformal map.  Returns 1 for a valid hit, 0 otherwise. */
+int oracle_conformal(float x, float y, float *u, float *v)
+{
+    float y2 = y * y;
+    float r2 = fmaf(x, x, y2);
+    if (!(r2 > 0.0f && r2 <= FLT_MAX)) { *u = 0.0f; *v = 0.0f; return 0; }
+    *u = x / r2;
+    *v = y / r2;
+    return 1;
+}
+
+/* rho = u cos(theta_j) + v sin(theta_j), scaled to bin units and floored.  -1 if out of range. */
+int oracle_rho_bin(float u, float v, float Cj, float Sj, float Bf, int n_rho)
+{
+    float w = fmaf(v, Sj, Bf);
+    float t = fmaf(u, Cj, w);
+    if (t >= 0.0f && t < (float)n_rho) return (int)t;
+    return -1;
+}
+
+/* The binned parameter matrix of Sec. III: bins[i*n_theta + j] = bin of rho_ij, or -1 when the
+ * hit is invalid or rho_ij falls outside [rho_min, rho_max).  Used by the tests. */
+void oracle_bins(int n_theta, int n_rho, const float *C, const float *S, float Bf,
+                 const float *x, const float *y, long n_hits, int32_t *bins)
+{
+    for (long i = 0; i < n_hits; ++i) {
+        float u, v;
+        int ok = oracle_conformal(x[i], y[i], &u, &v);
+        for (int j = 0; j < n_theta; ++j)
+            bins[(size_t)i * n_theta + j] = ok ? oracle_rho_bin(u, v, C[j], S[j], Bf, n_rho) : -1;
+    }
+}
+
+/* Voting: acc[j*n_rho + k] counts the hits whose rho at theta_j falls in bin k. */
+void oracle_vote(int n_theta, int n_rho, const float *C, const float *S, float Bf,
+                 const float *x, const float *y, long n_hits, int32_t *acc)
+{
+    memset(acc, 0, sizeof(int32_t) * (size_t)n_theta * (size_t)n_rho);
+    for (long i = 0; i < n_hits; ++i) {
+        float u, v;
+        if (!oracle_conformal(x[i], y[i], &u, &v)) continue;
+        for (int j = 0; j < n_theta; ++j) {
+            int k = oracle_rho_bin(u, v, C[j], S[j], Bf, n_rho);
+            if (k >= 0) acc[(size_t)j * n_rho + k] += 1;
+        }
+    }
+}
+
+/* Is cell (j,k) a peak?  Threshold plus the 3x3 local-maximum test with the raster tie rule. */
+int oracle_is_peak(const int32_t *acc, int n_theta, int n_rho, int threshold, int j, int k)
+{
+    int32_t c = acc[(size_t)j * n_rho + k];
+    if (c < threshold) return 0;
+    for (int dj = -1; dj <= 1; ++dj) {
+        for (int dk = -1; dk <= 1; ++dk) {
+            if (dj == 0 && dk == 0) continue;
+            int jn = j + dj, kn = k + dk;
+            if (jn < 0 || jn >= n_theta || kn < 0 || kn >= n_rho) continue;
+            int32_t n = acc[(size_t)jn * n_rho + kn];
+            int precedes = (dj < 0) || (dj == 0 && dk < 0);
+            if (precedes) { if (!(c > n)) return 0; }
+            else          { if (!(c >= n)) return 0; }
+        }
+    }
+    return 1;
+}
+
+/* Peak list in raster order.  Writes at most cap entries, returns the true number of peaks. */
+long oracle_peaks(const int32_t *acc, int n_theta, int n_rho, int threshold,
+                  int32_t *pj, int32_t *pk, int32_t *pc, long cap)
+{
+    long n = 0;
+    for (int j = 0; j < n_theta; ++j)
+        for (int k = 0; k < n_rho; ++k)
+            if (oracle_is_peak(acc, n_theta, n_rho, threshold, j, k)) {
+                if (n < cap) { pj[n] = j; pk[n] = k; pc[n] = acc[(size_t)j * n_rho + k]; }
+                ++n;
+            }
+    return n;
+}
+
+/* Retention mask: keep_i = 1 iff hit i is within rho_window bins of a peak at the peak's theta. */
+void oracle_retain(int n_rho, const float *C, const float *S, float Bf, int rho_window,
+                   const float *x, const float *y, long n_hits,
+                   const int32_t *pj, const int32_t *pk, long n_peaks, uint8_t *keep)
+{
+    for (long i = 0; i < n_hits; ++i) {
+        float u, v;
+        keep[i] = 0;
+        if (!oracle_conformal(x[i], y[i], &u, &v)) continue;
+        for (long p = 0; p < n_peaks; ++p) {
+            int k = oracle_rho_bin(u, v, C[pj[p]], S[pj[p]], Bf, n_rho);
+            if (k < 0) continue;
+            int d = k - pk[p];
+            if (d < 0) d = -d;
+            if (d <= rho_window) { keep[i] = 1; break; }
+        }
+    }
+}
+
+/*
+ * Whole hot path over CSR-packed events: per event vote, find all peaks, keep hits near any
+ * of them, and return the first `cap` peaks of each event (raster order) with the true count.
+ * Events are independent (Sec. III), so they are spread over n_threads OpenMP threads; each
+ * event is still computed by the plain single-event routines above.
+ * peaks_out holds cap triples (j, k, count) per event.  Returns 0, or -1 on allocation failure.
+ */
+int oracle_run_batch(int n_theta, int n_rho, double rho_min, double rho_max, int threshold,
+                     int rho_window, const float *x, const float *y, const uint32_t *offsets,
+                     long n_events, long cap, int32_t *peaks_out, int64_t *n_peaks_out,
+                     uint8_t *keep, int n_threads)
+{
+    float *C = (float *)malloc(sizeof(float) * (size_t)n_theta);
+    float *S = (float *)malloc(sizeof(float) * (size_t)n_theta);
+    float Bf;
+    int failed = 0;
+    if (!C || !S || oracle_tables(n_theta, n_rho, rho_min, rho_max, C, S, &Bf) != 0) {
+        free(C); free(S); return -1;
+    }
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+    for (long e = 0; e < n_events; ++e) {
+        long a = offsets[e], h = (long)offsets[e + 1] - (long)offsets[e];
+        long max_p = (long)n_theta * n_rho;
+        int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * (size_t)max_p);
+        int32_t *pj = (int32_t *)malloc(sizeof(int32_t) * (size_t)max_p);
+        int32_t *pk = (int32_t *)malloc(sizeof(int32_t) * (size_t)max_p);
+        int32_t *pc = (int32_t *)malloc(sizeof(int32_t) * (size_t)max_p);
+        if (!acc || !pj || !pk || !pc) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+            oracle_vote(n_theta, n_rho, C, S, Bf, x + a, y + a, h, acc);
+            long np = oracle_peaks(acc, n_theta, n_rho, threshold, pj, pk, pc, max_p);
+            oracle_retain(n_rho, C, S, Bf, rho_window, x + a, y + a, h, pj, pk, np, keep + a);
+            n_peaks_out[e] = np;
+            for (long p = 0; p < np && p < cap; ++p) {
+                peaks_out[(e * cap + p) * 3 + 0] = pj[p];
+                peaks_out[(e * cap + p) * 3 + 1] = pk[p];
+                peaks_out[(e * cap + p) * 3 + 2] = pc[p];
+            }
+        }
+        free(acc); free(pj); free(pk); free(pc);
+    }
+    free(C); free(S);
+    return failed ? -1 : 0;
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,183 @@
+"""Python access to the CPU oracle (oracle/hough_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the benchmark's CPU
+baseline leg.  The product path never imports this module.  It shares no code with the HIP
+library: the C file builds its own tables and applies the binning rule itself.
+
+The functions mirror the steps of the method (see the C file's header for the rules):
+  Grid        uniform (theta, rho) discretisation constants (Sec. II)
+  conformal() Eq. (1)
+  rho_bin()   the bin index of rho = u cos(theta_j) + v sin(theta_j) for one hit and column (Sec. II)
+  bins()      the same for every hit and column: the binned parameter matrix R of Sec. III
+  vote()      accumulator (Sec. II, Sec. III)
+  peaks()     threshold + 3x3 local maxima in raster order (Sec. II)
+  retain()    per-hit keep mask (Sec. I, Sec. II)
+  run_batch() all of the above over CSR-packed events
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hough_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+GCC_FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+             "-fopenmp", "-Wall", "-Wextra"]
+
+
+def build(out: str = _LIB, extra_flags=()) -> str:
+    """Compile the oracle with gcc (always recompiles)."""
+    cmd = ["gcc", *GCC_FLAGS, *extra_flags, "-o", out, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+_lib = None
+
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        c_int, c_long, c_double, c_float = ctypes.c_int, ctypes.c_long, ctypes.c_double, ctypes.c_float
+        L.oracle_tables.argtypes = [c_int, c_int, c_double, c_double, _f32p, _f32p, ctypes.POINTER(c_float)]
+        L.oracle_tables.restype = c_int
+        L.oracle_conformal.argtypes = [c_float, c_float, ctypes.POINTER(c_float), ctypes.POINTER(c_float)]
+        L.oracle_conformal.restype = c_int
+        L.oracle_rho_bin.argtypes = [c_float, c_float, c_float, c_float, c_float, c_int]
+        L.oracle_rho_bin.restype = c_int
+        L.oracle_bins.argtypes = [c_int, c_int, _f32p, _f32p, c_float, _f32p, _f32p, c_long, _i32p]
+        L.oracle_bins.restype = None
+        L.oracle_vote.argtypes = [c_int, c_int, _f32p, _f32p, c_float, _f32p, _f32p, c_long, _i32p]
+        L.oracle_vote.restype = None
+        L.oracle_is_peak.argtypes = [_i32p, c_int, c_int, c_int, c_int, c_int]
+        L.oracle_is_peak.restype = c_int
+        L.oracle_peaks.argtypes = [_i32p, c_int, c_int, c_int, _i32p, _i32p, _i32p, c_long]
+        L.oracle_peaks.restype = c_long
+        L.oracle_retain.argtypes = [c_int, _f32p, _f32p, c_float, c_int, _f32p, _f32p, c_long,
+                                    _i32p, _i32p, c_long, _u8p]
+        L.oracle_retain.restype = None
+        L.oracle_run_batch.argtypes = [c_int, c_int, c_double, c_double, c_int, c_int, _f32p, _f32p,
+                                       _u32p, c_long, c_long, _i32p, _i64p, _u8p, c_int]
+        L.oracle_run_batch.restype = c_int
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = c_int
+        _lib = L
+    return _lib
+
+
+class Grid:
+    """The (theta, rho) grid and its binning constants, as the oracle computes them."""
+
+    def __init__(self, n_theta: int, n_rho: int, rho_min: float, rho_max: float):
+        self.n_theta, self.n_rho = int(n_theta), int(n_rho)
+        self.rho_min, self.rho_max = float(rho_min), float(rho_max)
+        self.C = np.zeros(self.n_theta, np.float32)
+        self.S = np.zeros(self.n_theta, np.float32)
+        b = ctypes.c_float()
+        if lib().oracle_tables(self.n_theta, self.n_rho, self.rho_min, self.rho_max, self.C, self.S,
+                               ctypes.byref(b)) != 0:
+            raise ValueError("invalid grid")
+        self.B = np.float32(b.value)
+
+    @classmethod
+    def of(cls, wl) -> "Grid":
+        return cls(wl.n_theta, wl.n_rho, wl.rho_min, wl.rho_max)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def conformal(x: float, y: float):
+    """Eq. (1) for one hit: (valid, u, v)."""
+    u, v = ctypes.c_float(), ctypes.c_float()
+    ok = lib().oracle_conformal(float(np.float32(x)), float(np.float32(y)), ctypes.byref(u), ctypes.byref(v))
+    return bool(ok), np.float32(u.value), np.float32(v.value)
+
+
+def rho_bin(g: Grid, u, v, j: int) -> int:
+    return int(lib().oracle_rho_bin(float(u), float(v), float(g.C[j]), float(g.S[j]), float(g.B), g.n_rho))
+
+
+def bins(g: Grid, x, y) -> np.ndarray:
+    """Bin index of rho_ij for every hit i and column j ([H, n_theta]; -1 = no vote)."""
+    x, y = _f32(x), _f32(y)
+    out = np.zeros((x.size, g.n_theta), np.int32)
+    if x.size:
+        lib().oracle_bins(g.n_theta, g.n_rho, g.C, g.S, float(g.B), x, y, x.size, out)
+    return out
+
+
+def vote(g: Grid, x, y) -> np.ndarray:
+    x, y = _f32(x), _f32(y)
+    acc = np.zeros((g.n_theta, g.n_rho), np.int32)
+    lib().oracle_vote(g.n_theta, g.n_rho, g.C, g.S, float(g.B), x, y, x.size, acc)
+    return acc
+
+
+def peaks(acc: np.ndarray, threshold: int, cap: int | None = None):
+    """All peaks (or the first `cap`) in raster order: (j, k, count) arrays and the true count."""
+    acc = np.ascontiguousarray(acc, dtype=np.int32)
+    nt, nr = acc.shape
+    cap = nt * nr if cap is None else int(cap)
+    pj = np.zeros(max(cap, 1), np.int32); pk = np.zeros_like(pj); pc = np.zeros_like(pj)
+    n = int(lib().oracle_peaks(acc, nt, nr, int(threshold), pj, pk, pc, cap))
+    m = min(n, cap)
+    return pj[:m].copy(), pk[:m].copy(), pc[:m].copy(), n
+
+
+def is_peak(acc: np.ndarray, threshold: int, j: int, k: int) -> bool:
+    acc = np.ascontiguousarray(acc, dtype=np.int32)
+    return bool(lib().oracle_is_peak(acc, acc.shape[0], acc.shape[1], int(threshold), int(j), int(k)))
+
+
+def retain(g: Grid, x, y, pj, pk, rho_window: int = 1) -> np.ndarray:
+    x, y = _f32(x), _f32(y)
+    pj = np.ascontiguousarray(pj, np.int32); pk = np.ascontiguousarray(pk, np.int32)
+    keep = np.zeros(x.size, np.uint8)
+    lib().oracle_retain(g.n_rho, g.C, g.S, float(g.B), int(rho_window), x, y, x.size, pj, pk, pj.size, keep)
+    return keep
+
+
+def run_batch(wl_or_grid, x, y, offsets, threshold: int | None = None, rho_window: int | None = None,
+              cap: int = 4096, n_threads: int = 1):
+    """Whole path over CSR events.  Returns (peaks[E, cap, 3] as (j, k, count), n_peaks[E], keep[H])."""
+    if isinstance(wl_or_grid, Grid):
+        g = wl_or_grid
+        if threshold is None or rho_window is None:
+            raise ValueError("threshold and rho_window are required with a Grid")
+    else:
+        wl = wl_or_grid
+        g = Grid.of(wl)
+        threshold = wl.threshold if threshold is None else threshold
+        rho_window = wl.rho_window if rho_window is None else rho_window
+    x, y = _f32(x), _f32(y)
+    offsets = np.ascontiguousarray(offsets, np.uint32)
+    E = offsets.size - 1
+    out = np.zeros((max(E, 1), max(cap, 1), 3), np.int32)
+    n_peaks = np.zeros(max(E, 1), np.int64)
+    keep = np.zeros(max(x.size, 1), np.uint8)
+    rc = lib().oracle_run_batch(g.n_theta, g.n_rho, g.rho_min, g.rho_max, int(threshold), int(rho_window),
+                                x if x.size else np.zeros(1, np.float32), y if y.size else np.zeros(1, np.float32),
+                                offsets, E, int(cap), out, n_peaks, keep, int(n_threads))
+    if rc != 0:
+        raise MemoryError("oracle_run_batch failed")
+    return out[:E], n_peaks[:E], keep[:x.size]
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())

@@ -1,0 +1,443 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test fixes part of the oracle to something independent: exact rational arithmetic
+(IEEE rounding done by hand), the mathematics of the conformal map and of circles through
+the origin, brute force over tiny inputs written as separate code, the paper's printed grid
+constants, and invariants of the accumulator.  A dropped term, a wrong sign or index, or a
+transposed operand in the oracle fails at least one of them.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from tests import exact_fp32 as X
+from paper_2607_04067_amd import synth
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# ----------------------------------------------------------------------------- helper pins
+def test_exact_helper_matches_ieee_hardware():
+    """The rational helper rounds like IEEE binary32 (numpy float32 mul/div/add are IEEE)."""
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal(2000).astype(np.float32) * np.float32(1e3)
+    b = rng.standard_normal(2000).astype(np.float32) * np.float32(1e-3)
+    for p, q in zip(a, b):
+        assert X.to32(X.mul(p, q)) == np.float32(p) * np.float32(q)
+        assert X.to32(X.div(p, q)) == np.float32(p) / np.float32(q)
+        assert X.to32(X.rn32(X.f(p) + X.f(q))) == np.float32(p) + np.float32(q)
+
+
+# ----------------------------------------------------------------------- Eq. (1) conformal
+def test_conformal_powers_of_two_exact(orc):
+    for m in range(-10, 12):
+        ok, u, v = orc.conformal(2.0 ** m, 0.0)
+        assert ok and u == np.float32(2.0 ** -m) and v == 0.0
+        ok, u, v = orc.conformal(0.0, 2.0 ** m)
+        assert ok and u == 0.0 and v == np.float32(2.0 ** -m)
+
+
+def test_conformal_matches_exact_rounding_and_fp64(orc):
+    x, y = synth.random_hits(400, seed=3, r_lo=1.0, r_hi=2000.0)
+    for xi, yi in zip(x, y):
+        ok, u, v = orc.conformal(xi, yi)
+        assert ok
+        r2 = X.fma(xi, xi, X.to32(X.mul(yi, yi)))
+        assert u == X.to32(X.div(xi, X.to32(r2)))
+        assert v == X.to32(X.div(yi, X.to32(r2)))
+        # and u, v are within a few ulp of the exact Eq. (1) values
+        d = float(xi) ** 2 + float(yi) ** 2
+        assert abs(float(u) - float(xi) / d) <= 2.0 ** -21 * abs(float(xi) / d) + 1e-45
+        assert abs(float(v) - float(yi) / d) <= 2.0 ** -21 * abs(float(yi) / d) + 1e-45
+        # odd symmetry of the map
+        ok2, u2, v2 = orc.conformal(-xi, -yi)
+        assert ok2 and u2 == -u and v2 == -v
+
+
+@pytest.mark.parametrize("x,y", [(0.0, 0.0), (float("nan"), 1.0), (1.0, float("inf")),
+                                 (1e20, 0.0), (0.0, -1e-23)])
+def test_conformal_invalid_hits(orc, x, y):
+    ok, _, _ = orc.conformal(x, y)
+    assert not ok
+
+
+def test_circle_through_origin_maps_to_line(orc):
+    """Circles through the origin become lines a*u + b*v = 1/2 (the geometry behind Eq. 1)."""
+    for a_ang, radius in [(0.3, 500.0), (2.0, 250.0), (-1.2, 1500.0), (3.0, 120.0)]:
+        px, py = synth.circle_points(a_ang, radius, np.linspace(10.0, 1.9 * radius, 40))
+        a, b = radius * math.cos(a_ang), radius * math.sin(a_ang)
+        for xi, yi in zip(px.astype(np.float32), py.astype(np.float32)):
+            ok, u, v = orc.conformal(xi, yi)
+            assert ok
+            assert abs(a * float(u) + b * float(v) - 0.5) < 5e-4
+
+
+# ------------------------------------------------------------------------- grid constants
+def test_paper_grid_constants(orc):
+    """Sec. II: rho on [-0.01, 0.01] in 1000 bins (d_rho = 2e-5); theta on [0, pi) in 1000 bins."""
+    g = orc.Grid(1000, 1000, -0.01, 0.01)
+    # C_0 = A cos 0 = A = 1/d_rho and S_0 = 0 exactly; B = -rho_min * A = 500
+    assert g.C[0] == np.float32(1.0 / 2e-5) == np.float32(50000.0)
+    assert g.S[0] == 0.0 and g.B == np.float32(500.0)
+    # theta_500 = pi/2: S = A exactly, C tiny
+    assert g.S[500] == np.float32(50000.0) and abs(float(g.C[500])) < 1e-9
+    # consecutive columns are pi/1000 apart: C_j = A cos(j pi/1000) to within half an f32 ulp
+    j = np.arange(1000)
+    ref = 50000.0 * np.cos(j * math.pi / 1000.0)
+    assert np.all(np.abs(g.C.astype(np.float64) - ref) <= np.spacing(np.abs(g.C)).astype(np.float64) * 0.5 + 1e-9)
+    ref = 50000.0 * np.sin(j * math.pi / 1000.0)
+    assert np.all(np.abs(g.S.astype(np.float64) - ref) <= np.spacing(np.abs(g.S)).astype(np.float64) * 0.5 + 1e-9)
+
+
+@pytest.mark.parametrize("name,A,B", [("plain-16ev-180x128", 12800.0, 64.0),
+                                      ("paper-1000ev-360x256", 25600.0, 128.0),
+                                      ("dense-2000ev-720x512", 51200.0, 256.0)])
+def test_workload_grid_constants(orc, name, A, B):
+    wl = synth.WORKLOADS[name]
+    g = orc.Grid.of(wl)
+    assert g.C[0] == np.float32(A) and g.S[0] == 0.0 and g.B == np.float32(B)
+    assert np.all(g.S >= 0)                       # theta in [0, pi)
+    assert np.all(np.diff(g.C) < 0)               # cos decreasing on [0, pi)
+
+
+# -------------------------------------------------------------------------- the bin rule
+def test_bin_column_zero_closed_form(orc):
+    """At theta_0 = 0: C_0 = A, S_0 = 0, so t = RN(u*A + B) and k = floor(t)."""
+    g = orc.Grid(180, 128, -1 / 200, 1 / 200)
+    x, y = synth.random_hits(500, seed=5, r_lo=150.0, r_hi=900.0)
+    b = orc.bins(g, x, y)
+    for i, (xi, yi) in enumerate(zip(x, y)):
+        ok, u, v = orc.conformal(xi, yi)
+        t = X.rn32(X.f(u) * Fraction(12800) + Fraction(64))
+        k = math.floor(t) if (t >= 0 and t < 128) else -1
+        assert b[i, 0] == k
+
+
+def test_bin_rule_exact_all_columns(orc):
+    """Every column: t = RN(u*C_j + RN(v*S_j + B)), in range iff 0 <= t < n_rho, k = floor(t)."""
+    g = orc.Grid(37, 64, -0.004, 0.0045)
+    x, y = synth.random_hits(40, seed=6, r_lo=120.0, r_hi=900.0)
+    b = orc.bins(g, x, y)
+    for i, (xi, yi) in enumerate(zip(x, y)):
+        ok, u, v = orc.conformal(xi, yi)
+        for j in range(g.n_theta):
+            w = X.fma(v, g.S[j], g.B)
+            t = X.fma(u, g.C[j], X.to32(w))
+            k = math.floor(t) if (t >= 0 and t < g.n_rho) else -1
+            assert b[i, j] == k, (i, j)
+
+
+def _fp64_rebin_check(orc, g, x, y, rel_tol=1e-5):
+    """Bins from the exact rho (float64 from the float32 hits) may differ from the FP32 rule
+    only for votes whose exact position lies within rel_tol*(rho_max-rho_min) of a bin edge."""
+    b = orc.bins(g, x, y).astype(np.int64)
+    xd, yd = x.astype(np.float64), y.astype(np.float64)
+    d = xd * xd + yd * yd
+    theta = (np.arange(g.n_theta) * math.pi) / g.n_theta
+    rho = (xd[:, None] * np.cos(theta)[None, :] + yd[:, None] * np.sin(theta)[None, :]) / d[:, None]
+    t64 = (rho - g.rho_min) * (g.n_rho / (g.rho_max - g.rho_min))
+    k64 = np.where((t64 >= 0) & (t64 < g.n_rho), np.floor(t64), -1).astype(np.int64)
+    bad = b != k64
+    edge_dist = np.abs(t64 - np.round(t64))           # distance to the nearest edge, in bins
+    tol_bins = rel_tol * g.n_rho
+    assert np.all(edge_dist[bad] <= tol_bins), (edge_dist[bad].max(), tol_bins)
+    # where they differ they differ by one bin (or one side is just out of range)
+    assert np.all((np.abs(b[bad] - k64[bad]) == 1) | (b[bad] == -1) | (k64[bad] == -1))
+    return int(bad.sum()), int(b.size), float(edge_dist[bad].max()) if bad.any() else 0.0
+
+
+@pytest.mark.parametrize("name,n_events", [("plain-16ev-180x128", 16), ("paper-1000ev-360x256", 6),
+                                           ("dense-2000ev-720x512", 2)])
+def test_fp64_rebinning(orc, name, n_events):
+    wl = synth.WORKLOADS[name]
+    ev = synth.make_events(wl, 0, n_events=n_events)
+    n_bad, n_all, worst = _fp64_rebin_check(orc, orc.Grid.of(wl), ev.x, ev.y)
+    assert n_bad <= 1e-4 * n_all
+
+
+def test_fp64_rebinning_random_annulus(orc):
+    g = orc.Grid(360, 256, -1 / 200, 1 / 200)
+    x, y = synth.random_hits(3000, seed=9, r_lo=150.0, r_hi=1000.0)   # includes out-of-range rho
+    _fp64_rebin_check(orc, g, x, y)
+
+
+# ------------------------------------------------------- closed-form track (a1 + a2 + a3)
+def _track_for_cell(g, j, k):
+    """Circle through the origin whose line passes through the centre of cell (j, k)."""
+    theta = (j * math.pi) / g.n_theta
+    rho = g.rho_min + (k + 0.5) * (g.rho_max - g.rho_min) / g.n_rho
+    radius = 1.0 / (2.0 * abs(rho))
+    centre_angle = theta if rho > 0 else theta + math.pi
+    radii = synth.layer_radii()
+    radii = radii[radii <= 2.0 * radius * (1 - 1e-9)]
+    px, py = synth.circle_points(centre_angle, radius, radii)
+    return px.astype(np.float32), py.astype(np.float32)
+
+
+@pytest.mark.parametrize("name", ["plain-16ev-180x128", "paper-1000ev-360x256", "dense-2000ev-720x512"])
+def test_single_track_peaks_at_its_cell(orc, name):
+    """A noiseless circle with centre (a, b) through the origin satisfies
+    u cos(phi) + v sin(phi) = 1/(2R), phi = atan2(b, a): all its hits vote for that cell."""
+    wl = synth.WORKLOADS[name]
+    g = orc.Grid.of(wl)
+    rng = np.random.default_rng(11)
+    for _ in range(6):
+        j = int(rng.integers(3, g.n_theta - 3))
+        k = int(rng.integers(g.n_rho // 4, 3 * g.n_rho // 4))
+        if k == g.n_rho // 2 - 1 or k == g.n_rho // 2:
+            continue
+        x, y = _track_for_cell(g, j, k)
+        n = x.size
+        acc = orc.vote(g, x, y)
+        assert acc[j, k] == n
+        others = acc.copy(); others[j, k] = -1
+        assert others.max() < n                       # the unique maximum
+        assert orc.is_peak(acc, 2, j, k)
+        pj, pk, pc, npk = orc.peaks(acc, n)           # threshold at N: exactly this peak
+        assert npk == 1 and (pj[0], pk[0], pc[0]) == (j, k, n)
+        assert orc.retain(g, x, y, pj, pk, 0).all()   # every hit sits in the peak's own bin
+
+
+def test_random_track_max_within_one_bin(orc):
+    g = orc.Grid(360, 256, -1 / 200, 1 / 200)
+    rng = np.random.default_rng(12)
+    dtheta = math.pi / g.n_theta
+    for _ in range(20):
+        radius = float(rng.uniform(150.0, 3000.0))
+        phi_c = float(rng.uniform(-math.pi, math.pi))
+        radii = synth.layer_radii(); radii = radii[radii <= 2 * radius * (1 - 1e-9)]
+        px, py = synth.circle_points(phi_c, radius, radii)
+        acc = orc.vote(g, px.astype(np.float32), py.astype(np.float32))
+        theta_star, rho_star = (phi_c, 1 / (2 * radius)) if phi_c >= 0 else (phi_c + math.pi, -1 / (2 * radius))
+        if theta_star < 3 * dtheta or theta_star > math.pi - 3 * dtheta:
+            continue
+        j, k = np.unravel_index(np.argmax(acc), acc.shape)
+        t_star = (rho_star - g.rho_min) * g.n_rho / (g.rho_max - g.rho_min)
+        assert abs(j - theta_star / dtheta) <= 1.0 + 1e-9
+        assert abs(k - math.floor(t_star)) <= 1
+
+
+# --------------------------------------------------------------------- brute force, tiny
+def _brute_bins(g, x, y):
+    out = np.full((len(x), g.n_theta), -1, np.int64)
+    for i, (xi, yi) in enumerate(zip(x, y)):
+        r2 = X.fma(xi, xi, X.to32(X.mul(yi, yi)))
+        if not (r2 > 0 and r2 <= X._MAXF):
+            continue
+        u, v = X.to32(X.div(xi, X.to32(r2))), X.to32(X.div(yi, X.to32(r2)))
+        for j in range(g.n_theta):
+            t = X.fma(u, g.C[j], X.to32(X.fma(v, g.S[j], g.B)))
+            if 0 <= t < g.n_rho:
+                out[i, j] = math.floor(t)
+    return out
+
+
+def _brute_acc(g, kb):
+    """Cell-major recount: acc[j][k] = #{i : k_i(j) = k}."""
+    acc = np.zeros((g.n_theta, g.n_rho), np.int64)
+    for j in range(g.n_theta):
+        for k in range(g.n_rho):
+            acc[j, k] = int(np.sum(kb[:, j] == k))
+    return acc
+
+
+def _brute_peaks(acc, T):
+    nt, nr = acc.shape
+    key = lambda j, k: j * nr + k
+    out = []
+    for j in range(nt):
+        for k in range(nr):
+            c = acc[j, k]
+            if c < T:
+                continue
+            good = True
+            for jn, kn in [(j - 1, k - 1), (j - 1, k), (j - 1, k + 1), (j, k - 1),
+                           (j, k + 1), (j + 1, k - 1), (j + 1, k), (j + 1, k + 1)]:
+                if not (0 <= jn < nt and 0 <= kn < nr):
+                    continue
+                n = acc[jn, kn]
+                good &= (c > n) if key(jn, kn) < key(j, k) else (c >= n)
+            if good:
+                out.append((j, k, int(c)))
+    return out
+
+
+def _brute_keep(kb, plist, W):
+    keep = np.zeros(kb.shape[0], np.uint8)
+    for i in range(kb.shape[0]):
+        for (j, k, _) in plist:
+            if kb[i, j] >= 0 and abs(int(kb[i, j]) - k) <= W:
+                keep[i] = 1
+    return keep
+
+
+def test_brute_force_tiny_events(orc):
+    rng = np.random.default_rng(13)
+    for trial in range(120):
+        nt, nr = int(rng.integers(1, 17)), int(rng.integers(1, 17))
+        lo = float(rng.uniform(-0.006, -0.001)); hi = float(rng.uniform(0.001, 0.006))
+        g = orc.Grid(nt, nr, lo, hi)
+        n = int(rng.integers(0, 9))
+        x, y = synth.random_hits(n, seed=1000 + trial, r_lo=120.0, r_hi=900.0)
+        if n and trial % 5 == 0:      # duplicates and an invalid hit
+            x = np.concatenate([x, x[:1], np.float32([0.0])]); y = np.concatenate([y, y[:1], np.float32([0.0])])
+        kb = _brute_bins(g, x, y)
+        assert np.array_equal(orc.bins(g, x, y), kb)
+        acc = orc.vote(g, x, y)
+        assert np.array_equal(acc, _brute_acc(g, kb))
+        T = int(rng.integers(1, 4))
+        pj, pk, pc, npk = orc.peaks(acc, T)
+        ref = _brute_peaks(acc, T)
+        assert npk == len(ref) and list(zip(pj.tolist(), pk.tolist(), pc.tolist())) == ref
+        W = int(rng.integers(0, 3))
+        assert np.array_equal(orc.retain(g, x, y, pj, pk, W), _brute_keep(kb, ref, W))
+
+
+# ----------------------------------------------------------- peak rule on injected grids
+def _peaks_of(orc, grid, T):
+    pj, pk, pc, n = orc.peaks(np.array(grid, np.int32), T)
+    return list(zip(pj.tolist(), pk.tolist()))
+
+
+def test_peak_plateaus_keep_first_cell_in_raster_order(orc):
+    g = np.zeros((5, 6), np.int32)
+    g[2, 2] = g[2, 3] = 9                     # horizontal pair
+    assert _peaks_of(orc, g, 1) == [(2, 2)]
+    g = np.zeros((5, 6), np.int32)
+    g[1, 3] = g[2, 3] = 9                     # vertical pair (smaller j first)
+    assert _peaks_of(orc, g, 1) == [(1, 3)]
+    g = np.zeros((5, 6), np.int32)
+    g[1, 4] = g[2, 3] = 9                     # anti-diagonal pair
+    assert _peaks_of(orc, g, 1) == [(1, 4)]
+    g = np.zeros((6, 6), np.int32)
+    g[1:4, 1:4] = 7                           # flat 3x3 plateau
+    assert _peaks_of(orc, g, 1) == [(1, 1)]
+    g = np.zeros((6, 6), np.int32)
+    g[2, 2] = g[3, 2] = g[3, 3] = g[3, 4] = 5  # L-shape
+    assert _peaks_of(orc, g, 1) == [(2, 2)]
+
+
+def test_peak_test_is_local_to_the_3x3_window(orc):
+    g = np.zeros((5, 6), np.int32)
+    g[2, 1] = g[2, 2] = 6
+    g[3, 3] = 8          # higher cell inside the window of (2,2) but outside that of (2,1)
+    assert _peaks_of(orc, g, 1) == [(2, 1), (3, 3)]
+    g[3, 2] = 8          # now also inside the window of (2,1): the plateau has no peak
+    assert _peaks_of(orc, g, 1) == [(3, 2)]
+
+
+def test_peak_edges_corners_and_threshold(orc):
+    g = np.zeros((4, 5), np.int32)
+    g[0, 0] = 3; g[0, 4] = 3; g[3, 0] = 3; g[3, 4] = 4; g[1, 2] = 2
+    assert _peaks_of(orc, g, 3) == [(0, 0), (0, 4), (3, 0), (3, 4)]   # corners count, no wrap
+    assert _peaks_of(orc, g, 4) == [(3, 4)]                          # count = T-1 is not a peak
+    assert _peaks_of(orc, g, 2) == [(0, 0), (0, 4), (1, 2), (3, 0), (3, 4)]
+    assert _peaks_of(orc, np.zeros((3, 3), np.int32), 1) == []
+    # theta does not wrap: (0,k) and (n-1, n_rho-1-k) are not neighbours
+    g = np.zeros((4, 4), np.int32); g[0, 1] = 5; g[3, 2] = 5
+    assert _peaks_of(orc, g, 1) == [(0, 1), (3, 2)]
+
+
+def test_peak_invariants_on_events(orc):
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 0, n_events=2)
+    for e in range(2):
+        acc = orc.vote(g, *ev.event(e))
+        pj, pk, pc, n = orc.peaks(acc, wl.threshold)
+        assert np.all(pc >= wl.threshold) and np.all(acc[pj, pk] == pc)
+        order = pj.astype(np.int64) * g.n_rho + pk
+        assert np.all(np.diff(order) > 0)                       # raster order
+        s = set(zip(pj.tolist(), pk.tolist()))
+        for j, k in s:                                          # no two 8-adjacent peaks
+            for dj in (-1, 0, 1):
+                for dk in (-1, 0, 1):
+                    if (dj or dk) and (j + dj, k + dk) in s:
+                        raise AssertionError("adjacent peaks")
+        # the global maximum cell's plateau contributes a peak: the raster-first maximum is one
+        jm, km = np.unravel_index(np.argmax(acc), acc.shape)
+        assert (jm, km) in s
+
+
+# ------------------------------------------------------------------ voting invariants
+def test_vote_conservation_and_single_hits(orc):
+    wl = synth.WORKLOADS["plain-16ev-180x128"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 0, n_events=3)
+    for e in range(3):
+        x, y = ev.event(e)
+        acc = orc.vote(g, x, y)
+        kb = orc.bins(g, x, y)
+        assert acc.sum() == int((kb >= 0).sum())
+    x, y = synth.random_hits(5, seed=21, r_lo=150, r_hi=900)
+    for i in range(5):
+        acc = orc.vote(g, x[i:i + 1], y[i:i + 1])
+        kb = orc.bins(g, x[i:i + 1], y[i:i + 1])[0]
+        assert np.all(acc.sum(axis=1) == (kb >= 0))
+        assert np.all(acc[np.arange(g.n_theta)[kb >= 0], kb[kb >= 0]] == 1)
+
+
+def test_permutation_invariance(orc):
+    wl = synth.WORKLOADS["plain-16ev-180x128"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 0, n_events=1)
+    x, y = ev.event(0)
+    perm = np.random.default_rng(4).permutation(x.size)
+    a1, a2 = orc.vote(g, x, y), orc.vote(g, x[perm], y[perm])
+    assert np.array_equal(a1, a2)
+    p1 = orc.peaks(a1, 20); p2 = orc.peaks(a2, 20)
+    assert all(np.array_equal(u, v) for u, v in zip(p1[:3], p2[:3]))
+    k1 = orc.retain(g, x, y, p1[0], p1[1], 1); k2 = orc.retain(g, x[perm], y[perm], p2[0], p2[1], 1)
+    assert np.array_equal(k1[perm], k2)
+
+
+def test_keep_monotone_in_threshold_and_window(orc):
+    wl = synth.WORKLOADS["plain-16ev-180x128"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 0, n_events=2)
+    for e in range(2):
+        x, y = ev.event(e)
+        acc = orc.vote(g, x, y)
+        prev = None
+        for T in [8, 14, 20, 26, 34, 60]:
+            pj, pk, _, _ = orc.peaks(acc, T)
+            keep = orc.retain(g, x, y, pj, pk, 1)
+            if prev is not None:
+                assert np.all(keep <= prev)                     # raising T never adds a hit
+            prev = keep
+            wide = orc.retain(g, x, y, pj, pk, g.n_rho)         # W >= n_rho: any in-range bin at a peak column
+            kb = orc.bins(g, x, y)
+            cols = np.unique(pj)
+            ref = (kb[:, cols] >= 0).any(axis=1) if cols.size else np.zeros(x.size, bool)
+            assert np.array_equal(wide.astype(bool), ref)
+            # every hit that voted into a peak cell is kept
+            for j, k in zip(pj, pk):
+                assert np.all(keep[kb[:, j] == k] == 1)
+
+
+def test_run_batch_equals_per_event_steps(orc):
+    wl = synth.WORKLOADS["plain-16ev-180x128"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 0, n_events=4)
+    cap = 100
+    pk_b, n_b, keep_b = orc.run_batch(wl, ev.x, ev.y, ev.offsets, threshold=20, cap=cap, n_threads=2)
+    for e in range(4):
+        x, y = ev.event(e)
+        acc = orc.vote(g, x, y)
+        pj, pk, pc, n = orc.peaks(acc, 20)
+        assert n_b[e] == n
+        m = min(n, cap)
+        assert np.array_equal(pk_b[e, :m], np.stack([pj, pk, pc], 1)[:m])
+        a, b = int(ev.offsets[e]), int(ev.offsets[e + 1])
+        assert np.array_equal(keep_b[a:b], orc.retain(g, x, y, pj, pk, 1))
+
+
+def test_empty_event(orc):
+    g = orc.Grid(16, 8, -0.005, 0.005)
+    acc = orc.vote(g, np.zeros(0, np.float32), np.zeros(0, np.float32))
+    assert acc.sum() == 0 and orc.peaks(acc, 1)[3] == 0
+    pk, n, keep = orc.run_batch(g, np.zeros(0, np.float32), np.zeros(0, np.float32),
+                                np.zeros(3, np.uint32), threshold=1, rho_window=1, cap=4)
+    assert n.tolist() == [0, 0] and keep.size == 0
