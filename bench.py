@@ -1,0 +1,182 @@
+"""Benchmark of the conformal Hough hot path on one MI355X.
+
+A step is one pass of the whole path (conformal map, theta sweep and vote, 3x3 peaks, retention
+mask) over one batch of synthetic drift-chamber events already resident in HBM, done by one
+launch of the fused batch kernel (hough_run_batch).  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-plain]
+
+The default workload is 1,000 events on a 360 x 256 grid (threshold 10, +-1 rho bin window).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2607_04067_amd import synth  # noqa: E402
+
+METRIC = "events/s + Gvotes/s on 1 MI355X; p50/p99 event latency, served vs plain"
+DEFAULT_WORKLOAD = "paper-1000ev-360x256"
+# Per-event capacity of the peak list; every event of these workloads fits (no truncation).
+MAX_PEAKS = {"plain-16ev-180x128": 1024, "paper-1000ev-360x256": 4096,
+             "batch-10000ev-360x256": 8192, "dense-2000ev-720x512": 16384}
+
+# MI355X: 256 CUs, 4 SIMD16 units each, 2.4 GHz peak engine clock.
+N_CU, LANES_PER_CU_CLK, CLOCK_HZ = 256, 64, 2.4e9
+VALU_LANE_OPS_PER_S = N_CU * LANES_PER_CU_CLK * CLOCK_HZ          # 39.3 T 32-bit lane-ops/s
+OPS_PER_VOTE = 4      # 2 FMA (rho), 1 float->int (bin), 1 index (cell address); the +1 is on the LDS
+VOTE_PEAK_PER_S = VALU_LANE_OPS_PER_S / OPS_PER_VOTE              # 9.83 T votes/s
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, ev, budget_s: float = 20.0):
+    """The CPU oracle, as it stands, on the machine's host cores over a bounded sample."""
+    from oracle import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    # size the sample from a one-thread probe so that it costs about budget_s of CPU time
+    probe = ev.subset(np.arange(min(8, ev.n_events)))
+    t0 = time.perf_counter()
+    oracle.run_batch(wl, probe.x, probe.y, probe.offsets, cap=MAX_PEAKS[wl.name], n_threads=1)
+    per_event = (time.perf_counter() - t0) / probe.n_events
+    n = int(min(ev.n_events, max(threads, budget_s / max(per_event, 1e-6))))
+    sample = ev.subset(np.arange(n))
+    t0 = time.perf_counter()
+    oracle.run_batch(wl, sample.x, sample.y, sample.offsets, cap=MAX_PEAKS[wl.name], n_threads=threads)
+    dt = time.perf_counter() - t0
+    votes = sample.n_hits * wl.n_theta
+    return {"value": round(n / dt, 2), "unit": "events/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {ev.n_events} events of {wl.name} (whole path, all peaks)",
+            "gvotes_per_s": round(votes / dt / 1e9, 4), "seconds": round(dt, 3)}
+
+
+def plain_path(H, wl, ev, n_events: int = 200):
+    """Per-event launches (vote, peaks, retain) with the accumulator in HBM, for comparison."""
+    import torch
+    ctx = H.Context.for_workload(wl)
+    sub = ev.subset(np.arange(min(n_events, ev.n_events)))
+    xt, yt, _ = H.to_device(sub)
+    cap = MAX_PEAKS[wl.name]
+    dt_acc = torch.int16 if wl.acc == "u16" else torch.int32
+    acc = torch.empty((wl.n_theta, wl.n_rho), dtype=dt_acc, device="cuda")
+    peaks = torch.zeros((cap, 2), dtype=torch.int32, device="cuda")
+    npk = torch.zeros(1, dtype=torch.int32, device="cuda")
+    keep = torch.zeros(sub.n_hits, dtype=torch.uint8, device="cuda")
+    offs = sub.offsets.astype(np.int64)
+
+    def one_pass():
+        for e in range(sub.n_events):
+            a, b = int(offs[e]), int(offs[e + 1])
+            ctx.vote(xt[a:b], yt[a:b], acc)
+            ctx.peaks(acc, cap, peaks, npk)
+            ctx.retain(xt[a:b], yt[a:b], peaks, npk, cap, keep[a:b])
+
+    one_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    one_pass()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return {"events_per_s": round(sub.n_events / dt, 1), "events": sub.n_events,
+            "launches_per_event": 3, "ms_per_event": round(dt / sub.n_events * 1e3, 4)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the path is single-GPU; events shard across GPUs "
+              f"with no exchange, see DESIGN.md); got --gpus {args.gpus}", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2607_04067_amd import hough as H
+
+    wl = synth.WORKLOADS[args.workload]
+    log(f"generating {wl.n_events} events of {wl.name}")
+    ev = synth.make_events(wl, 0)
+    votes = ev.n_hits * wl.n_theta
+    ctx = H.Context.for_workload(wl, max_peaks=MAX_PEAKS[wl.name])
+    xt, yt, ot = H.to_device(ev)
+    E = ev.n_events
+    peaks = torch.zeros((E, MAX_PEAKS[wl.name], 2), dtype=torch.int32, device="cuda")
+    npk = torch.zeros(E, dtype=torch.int32, device="cuda")
+    keep = torch.zeros(ev.n_hits, dtype=torch.uint8, device="cuda")
+    status = torch.zeros(E, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        ctx.run_batch(xt, yt, ot, peaks, npk, keep, status, stream)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        ctx.run_batch(xt, yt, ot, peaks, npk, keep, status, stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    ms_per_step = wall / args.steps * 1e3
+    st = status.cpu().numpy()
+    keep_np = keep.cpu().numpy()
+    labels = ev.labels
+    events_per_s = E / (ms_per_step / 1e3)
+    achieved = votes / (kern_ms / 1e3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(events_per_s, 1), "unit": "events/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "events": E, "hits": ev.n_hits, "n_theta": wl.n_theta,
+                   "n_rho": wl.n_rho, "threshold": wl.threshold, "rho_window": wl.rho_window,
+                   "max_peaks": MAX_PEAKS[wl.name], "path": "hough_run_batch (one fused launch)"},
+        "gvotes_per_s": round(votes / (ms_per_step / 1e3) / 1e9, 2),
+        "kernel_ms": round(kern_ms, 4),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": round(VOTE_PEAK_PER_S / 1e9, 1),
+                     "unit": "Gvote/s", "frac": round(achieved / (VOTE_PEAK_PER_S / 1e9), 4),
+                     "traffic": None, "kernel": "k_batch",
+                     "hbm_algorithmic_gbs": round((ev.n_hits * 9 + E * 12) / (kern_ms / 1e3) / 1e9, 2)},
+        "retention": {"R_c": round(float(keep_np.mean()), 4) if keep_np.size else None,
+                      "R_s": round(float(keep_np[labels >= 0].mean()), 4) if (labels >= 0).any() else None,
+                      "peaks_per_event": round(float(npk.float().mean().item()), 1),
+                      "events_flagged": int((st != 0).sum())},
+        "paper_context": "paper: 1,000 simulated events in 0.14 s end to end (7,143 events/s) on an "
+                         "RTX 5060 Ti with a 1000x1000 grid; different data, grid and GPU",
+    }
+    if not args.no_plain:
+        log("plain per-event path")
+        out["plain"] = plain_path(H, wl, ev)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(wl, ev)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,146 @@
+/*
+ * hough.h -- C ABI of libhough.so, the MI355X (gfx950) conformal Hough transform for
+ * drift-chamber hits.
+ *
+ * The library runs the data-parallel hot path of the matrix-based conformal Hough transform:
+ *   1. conformal map of each hit (x, y) -> (u, v) = (x, y) / (x^2 + y^2)          [Eq. (1)]
+ *   2. theta sweep: rho_ij = u_i cos(theta_j) + v_i sin(theta_j) for every hit and every
+ *      theta column, binned on a uniform (theta, rho) grid                       [Sec. II, Sec. III]
+ *   3. voting into a per-event integer accumulator acc[theta][rho]              [Sec. II, Sec. III]
+ *   4. threshold + 3x3 local-maximum peaks, returned in raster order            [Sec. II]
+ *   5. the retention mask: a hit is kept when it lies within rho_window rho bins
+ *      of a peak at the peak's own theta                                       [Sec. I, Sec. II]
+ * An event is the point set of hit wire positions {(x_i, y_i)} of Sec. II.
+ *
+ * Exact rules (every result is an integer and is reproduced bit for bit by the CPU oracle):
+ *   - theta_j = (j * pi) / n_theta in double (lower bin edge), j = 0 .. n_theta-1.
+ *   - A = n_rho / (rho_max - rho_min), B = -rho_min * A in double; per column
+ *     C_j = (float)(A cos theta_j), S_j = (float)(A sin theta_j); Bf = (float)B.
+ *   - a hit is valid iff r2 = fmaf(x, x, y*y) satisfies 0 < r2 <= FLT_MAX; then u = x/r2 and
+ *     v = y/r2 (IEEE single-precision division).  Invalid hits vote nowhere and are never kept.
+ *   - bin of hit i in column j: w = fmaf(v, S_j, Bf); t = fmaf(u, C_j, w); in range iff
+ *     0 <= t < n_rho, and then k = (int)t.  Out-of-range votes are dropped.
+ *   - acc[j][k] = number of valid hits whose bin in column j is k.
+ *   - (j, k) is a peak iff acc[j][k] >= threshold and, for each of its 8 neighbours inside the
+ *     grid, acc[j][k] > neighbour when the neighbour comes first in raster order (smaller j,
+ *     or equal j and smaller k) and acc[j][k] >= neighbour otherwise.  theta does not wrap.
+ *   - keep_i = 1 iff hit i is valid and some peak (jp, kp) has hit i's bin in column jp in
+ *     range with |bin - kp| <= rho_window.
+ *
+ * Memory and streams: every array argument is a DEVICE pointer owned by the caller (for
+ * instance torch tensors' data pointers).  `stream` is a hipStream_t (NULL = the default
+ * stream).  Calls are asynchronous: HOUGH_OK means "validated and enqueued".  A context owns its
+ * constant tables and a small device workspace; calls that share a context must be ordered on
+ * one stream (they share the workspace) and one host thread at a time may use a context.
+ * No call allocates device memory after hough_config, and none synchronises the device, so
+ * the calls may be captured into a HIP graph.
+ *
+ * Errors: host-detectable problems return a negative status synchronously and enqueue nothing.
+ * Conditions only the device sees (a truncated peak list, an event too large for the fused
+ * kernel) are reported through the n_peaks / status outputs.
+ */
+#ifndef HOUGH_H
+#define HOUGH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HOUGH_OK          0
+#define HOUGH_EINVAL    (-1)   /* bad argument: null pointer, bad grid or parameter          */
+#define HOUGH_ENOMEM    (-2)   /* device or host allocation failed in hough_config            */
+#define HOUGH_EOVERFLOW (-3)   /* a count could exceed the output type (u16 accumulator)      */
+#define HOUGH_EDEVICE   (-4)   /* a HIP runtime call or kernel launch failed                  */
+
+#define HOUGH_ACC_U16 1        /* accumulator cells are uint16_t (needs n_hits <= 65535)     */
+#define HOUGH_ACC_I32 2        /* accumulator cells are int32_t                               */
+
+/* Per-event status bits written by hough_run_batch. */
+#define HOUGH_EV_PEAKS_TRUNCATED 1u  /* more peaks than max_peaks; n_peaks holds the true count */
+#define HOUGH_EV_INVALID_HITS    2u  /* the event contains invalid hits (they were ignored)     */
+#define HOUGH_EV_TOO_MANY_HITS   4u  /* more hits than hough_max_batch_hits(): event skipped,
+                                        its n_peaks and keep are written as zero               */
+
+/* The (theta, rho) grid and the peak / retention parameters (Sec. II). */
+typedef struct hough_params {
+    int32_t n_theta;     /* theta bins on [0, pi), 1 .. 65535                                */
+    int32_t n_rho;       /* rho bins on [rho_min, rho_max), 1 .. hough_max_n_rho()           */
+    double  rho_min;     /* lower rho edge (inverse length units of the hit coordinates)     */
+    double  rho_max;     /* upper rho edge, > rho_min                                         */
+    int32_t acc_type;    /* HOUGH_ACC_U16 or HOUGH_ACC_I32: element type of hough_vote's acc */
+    int32_t threshold;   /* minimum peak count, >= 1                                          */
+    int32_t rho_window;  /* retention half-width in rho bins, >= 0                            */
+    int32_t max_peaks;   /* per-event capacity of hough_run_batch's peak list, >= 0           */
+} hough_params;
+
+/* One peak: grid cell and its count.  8 bytes, no padding. */
+typedef struct hough_peak {
+    uint16_t theta_bin;
+    uint16_t rho_bin;
+    uint32_t count;
+} hough_peak;
+
+typedef struct hough_ctx hough_ctx;   /* opaque; owned by the library */
+
+/* Validate `p`, build the per-column constants C_j, S_j on the host (double libm cos/sin, each
+ * rounded once to float) and upload them, and allocate the workspace on the current device.
+ * On success *out receives a new context.  Returns HOUGH_EINVAL for a bad grid or parameter
+ * (including a grid whose rho extent does not fit the on-chip accumulator tile),
+ * HOUGH_ENOMEM / HOUGH_EDEVICE on allocation or copy failure. */
+int hough_config(const hough_params *p, hough_ctx **out);
+
+/* Release a context (waits for nothing: the caller must have finished its work on it). */
+void hough_destroy(hough_ctx *ctx);
+
+/* Copy the parameters a context was configured with. */
+int hough_get_params(const hough_ctx *ctx, hough_params *out);
+
+/* Steps 1-3 for one event (Eq. (1), Sec. II, Sec. III).
+ * x, y: n_hits floats each (hit coordinates, SoA).  acc: n_theta * n_rho cells of the
+ * configured acc_type, row-major acc[j * n_rho + k]; every cell is written (no pre-zeroing).
+ * n_hits == 0 is valid (acc becomes all zero; x and y may then be NULL).
+ * HOUGH_EOVERFLOW if acc_type is HOUGH_ACC_U16 and n_hits > 65535. */
+int hough_vote(hough_ctx *ctx, const float *x, const float *y, uint32_t n_hits,
+               void *acc, void *stream);
+
+/* Step 4 for one event (Sec. II): peaks of `acc` (as written by hough_vote, same acc_type).
+ * The first min(count, cap) peaks in raster order go to peaks[0 .. cap-1]; *n_peaks (device)
+ * receives the true count, which may exceed cap.  cap == 0 is valid (count only). */
+int hough_peaks(hough_ctx *ctx, const void *acc, hough_peak *peaks, uint32_t cap,
+                uint32_t *n_peaks, void *stream);
+
+/* Step 5 for one event (Sec. I, Sec. II): keep[i] = 1 iff hit i is within rho_window rho bins
+ * of one of the peaks peaks[0 .. min(*n_peaks, cap)-1] (n_peaks is a device pointer, as
+ * written by hough_peaks), else 0.  Peak cells outside the grid are ignored. */
+int hough_retain(hough_ctx *ctx, const float *x, const float *y, uint32_t n_hits,
+                 const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
+                 uint8_t *keep, void *stream);
+
+/* Steps 1-5 for a batch of events packed CSR (Sec. III: events are independent and are
+ * processed in batches), in one persistent fused kernel that never writes an accumulator.
+ * x, y: offsets[n_events] floats; hits of event e are [offsets[e], offsets[e+1]).
+ * offsets: n_events + 1 uint32 (device), non-decreasing, offsets[0] may be non-zero.
+ * peaks: n_events * max_peaks entries; event e's peaks go to peaks[e * max_peaks ...] in raster
+ * order, truncated at max_peaks.  n_peaks[e]: the true peak count.  keep: offsets[n_events]
+ * bytes (indexed like x), computed from ALL peaks of the event even when the list is
+ * truncated.  status[e]: HOUGH_EV_* bits.  n_events == 0 is valid. */
+int hough_run_batch(hough_ctx *ctx, const float *x, const float *y, const uint32_t *offsets,
+                    uint32_t n_events, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
+                    uint32_t *status, void *stream);
+
+/* Largest number of hits per event hough_run_batch processes for this context. */
+uint32_t hough_max_batch_hits(const hough_ctx *ctx);
+
+/* Largest n_rho hough_config accepts on the current device. */
+int32_t hough_max_n_rho(void);
+
+/* Static description of a status code. */
+const char *hough_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOUGH_H */

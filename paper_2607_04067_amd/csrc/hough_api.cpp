@@ -1,0 +1,239 @@
+// Host side of libhough.so: parameter validation, the per-column constants, workspace
+// ownership and kernel dispatch behind the C ABI declared in include/hough.h.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "hough_internal.h"
+
+namespace hough {
+int batch_blocks_per_cu(const BatchPlan &p);
+}
+
+struct hough_ctx {
+    hough_params p;
+    int device;
+    float *d_tables;        // C[n_theta] then S[n_theta]
+    uint32_t *d_work;       // [0]: work counter of the fused kernel
+    hough::GridArgs g;
+    hough::BatchPlan plan;
+    size_t lds_limit;
+    int n_cu;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+int lds_limit_bytes(int device, size_t *out) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+        return HOUGH_EDEVICE;
+    *out = (size_t)v;
+    return HOUGH_OK;
+}
+
+bool grid_fits(int n_rho, size_t limit) {
+    if (hough::vote_lds_bytes(n_rho) > limit) return false;
+    if (hough::peaks_lds_bytes(n_rho) > limit) return false;
+    hough::BatchPlan p;
+    return hough::plan_batch(1, n_rho, 4, 1, limit, &p) == 0;
+}
+
+// Default launch shape of the fused kernel: the most waves per workgroup that still lets the
+// tile's LDS footprint keep at least one workgroup per CU, preferring two workgroups per CU.
+int default_plan(hough_ctx *c) {
+    const size_t cu_lds = 160 * 1024;
+    int best = -1;
+    hough::BatchPlan pick{};
+    const int waves_opts[3] = {16, 8, 4};
+    for (int wi = 0; wi < 3; ++wi) {
+        hough::BatchPlan p;
+        if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves_opts[wi], 1, c->lds_limit, &p) != 0) continue;
+        const int per_cu = (int)(cu_lds / p.lds_bytes);
+        const int waves_per_cu = per_cu * p.waves;
+        const int score = (per_cu >= 2 ? 1000 : 0) + waves_per_cu;
+        if (score > best) { best = score; pick = p; }
+    }
+    if (best < 0) return HOUGH_EINVAL;
+    c->plan = pick;
+    return HOUGH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hough_status_string(int status) {
+    switch (status) {
+        case HOUGH_OK: return "ok";
+        case HOUGH_EINVAL: return "invalid argument";
+        case HOUGH_ENOMEM: return "out of memory";
+        case HOUGH_EOVERFLOW: return "count may overflow the accumulator type";
+        case HOUGH_EDEVICE: return "HIP runtime or launch failure";
+        default: return "unknown status";
+    }
+}
+
+int32_t hough_max_n_rho(void) {
+    int dev = 0;
+    size_t limit = 0;
+    if (hipGetDevice(&dev) != hipSuccess || lds_limit_bytes(dev, &limit) != HOUGH_OK) return 0;
+    int lo = 0, hi = 65535;
+    while (lo < hi) {                      // largest n_rho whose kernels fit the LDS
+        const int mid = (lo + hi + 1) / 2;
+        if (grid_fits(mid, limit)) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+int hough_config(const hough_params *p, hough_ctx **out) {
+    if (!p || !out) return HOUGH_EINVAL;
+    *out = nullptr;
+    if (p->n_theta < 1 || p->n_theta > 65535 || p->n_rho < 1 || p->n_rho > 65535) return HOUGH_EINVAL;
+    if (!isfinite(p->rho_min) || !isfinite(p->rho_max) || !(p->rho_max > p->rho_min)) return HOUGH_EINVAL;
+    if (p->acc_type != HOUGH_ACC_U16 && p->acc_type != HOUGH_ACC_I32) return HOUGH_EINVAL;
+    if (p->threshold < 1 || p->rho_window < 0 || p->max_peaks < 0) return HOUGH_EINVAL;
+    const double A = (double)p->n_rho / (p->rho_max - p->rho_min);
+    const double B = -p->rho_min * A;
+    if (!isfinite(A) || !isfinite(B) || !(fabs(A) < 1e30) || !(fabs(B) < 1e30)) return HOUGH_EINVAL;
+
+    const char *fail = getenv("HOUGH_TEST_FAIL_ALLOC");   // test hook for the ENOMEM path
+    if (fail && fail[0] == '1') return HOUGH_ENOMEM;
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HOUGH_EDEVICE;
+    size_t limit = 0;
+    int rc = lds_limit_bytes(dev, &limit);
+    if (rc != HOUGH_OK) return rc;
+    if (!grid_fits(p->n_rho, limit)) return HOUGH_EINVAL;
+
+    hough_ctx *c = new (std::nothrow) hough_ctx();
+    if (!c) return HOUGH_ENOMEM;
+    c->p = *p;
+    c->device = dev;
+    c->lds_limit = limit;
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        delete c;
+        return HOUGH_EDEVICE;
+    }
+
+    // Per-column constants: theta_j = (j*pi)/n_theta in double, times A, rounded once to float.
+    std::vector<float> tab(2 * (size_t)p->n_theta);
+    for (int j = 0; j < p->n_theta; ++j) {
+        const double theta = ((double)j * kPi) / (double)p->n_theta;
+        tab[j] = (float)(A * cos(theta));
+        tab[p->n_theta + j] = (float)(A * sin(theta));
+    }
+    if (hipMalloc(&c->d_tables, tab.size() * sizeof(float)) != hipSuccess) {
+        delete c;
+        return HOUGH_ENOMEM;
+    }
+    if (hipMalloc(&c->d_work, 256) != hipSuccess) {
+        (void)hipFree(c->d_tables);
+        delete c;
+        return HOUGH_ENOMEM;
+    }
+    if (hipMemcpy(c->d_tables, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(c->d_work, 0, 256) != hipSuccess) {
+        hough_destroy(c);
+        return HOUGH_EDEVICE;
+    }
+
+    hough::GridArgs &g = c->g;
+    g.C = c->d_tables;
+    g.S = c->d_tables + p->n_theta;
+    g.n_theta = p->n_theta;
+    g.n_rho = p->n_rho;
+    g.Bf = (float)B;
+    g.nrho_f = (float)p->n_rho;
+    g.A_f = (float)fabs(A);
+    g.safe_margin = 1e-5f * (float)p->n_rho + 0.01f;
+    g.threshold = (uint32_t)p->threshold;
+    g.rho_window = p->rho_window < p->n_rho ? p->rho_window : p->n_rho;
+
+    rc = default_plan(c);
+    if (rc != HOUGH_OK) {
+        hough_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return HOUGH_OK;
+}
+
+void hough_destroy(hough_ctx *c) {
+    if (!c) return;
+    if (c->d_tables) (void)hipFree(c->d_tables);
+    if (c->d_work) (void)hipFree(c->d_work);
+    delete c;
+}
+
+int hough_get_params(const hough_ctx *c, hough_params *out) {
+    if (!c || !out) return HOUGH_EINVAL;
+    *out = c->p;
+    return HOUGH_OK;
+}
+
+uint32_t hough_max_batch_hits(const hough_ctx *c) { return c ? hough::kMaxBatchHits : 0u; }
+
+int hough_vote(hough_ctx *c, const float *x, const float *y, uint32_t n_hits, void *acc, void *stream) {
+    if (!c || !acc) return HOUGH_EINVAL;
+    if (n_hits && (!x || !y)) return HOUGH_EINVAL;
+    if (c->p.acc_type == HOUGH_ACC_U16 && n_hits > 65535u) return HOUGH_EOVERFLOW;
+    const hipError_t e = hough::launch_vote(c->g, x, y, n_hits, acc, c->p.acc_type, (hipStream_t)stream);
+    return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
+}
+
+int hough_peaks(hough_ctx *c, const void *acc, hough_peak *peaks, uint32_t cap, uint32_t *n_peaks,
+                void *stream) {
+    if (!c || !acc || !n_peaks || (cap && !peaks)) return HOUGH_EINVAL;
+    if (((uintptr_t)peaks & 7u) != 0) return HOUGH_EINVAL;
+    const hipError_t e = hough::launch_peaks(c->g, acc, c->p.acc_type, peaks, cap, n_peaks,
+                                             (hipStream_t)stream);
+    return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
+}
+
+int hough_retain(hough_ctx *c, const float *x, const float *y, uint32_t n_hits,
+                 const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap, uint8_t *keep,
+                 void *stream) {
+    if (!c || !n_peaks || (cap && !peaks)) return HOUGH_EINVAL;
+    if (n_hits && (!x || !y || !keep)) return HOUGH_EINVAL;
+    if (((uintptr_t)peaks & 7u) != 0) return HOUGH_EINVAL;
+    const hipError_t e = hough::launch_retain(c->g, x, y, n_hits, peaks, n_peaks, cap, keep,
+                                              (hipStream_t)stream);
+    return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
+}
+
+int hough_run_batch(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,
+                    uint32_t n_events, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
+                    uint32_t *status, void *stream) {
+    if (!c) return HOUGH_EINVAL;
+    if (n_events == 0) return HOUGH_OK;
+    if (!x || !y || !offsets || !n_peaks || !keep || !status) return HOUGH_EINVAL;
+    if (c->p.max_peaks > 0 && !peaks) return HOUGH_EINVAL;
+    if (((uintptr_t)peaks & 7u) != 0) return HOUGH_EINVAL;
+    hough::BatchPlan plan = c->plan;
+    const int per_cu = hough::batch_blocks_per_cu(plan);
+    if (per_cu < 1) return HOUGH_EDEVICE;
+    long grid = (long)per_cu * c->n_cu;
+    if (grid > (long)n_events) grid = n_events;
+    plan.grid = (int)grid;
+    hough::BatchArgs a;
+    a.x = x;
+    a.y = y;
+    a.offsets = offsets;
+    a.n_events = n_events;
+    a.peaks = c->p.max_peaks > 0 ? peaks : nullptr;
+    a.n_peaks = n_peaks;
+    a.keep = keep;
+    a.status = status;
+    a.max_peaks = (uint32_t)c->p.max_peaks;
+    a.queue = c->d_work;
+    const hipError_t e = hough::launch_batch(c->g, plan, a, (hipStream_t)stream);
+    return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal declarations of libhough.so shared by its host API and its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hough.h"
+
+namespace hough {
+
+// Lanes of a CDNA wavefront; every tile is a whole number of 64-column groups so that one
+// lane owns one theta column.
+constexpr int kWave = 64;
+// The fused batch kernel keeps one keep bit per hit of the event in LDS.
+constexpr uint32_t kMaxBatchHits = 32768;
+// Bit 31 of an LDS accumulator cell marks "within rho_window of a peak" during retention.
+constexpr uint32_t kMark = 0x80000000u;
+
+// Grid constants as the kernels see them.
+struct GridArgs {
+    const float *C;      // [n_theta] (float)(A cos theta_j)
+    const float *S;      // [n_theta] (float)(A sin theta_j)
+    int32_t n_theta;
+    int32_t n_rho;
+    float Bf;            // (float)(-rho_min * A)
+    float nrho_f;        // (float)n_rho
+    float A_f;           // (float)A, for the per-hit "all votes in range" test
+    float safe_margin;   // absolute slack of that test, in bins
+    uint32_t threshold;
+    int32_t rho_window;
+};
+
+// Launch shape of the fused batch kernel (chosen by the host; see plan_batch()).
+struct BatchPlan {
+    int waves;           // waves per workgroup
+    int groups;          // 64-column groups per theta tile
+    int tile_cols;       // 64 * groups, including one halo column on each side
+    int out_cols;        // tile_cols - 2 output columns per tile
+    int n_tiles;         // ceil(n_theta / out_cols)
+    size_t lds_bytes;    // dynamic LDS per workgroup
+    int grid;            // persistent workgroups
+};
+
+struct BatchArgs {
+    const float *x;
+    const float *y;
+    const uint32_t *offsets;
+    uint32_t n_events;
+    hough_peak *peaks;
+    uint32_t *n_peaks;
+    uint8_t *keep;
+    uint32_t *status;
+    uint32_t max_peaks;
+    uint32_t *queue;     // [2] work counter and exit counter (device, zero between launches)
+};
+
+// Launchers (hough_kernels.hip).  All return a hipError_t from the launch.
+hipError_t launch_vote(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
+                       void *acc, int acc_type, hipStream_t s);
+hipError_t launch_peaks(const GridArgs &g, const void *acc, int acc_type, hough_peak *peaks,
+                        uint32_t cap, uint32_t *n_peaks, hipStream_t s);
+hipError_t launch_retain(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
+                         const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
+                         uint8_t *keep, hipStream_t s);
+hipError_t launch_batch(const GridArgs &g, const BatchPlan &p, const BatchArgs &a, hipStream_t s);
+
+// LDS needs and plans (hough_kernels.hip).
+size_t vote_lds_bytes(int n_rho);
+size_t peaks_lds_bytes(int n_rho);
+size_t batch_lds_bytes(int n_rho, int waves, int groups);
+int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out);
+
+}  // namespace hough

@@ -1,0 +1,682 @@
+// HIP kernels of libhough.so (gfx950 / CDNA4, wave64).
+//
+// Layout shared by every kernel that votes: a theta tile of TW = 64*G columns lives in LDS as
+// tile[k * TW + c] (rho-major, one 32-bit counter per cell).  Lane l of a wave owns column
+// c = 64*q + l of group q, so the 64 atomics one ds_add_u32 issues for one hit land in 64
+// consecutive dwords of one row slice: distinct banks, never the same address.  Hits are
+// wave-uniform: a wave maps 64 hits at a time (one per lane), compacts the valid ones into a
+// per-wave LDS stage with ballot/mbcnt, then every lane sweeps its own column over the staged
+// hits (the theta sweep of Sec. III: one column = one parallel task, hits streamed through it).
+//
+// Row n_rho of the tile is a dummy row: lanes whose column lies outside [0, n_theta) carry
+// C = S = 0 and B = n_rho, so they "vote" there instead of taking a branch per vote.
+//
+// Floating point: the bin of a hit in a column is t = fma(u, C_j, fma(v, S_j, B)) with
+// k = (int)t, exactly as the C-ABI header states.  Hits whose votes are provably all in range
+// (|rho| bounded by sqrt(u^2+v^2) with slack for rounding) skip the range test; the others take
+// the literal test 0 <= t < n_rho.
+#include <float.h>
+
+#include "hough_internal.h"
+
+namespace hough {
+namespace {
+
+constexpr int kStageBytes = kWave * (int)(sizeof(float2) + sizeof(uint32_t));
+
+// ------------------------------------------------------------------ per-hit arithmetic
+// Eq. (1).  Returns false for a hit whose r2 is zero, non-finite or overflowed.
+__device__ __forceinline__ bool conformal(float x, float y, float &u, float &v) {
+    const float y2 = y * y;
+    const float r2 = __builtin_fmaf(x, x, y2);
+    const bool ok = (r2 > 0.0f) && (r2 <= FLT_MAX);
+    const float d = ok ? r2 : 1.0f;
+    u = x / d;
+    v = y / d;
+    return ok;
+}
+
+// True when every column's t lies strictly inside (0, n_rho): |t - B| <= sqrt(u^2+v^2)*A plus
+// rounding (a few 2^-24 relative), covered by the 1e-4 relative and safe_margin absolute slack.
+__device__ __forceinline__ bool all_in_range(float u, float v, const GridArgs &g) {
+    const float r = __builtin_sqrtf(__builtin_fmaf(u, u, v * v));
+    const float m = r * g.A_f * 1.0001f + g.safe_margin;
+    return (g.Bf - m > 0.0f) && (g.Bf + m < g.nrho_f);
+}
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ void lds_inc(uint32_t *p) {
+    __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-lane constants of the columns a lane owns in the current tile.
+template <int G>
+struct Cols {
+    float C[G], S[G], B[G];
+};
+
+template <int G>
+__device__ __forceinline__ Cols<G> load_cols(const GridArgs &g, int first_col, int lane) {
+    Cols<G> cl;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const int j = first_col + 64 * q + lane;
+        const bool in = (j >= 0) && (j < g.n_theta);
+        cl.C[q] = in ? g.C[j] : 0.0f;
+        cl.S[q] = in ? g.S[j] : 0.0f;
+        cl.B[q] = in ? g.Bf : g.nrho_f;     // out-of-grid lanes land in the dummy row
+    }
+    return cl;
+}
+
+// Map up to 64 hits [base, end) (one per lane) and compact the valid ones into the wave's
+// stage: all-in-range hits first, then the others.  Returns (n_safe, n_total) and, through
+// `bad`, whether this lane met an invalid hit.  `skip` hides hits the caller is done with.
+struct StageCount { uint32_t safe, total; };
+
+__device__ __forceinline__ StageCount stage_hits(float2 *st, uint32_t *sidx, const float *x,
+                                                 const float *y, uint32_t base, uint32_t end,
+                                                 bool skip, const GridArgs &g, int lane,
+                                                 uint32_t &bad) {
+    const uint32_t i = base + lane;
+    const bool in = (i < end) && !skip;
+    float xi = 0.0f, yi = 0.0f;
+    if (in) { xi = x[i]; yi = y[i]; }
+    float u, v;
+    const bool ok = conformal(xi, yi, u, v);
+    const bool valid = in && ok;
+    if (in && !ok) bad = 1u;
+    const bool safe = valid && all_in_range(u, v, g);
+    const uint64_t bs = __ballot(safe);
+    const uint64_t bu = __ballot(valid && !safe);
+    const uint32_t ns = (uint32_t)__popcll(bs);
+    const uint32_t pos = safe ? mbcnt(bs) : ns + mbcnt(bu);
+    if (valid) {
+        st[pos] = make_float2(u, v);
+        if (sidx) sidx[pos] = i;
+    }
+    wave_sync();
+    return StageCount{ns, ns + (uint32_t)__popcll(bu)};
+}
+
+// Steps 2-3: sweep the staged hits through the lane's columns and vote.
+template <int G>
+__device__ __forceinline__ void vote1(uint32_t *tile, float u, float v, const Cols<G> &cl, int lane) {
+    constexpr int TW = 64 * G;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const float w = __builtin_fmaf(v, cl.S[q], cl.B[q]);
+        const float t = __builtin_fmaf(u, cl.C[q], w);
+        lds_inc(&tile[(int)t * TW + 64 * q + lane]);
+    }
+}
+
+// The staged hits are read four at a time (two 16-byte broadcast reads) one step ahead of
+// the votes that use them, so a wave never waits on its own atomics to fetch the next hits.
+template <int G>
+__device__ __forceinline__ void vote_staged(uint32_t *tile, const float2 *st, StageCount n,
+                                            const Cols<G> &cl, float nrho_f, int lane) {
+    constexpr int TW = 64 * G;
+    const float4 *st4 = reinterpret_cast<const float4 *>(st);
+    const uint32_t n4 = n.safe >> 2;
+    if (n4) {
+        float4 a = st4[0], b = st4[1];
+        for (uint32_t i = 1; i < n4; ++i) {
+            const float4 na = st4[2 * i], nb = st4[2 * i + 1];
+            vote1<G>(tile, a.x, a.y, cl, lane);
+            vote1<G>(tile, a.z, a.w, cl, lane);
+            vote1<G>(tile, b.x, b.y, cl, lane);
+            vote1<G>(tile, b.z, b.w, cl, lane);
+            a = na;
+            b = nb;
+        }
+        vote1<G>(tile, a.x, a.y, cl, lane);
+        vote1<G>(tile, a.z, a.w, cl, lane);
+        vote1<G>(tile, b.x, b.y, cl, lane);
+        vote1<G>(tile, b.z, b.w, cl, lane);
+    }
+    for (uint32_t h = n4 * 4; h < n.safe; ++h) vote1<G>(tile, st[h].x, st[h].y, cl, lane);
+    for (uint32_t h = n.safe; h < n.total; ++h) {
+        const float2 p = st[h];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const float w = __builtin_fmaf(p.y, cl.S[q], cl.B[q]);
+            const float t = __builtin_fmaf(p.x, cl.C[q], w);
+            if (t >= 0.0f && t < nrho_f) lds_inc(&tile[(int)t * TW + 64 * q + lane]);
+        }
+    }
+}
+
+template <int G>
+__device__ void vote_range(uint32_t *tile, float2 *st, const float *x, const float *y,
+                           uint32_t hb, uint32_t he, const Cols<G> &cl, const GridArgs &g,
+                           int lane, uint32_t &bad) {
+    for (uint32_t base = hb; base < he; base += 64) {
+        const StageCount n = stage_hits(st, nullptr, x, y, base, he, false, g, lane, bad);
+        vote_staged<G>(tile, st, n, cl, g.nrho_f, lane);
+        wave_sync();
+    }
+}
+
+// Step 4 on one 32-row word of column c: bit b set iff (c, 32*wd + b) is a peak.
+// The lane holds the 3x3 window of columns c-1, c, c+1 and slides it down the rows.
+// Raster order is (theta, rho), so column c-1 and row k-1 of column c come first:
+// peak <=> count >= threshold, count > every earlier neighbour, count >= every later one,
+// i.e. count >= max(threshold, max(earlier) + 1, max(later)).  Rows outside the grid are 0.
+template <int TW>
+__device__ __forceinline__ uint32_t peak_word(const uint32_t *tile, int c, int wd, int n_rho,
+                                              uint32_t T) {
+    const int cl = c > 0 ? c - 1 : 0;
+    const int cr = c < TW - 1 ? c + 1 : TW - 1;
+    const int k0 = wd * 32;
+    uint32_t Lp = 0, Mp = 0, Rp = 0;
+    if (k0 > 0) {
+        const uint32_t *r = tile + (k0 - 1) * TW;
+        Lp = r[cl]; Mp = r[c]; Rp = r[cr];
+    }
+    const uint32_t *r0 = tile + k0 * TW;
+    uint32_t Lc = r0[cl], Mc = r0[c], Rc = r0[cr];
+    const int kend = (k0 + 32 < n_rho) ? k0 + 32 : n_rho;
+    uint32_t mask = 0;
+    for (int k = k0; k < kend; ++k) {
+        uint32_t Ln = 0, Mn = 0, Rn = 0;
+        if (k + 1 < n_rho) {
+            const uint32_t *r = tile + (k + 1) * TW;
+            Ln = r[cl]; Mn = r[c]; Rn = r[cr];
+        }
+        const uint32_t before = max(max(Lp, Lc), max(Ln, Mp));
+        const uint32_t after = max(max(Rp, Rc), max(Rn, Mn));
+        const uint32_t need = max(max(T, before + 1u), after);
+        mask |= (uint32_t)(Mc >= need) << (k - k0);
+        Lp = Lc; Mp = Mc; Rp = Rc;
+        Lc = Ln; Mc = Mn; Rc = Rn;
+    }
+    return mask;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void store_peak(hough_peak *out, uint32_t j, uint32_t k, uint32_t c) {
+    uint2 *p = reinterpret_cast<uint2 *>(out);
+    *p = make_uint2((j & 0xffffu) | (k << 16), c);
+}
+
+// Step 4 (compaction) and the marks of step 5, run by one wave.  Columns are visited in
+// order and each lane lists its own column's peaks in rho order, so the event's list comes
+// out in raster order.  Every cell within rho_window of a peak gets bit 31 set (each lane only
+// touches its own column).  Returns the number of peaks in this tile.
+template <int G>
+__device__ uint32_t emit_and_mark(uint32_t *tile, const uint32_t *pmask, int nwords, int first_col,
+                                  const GridArgs &g, hough_peak *out, uint32_t cap,
+                                  uint32_t running, int lane) {
+    constexpr int TW = 64 * G;
+    const uint32_t start = running;
+    for (int q = 0; q < G; ++q) {
+        const int c = 64 * q + lane;
+        uint32_t cnt = 0;
+        for (int wd = 0; wd < nwords; ++wd) cnt += __popc(pmask[wd * TW + c]);
+        const uint32_t incl = wave_inclusive_scan(cnt, lane);
+        const uint32_t total = __shfl(incl, 63, 64);
+        uint32_t idx = running + incl - cnt;
+        const uint32_t j = (uint32_t)(first_col + c);
+        for (int wd = 0; wd < nwords; ++wd) {
+            uint32_t m = pmask[wd * TW + c];
+            while (m) {
+                const int b = __builtin_ctz(m);
+                m &= m - 1u;
+                const int k = wd * 32 + b;
+                const uint32_t cv = tile[k * TW + c] & ~kMark;
+                if (idx < cap) store_peak(out + idx, j, (uint32_t)k, cv);
+                ++idx;
+                const int lo = k - g.rho_window > 0 ? k - g.rho_window : 0;
+                const int hi = k + g.rho_window < g.n_rho - 1 ? k + g.rho_window : g.n_rho - 1;
+                for (int kk = lo; kk <= hi; ++kk) tile[kk * TW + c] |= kMark;
+            }
+        }
+        running += total;
+    }
+    return running - start;
+}
+
+// Step 5 on the current tile: every hit not yet kept looks up its own cell in each of the
+// lane's columns; a marked cell in any column of the tile keeps the hit.  Hits are taken four
+// at a time so that their 4*G cell reads are in flight together.
+template <int G>
+__device__ __forceinline__ uint32_t lookup1(const uint32_t *tile, float u, float v, bool checked,
+                                            const Cols<G> &cl, float nrho_f, int lane) {
+    constexpr int TW = 64 * G;
+    uint32_t m = 0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const float w = __builtin_fmaf(v, cl.S[q], cl.B[q]);
+        const float t = __builtin_fmaf(u, cl.C[q], w);
+        if (!checked || (t >= 0.0f && t < nrho_f)) m |= tile[(int)t * TW + 64 * q + lane];
+    }
+    return m;
+}
+
+__device__ __forceinline__ void keep_hit(uint32_t *keepbits, uint32_t hit) {
+    __hip_atomic_fetch_or(&keepbits[hit >> 5], 1u << (hit & 31), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int G>
+__device__ void retain_range(const uint32_t *tile, float2 *st, uint32_t *sidx, const float *x,
+                             const float *y, uint32_t hb, uint32_t he, uint32_t *keepbits,
+                             const Cols<G> &cl, const GridArgs &g, int lane) {
+    uint32_t unused = 0;
+    for (uint32_t base = hb; base < he; base += 64) {
+        const uint32_t i = base + lane;
+        const bool done = (i < he) && ((keepbits[i >> 5] >> (i & 31)) & 1u);
+        const StageCount n = stage_hits(st, sidx, x, y, base, he, done, g, lane, unused);
+        const float4 *st4 = reinterpret_cast<const float4 *>(st);
+        uint32_t h = 0;
+        for (; h + 4 <= n.safe; h += 4) {
+            const float4 a = st4[h >> 1], b = st4[(h >> 1) + 1];
+            const uint32_t m0 = lookup1<G>(tile, a.x, a.y, false, cl, g.nrho_f, lane);
+            const uint32_t m1 = lookup1<G>(tile, a.z, a.w, false, cl, g.nrho_f, lane);
+            const uint32_t m2 = lookup1<G>(tile, b.x, b.y, false, cl, g.nrho_f, lane);
+            const uint32_t m3 = lookup1<G>(tile, b.z, b.w, false, cl, g.nrho_f, lane);
+            const uint64_t k0 = __ballot((m0 & kMark) != 0u), k1 = __ballot((m1 & kMark) != 0u);
+            const uint64_t k2 = __ballot((m2 & kMark) != 0u), k3 = __ballot((m3 & kMark) != 0u);
+            if (lane == 0) {
+                if (k0) keep_hit(keepbits, sidx[h]);
+                if (k1) keep_hit(keepbits, sidx[h + 1]);
+                if (k2) keep_hit(keepbits, sidx[h + 2]);
+                if (k3) keep_hit(keepbits, sidx[h + 3]);
+            }
+        }
+        for (; h < n.total; ++h) {
+            const float2 p = st[h];
+            const uint32_t m = lookup1<G>(tile, p.x, p.y, h >= n.safe, cl, g.nrho_f, lane);
+            if (__ballot((m & kMark) != 0u) != 0ull && lane == 0) keep_hit(keepbits, sidx[h]);
+        }
+        wave_sync();
+    }
+}
+
+// ------------------------------------------------------------------------ plain path
+// hough_vote: one workgroup per 64-column group, all hits of the event swept through it.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__restrict__ x,
+                                                  const float *__restrict__ y, uint32_t n_hits,
+                                                  void *acc, int acc_type) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    uint32_t *tile = lds;
+    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int first = blockIdx.x * 64;
+    for (int i = threadIdx.x; i < g.n_rho * 16; i += NW * 64)
+        reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
+    const Cols<1> cl = load_cols<1>(g, first, lane);
+    __syncthreads();
+    const uint32_t hb = (uint32_t)((uint64_t)n_hits * wave / NW);
+    const uint32_t he = (uint32_t)((uint64_t)n_hits * (wave + 1) / NW);
+    uint32_t bad = 0;
+    vote_range<1>(tile, stage + wave * 64, x, y, hb, he, cl, g, lane, bad);
+    __syncthreads();
+    // Write-out: lane = column (theta row of acc), wave = a slice of rho.
+    const int j = first + lane;
+    if (j >= g.n_theta) return;
+    const int kb = (int)((int64_t)g.n_rho * wave / NW), ke = (int)((int64_t)g.n_rho * (wave + 1) / NW);
+    if (acc_type == HOUGH_ACC_U16) {
+        uint16_t *row = static_cast<uint16_t *>(acc) + (size_t)j * g.n_rho;
+        for (int k = kb; k < ke; ++k) row[k] = (uint16_t)tile[k * 64 + lane];
+    } else {
+        uint32_t *row = static_cast<uint32_t *>(acc) + (size_t)j * g.n_rho;
+        for (int k = kb; k < ke; ++k) row[k] = tile[k * 64 + lane];
+    }
+}
+
+// hough_peaks: one workgroup; rows are staged NW at a time (plus one halo row on each side)
+// and each wave tests one row, lanes over rho.  Counts are prefix-summed across waves so the
+// list is written in raster order.
+template <int NW, typename T>
+__global__ __launch_bounds__(NW * 64) void k_peaks(GridArgs g, const T *__restrict__ acc,
+                                                   hough_peak *out, uint32_t cap,
+                                                   uint32_t *n_peaks) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    uint32_t *rows = lds;   // [(NW + 2) * n_rho], buffer row r holds grid row jb - 1 + r
+    __shared__ uint32_t s_cnt[NW];
+    __shared__ uint32_t s_total;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nr = g.n_rho;
+    if (threadIdx.x == 0) s_total = 0;
+    for (int jb = 0; jb < g.n_theta; jb += NW) {
+        for (int idx = threadIdx.x; idx < (NW + 2) * nr; idx += NW * 64) {
+            const int r = idx / nr, k = idx - r * nr, jj = jb - 1 + r;
+            rows[idx] = (jj >= 0 && jj < g.n_theta) ? (uint32_t)acc[(size_t)jj * nr + k] : 0u;
+        }
+        __syncthreads();
+        const int j = jb + wave;
+        const uint32_t *up = rows + wave * nr, *mid = up + nr, *dn = mid + nr;
+        uint32_t cnt = 0;
+        auto is_peak = [&](int k) -> bool {
+            const uint32_t c = mid[k];
+            const uint32_t l = k > 0 ? 1u : 0u, r = k + 1 < nr ? 1u : 0u;
+            const uint32_t before = max(max(l ? up[k - 1] : 0u, up[k]),
+                                        max(r ? up[k + 1] : 0u, l ? mid[k - 1] : 0u));
+            const uint32_t after = max(max(r ? mid[k + 1] : 0u, l ? dn[k - 1] : 0u),
+                                       max(dn[k], r ? dn[k + 1] : 0u));
+            return c >= max(max(g.threshold, before + 1u), after);
+        };
+        if (j < g.n_theta) {
+            for (int kc = 0; kc < nr; kc += 64) {
+                const int k = kc + lane;
+                cnt += (uint32_t)__popcll(__ballot(k < nr && is_peak(k)));
+            }
+        }
+        if (lane == 0) s_cnt[wave] = cnt;
+        __syncthreads();
+        uint32_t base = s_total;
+        for (int w = 0; w < wave; ++w) base += s_cnt[w];
+        if (j < g.n_theta) {
+            for (int kc = 0; kc < nr; kc += 64) {
+                const int k = kc + lane;
+                const bool p = k < nr && is_peak(k);
+                const uint64_t m = __ballot(p);
+                if (p) {
+                    const uint32_t idx = base + mbcnt(m);
+                    if (idx < cap) store_peak(out + idx, (uint32_t)j, (uint32_t)k, mid[k]);
+                }
+                base += (uint32_t)__popcll(m);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t s = 0;
+            for (int w = 0; w < NW; ++w) s += s_cnt[w];
+            s_total += s;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *n_peaks = s_total;
+}
+
+// hough_retain: one thread per hit.  Peak rows are processed in blocks that fit LDS: for
+// each block a dilated bitmap (bit k of row j set iff a peak (j, k') has |k - k'| <= W) is
+// built from the peak list, then every unkept hit looks up its own bin in each peak row.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__restrict__ x,
+                                                    const float *__restrict__ y, uint32_t n_hits,
+                                                    const hough_peak *__restrict__ peaks,
+                                                    const uint32_t *n_peaks, uint32_t cap,
+                                                    uint8_t *keep, int rows_per_block) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    const int words = (g.n_rho + 31) / 32;
+    uint32_t *dil = lds;                                   // [rows_per_block * words]
+    uint32_t *rowany = dil + (size_t)rows_per_block * words;   // [rows_per_block]
+    const uint32_t np = min(*n_peaks, cap);
+    const uint32_t i = blockIdx.x * (NW * 64) + threadIdx.x;
+    const bool in = i < n_hits;
+    float u = 0.0f, v = 0.0f;
+    bool valid = false;
+    if (in) valid = conformal(x[i], y[i], u, v);
+    uint32_t kept = 0;
+    for (int ja = 0; ja < g.n_theta; ja += rows_per_block) {
+        const int nrow = min(rows_per_block, g.n_theta - ja);
+        for (int t = threadIdx.x; t < nrow * words; t += NW * 64) dil[t] = 0u;
+        for (int t = threadIdx.x; t < nrow; t += NW * 64) rowany[t] = 0u;
+        __syncthreads();
+        for (uint32_t p = threadIdx.x; p < np; p += NW * 64) {
+            const uint2 pk = reinterpret_cast<const uint2 *>(peaks)[p];
+            const int j = (int)(pk.x & 0xffffu), k = (int)(pk.x >> 16);
+            if (j < ja || j >= ja + nrow || k >= g.n_rho) continue;
+            const int lo = k - g.rho_window > 0 ? k - g.rho_window : 0;
+            const int hi = k + g.rho_window < g.n_rho - 1 ? k + g.rho_window : g.n_rho - 1;
+            uint32_t *row = dil + (size_t)(j - ja) * words;
+            for (int wd = lo >> 5; wd <= (hi >> 5); ++wd) {
+                const int a = max(lo, wd * 32) - wd * 32, b = min(hi, wd * 32 + 31) - wd * 32;
+                const uint32_t m = (b == 31 ? 0xffffffffu : ((1u << (b + 1)) - 1u)) & ~((1u << a) - 1u);
+                __hip_atomic_fetch_or(&row[wd], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            rowany[j - ja] = 1u;
+        }
+        __syncthreads();
+        if (valid && !kept) {
+            for (int r = 0; r < nrow; ++r) {
+                if (!rowany[r]) continue;
+                const int j = ja + r;
+                const float w = __builtin_fmaf(v, g.S[j], g.Bf);
+                const float t = __builtin_fmaf(u, g.C[j], w);
+                if (t >= 0.0f && t < g.nrho_f) {
+                    const int k = (int)t;
+                    if ((dil[(size_t)r * words + (k >> 5)] >> (k & 31)) & 1u) { kept = 1; break; }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (in) keep[i] = (uint8_t)kept;
+}
+
+// ------------------------------------------------------------------------ fused batch path
+// One workgroup processes one event at a time, taken from a global work counter; the event's
+// theta tiles are processed in order: zero, vote, find peaks, list + mark, retain.  The keep
+// bits of the event's hits live in LDS until the event is done.
+// queue[0] is the work counter and queue[1] counts workgroups that have left the loop; the
+// last one to leave (every pop has then happened) puts both back to zero for the next launch,
+// so a launch is a single kernel with no memset.
+template <int NW, int G>
+__global__ __launch_bounds__(NW * 64) void k_batch(GridArgs g, BatchArgs a, int n_tiles, int nwords) {
+    constexpr int TW = 64 * G, OUT = TW - 2, NT = NW * 64;
+    extern __shared__ __align__(16) uint32_t lds[];
+    uint32_t *tile = lds;                                                  // [(n_rho + 1) * TW]
+    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * TW);   // [NW * 64]
+    uint32_t *sidx = reinterpret_cast<uint32_t *>(stage + NW * 64);        // [NW * 64]
+    uint32_t *pmask = sidx + NW * 64;                                      // [nwords * TW]
+    uint32_t *keepbits = pmask + (size_t)nwords * TW;                      // [kMaxBatchHits / 32]
+    __shared__ uint32_t s_event, s_npeaks, s_tile_peaks, s_flags;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_event = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const uint32_t e = s_event;
+        if (e >= a.n_events) {
+            if (threadIdx.x == 0 && atomicAdd(a.queue + 1, 1u) == gridDim.x - 1u) {
+                __hip_atomic_store(a.queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(a.queue + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            break;
+        }
+        const uint32_t h0 = a.offsets[e], h1 = a.offsets[e + 1];
+        if (h1 < h0) {                       // malformed offsets: touch nothing but the counters
+            if (threadIdx.x == 0) { a.n_peaks[e] = 0u; a.status[e] = HOUGH_EV_TOO_MANY_HITS; }
+            __syncthreads();
+            continue;
+        }
+        const uint32_t H = h1 - h0;
+        if (H > kMaxBatchHits || H == 0u) {
+            for (uint32_t i = threadIdx.x; i < H; i += NT) a.keep[h0 + i] = 0u;
+            if (threadIdx.x == 0) {
+                a.n_peaks[e] = 0u;
+                a.status[e] = H ? HOUGH_EV_TOO_MANY_HITS : 0u;
+            }
+            __syncthreads();
+            continue;
+        }
+        for (uint32_t i = threadIdx.x; i < (H + 31u) / 32u; i += NT) keepbits[i] = 0u;
+        if (threadIdx.x == 0) { s_npeaks = 0u; s_flags = 0u; }
+        const uint32_t hb = (uint32_t)((uint64_t)H * wave / NW);
+        const uint32_t he = (uint32_t)((uint64_t)H * (wave + 1) / NW);
+        const float *xe = a.x + h0, *ye = a.y + h0;
+        hough_peak *pe = a.peaks ? a.peaks + (size_t)e * a.max_peaks : nullptr;
+        uint32_t bad = 0;
+        for (int t = 0; t < n_tiles; ++t) {
+            const int first = t * OUT - 1;      // grid column of lane 0 of group 0
+            const Cols<G> cl = load_cols<G>(g, first, lane);
+            for (int i = threadIdx.x; i < (g.n_rho + 1) * TW / 4; i += NT)
+                reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
+            __syncthreads();
+            vote_range<G>(tile, stage + wave * 64, xe, ye, hb, he, cl, g, lane, bad);
+            __syncthreads();
+            for (int unit = wave; unit < G * nwords; unit += NW) {
+                const int q = unit / nwords, wd = unit - q * nwords;
+                const int c = 64 * q + lane;
+                const int j = first + c;
+                const bool out_col = (c >= 1) && (c <= TW - 2) && (j < g.n_theta);
+                const uint32_t m = peak_word<TW>(tile, c, wd, g.n_rho, g.threshold);
+                pmask[wd * TW + c] = out_col ? m : 0u;
+            }
+            __syncthreads();
+            if (wave == 0) {
+                const uint32_t n = emit_and_mark<G>(tile, pmask, nwords, first, g, pe,
+                                                    pe ? a.max_peaks : 0u, s_npeaks, lane);
+                if (lane == 0) { s_npeaks += n; s_tile_peaks = n; }
+            }
+            __syncthreads();
+            if (s_tile_peaks)
+                retain_range<G>(tile, stage + wave * 64, sidx + wave * 64, xe, ye, hb, he,
+                                keepbits, cl, g, lane);
+            __syncthreads();
+        }
+        if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
+        for (uint32_t i = threadIdx.x; i < H; i += NT)
+            a.keep[h0 + i] = (uint8_t)((keepbits[i >> 5] >> (i & 31)) & 1u);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t np = s_npeaks;
+            a.n_peaks[e] = np;
+            a.status[e] = s_flags | (np > a.max_peaks ? HOUGH_EV_PEAKS_TRUNCATED : 0u);
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int kVoteWaves = 16;
+constexpr int kPeakWaves = 16;
+constexpr int kRetainWaves = 8;
+
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace
+
+size_t vote_lds_bytes(int n_rho) {
+    return (size_t)(n_rho + 1) * 64 * 4 + (size_t)kVoteWaves * 64 * sizeof(float2) + 256;
+}
+
+size_t peaks_lds_bytes(int n_rho) { return (size_t)(kPeakWaves + 2) * n_rho * 4 + 256; }
+
+size_t batch_lds_bytes(int n_rho, int waves, int groups) {
+    const size_t tw = 64u * groups, nwords = (size_t)(n_rho + 31) / 32;
+    return (size_t)(n_rho + 1) * tw * 4 + (size_t)waves * kStageBytes + nwords * tw * 4 +
+           kMaxBatchHits / 8;
+}
+
+int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out) {
+    if (!(waves == 4 || waves == 8 || waves == 16) || !(groups == 1 || groups == 2)) return -1;
+    BatchPlan p{};
+    p.waves = waves;
+    p.groups = groups;
+    p.tile_cols = 64 * groups;
+    p.out_cols = p.tile_cols - 2;
+    p.n_tiles = (n_theta + p.out_cols - 1) / p.out_cols;
+    p.lds_bytes = batch_lds_bytes(n_rho, waves, groups);
+    if (p.lds_bytes + 256 > lds_limit) return -1;      // room for the kernel's static LDS
+    p.grid = 0;
+    *out = p;
+    return 0;
+}
+
+hipError_t launch_vote(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
+                       void *acc, int acc_type, hipStream_t s) {
+    const size_t lds = vote_lds_bytes(g.n_rho);
+    allow_lds(k_vote<kVoteWaves>, lds);
+    const int blocks = (g.n_theta + 63) / 64;
+    hipLaunchKernelGGL(k_vote<kVoteWaves>, dim3(blocks), dim3(kVoteWaves * 64), lds, s, g, x, y,
+                       n_hits, acc, acc_type);
+    return hipGetLastError();
+}
+
+hipError_t launch_peaks(const GridArgs &g, const void *acc, int acc_type, hough_peak *peaks,
+                        uint32_t cap, uint32_t *n_peaks, hipStream_t s) {
+    const size_t lds = peaks_lds_bytes(g.n_rho);
+    if (acc_type == HOUGH_ACC_U16) {
+        allow_lds(k_peaks<kPeakWaves, uint16_t>, lds);
+        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint16_t>), dim3(1), dim3(kPeakWaves * 64), lds, s, g,
+                           static_cast<const uint16_t *>(acc), peaks, cap, n_peaks);
+    } else {
+        allow_lds(k_peaks<kPeakWaves, uint32_t>, lds);
+        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint32_t>), dim3(1), dim3(kPeakWaves * 64), lds, s, g,
+                           static_cast<const uint32_t *>(acc), peaks, cap, n_peaks);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_retain(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
+                         const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
+                         uint8_t *keep, hipStream_t s) {
+    if (n_hits == 0) return hipSuccess;
+    const int words = (g.n_rho + 31) / 32;
+    const size_t budget = 60 * 1024;
+    int rows = (int)(budget / ((size_t)words * 4 + 4));
+    if (rows > g.n_theta) rows = g.n_theta;
+    if (rows < 1) rows = 1;
+    const size_t lds = (size_t)rows * words * 4 + (size_t)rows * 4;
+    allow_lds(k_retain<kRetainWaves>, lds);
+    const int blocks = (int)((n_hits + kRetainWaves * 64 - 1) / (kRetainWaves * 64));
+    hipLaunchKernelGGL(k_retain<kRetainWaves>, dim3(blocks), dim3(kRetainWaves * 64), lds, s, g, x, y,
+                       n_hits, peaks, n_peaks, cap, keep, rows);
+    return hipGetLastError();
+}
+
+template <int NW, int G>
+static hipError_t launch_batch_t(const GridArgs &g, const BatchPlan &p, const BatchArgs &a,
+                                 hipStream_t s) {
+    allow_lds(k_batch<NW, G>, p.lds_bytes);
+    const int nwords = (g.n_rho + 31) / 32;
+    hipLaunchKernelGGL((k_batch<NW, G>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
+                       p.n_tiles, nwords);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const GridArgs &g, const BatchPlan &p, const BatchArgs &a, hipStream_t s) {
+    switch (p.waves * 10 + p.groups) {
+        case 41: return launch_batch_t<4, 1>(g, p, a, s);
+        case 42: return launch_batch_t<4, 2>(g, p, a, s);
+        case 81: return launch_batch_t<8, 1>(g, p, a, s);
+        case 82: return launch_batch_t<8, 2>(g, p, a, s);
+        case 161: return launch_batch_t<16, 1>(g, p, a, s);
+        case 162: return launch_batch_t<16, 2>(g, p, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Workgroups of the fused kernel that fit one CU at once (for sizing the persistent grid).
+int batch_blocks_per_cu(const BatchPlan &p) {
+    int n = 0;
+    hipError_t err = hipErrorInvalidValue;
+    switch (p.waves * 10 + p.groups) {
+        case 41: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<4, 1>, 256, p.lds_bytes); break;
+        case 42: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<4, 2>, 256, p.lds_bytes); break;
+        case 81: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<8, 1>, 512, p.lds_bytes); break;
+        case 82: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<8, 2>, 512, p.lds_bytes); break;
+        case 161: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<16, 1>, 1024, p.lds_bytes); break;
+        case 162: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<16, 2>, 1024, p.lds_bytes); break;
+        default: break;
+    }
+    return err == hipSuccess ? n : 0;
+}
+
+}  // namespace hough

@@ -1,0 +1,244 @@
+"""ctypes binding of libhough.so (see include/hough.h for the exact semantics).
+
+This module only marshals arguments: it checks that tensors live on the GPU with the right
+dtype and layout, passes their device pointers and torch's current HIP stream to the C ABI,
+and decodes results.  Every step of the method runs in the library's HIP kernels; there is no
+fallback, and loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhough.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "hough.h")
+
+HOUGH_OK, HOUGH_EINVAL, HOUGH_ENOMEM, HOUGH_EOVERFLOW, HOUGH_EDEVICE = 0, -1, -2, -3, -4
+ACC_U16, ACC_I32 = 1, 2
+EV_PEAKS_TRUNCATED, EV_INVALID_HITS, EV_TOO_MANY_HITS = 1, 2, 4
+
+
+class HoughError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what} failed: {status_string(status)} ({status})")
+        self.status = status
+
+
+class hough_params(ctypes.Structure):
+    _fields_ = [("n_theta", ctypes.c_int32), ("n_rho", ctypes.c_int32),
+                ("rho_min", ctypes.c_double), ("rho_max", ctypes.c_double),
+                ("acc_type", ctypes.c_int32), ("threshold", ctypes.c_int32),
+                ("rho_window", ctypes.c_int32), ("max_peaks", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhough.so (raises if it is not built; nothing runs without it)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_2607_04067_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, u32, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int
+    L.hough_config.argtypes = [ctypes.POINTER(hough_params), ctypes.POINTER(vp)]
+    L.hough_config.restype = i32
+    L.hough_destroy.argtypes = [vp]
+    L.hough_destroy.restype = None
+    L.hough_get_params.argtypes = [vp, ctypes.POINTER(hough_params)]
+    L.hough_get_params.restype = i32
+    L.hough_vote.argtypes = [vp, vp, vp, u32, vp, vp]
+    L.hough_vote.restype = i32
+    L.hough_peaks.argtypes = [vp, vp, vp, u32, vp, vp]
+    L.hough_peaks.restype = i32
+    L.hough_retain.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp]
+    L.hough_retain.restype = i32
+    L.hough_run_batch.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp]
+    L.hough_run_batch.restype = i32
+    L.hough_max_batch_hits.argtypes = [vp]
+    L.hough_max_batch_hits.restype = u32
+    L.hough_max_n_rho.argtypes = []
+    L.hough_max_n_rho.restype = ctypes.c_int32
+    L.hough_status_string.argtypes = [i32]
+    L.hough_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def status_string(status: int) -> str:
+    return load().hough_status_string(int(status)).decode()
+
+
+def header_functions(path: str = HEADER_PATH) -> list[str]:
+    """Names of the functions include/hough.h declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hough_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(rc: int, what: str):
+    if rc != HOUGH_OK:
+        raise HoughError(rc, what)
+
+
+def _dev(t: torch.Tensor, dtype, name: str, numel: int | None = None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} needs at least {numel} elements, has {t.numel()}")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def decode_peaks(peaks: torch.Tensor | np.ndarray, n: int | None = None) -> np.ndarray:
+    """hough_peak records (int32 pairs) -> int64 array [n, 3] of (theta_bin, rho_bin, count)."""
+    a = peaks.detach().cpu().numpy() if isinstance(peaks, torch.Tensor) else np.asarray(peaks)
+    a = a.reshape(-1, 2).view(np.uint32)
+    if n is not None:
+        a = a[:n]
+    return np.stack([a[:, 0] & 0xFFFF, a[:, 0] >> 16, a[:, 1]], axis=1).astype(np.int64)
+
+
+class Context:
+    """One configured (theta, rho) grid on the current GPU (wraps hough_ctx)."""
+
+    def __init__(self, n_theta: int, n_rho: int, rho_min: float, rho_max: float, acc_type: str = "i32",
+                 threshold: int = 1, rho_window: int = 1, max_peaks: int = 0):
+        self._lib = load()
+        self.params = hough_params(int(n_theta), int(n_rho), float(rho_min), float(rho_max),
+                                   ACC_U16 if acc_type == "u16" else ACC_I32, int(threshold),
+                                   int(rho_window), int(max_peaks))
+        self.acc_type = acc_type
+        self._ctx = ctypes.c_void_p()
+        _check(self._lib.hough_config(ctypes.byref(self.params), ctypes.byref(self._ctx)), "hough_config")
+        self._dummy = torch.zeros(8, dtype=torch.int32, device="cuda")
+
+    @classmethod
+    def for_workload(cls, wl, max_peaks: int = 4096, threshold: int | None = None,
+                     rho_window: int | None = None) -> "Context":
+        return cls(wl.n_theta, wl.n_rho, wl.rho_min, wl.rho_max, wl.acc,
+                   wl.threshold if threshold is None else threshold,
+                   wl.rho_window if rho_window is None else rho_window, max_peaks)
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            self._lib.hough_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_theta(self) -> int:
+        return self.params.n_theta
+
+    @property
+    def n_rho(self) -> int:
+        return self.params.n_rho
+
+    @property
+    def max_batch_hits(self) -> int:
+        return int(self._lib.hough_max_batch_hits(self._ctx))
+
+    def _ptr_or_dummy(self, t: torch.Tensor, dtype, name: str) -> int:
+        if t.numel() == 0:
+            return self._dummy.data_ptr()
+        return _dev(t, dtype, name)
+
+    # ------------------------------------------------------------------ plain path
+    def vote(self, x: torch.Tensor, y: torch.Tensor, acc: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Accumulator [n_theta, n_rho] (int32, or int16 holding uint16 bits) of one event."""
+        n = x.numel()
+        if y.numel() != n:
+            raise ValueError("x and y differ in length")
+        dt = torch.int16 if self.acc_type == "u16" else torch.int32
+        if acc is None:
+            acc = torch.empty((self.n_theta, self.n_rho), dtype=dt, device=x.device)
+        pa = _dev(acc, dt, "acc", self.n_theta * self.n_rho)
+        px = self._ptr_or_dummy(x, torch.float32, "x")
+        py = self._ptr_or_dummy(y, torch.float32, "y")
+        _check(self._lib.hough_vote(self._ctx, px, py, n, pa, _stream(stream)), "hough_vote")
+        return acc
+
+    def peaks(self, acc: torch.Tensor, cap: int, peaks: torch.Tensor | None = None,
+              n_peaks: torch.Tensor | None = None, stream=None):
+        """(peaks int32 [cap, 2] hough_peak records, n_peaks int32 [1] true count)."""
+        dt = torch.int16 if self.acc_type == "u16" else torch.int32
+        pa = _dev(acc, dt, "acc", self.n_theta * self.n_rho)
+        if peaks is None:
+            peaks = torch.zeros((max(cap, 1), 2), dtype=torch.int32, device=acc.device)
+        if n_peaks is None:
+            n_peaks = torch.zeros(1, dtype=torch.int32, device=acc.device)
+        pp = _dev(peaks, torch.int32, "peaks", 2 * cap)
+        pn = _dev(n_peaks, torch.int32, "n_peaks", 1)
+        _check(self._lib.hough_peaks(self._ctx, pa, pp, int(cap), pn, _stream(stream)), "hough_peaks")
+        return peaks, n_peaks
+
+    def retain(self, x: torch.Tensor, y: torch.Tensor, peaks: torch.Tensor, n_peaks: torch.Tensor, cap: int,
+               keep: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        n = x.numel()
+        if keep is None:
+            keep = torch.empty(n, dtype=torch.uint8, device=x.device)
+        pk = self._ptr_or_dummy(keep, torch.uint8, "keep")
+        pp = _dev(peaks, torch.int32, "peaks", 2 * cap)
+        pn = _dev(n_peaks, torch.int32, "n_peaks", 1)
+        px = self._ptr_or_dummy(x, torch.float32, "x")
+        py = self._ptr_or_dummy(y, torch.float32, "y")
+        _check(self._lib.hough_retain(self._ctx, px, py, n, pp, pn, int(cap), pk, _stream(stream)),
+               "hough_retain")
+        return keep
+
+    # ----------------------------------------------------------------- fused batch
+    def run_batch(self, x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, peaks: torch.Tensor | None = None,
+                  n_peaks: torch.Tensor | None = None, keep: torch.Tensor | None = None,
+                  status: torch.Tensor | None = None, stream=None):
+        """Whole path over CSR events.  offsets: int32 [E+1] (uint32 values).
+        Returns (peaks int32 [E, max_peaks, 2], n_peaks int32 [E], keep uint8 [H], status int32 [E])."""
+        E = offsets.numel() - 1
+        mp = self.params.max_peaks
+        dev = offsets.device
+        if peaks is None:
+            peaks = torch.zeros((max(E, 1), max(mp, 1), 2), dtype=torch.int32, device=dev)
+        if n_peaks is None:
+            n_peaks = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
+        if status is None:
+            status = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
+        if keep is None:
+            keep = torch.zeros(x.numel(), dtype=torch.uint8, device=dev)
+        po = _dev(offsets, torch.int32, "offsets", E + 1)
+        pp = _dev(peaks, torch.int32, "peaks", 2 * E * mp) if mp > 0 else 0
+        pn = _dev(n_peaks, torch.int32, "n_peaks", E)
+        ps = _dev(status, torch.int32, "status", E)
+        pk = self._ptr_or_dummy(keep, torch.uint8, "keep")
+        px = self._ptr_or_dummy(x, torch.float32, "x")
+        py = self._ptr_or_dummy(y, torch.float32, "y")
+        _check(self._lib.hough_run_batch(self._ctx, px, py, po, E, pp, pn, pk, ps, _stream(stream)),
+               "hough_run_batch")
+        return peaks, n_peaks, keep, status
+
+
+def to_device(batch, device="cuda"):
+    """Move an EventBatch's hits and offsets to the GPU (x, y float32; offsets int32)."""
+    x = torch.from_numpy(np.ascontiguousarray(batch.x)).to(device)
+    y = torch.from_numpy(np.ascontiguousarray(batch.y)).to(device)
+    off = torch.from_numpy(batch.offsets.astype(np.int64).astype(np.int32)).to(device)
+    return x, y, off

@@ -1,0 +1,59 @@
+"""Host-only checks of the C-ABI library: it loads and exports what include/hough.h declares.
+
+No compute call is made here (there is no GPU in this environment)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2607_04067_amd", "libhough.so")
+
+
+@pytest.fixture(scope="module")
+def hough_mod():
+    if not os.path.exists(LIB):
+        from paper_2607_04067_amd import build
+        build.build()
+    from paper_2607_04067_amd import hough
+    return hough
+
+
+def test_library_exports_every_declared_function(hough_mod):
+    lib = hough_mod.load()
+    names = hough_mod.header_functions()
+    assert {"hough_config", "hough_vote", "hough_peaks", "hough_retain", "hough_run_batch"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layouts_match_header(hough_mod):
+    # hough_params: 2 x int32, 2 x double, 4 x int32 = 40 bytes; hough_peak: 8 bytes
+    assert ctypes.sizeof(hough_mod.hough_params) == 40
+    text = open(os.path.join(ROOT, "include", "hough.h")).read()
+    peak = re.search(r"typedef struct hough_peak \{(.*?)\}", text, re.S).group(1)
+    assert re.findall(r"(uint\d+_t)", peak) == ["uint16_t", "uint16_t", "uint32_t"]
+
+
+def test_status_strings(hough_mod):
+    for code in (0, -1, -2, -3, -4):
+        assert hough_mod.status_string(code) != "unknown status"
+
+
+def test_peak_record_decoding(hough_mod):
+    import numpy as np
+    rec = np.array([[3 | (17 << 16), 42], [65535 | (1 << 16), 7]], dtype=np.uint32).view(np.int32)
+    assert hough_mod.decode_peaks(rec).tolist() == [[3, 17, 42], [65535, 1, 7]]
+
+
+def test_product_path_never_touches_the_oracle():
+    """Nothing under the package may import, load or run the CPU oracle."""
+    pkg = os.path.join(ROOT, "paper_2607_04067_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                for pat in (r"import\s+oracle", r"from\s+oracle", r"liboracle", r"hough_oracle",
+                            r"oracle_[a-z]+\s*\("):
+                    assert not re.search(pat, text), (f, pat)

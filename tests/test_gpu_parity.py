@@ -1,0 +1,293 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every output is an integer (accumulator counts, peak cells and counts, keep flags), so the bar
+is equality.  Small cases cover several theta tiles and ragged tails; the full-size workloads
+run in the launch configuration the benchmark uses and are checked on sampled events.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2607_04067_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_04067_amd import hough
+    hough.load()
+    return hough
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _acc_np(acc, acc_type):
+    a = acc.cpu().numpy()
+    return a.view(np.uint16).astype(np.int32) if acc_type == "u16" else a
+
+
+def _oracle_peaks(orc, acc, T):
+    pj, pk, pc, n = orc.peaks(acc, T)
+    return np.stack([pj, pk, pc], 1).astype(np.int64), n
+
+
+def _plain_event(H, ctx, x, y, cap):
+    acc = ctx.vote(_t(x), _t(y))
+    peaks, npk = ctx.peaks(acc, cap)
+    keep = ctx.retain(_t(x), _t(y), peaks, npk, cap)
+    return acc, peaks, npk, keep
+
+
+SAMPLES = [("plain-16ev-180x128", 16), ("paper-1000ev-360x256", 4), ("batch-10000ev-360x256", 4),
+           ("dense-2000ev-720x512", 2)]
+
+
+@pytest.mark.parametrize("name,n_events", SAMPLES)
+def test_plain_path_parity(H, orc, name, n_events):
+    wl = synth.WORKLOADS[name]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 0, n_events=n_events)
+    for T in sorted({wl.threshold, 30, 40}):
+        ctx = H.Context.for_workload(wl, threshold=T)
+        for e in range(n_events):
+            say(f"plain {name} T={T} event={e}")
+            x, y = ev.event(e)
+            acc_ref = orc.vote(g, x, y)
+            cap = 1 << 15
+            acc, peaks, npk, keep = _plain_event(H, ctx, x, y, cap)
+            assert np.array_equal(_acc_np(acc, wl.acc), acc_ref)
+            ref, n_ref = _oracle_peaks(orc, acc_ref, T)
+            assert int(npk.item()) == n_ref
+            assert np.array_equal(H.decode_peaks(peaks, n_ref), ref)
+            keep_ref = orc.retain(g, x, y, ref[:, 0], ref[:, 1], wl.rho_window)
+            assert np.array_equal(keep.cpu().numpy(), keep_ref)
+        ctx.close()
+
+
+def test_peaks_truncation_and_retain_windows(H, orc):
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    g = orc.Grid.of(wl)
+    x, y = synth.make_events(wl, 0, n_events=1).event(0)
+    acc_ref = orc.vote(g, x, y)
+    for W in (0, 1, 3, 17):
+        ctx = H.Context.for_workload(wl, threshold=30, rho_window=W)
+        acc = ctx.vote(_t(x), _t(y))
+        ref, n_ref = _oracle_peaks(orc, acc_ref, 30)
+        for cap in (0, 1, 5, n_ref, n_ref + 3):
+            peaks, npk = ctx.peaks(acc, cap)
+            assert int(npk.item()) == n_ref
+            m = min(cap, n_ref)
+            assert np.array_equal(H.decode_peaks(peaks, m), ref[:m])
+            keep = ctx.retain(_t(x), _t(y), peaks, npk, cap)     # retains with the first cap peaks
+            keep_ref = orc.retain(g, x, y, ref[:m, 0], ref[:m, 1], W)
+            assert np.array_equal(keep.cpu().numpy(), keep_ref), (W, cap)
+        ctx.close()
+
+
+def _batch_check(H, orc, ctx, g, T, W, x, y, offsets, max_peaks):
+    import torch
+    xt, yt, ot = _t(x), _t(y), _t(offsets.astype(np.int64).astype(np.int32))
+    peaks, npk, keep, status = ctx.run_batch(xt, yt, ot)
+    torch.cuda.synchronize()
+    pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, offsets, threshold=T, rho_window=W,
+                                            cap=max(max_peaks, 1), n_threads=8)
+    npk = npk.cpu().numpy()[:len(offsets) - 1]
+    assert np.array_equal(npk.astype(np.int64), n_ref)
+    assert np.array_equal(keep.cpu().numpy()[:x.size], keep_ref)
+    p = peaks.cpu().numpy()
+    for e in range(len(offsets) - 1):
+        m = int(min(n_ref[e], max_peaks))
+        if m:
+            assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), e
+    return status.cpu().numpy()[:len(offsets) - 1]
+
+
+@pytest.mark.parametrize("name,n_events", [("plain-16ev-180x128", 16), ("paper-1000ev-360x256", 24),
+                                           ("batch-10000ev-360x256", 24), ("dense-2000ev-720x512", 4)])
+def test_run_batch_parity(H, orc, name, n_events):
+    wl = synth.WORKLOADS[name]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 0, n_events=n_events)
+    for T, mp in [(wl.threshold, 20000), (wl.threshold, 100), (40, 64)]:
+        say(f"batch {name} T={T} max_peaks={mp}")
+        ctx = H.Context.for_workload(wl, threshold=T, max_peaks=mp)
+        st = _batch_check(H, orc, ctx, g, T, wl.rho_window, ev.x, ev.y, ev.offsets, mp)
+        n_ref = orc.run_batch(g, ev.x, ev.y, ev.offsets, threshold=T, rho_window=1, cap=1)[1]
+        assert np.array_equal(st & H.EV_PEAKS_TRUNCATED, (n_ref > mp).astype(np.int32))
+        ctx.close()
+
+
+def _edge_events():
+    """Events that exercise every special case of the path."""
+    rng = np.random.default_rng(77)
+    evs = []
+    evs.append((np.zeros(0, np.float32), np.zeros(0, np.float32)))                    # empty
+    evs.append((np.float32([350.0]), np.float32([-120.0])))                            # one hit
+    x, y = synth.random_hits(300, seed=5, r_lo=150.0, r_hi=1200.0)                     # rho out of range
+    evs.append((x, y))
+    x, y = synth.random_hits(200, seed=6, r_lo=199.0, r_hi=201.0)                      # |rho| at the edge
+    evs.append((x, y))
+    ang = rng.uniform(0, 2 * np.pi, 64)
+    evs.append(((200.0 * np.cos(ang)).astype(np.float32), (200.0 * np.sin(ang)).astype(np.float32)))
+    x, y = synth.random_hits(120, seed=7)
+    x = x.copy(); y = y.copy()
+    x[:6] = [0.0, np.nan, np.inf, 1e20, -0.0, 1e-23]; y[:6] = [0.0, 1.0, 0.0, 0.0, 0.0, 0.0]
+    evs.append((x, y))                                                                 # invalid hits
+    x, y = synth.random_hits(40, seed=8)
+    evs.append((np.tile(x, 5), np.tile(y, 5)))                                         # duplicates
+    ev = synth.make_events("dense-2000ev-720x512", 3, n_events=1)
+    evs.append(ev.event(0))
+    return evs
+
+
+@pytest.mark.parametrize("n_theta,n_rho,lo,hi", [(180, 128, -1 / 200, 1 / 200), (61, 33, -0.004, 0.006),
+                                                 (62, 64, -0.005, 0.005), (63, 100, -0.0045, 0.0047),
+                                                 (125, 7, -0.003, 0.004), (1, 1, -0.005, 0.005),
+                                                 (200, 320, -0.006, 0.002), (124, 31, 0.0, 0.005)])
+def test_edge_cases_all_entry_points(H, orc, n_theta, n_rho, lo, hi):
+    g = orc.Grid(n_theta, n_rho, lo, hi)
+    evs = _edge_events()
+    for T in (1, 3, 9):
+        ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, 1, 512)
+        for i, (x, y) in enumerate(evs):
+            say(f"edge grid={n_theta}x{n_rho} T={T} event={i} hits={x.size}")
+            acc_ref = orc.vote(g, x, y)
+            acc, peaks, npk, keep = _plain_event(H, ctx, x, y, 1 << 16)
+            assert np.array_equal(acc.cpu().numpy(), acc_ref)
+            ref, n_ref = _oracle_peaks(orc, acc_ref, T)
+            assert int(npk.item()) == n_ref and np.array_equal(H.decode_peaks(peaks, n_ref), ref)
+            assert np.array_equal(keep.cpu().numpy(), orc.retain(g, x, y, ref[:, 0], ref[:, 1], 1))
+        xs = np.concatenate([e[0] for e in evs]); ys = np.concatenate([e[1] for e in evs])
+        offs = np.zeros(len(evs) + 1, np.uint32); offs[1:] = np.cumsum([e[0].size for e in evs])
+        st = _batch_check(H, orc, ctx, g, T, 1, xs, ys, offs, 512)
+        assert st[5] & H.EV_INVALID_HITS and not (st[2] & H.EV_INVALID_HITS)
+        ctx.close()
+
+
+def test_u16_accumulator_and_overflow_guard(H, orc):
+    import torch
+    wl = synth.WORKLOADS["plain-16ev-180x128"]
+    g = orc.Grid.of(wl)
+    ctx = H.Context.for_workload(wl)
+    x, y = synth.random_hits(65536, seed=3)
+    with pytest.raises(H.HoughError) as ei:
+        ctx.vote(_t(x), _t(y))
+    assert ei.value.status == H.HOUGH_EOVERFLOW
+    acc = ctx.vote(_t(x[:65535]), _t(y[:65535]))             # the largest event u16 accepts
+    assert np.array_equal(_acc_np(acc, "u16"), orc.vote(g, x[:65535], y[:65535]))
+    ctx.close()
+
+
+def test_large_events_in_batch(H, orc):
+    """Events up to the fused kernel's hit limit are exact; larger ones are flagged and zeroed."""
+    g = orc.Grid(360, 256, -1 / 200, 1 / 200)
+    ctx = H.Context(360, 256, -1 / 200, 1 / 200, "i32", 40, 1, 4096)
+    lim = ctx.max_batch_hits
+    x1, y1 = synth.random_hits(lim, seed=1, r_lo=200, r_hi=810)
+    x2, y2 = synth.random_hits(lim + 1, seed=2, r_lo=200, r_hi=810)
+    x3, y3 = synth.random_hits(50, seed=3, r_lo=200, r_hi=810)
+    xs = np.concatenate([x1, x2, x3]); ys = np.concatenate([y1, y2, y3])
+    offs = np.array([0, lim, 2 * lim + 1, 2 * lim + 51], np.uint32)
+    import torch
+    peaks, npk, keep, st = ctx.run_batch(_t(xs), _t(ys), _t(offs.astype(np.int32)))
+    torch.cuda.synchronize()
+    st = st.cpu().numpy(); npk = npk.cpu().numpy(); keep = keep.cpu().numpy()
+    assert st[1] == H.EV_TOO_MANY_HITS and npk[1] == 0 and not keep[lim:2 * lim + 1].any()
+    for e, (a, b) in [(0, (0, lim)), (2, (2 * lim + 1, 2 * lim + 51))]:
+        acc = orc.vote(g, xs[a:b], ys[a:b])
+        ref, n_ref = _oracle_peaks(orc, acc, 40)
+        assert npk[e] == n_ref and st[e] == (H.EV_PEAKS_TRUNCATED if n_ref > 4096 else 0)
+        m = min(n_ref, 4096)
+        assert np.array_equal(H.decode_peaks(peaks[e].cpu(), m), ref[:m])
+        assert np.array_equal(keep[a:b], orc.retain(g, xs[a:b], ys[a:b], ref[:, 0], ref[:, 1], 1))
+    ctx.close()
+
+
+def test_determinism_and_batch_independence(H):
+    import torch
+    wl = synth.WORKLOADS["batch-10000ev-360x256"]
+    ev = synth.make_events(wl, 0, n_events=300)
+    ctx = H.Context.for_workload(wl, max_peaks=8192)
+    xt, yt, ot = H.to_device(ev)
+    first = [t.clone() for t in ctx.run_batch(xt, yt, ot)]
+    for _ in range(3):
+        again = ctx.run_batch(xt, yt, ot)
+        assert all(torch.equal(a, b) for a, b in zip(first, again))
+    for e in (0, 137, 299):            # an event alone equals the same event inside the batch
+        sub = ev.subset([e])
+        xs, ys, os_ = H.to_device(sub)
+        p, n, k, s = ctx.run_batch(xs, ys, os_)
+        a, b = int(ev.offsets[e]), int(ev.offsets[e + 1])
+        assert torch.equal(n[0], first[1][e]) and torch.equal(k, first[2][a:b])
+        m = min(int(n[0]), 8192)
+        assert torch.equal(p[0, :m], first[0][e, :m])
+    # permuting the hits of an event permutes keep and leaves the peaks unchanged
+    x, y = ev.event(5)
+    perm = np.random.default_rng(0).permutation(x.size)
+    offs = np.array([0, x.size], np.int32)
+    p1, n1, k1, _ = ctx.run_batch(_t(x), _t(y), _t(offs))
+    p2, n2, k2, _ = ctx.run_batch(_t(x[perm]), _t(y[perm]), _t(offs))
+    assert torch.equal(n1, n2) and torch.equal(p1, p2)
+    assert np.array_equal(k1.cpu().numpy()[perm], k2.cpu().numpy())
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["paper-1000ev-360x256", "batch-10000ev-360x256", "dense-2000ev-720x512"])
+def test_full_size_sampled(H, orc, name):
+    """The whole workload in one launch (as timed by the benchmark); sampled events vs oracle."""
+    import torch
+    from bench import MAX_PEAKS
+    wl = synth.WORKLOADS[name]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 0)
+    ctx = H.Context.for_workload(wl, max_peaks=MAX_PEAKS[name])
+    xt, yt, ot = H.to_device(ev)
+    say(f"full {name}: {ev.n_events} events, {ev.n_hits} hits")
+    peaks, npk, keep, st = ctx.run_batch(xt, yt, ot)
+    torch.cuda.synchronize()
+    npk = npk.cpu().numpy(); keep = keep.cpu().numpy(); st = st.cpu().numpy()
+    assert np.all(st == 0)
+    sample = np.unique(np.linspace(0, ev.n_events - 1, 10).astype(int))
+    sub = ev.subset(sample)
+    pk_ref, n_ref, keep_ref = orc.run_batch(wl, sub.x, sub.y, sub.offsets, cap=MAX_PEAKS[name], n_threads=8)
+    for i, e in enumerate(sample):
+        a, b = int(ev.offsets[e]), int(ev.offsets[e + 1])
+        assert npk[e] == n_ref[i]
+        assert np.array_equal(keep[a:b], keep_ref[int(sub.offsets[i]):int(sub.offsets[i + 1])])
+        m = int(n_ref[i])
+        assert np.array_equal(H.decode_peaks(peaks[e].cpu(), m), pk_ref[i, :m].astype(np.int64))
+    ctx.close()
+
+
+def test_invalid_arguments(H):
+    import torch
+    with pytest.raises(H.HoughError):
+        H.Context(360, 256, -0.005, 0.005, "i32", 0)               # threshold < 1
+    with pytest.raises(H.HoughError):
+        H.Context(360, 256, 0.005, -0.005)                          # empty rho range
+    with pytest.raises(H.HoughError):
+        H.Context(0, 256, -0.005, 0.005)
+    big = int(H.load().hough_max_n_rho())
+    assert big >= 512
+    with pytest.raises(H.HoughError):
+        H.Context(360, big + 1, -0.005, 0.005)
+    ctx = H.Context(360, big, -0.005, 0.005, "i32", 3, 1, 16)
+    x, y = synth.random_hits(100, seed=1)
+    acc = ctx.vote(_t(x), _t(y))
+    assert int(acc.sum()) > 0
+    with pytest.raises(ValueError):
+        ctx.vote(torch.from_numpy(x), torch.from_numpy(y))        # host tensors are refused
+    ctx.close()
