@@ -27,7 +27,7 @@ from paper_2607_04067_amd import synth  # noqa: E402
 METRIC = "events/s + Gvotes/s on 1 MI355X; p50/p99 event latency, served vs plain"
 DEFAULT_WORKLOAD = "paper-1000ev-360x256"
 # Per-event capacity of the peak list; every event of these workloads fits (no truncation).
-MAX_PEAKS = {"plain-16ev-180x128": 1024, "paper-1000ev-360x256": 4096,
+MAX_PEAKS = {"plain-16ev-180x128": 1024, "paper-1000ev-360x256": 8192,
              "batch-10000ev-360x256": 8192, "dense-2000ev-720x512": 16384}
 
 # MI355X: 256 CUs, 4 SIMD16 units each, 2.4 GHz peak engine clock.
