@@ -43,19 +43,19 @@ bool grid_fits(int n_rho, size_t limit) {
     return hough::plan_batch(1, n_rho, 4, 1, limit, &p) == 0;
 }
 
-// Default launch shape of the fused kernel: the most waves per workgroup that still lets the
-// tile's LDS footprint keep at least one workgroup per CU, preferring two workgroups per CU.
+// Default launch shape of the fused kernel: the candidate with the most resident waves per CU
+// (from the occupancy API, which accounts for LDS, VGPRs and SGPRs), ties broken towards more
+// workgroups per CU so that one workgroup's barrier phases overlap another's votes.
 int default_plan(hough_ctx *c) {
-    const size_t cu_lds = 160 * 1024;
     int best = -1;
     hough::BatchPlan pick{};
-    const int waves_opts[3] = {16, 8, 4};
+    const int waves_opts[3] = {8, 16, 4};
     for (int wi = 0; wi < 3; ++wi) {
         hough::BatchPlan p;
         if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves_opts[wi], 1, c->lds_limit, &p) != 0) continue;
-        const int per_cu = (int)(cu_lds / p.lds_bytes);
-        const int waves_per_cu = per_cu * p.waves;
-        const int score = (per_cu >= 2 ? 1000 : 0) + waves_per_cu;
+        const int per_cu = hough::batch_blocks_per_cu(p);
+        if (per_cu < 1) continue;
+        const int score = per_cu * p.waves * 16 + per_cu;
         if (score > best) { best = score; pick = p; }
     }
     if (best < 0) return HOUGH_EINVAL;

@@ -11,8 +11,9 @@ namespace hough {
 // Lanes of a CDNA wavefront; every tile is a whole number of 64-column groups so that one
 // lane owns one theta column.
 constexpr int kWave = 64;
-// The fused batch kernel keeps one keep bit per hit of the event in LDS.
-constexpr uint32_t kMaxBatchHits = 32768;
+// Largest event of the fused batch kernel: a count then fits 15 bits of a packed 16-bit LDS
+// counter (the 16th bit is the retention mark), and the keep bits of the event fit LDS.
+constexpr uint32_t kMaxBatchHits = 32767;
 // Bit 31 of an LDS accumulator cell marks "within rho_window of a peak" during retention.
 constexpr uint32_t kMark = 0x80000000u;
 

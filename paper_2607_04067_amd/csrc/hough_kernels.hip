@@ -48,8 +48,8 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ __forceinline__ void lds_inc(uint32_t *p) {
-    __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+__device__ __forceinline__ void lds_add(uint32_t *p, uint32_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -77,6 +77,28 @@ __device__ __forceinline__ Cols<G> load_cols(const GridArgs &g, int first_col, i
     }
     return cl;
 }
+
+// Where a lane's cells live in a tile row.  Unpacked: one 32-bit counter per cell, column
+// 64q + l at dword 64q + l.  Packed: two 16-bit counters per dword, columns 64q + l and
+// 64q + l + 32 (l < 32) share dword 32q + l; the two lanes sharing a dword sit in different
+// halves of the wave, which the LDS serves in separate passes, so they never conflict.
+// The top bit of a counter marks "within rho_window of a peak" during retention.
+template <int G, bool PACKED>
+struct Lane {
+    static constexpr int TW = 64 * G;
+    static constexpr int STRIDE = PACKED ? TW / 2 : TW;    // dwords per tile row
+    uint32_t col[G];
+    uint32_t shift, inc, mark, cmask;
+    __device__ __forceinline__ explicit Lane(int lane) {
+#pragma unroll
+        for (int q = 0; q < G; ++q) col[q] = PACKED ? 32 * q + (lane & 31) : 64 * q + lane;
+        shift = PACKED ? 16u * (uint32_t)(lane >> 5) : 0u;
+        inc = 1u << shift;
+        mark = PACKED ? (0x8000u << shift) : kMark;
+        cmask = PACKED ? 0x7fffu : ~kMark;
+    }
+    __device__ __forceinline__ uint32_t count(uint32_t dword) const { return (dword >> shift) & cmask; }
+};
 
 // Map up to 64 hits [base, end) (one per lane) and compact the valid ones into the wave's
 // stage: all-in-range hits first, then the others.  Returns (n_safe, n_total) and, through
@@ -108,99 +130,132 @@ __device__ __forceinline__ StageCount stage_hits(float2 *st, uint32_t *sidx, con
     return StageCount{ns, ns + (uint32_t)__popcll(bu)};
 }
 
-// Steps 2-3: sweep the staged hits through the lane's columns and vote.
-template <int G>
-__device__ __forceinline__ void vote1(uint32_t *tile, float u, float v, const Cols<G> &cl, int lane) {
-    constexpr int TW = 64 * G;
+// Steps 2-3: sweep one staged hit through the lane's columns and vote.
+template <int G, bool P>
+__device__ __forceinline__ void vote1(uint32_t *tile, float u, float v, const Cols<G> &cl,
+                                      const Lane<G, P> &ln) {
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         const float w = __builtin_fmaf(v, cl.S[q], cl.B[q]);
         const float t = __builtin_fmaf(u, cl.C[q], w);
-        lds_inc(&tile[(int)t * TW + 64 * q + lane]);
+        lds_add(&tile[(int)t * Lane<G, P>::STRIDE + ln.col[q]], ln.inc);
     }
 }
 
 // The staged hits are read four at a time (two 16-byte broadcast reads) one step ahead of
 // the votes that use them, so a wave never waits on its own atomics to fetch the next hits.
-template <int G>
+template <int G, bool P>
 __device__ __forceinline__ void vote_staged(uint32_t *tile, const float2 *st, StageCount n,
-                                            const Cols<G> &cl, float nrho_f, int lane) {
-    constexpr int TW = 64 * G;
+                                            const Cols<G> &cl, const Lane<G, P> &ln, float nrho_f) {
     const float4 *st4 = reinterpret_cast<const float4 *>(st);
     const uint32_t n4 = n.safe >> 2;
     if (n4) {
         float4 a = st4[0], b = st4[1];
         for (uint32_t i = 1; i < n4; ++i) {
             const float4 na = st4[2 * i], nb = st4[2 * i + 1];
-            vote1<G>(tile, a.x, a.y, cl, lane);
-            vote1<G>(tile, a.z, a.w, cl, lane);
-            vote1<G>(tile, b.x, b.y, cl, lane);
-            vote1<G>(tile, b.z, b.w, cl, lane);
+            vote1<G, P>(tile, a.x, a.y, cl, ln);
+            vote1<G, P>(tile, a.z, a.w, cl, ln);
+            vote1<G, P>(tile, b.x, b.y, cl, ln);
+            vote1<G, P>(tile, b.z, b.w, cl, ln);
             a = na;
             b = nb;
         }
-        vote1<G>(tile, a.x, a.y, cl, lane);
-        vote1<G>(tile, a.z, a.w, cl, lane);
-        vote1<G>(tile, b.x, b.y, cl, lane);
-        vote1<G>(tile, b.z, b.w, cl, lane);
+        vote1<G, P>(tile, a.x, a.y, cl, ln);
+        vote1<G, P>(tile, a.z, a.w, cl, ln);
+        vote1<G, P>(tile, b.x, b.y, cl, ln);
+        vote1<G, P>(tile, b.z, b.w, cl, ln);
     }
-    for (uint32_t h = n4 * 4; h < n.safe; ++h) vote1<G>(tile, st[h].x, st[h].y, cl, lane);
+    for (uint32_t h = n4 * 4; h < n.safe; ++h) vote1<G, P>(tile, st[h].x, st[h].y, cl, ln);
     for (uint32_t h = n.safe; h < n.total; ++h) {
         const float2 p = st[h];
 #pragma unroll
         for (int q = 0; q < G; ++q) {
             const float w = __builtin_fmaf(p.y, cl.S[q], cl.B[q]);
             const float t = __builtin_fmaf(p.x, cl.C[q], w);
-            if (t >= 0.0f && t < nrho_f) lds_inc(&tile[(int)t * TW + 64 * q + lane]);
+            if (t >= 0.0f && t < nrho_f) lds_add(&tile[(int)t * Lane<G, P>::STRIDE + ln.col[q]], ln.inc);
         }
     }
 }
 
-template <int G>
-__device__ void vote_range(uint32_t *tile, float2 *st, const float *x, const float *y,
-                           uint32_t hb, uint32_t he, const Cols<G> &cl, const GridArgs &g,
-                           int lane, uint32_t &bad) {
+// Votes of hits [hb, he); returns the number of valid hits seen.
+template <int G, bool P>
+__device__ uint32_t vote_range(uint32_t *tile, float2 *st, const float *x, const float *y,
+                               uint32_t hb, uint32_t he, const Cols<G> &cl, const Lane<G, P> &ln,
+                               const GridArgs &g, int lane, uint32_t &bad) {
+    uint32_t n_valid = 0;
     for (uint32_t base = hb; base < he; base += 64) {
         const StageCount n = stage_hits(st, nullptr, x, y, base, he, false, g, lane, bad);
-        vote_staged<G>(tile, st, n, cl, g.nrho_f, lane);
+        n_valid += n.total;
+        vote_staged<G, P>(tile, st, n, cl, ln, g.nrho_f);
         wave_sync();
     }
+    return n_valid;
 }
 
-// Step 4 on one 32-row word of column c: bit b set iff (c, 32*wd + b) is a peak.
-// The lane holds the 3x3 window of columns c-1, c, c+1 and slides it down the rows.
-// Raster order is (theta, rho), so column c-1 and row k-1 of column c come first:
-// peak <=> count >= threshold, count > every earlier neighbour, count >= every later one,
-// i.e. count >= max(threshold, max(earlier) + 1, max(later)).  Rows outside the grid are 0.
-template <int TW>
-__device__ __forceinline__ uint32_t peak_word(const uint32_t *tile, int c, int wd, int n_rho,
-                                              uint32_t T) {
-    const int cl = c > 0 ? c - 1 : 0;
-    const int cr = c < TW - 1 ? c + 1 : TW - 1;
-    const int k0 = wd * 32;
-    uint32_t Lp = 0, Mp = 0, Rp = 0;
-    if (k0 > 0) {
-        const uint32_t *r = tile + (k0 - 1) * TW;
-        Lp = r[cl]; Mp = r[c]; Rp = r[cr];
+// Step 4 on rows [16*u, 16*u + 16) of the lane's columns: bit b of mask[q] is set iff cell
+// (column 64q + lane, row 16*u + b) is a peak.  Raster order is (theta, rho), so the column to
+// the left and the row above come first:
+//   peak <=> count >= threshold, count > every earlier neighbour, count >= every later one
+//        <=> count >= max(threshold, max(earlier) + 1, max(later)).
+// The lane slides a three-row window down its own column, reading four rows at a time; the
+// vertical maxima of the neighbouring columns come from the neighbouring lanes through DPP wave
+// shifts (and across a 64-column group boundary through readlane).  Rows outside the grid count
+// as 0.  The two edge columns of the tile are halo columns; the caller drops their bits.
+constexpr int kPeakRows = 16;
+
+template <int G, bool P>
+__device__ __forceinline__ uint32_t cell_or_zero(const uint32_t *tile, int k, int n_rho,
+                                                 const Lane<G, P> &ln, int q) {
+    const bool in = (k >= 0) && (k < n_rho);
+    const uint32_t d = tile[(in ? k : 0) * Lane<G, P>::STRIDE + ln.col[q]];
+    return in ? ln.count(d) : 0u;
+}
+
+template <int G, bool P>
+__device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_rho, uint32_t T,
+                                          const Lane<G, P> &ln, int lane, uint32_t *mask) {
+    const int k0 = unit * kPeakRows;
+    uint32_t Mp[G], Mc[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        Mp[q] = cell_or_zero<G, P>(tile, k0 - 1, n_rho, ln, q);
+        Mc[q] = cell_or_zero<G, P>(tile, k0, n_rho, ln, q);
+        mask[q] = 0u;
     }
-    const uint32_t *r0 = tile + k0 * TW;
-    uint32_t Lc = r0[cl], Mc = r0[c], Rc = r0[cr];
-    const int kend = (k0 + 32 < n_rho) ? k0 + 32 : n_rho;
-    uint32_t mask = 0;
-    for (int k = k0; k < kend; ++k) {
-        uint32_t Ln = 0, Mn = 0, Rn = 0;
-        if (k + 1 < n_rho) {
-            const uint32_t *r = tile + (k + 1) * TW;
-            Ln = r[cl]; Mn = r[c]; Rn = r[cr];
+#pragma unroll 1
+    for (int r0 = 0; r0 < kPeakRows; r0 += 4) {
+        uint32_t N[G][4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+#pragma unroll
+            for (int q = 0; q < G; ++q) N[q][d] = cell_or_zero<G, P>(tile, k0 + r0 + d + 1, n_rho, ln, q);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const int k = k0 + r0 + d;
+            uint32_t V[G];
+#pragma unroll
+            for (int q = 0; q < G; ++q) V[q] = max(max(Mp[q], Mc[q]), N[q][d]);
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                uint32_t VL = __builtin_amdgcn_update_dpp(0u, V[q], 0x138, 0xf, 0xf, true);   // lane - 1
+                uint32_t VR = __builtin_amdgcn_update_dpp(0u, V[q], 0x130, 0xf, 0xf, true);   // lane + 1
+                if (q > 0) {
+                    const uint32_t x = __builtin_amdgcn_readlane(V[q > 0 ? q - 1 : 0], 63);
+                    VL = lane == 0 ? x : VL;
+                }
+                if (q + 1 < G) {
+                    const uint32_t x = __builtin_amdgcn_readlane(V[q + 1 < G ? q + 1 : 0], 0);
+                    VR = lane == 63 ? x : VR;
+                }
+                const uint32_t before = max(VL, Mp[q]);
+                const uint32_t after = max(VR, N[q][d]);
+                const uint32_t need = max(max(T, before + 1u), after);
+                mask[q] |= (uint32_t)(k < n_rho && Mc[q] >= need) << (r0 + d);
+            }
+#pragma unroll
+            for (int q = 0; q < G; ++q) { Mp[q] = Mc[q]; Mc[q] = N[q][d]; }
         }
-        const uint32_t before = max(max(Lp, Lc), max(Ln, Mp));
-        const uint32_t after = max(max(Rp, Rc), max(Rn, Mn));
-        const uint32_t need = max(max(T, before + 1u), after);
-        mask |= (uint32_t)(Mc >= need) << (k - k0);
-        Lp = Lc; Mp = Mc; Rp = Rc;
-        Lc = Ln; Mc = Mn; Rc = Rn;
     }
-    return mask;
 }
 
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
@@ -217,98 +272,119 @@ __device__ __forceinline__ void store_peak(hough_peak *out, uint32_t j, uint32_t
     *p = make_uint2((j & 0xffffu) | (k << 16), c);
 }
 
-// Step 4 (compaction) and the marks of step 5, run by one wave.  Columns are visited in
-// order and each lane lists its own column's peaks in rho order, so the event's list comes
-// out in raster order.  Every cell within rho_window of a peak gets bit 31 set (each lane only
-// touches its own column).  Returns the number of peaks in this tile.
-template <int G>
+// Step 4 (listing) and the marks of step 5, shared by all waves.  pmask[wd * TW + c] holds the
+// peak bits of column c, rows 32*wd ...  Every wave computes the per-column peak counts and
+// their prefix over the tile's columns (raster order is column-major), then lists the peaks of
+// its own words at base + (peaks in earlier columns) + (peaks above in the same column).  Each
+// peak sets the mark bit of every cell within rho_window rows of it (atomic OR: neighbouring
+// words belong to other waves).  Returns the tile's peak count.
+template <int G, bool P>
 __device__ uint32_t emit_and_mark(uint32_t *tile, const uint32_t *pmask, int nwords, int first_col,
-                                  const GridArgs &g, hough_peak *out, uint32_t cap,
-                                  uint32_t running, int lane) {
-    constexpr int TW = 64 * G;
-    const uint32_t start = running;
+                                  const GridArgs &g, hough_peak *out, uint32_t cap, uint32_t base,
+                                  const Lane<G, P> &ln, int lane, int wave, int n_waves) {
+    constexpr int TW = 64 * G, ST = Lane<G, P>::STRIDE;
+    uint32_t colbase[G];
+    uint32_t carry = 0;
+#pragma unroll
     for (int q = 0; q < G; ++q) {
-        const int c = 64 * q + lane;
-        uint32_t cnt = 0;
-        for (int wd = 0; wd < nwords; ++wd) cnt += __popc(pmask[wd * TW + c]);
-        const uint32_t incl = wave_inclusive_scan(cnt, lane);
-        const uint32_t total = __shfl(incl, 63, 64);
-        uint32_t idx = running + incl - cnt;
-        const uint32_t j = (uint32_t)(first_col + c);
-        for (int wd = 0; wd < nwords; ++wd) {
+        uint32_t tot = 0;
+        for (int w = 0; w < nwords; ++w) tot += __popc(pmask[w * TW + 64 * q + lane]);
+        const uint32_t incl = wave_inclusive_scan(tot, lane);
+        colbase[q] = carry + incl - tot;
+        carry += __shfl(incl, 63, 64);
+    }
+    if (carry == 0u) return 0u;
+    for (int wd = wave; wd < nwords; wd += n_waves) {
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const int c = 64 * q + lane;
             uint32_t m = pmask[wd * TW + c];
+            if (!m) continue;
+            uint32_t idx = base + colbase[q];
+            for (int w = 0; w < wd; ++w) idx += __popc(pmask[w * TW + c]);
+            const uint32_t j = (uint32_t)(first_col + c);
             while (m) {
                 const int b = __builtin_ctz(m);
                 m &= m - 1u;
                 const int k = wd * 32 + b;
-                const uint32_t cv = tile[k * TW + c] & ~kMark;
+                const uint32_t cv = ln.count(tile[k * ST + ln.col[q]]);
                 if (idx < cap) store_peak(out + idx, j, (uint32_t)k, cv);
                 ++idx;
                 const int lo = k - g.rho_window > 0 ? k - g.rho_window : 0;
                 const int hi = k + g.rho_window < g.n_rho - 1 ? k + g.rho_window : g.n_rho - 1;
-                for (int kk = lo; kk <= hi; ++kk) tile[kk * TW + c] |= kMark;
+                for (int kk = lo; kk <= hi; ++kk)
+                    __hip_atomic_fetch_or(&tile[kk * ST + ln.col[q]], ln.mark, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
-        running += total;
     }
-    return running - start;
+    return carry;
 }
 
 // Step 5 on the current tile: every hit not yet kept looks up its own cell in each of the
 // lane's columns; a marked cell in any column of the tile keeps the hit.  Hits are taken four
-// at a time so that their 4*G cell reads are in flight together.
-template <int G>
+// at a time so that their 4*G cell reads are in flight together.  Returns how many hits this
+// wave newly kept.
+template <int G, bool P>
 __device__ __forceinline__ uint32_t lookup1(const uint32_t *tile, float u, float v, bool checked,
-                                            const Cols<G> &cl, float nrho_f, int lane) {
-    constexpr int TW = 64 * G;
+                                            const Cols<G> &cl, const Lane<G, P> &ln, float nrho_f) {
     uint32_t m = 0;
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         const float w = __builtin_fmaf(v, cl.S[q], cl.B[q]);
         const float t = __builtin_fmaf(u, cl.C[q], w);
-        if (!checked || (t >= 0.0f && t < nrho_f)) m |= tile[(int)t * TW + 64 * q + lane];
+        if (!checked || (t >= 0.0f && t < nrho_f)) m |= tile[(int)t * Lane<G, P>::STRIDE + ln.col[q]];
     }
-    return m;
+    return m & ln.mark;
 }
 
-__device__ __forceinline__ void keep_hit(uint32_t *keepbits, uint32_t hit) {
-    __hip_atomic_fetch_or(&keepbits[hit >> 5], 1u << (hit & 31), __ATOMIC_RELAXED,
-                          __HIP_MEMORY_SCOPE_WORKGROUP);
+// The kept hits of a stage are known as a 64-bit mask over stage slots; the lanes set the keep
+// bits of their own slots together.  Each hit belongs to one wave's range and is staged only
+// while its bit is clear, so the number of newly kept hits is the popcount of the mask.
+__device__ __forceinline__ uint32_t keep_slots(uint32_t *keepbits, const uint32_t *sidx,
+                                               uint64_t kept, int lane) {
+    if ((kept >> lane) & 1ull) {
+        const uint32_t hit = sidx[lane];
+        __hip_atomic_fetch_or(&keepbits[hit >> 5], 1u << (hit & 31), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    return (uint32_t)__popcll(kept);
 }
 
-template <int G>
-__device__ void retain_range(const uint32_t *tile, float2 *st, uint32_t *sidx, const float *x,
-                             const float *y, uint32_t hb, uint32_t he, uint32_t *keepbits,
-                             const Cols<G> &cl, const GridArgs &g, int lane) {
-    uint32_t unused = 0;
+template <int G, bool P>
+__device__ uint32_t retain_range(const uint32_t *tile, float2 *st, uint32_t *sidx, const float *x,
+                                 const float *y, uint32_t hb, uint32_t he, uint32_t *keepbits,
+                                 const Cols<G> &cl, const Lane<G, P> &ln, const GridArgs &g, int lane) {
+    uint32_t unused = 0, newly = 0;
     for (uint32_t base = hb; base < he; base += 64) {
         const uint32_t i = base + lane;
         const bool done = (i < he) && ((keepbits[i >> 5] >> (i & 31)) & 1u);
+        if (__ballot((i < he) && !done) == 0ull) continue;      // whole chunk already kept
         const StageCount n = stage_hits(st, sidx, x, y, base, he, done, g, lane, unused);
         const float4 *st4 = reinterpret_cast<const float4 *>(st);
+        uint64_t kept = 0;
         uint32_t h = 0;
         for (; h + 4 <= n.safe; h += 4) {
             const float4 a = st4[h >> 1], b = st4[(h >> 1) + 1];
-            const uint32_t m0 = lookup1<G>(tile, a.x, a.y, false, cl, g.nrho_f, lane);
-            const uint32_t m1 = lookup1<G>(tile, a.z, a.w, false, cl, g.nrho_f, lane);
-            const uint32_t m2 = lookup1<G>(tile, b.x, b.y, false, cl, g.nrho_f, lane);
-            const uint32_t m3 = lookup1<G>(tile, b.z, b.w, false, cl, g.nrho_f, lane);
-            const uint64_t k0 = __ballot((m0 & kMark) != 0u), k1 = __ballot((m1 & kMark) != 0u);
-            const uint64_t k2 = __ballot((m2 & kMark) != 0u), k3 = __ballot((m3 & kMark) != 0u);
-            if (lane == 0) {
-                if (k0) keep_hit(keepbits, sidx[h]);
-                if (k1) keep_hit(keepbits, sidx[h + 1]);
-                if (k2) keep_hit(keepbits, sidx[h + 2]);
-                if (k3) keep_hit(keepbits, sidx[h + 3]);
-            }
+            const uint32_t m0 = lookup1<G, P>(tile, a.x, a.y, false, cl, ln, g.nrho_f);
+            const uint32_t m1 = lookup1<G, P>(tile, a.z, a.w, false, cl, ln, g.nrho_f);
+            const uint32_t m2 = lookup1<G, P>(tile, b.x, b.y, false, cl, ln, g.nrho_f);
+            const uint32_t m3 = lookup1<G, P>(tile, b.z, b.w, false, cl, ln, g.nrho_f);
+            const uint64_t one = 1ull << h;
+            kept |= __ballot(m0 != 0u) ? one : 0ull;
+            kept |= __ballot(m1 != 0u) ? one << 1 : 0ull;
+            kept |= __ballot(m2 != 0u) ? one << 2 : 0ull;
+            kept |= __ballot(m3 != 0u) ? one << 3 : 0ull;
         }
         for (; h < n.total; ++h) {
             const float2 p = st[h];
-            const uint32_t m = lookup1<G>(tile, p.x, p.y, h >= n.safe, cl, g.nrho_f, lane);
-            if (__ballot((m & kMark) != 0u) != 0ull && lane == 0) keep_hit(keepbits, sidx[h]);
+            const uint32_t m = lookup1<G, P>(tile, p.x, p.y, h >= n.safe, cl, ln, g.nrho_f);
+            kept |= __ballot(m != 0u) ? (1ull << h) : 0ull;
         }
+        newly += keep_slots(keepbits, sidx, kept, lane);
         wave_sync();
     }
+    return newly;
 }
 
 // ------------------------------------------------------------------------ plain path
@@ -329,7 +405,8 @@ __global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__res
     const uint32_t hb = (uint32_t)((uint64_t)n_hits * wave / NW);
     const uint32_t he = (uint32_t)((uint64_t)n_hits * (wave + 1) / NW);
     uint32_t bad = 0;
-    vote_range<1>(tile, stage + wave * 64, x, y, hb, he, cl, g, lane, bad);
+    const Lane<1, false> ln(lane);
+    vote_range<1, false>(tile, stage + wave * 64, x, y, hb, he, cl, ln, g, lane, bad);
     __syncthreads();
     // Write-out: lane = column (theta row of acc), wave = a slice of rho.
     const int j = first + lane;
@@ -468,22 +545,26 @@ __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__r
 
 // ------------------------------------------------------------------------ fused batch path
 // One workgroup processes one event at a time, taken from a global work counter; the event's
-// theta tiles are processed in order: zero, vote, find peaks, list + mark, retain.  The keep
-// bits of the event's hits live in LDS until the event is done.
+// theta tiles are processed in order: zero, vote, find peaks, list + mark, retain.  Counters are
+// packed two per dword (an event has at most kMaxBatchHits hits, so a count fits 15 bits and the
+// 16th is the retention mark).  The keep bits of the event's hits live in LDS until the event
+// is done.  Retention is skipped for the rest of the event once every valid hit is kept.
 // queue[0] is the work counter and queue[1] counts workgroups that have left the loop; the
 // last one to leave (every pop has then happened) puts both back to zero for the next launch,
 // so a launch is a single kernel with no memset.
 template <int NW, int G>
-__global__ __launch_bounds__(NW * 64) void k_batch(GridArgs g, BatchArgs a, int n_tiles, int nwords) {
-    constexpr int TW = 64 * G, OUT = TW - 2, NT = NW * 64;
+__global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, BatchArgs a, int n_tiles, int nwords) {
+    using L = Lane<G, true>;
+    constexpr int TW = L::TW, ST = L::STRIDE, OUT = TW - 2, NT = NW * 64;
     extern __shared__ __align__(16) uint32_t lds[];
-    uint32_t *tile = lds;                                                  // [(n_rho + 1) * TW]
-    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * TW);   // [NW * 64]
+    uint32_t *tile = lds;                                                  // [(n_rho + 1) * ST]
+    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * ST);   // [NW * 64]
     uint32_t *sidx = reinterpret_cast<uint32_t *>(stage + NW * 64);        // [NW * 64]
     uint32_t *pmask = sidx + NW * 64;                                      // [nwords * TW]
-    uint32_t *keepbits = pmask + (size_t)nwords * TW;                      // [kMaxBatchHits / 32]
-    __shared__ uint32_t s_event, s_npeaks, s_tile_peaks, s_flags;
+    uint32_t *keepbits = pmask + (size_t)nwords * TW;                      // [kMaxBatchHits / 32 + 1]
+    __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const L ln(lane);
 
     for (;;) {
         if (threadIdx.x == 0) s_event = atomicAdd(a.queue, 1u);
@@ -513,38 +594,44 @@ __global__ __launch_bounds__(NW * 64) void k_batch(GridArgs g, BatchArgs a, int 
             continue;
         }
         for (uint32_t i = threadIdx.x; i < (H + 31u) / 32u; i += NT) keepbits[i] = 0u;
-        if (threadIdx.x == 0) { s_npeaks = 0u; s_flags = 0u; }
+        if (threadIdx.x == 0) { s_npeaks = 0u; s_flags = 0u; s_nvalid = 0u; s_nkept = 0u; }
         const uint32_t hb = (uint32_t)((uint64_t)H * wave / NW);
         const uint32_t he = (uint32_t)((uint64_t)H * (wave + 1) / NW);
         const float *xe = a.x + h0, *ye = a.y + h0;
         hough_peak *pe = a.peaks ? a.peaks + (size_t)e * a.max_peaks : nullptr;
+        const uint32_t cap = pe ? a.max_peaks : 0u;
         uint32_t bad = 0;
         for (int t = 0; t < n_tiles; ++t) {
             const int first = t * OUT - 1;      // grid column of lane 0 of group 0
             const Cols<G> cl = load_cols<G>(g, first, lane);
-            for (int i = threadIdx.x; i < (g.n_rho + 1) * TW / 4; i += NT)
+            for (int i = threadIdx.x; i < (g.n_rho + 1) * ST / 4; i += NT)
                 reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
             __syncthreads();
-            vote_range<G>(tile, stage + wave * 64, xe, ye, hb, he, cl, g, lane, bad);
+            const uint32_t nv = vote_range<G, true>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad);
+            if (t == 0 && lane == 0 && nv) atomicAdd(&s_nvalid, nv);
             __syncthreads();
-            for (int unit = wave; unit < G * nwords; unit += NW) {
-                const int q = unit / nwords, wd = unit - q * nwords;
-                const int c = 64 * q + lane;
-                const int j = first + c;
-                const bool out_col = (c >= 1) && (c <= TW - 2) && (j < g.n_theta);
-                const uint32_t m = peak_word<TW>(tile, c, wd, g.n_rho, g.threshold);
-                pmask[wd * TW + c] = out_col ? m : 0u;
+            for (int u = wave; u < 2 * nwords; u += NW) {
+                uint32_t m[G];
+                peak_rows<G, true>(tile, u, g.n_rho, g.threshold, ln, lane, m);
+                uint16_t *pm16 = reinterpret_cast<uint16_t *>(pmask);
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    const int c = 64 * q + lane;
+                    const bool out_col = (c >= 1) && (c <= TW - 2) && (first + c < g.n_theta);
+                    pm16[((u >> 1) * TW + c) * 2 + (u & 1)] = out_col ? (uint16_t)m[q] : (uint16_t)0;
+                }
             }
             __syncthreads();
-            if (wave == 0) {
-                const uint32_t n = emit_and_mark<G>(tile, pmask, nwords, first, g, pe,
-                                                    pe ? a.max_peaks : 0u, s_npeaks, lane);
-                if (lane == 0) { s_npeaks += n; s_tile_peaks = n; }
-            }
+            const uint32_t base = s_npeaks;
+            const uint32_t np = emit_and_mark<G, true>(tile, pmask, nwords, first, g, pe, cap, base,
+                                                       ln, lane, wave, NW);
             __syncthreads();
-            if (s_tile_peaks)
-                retain_range<G>(tile, stage + wave * 64, sidx + wave * 64, xe, ye, hb, he,
-                                keepbits, cl, g, lane);
+            if (threadIdx.x == 0) s_npeaks = base + np;
+            if (np && s_nkept < s_nvalid) {
+                const uint32_t newly = retain_range<G, true>(tile, stage + wave * 64, sidx + wave * 64,
+                                                             xe, ye, hb, he, keepbits, cl, ln, g, lane);
+                if (lane == 0 && newly) atomicAdd(&s_nkept, newly);
+            }
             __syncthreads();
         }
         if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
@@ -580,8 +667,8 @@ size_t peaks_lds_bytes(int n_rho) { return (size_t)(kPeakWaves + 2) * n_rho * 4 
 
 size_t batch_lds_bytes(int n_rho, int waves, int groups) {
     const size_t tw = 64u * groups, nwords = (size_t)(n_rho + 31) / 32;
-    return (size_t)(n_rho + 1) * tw * 4 + (size_t)waves * kStageBytes + nwords * tw * 4 +
-           kMaxBatchHits / 8;
+    return (size_t)(n_rho + 1) * (tw / 2) * 4 + (size_t)waves * kStageBytes + nwords * tw * 4 +
+           (kMaxBatchHits / 32 + 1) * 4;
 }
 
 int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out) {
