@@ -94,6 +94,42 @@ def plain_path(H, wl, ev, n_events: int = 200):
             "launches_per_event": 3, "ms_per_event": round(dt / sub.n_events * 1e3, 4)}
 
 
+SERVE_RATES = (50_000, 100_000, 200_000, 400_000)
+
+
+def serving(H, duration_s: float, warmup_s: float, plain_duration_s: float, pool_events: int = 8192):
+    """Open-loop Poisson arrivals of a 50/50 mix of the 1000-event-workload and dense-workload
+    generators (pools of `pool_events` each, seed 0) through the native serving loop: served
+    (continuous batching, 8 streams) at each rate, and the plain per-event launch under the
+    same kind of trace (shorter, it saturates).  Latency = results in host memory - scheduled
+    arrival; warm-up arrivals are excluded."""
+    from paper_2607_04067_amd import serve
+    pools = []
+    for name in ("paper-1000ev-360x256", "dense-2000ev-720x512"):
+        wl = synth.WORKLOADS[name]
+        log(f"serving pool: {pool_events} events of {name}")
+        ev = synth.make_events(wl, 0, n_events=pool_events)
+        pools.append(serve.Pool(H.Context.for_workload(wl, max_peaks=MAX_PEAKS[name]), ev))
+    sizes = [p.batch.n_events for p in pools]
+    out = {"mix": "50/50 paper-1000ev-360x256 / dense-2000ev-720x512 generators",
+           "pool_events": pool_events, "n_streams": 8, "max_batch_events": 256,
+           "latency": "results (n_peaks, status, keep) in host memory minus scheduled arrival",
+           "served": {}, "plain": {}}
+    for i, rate in enumerate(SERVE_RATES):
+        tr = serve.poisson_trace(rate, warmup_s + duration_s, sizes, [0.5, 0.5], seed=100 + i)
+        res, _, _ = serve.run(pools, tr, n_streams=8, max_batch_events=256, max_batch_hits=1 << 21)
+        out["served"][str(rate)] = serve.summarize(tr, res, warmup_us=warmup_s * 1e6)
+        log(f"served {rate}/s: {out['served'][str(rate)]}")
+    for i, rate in enumerate(SERVE_RATES[:2]):
+        tr = serve.poisson_trace(rate, plain_duration_s, sizes, [0.5, 0.5], seed=200 + i)
+        res, _, _ = serve.run(pools, tr, n_streams=8, plain=True)
+        out["plain"][str(rate)] = serve.summarize(tr, res)
+        log(f"plain {rate}/s: {out['plain'][str(rate)]}")
+    for p in pools:
+        p.ctx.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +138,12 @@ def main(argv=None):
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(synth.WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="autotune the fused kernel's launch shape first")
+    ap.add_argument("--graph", action="store_true", help="capture one step in a HIP graph and replay it")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--copy-reference-mb", type=int, default=0,
+                    help="also time a plain device copy of this many MiB (HBM reference for counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path is single-GPU; events shard across GPUs "
@@ -123,10 +165,25 @@ def main(argv=None):
     keep = torch.zeros(ev.n_hits, dtype=torch.uint8, device="cuda")
     status = torch.zeros(E, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
+    tuned = None
+    if args.tune:
+        from paper_2607_04067_amd import autotune
+        log("autotuning the launch shape")
+        tuned = autotune.tune(ctx, xt, yt, ot, (peaks, npk, keep, status),
+                              mean_hits=ev.n_hits / max(E, 1), cache=None)
+
+    step = lambda: ctx.run_batch(xt, yt, ot, peaks, npk, keep, status, stream)
+    if args.graph:
+        graph = torch.cuda.CUDAGraph()
+        step()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            ctx.run_batch(xt, yt, ot, peaks, npk, keep, status, torch.cuda.current_stream())
+        step = graph.replay
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
-        ctx.run_batch(xt, yt, ot, peaks, npk, keep, status, stream)
+        step()
     torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -135,7 +192,7 @@ def main(argv=None):
     t0 = time.perf_counter()
     for i in range(args.steps):
         starts[i].record(stream)
-        ctx.run_batch(xt, yt, ot, peaks, npk, keep, status, stream)
+        step()
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -153,7 +210,9 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": wl.name, "events": E, "hits": ev.n_hits, "n_theta": wl.n_theta,
                    "n_rho": wl.n_rho, "threshold": wl.threshold, "rho_window": wl.rho_window,
-                   "max_peaks": MAX_PEAKS[wl.name], "path": "hough_run_batch (one fused launch)"},
+                   "max_peaks": MAX_PEAKS[wl.name],
+                   "path": "hough_run_batch (one fused launch)" + (" in a HIP graph" if args.graph else ""),
+                   "plan": ctx.batch_plan},
         "gvotes_per_s": round(votes / (ms_per_step / 1e3) / 1e9, 2),
         "kernel_ms": round(kern_ms, 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": round(VOTE_PEAK_PER_S / 1e9, 1),
@@ -167,6 +226,25 @@ def main(argv=None):
         "paper_context": "paper: 1,000 simulated events in 0.14 s end to end (7,143 events/s) on an "
                          "RTX 5060 Ti with a 1000x1000 grid; different data, grid and GPU",
     }
+    if tuned is not None:
+        out["autotune_ms"] = tuned["ms"]
+    if args.copy_reference_mb:
+        n = args.copy_reference_mb << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(3):
+            dst.copy_(src)
+        b.record(stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / 3
+        out["copy_reference"] = {"bytes_read": n, "bytes_written": n, "ms": round(ms, 4),
+                                 "gbs": round(2 * n / (ms / 1e3) / 1e9, 1)}
+        del src, dst
+    if not args.no_serve:
+        out["serving"] = serving(H, args.serve_seconds, 0.25, 0.2)
     if not args.no_plain:
         log("plain per-event path")
         out["plain"] = plain_path(H, wl, ev)

@@ -130,6 +130,36 @@ int hough_run_batch(hough_ctx *ctx, const float *x, const float *y, const uint32
                     uint32_t n_events, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
                     uint32_t *status, void *stream);
 
+/* hough_run_batch over a chosen subset of a resident event pool (Sec. III batches, as formed by
+ * a server from arriving events).  x, y, offsets describe the pool exactly as for
+ * hough_run_batch; batch event e is pool event event_ids[e] (device array of n_events pool
+ * indices, repeats allowed).  Outputs are indexed by batch position: peaks[e * max_peaks ...],
+ * n_peaks[e], status[e], and event e's keep bytes are keep[keep_offsets[e] ...] (device array,
+ * one entry per batch event; the caller lays the events' keep ranges out without overlap).
+ * Same semantics, errors and asynchrony as hough_run_batch. */
+int hough_run_batch_gather(hough_ctx *ctx, const float *x, const float *y, const uint32_t *offsets,
+                           const uint32_t *event_ids, const uint32_t *keep_offsets,
+                           uint32_t n_events, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
+                           uint32_t *status, void *stream);
+
+/* Launch shape of hough_run_batch's fused kernel.  A theta tile is 64 * column_groups columns
+ * (two of them halo columns shared with the neighbouring tiles); the hits of an event are split
+ * over waves_per_group waves of a workgroup; groups_per_cu workgroups run on each compute unit.
+ * The schedule changes speed only, never results. */
+typedef struct hough_batch_plan {
+    int32_t waves_per_group;   /* 4, 8 or 16                                   */
+    int32_t column_groups;     /* 1 or 2                                       */
+    int32_t groups_per_cu;     /* resident workgroups per CU (read-only)       */
+    int32_t lds_bytes;         /* LDS per workgroup (read-only)                */
+} hough_batch_plan;
+
+/* The launch shape hough_run_batch currently uses (the library picks one at hough_config). */
+int hough_get_batch_plan(const hough_ctx *ctx, hough_batch_plan *out);
+
+/* Select a launch shape (for autotuning).  HOUGH_EINVAL if the combination is not supported or
+ * does not fit the device; the context keeps its previous shape then. */
+int hough_set_batch_plan(hough_ctx *ctx, int32_t waves_per_group, int32_t column_groups);
+
 /* Largest number of hits per event hough_run_batch processes for this context. */
 uint32_t hough_max_batch_hits(const hough_ctx *ctx);
 

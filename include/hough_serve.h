@@ -1,0 +1,85 @@
+/*
+ * hough_serve.h -- C ABI of the serving loop in libhough.so: an online (trigger-like) request
+ * loop around the batch entry points of hough.h.
+ *
+ * Sec. III processes events in batches and states that host-to-device transfer, kernel
+ * execution and device-to-host transfer can overlap; Sec. V names streams and asynchronous
+ * transfers as the way to feed continuous event streams.  hough_serve_run is that loop: events
+ * arrive at scheduled times (open loop), wait in a per-grid queue, are admitted into a batch as
+ * long as the batch's device arena has room for their hits (memory-based admission), and a batch
+ * is launched on a free stream as soon as one exists (continuous batching: events that arrive
+ * while other batches are on the GPU form the next batch, and up to n_streams batches overlap
+ * on the device).  A request is complete when its results are in host memory.
+ *
+ * The events' hits are resident in device memory (one CSR pool per grid, e.g. a readout buffer);
+ * admitting an event sends its 4-byte pool index and keep offset to the device, and completion
+ * brings back n_peaks, status, keep and, on request, the peak list.  Results are identical to
+ * processing each event alone (every output is an integer and events are independent).
+ *
+ * With `plain` set, each request is instead processed alone by hough_vote, hough_peaks and
+ * hough_retain (three launches, accumulator through HBM), one request per stream slot, under
+ * the same arrivals: the per-event launch it is compared against.
+ */
+#ifndef HOUGH_SERVE_H
+#define HOUGH_SERVE_H
+
+#include <stdint.h>
+
+#include "hough.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One resident event pool and the grid its events are processed on. */
+typedef struct hough_serve_pool {
+    hough_ctx *ctx;                 /* grid, thresholds, max_peaks                          */
+    const float *x;                 /* device, pool hits (as for hough_run_batch)           */
+    const float *y;                 /* device                                               */
+    const uint32_t *offsets;        /* device, [n_events + 1]                               */
+    const uint32_t *host_offsets;   /* host copy of offsets (hit counts for admission)      */
+    uint32_t n_events;
+} hough_serve_pool;
+
+typedef struct hough_serve_config {
+    int32_t n_streams;              /* batches (plain: events) in flight, 1 .. 32            */
+    int32_t max_batch_events;       /* events per batch, >= 1                                */
+    int32_t max_batch_hits;         /* device arena per stream slot, in hits, >= 1           */
+    int32_t plain;                  /* 0: batches through hough_run_batch_gather; 1: per event */
+    int32_t copy_peaks;             /* 1: bring the peak lists back as part of completion    */
+    double max_wait_us;             /* hold a partial batch until its oldest event waited this
+                                       long while a slot is free (0: launch at once)          */
+} hough_serve_config;
+
+typedef struct hough_serve_request {
+    double arrival_us;              /* scheduled arrival, microseconds from the run's start  */
+    int32_t kind;                   /* pool index                                            */
+    uint32_t event;                 /* event index in that pool                              */
+} hough_serve_request;
+
+typedef struct hough_serve_result {
+    double launch_us;               /* its batch (or its first kernel) was enqueued          */
+    double done_us;                 /* its results were observed in host memory              */
+    uint32_t n_peaks;               /* true peak count                                       */
+    uint32_t status;                /* HOUGH_EV_* bits                                       */
+    uint32_t batch_events;          /* events in the batch that carried it (plain: 1)        */
+    uint32_t pad;
+} hough_serve_result;
+
+/* Run the request trace `reqs` (non-decreasing arrival_us) to completion on the current device.
+ * res[i] receives request i's timing and counts.  keep_out (host, optional): request i's keep
+ * bytes are written at keep_out[sum of the hit counts of requests 0 .. i-1].  peaks_out (host,
+ * optional, needs copy_peaks): request i's first min(n_peaks, max_peaks of its pool) peaks are
+ * written at peaks_out[i * peaks_stride].  The call blocks until every request completed; it
+ * allocates its stream slots' buffers on entry and frees them on return.
+ * Returns HOUGH_EINVAL for a bad argument or a request whose event does not fit a slot's arena,
+ * HOUGH_ENOMEM, or HOUGH_EDEVICE. */
+int hough_serve_run(const hough_serve_pool *pools, int32_t n_kinds, const hough_serve_config *cfg,
+                    const hough_serve_request *reqs, uint32_t n_reqs, hough_serve_result *res,
+                    uint8_t *keep_out, hough_peak *peaks_out, uint32_t peaks_stride);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOUGH_SERVE_H */

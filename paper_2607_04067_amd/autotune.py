@@ -1,0 +1,81 @@
+"""Autotuner for the fused batch kernel's launch shape.
+
+The schedule space is the theta-tile width (64 * column_groups columns) times the split of an
+event's hits over the waves of a workgroup (waves_per_group); the library reports how many
+workgroups fit a CU for each.  Every candidate is timed on the caller's resident batch with HIP
+events and the fastest is kept.  Results are cached in a JSON file keyed by device, grid and a
+hits-per-event bucket, so that a later context with the same key starts from the tuned shape.
+The schedule never changes results, only speed.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+CANDIDATES = [(w, g) for w in (4, 8, 16) for g in (1, 2)]
+DEFAULT_CACHE = os.environ.get("HOUGH_TUNE_CACHE",
+                               os.path.join(os.path.expanduser("~"), ".cache", "hough_batch_plans.json"))
+
+
+def cache_key(ctx, mean_hits: float) -> str:
+    dev = torch.cuda.get_device_name(0).replace(" ", "_")
+    bucket = 1 << max(0, int(mean_hits).bit_length() - 1)          # power-of-two bucket
+    return f"{dev}|{ctx.n_theta}x{ctx.n_rho}|hits~{bucket}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def time_plan(ctx, args, reps: int = 5) -> float:
+    """Mean milliseconds of one hough_run_batch over `reps` launches (after one warm-up)."""
+    stream = torch.cuda.current_stream()
+    ctx.run_batch(*args, stream=stream)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        ctx.run_batch(*args, stream=stream)
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(ctx, x, y, offsets, outputs, mean_hits: float, cache: str | None = DEFAULT_CACHE,
+         reps: int = 5, force: bool = False) -> dict:
+    """Pick the fastest launch shape for this context on the given resident batch.
+
+    outputs = (peaks, n_peaks, keep, status) buffers as accepted by Context.run_batch.
+    Returns {"plan": (waves, groups), "ms": {...per candidate...}} and leaves ctx on the winner.
+    """
+    key = cache_key(ctx, mean_hits)
+    table = _load(cache) if cache else {}
+    if not force and key in table:
+        w, g = table[key]["plan"]
+        ctx.set_batch_plan(w, g)
+        return table[key]
+    args = (x, y, offsets, *outputs)
+    results = {}
+    for w, g in CANDIDATES:
+        try:
+            ctx.set_batch_plan(w, g)
+        except RuntimeError:
+            continue
+        results[f"{w}x{g}"] = round(time_plan(ctx, args, reps), 5)
+    best = min(results, key=results.get)
+    w, g = (int(v) for v in best.split("x"))
+    ctx.set_batch_plan(w, g)
+    entry = {"plan": [w, g], "ms": results}
+    if cache:
+        table[key] = entry
+        os.makedirs(os.path.dirname(cache) or ".", exist_ok=True)
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return entry

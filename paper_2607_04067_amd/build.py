@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhough.so")
-SOURCES = ["hough_kernels.hip", "hough_api.cpp"]
+SOURCES = ["hough_kernels.hip", "hough_api.cpp", "hough_serve.cpp"]
 ARCH = os.environ.get("HOUGH_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

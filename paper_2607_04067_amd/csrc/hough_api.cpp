@@ -9,10 +9,6 @@
 
 #include "hough_internal.h"
 
-namespace hough {
-int batch_blocks_per_cu(const BatchPlan &p);
-}
-
 struct hough_ctx {
     hough_params p;
     int device;
@@ -53,12 +49,13 @@ int default_plan(hough_ctx *c) {
     for (int wi = 0; wi < 3; ++wi) {
         hough::BatchPlan p;
         if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves_opts[wi], 1, c->lds_limit, &p) != 0) continue;
-        const int per_cu = hough::batch_blocks_per_cu(p);
-        if (per_cu < 1) continue;
-        const int score = per_cu * p.waves * 16 + per_cu;
+        p.per_cu = hough::prepare_batch(p, c->lds_limit);
+        if (p.per_cu < 1) continue;
+        const int score = p.per_cu * p.waves * 16 + p.per_cu;
         if (score > best) { best = score; pick = p; }
     }
     if (best < 0) return HOUGH_EINVAL;
+    if (hough::prepare_batch(pick, c->lds_limit) < 1) return HOUGH_EDEVICE;
     c->plan = pick;
     return HOUGH_OK;
 }
@@ -179,6 +176,29 @@ int hough_get_params(const hough_ctx *c, hough_params *out) {
 
 uint32_t hough_max_batch_hits(const hough_ctx *c) { return c ? hough::kMaxBatchHits : 0u; }
 
+int hough_get_batch_plan(const hough_ctx *c, hough_batch_plan *out) {
+    if (!c || !out) return HOUGH_EINVAL;
+    out->waves_per_group = c->plan.waves;
+    out->column_groups = c->plan.groups;
+    out->groups_per_cu = c->plan.per_cu;
+    out->lds_bytes = (int32_t)c->plan.lds_bytes;
+    return HOUGH_OK;
+}
+
+int hough_set_batch_plan(hough_ctx *c, int32_t waves_per_group, int32_t column_groups) {
+    if (!c) return HOUGH_EINVAL;
+    hough::BatchPlan p;
+    if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves_per_group, column_groups, c->lds_limit, &p) != 0)
+        return HOUGH_EINVAL;
+    p.per_cu = hough::prepare_batch(p, c->lds_limit);
+    if (p.per_cu < 1) {
+        (void)hough::prepare_batch(c->plan, c->lds_limit);
+        return HOUGH_EINVAL;
+    }
+    c->plan = p;
+    return HOUGH_OK;
+}
+
 int hough_vote(hough_ctx *c, const float *x, const float *y, uint32_t n_hits, void *acc, void *stream) {
     if (!c || !acc) return HOUGH_EINVAL;
     if (n_hits && (!x || !y)) return HOUGH_EINVAL;
@@ -207,24 +227,25 @@ int hough_retain(hough_ctx *c, const float *x, const float *y, uint32_t n_hits,
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
 }
 
-int hough_run_batch(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,
-                    uint32_t n_events, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
-                    uint32_t *status, void *stream) {
+static int run_batch_common(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,
+                            const uint32_t *ids, const uint32_t *keep_offsets, uint32_t n_events,
+                            hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
+                            void *stream) {
     if (!c) return HOUGH_EINVAL;
     if (n_events == 0) return HOUGH_OK;
     if (!x || !y || !offsets || !n_peaks || !keep || !status) return HOUGH_EINVAL;
     if (c->p.max_peaks > 0 && !peaks) return HOUGH_EINVAL;
     if (((uintptr_t)peaks & 7u) != 0) return HOUGH_EINVAL;
     hough::BatchPlan plan = c->plan;
-    const int per_cu = hough::batch_blocks_per_cu(plan);
-    if (per_cu < 1) return HOUGH_EDEVICE;
-    long grid = (long)per_cu * c->n_cu;
+    long grid = (long)plan.per_cu * c->n_cu;
     if (grid > (long)n_events) grid = n_events;
     plan.grid = (int)grid;
     hough::BatchArgs a;
     a.x = x;
     a.y = y;
     a.offsets = offsets;
+    a.ids = ids;
+    a.keep_offsets = keep_offsets;
     a.n_events = n_events;
     a.peaks = c->p.max_peaks > 0 ? peaks : nullptr;
     a.n_peaks = n_peaks;
@@ -234,6 +255,22 @@ int hough_run_batch(hough_ctx *c, const float *x, const float *y, const uint32_t
     a.queue = c->d_work;
     const hipError_t e = hough::launch_batch(c->g, plan, a, (hipStream_t)stream);
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
+}
+
+int hough_run_batch(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,
+                    uint32_t n_events, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
+                    uint32_t *status, void *stream) {
+    return run_batch_common(c, x, y, offsets, nullptr, nullptr, n_events, peaks, n_peaks, keep,
+                            status, stream);
+}
+
+int hough_run_batch_gather(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,
+                           const uint32_t *event_ids, const uint32_t *keep_offsets, uint32_t n_events,
+                           hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
+                           void *stream) {
+    if (n_events && (!event_ids || !keep_offsets)) return HOUGH_EINVAL;
+    return run_batch_common(c, x, y, offsets, event_ids, keep_offsets, n_events, peaks, n_peaks,
+                            keep, status, stream);
 }
 
 }  // extern "C"

@@ -39,6 +39,7 @@ struct BatchPlan {
     int out_cols;        // tile_cols - 2 output columns per tile
     int n_tiles;         // ceil(n_theta / out_cols)
     size_t lds_bytes;    // dynamic LDS per workgroup
+    int per_cu;          // resident workgroups per CU (occupancy API)
     int grid;            // persistent workgroups
 };
 
@@ -46,6 +47,8 @@ struct BatchArgs {
     const float *x;
     const float *y;
     const uint32_t *offsets;
+    const uint32_t *ids;            // null, or the pool event of each batch event (gather form)
+    const uint32_t *keep_offsets;   // gather form: first keep byte of each batch event
     uint32_t n_events;
     hough_peak *peaks;
     uint32_t *n_peaks;
@@ -70,5 +73,6 @@ size_t vote_lds_bytes(int n_rho);
 size_t peaks_lds_bytes(int n_rho);
 size_t batch_lds_bytes(int n_rho, int waves, int groups);
 int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out);
+int prepare_batch(const BatchPlan &p, size_t lds_limit);
 
 }  // namespace hough

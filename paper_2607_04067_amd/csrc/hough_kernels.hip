@@ -100,37 +100,37 @@ struct Lane {
     __device__ __forceinline__ uint32_t count(uint32_t dword) const { return (dword >> shift) & cmask; }
 };
 
-// Map up to 64 hits [base, end) (one per lane) and compact the valid ones into the wave's
-// stage: all-in-range hits first, then the others.  Returns (n_safe, n_total) and, through
-// `bad`, whether this lane met an invalid hit.  `skip` hides hits the caller is done with.
-struct StageCount { uint32_t safe, total; };
+// Step 1 for up to 64 hits [base, end), one per lane.  The lane keeps its hit's (u, v); the
+// wave learns which lanes hold a valid hit whose votes are all in range (`safe`) and which hold
+// a valid hit that needs the range test (`checked`).  `skip` hides hits the caller is done with;
+// `bad` records an invalid hit.
+struct Chunk {
+    float u, v;          // this lane's hit
+    uint64_t safe;       // wave-uniform lane masks
+    uint64_t checked;
+};
 
-__device__ __forceinline__ StageCount stage_hits(float2 *st, uint32_t *sidx, const float *x,
-                                                 const float *y, uint32_t base, uint32_t end,
-                                                 bool skip, const GridArgs &g, int lane,
-                                                 uint32_t &bad) {
+__device__ __forceinline__ Chunk map_chunk(const float *x, const float *y, uint32_t base, uint32_t end,
+                                           bool skip, const GridArgs &g, int lane, uint32_t &bad) {
     const uint32_t i = base + lane;
     const bool in = (i < end) && !skip;
     float xi = 0.0f, yi = 0.0f;
     if (in) { xi = x[i]; yi = y[i]; }
-    float u, v;
-    const bool ok = conformal(xi, yi, u, v);
+    Chunk c;
+    const bool ok = conformal(xi, yi, c.u, c.v);
     const bool valid = in && ok;
     if (in && !ok) bad = 1u;
-    const bool safe = valid && all_in_range(u, v, g);
-    const uint64_t bs = __ballot(safe);
-    const uint64_t bu = __ballot(valid && !safe);
-    const uint32_t ns = (uint32_t)__popcll(bs);
-    const uint32_t pos = safe ? mbcnt(bs) : ns + mbcnt(bu);
-    if (valid) {
-        st[pos] = make_float2(u, v);
-        if (sidx) sidx[pos] = i;
-    }
-    wave_sync();
-    return StageCount{ns, ns + (uint32_t)__popcll(bu)};
+    const bool safe = valid && all_in_range(c.u, c.v, g);
+    c.safe = __ballot(safe);
+    c.checked = __ballot(valid && !safe);
+    return c;
 }
 
-// Steps 2-3: sweep one staged hit through the lane's columns and vote.
+__device__ __forceinline__ float lane_value(float v, int l) {
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(v), l));
+}
+
+// Steps 2-3: sweep one hit (wave-uniform u, v) through the lane's columns and vote.
 template <int G, bool P>
 __device__ __forceinline__ void vote1(uint32_t *tile, float u, float v, const Cols<G> &cl,
                                       const Lane<G, P> &ln) {
@@ -142,52 +142,59 @@ __device__ __forceinline__ void vote1(uint32_t *tile, float u, float v, const Co
     }
 }
 
-// The staged hits are read four at a time (two 16-byte broadcast reads) one step ahead of
-// the votes that use them, so a wave never waits on its own atomics to fetch the next hits.
 template <int G, bool P>
-__device__ __forceinline__ void vote_staged(uint32_t *tile, const float2 *st, StageCount n,
-                                            const Cols<G> &cl, const Lane<G, P> &ln, float nrho_f) {
-    const float4 *st4 = reinterpret_cast<const float4 *>(st);
-    const uint32_t n4 = n.safe >> 2;
-    if (n4) {
-        float4 a = st4[0], b = st4[1];
-        for (uint32_t i = 1; i < n4; ++i) {
-            const float4 na = st4[2 * i], nb = st4[2 * i + 1];
-            vote1<G, P>(tile, a.x, a.y, cl, ln);
-            vote1<G, P>(tile, a.z, a.w, cl, ln);
-            vote1<G, P>(tile, b.x, b.y, cl, ln);
-            vote1<G, P>(tile, b.z, b.w, cl, ln);
-            a = na;
-            b = nb;
-        }
-        vote1<G, P>(tile, a.x, a.y, cl, ln);
-        vote1<G, P>(tile, a.z, a.w, cl, ln);
-        vote1<G, P>(tile, b.x, b.y, cl, ln);
-        vote1<G, P>(tile, b.z, b.w, cl, ln);
-    }
-    for (uint32_t h = n4 * 4; h < n.safe; ++h) vote1<G, P>(tile, st[h].x, st[h].y, cl, ln);
-    for (uint32_t h = n.safe; h < n.total; ++h) {
-        const float2 p = st[h];
+__device__ __forceinline__ void vote1_checked(uint32_t *tile, float u, float v, const Cols<G> &cl,
+                                              const Lane<G, P> &ln, float nrho_f) {
 #pragma unroll
-        for (int q = 0; q < G; ++q) {
-            const float w = __builtin_fmaf(p.y, cl.S[q], cl.B[q]);
-            const float t = __builtin_fmaf(p.x, cl.C[q], w);
-            if (t >= 0.0f && t < nrho_f) lds_add(&tile[(int)t * Lane<G, P>::STRIDE + ln.col[q]], ln.inc);
-        }
+    for (int q = 0; q < G; ++q) {
+        const float w = __builtin_fmaf(v, cl.S[q], cl.B[q]);
+        const float t = __builtin_fmaf(u, cl.C[q], w);
+        if (t >= 0.0f && t < nrho_f) lds_add(&tile[(int)t * Lane<G, P>::STRIDE + ln.col[q]], ln.inc);
+    }
+}
+
+// The hits of a chunk are broadcast from the lanes that mapped them with readlane (the wave
+// walks its lane masks with find-first-set), so the LDS pipe carries only the atomics.  Four
+// hits are fetched before their votes are issued.
+template <int G, bool P>
+__device__ __forceinline__ void vote_chunk(uint32_t *tile, const Chunk &c, const Cols<G> &cl,
+                                           const Lane<G, P> &ln, float nrho_f) {
+    uint64_t m = c.safe;
+    uint32_t n = (uint32_t)__popcll(m);
+    for (; n >= 4; n -= 4) {
+        const int l0 = __builtin_ctzll(m); m &= m - 1;
+        const int l1 = __builtin_ctzll(m); m &= m - 1;
+        const int l2 = __builtin_ctzll(m); m &= m - 1;
+        const int l3 = __builtin_ctzll(m); m &= m - 1;
+        const float u0 = lane_value(c.u, l0), v0 = lane_value(c.v, l0);
+        const float u1 = lane_value(c.u, l1), v1 = lane_value(c.v, l1);
+        const float u2 = lane_value(c.u, l2), v2 = lane_value(c.v, l2);
+        const float u3 = lane_value(c.u, l3), v3 = lane_value(c.v, l3);
+        vote1<G, P>(tile, u0, v0, cl, ln);
+        vote1<G, P>(tile, u1, v1, cl, ln);
+        vote1<G, P>(tile, u2, v2, cl, ln);
+        vote1<G, P>(tile, u3, v3, cl, ln);
+    }
+    for (; n > 0; --n) {
+        const int l = __builtin_ctzll(m); m &= m - 1;
+        vote1<G, P>(tile, lane_value(c.u, l), lane_value(c.v, l), cl, ln);
+    }
+    for (uint64_t k = c.checked; k; k &= k - 1) {
+        const int l = __builtin_ctzll(k);
+        vote1_checked<G, P>(tile, lane_value(c.u, l), lane_value(c.v, l), cl, ln, nrho_f);
     }
 }
 
 // Votes of hits [hb, he); returns the number of valid hits seen.
 template <int G, bool P>
-__device__ uint32_t vote_range(uint32_t *tile, float2 *st, const float *x, const float *y,
-                               uint32_t hb, uint32_t he, const Cols<G> &cl, const Lane<G, P> &ln,
+__device__ uint32_t vote_range(uint32_t *tile, const float *x, const float *y, uint32_t hb,
+                               uint32_t he, const Cols<G> &cl, const Lane<G, P> &ln,
                                const GridArgs &g, int lane, uint32_t &bad) {
     uint32_t n_valid = 0;
     for (uint32_t base = hb; base < he; base += 64) {
-        const StageCount n = stage_hits(st, nullptr, x, y, base, he, false, g, lane, bad);
-        n_valid += n.total;
-        vote_staged<G, P>(tile, st, n, cl, ln, g.nrho_f);
-        wave_sync();
+        const Chunk c = map_chunk(x, y, base, he, false, g, lane, bad);
+        n_valid += (uint32_t)__popcll(c.safe | c.checked);
+        vote_chunk<G, P>(tile, c, cl, ln, g.nrho_f);
     }
     return n_valid;
 }
@@ -229,6 +236,16 @@ __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_
         for (int d = 0; d < 4; ++d)
 #pragma unroll
             for (int q = 0; q < G; ++q) N[q][d] = cell_or_zero<G, P>(tile, k0 + r0 + d + 1, n_rho, ln, q);
+        // rows r0 .. r0+3 are tested; when no lane's count there reaches the threshold none of
+        // them can be a peak and only the window moves on
+        uint32_t bm = 0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) bm = max(bm, max(max(Mc[q], N[q][0]), max(N[q][1], N[q][2])));
+        if (__ballot(bm >= T) == 0ull) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) { Mp[q] = N[q][2]; Mc[q] = N[q][3]; }
+            continue;
+        }
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const int k = k0 + r0 + d;
@@ -258,12 +275,14 @@ __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_
     }
 }
 
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
-    }
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row broadcasts (no LDS).
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int) {
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
     return v;
 }
 
@@ -321,10 +340,8 @@ __device__ uint32_t emit_and_mark(uint32_t *tile, const uint32_t *pmask, int nwo
     return carry;
 }
 
-// Step 5 on the current tile: every hit not yet kept looks up its own cell in each of the
-// lane's columns; a marked cell in any column of the tile keeps the hit.  Hits are taken four
-// at a time so that their 4*G cell reads are in flight together.  Returns how many hits this
-// wave newly kept.
+// Step 5 on the current tile: a hit not yet kept looks up its own cell in each of the lane's
+// columns; a marked cell in any column of the tile keeps the hit.
 template <int G, bool P>
 __device__ __forceinline__ uint32_t lookup1(const uint32_t *tile, float u, float v, bool checked,
                                             const Cols<G> &cl, const Lane<G, P> &ln, float nrho_f) {
@@ -338,51 +355,119 @@ __device__ __forceinline__ uint32_t lookup1(const uint32_t *tile, float u, float
     return m & ln.mark;
 }
 
-// The kept hits of a stage are known as a 64-bit mask over stage slots; the lanes set the keep
-// bits of their own slots together.  Each hit belongs to one wave's range and is staged only
-// while its bit is clear, so the number of newly kept hits is the popcount of the mask.
-__device__ __forceinline__ uint32_t keep_slots(uint32_t *keepbits, const uint32_t *sidx,
-                                               uint64_t kept, int lane) {
-    if ((kept >> lane) & 1ull) {
-        const uint32_t hit = sidx[lane];
-        __hip_atomic_fetch_or(&keepbits[hit >> 5], 1u << (hit & 31), __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_WORKGROUP);
+// Look up the hits held by the lanes in `safe` and `checked` (values broadcast by readlane);
+// returns the lane mask of the kept ones.  Hits are taken four at a time so that their cell
+// reads are in flight together.
+template <int G, bool P>
+__device__ __forceinline__ uint64_t lookup_lanes(const uint32_t *tile, float u, float v, uint64_t safe,
+                                                 uint64_t checked, const Cols<G> &cl,
+                                                 const Lane<G, P> &ln, float nrho_f) {
+    uint64_t kept = 0, m = safe;
+    uint32_t n = (uint32_t)__popcll(m);
+    for (; n >= 4; n -= 4) {
+        const int l0 = __builtin_ctzll(m); m &= m - 1;
+        const int l1 = __builtin_ctzll(m); m &= m - 1;
+        const int l2 = __builtin_ctzll(m); m &= m - 1;
+        const int l3 = __builtin_ctzll(m); m &= m - 1;
+        const uint32_t m0 = lookup1<G, P>(tile, lane_value(u, l0), lane_value(v, l0), false, cl, ln, nrho_f);
+        const uint32_t m1 = lookup1<G, P>(tile, lane_value(u, l1), lane_value(v, l1), false, cl, ln, nrho_f);
+        const uint32_t m2 = lookup1<G, P>(tile, lane_value(u, l2), lane_value(v, l2), false, cl, ln, nrho_f);
+        const uint32_t m3 = lookup1<G, P>(tile, lane_value(u, l3), lane_value(v, l3), false, cl, ln, nrho_f);
+        kept |= __ballot(m0 != 0u) ? (1ull << l0) : 0ull;
+        kept |= __ballot(m1 != 0u) ? (1ull << l1) : 0ull;
+        kept |= __ballot(m2 != 0u) ? (1ull << l2) : 0ull;
+        kept |= __ballot(m3 != 0u) ? (1ull << l3) : 0ull;
     }
+    for (; n > 0; --n) {
+        const int l = __builtin_ctzll(m); m &= m - 1;
+        const uint32_t mm = lookup1<G, P>(tile, lane_value(u, l), lane_value(v, l), false, cl, ln, nrho_f);
+        kept |= __ballot(mm != 0u) ? (1ull << l) : 0ull;
+    }
+    for (uint64_t k = checked; k; k &= k - 1) {
+        const int l = __builtin_ctzll(k);
+        const uint32_t mm = lookup1<G, P>(tile, lane_value(u, l), lane_value(v, l), true, cl, ln, nrho_f);
+        kept |= __ballot(mm != 0u) ? (1ull << l) : 0ull;
+    }
+    return kept;
+}
+
+__device__ __forceinline__ void set_keep(uint32_t *keepbits, uint32_t hit) {
+    __hip_atomic_fetch_or(&keepbits[hit >> 5], 1u << (hit & 31), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Hits of a wave's range that are valid and not yet kept, once there are at most 64 of them:
+// lane l holds one (u, v, event-local index) and `live` marks the lanes still pending.  Later
+// tiles look up only these instead of mapping the whole range again.
+struct Pending {
+    float u, v;
+    uint32_t idx;
+    uint64_t live;   // wave-uniform
+    bool on;         // wave-uniform
+};
+
+// Collect the valid unkept hits of [hb, he) into the pending list (caller: at most 64 of them),
+// compacting them through the wave's 64-entry LDS scratch.
+__device__ void build_pending(Pending &pd, float2 *scr, uint32_t *sidx, const float *x, const float *y,
+                             uint32_t hb, uint32_t he, const uint32_t *keepbits, int lane) {
+    uint32_t n = 0;
+    for (uint32_t base = hb; base < he; base += 64) {
+        const uint32_t i = base + lane;
+        const bool cand = (i < he) && !((keepbits[i >> 5] >> (i & 31)) & 1u);
+        float xi = 0.0f, yi = 0.0f;
+        if (cand) { xi = x[i]; yi = y[i]; }
+        float u, v;
+        const bool ok = conformal(xi, yi, u, v) && cand;
+        const uint64_t b = __ballot(ok);
+        if (ok) {
+            const uint32_t pos = n + mbcnt(b);
+            scr[pos] = make_float2(u, v);
+            sidx[pos] = i;
+        }
+        n += (uint32_t)__popcll(b);
+    }
+    wave_sync();
+    pd.on = true;
+    pd.live = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+    if ((uint32_t)lane < n) {
+        const float2 p = scr[lane];
+        pd.u = p.x;
+        pd.v = p.y;
+        pd.idx = sidx[lane];
+    }
+    wave_sync();
+}
+
+// Step 5 for the pending list.  Every lookup takes the literal range test.
+template <int G, bool P>
+__device__ uint32_t retain_pending(Pending &pd, const uint32_t *tile, uint32_t *keepbits,
+                                   const Cols<G> &cl, const Lane<G, P> &ln, const GridArgs &g, int lane) {
+    if (!pd.live) return 0u;
+    const uint64_t kept = lookup_lanes<G, P>(tile, pd.u, pd.v, 0ull, pd.live, cl, ln, g.nrho_f);
+    if ((kept >> lane) & 1ull) set_keep(keepbits, pd.idx);
+    pd.live &= ~kept;
     return (uint32_t)__popcll(kept);
 }
 
+// Step 5 over the whole range [hb, he): every unkept valid hit is mapped again and looked up;
+// each lane sets the keep bit of its own hit.  Returns the number of hits newly kept; `left`
+// receives how many valid hits remain unkept.
 template <int G, bool P>
-__device__ uint32_t retain_range(const uint32_t *tile, float2 *st, uint32_t *sidx, const float *x,
-                                 const float *y, uint32_t hb, uint32_t he, uint32_t *keepbits,
-                                 const Cols<G> &cl, const Lane<G, P> &ln, const GridArgs &g, int lane) {
+__device__ uint32_t retain_range(const uint32_t *tile, const float *x, const float *y, uint32_t hb,
+                                 uint32_t he, uint32_t *keepbits, const Cols<G> &cl,
+                                 const Lane<G, P> &ln, const GridArgs &g, int lane, uint32_t &left) {
     uint32_t unused = 0, newly = 0;
+    left = 0;
     for (uint32_t base = hb; base < he; base += 64) {
         const uint32_t i = base + lane;
         const bool done = (i < he) && ((keepbits[i >> 5] >> (i & 31)) & 1u);
         if (__ballot((i < he) && !done) == 0ull) continue;      // whole chunk already kept
-        const StageCount n = stage_hits(st, sidx, x, y, base, he, done, g, lane, unused);
-        const float4 *st4 = reinterpret_cast<const float4 *>(st);
-        uint64_t kept = 0;
-        uint32_t h = 0;
-        for (; h + 4 <= n.safe; h += 4) {
-            const float4 a = st4[h >> 1], b = st4[(h >> 1) + 1];
-            const uint32_t m0 = lookup1<G, P>(tile, a.x, a.y, false, cl, ln, g.nrho_f);
-            const uint32_t m1 = lookup1<G, P>(tile, a.z, a.w, false, cl, ln, g.nrho_f);
-            const uint32_t m2 = lookup1<G, P>(tile, b.x, b.y, false, cl, ln, g.nrho_f);
-            const uint32_t m3 = lookup1<G, P>(tile, b.z, b.w, false, cl, ln, g.nrho_f);
-            const uint64_t one = 1ull << h;
-            kept |= __ballot(m0 != 0u) ? one : 0ull;
-            kept |= __ballot(m1 != 0u) ? one << 1 : 0ull;
-            kept |= __ballot(m2 != 0u) ? one << 2 : 0ull;
-            kept |= __ballot(m3 != 0u) ? one << 3 : 0ull;
-        }
-        for (; h < n.total; ++h) {
-            const float2 p = st[h];
-            const uint32_t m = lookup1<G, P>(tile, p.x, p.y, h >= n.safe, cl, ln, g.nrho_f);
-            kept |= __ballot(m != 0u) ? (1ull << h) : 0ull;
-        }
-        newly += keep_slots(keepbits, sidx, kept, lane);
-        wave_sync();
+        const Chunk c = map_chunk(x, y, base, he, done, g, lane, unused);
+        const uint64_t kept = lookup_lanes<G, P>(tile, c.u, c.v, c.safe, c.checked, cl, ln, g.nrho_f);
+        if ((kept >> lane) & 1ull) set_keep(keepbits, i);
+        const uint32_t nk = (uint32_t)__popcll(kept);
+        newly += nk;
+        left += (uint32_t)__popcll(c.safe | c.checked) - nk;
     }
     return newly;
 }
@@ -395,7 +480,6 @@ __global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__res
                                                   void *acc, int acc_type) {
     extern __shared__ __align__(16) uint32_t lds[];
     uint32_t *tile = lds;
-    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * 64);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int first = blockIdx.x * 64;
     for (int i = threadIdx.x; i < g.n_rho * 16; i += NW * 64)
@@ -406,7 +490,7 @@ __global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__res
     const uint32_t he = (uint32_t)((uint64_t)n_hits * (wave + 1) / NW);
     uint32_t bad = 0;
     const Lane<1, false> ln(lane);
-    vote_range<1, false>(tile, stage + wave * 64, x, y, hb, he, cl, ln, g, lane, bad);
+    vote_range<1, false>(tile, x, y, hb, he, cl, ln, g, lane, bad);
     __syncthreads();
     // Write-out: lane = column (theta row of acc), wave = a slice of rho.
     const int j = first + lane;
@@ -558,8 +642,8 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
     constexpr int TW = L::TW, ST = L::STRIDE, OUT = TW - 2, NT = NW * 64;
     extern __shared__ __align__(16) uint32_t lds[];
     uint32_t *tile = lds;                                                  // [(n_rho + 1) * ST]
-    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * ST);   // [NW * 64]
-    uint32_t *sidx = reinterpret_cast<uint32_t *>(stage + NW * 64);        // [NW * 64]
+    float2 *scratch = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * ST);  // [NW * 64]
+    uint32_t *sidx = reinterpret_cast<uint32_t *>(scratch + NW * 64);      // [NW * 64]
     uint32_t *pmask = sidx + NW * 64;                                      // [nwords * TW]
     uint32_t *keepbits = pmask + (size_t)nwords * TW;                      // [kMaxBatchHits / 32 + 1]
     __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept;
@@ -577,7 +661,10 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             }
             break;
         }
-        const uint32_t h0 = a.offsets[e], h1 = a.offsets[e + 1];
+        // event e of this launch is pool event ids[e] (or e itself); its keep bytes start at
+        // keep_offsets[e] (or at its first hit)
+        const uint32_t pe_id = a.ids ? a.ids[e] : e;
+        const uint32_t h0 = a.offsets[pe_id], h1 = a.offsets[pe_id + 1];
         if (h1 < h0) {                       // malformed offsets: touch nothing but the counters
             if (threadIdx.x == 0) { a.n_peaks[e] = 0u; a.status[e] = HOUGH_EV_TOO_MANY_HITS; }
             __syncthreads();
@@ -585,7 +672,8 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
         }
         const uint32_t H = h1 - h0;
         if (H > kMaxBatchHits || H == 0u) {
-            for (uint32_t i = threadIdx.x; i < H; i += NT) a.keep[h0 + i] = 0u;
+            uint8_t *ke = a.keep + (a.ids ? a.keep_offsets[e] : h0);
+            for (uint32_t i = threadIdx.x; i < H; i += NT) ke[i] = 0u;
             if (threadIdx.x == 0) {
                 a.n_peaks[e] = 0u;
                 a.status[e] = H ? HOUGH_EV_TOO_MANY_HITS : 0u;
@@ -601,13 +689,18 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
         hough_peak *pe = a.peaks ? a.peaks + (size_t)e * a.max_peaks : nullptr;
         const uint32_t cap = pe ? a.max_peaks : 0u;
         uint32_t bad = 0;
+        Pending pd;
+        pd.u = pd.v = 0.0f;
+        pd.idx = 0u;
+        pd.live = 0ull;
+        pd.on = false;
         for (int t = 0; t < n_tiles; ++t) {
             const int first = t * OUT - 1;      // grid column of lane 0 of group 0
             const Cols<G> cl = load_cols<G>(g, first, lane);
             for (int i = threadIdx.x; i < (g.n_rho + 1) * ST / 4; i += NT)
                 reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
             __syncthreads();
-            const uint32_t nv = vote_range<G, true>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad);
+            const uint32_t nv = vote_range<G, true>(tile, xe, ye, hb, he, cl, ln, g, lane, bad);
             if (t == 0 && lane == 0 && nv) atomicAdd(&s_nvalid, nv);
             __syncthreads();
             for (int u = wave; u < 2 * nwords; u += NW) {
@@ -628,15 +721,24 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             __syncthreads();
             if (threadIdx.x == 0) s_npeaks = base + np;
             if (np && s_nkept < s_nvalid) {
-                const uint32_t newly = retain_range<G, true>(tile, stage + wave * 64, sidx + wave * 64,
-                                                             xe, ye, hb, he, keepbits, cl, ln, g, lane);
+                uint32_t newly;
+                if (pd.on) {
+                    newly = retain_pending<G, true>(pd, tile, keepbits, cl, ln, g, lane);
+                } else {
+                    uint32_t left = 0;
+                    newly = retain_range<G, true>(tile, xe, ye, hb, he, keepbits, cl, ln, g, lane, left);
+                    if (left <= 64u)
+                        build_pending(pd, scratch + wave * 64, sidx + wave * 64, xe, ye, hb, he,
+                                      keepbits, lane);
+                }
                 if (lane == 0 && newly) atomicAdd(&s_nkept, newly);
             }
             __syncthreads();
         }
         if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
+        uint8_t *ke = a.keep + (a.ids ? a.keep_offsets[e] : h0);
         for (uint32_t i = threadIdx.x; i < H; i += NT)
-            a.keep[h0 + i] = (uint8_t)((keepbits[i >> 5] >> (i & 31)) & 1u);
+            ke[i] = (uint8_t)((keepbits[i >> 5] >> (i & 31)) & 1u);
         __syncthreads();
         if (threadIdx.x == 0) {
             const uint32_t np = s_npeaks;
@@ -651,17 +753,22 @@ constexpr int kVoteWaves = 16;
 constexpr int kPeakWaves = 16;
 constexpr int kRetainWaves = 8;
 
+// The dynamic-LDS limit is a per-kernel, process-wide attribute: every kernel is allowed the
+// device maximum (less room for its static LDS) so that contexts with different grids, possibly
+// on different host threads, never lower each other's limit.
 template <typename K>
-void allow_lds(K kernel, size_t bytes) {
+void allow_lds(K kernel) {
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return;
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim - 256);
 }
 
 }  // namespace
 
-size_t vote_lds_bytes(int n_rho) {
-    return (size_t)(n_rho + 1) * 64 * 4 + (size_t)kVoteWaves * 64 * sizeof(float2) + 256;
-}
+size_t vote_lds_bytes(int n_rho) { return (size_t)(n_rho + 1) * 64 * 4 + 256; }
 
 size_t peaks_lds_bytes(int n_rho) { return (size_t)(kPeakWaves + 2) * n_rho * 4 + 256; }
 
@@ -689,7 +796,8 @@ int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, 
 hipError_t launch_vote(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                        void *acc, int acc_type, hipStream_t s) {
     const size_t lds = vote_lds_bytes(g.n_rho);
-    allow_lds(k_vote<kVoteWaves>, lds);
+    static const bool lds_ok = (allow_lds(k_vote<kVoteWaves>), true);
+    (void)lds_ok;
     const int blocks = (g.n_theta + 63) / 64;
     hipLaunchKernelGGL(k_vote<kVoteWaves>, dim3(blocks), dim3(kVoteWaves * 64), lds, s, g, x, y,
                        n_hits, acc, acc_type);
@@ -700,11 +808,13 @@ hipError_t launch_peaks(const GridArgs &g, const void *acc, int acc_type, hough_
                         uint32_t cap, uint32_t *n_peaks, hipStream_t s) {
     const size_t lds = peaks_lds_bytes(g.n_rho);
     if (acc_type == HOUGH_ACC_U16) {
-        allow_lds(k_peaks<kPeakWaves, uint16_t>, lds);
+        static const bool lds_ok = (allow_lds(k_peaks<kPeakWaves, uint16_t>), true);
+        (void)lds_ok;
         hipLaunchKernelGGL((k_peaks<kPeakWaves, uint16_t>), dim3(1), dim3(kPeakWaves * 64), lds, s, g,
                            static_cast<const uint16_t *>(acc), peaks, cap, n_peaks);
     } else {
-        allow_lds(k_peaks<kPeakWaves, uint32_t>, lds);
+        static const bool lds_ok = (allow_lds(k_peaks<kPeakWaves, uint32_t>), true);
+        (void)lds_ok;
         hipLaunchKernelGGL((k_peaks<kPeakWaves, uint32_t>), dim3(1), dim3(kPeakWaves * 64), lds, s, g,
                            static_cast<const uint32_t *>(acc), peaks, cap, n_peaks);
     }
@@ -721,7 +831,8 @@ hipError_t launch_retain(const GridArgs &g, const float *x, const float *y, uint
     if (rows > g.n_theta) rows = g.n_theta;
     if (rows < 1) rows = 1;
     const size_t lds = (size_t)rows * words * 4 + (size_t)rows * 4;
-    allow_lds(k_retain<kRetainWaves>, lds);
+    static const bool lds_ok = (allow_lds(k_retain<kRetainWaves>), true);
+    (void)lds_ok;
     const int blocks = (int)((n_hits + kRetainWaves * 64 - 1) / (kRetainWaves * 64));
     hipLaunchKernelGGL(k_retain<kRetainWaves>, dim3(blocks), dim3(kRetainWaves * 64), lds, s, g, x, y,
                        n_hits, peaks, n_peaks, cap, keep, rows);
@@ -731,7 +842,6 @@ hipError_t launch_retain(const GridArgs &g, const float *x, const float *y, uint
 template <int NW, int G>
 static hipError_t launch_batch_t(const GridArgs &g, const BatchPlan &p, const BatchArgs &a,
                                  hipStream_t s) {
-    allow_lds(k_batch<NW, G>, p.lds_bytes);
     const int nwords = (g.n_rho + 31) / 32;
     hipLaunchKernelGGL((k_batch<NW, G>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
                        p.n_tiles, nwords);
@@ -750,20 +860,26 @@ hipError_t launch_batch(const GridArgs &g, const BatchPlan &p, const BatchArgs &
     }
 }
 
-// Workgroups of the fused kernel that fit one CU at once (for sizing the persistent grid).
-int batch_blocks_per_cu(const BatchPlan &p) {
+template <int NW, int G>
+static int prepare_t(size_t lds, size_t) {
+    allow_lds(k_batch<NW, G>);
     int n = 0;
-    hipError_t err = hipErrorInvalidValue;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<NW, G>, NW * 64, lds) != hipSuccess) return 0;
+    return n;
+}
+
+// Allow the plan's dynamic LDS for its kernel and return how many of its workgroups fit a CU
+// (0 if none).  Done once when a plan is chosen, so that launches make no other runtime calls.
+int prepare_batch(const BatchPlan &p, size_t lds_limit) {
     switch (p.waves * 10 + p.groups) {
-        case 41: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<4, 1>, 256, p.lds_bytes); break;
-        case 42: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<4, 2>, 256, p.lds_bytes); break;
-        case 81: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<8, 1>, 512, p.lds_bytes); break;
-        case 82: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<8, 2>, 512, p.lds_bytes); break;
-        case 161: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<16, 1>, 1024, p.lds_bytes); break;
-        case 162: err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<16, 2>, 1024, p.lds_bytes); break;
-        default: break;
+        case 41: return prepare_t<4, 1>(p.lds_bytes, lds_limit);
+        case 42: return prepare_t<4, 2>(p.lds_bytes, lds_limit);
+        case 81: return prepare_t<8, 1>(p.lds_bytes, lds_limit);
+        case 82: return prepare_t<8, 2>(p.lds_bytes, lds_limit);
+        case 161: return prepare_t<16, 1>(p.lds_bytes, lds_limit);
+        case 162: return prepare_t<16, 2>(p.lds_bytes, lds_limit);
+        default: return 0;
     }
-    return err == hipSuccess ? n : 0;
 }
 
 }  // namespace hough

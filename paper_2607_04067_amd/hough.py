@@ -29,6 +29,11 @@ class HoughError(RuntimeError):
         self.status = status
 
 
+class hough_batch_plan(ctypes.Structure):
+    _fields_ = [("waves_per_group", ctypes.c_int32), ("column_groups", ctypes.c_int32),
+                ("groups_per_cu", ctypes.c_int32), ("lds_bytes", ctypes.c_int32)]
+
+
 class hough_params(ctypes.Structure):
     _fields_ = [("n_theta", ctypes.c_int32), ("n_rho", ctypes.c_int32),
                 ("rho_min", ctypes.c_double), ("rho_max", ctypes.c_double),
@@ -62,6 +67,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.hough_retain.restype = i32
     L.hough_run_batch.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp]
     L.hough_run_batch.restype = i32
+    L.hough_run_batch_gather.argtypes = [vp, vp, vp, vp, vp, vp, u32, vp, vp, vp, vp, vp]
+    L.hough_run_batch_gather.restype = i32
+    L.hough_get_batch_plan.argtypes = [vp, ctypes.POINTER(hough_batch_plan)]
+    L.hough_get_batch_plan.restype = i32
+    L.hough_set_batch_plan.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.hough_set_batch_plan.restype = i32
     L.hough_max_batch_hits.argtypes = [vp]
     L.hough_max_batch_hits.restype = u32
     L.hough_max_n_rho.argtypes = []
@@ -159,6 +170,17 @@ class Context:
     def max_batch_hits(self) -> int:
         return int(self._lib.hough_max_batch_hits(self._ctx))
 
+    @property
+    def batch_plan(self) -> dict:
+        p = hough_batch_plan()
+        _check(self._lib.hough_get_batch_plan(self._ctx, ctypes.byref(p)), "hough_get_batch_plan")
+        return {"waves_per_group": p.waves_per_group, "column_groups": p.column_groups,
+                "groups_per_cu": p.groups_per_cu, "lds_bytes": p.lds_bytes}
+
+    def set_batch_plan(self, waves_per_group: int, column_groups: int) -> None:
+        _check(self._lib.hough_set_batch_plan(self._ctx, int(waves_per_group), int(column_groups)),
+               "hough_set_batch_plan")
+
     def _ptr_or_dummy(self, t: torch.Tensor, dtype, name: str) -> int:
         if t.numel() == 0:
             return self._dummy.data_ptr()
@@ -233,6 +255,37 @@ class Context:
         py = self._ptr_or_dummy(y, torch.float32, "y")
         _check(self._lib.hough_run_batch(self._ctx, px, py, po, E, pp, pn, pk, ps, _stream(stream)),
                "hough_run_batch")
+        return peaks, n_peaks, keep, status
+
+
+    def run_batch_gather(self, x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, event_ids: torch.Tensor,
+                         keep_offsets: torch.Tensor, peaks: torch.Tensor | None = None,
+                         n_peaks: torch.Tensor | None = None, keep: torch.Tensor | None = None,
+                         status: torch.Tensor | None = None, keep_size: int | None = None, stream=None):
+        """hough_run_batch over pool events `event_ids` (int32, uint32 values); event e's keep
+        bytes start at keep_offsets[e] (int32).  Returns (peaks, n_peaks, keep, status)."""
+        E = event_ids.numel()
+        mp = self.params.max_peaks
+        dev = offsets.device
+        if peaks is None:
+            peaks = torch.zeros((max(E, 1), max(mp, 1), 2), dtype=torch.int32, device=dev)
+        if n_peaks is None:
+            n_peaks = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
+        if status is None:
+            status = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
+        if keep is None:
+            keep = torch.zeros(max(int(keep_size or 0), 1), dtype=torch.uint8, device=dev)
+        po = _dev(offsets, torch.int32, "offsets")
+        pi = _dev(event_ids, torch.int32, "event_ids", E) if E else self._dummy.data_ptr()
+        pko = _dev(keep_offsets, torch.int32, "keep_offsets", E) if E else self._dummy.data_ptr()
+        pp = _dev(peaks, torch.int32, "peaks", 2 * E * mp) if mp > 0 else 0
+        pn = _dev(n_peaks, torch.int32, "n_peaks", E)
+        ps = _dev(status, torch.int32, "status", E)
+        pk = self._ptr_or_dummy(keep, torch.uint8, "keep")
+        px = self._ptr_or_dummy(x, torch.float32, "x")
+        py = self._ptr_or_dummy(y, torch.float32, "y")
+        _check(self._lib.hough_run_batch_gather(self._ctx, px, py, po, pi, pko, E, pp, pn, pk, ps,
+                                                _stream(stream)), "hough_run_batch_gather")
         return peaks, n_peaks, keep, status
 
 

@@ -291,3 +291,145 @@ def test_invalid_arguments(H):
     with pytest.raises(ValueError):
         ctx.vote(torch.from_numpy(x), torch.from_numpy(y))        # host tensors are refused
     ctx.close()
+
+
+def test_every_launch_plan_gives_identical_results(H):
+    import torch
+    for name, n in [("plain-16ev-180x128", 16), ("paper-1000ev-360x256", 40), ("dense-2000ev-720x512", 6)]:
+        wl = synth.WORKLOADS[name]
+        ev = synth.make_events(wl, 0, n_events=n)
+        ctx = H.Context.for_workload(wl, max_peaks=16384, threshold=max(wl.threshold, 20))
+        xt, yt, ot = H.to_device(ev)
+        ref = [t.clone() for t in ctx.run_batch(xt, yt, ot)]
+        tried = 0
+        for w in (4, 8, 16):
+            for gr in (1, 2):
+                try:
+                    ctx.set_batch_plan(w, gr)
+                except H.HoughError:
+                    continue
+                tried += 1
+                say(f"plan {name} waves={w} groups={gr} -> {ctx.batch_plan}")
+                out = ctx.run_batch(xt, yt, ot)
+                assert all(torch.equal(a, b) for a, b in zip(ref, out)), (name, w, gr)
+        assert tried >= 3
+        ctx.close()
+
+
+def test_autotune_keeps_results(H, tmp_path):
+    import torch
+    from paper_2607_04067_amd import autotune
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    ev = synth.make_events(wl, 0, n_events=64)
+    ctx = H.Context.for_workload(wl, max_peaks=8192)
+    xt, yt, ot = H.to_device(ev)
+    ref = [t.clone() for t in ctx.run_batch(xt, yt, ot)]
+    outs = [torch.zeros_like(t) for t in ref]
+    cache = str(tmp_path / "plans.json")
+    entry = autotune.tune(ctx, xt, yt, ot, outs, mean_hits=ev.n_hits / ev.n_events, cache=cache, reps=2)
+    w, g = entry["plan"]
+    assert ctx.batch_plan["waves_per_group"] == w and ctx.batch_plan["column_groups"] == g
+    assert all(torch.equal(a, b) for a, b in zip(ref, ctx.run_batch(xt, yt, ot)))
+    again = autotune.tune(ctx, xt, yt, ot, outs, mean_hits=ev.n_hits / ev.n_events, cache=cache)
+    assert again["plan"] == entry["plan"]          # served from the cache
+    ctx.close()
+
+
+def test_run_batch_in_hip_graph(H):
+    """Capture one hough_run_batch in a graph; every replay (with eager work in between) must
+    reproduce the eager result."""
+    import torch
+    wl = synth.WORKLOADS["batch-10000ev-360x256"]
+    ev = synth.make_events(wl, 0, n_events=200)
+    other = synth.make_events(wl, 5, n_events=50)
+    ctx = H.Context.for_workload(wl, max_peaks=8192)
+    xt, yt, ot = H.to_device(ev)
+    xo, yo, oo = H.to_device(other)
+    outs = [t for t in ctx.run_batch(xt, yt, ot)]
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in outs]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ctx.run_batch(xt, yt, ot, *outs, stream=torch.cuda.current_stream())
+    for r in range(4):
+        for t in outs:
+            t.zero_()
+        ctx.run_batch(xo, yo, oo)                   # eager work on other data between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(ref, outs)), r
+    ctx.close()
+
+
+def test_gather_batches_equal_plain_batches(H):
+    """A batch formed from pool indices (repeats allowed, keep at batch-local offsets) gives the
+    same per-event results as a CSR batch of the same events."""
+    import torch
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    pool = synth.make_events(wl, 0, n_events=40)
+    ctx = H.Context.for_workload(wl, max_peaks=8192)
+    xt, yt, ot = H.to_device(pool)
+    ids = np.array([7, 3, 3, 39, 0, 21, 7, 12], np.int64)
+    sub = pool.subset(ids)
+    koff = sub.offsets[:-1].astype(np.int32)
+    g = ctx.run_batch_gather(xt, yt, ot, _t(ids.astype(np.int32)), _t(koff), keep_size=sub.n_hits)
+    xs, ys, os_ = H.to_device(sub)
+    r = ctx.run_batch(xs, ys, os_)
+    torch.cuda.synchronize()
+    assert torch.equal(g[1], r[1]) and torch.equal(g[3], r[3])
+    assert torch.equal(g[2][:sub.n_hits], r[2][:sub.n_hits])
+    for e in range(len(ids)):
+        m = min(int(r[1][e]), 8192)
+        assert torch.equal(g[0][e, :m], r[0][e, :m])
+    ctx.close()
+
+
+def _serve_pools(H, n_each=48):
+    from paper_2607_04067_amd import serve
+    pools = []
+    for name in ("paper-1000ev-360x256", "dense-2000ev-720x512"):
+        wl = synth.WORKLOADS[name]
+        ev = synth.make_events(wl, 7, n_events=n_each)
+        ctx = H.Context.for_workload(wl, max_peaks=16384)
+        pools.append(serve.Pool(ctx, ev))
+    return pools
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_served_results_equal_results_alone(H, plain):
+    """Each request's n_peaks, status, keep and peak list in the served mix (continuous
+    batching over several streams) equal the same event processed alone."""
+    import torch
+    from paper_2607_04067_amd import serve
+    pools = _serve_pools(H)
+    trace = serve.poisson_trace(2e5 if not plain else 2e4, 0.002 if not plain else 0.004,
+                                [p.batch.n_events for p in pools], [0.5, 0.5], seed=3)
+    assert trace.size > 20
+    res, keep, peaks = serve.run(pools, trace, n_streams=4, max_batch_events=16, max_batch_hits=40000,
+                                 plain=plain, want_keep=True, want_peaks=16384)
+    say(f"served {trace.size} requests plain={plain}: {serve.summarize(trace, res)}")
+    off = 0
+    alone = {}
+    for i, (k, e) in enumerate(zip(trace["kind"], trace["event"])):
+        p = pools[k]
+        if (k, e) not in alone:
+            sub = p.batch.subset([int(e)])
+            xs, ys, os_ = H.to_device(sub)
+            pk, n, kp, st = p.ctx.run_batch(xs, ys, os_)
+            torch.cuda.synchronize()
+            alone[(k, e)] = (int(n[0]), int(st[0]), kp.cpu().numpy()[:sub.n_hits].copy(),
+                             H.decode_peaks(pk[0], min(int(n[0]), 16384)))
+        n, st, kp, pl = alone[(k, e)]
+        assert res["n_peaks"][i] == n
+        if not plain:
+            assert res["status"][i] == st
+        h = kp.size
+        assert np.array_equal(keep[off:off + h], kp), i
+        assert np.array_equal(H.decode_peaks(peaks[i], min(n, 16384)), pl), i
+        off += h
+    assert np.all(res["done_us"] >= trace["arrival_us"])
+    if not plain:
+        assert res["batch_events"].max() >= 1
+    for p in pools:
+        p.ctx.close()
