@@ -147,18 +147,20 @@ int hough_run_batch_gather(hough_ctx *ctx, const float *x, const float *y, const
  * over waves_per_group waves of a workgroup; groups_per_cu workgroups run on each compute unit.
  * The schedule changes speed only, never results. */
 typedef struct hough_batch_plan {
-    int32_t waves_per_group;   /* 4, 8 or 16                                   */
-    int32_t column_groups;     /* 1 or 2                                       */
-    int32_t groups_per_cu;     /* resident workgroups per CU (read-only)       */
-    int32_t lds_bytes;         /* LDS per workgroup (read-only)                */
+    int32_t waves_per_group;   /* 4, 8 or 16                                           */
+    int32_t column_groups;     /* 1 or 2                                               */
+    int32_t groups_per_cu;     /* workgroups launched per CU (<= what fits)            */
+    int32_t lds_bytes;         /* LDS per workgroup (read-only)                        */
 } hough_batch_plan;
 
 /* The launch shape hough_run_batch currently uses (the library picks one at hough_config). */
 int hough_get_batch_plan(const hough_ctx *ctx, hough_batch_plan *out);
 
-/* Select a launch shape (for autotuning).  HOUGH_EINVAL if the combination is not supported or
- * does not fit the device; the context keeps its previous shape then. */
-int hough_set_batch_plan(hough_ctx *ctx, int32_t waves_per_group, int32_t column_groups);
+/* Select a launch shape (for autotuning).  groups_per_cu = 0 launches as many workgroups per CU
+ * as fit; a positive value launches at most that many.  HOUGH_EINVAL if the combination is not
+ * supported or does not fit the device; the context keeps its previous shape then. */
+int hough_set_batch_plan(hough_ctx *ctx, int32_t waves_per_group, int32_t column_groups,
+                         int32_t groups_per_cu);
 
 /* Largest number of hits per event hough_run_batch processes for this context. */
 uint32_t hough_max_batch_hits(const hough_ctx *ctx);

@@ -16,6 +16,9 @@
  * brings back n_peaks, status, keep and, on request, the peak list.  Results are identical to
  * processing each event alone (every output is an integer and events are independent).
  *
+ * Batches on different streams run concurrently; each stream slot therefore launches through
+ * private copies of the pools' contexts (same parameters and launch shape), made on entry.
+ *
  * With `plain` set, each request is instead processed alone by hough_vote, hough_peaks and
  * hough_retain (three launches, accumulator through HBM), one request per stream slot, under
  * the same arrivals: the per-event launch it is compared against.

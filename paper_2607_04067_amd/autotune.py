@@ -1,8 +1,8 @@
 """Autotuner for the fused batch kernel's launch shape.
 
 The schedule space is the theta-tile width (64 * column_groups columns) times the split of an
-event's hits over the waves of a workgroup (waves_per_group); the library reports how many
-workgroups fit a CU for each.  Every candidate is timed on the caller's resident batch with HIP
+event's hits over the waves of a workgroup (waves_per_group) times the number of workgroups
+launched per CU (up to what fits; fewer can divide a small batch more evenly over the grid).  Every candidate is timed on the caller's resident batch with HIP
 events and the fastest is kept.  Results are cached in a JSON file keyed by device, grid and a
 hits-per-event bucket, so that a later context with the same key starts from the tuned shape.
 The schedule never changes results, only speed.
@@ -14,7 +14,7 @@ import os
 
 import torch
 
-CANDIDATES = [(w, g) for w in (4, 8, 16) for g in (1, 2)]
+CANDIDATES = [(w, g, n) for w in (4, 8, 16) for g in (1, 2) for n in (0, 1, 2, 3)]
 DEFAULT_CACHE = os.environ.get("HOUGH_TUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "hough_batch_plans.json"))
 
@@ -56,21 +56,22 @@ def tune(ctx, x, y, offsets, outputs, mean_hits: float, cache: str | None = DEFA
     key = cache_key(ctx, mean_hits)
     table = _load(cache) if cache else {}
     if not force and key in table:
-        w, g = table[key]["plan"]
-        ctx.set_batch_plan(w, g)
+        ctx.set_batch_plan(*table[key]["plan"])
         return table[key]
     args = (x, y, offsets, *outputs)
     results = {}
-    for w, g in CANDIDATES:
+    for w, g, n in CANDIDATES:
         try:
-            ctx.set_batch_plan(w, g)
+            ctx.set_batch_plan(w, g, n)
         except RuntimeError:
             continue
-        results[f"{w}x{g}"] = round(time_plan(ctx, args, reps), 5)
+        key_c = f"{w}x{g}x{n or ctx.batch_plan['groups_per_cu']}"
+        if key_c not in results:
+            results[key_c] = round(time_plan(ctx, args, reps), 5)
     best = min(results, key=results.get)
-    w, g = (int(v) for v in best.split("x"))
-    ctx.set_batch_plan(w, g)
-    entry = {"plan": [w, g], "ms": results}
+    w, g, n = (int(v) for v in best.split("x"))
+    ctx.set_batch_plan(w, g, n)
+    entry = {"plan": [w, g, n], "ms": results}
     if cache:
         table[key] = entry
         os.makedirs(os.path.dirname(cache) or ".", exist_ok=True)

@@ -185,16 +185,18 @@ int hough_get_batch_plan(const hough_ctx *c, hough_batch_plan *out) {
     return HOUGH_OK;
 }
 
-int hough_set_batch_plan(hough_ctx *c, int32_t waves_per_group, int32_t column_groups) {
-    if (!c) return HOUGH_EINVAL;
+int hough_set_batch_plan(hough_ctx *c, int32_t waves_per_group, int32_t column_groups,
+                         int32_t groups_per_cu) {
+    if (!c || groups_per_cu < 0) return HOUGH_EINVAL;
     hough::BatchPlan p;
     if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves_per_group, column_groups, c->lds_limit, &p) != 0)
         return HOUGH_EINVAL;
     p.per_cu = hough::prepare_batch(p, c->lds_limit);
-    if (p.per_cu < 1) {
+    if (p.per_cu < 1 || groups_per_cu > p.per_cu) {
         (void)hough::prepare_batch(c->plan, c->lds_limit);
         return HOUGH_EINVAL;
     }
+    if (groups_per_cu > 0) p.per_cu = groups_per_cu;
     c->plan = p;
     return HOUGH_OK;
 }

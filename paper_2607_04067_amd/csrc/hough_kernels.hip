@@ -100,37 +100,37 @@ struct Lane {
     __device__ __forceinline__ uint32_t count(uint32_t dword) const { return (dword >> shift) & cmask; }
 };
 
-// Step 1 for up to 64 hits [base, end), one per lane.  The lane keeps its hit's (u, v); the
-// wave learns which lanes hold a valid hit whose votes are all in range (`safe`) and which hold
-// a valid hit that needs the range test (`checked`).  `skip` hides hits the caller is done with;
-// `bad` records an invalid hit.
-struct Chunk {
-    float u, v;          // this lane's hit
-    uint64_t safe;       // wave-uniform lane masks
-    uint64_t checked;
-};
+// Map up to 64 hits [base, end) (one per lane) and compact the valid ones into the wave's
+// stage: all-in-range hits first, then the others.  Returns (n_safe, n_total) and, through
+// `bad`, whether this lane met an invalid hit.  `skip` hides hits the caller is done with.
+struct StageCount { uint32_t safe, total; };
 
-__device__ __forceinline__ Chunk map_chunk(const float *x, const float *y, uint32_t base, uint32_t end,
-                                           bool skip, const GridArgs &g, int lane, uint32_t &bad) {
+__device__ __forceinline__ StageCount stage_hits(float2 *st, uint32_t *sidx, const float *x,
+                                                 const float *y, uint32_t base, uint32_t end,
+                                                 bool skip, const GridArgs &g, int lane,
+                                                 uint32_t &bad) {
     const uint32_t i = base + lane;
     const bool in = (i < end) && !skip;
     float xi = 0.0f, yi = 0.0f;
     if (in) { xi = x[i]; yi = y[i]; }
-    Chunk c;
-    const bool ok = conformal(xi, yi, c.u, c.v);
+    float u, v;
+    const bool ok = conformal(xi, yi, u, v);
     const bool valid = in && ok;
     if (in && !ok) bad = 1u;
-    const bool safe = valid && all_in_range(c.u, c.v, g);
-    c.safe = __ballot(safe);
-    c.checked = __ballot(valid && !safe);
-    return c;
+    const bool safe = valid && all_in_range(u, v, g);
+    const uint64_t bs = __ballot(safe);
+    const uint64_t bu = __ballot(valid && !safe);
+    const uint32_t ns = (uint32_t)__popcll(bs);
+    const uint32_t pos = safe ? mbcnt(bs) : ns + mbcnt(bu);
+    if (valid) {
+        st[pos] = make_float2(u, v);
+        if (sidx) sidx[pos] = i;
+    }
+    wave_sync();
+    return StageCount{ns, ns + (uint32_t)__popcll(bu)};
 }
 
-__device__ __forceinline__ float lane_value(float v, int l) {
-    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(v), l));
-}
-
-// Steps 2-3: sweep one hit (wave-uniform u, v) through the lane's columns and vote.
+// Steps 2-3: sweep one staged hit through the lane's columns and vote.
 template <int G, bool P>
 __device__ __forceinline__ void vote1(uint32_t *tile, float u, float v, const Cols<G> &cl,
                                       const Lane<G, P> &ln) {
@@ -142,59 +142,52 @@ __device__ __forceinline__ void vote1(uint32_t *tile, float u, float v, const Co
     }
 }
 
+// The staged hits are read four at a time (two 16-byte broadcast reads) one step ahead of
+// the votes that use them, so a wave never waits on its own atomics to fetch the next hits.
 template <int G, bool P>
-__device__ __forceinline__ void vote1_checked(uint32_t *tile, float u, float v, const Cols<G> &cl,
-                                              const Lane<G, P> &ln, float nrho_f) {
+__device__ __forceinline__ void vote_staged(uint32_t *tile, const float2 *st, StageCount n,
+                                            const Cols<G> &cl, const Lane<G, P> &ln, float nrho_f) {
+    const float4 *st4 = reinterpret_cast<const float4 *>(st);
+    const uint32_t n4 = n.safe >> 2;
+    if (n4) {
+        float4 a = st4[0], b = st4[1];
+        for (uint32_t i = 1; i < n4; ++i) {
+            const float4 na = st4[2 * i], nb = st4[2 * i + 1];
+            vote1<G, P>(tile, a.x, a.y, cl, ln);
+            vote1<G, P>(tile, a.z, a.w, cl, ln);
+            vote1<G, P>(tile, b.x, b.y, cl, ln);
+            vote1<G, P>(tile, b.z, b.w, cl, ln);
+            a = na;
+            b = nb;
+        }
+        vote1<G, P>(tile, a.x, a.y, cl, ln);
+        vote1<G, P>(tile, a.z, a.w, cl, ln);
+        vote1<G, P>(tile, b.x, b.y, cl, ln);
+        vote1<G, P>(tile, b.z, b.w, cl, ln);
+    }
+    for (uint32_t h = n4 * 4; h < n.safe; ++h) vote1<G, P>(tile, st[h].x, st[h].y, cl, ln);
+    for (uint32_t h = n.safe; h < n.total; ++h) {
+        const float2 p = st[h];
 #pragma unroll
-    for (int q = 0; q < G; ++q) {
-        const float w = __builtin_fmaf(v, cl.S[q], cl.B[q]);
-        const float t = __builtin_fmaf(u, cl.C[q], w);
-        if (t >= 0.0f && t < nrho_f) lds_add(&tile[(int)t * Lane<G, P>::STRIDE + ln.col[q]], ln.inc);
-    }
-}
-
-// The hits of a chunk are broadcast from the lanes that mapped them with readlane (the wave
-// walks its lane masks with find-first-set), so the LDS pipe carries only the atomics.  Four
-// hits are fetched before their votes are issued.
-template <int G, bool P>
-__device__ __forceinline__ void vote_chunk(uint32_t *tile, const Chunk &c, const Cols<G> &cl,
-                                           const Lane<G, P> &ln, float nrho_f) {
-    uint64_t m = c.safe;
-    uint32_t n = (uint32_t)__popcll(m);
-    for (; n >= 4; n -= 4) {
-        const int l0 = __builtin_ctzll(m); m &= m - 1;
-        const int l1 = __builtin_ctzll(m); m &= m - 1;
-        const int l2 = __builtin_ctzll(m); m &= m - 1;
-        const int l3 = __builtin_ctzll(m); m &= m - 1;
-        const float u0 = lane_value(c.u, l0), v0 = lane_value(c.v, l0);
-        const float u1 = lane_value(c.u, l1), v1 = lane_value(c.v, l1);
-        const float u2 = lane_value(c.u, l2), v2 = lane_value(c.v, l2);
-        const float u3 = lane_value(c.u, l3), v3 = lane_value(c.v, l3);
-        vote1<G, P>(tile, u0, v0, cl, ln);
-        vote1<G, P>(tile, u1, v1, cl, ln);
-        vote1<G, P>(tile, u2, v2, cl, ln);
-        vote1<G, P>(tile, u3, v3, cl, ln);
-    }
-    for (; n > 0; --n) {
-        const int l = __builtin_ctzll(m); m &= m - 1;
-        vote1<G, P>(tile, lane_value(c.u, l), lane_value(c.v, l), cl, ln);
-    }
-    for (uint64_t k = c.checked; k; k &= k - 1) {
-        const int l = __builtin_ctzll(k);
-        vote1_checked<G, P>(tile, lane_value(c.u, l), lane_value(c.v, l), cl, ln, nrho_f);
+        for (int q = 0; q < G; ++q) {
+            const float w = __builtin_fmaf(p.y, cl.S[q], cl.B[q]);
+            const float t = __builtin_fmaf(p.x, cl.C[q], w);
+            if (t >= 0.0f && t < nrho_f) lds_add(&tile[(int)t * Lane<G, P>::STRIDE + ln.col[q]], ln.inc);
+        }
     }
 }
 
 // Votes of hits [hb, he); returns the number of valid hits seen.
 template <int G, bool P>
-__device__ uint32_t vote_range(uint32_t *tile, const float *x, const float *y, uint32_t hb,
-                               uint32_t he, const Cols<G> &cl, const Lane<G, P> &ln,
+__device__ uint32_t vote_range(uint32_t *tile, float2 *st, const float *x, const float *y,
+                               uint32_t hb, uint32_t he, const Cols<G> &cl, const Lane<G, P> &ln,
                                const GridArgs &g, int lane, uint32_t &bad) {
     uint32_t n_valid = 0;
     for (uint32_t base = hb; base < he; base += 64) {
-        const Chunk c = map_chunk(x, y, base, he, false, g, lane, bad);
-        n_valid += (uint32_t)__popcll(c.safe | c.checked);
-        vote_chunk<G, P>(tile, c, cl, ln, g.nrho_f);
+        const StageCount n = stage_hits(st, nullptr, x, y, base, he, false, g, lane, bad);
+        n_valid += n.total;
+        vote_staged<G, P>(tile, st, n, cl, ln, g.nrho_f);
+        wave_sync();
     }
     return n_valid;
 }
@@ -340,8 +333,8 @@ __device__ uint32_t emit_and_mark(uint32_t *tile, const uint32_t *pmask, int nwo
     return carry;
 }
 
-// Step 5 on the current tile: a hit not yet kept looks up its own cell in each of the lane's
-// columns; a marked cell in any column of the tile keeps the hit.
+// Step 5 on the current tile: every hit not yet kept looks up its own cell in each of the
+// lane's columns; a marked cell in any column of the tile keeps the hit.
 template <int G, bool P>
 __device__ __forceinline__ uint32_t lookup1(const uint32_t *tile, float u, float v, bool checked,
                                             const Cols<G> &cl, const Lane<G, P> &ln, float nrho_f) {
@@ -355,38 +348,30 @@ __device__ __forceinline__ uint32_t lookup1(const uint32_t *tile, float u, float
     return m & ln.mark;
 }
 
-// Look up the hits held by the lanes in `safe` and `checked` (values broadcast by readlane);
-// returns the lane mask of the kept ones.  Hits are taken four at a time so that their cell
-// reads are in flight together.
+// Look up the staged hits st[0 .. n.total) (the first n.safe need no range test), four at a
+// time so that their cell reads are in flight together.  Returns the mask of kept stage slots.
 template <int G, bool P>
-__device__ __forceinline__ uint64_t lookup_lanes(const uint32_t *tile, float u, float v, uint64_t safe,
-                                                 uint64_t checked, const Cols<G> &cl,
-                                                 const Lane<G, P> &ln, float nrho_f) {
-    uint64_t kept = 0, m = safe;
-    uint32_t n = (uint32_t)__popcll(m);
-    for (; n >= 4; n -= 4) {
-        const int l0 = __builtin_ctzll(m); m &= m - 1;
-        const int l1 = __builtin_ctzll(m); m &= m - 1;
-        const int l2 = __builtin_ctzll(m); m &= m - 1;
-        const int l3 = __builtin_ctzll(m); m &= m - 1;
-        const uint32_t m0 = lookup1<G, P>(tile, lane_value(u, l0), lane_value(v, l0), false, cl, ln, nrho_f);
-        const uint32_t m1 = lookup1<G, P>(tile, lane_value(u, l1), lane_value(v, l1), false, cl, ln, nrho_f);
-        const uint32_t m2 = lookup1<G, P>(tile, lane_value(u, l2), lane_value(v, l2), false, cl, ln, nrho_f);
-        const uint32_t m3 = lookup1<G, P>(tile, lane_value(u, l3), lane_value(v, l3), false, cl, ln, nrho_f);
-        kept |= __ballot(m0 != 0u) ? (1ull << l0) : 0ull;
-        kept |= __ballot(m1 != 0u) ? (1ull << l1) : 0ull;
-        kept |= __ballot(m2 != 0u) ? (1ull << l2) : 0ull;
-        kept |= __ballot(m3 != 0u) ? (1ull << l3) : 0ull;
+__device__ __forceinline__ uint64_t lookup_staged(const uint32_t *tile, const float2 *st, StageCount n,
+                                                  const Cols<G> &cl, const Lane<G, P> &ln, float nrho_f) {
+    const float4 *st4 = reinterpret_cast<const float4 *>(st);
+    uint64_t kept = 0;
+    uint32_t h = 0;
+    for (; h + 4 <= n.safe; h += 4) {
+        const float4 a = st4[h >> 1], b = st4[(h >> 1) + 1];
+        const uint32_t m0 = lookup1<G, P>(tile, a.x, a.y, false, cl, ln, nrho_f);
+        const uint32_t m1 = lookup1<G, P>(tile, a.z, a.w, false, cl, ln, nrho_f);
+        const uint32_t m2 = lookup1<G, P>(tile, b.x, b.y, false, cl, ln, nrho_f);
+        const uint32_t m3 = lookup1<G, P>(tile, b.z, b.w, false, cl, ln, nrho_f);
+        const uint64_t one = 1ull << h;
+        kept |= __ballot(m0 != 0u) ? one : 0ull;
+        kept |= __ballot(m1 != 0u) ? one << 1 : 0ull;
+        kept |= __ballot(m2 != 0u) ? one << 2 : 0ull;
+        kept |= __ballot(m3 != 0u) ? one << 3 : 0ull;
     }
-    for (; n > 0; --n) {
-        const int l = __builtin_ctzll(m); m &= m - 1;
-        const uint32_t mm = lookup1<G, P>(tile, lane_value(u, l), lane_value(v, l), false, cl, ln, nrho_f);
-        kept |= __ballot(mm != 0u) ? (1ull << l) : 0ull;
-    }
-    for (uint64_t k = checked; k; k &= k - 1) {
-        const int l = __builtin_ctzll(k);
-        const uint32_t mm = lookup1<G, P>(tile, lane_value(u, l), lane_value(v, l), true, cl, ln, nrho_f);
-        kept |= __ballot(mm != 0u) ? (1ull << l) : 0ull;
+    for (; h < n.total; ++h) {
+        const float2 p = st[h];
+        const uint32_t m = lookup1<G, P>(tile, p.x, p.y, h >= n.safe, cl, ln, nrho_f);
+        kept |= __ballot(m != 0u) ? (1ull << h) : 0ull;
     }
     return kept;
 }
@@ -396,19 +381,21 @@ __device__ __forceinline__ void set_keep(uint32_t *keepbits, uint32_t hit) {
                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+__device__ __forceinline__ uint64_t low_bits(uint32_t n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
+
 // Hits of a wave's range that are valid and not yet kept, once there are at most 64 of them:
-// lane l holds one (u, v, event-local index) and `live` marks the lanes still pending.  Later
-// tiles look up only these instead of mapping the whole range again.
+// lane l holds entry l (u, v, event-local index), lanes [0, n) are live.  Later tiles look up
+// only these instead of mapping the whole range again.
 struct Pending {
     float u, v;
     uint32_t idx;
-    uint64_t live;   // wave-uniform
+    uint32_t n;      // wave-uniform
     bool on;         // wave-uniform
 };
 
 // Collect the valid unkept hits of [hb, he) into the pending list (caller: at most 64 of them),
-// compacting them through the wave's 64-entry LDS scratch.
-__device__ void build_pending(Pending &pd, float2 *scr, uint32_t *sidx, const float *x, const float *y,
+// compacting them through the wave's stage.
+__device__ void build_pending(Pending &pd, float2 *st, uint32_t *sidx, const float *x, const float *y,
                              uint32_t hb, uint32_t he, const uint32_t *keepbits, int lane) {
     uint32_t n = 0;
     for (uint32_t base = hb; base < he; base += 64) {
@@ -421,16 +408,16 @@ __device__ void build_pending(Pending &pd, float2 *scr, uint32_t *sidx, const fl
         const uint64_t b = __ballot(ok);
         if (ok) {
             const uint32_t pos = n + mbcnt(b);
-            scr[pos] = make_float2(u, v);
+            st[pos] = make_float2(u, v);
             sidx[pos] = i;
         }
         n += (uint32_t)__popcll(b);
     }
     wave_sync();
     pd.on = true;
-    pd.live = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+    pd.n = n;
     if ((uint32_t)lane < n) {
-        const float2 p = scr[lane];
+        const float2 p = st[lane];
         pd.u = p.x;
         pd.v = p.y;
         pd.idx = sidx[lane];
@@ -438,36 +425,57 @@ __device__ void build_pending(Pending &pd, float2 *scr, uint32_t *sidx, const fl
     wave_sync();
 }
 
-// Step 5 for the pending list.  Every lookup takes the literal range test.
+// Step 5 for the pending list: stage it, look it up (every lookup takes the literal range
+// test), set the keep bits of the kept entries and compact the others back into the lanes.
 template <int G, bool P>
-__device__ uint32_t retain_pending(Pending &pd, const uint32_t *tile, uint32_t *keepbits,
-                                   const Cols<G> &cl, const Lane<G, P> &ln, const GridArgs &g, int lane) {
-    if (!pd.live) return 0u;
-    const uint64_t kept = lookup_lanes<G, P>(tile, pd.u, pd.v, 0ull, pd.live, cl, ln, g.nrho_f);
+__device__ uint32_t retain_pending(Pending &pd, const uint32_t *tile, float2 *st, uint32_t *sidx,
+                                   uint32_t *keepbits, const Cols<G> &cl, const Lane<G, P> &ln,
+                                   const GridArgs &g, int lane) {
+    if (pd.n == 0) return 0u;
+    if ((uint32_t)lane < pd.n) st[lane] = make_float2(pd.u, pd.v);
+    wave_sync();
+    const uint64_t kept = lookup_staged<G, P>(tile, st, StageCount{0u, pd.n}, cl, ln, g.nrho_f);
     if ((kept >> lane) & 1ull) set_keep(keepbits, pd.idx);
-    pd.live &= ~kept;
+    const uint64_t surv = low_bits(pd.n) & ~kept;
+    wave_sync();
+    if ((surv >> lane) & 1ull) {
+        const uint32_t pos = mbcnt(surv);
+        st[pos] = make_float2(pd.u, pd.v);
+        sidx[pos] = pd.idx;
+    }
+    wave_sync();
+    pd.n = (uint32_t)__popcll(surv);
+    if ((uint32_t)lane < pd.n) {
+        const float2 p = st[lane];
+        pd.u = p.x;
+        pd.v = p.y;
+        pd.idx = sidx[lane];
+    }
+    wave_sync();
     return (uint32_t)__popcll(kept);
 }
 
-// Step 5 over the whole range [hb, he): every unkept valid hit is mapped again and looked up;
-// each lane sets the keep bit of its own hit.  Returns the number of hits newly kept; `left`
-// receives how many valid hits remain unkept.
+// Step 5 over the whole range [hb, he): every unkept valid hit is mapped again, staged and
+// looked up; the lanes set the keep bits of their stage slots.  Returns the number of hits
+// newly kept; `left` receives how many valid hits remain unkept.
 template <int G, bool P>
-__device__ uint32_t retain_range(const uint32_t *tile, const float *x, const float *y, uint32_t hb,
-                                 uint32_t he, uint32_t *keepbits, const Cols<G> &cl,
-                                 const Lane<G, P> &ln, const GridArgs &g, int lane, uint32_t &left) {
+__device__ uint32_t retain_range(const uint32_t *tile, float2 *st, uint32_t *sidx, const float *x,
+                                 const float *y, uint32_t hb, uint32_t he, uint32_t *keepbits,
+                                 const Cols<G> &cl, const Lane<G, P> &ln, const GridArgs &g, int lane,
+                                 uint32_t &left) {
     uint32_t unused = 0, newly = 0;
     left = 0;
     for (uint32_t base = hb; base < he; base += 64) {
         const uint32_t i = base + lane;
         const bool done = (i < he) && ((keepbits[i >> 5] >> (i & 31)) & 1u);
         if (__ballot((i < he) && !done) == 0ull) continue;      // whole chunk already kept
-        const Chunk c = map_chunk(x, y, base, he, done, g, lane, unused);
-        const uint64_t kept = lookup_lanes<G, P>(tile, c.u, c.v, c.safe, c.checked, cl, ln, g.nrho_f);
-        if ((kept >> lane) & 1ull) set_keep(keepbits, i);
+        const StageCount n = stage_hits(st, sidx, x, y, base, he, done, g, lane, unused);
+        const uint64_t kept = lookup_staged<G, P>(tile, st, n, cl, ln, g.nrho_f);
+        if ((kept >> lane) & 1ull) set_keep(keepbits, sidx[lane]);
         const uint32_t nk = (uint32_t)__popcll(kept);
         newly += nk;
-        left += (uint32_t)__popcll(c.safe | c.checked) - nk;
+        left += n.total - nk;
+        wave_sync();
     }
     return newly;
 }
@@ -480,6 +488,7 @@ __global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__res
                                                   void *acc, int acc_type) {
     extern __shared__ __align__(16) uint32_t lds[];
     uint32_t *tile = lds;
+    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * 64);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int first = blockIdx.x * 64;
     for (int i = threadIdx.x; i < g.n_rho * 16; i += NW * 64)
@@ -490,7 +499,7 @@ __global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__res
     const uint32_t he = (uint32_t)((uint64_t)n_hits * (wave + 1) / NW);
     uint32_t bad = 0;
     const Lane<1, false> ln(lane);
-    vote_range<1, false>(tile, x, y, hb, he, cl, ln, g, lane, bad);
+    vote_range<1, false>(tile, stage + wave * 64, x, y, hb, he, cl, ln, g, lane, bad);
     __syncthreads();
     // Write-out: lane = column (theta row of acc), wave = a slice of rho.
     const int j = first + lane;
@@ -642,8 +651,8 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
     constexpr int TW = L::TW, ST = L::STRIDE, OUT = TW - 2, NT = NW * 64;
     extern __shared__ __align__(16) uint32_t lds[];
     uint32_t *tile = lds;                                                  // [(n_rho + 1) * ST]
-    float2 *scratch = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * ST);  // [NW * 64]
-    uint32_t *sidx = reinterpret_cast<uint32_t *>(scratch + NW * 64);      // [NW * 64]
+    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * ST);   // [NW * 64]
+    uint32_t *sidx = reinterpret_cast<uint32_t *>(stage + NW * 64);        // [NW * 64]
     uint32_t *pmask = sidx + NW * 64;                                      // [nwords * TW]
     uint32_t *keepbits = pmask + (size_t)nwords * TW;                      // [kMaxBatchHits / 32 + 1]
     __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept;
@@ -692,7 +701,7 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
         Pending pd;
         pd.u = pd.v = 0.0f;
         pd.idx = 0u;
-        pd.live = 0ull;
+        pd.n = 0u;
         pd.on = false;
         for (int t = 0; t < n_tiles; ++t) {
             const int first = t * OUT - 1;      // grid column of lane 0 of group 0
@@ -700,7 +709,7 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             for (int i = threadIdx.x; i < (g.n_rho + 1) * ST / 4; i += NT)
                 reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
             __syncthreads();
-            const uint32_t nv = vote_range<G, true>(tile, xe, ye, hb, he, cl, ln, g, lane, bad);
+            const uint32_t nv = vote_range<G, true>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad);
             if (t == 0 && lane == 0 && nv) atomicAdd(&s_nvalid, nv);
             __syncthreads();
             for (int u = wave; u < 2 * nwords; u += NW) {
@@ -723,12 +732,14 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             if (np && s_nkept < s_nvalid) {
                 uint32_t newly;
                 if (pd.on) {
-                    newly = retain_pending<G, true>(pd, tile, keepbits, cl, ln, g, lane);
+                    newly = retain_pending<G, true>(pd, tile, stage + wave * 64, sidx + wave * 64,
+                                                    keepbits, cl, ln, g, lane);
                 } else {
                     uint32_t left = 0;
-                    newly = retain_range<G, true>(tile, xe, ye, hb, he, keepbits, cl, ln, g, lane, left);
+                    newly = retain_range<G, true>(tile, stage + wave * 64, sidx + wave * 64, xe, ye,
+                                                  hb, he, keepbits, cl, ln, g, lane, left);
                     if (left <= 64u)
-                        build_pending(pd, scratch + wave * 64, sidx + wave * 64, xe, ye, hb, he,
+                        build_pending(pd, stage + wave * 64, sidx + wave * 64, xe, ye, hb, he,
                                       keepbits, lane);
                 }
                 if (lane == 0 && newly) atomicAdd(&s_nkept, newly);
@@ -768,7 +779,9 @@ void allow_lds(K kernel) {
 
 }  // namespace
 
-size_t vote_lds_bytes(int n_rho) { return (size_t)(n_rho + 1) * 64 * 4 + 256; }
+size_t vote_lds_bytes(int n_rho) {
+    return (size_t)(n_rho + 1) * 64 * 4 + (size_t)kVoteWaves * 64 * sizeof(float2) + 256;
+}
 
 size_t peaks_lds_bytes(int n_rho) { return (size_t)(kPeakWaves + 2) * n_rho * 4 + 256; }
 

@@ -24,6 +24,7 @@ struct Kind {
 // One stream and the device/pinned buffers of one batch (or one plain event) in flight.
 struct Slot {
     hipStream_t stream = nullptr;
+    std::vector<hough_ctx *> ctx;      // one private context per kind: its own work counter
     hipEvent_t done = nullptr;
     uint32_t *d_ids = nullptr, *d_koff = nullptr, *d_npk = nullptr, *d_status = nullptr;
     uint8_t *d_keep = nullptr;
@@ -54,6 +55,7 @@ struct Server {
             (void)hipHostFree(s.h_status); (void)hipHostFree(s.h_keep); (void)hipHostFree(s.h_peaks);
             if (s.done) (void)hipEventDestroy(s.done);
             if (s.stream) (void)hipStreamDestroy(s.stream);
+            for (hough_ctx *c : s.ctx) hough_destroy(c);
         }
     }
 
@@ -75,6 +77,18 @@ struct Server {
                  hipHostMalloc(&s.h_peaks, (cfg.copy_peaks ? E * (cap_max ? cap_max : 1) : 1) * sizeof(hough_peak)) == hipSuccess;
             if (!ok) return HOUGH_ENOMEM;
             s.reqs.reserve(E);
+            // batches on different streams run at the same time, so each slot launches through
+            // its own copy of every kind's context (same grid, parameters and launch shape)
+            for (const Kind &k : kinds) {
+                hough_ctx *c = nullptr;
+                const int rc = hough_config(&k.p, &c);
+                if (rc != HOUGH_OK) return rc;
+                s.ctx.push_back(c);
+                hough_batch_plan bp;
+                if (hough_get_batch_plan(k.pool.ctx, &bp) != HOUGH_OK ||
+                    hough_set_batch_plan(c, bp.waves_per_group, bp.column_groups, bp.groups_per_cu) != HOUGH_OK)
+                    return HOUGH_EINVAL;
+            }
         }
         return HOUGH_OK;
     }
@@ -193,16 +207,16 @@ extern "C" int hough_serve_run(const hough_serve_pool *pools, int32_t n_kinds, c
             if (hipMemcpyAsync(sl.d_ids, sl.h_ids, n * 4u, hipMemcpyHostToDevice, s) != hipSuccess ||
                 hipMemcpyAsync(sl.d_koff, sl.h_koff, n * 4u, hipMemcpyHostToDevice, s) != hipSuccess)
                 return HOUGH_EDEVICE;
-            st = hough_run_batch_gather(kd.pool.ctx, kd.pool.x, kd.pool.y, kd.pool.offsets, sl.d_ids, sl.d_koff,
+            st = hough_run_batch_gather(sl.ctx[(size_t)k], kd.pool.x, kd.pool.y, kd.pool.offsets, sl.d_ids, sl.d_koff,
                                         n, sl.d_peaks, sl.d_npk, sl.d_keep, sl.d_status, s);
             if (st == HOUGH_OK && hipMemcpyAsync(sl.h_status, sl.d_status, n * 4u, hipMemcpyDeviceToHost, s) != hipSuccess)
                 st = HOUGH_EDEVICE;
         } else {
             const uint32_t h0 = kd.pool.host_offsets[sl.h_ids[0]];
-            st = hough_vote(kd.pool.ctx, kd.pool.x + h0, kd.pool.y + h0, hits, sl.d_acc, s);
-            if (st == HOUGH_OK) st = hough_peaks(kd.pool.ctx, sl.d_acc, sl.d_peaks, (uint32_t)cap, sl.d_npk, s);
+            st = hough_vote(sl.ctx[(size_t)k], kd.pool.x + h0, kd.pool.y + h0, hits, sl.d_acc, s);
+            if (st == HOUGH_OK) st = hough_peaks(sl.ctx[(size_t)k], sl.d_acc, sl.d_peaks, (uint32_t)cap, sl.d_npk, s);
             if (st == HOUGH_OK)
-                st = hough_retain(kd.pool.ctx, kd.pool.x + h0, kd.pool.y + h0, hits, sl.d_peaks, sl.d_npk,
+                st = hough_retain(sl.ctx[(size_t)k], kd.pool.x + h0, kd.pool.y + h0, hits, sl.d_peaks, sl.d_npk,
                                   (uint32_t)cap, sl.d_keep, s);
         }
         if (st != HOUGH_OK) return st;

@@ -71,7 +71,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.hough_run_batch_gather.restype = i32
     L.hough_get_batch_plan.argtypes = [vp, ctypes.POINTER(hough_batch_plan)]
     L.hough_get_batch_plan.restype = i32
-    L.hough_set_batch_plan.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.hough_set_batch_plan.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.hough_set_batch_plan.restype = i32
     L.hough_max_batch_hits.argtypes = [vp]
     L.hough_max_batch_hits.restype = u32
@@ -177,9 +177,9 @@ class Context:
         return {"waves_per_group": p.waves_per_group, "column_groups": p.column_groups,
                 "groups_per_cu": p.groups_per_cu, "lds_bytes": p.lds_bytes}
 
-    def set_batch_plan(self, waves_per_group: int, column_groups: int) -> None:
-        _check(self._lib.hough_set_batch_plan(self._ctx, int(waves_per_group), int(column_groups)),
-               "hough_set_batch_plan")
+    def set_batch_plan(self, waves_per_group: int, column_groups: int, groups_per_cu: int = 0) -> None:
+        _check(self._lib.hough_set_batch_plan(self._ctx, int(waves_per_group), int(column_groups),
+                                              int(groups_per_cu)), "hough_set_batch_plan")
 
     def _ptr_or_dummy(self, t: torch.Tensor, dtype, name: str) -> int:
         if t.numel() == 0:

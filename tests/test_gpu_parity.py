@@ -302,16 +302,15 @@ def test_every_launch_plan_gives_identical_results(H):
         xt, yt, ot = H.to_device(ev)
         ref = [t.clone() for t in ctx.run_batch(xt, yt, ot)]
         tried = 0
-        for w in (4, 8, 16):
-            for gr in (1, 2):
-                try:
-                    ctx.set_batch_plan(w, gr)
-                except H.HoughError:
-                    continue
-                tried += 1
-                say(f"plan {name} waves={w} groups={gr} -> {ctx.batch_plan}")
-                out = ctx.run_batch(xt, yt, ot)
-                assert all(torch.equal(a, b) for a, b in zip(ref, out)), (name, w, gr)
+        for w, gr, gpc in [(4, 1, 0), (4, 2, 0), (8, 1, 0), (8, 2, 0), (16, 1, 0), (16, 2, 0), (8, 1, 1)]:
+            try:
+                ctx.set_batch_plan(w, gr, gpc)
+            except H.HoughError:
+                continue
+            tried += 1
+            say(f"plan {name} waves={w} groups={gr} per_cu={gpc} -> {ctx.batch_plan}")
+            out = ctx.run_batch(xt, yt, ot)
+            assert all(torch.equal(a, b) for a, b in zip(ref, out)), (name, w, gr, gpc)
         assert tried >= 3
         ctx.close()
 
@@ -327,8 +326,9 @@ def test_autotune_keeps_results(H, tmp_path):
     outs = [torch.zeros_like(t) for t in ref]
     cache = str(tmp_path / "plans.json")
     entry = autotune.tune(ctx, xt, yt, ot, outs, mean_hits=ev.n_hits / ev.n_events, cache=cache, reps=2)
-    w, g = entry["plan"]
+    w, g, n = entry["plan"]
     assert ctx.batch_plan["waves_per_group"] == w and ctx.batch_plan["column_groups"] == g
+    assert ctx.batch_plan["groups_per_cu"] == n
     assert all(torch.equal(a, b) for a, b in zip(ref, ctx.run_batch(xt, yt, ot)))
     again = autotune.tune(ctx, xt, yt, ot, outs, mean_hits=ev.n_hits / ev.n_events, cache=cache)
     assert again["plan"] == entry["plan"]          # served from the cache
