@@ -11,6 +11,7 @@ The default workload is 1,000 events on a 360 x 256 grid (threshold 10, +-1 rho 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -42,6 +43,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_id() -> str:
+    """Short hash of the kernel sources; profile records carry the one they were taken with."""
+    h = hashlib.sha256()
+    for f in ("hough_kernels.hip", "hough_internal.h"):
+        with open(os.path.join(ROOT, "paper_2607_04067_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: str, plan):
+    """HBM bytes per k_batch launch from the committed rocprofv3 counter summary of this
+    workload (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a 1 GiB device copy).
+    None when there is no summary, or the kernel sources or the launch plan differ from the
+    ones the counters were taken with."""
+    path = os.path.join(ROOT, "profiles", f"k_batch_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        text = fh.read()
+    start = text.find("```json")
+    if start < 0:
+        return None
+    rec = json.loads(text[start + 7:text.index("```", start + 7)])
+    cur = [plan["waves_per_group"], plan["column_groups"], plan["groups_per_cu"]]
+    if rec.get("source") != kernel_source_id() or rec.get("plan") != cur:
+        return None
+    return rec
+
+
 def cpu_baseline(wl, ev, budget_s: float = 20.0):
     """The CPU oracle, as it stands, on the machine's host cores over a bounded sample."""
     from oracle import oracle
@@ -57,9 +87,17 @@ def cpu_baseline(wl, ev, budget_s: float = 20.0):
     oracle.run_batch(wl, sample.x, sample.y, sample.offsets, cap=MAX_PEAKS[wl.name], n_threads=threads)
     dt = time.perf_counter() - t0
     votes = sample.n_hits * wl.n_theta
+    # the same oracle on one core, over a smaller sample (about a tenth of the budget)
+    n1 = int(min(n, max(1, 0.1 * budget_s / max(per_event, 1e-6))))
+    one = ev.subset(np.arange(n1))
+    t0 = time.perf_counter()
+    oracle.run_batch(wl, one.x, one.y, one.offsets, cap=MAX_PEAKS[wl.name], n_threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": round(n / dt, 2), "unit": "events/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} of {ev.n_events} events of {wl.name} (whole path, all peaks)",
-            "gvotes_per_s": round(votes / dt / 1e9, 4), "seconds": round(dt, 3)}
+            "gvotes_per_s": round(votes / dt / 1e9, 4), "seconds": round(dt, 3),
+            "one_core": {"events_per_s": round(n1 / dt1, 2), "sample_events": n1,
+                         "seconds": round(dt1, 3)}}
 
 
 def plain_path(H, wl, ev, n_events: int = 200):
@@ -89,9 +127,68 @@ def plain_path(H, wl, ev, n_events: int = 200):
     one_pass()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # votes that land in the grid (the accumulator total), beside the attempted votes
+    landed = torch.zeros((), dtype=torch.int64, device="cuda")
+    for e in range(sub.n_events):
+        a, b = int(offs[e]), int(offs[e + 1])
+        ctx.vote(xt[a:b], yt[a:b], acc)
+        cells = acc.to(torch.int64) & 0xFFFF if wl.acc == "u16" else acc.to(torch.int64)
+        landed += cells.sum()
+    landed_frac = float(landed.item()) / max(1, sub.n_hits * wl.n_theta)
     ctx.close()
     return {"events_per_s": round(sub.n_events / dt, 1), "events": sub.n_events,
-            "launches_per_event": 3, "ms_per_event": round(dt / sub.n_events * 1e3, 4)}
+            "launches_per_event": 3, "ms_per_event": round(dt / sub.n_events * 1e3, 4),
+            "landed_vote_fraction": round(landed_frac, 5)}
+
+
+def end_to_end(H, ctx, wl, ev, reps: int = 10):
+    """PCIe-inclusive rate of the batch path: hits and offsets from pinned host memory to HBM,
+    one fused launch, then n_peaks, status and keep (and, in the second figure, the whole
+    fixed-capacity peak buffer) back to pinned host memory, all on one stream.  Median of reps."""
+    import torch
+    E, cap = ev.n_events, MAX_PEAKS[wl.name]
+    hx = torch.from_numpy(ev.x).pin_memory()
+    hy = torch.from_numpy(ev.y).pin_memory()
+    ho = torch.from_numpy(ev.offsets.astype(np.int32)).pin_memory()
+    dx, dy = torch.empty_like(hx, device="cuda"), torch.empty_like(hy, device="cuda")
+    do = torch.empty_like(ho, device="cuda")
+    peaks = torch.zeros((E, cap, 2), dtype=torch.int32, device="cuda")
+    npk = torch.zeros(E, dtype=torch.int32, device="cuda")
+    keep = torch.zeros(ev.n_hits, dtype=torch.uint8, device="cuda")
+    status = torch.zeros(E, dtype=torch.int32, device="cuda")
+    h_npk = torch.empty(E, dtype=torch.int32).pin_memory()
+    h_status = torch.empty(E, dtype=torch.int32).pin_memory()
+    h_keep = torch.empty(ev.n_hits, dtype=torch.uint8).pin_memory()
+    h_peaks = torch.empty((E, cap, 2), dtype=torch.int32).pin_memory()
+    stream = torch.cuda.current_stream()
+
+    def once(with_peaks):
+        dx.copy_(hx, non_blocking=True)
+        dy.copy_(hy, non_blocking=True)
+        do.copy_(ho, non_blocking=True)
+        ctx.run_batch(dx, dy, do, peaks, npk, keep, status, stream)
+        h_npk.copy_(npk, non_blocking=True)
+        h_status.copy_(status, non_blocking=True)
+        h_keep.copy_(keep, non_blocking=True)
+        if with_peaks:
+            h_peaks.copy_(peaks, non_blocking=True)
+
+    out = {"h2d_bytes": 8 * ev.n_hits + 4 * (E + 1)}
+    for key, with_peaks in (("counts_keep", False), ("with_peak_buffer", True)):
+        once(with_peaks)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            once(with_peaks)
+            b.record(stream)
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = float(np.median(times))
+        out[key] = {"ms": round(ms, 4), "events_per_s": round(E / (ms / 1e3), 1)}
+    out["with_peak_buffer"]["d2h_peak_bytes"] = E * cap * 8
+    return out
 
 
 SERVE_RATES = (50_000, 100_000, 200_000, 400_000)
@@ -141,6 +238,7 @@ def main(argv=None):
     ap.add_argument("--tune", action="store_true", help="autotune the fused kernel's launch shape first")
     ap.add_argument("--graph", action="store_true", help="capture one step in a HIP graph and replay it")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-e2e", action="store_true", help="skip the PCIe-inclusive measurement")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--copy-reference-mb", type=int, default=0,
                     help="also time a plain device copy of this many MiB (HBM reference for counters)")
@@ -196,13 +294,19 @@ def main(argv=None):
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    kern_times = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    kern_ms = float(np.mean(kern_times))
     ms_per_step = wall / args.steps * 1e3
     st = status.cpu().numpy()
     keep_np = keep.cpu().numpy()
     labels = ev.labels
     events_per_s = E / (ms_per_step / 1e3)
     achieved = votes / (kern_ms / 1e3) / 1e9
+    cap = MAX_PEAKS[wl.name]
+    stored = int(np.minimum(npk.cpu().numpy().astype(np.int64), cap).sum())
+    # algorithmic HBM bytes per launch: x, y and offsets in; keep, peak records, n_peaks, status out
+    algo_bytes = 8 * ev.n_hits + 4 * (E + 1) + ev.n_hits + 8 * stored + 8 * E
+    prof = profiled_traffic(wl.name, ctx.batch_plan)
     out = {
         "metric": METRIC, "value": round(events_per_s, 1), "unit": "events/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -215,10 +319,15 @@ def main(argv=None):
                    "plan": ctx.batch_plan},
         "gvotes_per_s": round(votes / (ms_per_step / 1e3) / 1e9, 2),
         "kernel_ms": round(kern_ms, 4),
+        "kernel_ms_median": round(float(np.median(kern_times)), 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": round(VOTE_PEAK_PER_S / 1e9, 1),
                      "unit": "Gvote/s", "frac": round(achieved / (VOTE_PEAK_PER_S / 1e9), 4),
-                     "traffic": None, "kernel": "k_batch",
-                     "hbm_algorithmic_gbs": round((ev.n_hits * 9 + E * 12) / (kern_ms / 1e3) / 1e9, 2)},
+                     "traffic": prof["traffic_bytes"] if prof else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "kernel": "k_batch",
+                     "algorithmic_bytes": algo_bytes,
+                     "hbm_algorithmic_gbs": round(algo_bytes / (kern_ms / 1e3) / 1e9, 2),
+                     "hbm_frac": round(algo_bytes / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "retention": {"R_c": round(float(keep_np.mean()), 4) if keep_np.size else None,
                       "R_s": round(float(keep_np[labels >= 0].mean()), 4) if (labels >= 0).any() else None,
                       "peaks_per_event": round(float(npk.float().mean().item()), 1),
@@ -243,6 +352,9 @@ def main(argv=None):
         out["copy_reference"] = {"bytes_read": n, "bytes_written": n, "ms": round(ms, 4),
                                  "gbs": round(2 * n / (ms / 1e3) / 1e9, 1)}
         del src, dst
+    if not args.no_e2e:
+        log("end to end (pinned host buffers, PCIe)")
+        out["end_to_end"] = end_to_end(H, ctx, wl, ev)
     if not args.no_serve:
         out["serving"] = serving(H, args.serve_seconds, 0.25, 0.2)
     if not args.no_plain:
