@@ -142,28 +142,52 @@ __device__ __forceinline__ void vote1(uint32_t *tile, float u, float v, const Co
     }
 }
 
-// The staged hits are read four at a time (two 16-byte broadcast reads) one step ahead of
-// the votes that use them, so a wave never waits on its own atomics to fetch the next hits.
+// Four staged hits, one vote each per column.
+template <int G, bool P>
+__device__ __forceinline__ void vote4(uint32_t *tile, const float4 &a, const float4 &b,
+                                      const Cols<G> &cl, const Lane<G, P> &ln) {
+    vote1<G, P>(tile, a.x, a.y, cl, ln);
+    vote1<G, P>(tile, a.z, a.w, cl, ln);
+    vote1<G, P>(tile, b.x, b.y, cl, ln);
+    vote1<G, P>(tile, b.z, b.w, cl, ln);
+}
+
+// Wait for every outstanding LDS operation of the wave (lgkmcnt(0), other counters untouched).
+__device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0xc07f); }
+
+// Keep the compiler's scheduler from moving instructions across this point.
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// The staged hits are read four at a time (two 16-byte broadcast reads), one group ahead of
+// the votes that use them, alternating between two register sets.  The read of group c + 1 is
+// issued before the atomics of group c, and LDS operations complete in order, so the votes of
+// group c + 1 wait only for operations issued before the atomics of group c: a wave never
+// waits for its latest atomics.  The fences keep the compiler from reordering the groups.
 template <int G, bool P>
 __device__ __forceinline__ void vote_staged(uint32_t *tile, const float2 *st, StageCount n,
                                             const Cols<G> &cl, const Lane<G, P> &ln, float nrho_f) {
     const float4 *st4 = reinterpret_cast<const float4 *>(st);
     const uint32_t n4 = n.safe >> 2;
     if (n4) {
-        float4 a = st4[0], b = st4[1];
-        for (uint32_t i = 1; i < n4; ++i) {
-            const float4 na = st4[2 * i], nb = st4[2 * i + 1];
-            vote1<G, P>(tile, a.x, a.y, cl, ln);
-            vote1<G, P>(tile, a.z, a.w, cl, ln);
-            vote1<G, P>(tile, b.x, b.y, cl, ln);
-            vote1<G, P>(tile, b.z, b.w, cl, ln);
-            a = na;
-            b = nb;
+        float4 a0 = st4[0], b0 = st4[1];
+        lds_wait();
+        uint32_t c = 0;
+        for (; c + 2 < n4; c += 2) {
+            const float4 a1 = st4[2 * c + 2], b1 = st4[2 * c + 3];
+            sched_fence();
+            vote4<G, P>(tile, a0, b0, cl, ln);
+            sched_fence();
+            a0 = st4[2 * c + 4];
+            b0 = st4[2 * c + 5];
+            sched_fence();
+            vote4<G, P>(tile, a1, b1, cl, ln);
+            sched_fence();
         }
-        vote1<G, P>(tile, a.x, a.y, cl, ln);
-        vote1<G, P>(tile, a.z, a.w, cl, ln);
-        vote1<G, P>(tile, b.x, b.y, cl, ln);
-        vote1<G, P>(tile, b.z, b.w, cl, ln);
+        vote4<G, P>(tile, a0, b0, cl, ln);
+        if (c + 1 < n4) {
+            const float4 a1 = st4[2 * c + 2], b1 = st4[2 * c + 3];
+            vote4<G, P>(tile, a1, b1, cl, ln);
+        }
     }
     for (uint32_t h = n4 * 4; h < n.safe; ++h) vote1<G, P>(tile, st[h].x, st[h].y, cl, ln);
     for (uint32_t h = n.safe; h < n.total; ++h) {
