@@ -2,7 +2,8 @@
 
 The schedule space is the theta-tile width (64 * column_groups columns) times the split of an
 event's hits over the waves of a workgroup (waves_per_group) times the number of workgroups
-launched per CU (up to what fits; fewer can divide a small batch more evenly over the grid).  Every candidate is timed on the caller's resident batch with HIP
+launched per CU (up to what fits; fewer can divide a small batch more evenly over the grid).
+Every candidate is timed on the caller's resident batch with HIP
 events and the fastest is kept.  Results are cached in a JSON file keyed by device, grid and a
 hits-per-event bucket, so that a later context with the same key starts from the tuned shape.
 The schedule never changes results, only speed.
@@ -14,7 +15,7 @@ import os
 
 import torch
 
-CANDIDATES = [(w, g, n) for w in (4, 8, 16) for g in (1, 2) for n in (0, 1, 2, 3)]
+CANDIDATES = [(w, g, n) for w in (4, 6, 8, 16) for g in (1, 2) for n in (0, 1, 2, 3)]
 DEFAULT_CACHE = os.environ.get("HOUGH_TUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "hough_batch_plans.json"))
 

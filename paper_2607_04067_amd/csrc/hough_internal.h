@@ -11,11 +11,9 @@ namespace hough {
 // Lanes of a CDNA wavefront; every tile is a whole number of 64-column groups so that one
 // lane owns one theta column.
 constexpr int kWave = 64;
-// Largest event of the fused batch kernel: a count then fits 15 bits of a packed 16-bit LDS
-// counter (the 16th bit is the retention mark), and the keep bits of the event fit LDS.
+// Largest event of the fused batch kernel: a count then fits a packed 16-bit LDS counter, and
+// each wave's keep flags fit a few registers (at most 8192 hits per wave, 64 per lane).
 constexpr uint32_t kMaxBatchHits = 32767;
-// Bit 31 of an LDS accumulator cell marks "within rho_window of a peak" during retention.
-constexpr uint32_t kMark = 0x80000000u;
 
 // Grid constants as the kernels see them.
 struct GridArgs {

@@ -22,7 +22,7 @@
 namespace hough {
 namespace {
 
-constexpr int kStageBytes = kWave * (int)(sizeof(float2) + sizeof(uint32_t));
+constexpr int kStageBytes = kWave * (int)sizeof(float2);
 
 // ------------------------------------------------------------------ per-hit arithmetic
 // Eq. (1).  Returns false for a hit whose r2 is zero, non-finite or overflowed.
@@ -82,39 +82,34 @@ __device__ __forceinline__ Cols<G> load_cols(const GridArgs &g, int first_col, i
 // 64q + l at dword 64q + l.  Packed: two 16-bit counters per dword, columns 64q + l and
 // 64q + l + 32 (l < 32) share dword 32q + l; the two lanes sharing a dword sit in different
 // halves of the wave, which the LDS serves in separate passes, so they never conflict.
-// The top bit of a counter marks "within rho_window of a peak" during retention.
 template <int G, bool PACKED>
 struct Lane {
     static constexpr int TW = 64 * G;
     static constexpr int STRIDE = PACKED ? TW / 2 : TW;    // dwords per tile row
     uint32_t col[G];
-    uint32_t shift, inc, mark, cmask;
+    uint32_t shift, inc, cmask;
     __device__ __forceinline__ explicit Lane(int lane) {
 #pragma unroll
         for (int q = 0; q < G; ++q) col[q] = PACKED ? 32 * q + (lane & 31) : 64 * q + lane;
         shift = PACKED ? 16u * (uint32_t)(lane >> 5) : 0u;
         inc = 1u << shift;
-        mark = PACKED ? (0x8000u << shift) : kMark;
-        cmask = PACKED ? 0x7fffu : ~kMark;
+        cmask = PACKED ? 0xffffu : ~0u;
     }
     __device__ __forceinline__ uint32_t count(uint32_t dword) const { return (dword >> shift) & cmask; }
 };
 
 // Map up to 64 hits [base, end) (one per lane) and compact the valid ones into the wave's
 // stage: all-in-range hits first, then the others.  Returns (n_safe, n_total) and, through
-// `bad`, whether this lane met an invalid hit.  `skip` hides hits the caller is done with.
+// `bad`, whether this lane met an invalid hit, through `slot` the stage slot of the lane's hit
+// (-1 if none).  `skip` hides hits the caller is done with.
 struct StageCount { uint32_t safe, total; };
 
-__device__ __forceinline__ StageCount stage_hits(float2 *st, uint32_t *sidx, const float *x,
-                                                 const float *y, uint32_t base, uint32_t end,
-                                                 bool skip, const GridArgs &g, int lane,
-                                                 uint32_t &bad) {
-    const uint32_t i = base + lane;
-    const bool in = (i < end) && !skip;
-    float xi = 0.0f, yi = 0.0f;
-    if (in) { xi = x[i]; yi = y[i]; }
+// Stage the lane's hit (xi, yi) when `in`.
+__device__ __forceinline__ StageCount stage_values(float2 *st, float xi, float yi,
+                                                   bool in, const GridArgs &g,
+                                                   uint32_t &bad, int &slot) {
     float u, v;
-    const bool ok = conformal(xi, yi, u, v);
+    const bool ok = conformal(in ? xi : 0.0f, in ? yi : 0.0f, u, v);
     const bool valid = in && ok;
     if (in && !ok) bad = 1u;
     const bool safe = valid && all_in_range(u, v, g);
@@ -122,12 +117,21 @@ __device__ __forceinline__ StageCount stage_hits(float2 *st, uint32_t *sidx, con
     const uint64_t bu = __ballot(valid && !safe);
     const uint32_t ns = (uint32_t)__popcll(bs);
     const uint32_t pos = safe ? mbcnt(bs) : ns + mbcnt(bu);
-    if (valid) {
-        st[pos] = make_float2(u, v);
-        if (sidx) sidx[pos] = i;
-    }
+    if (valid) st[pos] = make_float2(u, v);
+    slot = valid ? (int)pos : -1;
     wave_sync();
     return StageCount{ns, ns + (uint32_t)__popcll(bu)};
+}
+
+__device__ __forceinline__ StageCount stage_hits(float2 *st, const float *x,
+                                                 const float *y, uint32_t base, uint32_t end,
+                                                 bool skip, const GridArgs &g, int lane,
+                                                 uint32_t &bad, int &slot) {
+    const uint32_t i = base + lane;
+    const bool in = (i < end) && !skip;
+    float xi = 0.0f, yi = 0.0f;
+    if (in) { xi = x[i]; yi = y[i]; }
+    return stage_values(st, xi, yi, in, g, bad, slot);
 }
 
 // Steps 2-3: sweep one staged hit through the lane's columns and vote.
@@ -201,14 +205,21 @@ __device__ __forceinline__ void vote_staged(uint32_t *tile, const float2 *st, St
     }
 }
 
-// Votes of hits [hb, he); returns the number of valid hits seen.
+// Votes of hits [hb, he); returns the number of valid hits seen.  The next 64 hits are loaded
+// while the current ones vote.
 template <int G, bool P>
 __device__ uint32_t vote_range(uint32_t *tile, float2 *st, const float *x, const float *y,
                                uint32_t hb, uint32_t he, const Cols<G> &cl, const Lane<G, P> &ln,
                                const GridArgs &g, int lane, uint32_t &bad) {
     uint32_t n_valid = 0;
+    float xn = 0.0f, yn = 0.0f;
+    if (hb + lane < he) { xn = x[hb + lane]; yn = y[hb + lane]; }
     for (uint32_t base = hb; base < he; base += 64) {
-        const StageCount n = stage_hits(st, nullptr, x, y, base, he, false, g, lane, bad);
+        const uint32_t i = base + lane;
+        const float xi = xn, yi = yn;
+        if (i + 64 < he) { xn = x[i + 64]; yn = y[i + 64]; }
+        int slot;
+        const StageCount n = stage_values(st, xi, yi, i < he, g, bad, slot);
         n_valid += n.total;
         vote_staged<G, P>(tile, st, n, cl, ln, g.nrho_f);
         wave_sync();
@@ -227,23 +238,27 @@ __device__ uint32_t vote_range(uint32_t *tile, float2 *st, const float *x, const
 // as 0.  The two edge columns of the tile are halo columns; the caller drops their bits.
 constexpr int kPeakRows = 16;
 
-template <int G, bool P>
+// Count of cell (row k, column of group q) or 0 outside the grid's rows.  Row k is the same for
+// every lane.  Interior units (CHECK false) never leave the grid; at the edges the address is
+// clamped into the tile so that the read is unconditional and only its value is dropped.
+template <bool CHECK, int G, bool P>
 __device__ __forceinline__ uint32_t cell_or_zero(const uint32_t *tile, int k, int n_rho,
                                                  const Lane<G, P> &ln, int q) {
-    const bool in = (k >= 0) && (k < n_rho);
-    const uint32_t d = tile[(in ? k : 0) * Lane<G, P>::STRIDE + ln.col[q]];
-    return in ? ln.count(d) : 0u;
+    if (!CHECK) return ln.count(tile[k * Lane<G, P>::STRIDE + ln.col[q]]);
+    const int kk = min(max(k, 0), n_rho);
+    const uint32_t d = tile[kk * Lane<G, P>::STRIDE + ln.col[q]];
+    return (k >= 0 && k < n_rho) ? ln.count(d) : 0u;
 }
 
-template <int G, bool P>
+template <bool CHECK, int G, bool P>
 __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_rho, uint32_t T,
                                           const Lane<G, P> &ln, int lane, uint32_t *mask) {
     const int k0 = unit * kPeakRows;
     uint32_t Mp[G], Mc[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
-        Mp[q] = cell_or_zero<G, P>(tile, k0 - 1, n_rho, ln, q);
-        Mc[q] = cell_or_zero<G, P>(tile, k0, n_rho, ln, q);
+        Mp[q] = cell_or_zero<CHECK, G, P>(tile, k0 - 1, n_rho, ln, q);
+        Mc[q] = cell_or_zero<CHECK, G, P>(tile, k0, n_rho, ln, q);
         mask[q] = 0u;
     }
 #pragma unroll 1
@@ -252,7 +267,7 @@ __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_
 #pragma unroll
         for (int d = 0; d < 4; ++d)
 #pragma unroll
-            for (int q = 0; q < G; ++q) N[q][d] = cell_or_zero<G, P>(tile, k0 + r0 + d + 1, n_rho, ln, q);
+            for (int q = 0; q < G; ++q) N[q][d] = cell_or_zero<CHECK, G, P>(tile, k0 + r0 + d + 1, n_rho, ln, q);
         // rows r0 .. r0+3 are tested; when no lane's count there reaches the threshold none of
         // them can be a peak and only the window moves on
         uint32_t bm = 0;
@@ -284,7 +299,7 @@ __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_
                 const uint32_t before = max(VL, Mp[q]);
                 const uint32_t after = max(VR, N[q][d]);
                 const uint32_t need = max(max(T, before + 1u), after);
-                mask[q] |= (uint32_t)(k < n_rho && Mc[q] >= need) << (r0 + d);
+                mask[q] |= (uint32_t)((!CHECK || k < n_rho) && Mc[q] >= need) << (r0 + d);
             }
 #pragma unroll
             for (int q = 0; q < G; ++q) { Mp[q] = Mc[q]; Mc[q] = N[q][d]; }
@@ -308,17 +323,21 @@ __device__ __forceinline__ void store_peak(hough_peak *out, uint32_t j, uint32_t
     *p = make_uint2((j & 0xffffu) | (k << 16), c);
 }
 
-// Step 4 (listing) and the marks of step 5, shared by all waves.  pmask[wd * TW + c] holds the
-// peak bits of column c, rows 32*wd ...  Every wave computes the per-column peak counts and
-// their prefix over the tile's columns (raster order is column-major), then lists the peaks of
-// its own words at base + (peaks in earlier columns) + (peaks above in the same column).  Each
-// peak sets the mark bit of every cell within rho_window rows of it (atomic OR: neighbouring
-// words belong to other waves).  Returns the tile's peak count.
+// Step 4 (listing) and the retention marks of step 5, shared by all waves.  pmask[wd * TW + c]
+// holds the peak bits of column c, rows 32*wd ...  Every wave computes the per-column peak
+// counts and their prefix over the tile's columns (raster order is column-major), then lists
+// the peaks of its own words at base + (peaks in earlier columns) + (peaks above in the same
+// column).  It also writes the dilated words dil[wd * TW + c]: bit b set iff a peak of column c
+// lies within rho_window rows of row 32*wd + b.  For rho_window < 32 a word follows from the
+// peak words above and below it; wider windows OR the row range of every peak into dil (which
+// the peak phase cleared).  Returns the tile's peak count.
 template <int G, bool P>
-__device__ uint32_t emit_and_mark(uint32_t *tile, const uint32_t *pmask, int nwords, int first_col,
-                                  const GridArgs &g, hough_peak *out, uint32_t cap, uint32_t base,
-                                  const Lane<G, P> &ln, int lane, int wave, int n_waves) {
+__device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask, uint32_t *dil,
+                                    int nwords, int first_col, const GridArgs &g, hough_peak *out,
+                                    uint32_t cap, uint32_t base, const Lane<G, P> &ln, int lane,
+                                    int wave, int n_waves) {
     constexpr int TW = 64 * G, ST = Lane<G, P>::STRIDE;
+    const int W = g.rho_window;
     uint32_t colbase[G];
     uint32_t carry = 0;
 #pragma unroll
@@ -335,6 +354,14 @@ __device__ uint32_t emit_and_mark(uint32_t *tile, const uint32_t *pmask, int nwo
         for (int q = 0; q < G; ++q) {
             const int c = 64 * q + lane;
             uint32_t m = pmask[wd * TW + c];
+            if (W < 32) {
+                const uint32_t up = wd > 0 ? pmask[(wd - 1) * TW + c] : 0u;
+                const uint32_t dn = wd + 1 < nwords ? pmask[(wd + 1) * TW + c] : 0u;
+                uint32_t d = m;
+                for (int sft = 1; sft <= W; ++sft)
+                    d |= (m << sft) | (m >> sft) | (up >> (32 - sft)) | (dn << (32 - sft));
+                dil[wd * TW + c] = d;
+            }
             if (!m) continue;
             uint32_t idx = base + colbase[q];
             for (int w = 0; w < wd; ++w) idx += __popc(pmask[w * TW + c]);
@@ -346,46 +373,54 @@ __device__ uint32_t emit_and_mark(uint32_t *tile, const uint32_t *pmask, int nwo
                 const uint32_t cv = ln.count(tile[k * ST + ln.col[q]]);
                 if (idx < cap) store_peak(out + idx, j, (uint32_t)k, cv);
                 ++idx;
-                const int lo = k - g.rho_window > 0 ? k - g.rho_window : 0;
-                const int hi = k + g.rho_window < g.n_rho - 1 ? k + g.rho_window : g.n_rho - 1;
-                for (int kk = lo; kk <= hi; ++kk)
-                    __hip_atomic_fetch_or(&tile[kk * ST + ln.col[q]], ln.mark, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (W >= 32) {
+                    const int lo = k - W > 0 ? k - W : 0;
+                    const int hi = k + W < g.n_rho - 1 ? k + W : g.n_rho - 1;
+                    for (int w = lo >> 5; w <= (hi >> 5); ++w) {
+                        const int a = max(lo, w * 32) - w * 32, e = min(hi, w * 32 + 31) - w * 32;
+                        const uint32_t rm = (e == 31 ? ~0u : ((1u << (e + 1)) - 1u)) & ~((1u << a) - 1u);
+                        __hip_atomic_fetch_or(&dil[w * TW + c], rm, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
             }
         }
     }
     return carry;
 }
 
-// Step 5 on the current tile: every hit not yet kept looks up its own cell in each of the
-// lane's columns; a marked cell in any column of the tile keeps the hit.
-template <int G, bool P>
-__device__ __forceinline__ uint32_t lookup1(const uint32_t *tile, float u, float v, bool checked,
-                                            const Cols<G> &cl, const Lane<G, P> &ln, float nrho_f) {
+// Step 5 on the current tile: a hit is kept when its own cell in some column of the tile has
+// its dil bit set.  Returns bit 0 set iff kept.
+template <int G>
+__device__ __forceinline__ uint32_t lookup1(const uint32_t *dil, float u, float v, bool checked,
+                                            const Cols<G> &cl, int lane, float nrho_f) {
     uint32_t m = 0;
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         const float w = __builtin_fmaf(v, cl.S[q], cl.B[q]);
         const float t = __builtin_fmaf(u, cl.C[q], w);
-        if (!checked || (t >= 0.0f && t < nrho_f)) m |= tile[(int)t * Lane<G, P>::STRIDE + ln.col[q]];
+        if (!checked || (t >= 0.0f && t < nrho_f)) {
+            const int k = (int)t;
+            m |= dil[(k >> 5) * (64 * G) + 64 * q + lane] >> (k & 31);
+        }
     }
-    return m & ln.mark;
+    return m & 1u;
 }
 
 // Look up the staged hits st[0 .. n.total) (the first n.safe need no range test), four at a
-// time so that their cell reads are in flight together.  Returns the mask of kept stage slots.
-template <int G, bool P>
-__device__ __forceinline__ uint64_t lookup_staged(const uint32_t *tile, const float2 *st, StageCount n,
-                                                  const Cols<G> &cl, const Lane<G, P> &ln, float nrho_f) {
+// time so that their reads are in flight together.  Returns the mask of kept stage slots.
+template <int G>
+__device__ __forceinline__ uint64_t lookup_staged(const uint32_t *dil, const float2 *st, StageCount n,
+                                                  const Cols<G> &cl, int lane, float nrho_f) {
     const float4 *st4 = reinterpret_cast<const float4 *>(st);
     uint64_t kept = 0;
     uint32_t h = 0;
     for (; h + 4 <= n.safe; h += 4) {
         const float4 a = st4[h >> 1], b = st4[(h >> 1) + 1];
-        const uint32_t m0 = lookup1<G, P>(tile, a.x, a.y, false, cl, ln, nrho_f);
-        const uint32_t m1 = lookup1<G, P>(tile, a.z, a.w, false, cl, ln, nrho_f);
-        const uint32_t m2 = lookup1<G, P>(tile, b.x, b.y, false, cl, ln, nrho_f);
-        const uint32_t m3 = lookup1<G, P>(tile, b.z, b.w, false, cl, ln, nrho_f);
+        const uint32_t m0 = lookup1<G>(dil, a.x, a.y, false, cl, lane, nrho_f);
+        const uint32_t m1 = lookup1<G>(dil, a.z, a.w, false, cl, lane, nrho_f);
+        const uint32_t m2 = lookup1<G>(dil, b.x, b.y, false, cl, lane, nrho_f);
+        const uint32_t m3 = lookup1<G>(dil, b.z, b.w, false, cl, lane, nrho_f);
         const uint64_t one = 1ull << h;
         kept |= __ballot(m0 != 0u) ? one : 0ull;
         kept |= __ballot(m1 != 0u) ? one << 1 : 0ull;
@@ -394,108 +429,116 @@ __device__ __forceinline__ uint64_t lookup_staged(const uint32_t *tile, const fl
     }
     for (; h < n.total; ++h) {
         const float2 p = st[h];
-        const uint32_t m = lookup1<G, P>(tile, p.x, p.y, h >= n.safe, cl, ln, nrho_f);
+        const uint32_t m = lookup1<G>(dil, p.x, p.y, h >= n.safe, cl, lane, nrho_f);
         kept |= __ballot(m != 0u) ? (1ull << h) : 0ull;
     }
     return kept;
 }
 
-__device__ __forceinline__ void set_keep(uint32_t *keepbits, uint32_t hit) {
-    __hip_atomic_fetch_or(&keepbits[hit >> 5], 1u << (hit & 31), __ATOMIC_RELAXED,
-                          __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 __device__ __forceinline__ uint64_t low_bits(uint32_t n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
 
+// Keep flags of a wave's hit range [hb, he), in registers: hit hb + 64*c + l is bit c of lane
+// l.  Only the wave that owns a range reads or writes its flags.
+template <int NW>
+struct KeepBits {
+    static constexpr int CHUNKS = ((int)((kMaxBatchHits + NW - 1) / NW) + 63) / 64;
+    static constexpr int WORDS = (CHUNKS + 31) / 32;
+    uint32_t w[WORDS];
+    __device__ __forceinline__ void clear() {
+#pragma unroll
+        for (int i = 0; i < WORDS; ++i) w[i] = 0u;
+    }
+    __device__ __forceinline__ bool get(uint32_t c) const {
+        uint32_t r = 0;
+#pragma unroll
+        for (int i = 0; i < WORDS; ++i) r |= ((c >> 5) == (uint32_t)i) ? w[i] : 0u;
+        return (r >> (c & 31)) & 1u;
+    }
+    __device__ __forceinline__ void set(uint32_t c) {
+#pragma unroll
+        for (int i = 0; i < WORDS; ++i) w[i] |= ((c >> 5) == (uint32_t)i) ? (1u << (c & 31)) : 0u;
+    }
+};
+
 // Hits of a wave's range that are valid and not yet kept, once there are at most 64 of them:
-// lane l holds entry l (u, v, event-local index), lanes [0, n) are live.  Later tiles look up
-// only these instead of mapping the whole range again.
+// lane l holds one entry (u, v, event-local index) while bit l of `live` is set.  Later tiles
+// look up only these instead of mapping the whole range again.
 struct Pending {
     float u, v;
     uint32_t idx;
-    uint32_t n;      // wave-uniform
+    uint64_t live;   // wave-uniform
     bool on;         // wave-uniform
 };
 
-// Collect the valid unkept hits of [hb, he) into the pending list (caller: at most 64 of them),
-// compacting them through the wave's stage.
-__device__ void build_pending(Pending &pd, float2 *st, uint32_t *sidx, const float *x, const float *y,
-                             uint32_t hb, uint32_t he, const uint32_t *keepbits, int lane) {
+// Collect the valid unkept hits of [hb, he) into the pending list (caller: at most 64 of
+// them): their indices are compacted through the wave's stage, then each lane maps its own.
+template <int NW>
+__device__ void build_pending(Pending &pd, float2 *st, const float *x, const float *y,
+                             uint32_t hb, uint32_t he, const KeepBits<NW> &kb, int lane) {
+    uint32_t *st32 = reinterpret_cast<uint32_t *>(st);
     uint32_t n = 0;
-    for (uint32_t base = hb; base < he; base += 64) {
+    uint32_t c = 0;
+    for (uint32_t base = hb; base < he; base += 64, ++c) {
         const uint32_t i = base + lane;
-        const bool cand = (i < he) && !((keepbits[i >> 5] >> (i & 31)) & 1u);
+        const bool cand = (i < he) && !kb.get(c);
         float xi = 0.0f, yi = 0.0f;
         if (cand) { xi = x[i]; yi = y[i]; }
         float u, v;
         const bool ok = conformal(xi, yi, u, v) && cand;
         const uint64_t b = __ballot(ok);
-        if (ok) {
-            const uint32_t pos = n + mbcnt(b);
-            st[pos] = make_float2(u, v);
-            sidx[pos] = i;
-        }
+        if (ok) st32[n + mbcnt(b)] = i;
         n += (uint32_t)__popcll(b);
     }
     wave_sync();
     pd.on = true;
-    pd.n = n;
+    pd.live = low_bits(n);
     if ((uint32_t)lane < n) {
-        const float2 p = st[lane];
-        pd.u = p.x;
-        pd.v = p.y;
-        pd.idx = sidx[lane];
+        pd.idx = st32[lane];
+        (void)conformal(x[pd.idx], y[pd.idx], pd.u, pd.v);
     }
     wave_sync();
 }
 
-// Step 5 for the pending list: stage it, look it up (every lookup takes the literal range
-// test), set the keep bits of the kept entries and compact the others back into the lanes.
-template <int G, bool P>
-__device__ uint32_t retain_pending(Pending &pd, const uint32_t *tile, float2 *st, uint32_t *sidx,
-                                   uint32_t *keepbits, const Cols<G> &cl, const Lane<G, P> &ln,
-                                   const GridArgs &g, int lane) {
-    if (pd.n == 0) return 0u;
-    if ((uint32_t)lane < pd.n) st[lane] = make_float2(pd.u, pd.v);
+// Step 5 for the pending list: stage the live entries, look them up (every lookup takes the
+// literal range test), hand each kept entry's flag to the lane that owns its hit and drop it.
+template <int G, int NW>
+__device__ uint32_t retain_pending(Pending &pd, const uint32_t *dil, float2 *st, KeepBits<NW> &kb,
+                                   uint32_t hb, const Cols<G> &cl, const GridArgs &g, int lane) {
+    if (pd.live == 0ull) return 0u;
+    const bool me = (pd.live >> lane) & 1ull;
+    const uint32_t pos = mbcnt(pd.live);
+    if (me) st[pos] = make_float2(pd.u, pd.v);
     wave_sync();
-    const uint64_t kept = lookup_staged<G, P>(tile, st, StageCount{0u, pd.n}, cl, ln, g.nrho_f);
-    if ((kept >> lane) & 1ull) set_keep(keepbits, pd.idx);
-    const uint64_t surv = low_bits(pd.n) & ~kept;
-    wave_sync();
-    if ((surv >> lane) & 1ull) {
-        const uint32_t pos = mbcnt(surv);
-        st[pos] = make_float2(pd.u, pd.v);
-        sidx[pos] = pd.idx;
+    const uint64_t kept = lookup_staged<G>(dil, st, StageCount{0u, (uint32_t)__popcll(pd.live)}, cl,
+                                           lane, g.nrho_f);
+    const uint64_t kept_lanes = __ballot(me && ((kept >> pos) & 1ull));
+    for (uint64_t km = kept_lanes; km; km &= km - 1ull) {
+        const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)pd.idx, __builtin_ctzll(km)) - hb;
+        if ((uint32_t)lane == (off & 63u)) kb.set(off >> 6);
     }
+    pd.live &= ~kept_lanes;
     wave_sync();
-    pd.n = (uint32_t)__popcll(surv);
-    if ((uint32_t)lane < pd.n) {
-        const float2 p = st[lane];
-        pd.u = p.x;
-        pd.v = p.y;
-        pd.idx = sidx[lane];
-    }
-    wave_sync();
-    return (uint32_t)__popcll(kept);
+    return (uint32_t)__popcll(kept_lanes);
 }
 
 // Step 5 over the whole range [hb, he): every unkept valid hit is mapped again, staged and
-// looked up; the lanes set the keep bits of their stage slots.  Returns the number of hits
-// newly kept; `left` receives how many valid hits remain unkept.
-template <int G, bool P>
-__device__ uint32_t retain_range(const uint32_t *tile, float2 *st, uint32_t *sidx, const float *x,
-                                 const float *y, uint32_t hb, uint32_t he, uint32_t *keepbits,
-                                 const Cols<G> &cl, const Lane<G, P> &ln, const GridArgs &g, int lane,
-                                 uint32_t &left) {
+// looked up; each lane sets the flag of its own hit when its stage slot was kept.  Returns the
+// number of hits newly kept; `left` receives how many valid hits remain unkept.
+template <int G, int NW>
+__device__ uint32_t retain_range(const uint32_t *dil, float2 *st, const float *x,
+                                 const float *y, uint32_t hb, uint32_t he, KeepBits<NW> &kb,
+                                 const Cols<G> &cl, const GridArgs &g, int lane, uint32_t &left) {
     uint32_t unused = 0, newly = 0;
     left = 0;
-    for (uint32_t base = hb; base < he; base += 64) {
+    uint32_t c = 0;
+    for (uint32_t base = hb; base < he; base += 64, ++c) {
         const uint32_t i = base + lane;
-        const bool done = (i < he) && ((keepbits[i >> 5] >> (i & 31)) & 1u);
+        const bool done = (i < he) && kb.get(c);
         if (__ballot((i < he) && !done) == 0ull) continue;      // whole chunk already kept
-        const StageCount n = stage_hits(st, sidx, x, y, base, he, done, g, lane, unused);
-        const uint64_t kept = lookup_staged<G, P>(tile, st, n, cl, ln, g.nrho_f);
-        if ((kept >> lane) & 1ull) set_keep(keepbits, sidx[lane]);
+        int slot;
+        const StageCount n = stage_hits(st, x, y, base, he, done, g, lane, unused, slot);
+        const uint64_t kept = lookup_staged<G>(dil, st, n, cl, lane, g.nrho_f);
+        if (slot >= 0 && ((kept >> slot) & 1ull)) kb.set(c);
         const uint32_t nk = (uint32_t)__popcll(kept);
         newly += nk;
         left += n.total - nk;
@@ -662,10 +705,11 @@ __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__r
 
 // ------------------------------------------------------------------------ fused batch path
 // One workgroup processes one event at a time, taken from a global work counter; the event's
-// theta tiles are processed in order: zero, vote, find peaks, list + mark, retain.  Counters are
-// packed two per dword (an event has at most kMaxBatchHits hits, so a count fits 15 bits and the
-// 16th is the retention mark).  The keep bits of the event's hits live in LDS until the event
-// is done.  Retention is skipped for the rest of the event once every valid hit is kept.
+// theta tiles are processed in order: vote, find peaks, list + dilate, then retain while the
+// tile is cleared for the next one.  Counters are packed two per dword (an event has at most
+// kMaxBatchHits hits, so a count fits 16 bits).  Wave w owns hits [hb, he) of the event for
+// voting and retention, and keeps their keep flags in registers until the event is done.
+// Retention is skipped for the rest of the event once every valid hit is kept.
 // queue[0] is the work counter and queue[1] counts workgroups that have left the loop; the
 // last one to leave (every pop has then happened) puts both back to zero for the next launch,
 // so a launch is a single kernel with no memset.
@@ -676,15 +720,27 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
     extern __shared__ __align__(16) uint32_t lds[];
     uint32_t *tile = lds;                                                  // [(n_rho + 1) * ST]
     float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * ST);   // [NW * 64]
-    uint32_t *sidx = reinterpret_cast<uint32_t *>(stage + NW * 64);        // [NW * 64]
-    uint32_t *pmask = sidx + NW * 64;                                      // [nwords * TW]
-    uint32_t *keepbits = pmask + (size_t)nwords * TW;                      // [kMaxBatchHits / 32 + 1]
+    uint32_t *pmask = reinterpret_cast<uint32_t *>(stage + NW * 64);       // [nwords * TW]
+    uint32_t *dil = pmask + (size_t)nwords * TW;                           // [(nwords + 1) * TW]
     __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const L ln(lane);
+    const int tile_words4 = (g.n_rho + 1) * ST / 4;
+
+    // the tile is all zero at the start of every tile; the dil row past the last word is read
+    // by the out-of-grid columns' dummy row and stays zero
+    for (int i = threadIdx.x; i < tile_words4; i += NT)
+        reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = threadIdx.x; i < TW; i += NT) dil[nwords * TW + i] = 0u;
 
     for (;;) {
-        if (threadIdx.x == 0) s_event = atomicAdd(a.queue, 1u);
+        if (threadIdx.x == 0) {
+            s_event = atomicAdd(a.queue, 1u);
+            s_npeaks = 0u;
+            s_flags = 0u;
+            s_nvalid = 0u;
+            s_nkept = 0u;
+        }
         __syncthreads();
         const uint32_t e = s_event;
         if (e >= a.n_events) {
@@ -714,31 +770,31 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             __syncthreads();
             continue;
         }
-        for (uint32_t i = threadIdx.x; i < (H + 31u) / 32u; i += NT) keepbits[i] = 0u;
-        if (threadIdx.x == 0) { s_npeaks = 0u; s_flags = 0u; s_nvalid = 0u; s_nkept = 0u; }
         const uint32_t hb = (uint32_t)((uint64_t)H * wave / NW);
         const uint32_t he = (uint32_t)((uint64_t)H * (wave + 1) / NW);
         const float *xe = a.x + h0, *ye = a.y + h0;
         hough_peak *pe = a.peaks ? a.peaks + (size_t)e * a.max_peaks : nullptr;
         const uint32_t cap = pe ? a.max_peaks : 0u;
         uint32_t bad = 0;
+        KeepBits<NW> kb;
+        kb.clear();
         Pending pd;
         pd.u = pd.v = 0.0f;
         pd.idx = 0u;
-        pd.n = 0u;
+        pd.live = 0ull;
         pd.on = false;
         for (int t = 0; t < n_tiles; ++t) {
             const int first = t * OUT - 1;      // grid column of lane 0 of group 0
             const Cols<G> cl = load_cols<G>(g, first, lane);
-            for (int i = threadIdx.x; i < (g.n_rho + 1) * ST / 4; i += NT)
-                reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
-            __syncthreads();
             const uint32_t nv = vote_range<G, true>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad);
             if (t == 0 && lane == 0 && nv) atomicAdd(&s_nvalid, nv);
             __syncthreads();
             for (int u = wave; u < 2 * nwords; u += NW) {
                 uint32_t m[G];
-                peak_rows<G, true>(tile, u, g.n_rho, g.threshold, ln, lane, m);
+                if (u >= 1 && (u + 1) * kPeakRows < g.n_rho)
+                    peak_rows<false, G, true>(tile, u, g.n_rho, g.threshold, ln, lane, m);
+                else
+                    peak_rows<true, G, true>(tile, u, g.n_rho, g.threshold, ln, lane, m);
                 uint16_t *pm16 = reinterpret_cast<uint16_t *>(pmask);
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
@@ -747,33 +803,41 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
                     pm16[((u >> 1) * TW + c) * 2 + (u & 1)] = out_col ? (uint16_t)m[q] : (uint16_t)0;
                 }
             }
+            if (g.rho_window >= 32)
+                for (int i = threadIdx.x; i < nwords * TW; i += NT) dil[i] = 0u;
             __syncthreads();
             const uint32_t base = s_npeaks;
-            const uint32_t np = emit_and_mark<G, true>(tile, pmask, nwords, first, g, pe, cap, base,
-                                                       ln, lane, wave, NW);
+            const uint32_t np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, pe, cap, base,
+                                                         ln, lane, wave, NW);
             __syncthreads();
             if (threadIdx.x == 0) s_npeaks = base + np;
+            // the counts are dead: clear the tile for the next one while retention reads dil
+            for (int i = threadIdx.x; i < tile_words4; i += NT)
+                reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
             if (np && s_nkept < s_nvalid) {
                 uint32_t newly;
                 if (pd.on) {
-                    newly = retain_pending<G, true>(pd, tile, stage + wave * 64, sidx + wave * 64,
-                                                    keepbits, cl, ln, g, lane);
+                    newly = retain_pending<G, NW>(pd, dil, stage + wave * 64, kb, hb, cl, g, lane);
                 } else {
                     uint32_t left = 0;
-                    newly = retain_range<G, true>(tile, stage + wave * 64, sidx + wave * 64, xe, ye,
-                                                  hb, he, keepbits, cl, ln, g, lane, left);
+                    newly = retain_range<G, NW>(dil, stage + wave * 64, xe, ye, hb, he, kb, cl, g,
+                                                lane, left);
                     if (left <= 64u)
-                        build_pending(pd, stage + wave * 64, sidx + wave * 64, xe, ye, hb, he,
-                                      keepbits, lane);
+                        build_pending<NW>(pd, stage + wave * 64, xe, ye, hb, he, kb, lane);
                 }
                 if (lane == 0 && newly) atomicAdd(&s_nkept, newly);
             }
             __syncthreads();
         }
         if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
-        uint8_t *ke = a.keep + (a.ids ? a.keep_offsets[e] : h0);
-        for (uint32_t i = threadIdx.x; i < H; i += NT)
-            ke[i] = (uint8_t)((keepbits[i >> 5] >> (i & 31)) & 1u);
+        {
+            uint8_t *ke = a.keep + (a.ids ? a.keep_offsets[e] : h0);
+            uint32_t c = 0;
+            for (uint32_t base = hb; base < he; base += 64, ++c) {
+                const uint32_t i = base + lane;
+                if (i < he) ke[i] = (uint8_t)kb.get(c);
+            }
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             const uint32_t np = s_npeaks;
@@ -812,11 +876,11 @@ size_t peaks_lds_bytes(int n_rho) { return (size_t)(kPeakWaves + 2) * n_rho * 4 
 size_t batch_lds_bytes(int n_rho, int waves, int groups) {
     const size_t tw = 64u * groups, nwords = (size_t)(n_rho + 31) / 32;
     return (size_t)(n_rho + 1) * (tw / 2) * 4 + (size_t)waves * kStageBytes + nwords * tw * 4 +
-           (kMaxBatchHits / 32 + 1) * 4;
+           (nwords + 1) * tw * 4;
 }
 
 int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out) {
-    if (!(waves == 4 || waves == 8 || waves == 16) || !(groups == 1 || groups == 2)) return -1;
+    if (!(waves == 4 || waves == 6 || waves == 8 || waves == 16) || !(groups == 1 || groups == 2)) return -1;
     BatchPlan p{};
     p.waves = waves;
     p.groups = groups;
@@ -889,6 +953,8 @@ hipError_t launch_batch(const GridArgs &g, const BatchPlan &p, const BatchArgs &
     switch (p.waves * 10 + p.groups) {
         case 41: return launch_batch_t<4, 1>(g, p, a, s);
         case 42: return launch_batch_t<4, 2>(g, p, a, s);
+        case 61: return launch_batch_t<6, 1>(g, p, a, s);
+        case 62: return launch_batch_t<6, 2>(g, p, a, s);
         case 81: return launch_batch_t<8, 1>(g, p, a, s);
         case 82: return launch_batch_t<8, 2>(g, p, a, s);
         case 161: return launch_batch_t<16, 1>(g, p, a, s);
@@ -911,6 +977,8 @@ int prepare_batch(const BatchPlan &p, size_t lds_limit) {
     switch (p.waves * 10 + p.groups) {
         case 41: return prepare_t<4, 1>(p.lds_bytes, lds_limit);
         case 42: return prepare_t<4, 2>(p.lds_bytes, lds_limit);
+        case 61: return prepare_t<6, 1>(p.lds_bytes, lds_limit);
+        case 62: return prepare_t<6, 2>(p.lds_bytes, lds_limit);
         case 81: return prepare_t<8, 1>(p.lds_bytes, lds_limit);
         case 82: return prepare_t<8, 2>(p.lds_bytes, lds_limit);
         case 161: return prepare_t<16, 1>(p.lds_bytes, lds_limit);

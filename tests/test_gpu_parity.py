@@ -130,6 +130,25 @@ def test_run_batch_parity(H, orc, name, n_events):
         ctx.close()
 
 
+@pytest.mark.parametrize("name", ["paper-1000ev-360x256", "dense-2000ev-720x512"])
+def test_run_batch_retention_windows(H, orc, name):
+    """Windows below one 32-row word, at the word size and beyond it, on both tile widths."""
+    wl = synth.WORKLOADS[name]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 3, n_events=6)
+    for W in (0, 2, 17, 31, 32, 45, 300):
+        for groups in (1, 2):
+            say(f"batch windows {name} W={W} groups={groups}")
+            ctx = H.Context.for_workload(wl, threshold=30, rho_window=W, max_peaks=20000)
+            try:
+                ctx.set_batch_plan(8, groups, 0)
+            except H.HoughError:
+                ctx.close()
+                continue
+            _batch_check(H, orc, ctx, g, 30, W, ev.x, ev.y, ev.offsets, 20000)
+            ctx.close()
+
+
 def _edge_events():
     """Events that exercise every special case of the path."""
     rng = np.random.default_rng(77)
@@ -302,7 +321,8 @@ def test_every_launch_plan_gives_identical_results(H):
         xt, yt, ot = H.to_device(ev)
         ref = [t.clone() for t in ctx.run_batch(xt, yt, ot)]
         tried = 0
-        for w, gr, gpc in [(4, 1, 0), (4, 2, 0), (8, 1, 0), (8, 2, 0), (16, 1, 0), (16, 2, 0), (8, 1, 1)]:
+        for w, gr, gpc in [(4, 1, 0), (4, 2, 0), (6, 1, 0), (6, 2, 0), (8, 1, 0), (8, 2, 0), (16, 1, 0),
+                           (16, 2, 0), (8, 1, 1), (6, 1, 3)]:
             try:
                 ctx.set_batch_plan(w, gr, gpc)
             except H.HoughError:
