@@ -549,36 +549,54 @@ __device__ uint32_t retain_range(const uint32_t *dil, float2 *st, const float *x
 
 // ------------------------------------------------------------------------ plain path
 // hough_vote: one workgroup per 64-column group, all hits of the event swept through it.
+// Counters are packed two per dword, so the hits go through in chunks of at most 65,535 (a
+// count then fits 16 bits); each chunk's tile is written out (first chunk) or added (later
+// chunks) to acc, each element by the one thread that owns it.
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__restrict__ x,
                                                   const float *__restrict__ y, uint32_t n_hits,
                                                   void *acc, int acc_type) {
+    using L = Lane<1, true>;
+    constexpr uint32_t kChunk = 65535u;
     extern __shared__ __align__(16) uint32_t lds[];
-    uint32_t *tile = lds;
-    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * 64);
+    uint32_t *tile = lds;                                                  // [(n_rho + 1) * 32]
+    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * L::STRIDE);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int first = blockIdx.x * 64;
-    for (int i = threadIdx.x; i < g.n_rho * 16; i += NW * 64)
-        reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
+    const L ln(lane);
     const Cols<1> cl = load_cols<1>(g, first, lane);
-    __syncthreads();
-    const uint32_t hb = (uint32_t)((uint64_t)n_hits * wave / NW);
-    const uint32_t he = (uint32_t)((uint64_t)n_hits * (wave + 1) / NW);
-    uint32_t bad = 0;
-    const Lane<1, false> ln(lane);
-    vote_range<1, false>(tile, stage + wave * 64, x, y, hb, he, cl, ln, g, lane, bad);
-    __syncthreads();
-    // Write-out: lane = column (theta row of acc), wave = a slice of rho.
     const int j = first + lane;
-    if (j >= g.n_theta) return;
     const int kb = (int)((int64_t)g.n_rho * wave / NW), ke = (int)((int64_t)g.n_rho * (wave + 1) / NW);
-    if (acc_type == HOUGH_ACC_U16) {
-        uint16_t *row = static_cast<uint16_t *>(acc) + (size_t)j * g.n_rho;
-        for (int k = kb; k < ke; ++k) row[k] = (uint16_t)tile[k * 64 + lane];
-    } else {
-        uint32_t *row = static_cast<uint32_t *>(acc) + (size_t)j * g.n_rho;
-        for (int k = kb; k < ke; ++k) row[k] = tile[k * 64 + lane];
-    }
+    uint32_t bad = 0;
+    uint32_t c0 = 0;
+    do {
+        const uint32_t c1 = n_hits - c0 > kChunk ? c0 + kChunk : n_hits;
+        for (int i = threadIdx.x; i < (g.n_rho + 1) * L::STRIDE / 4; i += NW * 64)
+            reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
+        __syncthreads();
+        const uint32_t hb = c0 + (uint32_t)((uint64_t)(c1 - c0) * wave / NW);
+        const uint32_t he = c0 + (uint32_t)((uint64_t)(c1 - c0) * (wave + 1) / NW);
+        vote_range<1, true>(tile, stage + wave * 64, x, y, hb, he, cl, ln, g, lane, bad);
+        __syncthreads();
+        // write-out: lane = column (theta row of acc), wave = a slice of rho
+        if (j < g.n_theta) {
+            if (acc_type == HOUGH_ACC_U16) {
+                uint16_t *row = static_cast<uint16_t *>(acc) + (size_t)j * g.n_rho;
+                for (int k = kb; k < ke; ++k) {
+                    const uint32_t v = ln.count(tile[k * L::STRIDE + ln.col[0]]);
+                    row[k] = (uint16_t)(c0 ? row[k] + v : v);
+                }
+            } else {
+                uint32_t *row = static_cast<uint32_t *>(acc) + (size_t)j * g.n_rho;
+                for (int k = kb; k < ke; ++k) {
+                    const uint32_t v = ln.count(tile[k * L::STRIDE + ln.col[0]]);
+                    row[k] = c0 ? row[k] + v : v;
+                }
+            }
+        }
+        __syncthreads();
+        c0 = c1;
+    } while (c0 < n_hits);
 }
 
 // hough_peaks: one workgroup; rows are staged NW at a time (plus one halo row on each side)
@@ -868,7 +886,7 @@ void allow_lds(K kernel) {
 }  // namespace
 
 size_t vote_lds_bytes(int n_rho) {
-    return (size_t)(n_rho + 1) * 64 * 4 + (size_t)kVoteWaves * 64 * sizeof(float2) + 256;
+    return (size_t)(n_rho + 1) * 32 * 4 + (size_t)kVoteWaves * kStageBytes + 256;
 }
 
 size_t peaks_lds_bytes(int n_rho) { return (size_t)(kPeakWaves + 2) * n_rho * 4 + 256; }

@@ -75,6 +75,10 @@ WORKLOADS: dict[str, Workload] = {w.name: w for w in [
     Workload("paper-1000ev-360x256", 1000, (2, 8), (0.05, 1.5), (0.10, 0.10), 360, 256, "i32", 10, salt=2),
     Workload("batch-10000ev-360x256", 10000, (1, 12), (0.05, 1.5), (0.02, 0.25), 360, 256, "i32", 10, salt=3),
     Workload("dense-2000ev-720x512", 2000, (12, 12), (0.05, 1.5), (0.30, 0.30), 720, 512, "i32", 12, salt=4),
+    # the paper's own grid (1000 x 1000 bins, rho in [-0.01, 0.01)) over the very events of the
+    # 1,000-event workload (same generator and salt)
+    Workload("paper-1000ev-1000x1000", 1000, (2, 8), (0.05, 1.5), (0.10, 0.10), 1000, 1000, "i32", 20,
+             rho_min=-0.01, rho_max=0.01, salt=2),
 ]}
 
 

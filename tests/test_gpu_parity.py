@@ -52,7 +52,7 @@ def _plain_event(H, ctx, x, y, cap):
 
 
 SAMPLES = [("plain-16ev-180x128", 16), ("paper-1000ev-360x256", 4), ("batch-10000ev-360x256", 4),
-           ("dense-2000ev-720x512", 2)]
+           ("dense-2000ev-720x512", 2), ("paper-1000ev-1000x1000", 2)]
 
 
 @pytest.mark.parametrize("name,n_events", SAMPLES)
@@ -116,7 +116,8 @@ def _batch_check(H, orc, ctx, g, T, W, x, y, offsets, max_peaks):
 
 
 @pytest.mark.parametrize("name,n_events", [("plain-16ev-180x128", 16), ("paper-1000ev-360x256", 24),
-                                           ("batch-10000ev-360x256", 24), ("dense-2000ev-720x512", 4)])
+                                           ("batch-10000ev-360x256", 24), ("dense-2000ev-720x512", 4),
+                                           ("paper-1000ev-1000x1000", 6)])
 def test_run_batch_parity(H, orc, name, n_events):
     wl = synth.WORKLOADS[name]
     g = orc.Grid.of(wl)
@@ -264,7 +265,8 @@ def test_determinism_and_batch_independence(H):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["paper-1000ev-360x256", "batch-10000ev-360x256", "dense-2000ev-720x512"])
+@pytest.mark.parametrize("name", ["paper-1000ev-360x256", "batch-10000ev-360x256", "dense-2000ev-720x512",
+                                  "paper-1000ev-1000x1000"])
 def test_full_size_sampled(H, orc, name):
     """The whole workload in one launch (as timed by the benchmark); sampled events vs oracle."""
     import torch
@@ -288,6 +290,38 @@ def test_full_size_sampled(H, orc, name):
         assert np.array_equal(keep[a:b], keep_ref[int(sub.offsets[i]):int(sub.offsets[i + 1])])
         m = int(min(n_ref[i], MAX_PEAKS[name]))
         assert np.array_equal(H.decode_peaks(peaks[e].cpu(), m), pk_ref[i, :m].astype(np.int64))
+    ctx.close()
+
+
+def test_largest_grid_parity(H, orc):
+    """The largest n_rho the library accepts, on the plain and the batch path."""
+    import torch
+    big = int(H.load().hough_max_n_rho())
+    assert big >= 1000                     # the paper's 1000-bin rho axis fits
+    wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
+    g = orc.Grid(130, big, wl.rho_min, wl.rho_max)
+    ev = synth.make_events(wl, 1, n_events=3)
+    ctx = H.Context(130, big, wl.rho_min, wl.rho_max, "i32", 12, 1, 20000)
+    say(f"largest grid 130x{big}: plan {ctx.batch_plan}")
+    _batch_check(H, orc, ctx, g, 12, 1, ev.x, ev.y, ev.offsets, 20000)
+    x, y = ev.event(0)
+    acc = ctx.vote(_t(x), _t(y))
+    torch.cuda.synchronize()
+    assert np.array_equal(acc.cpu().numpy().astype(np.int64), orc.vote(g, x, y).astype(np.int64))
+    ctx.close()
+
+
+def test_vote_chunks_beyond_16_bits(H, orc):
+    """An event of more than 65,535 hits: the plain vote adds its 16-bit chunks into acc."""
+    import torch
+    g = orc.Grid(70, 96, -0.005, 0.005)
+    x, y = synth.random_hits(70000, seed=9)
+    ctx = H.Context(70, 96, -0.005, 0.005, "i32", 5, 1, 64)
+    acc = ctx.vote(_t(x), _t(y))
+    torch.cuda.synchronize()
+    ref = orc.vote(g, x, y)
+    assert int(ref.max()) > 0
+    assert np.array_equal(acc.cpu().numpy().astype(np.int64), ref.astype(np.int64))
     ctx.close()
 
 
