@@ -437,50 +437,27 @@ __device__ __forceinline__ uint64_t lookup_staged(const uint32_t *dil, const flo
 
 __device__ __forceinline__ uint64_t low_bits(uint32_t n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
 
-// Keep flags of a wave's hit range [hb, he), in registers: hit hb + 64*c + l is bit c of lane
-// l.  Only the wave that owns a range reads or writes its flags.
-template <int NW>
-struct KeepBits {
-    static constexpr int CHUNKS = ((int)((kMaxBatchHits + NW - 1) / NW) + 63) / 64;
-    static constexpr int WORDS = (CHUNKS + 31) / 32;
-    uint32_t w[WORDS];
-    __device__ __forceinline__ void clear() {
-#pragma unroll
-        for (int i = 0; i < WORDS; ++i) w[i] = 0u;
-    }
-    __device__ __forceinline__ bool get(uint32_t c) const {
-        uint32_t r = 0;
-#pragma unroll
-        for (int i = 0; i < WORDS; ++i) r |= ((c >> 5) == (uint32_t)i) ? w[i] : 0u;
-        return (r >> (c & 31)) & 1u;
-    }
-    __device__ __forceinline__ void set(uint32_t c) {
-#pragma unroll
-        for (int i = 0; i < WORDS; ++i) w[i] |= ((c >> 5) == (uint32_t)i) ? (1u << (c & 31)) : 0u;
-    }
-};
-
 // Hits of a wave's range that are valid and not yet kept, once there are at most 64 of them:
-// lane l holds one entry (u, v, event-local index) while bit l of `live` is set.  Later tiles
+// lane l holds one entry (an event-local hit index) while bit l of `live` is set.  Later tiles
 // look up only these instead of mapping the whole range again.
 struct Pending {
-    float u, v;
     uint32_t idx;
     uint64_t live;   // wave-uniform
     bool on;         // wave-uniform
 };
 
 // Collect the valid unkept hits of [hb, he) into the pending list (caller: at most 64 of
-// them): their indices are compacted through the wave's stage, then each lane maps its own.
-template <int NW>
+// them): their indices are compacted through the wave's stage.
 __device__ void build_pending(Pending &pd, float2 *st, const float *x, const float *y,
-                             uint32_t hb, uint32_t he, const KeepBits<NW> &kb, int lane) {
+                             const uint8_t *ke, uint32_t hb, uint32_t he, int lane) {
+    // runs once per wave and event: keep the compiler from holding its per-lane addresses in
+    // registers across the whole event
+    asm volatile("" : "+v"(lane));
     uint32_t *st32 = reinterpret_cast<uint32_t *>(st);
     uint32_t n = 0;
-    uint32_t c = 0;
-    for (uint32_t base = hb; base < he; base += 64, ++c) {
+    for (uint32_t base = hb; base < he; base += 64) {
         const uint32_t i = base + lane;
-        const bool cand = (i < he) && !kb.get(c);
+        const bool cand = (i < he) && ke[i] == 0u;
         float xi = 0.0f, yi = 0.0f;
         if (cand) { xi = x[i]; yi = y[i]; }
         float u, v;
@@ -492,53 +469,53 @@ __device__ void build_pending(Pending &pd, float2 *st, const float *x, const flo
     wave_sync();
     pd.on = true;
     pd.live = low_bits(n);
-    if ((uint32_t)lane < n) {
-        pd.idx = st32[lane];
-        (void)conformal(x[pd.idx], y[pd.idx], pd.u, pd.v);
-    }
+    if ((uint32_t)lane < n) pd.idx = st32[lane];
     wave_sync();
 }
 
-// Step 5 for the pending list: stage the live entries, look them up (every lookup takes the
-// literal range test), hand each kept entry's flag to the lane that owns its hit and drop it.
-template <int G, int NW>
-__device__ uint32_t retain_pending(Pending &pd, const uint32_t *dil, float2 *st, KeepBits<NW> &kb,
-                                   uint32_t hb, const Cols<G> &cl, const GridArgs &g, int lane) {
+// Step 5 for the pending list: map and stage the live entries, look them up (every lookup
+// takes the literal range test), write the keep byte of each kept entry and drop it.
+template <int G>
+__device__ uint32_t retain_pending(Pending &pd, const uint32_t *dil, float2 *st, const float *x,
+                                   const float *y, uint8_t *ke, const Cols<G> &cl,
+                                   const GridArgs &g, int lane) {
     if (pd.live == 0ull) return 0u;
     const bool me = (pd.live >> lane) & 1ull;
     const uint32_t pos = mbcnt(pd.live);
-    if (me) st[pos] = make_float2(pd.u, pd.v);
+    if (me) {
+        float u, v;
+        (void)conformal(x[pd.idx], y[pd.idx], u, v);
+        st[pos] = make_float2(u, v);
+    }
     wave_sync();
     const uint64_t kept = lookup_staged<G>(dil, st, StageCount{0u, (uint32_t)__popcll(pd.live)}, cl,
                                            lane, g.nrho_f);
-    const uint64_t kept_lanes = __ballot(me && ((kept >> pos) & 1ull));
-    for (uint64_t km = kept_lanes; km; km &= km - 1ull) {
-        const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)pd.idx, __builtin_ctzll(km)) - hb;
-        if ((uint32_t)lane == (off & 63u)) kb.set(off >> 6);
-    }
+    const bool k_me = me && ((kept >> pos) & 1ull);
+    if (k_me) ke[pd.idx] = 1u;
+    const uint64_t kept_lanes = __ballot(k_me);
     pd.live &= ~kept_lanes;
     wave_sync();
     return (uint32_t)__popcll(kept_lanes);
 }
 
 // Step 5 over the whole range [hb, he): every unkept valid hit is mapped again, staged and
-// looked up; each lane sets the flag of its own hit when its stage slot was kept.  Returns the
-// number of hits newly kept; `left` receives how many valid hits remain unkept.
-template <int G, int NW>
+// looked up; each lane writes the keep byte of its own hit when its stage slot was kept (the
+// event's keep bytes were cleared when it started, and only this lane touches them).  Returns
+// the number of hits newly kept; `left` receives how many valid hits remain unkept.
+template <int G>
 __device__ uint32_t retain_range(const uint32_t *dil, float2 *st, const float *x,
-                                 const float *y, uint32_t hb, uint32_t he, KeepBits<NW> &kb,
+                                 const float *y, uint8_t *ke, uint32_t hb, uint32_t he,
                                  const Cols<G> &cl, const GridArgs &g, int lane, uint32_t &left) {
     uint32_t unused = 0, newly = 0;
     left = 0;
-    uint32_t c = 0;
-    for (uint32_t base = hb; base < he; base += 64, ++c) {
+    for (uint32_t base = hb; base < he; base += 64) {
         const uint32_t i = base + lane;
-        const bool done = (i < he) && kb.get(c);
+        const bool done = (i < he) && ke[i] != 0u;
         if (__ballot((i < he) && !done) == 0ull) continue;      // whole chunk already kept
         int slot;
         const StageCount n = stage_hits(st, x, y, base, he, done, g, lane, unused, slot);
         const uint64_t kept = lookup_staged<G>(dil, st, n, cl, lane, g.nrho_f);
-        if (slot >= 0 && ((kept >> slot) & 1ull)) kb.set(c);
+        if (slot >= 0 && ((kept >> slot) & 1ull)) ke[i] = 1u;
         const uint32_t nk = (uint32_t)__popcll(kept);
         newly += nk;
         left += n.total - nk;
@@ -760,7 +737,8 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             s_nkept = 0u;
         }
         __syncthreads();
-        const uint32_t e = s_event;
+        // wave-uniform values live in scalar registers
+        const uint32_t e = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_event);
         if (e >= a.n_events) {
             if (threadIdx.x == 0 && atomicAdd(a.queue + 1, 1u) == gridDim.x - 1u) {
                 __hip_atomic_store(a.queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -770,8 +748,9 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
         }
         // event e of this launch is pool event ids[e] (or e itself); its keep bytes start at
         // keep_offsets[e] (or at its first hit)
-        const uint32_t pe_id = a.ids ? a.ids[e] : e;
-        const uint32_t h0 = a.offsets[pe_id], h1 = a.offsets[pe_id + 1];
+        const uint32_t pe_id = (uint32_t)__builtin_amdgcn_readfirstlane((int)(a.ids ? a.ids[e] : e));
+        const uint32_t h0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.offsets[pe_id]);
+        const uint32_t h1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.offsets[pe_id + 1]);
         if (h1 < h0) {                       // malformed offsets: touch nothing but the counters
             if (threadIdx.x == 0) { a.n_peaks[e] = 0u; a.status[e] = HOUGH_EV_TOO_MANY_HITS; }
             __syncthreads();
@@ -794,10 +773,10 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
         hough_peak *pe = a.peaks ? a.peaks + (size_t)e * a.max_peaks : nullptr;
         const uint32_t cap = pe ? a.max_peaks : 0u;
         uint32_t bad = 0;
-        KeepBits<NW> kb;
-        kb.clear();
+        uint8_t *ke = a.keep + (a.ids ? (uint32_t)__builtin_amdgcn_readfirstlane((int)a.keep_offsets[e]) : h0);
+#pragma unroll 1
+        for (uint32_t i = hb + lane; i < he; i += 64) ke[i] = 0u;
         Pending pd;
-        pd.u = pd.v = 0.0f;
         pd.idx = 0u;
         pd.live = 0ull;
         pd.on = false;
@@ -821,8 +800,10 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
                     pm16[((u >> 1) * TW + c) * 2 + (u & 1)] = out_col ? (uint16_t)m[q] : (uint16_t)0;
                 }
             }
-            if (g.rho_window >= 32)
+            if (g.rho_window >= 32) {
+#pragma unroll 1
                 for (int i = threadIdx.x; i < nwords * TW; i += NT) dil[i] = 0u;
+            }
             __syncthreads();
             const uint32_t base = s_npeaks;
             const uint32_t np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, pe, cap, base,
@@ -830,32 +811,24 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             __syncthreads();
             if (threadIdx.x == 0) s_npeaks = base + np;
             // the counts are dead: clear the tile for the next one while retention reads dil
+#pragma unroll 1
             for (int i = threadIdx.x; i < tile_words4; i += NT)
                 reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
             if (np && s_nkept < s_nvalid) {
                 uint32_t newly;
                 if (pd.on) {
-                    newly = retain_pending<G, NW>(pd, dil, stage + wave * 64, kb, hb, cl, g, lane);
+                    newly = retain_pending<G>(pd, dil, stage + wave * 64, xe, ye, ke, cl, g, lane);
                 } else {
                     uint32_t left = 0;
-                    newly = retain_range<G, NW>(dil, stage + wave * 64, xe, ye, hb, he, kb, cl, g,
-                                                lane, left);
-                    if (left <= 64u)
-                        build_pending<NW>(pd, stage + wave * 64, xe, ye, hb, he, kb, lane);
+                    newly = retain_range<G>(dil, stage + wave * 64, xe, ye, ke, hb, he, cl, g, lane,
+                                            left);
+                    if (left <= 64u) build_pending(pd, stage + wave * 64, xe, ye, ke, hb, he, lane);
                 }
                 if (lane == 0 && newly) atomicAdd(&s_nkept, newly);
             }
             __syncthreads();
         }
         if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
-        {
-            uint8_t *ke = a.keep + (a.ids ? a.keep_offsets[e] : h0);
-            uint32_t c = 0;
-            for (uint32_t base = hb; base < he; base += 64, ++c) {
-                const uint32_t i = base + lane;
-                if (i < he) ke[i] = (uint8_t)kb.get(c);
-            }
-        }
         __syncthreads();
         if (threadIdx.x == 0) {
             const uint32_t np = s_npeaks;
