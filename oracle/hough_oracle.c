@@ -37,6 +37,8 @@
  *     in raster order.
  *   - keep_i iff hit i is valid and some peak (jp,kp) has k_i(jp) in range with
  *     |k_i(jp) - kp| <= rho_window, k_i(jp) computed with the bin rule above.
+ *   - the paper's own peak finder (relative threshold, then iterative extraction with
+ *     neighbourhood suppression) is oracle_peaks_iterative; its readings are stated there.
  */
 #include <float.h>
 #include <math.h>
@@ -143,6 +145,52 @@ long oracle_peaks(const int32_t *acc, int n_theta, int n_rho, int threshold,
                 if (n < cap) { pj[n] = j; pk[n] = k; pc[n] = acc[(size_t)j * n_rho + k]; }
                 ++n;
             }
+    return n;
+}
+
+/*
+ * Peak finding as Sec. II describes it for multi-track events: a threshold relative to the
+ * accumulator's global maximum, then iterative extraction.  The threshold is
+ *     thr = max(t_abs, ceil(max_count * frac_num / frac_den))
+ * (t_abs >= 1 keeps an empty accumulator from yielding peaks).  Each step takes the largest
+ * count among the cells still available and at or above thr, the first in raster order among
+ * equal counts; it becomes a peak, and every cell within r_theta columns and r_rho rows of it
+ * (inside the grid, no wrap of theta) stops being available.  The steps repeat until no
+ * available cell reaches thr.  Peaks are listed in the order they were taken; at most cap are
+ * written and the true number is returned (-1 on allocation failure).
+ */
+long oracle_peaks_iterative(const int32_t *acc, int n_theta, int n_rho, int t_abs,
+                            int frac_num, int frac_den, int r_theta, int r_rho,
+                            int32_t *pj, int32_t *pk, int32_t *pc, long cap)
+{
+    const size_t cells = (size_t)n_theta * (size_t)n_rho;
+    int32_t max_count = 0;
+    for (size_t c = 0; c < cells; ++c)
+        if (acc[c] > max_count) max_count = acc[c];
+    const int64_t rel = ((int64_t)max_count * frac_num + frac_den - 1) / frac_den;
+    const int64_t thr = rel > t_abs ? rel : t_abs;
+    uint8_t *gone = (uint8_t *)calloc(cells ? cells : 1, 1);
+    if (!gone) return -1;
+    long n = 0;
+    for (;;) {
+        long best = -1;
+        int32_t best_count = 0;
+        for (size_t c = 0; c < cells; ++c)
+            if (!gone[c] && acc[c] >= thr && (best < 0 || acc[c] > best_count)) {
+                best = (long)c;
+                best_count = acc[c];
+            }
+        if (best < 0) break;
+        const int j = (int)(best / n_rho), k = (int)(best % n_rho);
+        if (n < cap) { pj[n] = j; pk[n] = k; pc[n] = best_count; }
+        ++n;
+        for (int jj = j - r_theta; jj <= j + r_theta; ++jj) {
+            if (jj < 0 || jj >= n_theta) continue;
+            for (int kk = k - r_rho; kk <= k + r_rho; ++kk)
+                if (kk >= 0 && kk < n_rho) gone[(size_t)jj * n_rho + kk] = 1;
+        }
+    }
+    free(gone);
     return n;
 }
 

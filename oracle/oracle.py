@@ -67,6 +67,9 @@ def lib():
         L.oracle_is_peak.restype = c_int
         L.oracle_peaks.argtypes = [_i32p, c_int, c_int, c_int, _i32p, _i32p, _i32p, c_long]
         L.oracle_peaks.restype = c_long
+        L.oracle_peaks_iterative.argtypes = [_i32p, c_int, c_int, c_int, c_int, c_int, c_int, c_int,
+                                             _i32p, _i32p, _i32p, c_long]
+        L.oracle_peaks_iterative.restype = c_long
         L.oracle_retain.argtypes = [c_int, _f32p, _f32p, c_float, c_int, _f32p, _f32p, c_long,
                                     _i32p, _i32p, c_long, _u8p]
         L.oracle_retain.restype = None
@@ -136,6 +139,24 @@ def peaks(acc: np.ndarray, threshold: int, cap: int | None = None):
     cap = nt * nr if cap is None else int(cap)
     pj = np.zeros(max(cap, 1), np.int32); pk = np.zeros_like(pj); pc = np.zeros_like(pj)
     n = int(lib().oracle_peaks(acc, nt, nr, int(threshold), pj, pk, pc, cap))
+    m = min(n, cap)
+    return pj[:m].copy(), pk[:m].copy(), pc[:m].copy(), n
+
+
+def peaks_iterative(acc: np.ndarray, t_abs: int, frac: tuple[int, int], r_theta: int, r_rho: int,
+                    cap: int | None = None):
+    """The paper's peak finder (Sec. II): threshold max(t_abs, ceil(max * frac)), then the
+    largest remaining cell (raster-first among equals) is taken and its (2 r_theta + 1) x
+    (2 r_rho + 1) neighbourhood suppressed, repeatedly.  (j, k, count) in extraction order and
+    the true count."""
+    acc = np.ascontiguousarray(acc, dtype=np.int32)
+    nt, nr = acc.shape
+    cap = nt * nr if cap is None else int(cap)
+    pj = np.zeros(max(cap, 1), np.int32); pk = np.zeros_like(pj); pc = np.zeros_like(pj)
+    n = int(lib().oracle_peaks_iterative(acc, nt, nr, int(t_abs), int(frac[0]), int(frac[1]),
+                                         int(r_theta), int(r_rho), pj, pk, pc, cap))
+    if n < 0:
+        raise MemoryError("oracle_peaks_iterative")
     m = min(n, cap)
     return pj[:m].copy(), pk[:m].copy(), pc[:m].copy(), n
 

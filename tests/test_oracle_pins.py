@@ -441,3 +441,104 @@ def test_empty_event(orc):
     pk, n, keep = orc.run_batch(g, np.zeros(0, np.float32), np.zeros(0, np.float32),
                                 np.zeros(3, np.uint32), threshold=1, rho_window=1, cap=4)
     assert n.tolist() == [0, 0] and keep.size == 0
+
+
+# ------------------------------------------------- the paper's iterative peak finder (Sec. II)
+def _greedy_by_sorting(acc, t_abs, frac, rt, rr):
+    """Independent formulation: every cell at or above the threshold, sorted by (count
+    descending, raster index ascending), is taken unless an earlier taken cell lies within the
+    window.  Taking the largest remaining cell and suppressing its window, step by step, makes
+    exactly these choices, because suppression depends only on the cells already taken."""
+    nt, nr = acc.shape
+    mx = int(acc.max()) if acc.size else 0
+    thr = max(t_abs, -(-mx * frac[0] // frac[1]))
+    cells = [(-int(acc[j, k]), j * nr + k) for j in range(nt) for k in range(nr) if acc[j, k] >= thr]
+    taken = []
+    for negc, idx in sorted(cells):
+        j, k = divmod(idx, nr)
+        if all(abs(j - a) > rt or abs(k - b) > rr for a, b, _ in taken):
+            taken.append((j, k, -negc))
+    return taken
+
+
+def test_iterative_peaks_equal_sorted_greedy_on_random_grids(orc):
+    rng = np.random.default_rng(31)
+    for trial in range(60):
+        nt, nr = int(rng.integers(1, 14)), int(rng.integers(1, 14))
+        acc = rng.integers(0, int(rng.integers(1, 12)), size=(nt, nr)).astype(np.int32)
+        t_abs = int(rng.integers(1, 4))
+        frac = (int(rng.integers(0, 4)), int(rng.integers(1, 5)))
+        rt, rr = int(rng.integers(0, 3)), int(rng.integers(0, 3))
+        pj, pk, pc, n = orc.peaks_iterative(acc, t_abs, frac, rt, rr)
+        want = _greedy_by_sorting(acc, t_abs, frac, rt, rr)
+        assert n == len(want), trial
+        assert list(zip(pj.tolist(), pk.tolist(), pc.tolist())) == want, trial
+
+
+def test_iterative_peaks_hand_built(orc):
+    a = np.zeros((8, 10), np.int32)
+    a[2, 3], a[2, 5], a[6, 9], a[0, 0] = 9, 8, 7, 4
+    # window 1x1 around each taken cell: (2,5) is two rows away from (2,3) and survives
+    pj, pk, pc, n = orc.peaks_iterative(a, 1, (0, 1), 1, 1)
+    assert list(zip(pj, pk, pc)) == [(2, 3, 9), (2, 5, 8), (6, 9, 7), (0, 0, 4)]
+    # a wider rho window suppresses it; extraction order is by count
+    pj, pk, pc, n = orc.peaks_iterative(a, 1, (0, 1), 1, 2)
+    assert list(zip(pj, pk)) == [(2, 3), (6, 9), (0, 0)]
+    # relative threshold: ceil(9 * 7 / 9) = 7 keeps counts >= 7 only; ceil(9 * 8 / 9) = 8
+    assert orc.peaks_iterative(a, 1, (7, 9), 0, 0)[3] == 3
+    assert orc.peaks_iterative(a, 1, (8, 9), 0, 0)[3] == 2
+    assert orc.peaks_iterative(a, 1, (2, 3), 0, 0)[3] == 3          # ceil(6) = 6: 9, 8, 7
+    # the absolute floor applies when it is the larger
+    assert orc.peaks_iterative(a, 8, (0, 1), 0, 0)[3] == 2
+    # an empty accumulator has no peaks whatever the fraction
+    assert orc.peaks_iterative(np.zeros((5, 5), np.int32), 1, (0, 1), 1, 1)[3] == 0
+    # cap limits the list, never the count
+    pj, pk, pc, n = orc.peaks_iterative(a, 1, (0, 1), 0, 0, cap=2)
+    assert n == 4 and len(pj) == 2
+
+
+def test_iterative_peaks_ties_take_the_first_cell_in_raster_order(orc):
+    a = np.zeros((5, 6), np.int32)
+    a[3, 1] = a[1, 4] = a[1, 5] = 6
+    pj, pk, pc, n = orc.peaks_iterative(a, 1, (1, 2), 1, 1)
+    assert list(zip(pj, pk)) == [(1, 4), (3, 1)]                   # (1,5) is inside (1,4)'s window
+
+
+def test_iterative_peaks_no_theta_wrap_and_clipped_windows(orc):
+    a = np.zeros((6, 4), np.int32)
+    a[0, 0], a[5, 0], a[0, 3] = 5, 5, 5
+    pj, pk, pc, n = orc.peaks_iterative(a, 1, (0, 1), 2, 2)
+    assert n == 3                                                  # no cell is within 2 of another
+    pj, pk, pc, n = orc.peaks_iterative(a, 1, (0, 1), 2, 3)
+    assert list(zip(pj, pk)) == [(0, 0), (5, 0)]                   # rows 0..3 of columns 0..2 go
+
+
+def test_iterative_first_peak_is_a_local_maximum(orc):
+    """The first extracted cell is the first global maximum in raster order, so it also
+    passes the 3x3 test at any threshold it reaches."""
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 0, n_events=4)
+    for e in range(ev.n_events):
+        acc = orc.vote(g, *ev.event(e))
+        pj, pk, pc, n = orc.peaks_iterative(acc, 1, (1, 2), 3, 3)
+        assert n >= 1 and pc[0] == acc.max()
+        assert orc.is_peak(acc, int(pc[0]), int(pj[0]), int(pk[0]))
+        flat = int(np.argmax(acc))                                 # numpy: first maximum in raster order
+        assert (int(pj[0]), int(pk[0])) == divmod(flat, acc.shape[1])
+        assert np.all(np.diff(pc) <= 0)                            # extraction order is by count
+
+
+def test_iterative_single_track_is_the_only_peak(orc):
+    """A noiseless circle through a cell centre: one peak at that cell once the relative
+    threshold is above the level of the sinusoids' chance crossings."""
+    wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
+    g = orc.Grid.of(wl)
+    rng = np.random.default_rng(13)
+    for _ in range(4):
+        j = int(rng.integers(3, g.n_theta - 3))
+        k = int(rng.integers(g.n_rho // 4 + 10, g.n_rho // 2 - 10))
+        x, y = _track_for_cell(g, j, k)
+        acc = orc.vote(g, x, y)
+        pj, pk, pc, n = orc.peaks_iterative(acc, 2, (1, 2), 5, 5)
+        assert n == 1 and (pj[0], pk[0], pc[0]) == (j, k, x.size)
