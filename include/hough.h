@@ -62,6 +62,9 @@ extern "C" {
 #define HOUGH_EV_INVALID_HITS    2u  /* the event contains invalid hits (they were ignored)     */
 #define HOUGH_EV_TOO_MANY_HITS   4u  /* more hits than hough_max_batch_hits(): event skipped,
                                         its n_peaks and keep are written as zero               */
+#define HOUGH_EV_TOO_MANY_CANDIDATES 8u  /* hough_peaks_iterative: more cells reach the
+                                        threshold than hough_max_iterative_candidates(); no
+                                        peak was listed and n_peaks is zero                    */
 
 /* The (theta, rho) grid and the peak / retention parameters (Sec. II). */
 typedef struct hough_params {
@@ -110,6 +113,23 @@ int hough_vote(hough_ctx *ctx, const float *x, const float *y, uint32_t n_hits,
  * receives the true count, which may exceed cap.  cap == 0 is valid (count only). */
 int hough_peaks(hough_ctx *ctx, const void *acc, hough_peak *peaks, uint32_t cap,
                 uint32_t *n_peaks, void *stream);
+
+/* Step 4 for one event with the peak finder the paper describes for multi-track events
+ * (Sec. II): a threshold relative to the accumulator's global maximum,
+ *     thr = max(threshold of the context, ceil(max * frac_num / frac_den)),
+ * then iterative extraction: the largest remaining cell at or above thr (the first in raster
+ * order among equal counts) becomes a peak and every cell within r_theta theta bins and r_rho
+ * rho bins of it (clipped at the grid edges, theta does not wrap) is suppressed; repeat until
+ * no cell reaches thr.  acc as written by hough_vote.  The first min(count, cap) peaks, in
+ * extraction order, go to peaks; *n_peaks (device) receives the count; *status (device)
+ * receives 0, or HOUGH_EV_TOO_MANY_CANDIDATES when more than hough_max_iterative_candidates()
+ * cells reach thr (then *n_peaks is 0).  HOUGH_EINVAL for frac_den == 0 or a negative radius. */
+int hough_peaks_iterative(hough_ctx *ctx, const void *acc, uint32_t frac_num, uint32_t frac_den,
+                          int32_t r_theta, int32_t r_rho, hough_peak *peaks, uint32_t cap,
+                          uint32_t *n_peaks, uint32_t *status, void *stream);
+
+/* Largest number of cells at or above the threshold hough_peaks_iterative handles. */
+uint32_t hough_max_iterative_candidates(void);
 
 /* Step 5 for one event (Sec. I, Sec. II): keep[i] = 1 iff hit i is within rho_window rho bins
  * of one of the peaks peaks[0 .. min(*n_peaks, cap)-1] (n_peaks is a device pointer, as

@@ -39,6 +39,20 @@ bool grid_fits(int n_rho, size_t limit) {
     return hough::plan_batch(1, n_rho, 4, 1, limit, &p) == 0;
 }
 
+// Bound on u^2 + v^2 under which a hit's bin t = fma(u, C_j, fma(v, S_j, B)) lies strictly
+// inside (0, n_rho) for every column: |t - B| is at most A * sqrt(u^2 + v^2) plus the rounding
+// of C_j, S_j and the two fmas (a few 2^-24 of n_rho), well inside the margin kept here; the
+// float sum u^2 + v^2 itself is within 2^-22 of the exact one, inside the 1e-6 shrink.
+float safe_radius2(double A, double B, int n_rho) {
+    const double margin = 1e-5 * n_rho + 0.01;
+    const double room = (B < n_rho - B ? B : n_rho - B) - margin;
+    if (!(room > 0.0)) return 0.0f;
+    const double r = room / (fabs(A) * 1.0002);
+    float f = (float)(r * r * (1.0 - 1e-6));
+    if ((double)f > r * r * (1.0 - 1e-6)) f = nextafterf(f, 0.0f);
+    return f;
+}
+
 // Default launch shape of the fused kernel: the candidate with the most resident waves per CU
 // (from the occupancy API, which accounts for LDS, VGPRs and SGPRs); ties go to the earlier
 // candidate.  8 waves split the 16-row peak units and the 32-row words of a 256-row tile evenly
@@ -148,8 +162,7 @@ int hough_config(const hough_params *p, hough_ctx **out) {
     g.n_rho = p->n_rho;
     g.Bf = (float)B;
     g.nrho_f = (float)p->n_rho;
-    g.A_f = (float)fabs(A);
-    g.safe_margin = 1e-5f * (float)p->n_rho + 0.01f;
+    g.safe_r2 = safe_radius2(A, B, p->n_rho);
     g.threshold = (uint32_t)p->threshold;
     g.rho_window = p->rho_window < p->n_rho ? p->rho_window : p->n_rho;
 
@@ -218,6 +231,21 @@ int hough_peaks(hough_ctx *c, const void *acc, hough_peak *peaks, uint32_t cap, 
                                              (hipStream_t)stream);
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
 }
+
+int hough_peaks_iterative(hough_ctx *c, const void *acc, uint32_t frac_num, uint32_t frac_den,
+                          int32_t r_theta, int32_t r_rho, hough_peak *peaks, uint32_t cap,
+                          uint32_t *n_peaks, uint32_t *status, void *stream) {
+    if (!c || !acc || !n_peaks || !status || (cap && !peaks)) return HOUGH_EINVAL;
+    if (frac_den == 0 || r_theta < 0 || r_rho < 0) return HOUGH_EINVAL;
+    if (((uintptr_t)peaks & 7u) != 0) return HOUGH_EINVAL;
+    if (hough::peaks_iterative_lds_bytes() > c->lds_limit) return HOUGH_EDEVICE;
+    const hipError_t e = hough::launch_peaks_iterative(c->g, acc, c->p.acc_type, frac_num, frac_den,
+                                                       r_theta, r_rho, peaks, cap, n_peaks, status,
+                                                       (hipStream_t)stream);
+    return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
+}
+
+uint32_t hough_max_iterative_candidates(void) { return 16384u; }
 
 int hough_retain(hough_ctx *c, const float *x, const float *y, uint32_t n_hits,
                  const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap, uint8_t *keep,

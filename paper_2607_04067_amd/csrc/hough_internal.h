@@ -23,8 +23,7 @@ struct GridArgs {
     int32_t n_rho;
     float Bf;            // (float)(-rho_min * A)
     float nrho_f;        // (float)n_rho
-    float A_f;           // (float)A, for the per-hit "all votes in range" test
-    float safe_margin;   // absolute slack of that test, in bins
+    float safe_r2;       // u^2 + v^2 below this: every vote of the hit is in range
     uint32_t threshold;
     int32_t rho_window;
 };
@@ -69,6 +68,10 @@ hipError_t launch_batch(const GridArgs &g, const BatchPlan &p, const BatchArgs &
 // LDS needs and plans (hough_kernels.hip).
 size_t vote_lds_bytes(int n_rho);
 size_t peaks_lds_bytes(int n_rho);
+size_t peaks_iterative_lds_bytes();
+hipError_t launch_peaks_iterative(const GridArgs &g, const void *acc, int acc_type, uint32_t frac_num,
+                                  uint32_t frac_den, int r_theta, int r_rho, hough_peak *peaks,
+                                  uint32_t cap, uint32_t *n_peaks, uint32_t *status, hipStream_t s);
 size_t batch_lds_bytes(int n_rho, int waves, int groups);
 int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out);
 int prepare_batch(const BatchPlan &p, size_t lds_limit);

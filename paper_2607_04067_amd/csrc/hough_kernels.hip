@@ -36,12 +36,11 @@ __device__ __forceinline__ bool conformal(float x, float y, float &u, float &v) 
     return ok;
 }
 
-// True when every column's t lies strictly inside (0, n_rho): |t - B| <= sqrt(u^2+v^2)*A plus
-// rounding (a few 2^-24 relative), covered by the 1e-4 relative and safe_margin absolute slack.
+// True when every column's t lies strictly inside (0, n_rho).  |rho| <= sqrt(u^2 + v^2) for
+// every theta, so u^2 + v^2 below safe_r2 (set on the host with slack for the rounding of this
+// sum and of t) keeps every vote of the hit in range.
 __device__ __forceinline__ bool all_in_range(float u, float v, const GridArgs &g) {
-    const float r = __builtin_sqrtf(__builtin_fmaf(u, u, v * v));
-    const float m = r * g.A_f * 1.0001f + g.safe_margin;
-    return (g.Bf - m > 0.0f) && (g.Bf + m < g.nrho_f);
+    return __builtin_fmaf(u, u, v * v) < g.safe_r2;
 }
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
@@ -641,6 +640,180 @@ __global__ __launch_bounds__(NW * 64) void k_peaks(GridArgs g, const T *__restri
     if (threadIdx.x == 0) *n_peaks = s_total;
 }
 
+// hough_peaks_iterative: the paper's peak finder (relative threshold, then iterative
+// extraction with neighbourhood suppression) for one event, in one workgroup.  The cells at or
+// above the threshold are gathered into LDS as 64-bit keys (count << 32 | ~raster index), sorted
+// descending (larger count first, then earlier in raster order), and wave 0 takes each key that
+// no earlier taken cell suppresses: the choices of the step-by-step extraction, since
+// suppression depends only on the cells already taken.  Wave 0 works 64 keys at a time: a key
+// dies if an earlier taken cell covers it; the first live key of the group is taken and kills
+// the later ones it covers, until none is live.  Taken cells are written back over the keys
+// already consumed.  More than kIterCandidates cells at or above the threshold: status gets
+// HOUGH_EV_TOO_MANY_CANDIDATES and no peak is listed.
+constexpr uint32_t kIterCandidates = 16384;
+constexpr int kIterWaves = 16;
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, const T *__restrict__ acc,
+                                                                uint32_t frac_num, uint32_t frac_den,
+                                                                int r_theta, int r_rho, hough_peak *out,
+                                                                uint32_t cap, uint32_t *n_peaks,
+                                                                uint32_t *status) {
+    extern __shared__ __align__(16) uint64_t keys[];            // [kIterCandidates]
+    __shared__ uint32_t s_red[kIterWaves];
+    __shared__ uint32_t s_nc, s_nk;
+    constexpr int NT = kIterWaves * 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nr = (uint32_t)g.n_rho;
+    const uint32_t cells = (uint32_t)g.n_theta * nr;
+    const uint32_t floor_t = g.threshold;
+    if (tid == 0) { s_nc = 0u; s_nk = 0u; }
+    __syncthreads();
+    // pass 1: the global maximum, and every cell at or above the absolute floor while they fit
+    // (eight loads in flight per lane)
+    constexpr int U = 8;
+    uint32_t m = 0;
+    for (uint32_t base = (uint32_t)wave * 64u; base < cells; base += U * NT) {
+        uint32_t v[U];
+#pragma unroll
+        for (int r = 0; r < U; ++r) {
+            const uint32_t c = base + (uint32_t)r * NT + lane;
+            v[r] = c < cells ? (uint32_t)acc[c] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < U; ++r) {
+            const uint32_t c = base + (uint32_t)r * NT + lane;
+            m = max(m, v[r]);
+            const bool p = c < cells && v[r] >= floor_t;
+            const uint64_t b = __ballot(p);
+            if (b) {
+                uint32_t off = 0;
+                if (lane == 0) off = atomicAdd(&s_nc, (uint32_t)__popcll(b));
+                off = (uint32_t)__shfl((int)off, 0, 64);
+                const uint32_t pos = off + mbcnt(b);
+                if (p && pos < kIterCandidates) keys[pos] = ((uint64_t)v[r] << 32) | (uint64_t)(~c);
+            }
+        }
+    }
+    m = wave_max(m);
+    if (lane == 0) s_red[wave] = m;
+    __syncthreads();
+    uint32_t mx = 0;
+    for (int w = 0; w < kIterWaves; ++w) mx = max(mx, s_red[w]);
+    const uint64_t rel = ((uint64_t)mx * frac_num + frac_den - 1u) / frac_den;
+    const uint32_t thr = (uint32_t)min<uint64_t>(max<uint64_t>(rel, floor_t), 0xffffffffull);
+    const uint32_t n1 = s_nc;
+    __syncthreads();
+    // keep the keys that reach the relative threshold; if pass 1 overflowed, gather them again
+    if (n1 <= kIterCandidates) {
+        if (thr > floor_t) {
+            uint64_t mine[kIterCandidates / NT];
+#pragma unroll
+            for (int r = 0; r < (int)(kIterCandidates / NT); ++r) {
+                const uint32_t i = (uint32_t)tid + (uint32_t)r * NT;
+                mine[r] = i < n1 ? keys[i] : 0ull;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < (int)(kIterCandidates / NT); ++r) {
+                const bool p = (uint32_t)(mine[r] >> 32) >= thr && mine[r] != 0ull;
+                const uint64_t b = __ballot(p);
+                if (b) {
+                    uint32_t off = 0;
+                    if (lane == 0) off = atomicAdd(&s_nk, (uint32_t)__popcll(b));
+                    off = (uint32_t)__shfl((int)off, 0, 64);
+                    if (p) keys[off + mbcnt(b)] = mine[r];
+                }
+            }
+        } else if (tid == 0) {
+            s_nk = n1;
+        }
+    } else {
+        for (uint32_t base = (uint32_t)wave * 64u; base < cells; base += U * NT) {
+            uint32_t v[U];
+#pragma unroll
+            for (int r = 0; r < U; ++r) {
+                const uint32_t c = base + (uint32_t)r * NT + lane;
+                v[r] = c < cells ? (uint32_t)acc[c] : 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < U; ++r) {
+                const uint32_t c = base + (uint32_t)r * NT + lane;
+                const bool p = c < cells && v[r] >= thr;
+                const uint64_t b = __ballot(p);
+                if (b) {
+                    uint32_t off = 0;
+                    if (lane == 0) off = atomicAdd(&s_nk, (uint32_t)__popcll(b));
+                    off = (uint32_t)__shfl((int)off, 0, 64);
+                    const uint32_t pos = off + mbcnt(b);
+                    if (p && pos < kIterCandidates) keys[pos] = ((uint64_t)v[r] << 32) | (uint64_t)(~c);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t nc = s_nk;
+    if (nc > kIterCandidates) {
+        if (tid == 0) { *n_peaks = 0u; *status = HOUGH_EV_TOO_MANY_CANDIDATES; }
+        return;
+    }
+    // bitonic sort, descending, over the next power of two
+    uint32_t P = 1;
+    while (P < nc) P <<= 1;
+    for (uint32_t i = nc + tid; i < P; i += NT) keys[i] = 0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = tid; i < P; i += NT) {
+                const uint32_t ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t a = keys[i], b = keys[ixj];
+                    const bool desc = (i & k) == 0u;
+                    if (desc ? (a < b) : (a > b)) { keys[i] = b; keys[ixj] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (wave != 0) return;
+    // greedy extraction (wave 0): taken cells are stored as count << 32 | j << 16 | k
+    uint32_t taken = 0;
+    for (uint32_t base = 0; base < nc; base += 64) {
+        const uint32_t i = base + lane;
+        bool live = i < nc;
+        const uint64_t key = live ? keys[i] : 0ull;
+        const uint32_t c = ~(uint32_t)key, v = (uint32_t)(key >> 32);
+        const int j = live ? (int)(c / nr) : 0, k = live ? (int)(c - (uint32_t)j * nr) : 0;
+        wave_sync();
+        for (uint32_t a = 0; a < taken; ++a) {
+            const uint64_t t = keys[a];
+            const int ja = (int)((t >> 16) & 0xffffu), ka = (int)(t & 0xffffu);
+            live = live && !(abs(j - ja) <= r_theta && abs(k - ka) <= r_rho);
+        }
+        uint64_t b = __ballot(live);
+        while (b) {
+            const int f = __builtin_ctzll(b);
+            const int jf = __builtin_amdgcn_readlane(j, f), kf = __builtin_amdgcn_readlane(k, f);
+            const uint32_t vf = (uint32_t)__builtin_amdgcn_readlane((int)v, f);
+            if (lane == 0) {
+                keys[taken] = ((uint64_t)vf << 32) | ((uint64_t)jf << 16) | (uint64_t)kf;
+                if (taken < cap) store_peak(out + taken, (uint32_t)jf, (uint32_t)kf, vf);
+            }
+            ++taken;
+            live = live && lane != f && !(abs(j - jf) <= r_theta && abs(k - kf) <= r_rho);
+            b = __ballot(live);
+        }
+        wave_sync();
+    }
+    if (lane == 0) { *n_peaks = taken; *status = 0u; }
+}
+
 // hough_retain: one thread per hit.  Peak rows are processed in blocks that fit LDS: for
 // each block a dilated bitmap (bit k of row j set iff a peak (j, k') has |k - k'| <= W) is
 // built from the peak list, then every unkept hit looks up its own bin in each peak row.
@@ -912,6 +1085,28 @@ hipError_t launch_peaks(const GridArgs &g, const void *acc, int acc_type, hough_
     }
     return hipGetLastError();
 }
+
+hipError_t launch_peaks_iterative(const GridArgs &g, const void *acc, int acc_type, uint32_t frac_num,
+                                  uint32_t frac_den, int r_theta, int r_rho, hough_peak *peaks,
+                                  uint32_t cap, uint32_t *n_peaks, uint32_t *status, hipStream_t s) {
+    const size_t lds = (size_t)kIterCandidates * sizeof(uint64_t);
+    if (acc_type == HOUGH_ACC_U16) {
+        static const bool lds_ok = (allow_lds(k_peaks_iter<uint16_t>), true);
+        (void)lds_ok;
+        hipLaunchKernelGGL((k_peaks_iter<uint16_t>), dim3(1), dim3(kIterWaves * 64), lds, s, g,
+                           static_cast<const uint16_t *>(acc), frac_num, frac_den, r_theta, r_rho,
+                           peaks, cap, n_peaks, status);
+    } else {
+        static const bool lds_ok = (allow_lds(k_peaks_iter<uint32_t>), true);
+        (void)lds_ok;
+        hipLaunchKernelGGL((k_peaks_iter<uint32_t>), dim3(1), dim3(kIterWaves * 64), lds, s, g,
+                           static_cast<const uint32_t *>(acc), frac_num, frac_den, r_theta, r_rho,
+                           peaks, cap, n_peaks, status);
+    }
+    return hipGetLastError();
+}
+
+size_t peaks_iterative_lds_bytes() { return (size_t)kIterCandidates * sizeof(uint64_t) + 256; }
 
 hipError_t launch_retain(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                          const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,

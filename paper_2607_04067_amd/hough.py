@@ -20,7 +20,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "hough.h")
 
 HOUGH_OK, HOUGH_EINVAL, HOUGH_ENOMEM, HOUGH_EOVERFLOW, HOUGH_EDEVICE = 0, -1, -2, -3, -4
 ACC_U16, ACC_I32 = 1, 2
-EV_PEAKS_TRUNCATED, EV_INVALID_HITS, EV_TOO_MANY_HITS = 1, 2, 4
+EV_PEAKS_TRUNCATED, EV_INVALID_HITS, EV_TOO_MANY_HITS, EV_TOO_MANY_CANDIDATES = 1, 2, 4, 8
 
 
 class HoughError(RuntimeError):
@@ -63,6 +63,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.hough_vote.restype = i32
     L.hough_peaks.argtypes = [vp, vp, vp, u32, vp, vp]
     L.hough_peaks.restype = i32
+    L.hough_peaks_iterative.argtypes = [vp, vp, u32, u32, ctypes.c_int32, ctypes.c_int32, vp, u32, vp, vp, vp]
+    L.hough_peaks_iterative.restype = i32
+    L.hough_max_iterative_candidates.argtypes = []
+    L.hough_max_iterative_candidates.restype = u32
     L.hough_retain.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp]
     L.hough_retain.restype = i32
     L.hough_run_batch.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp]
@@ -214,6 +218,27 @@ class Context:
         pn = _dev(n_peaks, torch.int32, "n_peaks", 1)
         _check(self._lib.hough_peaks(self._ctx, pa, pp, int(cap), pn, _stream(stream)), "hough_peaks")
         return peaks, n_peaks
+
+    def peaks_iterative(self, acc: torch.Tensor, cap: int, frac=(1, 2), r_theta: int = 5, r_rho: int = 5,
+                        peaks: torch.Tensor | None = None, n_peaks: torch.Tensor | None = None,
+                        status: torch.Tensor | None = None, stream=None):
+        """The paper's peak finder: (peaks int32 [cap, 2] in extraction order, n_peaks int32 [1],
+        status int32 [1])."""
+        dt = torch.int16 if self.acc_type == "u16" else torch.int32
+        pa = _dev(acc, dt, "acc", self.n_theta * self.n_rho)
+        if peaks is None:
+            peaks = torch.zeros((max(cap, 1), 2), dtype=torch.int32, device=acc.device)
+        if n_peaks is None:
+            n_peaks = torch.zeros(1, dtype=torch.int32, device=acc.device)
+        if status is None:
+            status = torch.zeros(1, dtype=torch.int32, device=acc.device)
+        pp = _dev(peaks, torch.int32, "peaks", 2 * cap)
+        pn = _dev(n_peaks, torch.int32, "n_peaks", 1)
+        ps = _dev(status, torch.int32, "status", 1)
+        _check(self._lib.hough_peaks_iterative(self._ctx, pa, int(frac[0]), int(frac[1]), int(r_theta),
+                                               int(r_rho), pp, int(cap), pn, ps, _stream(stream)),
+               "hough_peaks_iterative")
+        return peaks, n_peaks, status
 
     def retain(self, x: torch.Tensor, y: torch.Tensor, peaks: torch.Tensor, n_peaks: torch.Tensor, cap: int,
                keep: torch.Tensor | None = None, stream=None) -> torch.Tensor:

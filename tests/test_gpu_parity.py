@@ -487,3 +487,94 @@ def test_served_results_equal_results_alone(H, plain):
         assert res["batch_events"].max() >= 1
     for p in pools:
         p.ctx.close()
+
+
+# ----------------------------------------------------- the paper's iterative peak finder (plain path)
+def _iter_case(H, orc, ctx, g, x, y, floor_t, frac, rt, rr, cap=4096):
+    import torch
+    acc = ctx.vote(_t(x), _t(y))
+    pk, npk, st = ctx.peaks_iterative(acc, cap, frac, rt, rr)
+    torch.cuda.synchronize()
+    acc_ref = orc.vote(g, x, y)
+    mx = int(acc_ref.max())
+    thr = max(floor_t, -(-mx * frac[0] // frac[1]))
+    over = int((acc_ref >= thr).sum()) > int(H.load().hough_max_iterative_candidates())
+    if over:
+        assert int(st.item()) == H.EV_TOO_MANY_CANDIDATES and int(npk.item()) == 0
+        return None
+    rj, rk, rc, n_ref = orc.peaks_iterative(acc_ref, floor_t, frac, rt, rr, cap)
+    assert int(st.item()) == 0
+    assert int(npk.item()) == n_ref
+    m = min(n_ref, cap)
+    got = H.decode_peaks(pk, m)
+    want = np.stack([rj, rk, rc], 1).astype(np.int64)
+    assert np.array_equal(got, want), (frac, rt, rr)
+    return pk, npk, n_ref
+
+
+# (frac, r_theta, r_rho) per grid; the oracle rescans the grid for every peak it takes, so the
+# larger grids use fractions that keep the peak count moderate
+ITER_SETTINGS = {
+    "paper-1000ev-360x256": [((1, 2), 5, 5), ((1, 3), 2, 8), ((2, 3), 0, 0), ((0, 1), 1, 1),
+                             ((1, 2), 40, 40), ((1, 4), 3, 0)],
+    "dense-2000ev-720x512": [((1, 2), 5, 5), ((2, 3), 0, 0), ((1, 2), 40, 40), ((1, 3), 3, 0)],
+    "paper-1000ev-1000x1000": [((1, 2), 5, 5), ((2, 3), 0, 0), ((1, 2), 40, 40), ((2, 5), 3, 0)],
+}
+
+
+@pytest.mark.parametrize("name", sorted(ITER_SETTINGS))
+def test_peaks_iterative_parity(H, orc, name):
+    wl = synth.WORKLOADS[name]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 0, n_events=2)
+    for floor_t in (wl.threshold, 2):
+        ctx = H.Context.for_workload(wl, threshold=floor_t)
+        for e in range(ev.n_events):
+            x, y = ev.event(e)
+            for frac, rt, rr in ITER_SETTINGS[name]:
+                say(f"iterative {name} floor={floor_t} event={e} frac={frac} window=({rt},{rr})")
+                _iter_case(H, orc, ctx, g, x, y, floor_t, frac, rt, rr)
+        ctx.close()
+
+
+def test_peaks_iterative_truncation_and_overflow(H, orc):
+    import torch
+    wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
+    g = orc.Grid.of(wl)
+    x, y = synth.make_events(wl, 0, n_events=1).event(0)
+    # floor 1: the first pass sees far more than the LDS holds, the relative threshold then
+    # leaves few cells, which a second pass over acc gathers
+    ctx = H.Context.for_workload(wl, threshold=1)
+    acc_ref = orc.vote(g, x, y)
+    assert int((acc_ref >= 1).sum()) > int(H.load().hough_max_iterative_candidates())
+    out = _iter_case(H, orc, ctx, g, x, y, 1, (1, 2), 4, 4)
+    assert out is not None
+    _, _, n = out
+    for cap in (0, 1, n - 1):
+        _iter_case(H, orc, ctx, g, x, y, 1, (1, 2), 4, 4, cap=cap)
+    # a tiny relative threshold keeps too many cells: flagged, nothing listed
+    assert _iter_case(H, orc, ctx, g, x, y, 1, (1, 1000), 1, 1) is None
+    with pytest.raises(H.HoughError):
+        ctx.peaks_iterative(ctx.vote(_t(x), _t(y)), 16, (1, 0), 1, 1)      # frac_den == 0
+    with pytest.raises(H.HoughError):
+        ctx.peaks_iterative(ctx.vote(_t(x), _t(y)), 16, (1, 2), -1, 1)     # negative radius
+    ctx.close()
+
+
+def test_paper_pipeline_vote_iterative_peaks_retain(H, orc):
+    """Plain path with the paper's peak finder: retention against its peaks matches the oracle."""
+    import torch
+    wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 2, n_events=3)
+    ctx = H.Context.for_workload(wl, threshold=wl.threshold)
+    for e in range(ev.n_events):
+        x, y = ev.event(e)
+        acc = ctx.vote(_t(x), _t(y))
+        pk, npk, st = ctx.peaks_iterative(acc, 256, (1, 2), 5, 5)
+        keep = ctx.retain(_t(x), _t(y), pk, npk, 256)
+        torch.cuda.synchronize()
+        rj, rk, rc, n = orc.peaks_iterative(orc.vote(g, x, y), wl.threshold, (1, 2), 5, 5, 256)
+        assert int(npk.item()) == n and n >= 1
+        assert np.array_equal(keep.cpu().numpy(), orc.retain(g, x, y, rj, rk, wl.rho_window))
+    ctx.close()
