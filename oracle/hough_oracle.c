@@ -214,6 +214,59 @@ void oracle_retain(int n_rho, const float *C, const float *S, float Bf, int rho_
 }
 
 /*
+ * Candidate circles and track parameters of peaks (Sec. II, Eq. (2) read with the factor two
+ * that Eq. (1) implies).  The line u cos(theta) + v sin(theta) = rho of the conformal plane is
+ * the circle through the origin with centre (cos theta, sin theta) / (2 rho) and radius
+ * 1 / (2 |rho|).  A peak (j, k) stands for theta_j = j pi / n_theta (the column's own angle)
+ * and the centre of rho bin k, rho = rho_min + (k + 1/2) (rho_max - rho_min) / n_rho.
+ * Transverse momentum: p_T [GeV/c] = 0.299792458 * B [T] * R [m].
+ * The peak's hits are those the retention rule associates with it alone (|k_i(j) - k| <=
+ * rho_window at the peak's column).  A track starting at the origin runs along the half of the
+ * circle on one side of the line from the origin through the centre; its charge is +1 when
+ * more of those hits lie counter-clockwise of that line than clockwise (side test
+ * C_j y - S_j x, times the sign of rho, in float with one fma), -1 in the opposite case and 0 on
+ * a tie.  The direction at the origin is phi0 = phi_c + q pi / 2, phi_c = atan2(b, a).
+ * out[7 * p + ...] = {a, b, R, pT, phi_c, q, n_hits} as doubles.
+ */
+void oracle_track_params(int n_theta, int n_rho, double rho_min, double rho_max, const float *C,
+                         const float *S, float Bf, int rho_window, double b_tesla,
+                         const float *x, const float *y, long n_hits,
+                         const int32_t *pj, const int32_t *pk, long n_peaks, double *out)
+{
+    const double pi = 3.14159265358979323846;
+    const double drho = (rho_max - rho_min) / (double)n_rho;
+    for (long p = 0; p < n_peaks; ++p) {
+        const int j = pj[p], k = pk[p];
+        const double theta = ((double)j * pi) / (double)n_theta;
+        const double rho = rho_min + ((double)k + 0.5) * drho;
+        const double a = cos(theta) / (2.0 * rho), b = sin(theta) / (2.0 * rho);
+        const double R = 1.0 / (2.0 * fabs(rho));
+        long ccw = 0, cw = 0, n = 0;
+        for (long i = 0; i < n_hits; ++i) {
+            float u, v;
+            if (!oracle_conformal(x[i], y[i], &u, &v)) continue;
+            const int ki = oracle_rho_bin(u, v, C[j], S[j], Bf, n_rho);
+            if (ki < 0) continue;
+            const int d = ki > k ? ki - k : k - ki;
+            if (d > rho_window) continue;
+            ++n;
+            float side = fmaf(C[j], y[i], -(S[j] * x[i]));
+            if (rho < 0.0) side = -side;
+            if (side > 0.0f) ++ccw;
+            else if (side < 0.0f) ++cw;
+        }
+        double *o = out + 7 * p;
+        o[0] = a;
+        o[1] = b;
+        o[2] = R;
+        o[3] = 0.299792458 * b_tesla * R * 1e-3;
+        o[4] = atan2(b, a);
+        o[5] = (double)(ccw > cw ? 1 : (ccw < cw ? -1 : 0));
+        o[6] = (double)n;
+    }
+}
+
+/*
  * Whole hot path over CSR-packed events: per event vote, find all peaks, keep hits near any
  * of them, and return the first `cap` peaks of each event (raster order) with the true count.
  * Events are independent (Sec. III), so they are spread over n_threads OpenMP threads; each

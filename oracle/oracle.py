@@ -70,6 +70,10 @@ def lib():
         L.oracle_peaks_iterative.argtypes = [_i32p, c_int, c_int, c_int, c_int, c_int, c_int, c_int,
                                              _i32p, _i32p, _i32p, c_long]
         L.oracle_peaks_iterative.restype = c_long
+        _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+        L.oracle_track_params.argtypes = [c_int, c_int, c_double, c_double, _f32p, _f32p, c_float, c_int,
+                                          c_double, _f32p, _f32p, c_long, _i32p, _i32p, c_long, _f64p]
+        L.oracle_track_params.restype = None
         L.oracle_retain.argtypes = [c_int, _f32p, _f32p, c_float, c_int, _f32p, _f32p, c_long,
                                     _i32p, _i32p, c_long, _u8p]
         L.oracle_retain.restype = None
@@ -159,6 +163,22 @@ def peaks_iterative(acc: np.ndarray, t_abs: int, frac: tuple[int, int], r_theta:
         raise MemoryError("oracle_peaks_iterative")
     m = min(n, cap)
     return pj[:m].copy(), pk[:m].copy(), pc[:m].copy(), n
+
+
+TRACK_FIELDS = ("a", "b", "radius", "pt", "phi_c", "charge", "n_hits")
+
+
+def track_params(g: Grid, x, y, pj, pk, rho_window: int = 1, b_tesla: float = 1.0) -> np.ndarray:
+    """Candidate circle and track parameters of each peak (Eq. (2) with the factor two of
+    Eq. (1)): float64 [n_peaks, 7] with columns TRACK_FIELDS (mm, mm, mm, GeV/c, rad, +-1/0,
+    hits associated with the peak)."""
+    x, y = _f32(x), _f32(y)
+    pj = np.ascontiguousarray(pj, dtype=np.int32)
+    pk = np.ascontiguousarray(pk, dtype=np.int32)
+    out = np.zeros((max(pj.size, 1), 7), np.float64)
+    lib().oracle_track_params(g.n_theta, g.n_rho, g.rho_min, g.rho_max, g.C, g.S, float(g.B),
+                              int(rho_window), float(b_tesla), x, y, x.size, pj, pk, pj.size, out)
+    return out[:pj.size].copy()
 
 
 def is_peak(acc: np.ndarray, threshold: int, j: int, k: int) -> bool:

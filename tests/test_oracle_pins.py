@@ -542,3 +542,58 @@ def test_iterative_single_track_is_the_only_peak(orc):
         acc = orc.vote(g, x, y)
         pj, pk, pc, n = orc.peaks_iterative(acc, 2, (1, 2), 5, 5)
         assert n == 1 and (pj[0], pk[0], pc[0]) == (j, k, x.size)
+
+
+# --------------------------------------------- candidate circles and track parameters (Eq. (2))
+def test_track_params_of_an_exact_cell_circle(orc):
+    """A circle built from a cell's own theta and rho-bin centre comes back exactly."""
+    wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
+    g = orc.Grid.of(wl)
+    rng = np.random.default_rng(41)
+    for _ in range(6):
+        j = int(rng.integers(3, g.n_theta - 3))
+        k = int(rng.integers(g.n_rho // 4 + 10, 3 * g.n_rho // 4 - 10))
+        if abs(k - g.n_rho // 2) < 12:
+            continue
+        x, y = _track_for_cell(g, j, k)
+        tp = orc.track_params(g, x, y, [j], [k], 1, 1.0)[0]
+        theta = (j * math.pi) / g.n_theta
+        rho = g.rho_min + (k + 0.5) * (g.rho_max - g.rho_min) / g.n_rho
+        radius = 1.0 / (2.0 * abs(rho))
+        assert tp[2] == pytest.approx(radius, rel=1e-12)
+        assert tp[0] == pytest.approx(math.cos(theta) / (2 * rho), rel=1e-12, abs=1e-9)
+        assert tp[1] == pytest.approx(math.sin(theta) / (2 * rho), rel=1e-12, abs=1e-9)
+        assert math.hypot(tp[0], tp[1]) == pytest.approx(radius, rel=1e-12)   # passes the origin
+        assert tp[3] == pytest.approx(0.299792458 * 1.0 * radius / 1000.0, rel=1e-12)
+        assert tp[6] == x.size                          # every hit votes in the peak's own cell
+
+
+@pytest.mark.parametrize("q", [1, -1])
+def test_track_params_recover_charge_direction_and_pt(orc, q):
+    """Single generated tracks that do not curl (2R beyond the outer layer): the first extracted
+    peak carries the track's charge, its direction at the origin within one inner-layer cell
+    (hits sit on wires, up to half a cell of 2 pi / 128 off the true circle, so the best line
+    can turn by about that much) and a radius whose rho lies within four bins of the truth
+    (a sanity bound: the wire quantisation moves the accumulator maximum by up to about three
+    bins of 2e-5 for these stiff tracks; 200 generated tracks stayed within 2.9)."""
+    wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
+    g = orc.Grid.of(wl)
+    dtheta = math.pi / g.n_theta
+    drho = (g.rho_max - g.rho_min) / g.n_rho
+    rng = np.random.default_rng(42 + q)
+    for _ in range(10):
+        pt = float(rng.uniform(0.3, 1.5))
+        radius = 1000.0 * pt / (synth.C_LIGHT_GEV_PER_T_M * 1.0)
+        phi0 = float(rng.uniform(0.0, 2.0 * math.pi))
+        tx, ty = synth.track_hits(radius, q, phi0, 1)
+        x, y = tx.astype(np.float32), ty.astype(np.float32)
+        acc = orc.vote(g, x, y)
+        pj, pk, pc, n = orc.peaks_iterative(acc, 5, (1, 2), 5, 5)
+        tp = orc.track_params(g, x, y, pj[:1], pk[:1], 1, 1.0)[0]
+        assert tp[5] == q
+        phi0_reco = tp[4] + tp[5] * math.pi / 2
+        assert abs(math.remainder(phi0_reco - phi0, 2 * math.pi)) <= 2 * math.pi / 128 + dtheta
+        assert abs(1 / (2 * tp[2]) - 1 / (2 * radius)) <= 4 * drho
+        assert tp[3] == pytest.approx(0.299792458 * tp[2] / 1000.0, rel=1e-12)
+        # the peak's own hits, counted through the retention rule with that one peak
+        assert tp[6] == int(orc.retain(g, x, y, pj[:1], pk[:1], 1).sum())
