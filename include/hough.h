@@ -128,6 +128,28 @@ int hough_peaks_iterative(hough_ctx *ctx, const void *acc, uint32_t frac_num, ui
                           int32_t r_theta, int32_t r_rho, hough_peak *peaks, uint32_t cap,
                           uint32_t *n_peaks, uint32_t *status, void *stream);
 
+/* A peak read as a candidate track (Sec. II, Eq. (2) with the factor two of Eq. (1)): the
+ * circle through the origin whose conformal line is u cos(theta) + v sin(theta) = rho, with
+ * theta = theta_bin * pi / n_theta and rho the centre of rho_bin.  48 bytes. */
+typedef struct hough_track {
+    double a, b;         /* circle centre, (cos theta, sin theta) / (2 rho), hit units       */
+    double radius;       /* 1 / (2 |rho|)                                                    */
+    double pt;           /* 0.299792458 * b_tesla * radius * 1e-3 (GeV/c for mm and tesla)   */
+    double phi_c;        /* atan2(b, a); the direction at the origin is phi_c + charge*pi/2   */
+    int32_t charge;      /* +1 when more of the peak's hits lie counter-clockwise of the line
+                            from the origin through the centre than clockwise, -1 for the
+                            opposite, 0 on a tie (side test sign(rho) (C_j y - S_j x) in float) */
+    uint32_t n_hits;     /* hits the retention rule associates with this peak alone          */
+} hough_track;
+
+/* Candidate circles and track parameters of the peaks peaks[0 .. min(*n_peaks, cap)-1] of one
+ * event (peaks and n_peaks as written by hough_peaks / hough_peaks_iterative; device
+ * pointers): tracks[p] for each of them.  x, y: the event's n_hits hits.  A peak outside the
+ * grid gets charge 0 and n_hits 0. */
+int hough_track_params(hough_ctx *ctx, const float *x, const float *y, uint32_t n_hits,
+                       const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
+                       double b_tesla, hough_track *tracks, void *stream);
+
 /* Largest number of cells at or above the threshold hough_peaks_iterative handles. */
 uint32_t hough_max_iterative_candidates(void);
 

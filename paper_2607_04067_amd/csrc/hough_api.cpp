@@ -247,6 +247,18 @@ int hough_peaks_iterative(hough_ctx *c, const void *acc, uint32_t frac_num, uint
 
 uint32_t hough_max_iterative_candidates(void) { return 16384u; }
 
+int hough_track_params(hough_ctx *c, const float *x, const float *y, uint32_t n_hits,
+                       const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
+                       double b_tesla, hough_track *tracks, void *stream) {
+    if (!c || !n_peaks || (cap && (!peaks || !tracks))) return HOUGH_EINVAL;
+    if (n_hits && (!x || !y)) return HOUGH_EINVAL;
+    if (((uintptr_t)peaks & 7u) != 0 || ((uintptr_t)tracks & 7u) != 0) return HOUGH_EINVAL;
+    if (!isfinite(b_tesla)) return HOUGH_EINVAL;
+    const hipError_t e = hough::launch_track_params(c->g, x, y, n_hits, peaks, n_peaks, cap, c->p.rho_min,
+                                                    c->p.rho_max, b_tesla, tracks, (hipStream_t)stream);
+    return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
+}
+
 int hough_retain(hough_ctx *c, const float *x, const float *y, uint32_t n_hits,
                  const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap, uint8_t *keep,
                  void *stream) {

@@ -69,6 +69,10 @@ hipError_t launch_batch(const GridArgs &g, const BatchPlan &p, const BatchArgs &
 size_t vote_lds_bytes(int n_rho);
 size_t peaks_lds_bytes(int n_rho);
 size_t peaks_iterative_lds_bytes();
+hipError_t launch_track_params(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
+                               const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
+                               double rho_min, double rho_max, double b_tesla, hough_track *out,
+                               hipStream_t s);
 hipError_t launch_peaks_iterative(const GridArgs &g, const void *acc, int acc_type, uint32_t frac_num,
                                   uint32_t frac_den, int r_theta, int r_rho, hough_peak *peaks,
                                   uint32_t cap, uint32_t *n_peaks, uint32_t *status, hipStream_t s);

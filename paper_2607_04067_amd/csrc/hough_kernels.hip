@@ -814,6 +814,61 @@ __global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, cons
     if (lane == 0) { *n_peaks = taken; *status = 0u; }
 }
 
+// hough_track_params: one wave per peak.  The lanes sweep the event's hits 64 at a time and
+// count, with ballots, the hits the retention rule associates with the peak and how many of
+// them lie on either side of the line from the origin through the circle's centre; lane 0
+// turns the peak into the circle (double precision) and writes the record.
+constexpr int kTrackWaves = 4;
+
+__global__ __launch_bounds__(kTrackWaves * 64) void k_track_params(GridArgs g, const float *__restrict__ x,
+                                                                   const float *__restrict__ y,
+                                                                   uint32_t n_hits, const hough_peak *peaks,
+                                                                   const uint32_t *n_peaks, uint32_t cap,
+                                                                   double rho_min, double rho_max,
+                                                                   double b_tesla, hough_track *out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t p = blockIdx.x * kTrackWaves + (uint32_t)wave;
+    const uint32_t np = min(*n_peaks, cap);
+    if (p >= np) return;
+    const uint2 rec = reinterpret_cast<const uint2 *>(peaks)[p];
+    const int j = (int)(rec.x & 0xffffu), k = (int)(rec.x >> 16);
+    const double pi = 3.14159265358979323846;
+    const double drho = (rho_max - rho_min) / (double)g.n_rho;
+    const double theta = ((double)j * pi) / (double)g.n_theta;
+    const double rho = rho_min + ((double)k + 0.5) * drho;
+    const bool in_grid = j < g.n_theta && k < g.n_rho;
+    const float Cj = in_grid ? g.C[j] : 0.0f, Sj = in_grid ? g.S[j] : 0.0f;
+    uint32_t n = 0, ccw = 0, cw = 0;
+    for (uint32_t base = 0; in_grid && base < n_hits; base += 64) {
+        const uint32_t i = base + lane;
+        float xi = 0.0f, yi = 0.0f;
+        if (i < n_hits) { xi = x[i]; yi = y[i]; }
+        float u, v;
+        const bool ok = conformal(xi, yi, u, v) && i < n_hits;
+        const float w = __builtin_fmaf(v, Sj, g.Bf);
+        const float t = __builtin_fmaf(u, Cj, w);
+        const bool in = ok && t >= 0.0f && t < g.nrho_f;
+        const int d = in ? abs((int)t - k) : 0;
+        const bool mine = in && d <= g.rho_window;
+        float side = __builtin_fmaf(Cj, yi, -(Sj * xi));
+        if (rho < 0.0) side = -side;
+        n += (uint32_t)__popcll(__ballot(mine));
+        ccw += (uint32_t)__popcll(__ballot(mine && side > 0.0f));
+        cw += (uint32_t)__popcll(__ballot(mine && side < 0.0f));
+    }
+    if (lane == 0) {
+        hough_track tr;
+        tr.a = cos(theta) / (2.0 * rho);
+        tr.b = sin(theta) / (2.0 * rho);
+        tr.radius = 1.0 / (2.0 * fabs(rho));
+        tr.pt = 0.299792458 * b_tesla * tr.radius * 1e-3;
+        tr.phi_c = atan2(tr.b, tr.a);
+        tr.charge = ccw > cw ? 1 : (ccw < cw ? -1 : 0);
+        tr.n_hits = n;
+        out[p] = tr;
+    }
+}
+
 // hough_retain: one thread per hit.  Peak rows are processed in blocks that fit LDS: for
 // each block a dilated bitmap (bit k of row j set iff a peak (j, k') has |k - k'| <= W) is
 // built from the peak list, then every unkept hit looks up its own bin in each peak row.
@@ -1107,6 +1162,17 @@ hipError_t launch_peaks_iterative(const GridArgs &g, const void *acc, int acc_ty
 }
 
 size_t peaks_iterative_lds_bytes() { return (size_t)kIterCandidates * sizeof(uint64_t) + 256; }
+
+hipError_t launch_track_params(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
+                               const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
+                               double rho_min, double rho_max, double b_tesla, hough_track *out,
+                               hipStream_t s) {
+    if (cap == 0) return hipSuccess;
+    const int blocks = (int)((cap + kTrackWaves - 1) / kTrackWaves);
+    hipLaunchKernelGGL(k_track_params, dim3(blocks), dim3(kTrackWaves * 64), 0, s, g, x, y, n_hits, peaks,
+                       n_peaks, cap, rho_min, rho_max, b_tesla, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_retain(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                          const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,

@@ -65,6 +65,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.hough_peaks.restype = i32
     L.hough_peaks_iterative.argtypes = [vp, vp, u32, u32, ctypes.c_int32, ctypes.c_int32, vp, u32, vp, vp, vp]
     L.hough_peaks_iterative.restype = i32
+    L.hough_track_params.argtypes = [vp, vp, vp, u32, vp, vp, u32, ctypes.c_double, vp, vp]
+    L.hough_track_params.restype = i32
     L.hough_max_iterative_candidates.argtypes = []
     L.hough_max_iterative_candidates.restype = u32
     L.hough_retain.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp]
@@ -128,6 +130,18 @@ def decode_peaks(peaks: torch.Tensor | np.ndarray, n: int | None = None) -> np.n
     if n is not None:
         a = a[:n]
     return np.stack([a[:, 0] & 0xFFFF, a[:, 0] >> 16, a[:, 1]], axis=1).astype(np.int64)
+
+
+# hough_track records: 5 doubles, int32 charge, uint32 n_hits (48 bytes)
+TRACK_DTYPE = np.dtype([("a", "<f8"), ("b", "<f8"), ("radius", "<f8"), ("pt", "<f8"), ("phi_c", "<f8"),
+                        ("charge", "<i4"), ("n_hits", "<u4")])
+
+
+def decode_tracks(tracks: torch.Tensor | np.ndarray, n: int | None = None) -> np.ndarray:
+    """hough_track records (a float64 tensor of 6 per record) -> numpy structured array."""
+    a = tracks.detach().cpu().numpy() if isinstance(tracks, torch.Tensor) else np.asarray(tracks)
+    a = np.ascontiguousarray(a).reshape(-1).view(np.uint8).view(TRACK_DTYPE)
+    return a[:n] if n is not None else a
 
 
 class Context:
@@ -239,6 +253,22 @@ class Context:
                                                int(r_rho), pp, int(cap), pn, ps, _stream(stream)),
                "hough_peaks_iterative")
         return peaks, n_peaks, status
+
+    def track_params(self, x: torch.Tensor, y: torch.Tensor, peaks: torch.Tensor, n_peaks: torch.Tensor,
+                     cap: int, b_tesla: float = 1.0, tracks: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+        """Candidate circles of the first min(n_peaks, cap) peaks: float64 [cap, 6] holding
+        hough_track records (decode with decode_tracks)."""
+        if tracks is None:
+            tracks = torch.zeros((max(cap, 1), 6), dtype=torch.float64, device=peaks.device)
+        pt = _dev(tracks, torch.float64, "tracks", 6 * cap)
+        pp = _dev(peaks, torch.int32, "peaks", 2 * cap)
+        pn = _dev(n_peaks, torch.int32, "n_peaks", 1)
+        px = self._ptr_or_dummy(x, torch.float32, "x")
+        py = self._ptr_or_dummy(y, torch.float32, "y")
+        _check(self._lib.hough_track_params(self._ctx, px, py, x.numel(), pp, pn, int(cap), float(b_tesla),
+                                            pt, _stream(stream)), "hough_track_params")
+        return tracks
 
     def retain(self, x: torch.Tensor, y: torch.Tensor, peaks: torch.Tensor, n_peaks: torch.Tensor, cap: int,
                keep: torch.Tensor | None = None, stream=None) -> torch.Tensor:

@@ -36,6 +36,12 @@ def test_struct_layouts_match_header(hough_mod):
     text = open(os.path.join(ROOT, "include", "hough.h")).read()
     peak = re.search(r"typedef struct hough_peak \{(.*?)\}", text, re.S).group(1)
     assert re.findall(r"(uint\d+_t)", peak) == ["uint16_t", "uint16_t", "uint32_t"]
+    # hough_track: five doubles, int32 charge, uint32 n_hits = 48 bytes, as decode_tracks reads it
+    track = re.sub(r"/\*.*?\*/", "", re.search(r"typedef struct hough_track \{(.*?)\}", text, re.S).group(1),
+                   flags=re.S)
+    assert re.findall(r"\b(double|int32_t|uint32_t)\b", track) == ["double"] * 4 + ["int32_t", "uint32_t"]
+    assert track.count(",") == 1 and hough_mod.TRACK_DTYPE.itemsize == 48
+    assert hough_mod.TRACK_DTYPE.names == ("a", "b", "radius", "pt", "phi_c", "charge", "n_hits")
 
 
 def test_status_strings(hough_mod):

@@ -578,3 +578,36 @@ def test_paper_pipeline_vote_iterative_peaks_retain(H, orc):
         assert int(npk.item()) == n and n >= 1
         assert np.array_equal(keep.cpu().numpy(), orc.retain(g, x, y, rj, rk, wl.rho_window))
     ctx.close()
+
+
+# ------------------------------------------------------------ candidate circles and track parameters
+@pytest.mark.parametrize("name,finder", [("paper-1000ev-1000x1000", "iterative"),
+                                         ("paper-1000ev-360x256", "3x3"), ("dense-2000ev-720x512", "3x3")])
+def test_track_params_parity(H, orc, name, finder):
+    import torch
+    wl = synth.WORKLOADS[name]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 4, n_events=2)
+    ctx = H.Context.for_workload(wl, threshold=max(wl.threshold, 20))
+    cap = 4096
+    for e in range(ev.n_events):
+        x, y = ev.event(e)
+        xt, yt = _t(x), _t(y)
+        acc = ctx.vote(xt, yt)
+        if finder == "iterative":
+            pk, npk, _ = ctx.peaks_iterative(acc, cap, (1, 2), 5, 5)
+        else:
+            pk, npk = ctx.peaks(acc, cap)
+        tr = ctx.track_params(xt, yt, pk, npk, cap, 1.0)
+        torch.cuda.synchronize()
+        n = min(int(npk.item()), cap)
+        assert n >= 1
+        got = H.decode_tracks(tr, n)
+        pl = H.decode_peaks(pk, n)
+        ref = orc.track_params(g, x, y, pl[:, 0], pl[:, 1], wl.rho_window, 1.0)
+        say(f"tracks {name} {finder} event={e} peaks={n}")
+        assert np.array_equal(got["charge"], ref[:, 5].astype(np.int32))
+        assert np.array_equal(got["n_hits"], ref[:, 6].astype(np.uint32))
+        for i, f in enumerate(("a", "b", "radius", "pt", "phi_c")):
+            np.testing.assert_allclose(got[f], ref[:, i], rtol=1e-12, atol=1e-9, err_msg=f)
+    ctx.close()
