@@ -204,6 +204,74 @@ def iterative_path(H, wl, ev, n_events: int = 200, frac=(1, 2), r_theta: int = 5
             "R_s": round(float(k[lab >= 0].mean()), 4) if (lab >= 0).any() else None}
 
 
+PT_BINS = (0.05, 0.2, 0.5, 1.0, 1.5)
+
+
+def physics(H, wl, ev, n_events: int = 200, frac=(1, 2), r_theta: int = 5, r_rho: int = 5):
+    """Track finding against the generator's truth, with the paper's peak finder on the GPU
+    (vote, relative threshold + iterative extraction, candidate circles).  A truth track's
+    candidate is the peak that keeps the most of its hits (retention with that peak alone, on
+    the GPU); the track counts as found when |pT_reco - pT_truth| < 20 MeV/c or that peak keeps
+    more than 90% of its hits (the paper's composite criterion).  Reports the efficiency per
+    pT range, and for found tracks the charge agreement and robust widths (1.4826 x median
+    absolute deviation) of the phi0 residual and of the relative pT residual."""
+    import torch
+    ctx = H.Context.for_workload(wl)
+    sub = ev.subset(np.arange(min(n_events, ev.n_events)))
+    xt, yt, _ = H.to_device(sub)
+    cap = 256
+    acc = torch.empty((wl.n_theta, wl.n_rho), dtype=torch.int16 if wl.acc == "u16" else torch.int32,
+                      device="cuda")
+    offs = sub.offsets.astype(np.int64)
+    one = torch.ones(1, dtype=torch.int32, device="cuda")
+    found, pts, dphi, dpt, qok = [], [], [], [], []
+    for e in range(sub.n_events):
+        a, b = int(offs[e]), int(offs[e + 1])
+        x, y = xt[a:b], yt[a:b]
+        ctx.vote(x, y, acc)
+        pk, npk, _ = ctx.peaks_iterative(acc, cap, frac, r_theta, r_rho)
+        tr = ctx.track_params(x, y, pk, npk, cap, wl.b_tesla)
+        n = min(int(npk.item()), cap)
+        tracks = H.decode_tracks(tr, n)
+        keeps = torch.zeros((max(n, 1), b - a), dtype=torch.uint8, device="cuda")
+        for p in range(n):
+            ctx.retain(x, y, pk[p:p + 1], one, 1, keeps[p])
+        kp = keeps[:n].cpu().numpy().astype(bool)
+        lab = sub.labels[a:b]
+        for t in np.nonzero(sub.track_event == e)[0]:
+            mine = lab == (t - np.searchsorted(sub.track_event, e))
+            pt_true = float(sub.track_pt[t])
+            pts.append(pt_true)
+            if n == 0 or not mine.any():
+                found.append(False)
+                continue
+            srr = kp[:, mine].sum(axis=1) / mine.sum()
+            best = int(np.argmax(srr))
+            pt_reco = float(tracks["pt"][best])
+            ok = abs(pt_reco - pt_true) < 0.020 or srr[best] > 0.9
+            found.append(ok)
+            if ok:
+                q = int(tracks["charge"][best])
+                qok.append(q == int(sub.track_charge[t]))
+                phi0 = float(tracks["phi_c"][best]) + q * np.pi / 2
+                dphi.append(float(np.remainder(phi0 - sub.track_phi0[t] + np.pi, 2 * np.pi) - np.pi))
+                dpt.append((pt_reco - pt_true) / pt_true)
+    ctx.close()
+    found, pts = np.array(found), np.array(pts)
+    robust = lambda v: round(float(1.4826 * np.median(np.abs(np.array(v) - np.median(v)))), 5) if v else None
+    by_pt = {}
+    for lo, hi in zip(PT_BINS[:-1], PT_BINS[1:]):
+        sel = (pts >= lo) & (pts < hi)
+        by_pt[f"{lo}-{hi}"] = round(float(found[sel].mean()), 4) if sel.any() else None
+    return {"events": sub.n_events, "tracks": int(found.size),
+            "finder": f"relative threshold {frac[0]}/{frac[1]}, window +-{r_theta} x +-{r_rho}",
+            "efficiency": round(float(found.mean()), 4) if found.size else None,
+            "efficiency_by_pt_gev": by_pt,
+            "charge_correct": round(float(np.mean(qok)), 4) if qok else None,
+            "phi0_width_rad": robust(dphi), "pt_rel_width": robust(dpt),
+            "criterion": "|pT_reco - pT_truth| < 20 MeV/c or > 90% of the track's hits kept by its peak"}
+
+
 def end_to_end(H, ctx, wl, ev, reps: int = 10):
     """PCIe-inclusive rate of the batch path: hits and offsets from pinned host memory to HBM,
     one fused launch, then n_peaks, status and keep (and, in the second figure, the whole
@@ -426,6 +494,8 @@ def main(argv=None):
         out["plain"] = plain_path(H, wl, ev)
         log("plain per-event path with the iterative peak finder")
         out["plain_iterative"] = iterative_path(H, wl, ev)
+        log("track finding against the truth")
+        out["physics"] = physics(H, wl, ev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, ev)
