@@ -340,7 +340,7 @@ def serving(H, duration_s: float, warmup_s: float, plain_duration_s: float, pool
         pools.append(serve.Pool(H.Context.for_workload(wl, max_peaks=MAX_PEAKS[name]), ev))
     sizes = [p.batch.n_events for p in pools]
     out = {"mix": "50/50 paper-1000ev-360x256 / dense-2000ev-720x512 generators",
-           "pool_events": pool_events, "n_streams": 8, "max_batch_events": 256,
+           "pool_events": pool_events, "n_streams": 8, "max_batch_events": 256, "small_batch_events": 64,
            "latency": "results (n_peaks, status, keep) in host memory minus scheduled arrival",
            "served": {}, "plain": {}}
     for i, rate in enumerate(SERVE_RATES):

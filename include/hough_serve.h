@@ -18,6 +18,9 @@
  *
  * Batches on different streams run concurrently; each stream slot therefore launches through
  * private copies of the pools' contexts (same parameters and launch shape), made on entry.
+ * Inside a batch the events are ordered largest first (the smallest fill the kernel's tail);
+ * a batch's ids and keep offsets go to the device in one copy and its n_peaks, status and
+ * keep bytes come back in one.
  *
  * With `plain` set, each request is instead processed alone by hough_vote, hough_peaks and
  * hough_retain (three launches, accumulator through HBM), one request per stream slot, under
@@ -50,6 +53,8 @@ typedef struct hough_serve_config {
     int32_t max_batch_hits;         /* device arena per stream slot, in hits, >= 1           */
     int32_t plain;                  /* 0: batches through hough_run_batch_gather; 1: per event */
     int32_t copy_peaks;             /* 1: bring the peak lists back as part of completion    */
+    int32_t small_batch_events;     /* batches of at most this many events run with 16-wave
+                                       workgroups (one event per CU finishes sooner); 0: never */
     double max_wait_us;             /* hold a partial batch until its oldest event waited this
                                        long while a slot is free (0: launch at once)          */
 } hough_serve_config;

@@ -4,6 +4,7 @@
 // its results; all per-event compute runs in the library's kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <new>
@@ -22,17 +23,21 @@ struct Kind {
 };
 
 // One stream and the device/pinned buffers of one batch (or one plain event) in flight.
+// A batch of n events moves in one copy each way: in = [ids (n) | keep offsets (n)] and
+// out = [n_peaks (n) | status (n) | keep bytes], packed for the batch's own n.
 struct Slot {
     hipStream_t stream = nullptr;
     std::vector<hough_ctx *> ctx;      // one private context per kind: its own work counter
+    std::vector<hough_ctx *> ctx_small;  // the same grid with 16-wave workgroups, for small batches
     hipEvent_t done = nullptr;
-    uint32_t *d_ids = nullptr, *d_koff = nullptr, *d_npk = nullptr, *d_status = nullptr;
-    uint8_t *d_keep = nullptr;
+    uint32_t *d_in = nullptr;
+    uint8_t *d_out = nullptr;
     hough_peak *d_peaks = nullptr;
     void *d_acc = nullptr;
-    uint32_t *h_ids = nullptr, *h_koff = nullptr, *h_npk = nullptr, *h_status = nullptr;
-    uint8_t *h_keep = nullptr;
+    uint32_t *h_in = nullptr;
+    uint8_t *h_out = nullptr;
     hough_peak *h_peaks = nullptr;
+    uint32_t n = 0;                    // events of the batch in flight
     bool busy = false;
     int kind = 0;
     double t_launch = 0.0;
@@ -48,14 +53,12 @@ struct Server {
     ~Server() {
         for (Slot &s : slots) {
             if (s.stream) (void)hipStreamSynchronize(s.stream);
-            (void)hipFree(s.d_ids); (void)hipFree(s.d_koff); (void)hipFree(s.d_npk);
-            (void)hipFree(s.d_status); (void)hipFree(s.d_keep); (void)hipFree(s.d_peaks);
-            (void)hipFree(s.d_acc);
-            (void)hipHostFree(s.h_ids); (void)hipHostFree(s.h_koff); (void)hipHostFree(s.h_npk);
-            (void)hipHostFree(s.h_status); (void)hipHostFree(s.h_keep); (void)hipHostFree(s.h_peaks);
+            (void)hipFree(s.d_in); (void)hipFree(s.d_out); (void)hipFree(s.d_peaks); (void)hipFree(s.d_acc);
+            (void)hipHostFree(s.h_in); (void)hipHostFree(s.h_out); (void)hipHostFree(s.h_peaks);
             if (s.done) (void)hipEventDestroy(s.done);
             if (s.stream) (void)hipStreamDestroy(s.stream);
             for (hough_ctx *c : s.ctx) hough_destroy(c);
+            for (hough_ctx *c : s.ctx_small) hough_destroy(c);
         }
     }
 
@@ -66,14 +69,10 @@ struct Server {
         for (Slot &s : slots) {
             bool ok = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) == hipSuccess &&
                       hipEventCreateWithFlags(&s.done, hipEventDisableTiming) == hipSuccess;
-            ok = ok && hipMalloc(&s.d_ids, E * 4) == hipSuccess && hipMalloc(&s.d_koff, E * 4) == hipSuccess &&
-                 hipMalloc(&s.d_npk, E * 4) == hipSuccess && hipMalloc(&s.d_status, E * 4) == hipSuccess &&
-                 hipMalloc(&s.d_keep, H) == hipSuccess &&
+            ok = ok && hipMalloc(&s.d_in, E * 8) == hipSuccess && hipMalloc(&s.d_out, E * 8 + H) == hipSuccess &&
                  hipMalloc(&s.d_peaks, E * (cap_max ? cap_max : 1) * sizeof(hough_peak)) == hipSuccess;
             if (ok && cfg.plain) ok = hipMalloc(&s.d_acc, acc_max) == hipSuccess;
-            ok = ok && hipHostMalloc(&s.h_ids, E * 4) == hipSuccess && hipHostMalloc(&s.h_koff, E * 4) == hipSuccess &&
-                 hipHostMalloc(&s.h_npk, E * 4) == hipSuccess && hipHostMalloc(&s.h_status, E * 4) == hipSuccess &&
-                 hipHostMalloc(&s.h_keep, H) == hipSuccess &&
+            ok = ok && hipHostMalloc(&s.h_in, E * 8) == hipSuccess && hipHostMalloc(&s.h_out, E * 8 + H) == hipSuccess &&
                  hipHostMalloc(&s.h_peaks, (cfg.copy_peaks ? E * (cap_max ? cap_max : 1) : 1) * sizeof(hough_peak)) == hipSuccess;
             if (!ok) return HOUGH_ENOMEM;
             s.reqs.reserve(E);
@@ -87,6 +86,15 @@ struct Server {
                 hough_batch_plan bp;
                 if (hough_get_batch_plan(k.pool.ctx, &bp) != HOUGH_OK ||
                     hough_set_batch_plan(c, bp.waves_per_group, bp.column_groups, bp.groups_per_cu) != HOUGH_OK)
+                    return HOUGH_EINVAL;
+                // a batch of fewer events than workgroup slots runs each event on one workgroup:
+                // 16 waves finish it sooner than 8 (when that shape fits; else the pool's shape)
+                hough_ctx *cs = nullptr;
+                const int rs = hough_config(&k.p, &cs);
+                if (rs != HOUGH_OK) return rs;
+                s.ctx_small.push_back(cs);
+                if (hough_set_batch_plan(cs, 16, 1, 0) != HOUGH_OK &&
+                    hough_set_batch_plan(cs, bp.waves_per_group, bp.column_groups, bp.groups_per_cu) != HOUGH_OK)
                     return HOUGH_EINVAL;
             }
         }
@@ -105,7 +113,7 @@ extern "C" int hough_serve_run(const hough_serve_pool *pools, int32_t n_kinds, c
                                uint8_t *keep_out, hough_peak *peaks_out, uint32_t peaks_stride) {
     if (!pools || n_kinds < 1 || !cfg || (n_reqs && (!reqs || !res))) return HOUGH_EINVAL;
     if (cfg->n_streams < 1 || cfg->n_streams > 32 || cfg->max_batch_events < 1 || cfg->max_batch_hits < 1 ||
-        !(cfg->max_wait_us >= 0.0))
+        cfg->small_batch_events < 0 || !(cfg->max_wait_us >= 0.0))
         return HOUGH_EINVAL;
     if (peaks_out && !cfg->copy_peaks) return HOUGH_EINVAL;
 
@@ -157,18 +165,22 @@ extern "C" int hough_serve_run(const hough_serve_pool *pools, int32_t n_kinds, c
     auto finish = [&](Slot &sl, double t) {
         const Kind &kd = srv->kinds[(size_t)sl.kind];
         const uint32_t n = (uint32_t)sl.reqs.size();
+        const uint32_t *h_npk = reinterpret_cast<const uint32_t *>(sl.h_out);
+        const uint32_t *h_status = h_npk + n;
+        const uint8_t *h_keep = sl.h_out + 8u * n;
+        const uint32_t *h_koff = sl.h_in + n;
         for (uint32_t j = 0; j < n; ++j) {
             const uint32_t r = sl.reqs[j];
             hough_serve_result &o = res[r];
             o.launch_us = sl.t_launch;
             o.done_us = t;
-            o.n_peaks = sl.h_npk[j];
+            o.n_peaks = h_npk[j];
             o.status = cfg->plain ? (o.n_peaks > (uint32_t)kd.p.max_peaks ? HOUGH_EV_PEAKS_TRUNCATED : 0u)
-                                  : sl.h_status[j];
+                                  : h_status[j];
             o.batch_events = n;
             o.pad = 0;
             const uint32_t H = hits_of(kd, reqs[r].event);
-            if (keep_out) std::memcpy(keep_out + keep_off[r], sl.h_keep + sl.h_koff[j], H);
+            if (keep_out) std::memcpy(keep_out + keep_off[r], h_keep + h_koff[j], H);
             if (peaks_out) {
                 uint32_t m = o.n_peaks < (uint32_t)kd.p.max_peaks ? o.n_peaks : (uint32_t)kd.p.max_peaks;
                 if (m > peaks_stride) m = peaks_stride;
@@ -190,13 +202,28 @@ extern "C" int hough_serve_run(const hough_serve_pool *pools, int32_t n_kinds, c
         while (h < q.size() && n < E) {                       // memory-based admission
             const uint32_t H = hits_of(kd, reqs[q[h]].event);
             if (hits + H > (uint32_t)cfg->max_batch_hits) break;
-            sl.h_ids[n] = reqs[q[h]].event;
-            sl.h_koff[n] = hits;
             sl.reqs.push_back(q[h]);
             hits += H;
             ++n;
             ++h;
         }
+        // the batch's events go largest first, so that the smallest ones fill the tail of the
+        // kernel; request order inside the slot follows
+        std::sort(sl.reqs.begin(), sl.reqs.end(), [&](uint32_t a, uint32_t b) {
+            const uint32_t ha = hits_of(kd, reqs[a].event), hb = hits_of(kd, reqs[b].event);
+            return ha != hb ? ha > hb : a < b;
+        });
+        uint32_t *h_ids = sl.h_in, *h_koff = sl.h_in + n;
+        uint32_t koff = 0;
+        for (uint32_t j = 0; j < n; ++j) {
+            h_ids[j] = reqs[sl.reqs[j]].event;
+            h_koff[j] = koff;
+            koff += hits_of(kd, h_ids[j]);
+        }
+        sl.n = n;
+        uint32_t *d_ids = sl.d_in, *d_koff = sl.d_in + n;
+        uint32_t *d_npk = reinterpret_cast<uint32_t *>(sl.d_out), *d_status = d_npk + n;
+        uint8_t *d_keep = sl.d_out + 8u * n;
         sl.kind = k;
         sl.busy = true;
         sl.t_launch = t;
@@ -204,24 +231,21 @@ extern "C" int hough_serve_run(const hough_serve_pool *pools, int32_t n_kinds, c
         const size_t cap = (size_t)kd.p.max_peaks;
         int st = HOUGH_OK;
         if (!cfg->plain) {
-            if (hipMemcpyAsync(sl.d_ids, sl.h_ids, n * 4u, hipMemcpyHostToDevice, s) != hipSuccess ||
-                hipMemcpyAsync(sl.d_koff, sl.h_koff, n * 4u, hipMemcpyHostToDevice, s) != hipSuccess)
+            if (hipMemcpyAsync(sl.d_in, sl.h_in, n * 8u, hipMemcpyHostToDevice, s) != hipSuccess)
                 return HOUGH_EDEVICE;
-            st = hough_run_batch_gather(sl.ctx[(size_t)k], kd.pool.x, kd.pool.y, kd.pool.offsets, sl.d_ids, sl.d_koff,
-                                        n, sl.d_peaks, sl.d_npk, sl.d_keep, sl.d_status, s);
-            if (st == HOUGH_OK && hipMemcpyAsync(sl.h_status, sl.d_status, n * 4u, hipMemcpyDeviceToHost, s) != hipSuccess)
-                st = HOUGH_EDEVICE;
+            hough_ctx *c = n <= (uint32_t)cfg->small_batch_events ? sl.ctx_small[(size_t)k] : sl.ctx[(size_t)k];
+            st = hough_run_batch_gather(c, kd.pool.x, kd.pool.y, kd.pool.offsets, d_ids, d_koff,
+                                        n, sl.d_peaks, d_npk, d_keep, d_status, s);
         } else {
-            const uint32_t h0 = kd.pool.host_offsets[sl.h_ids[0]];
+            const uint32_t h0 = kd.pool.host_offsets[h_ids[0]];
             st = hough_vote(sl.ctx[(size_t)k], kd.pool.x + h0, kd.pool.y + h0, hits, sl.d_acc, s);
-            if (st == HOUGH_OK) st = hough_peaks(sl.ctx[(size_t)k], sl.d_acc, sl.d_peaks, (uint32_t)cap, sl.d_npk, s);
+            if (st == HOUGH_OK) st = hough_peaks(sl.ctx[(size_t)k], sl.d_acc, sl.d_peaks, (uint32_t)cap, d_npk, s);
             if (st == HOUGH_OK)
-                st = hough_retain(sl.ctx[(size_t)k], kd.pool.x + h0, kd.pool.y + h0, hits, sl.d_peaks, sl.d_npk,
-                                  (uint32_t)cap, sl.d_keep, s);
+                st = hough_retain(sl.ctx[(size_t)k], kd.pool.x + h0, kd.pool.y + h0, hits, sl.d_peaks, d_npk,
+                                  (uint32_t)cap, d_keep, s);
         }
         if (st != HOUGH_OK) return st;
-        if (hipMemcpyAsync(sl.h_npk, sl.d_npk, n * 4u, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            (hits && hipMemcpyAsync(sl.h_keep, sl.d_keep, hits, hipMemcpyDeviceToHost, s) != hipSuccess) ||
+        if (hipMemcpyAsync(sl.h_out, sl.d_out, 8u * n + hits, hipMemcpyDeviceToHost, s) != hipSuccess ||
             (cfg->copy_peaks && cap &&
              hipMemcpyAsync(sl.h_peaks, sl.d_peaks, n * cap * sizeof(hough_peak), hipMemcpyDeviceToHost, s) != hipSuccess) ||
             hipEventRecord(sl.done, s) != hipSuccess)

@@ -44,6 +44,16 @@ def test_struct_layouts_match_header(hough_mod):
     assert hough_mod.TRACK_DTYPE.names == ("a", "b", "radius", "pt", "phi_c", "charge", "n_hits")
 
 
+def test_serve_config_layout_matches_header():
+    from paper_2607_04067_amd import serve
+    text = open(os.path.join(ROOT, "include", "hough_serve.h")).read()
+    body = re.sub(r"/\*.*?\*/", "", re.search(r"typedef struct hough_serve_config \{(.*?)\}", text, re.S).group(1),
+                  flags=re.S)
+    fields = re.findall(r"\b(int32_t|double)\s+(\w+);", body)
+    assert [n for _, n in fields] == [n for n, _ in serve.hough_serve_config._fields_]
+    assert ctypes.sizeof(serve.hough_serve_config) == 32
+
+
 def test_status_strings(hough_mod):
     for code in (0, -1, -2, -3, -4):
         assert hough_mod.status_string(code) != "unknown status"

@@ -450,10 +450,11 @@ def _serve_pools(H, n_each=48):
     return pools
 
 
-@pytest.mark.parametrize("plain", [False, True])
-def test_served_results_equal_results_alone(H, plain):
+@pytest.mark.parametrize("plain,small", [(False, 0), (False, 64), (True, 0)])
+def test_served_results_equal_results_alone(H, plain, small):
     """Each request's n_peaks, status, keep and peak list in the served mix (continuous
-    batching over several streams) equal the same event processed alone."""
+    batching over several streams, events reordered largest first inside a batch, small
+    batches on the 16-wave shape or not) equal the same event processed alone."""
     import torch
     from paper_2607_04067_amd import serve
     pools = _serve_pools(H)
@@ -461,7 +462,7 @@ def test_served_results_equal_results_alone(H, plain):
                                 [p.batch.n_events for p in pools], [0.5, 0.5], seed=3)
     assert trace.size > 20
     res, keep, peaks = serve.run(pools, trace, n_streams=4, max_batch_events=16, max_batch_hits=40000,
-                                 plain=plain, want_keep=True, want_peaks=16384)
+                                 plain=plain, want_keep=True, want_peaks=16384, small_batch_events=small)
     say(f"served {trace.size} requests plain={plain}: {serve.summarize(trace, res)}")
     off = 0
     alone = {}
