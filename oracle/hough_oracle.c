@@ -33,7 +33,8 @@
  *     t >= 0 and t < n_rho (as float), and then k = (int)t.  Out-of-range votes are dropped.
  *   - peak (j,k): acc[j][k] >= threshold, and for every 8-neighbour inside the grid,
  *     acc[j][k] > neighbour if the neighbour precedes (j,k) in raster order (smaller j, or same
- *     j and smaller k), otherwise acc[j][k] >= neighbour.  No wrap of theta.  Peaks are listed
+ *     j and smaller k), otherwise acc[j][k] >= neighbour.  No wrap of theta (unless the
+ *     theta-periodic topology is asked for: oracle_is_peak_periodic).  Peaks are listed
  *     in raster order.
  *   - keep_i iff hit i is valid and some peak (jp,kp) has k_i(jp) in range with
  *     |k_i(jp) - kp| <= rho_window, k_i(jp) computed with the bin rule above.
@@ -134,14 +135,51 @@ int oracle_is_peak(const int32_t *acc, int n_theta, int n_rho, int threshold, in
     return 1;
 }
 
+/* The 3x3 test on a theta-periodic grid.  With a symmetric rho range the line (theta + pi, rho)
+ * is the line (theta, -rho), so column n_theta - 1 borders column 0 with rho reversed: a
+ * neighbour step across that border from (j, k) to row k + dk lands on row n_rho - 1 - (k + dk)
+ * of the other edge column.  "Earlier in raster order" compares the neighbour's own (j, k);
+ * a cell that reaches itself across the border (n_theta == 1) is skipped. */
+int oracle_is_peak_periodic(const int32_t *acc, int n_theta, int n_rho, int threshold, int j, int k)
+{
+    int32_t c = acc[(size_t)j * n_rho + k];
+    if (c < threshold) return 0;
+    for (int dj = -1; dj <= 1; ++dj) {
+        for (int dk = -1; dk <= 1; ++dk) {
+            if (dj == 0 && dk == 0) continue;
+            int jn = j + dj, kn = k + dk;
+            if (jn < 0) { jn = n_theta - 1; kn = n_rho - 1 - kn; }
+            else if (jn >= n_theta) { jn = 0; kn = n_rho - 1 - kn; }
+            if (kn < 0 || kn >= n_rho) continue;
+            if (jn == j && kn == k) continue;
+            int32_t n = acc[(size_t)jn * n_rho + kn];
+            int precedes = (jn < j) || (jn == j && kn < k);
+            if (precedes) { if (!(c > n)) return 0; }
+            else          { if (!(c >= n)) return 0; }
+        }
+    }
+    return 1;
+}
+
+long oracle_peaks_mode(const int32_t *acc, int n_theta, int n_rho, int threshold, int periodic,
+                       int32_t *pj, int32_t *pk, int32_t *pc, long cap);
+
 /* Peak list in raster order.  Writes at most cap entries, returns the true number of peaks. */
 long oracle_peaks(const int32_t *acc, int n_theta, int n_rho, int threshold,
                   int32_t *pj, int32_t *pk, int32_t *pc, long cap)
 {
+    return oracle_peaks_mode(acc, n_theta, n_rho, threshold, 0, pj, pk, pc, cap);
+}
+
+/* The same list with the 3x3 test of either grid topology (periodic != 0: theta-periodic). */
+long oracle_peaks_mode(const int32_t *acc, int n_theta, int n_rho, int threshold, int periodic,
+                       int32_t *pj, int32_t *pk, int32_t *pc, long cap)
+{
     long n = 0;
     for (int j = 0; j < n_theta; ++j)
         for (int k = 0; k < n_rho; ++k)
-            if (oracle_is_peak(acc, n_theta, n_rho, threshold, j, k)) {
+            if (periodic ? oracle_is_peak_periodic(acc, n_theta, n_rho, threshold, j, k)
+                         : oracle_is_peak(acc, n_theta, n_rho, threshold, j, k)) {
                 if (n < cap) { pj[n] = j; pk[n] = k; pc[n] = acc[(size_t)j * n_rho + k]; }
                 ++n;
             }
@@ -276,7 +314,7 @@ void oracle_track_params(int n_theta, int n_rho, double rho_min, double rho_max,
 int oracle_run_batch(int n_theta, int n_rho, double rho_min, double rho_max, int threshold,
                      int rho_window, const float *x, const float *y, const uint32_t *offsets,
                      long n_events, long cap, int32_t *peaks_out, int64_t *n_peaks_out,
-                     uint8_t *keep, int n_threads)
+                     uint8_t *keep, int n_threads, int periodic)
 {
     float *C = (float *)malloc(sizeof(float) * (size_t)n_theta);
     float *S = (float *)malloc(sizeof(float) * (size_t)n_theta);
@@ -299,7 +337,7 @@ int oracle_run_batch(int n_theta, int n_rho, double rho_min, double rho_max, int
             failed = 1;
         } else {
             oracle_vote(n_theta, n_rho, C, S, Bf, x + a, y + a, h, acc);
-            long np = oracle_peaks(acc, n_theta, n_rho, threshold, pj, pk, pc, max_p);
+            long np = oracle_peaks_mode(acc, n_theta, n_rho, threshold, periodic, pj, pk, pc, max_p);
             oracle_retain(n_rho, C, S, Bf, rho_window, x + a, y + a, h, pj, pk, np, keep + a);
             n_peaks_out[e] = np;
             for (long p = 0; p < np && p < cap; ++p) {

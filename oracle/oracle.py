@@ -67,6 +67,10 @@ def lib():
         L.oracle_is_peak.restype = c_int
         L.oracle_peaks.argtypes = [_i32p, c_int, c_int, c_int, _i32p, _i32p, _i32p, c_long]
         L.oracle_peaks.restype = c_long
+        L.oracle_peaks_mode.argtypes = [_i32p, c_int, c_int, c_int, c_int, _i32p, _i32p, _i32p, c_long]
+        L.oracle_peaks_mode.restype = c_long
+        L.oracle_is_peak_periodic.argtypes = [_i32p, c_int, c_int, c_int, c_int, c_int]
+        L.oracle_is_peak_periodic.restype = c_int
         L.oracle_peaks_iterative.argtypes = [_i32p, c_int, c_int, c_int, c_int, c_int, c_int, c_int,
                                              _i32p, _i32p, _i32p, c_long]
         L.oracle_peaks_iterative.restype = c_long
@@ -78,7 +82,7 @@ def lib():
                                     _i32p, _i32p, c_long, _u8p]
         L.oracle_retain.restype = None
         L.oracle_run_batch.argtypes = [c_int, c_int, c_double, c_double, c_int, c_int, _f32p, _f32p,
-                                       _u32p, c_long, c_long, _i32p, _i64p, _u8p, c_int]
+                                       _u32p, c_long, c_long, _i32p, _i64p, _u8p, c_int, c_int]
         L.oracle_run_batch.restype = c_int
         L.oracle_max_threads.argtypes = []
         L.oracle_max_threads.restype = c_int
@@ -136,13 +140,14 @@ def vote(g: Grid, x, y) -> np.ndarray:
     return acc
 
 
-def peaks(acc: np.ndarray, threshold: int, cap: int | None = None):
-    """All peaks (or the first `cap`) in raster order: (j, k, count) arrays and the true count."""
+def peaks(acc: np.ndarray, threshold: int, cap: int | None = None, periodic: bool = False):
+    """All peaks (or the first `cap`) in raster order: (j, k, count) arrays and the true count.
+    periodic: theta-periodic grid (column n_theta - 1 borders column 0 with rho reversed)."""
     acc = np.ascontiguousarray(acc, dtype=np.int32)
     nt, nr = acc.shape
     cap = nt * nr if cap is None else int(cap)
     pj = np.zeros(max(cap, 1), np.int32); pk = np.zeros_like(pj); pc = np.zeros_like(pj)
-    n = int(lib().oracle_peaks(acc, nt, nr, int(threshold), pj, pk, pc, cap))
+    n = int(lib().oracle_peaks_mode(acc, nt, nr, int(threshold), int(bool(periodic)), pj, pk, pc, cap))
     m = min(n, cap)
     return pj[:m].copy(), pk[:m].copy(), pc[:m].copy(), n
 
@@ -181,9 +186,10 @@ def track_params(g: Grid, x, y, pj, pk, rho_window: int = 1, b_tesla: float = 1.
     return out[:pj.size].copy()
 
 
-def is_peak(acc: np.ndarray, threshold: int, j: int, k: int) -> bool:
+def is_peak(acc: np.ndarray, threshold: int, j: int, k: int, periodic: bool = False) -> bool:
     acc = np.ascontiguousarray(acc, dtype=np.int32)
-    return bool(lib().oracle_is_peak(acc, acc.shape[0], acc.shape[1], int(threshold), int(j), int(k)))
+    f = lib().oracle_is_peak_periodic if periodic else lib().oracle_is_peak
+    return bool(f(acc, acc.shape[0], acc.shape[1], int(threshold), int(j), int(k)))
 
 
 def retain(g: Grid, x, y, pj, pk, rho_window: int = 1) -> np.ndarray:
@@ -195,7 +201,7 @@ def retain(g: Grid, x, y, pj, pk, rho_window: int = 1) -> np.ndarray:
 
 
 def run_batch(wl_or_grid, x, y, offsets, threshold: int | None = None, rho_window: int | None = None,
-              cap: int = 4096, n_threads: int = 1):
+              cap: int = 4096, n_threads: int = 1, periodic: bool = False):
     """Whole path over CSR events.  Returns (peaks[E, cap, 3] as (j, k, count), n_peaks[E], keep[H])."""
     if isinstance(wl_or_grid, Grid):
         g = wl_or_grid
@@ -214,7 +220,7 @@ def run_batch(wl_or_grid, x, y, offsets, threshold: int | None = None, rho_windo
     keep = np.zeros(max(x.size, 1), np.uint8)
     rc = lib().oracle_run_batch(g.n_theta, g.n_rho, g.rho_min, g.rho_max, int(threshold), int(rho_window),
                                 x if x.size else np.zeros(1, np.float32), y if y.size else np.zeros(1, np.float32),
-                                offsets, E, int(cap), out, n_peaks, keep, int(n_threads))
+                                offsets, E, int(cap), out, n_peaks, keep, int(n_threads), int(bool(periodic)))
     if rc != 0:
         raise MemoryError("oracle_run_batch failed")
     return out[:E], n_peaks[:E], keep[:x.size]

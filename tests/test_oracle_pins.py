@@ -597,3 +597,61 @@ def test_track_params_recover_charge_direction_and_pt(orc, q):
         assert tp[3] == pytest.approx(0.299792458 * tp[2] / 1000.0, rel=1e-12)
         # the peak's own hits, counted through the retention rule with that one peak
         assert tp[6] == int(orc.retain(g, x, y, pj[:1], pk[:1], 1).sum())
+
+
+# ------------------------------------------------------- theta-periodic adjacency (a quality variant)
+def test_periodic_peaks_equal_plain_test_on_an_unrolled_grid(orc):
+    """With distinct counts (no ties) the periodic 3x3 test of column j equals the plain test
+    of column j + 1 of the grid extended by column n_theta - 1 reversed in rho on the left and
+    column 0 reversed on the right."""
+    rng = np.random.default_rng(51)
+    for trial in range(40):
+        nt, nr = int(rng.integers(2, 9)), int(rng.integers(1, 9))
+        acc = rng.permutation(nt * nr).astype(np.int32).reshape(nt, nr) + 1
+        ext = np.concatenate([acc[-1:, ::-1], acc, acc[:1, ::-1]], axis=0)
+        for T in (1, nt * nr // 2):
+            for j in range(nt):
+                for k in range(nr):
+                    assert orc.is_peak(acc, T, j, k, periodic=True) == orc.is_peak(ext, T, j + 1, k), (trial, j, k)
+
+
+def test_periodic_interior_columns_are_unchanged(orc):
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    g = orc.Grid.of(wl)
+    acc = orc.vote(g, *synth.make_events(wl, 0, n_events=1).event(0))
+    pj, pk, _, n = orc.peaks(acc, 10)
+    qj, qk, _, m = orc.peaks(acc, 10, periodic=True)
+    inner = lambda a, b: {(j, k) for j, k in zip(a, b) if 0 < j < g.n_theta - 1}
+    assert inner(pj, pk) == inner(qj, qk)
+
+
+def test_periodic_plateau_across_the_border_keeps_the_raster_first_cell(orc):
+    acc = np.zeros((6, 5), np.int32)
+    acc[5, 3] = 9                     # column n_theta - 1, row 3 ...
+    acc[0, 5 - 1 - 3] = 9             # ... borders column 0, row n_rho - 1 - 3 = 1
+    pj, pk, pc, n = orc.peaks(acc, 1, periodic=True)
+    assert list(zip(pj, pk)) == [(0, 1)]
+    pj, pk, pc, n = orc.peaks(acc, 1)                 # without the wrap both are peaks
+    assert list(zip(pj, pk)) == [(0, 1), (5, 3)]
+
+
+def test_periodic_single_track_at_theta_pi_has_one_peak(orc):
+    """A circle whose line lies halfway between the last column and theta = pi votes as much
+    into column n_theta - 1 at rho as into column 0 at -rho: the plain grid reports both ends,
+    the periodic one only the raster-first of the two."""
+    g = orc.Grid(360, 256, -1 / 200, 1 / 200)
+    for k in (170, 180):
+        theta = math.pi - 0.5 * math.pi / g.n_theta
+        rho = g.rho_min + (k + 0.5) * (g.rho_max - g.rho_min) / g.n_rho
+        radius = 1.0 / (2.0 * rho)
+        radii = synth.layer_radii()
+        radii = radii[radii <= 2.0 * radius * (1 - 1e-9)]
+        px, py = synth.circle_points(theta, radius, radii)
+        x, y = px.astype(np.float32), py.astype(np.float32)
+        acc = orc.vote(g, x, y)
+        T = x.size // 2
+        pj, pk, pc, n = orc.peaks(acc, T)
+        qj, qk, qc, m = orc.peaks(acc, T, periodic=True)
+        assert list(zip(pj.tolist(), pk.tolist())) == [(0, g.n_rho - 1 - k), (g.n_theta - 1, k)]
+        assert pc[0] == pc[1]
+        assert list(zip(qj.tolist(), qk.tolist())) == [(0, g.n_rho - 1 - k)]
