@@ -76,7 +76,16 @@ typedef struct hough_params {
     int32_t threshold;   /* minimum peak count, >= 1                                          */
     int32_t rho_window;  /* retention half-width in rho bins, >= 0                            */
     int32_t max_peaks;   /* per-event capacity of hough_run_batch's peak list, >= 0           */
+    int32_t flags;       /* HOUGH_FLAG_* bits, 0 for the plain grid                          */
+    int32_t reserved;    /* must be 0                                                         */
 } hough_params;
+
+/* hough_params.flags: treat theta as periodic in the 3x3 peak test (hough_peaks and the fused
+ * batch kernel): with a symmetric rho range (rho_min == -rho_max) the line (theta + pi, rho) is
+ * (theta, -rho), so column n_theta - 1 borders column 0 with rho reversed (a step across the
+ * border from row k + dk lands on row n_rho - 1 - (k + dk)); raster order still decides ties.
+ * Needs n_theta >= 2.  The iterative finder's suppression window does not wrap. */
+#define HOUGH_FLAG_THETA_PERIODIC 1
 
 /* One peak: grid cell and its count.  8 bytes, no padding. */
 typedef struct hough_peak {

@@ -109,6 +109,9 @@ int hough_config(const hough_params *p, hough_ctx **out) {
     if (!isfinite(p->rho_min) || !isfinite(p->rho_max) || !(p->rho_max > p->rho_min)) return HOUGH_EINVAL;
     if (p->acc_type != HOUGH_ACC_U16 && p->acc_type != HOUGH_ACC_I32) return HOUGH_EINVAL;
     if (p->threshold < 1 || p->rho_window < 0 || p->max_peaks < 0) return HOUGH_EINVAL;
+    if ((p->flags & ~HOUGH_FLAG_THETA_PERIODIC) != 0 || p->reserved != 0) return HOUGH_EINVAL;
+    if ((p->flags & HOUGH_FLAG_THETA_PERIODIC) && (p->n_theta < 2 || p->rho_min != -p->rho_max))
+        return HOUGH_EINVAL;
     const double A = (double)p->n_rho / (p->rho_max - p->rho_min);
     const double B = -p->rho_min * A;
     if (!isfinite(A) || !isfinite(B) || !(fabs(A) < 1e30) || !(fabs(B) < 1e30)) return HOUGH_EINVAL;
@@ -165,6 +168,7 @@ int hough_config(const hough_params *p, hough_ctx **out) {
     g.safe_r2 = safe_radius2(A, B, p->n_rho);
     g.threshold = (uint32_t)p->threshold;
     g.rho_window = p->rho_window < p->n_rho ? p->rho_window : p->n_rho;
+    g.periodic = (p->flags & HOUGH_FLAG_THETA_PERIODIC) ? 1 : 0;
 
     rc = default_plan(c);
     if (rc != HOUGH_OK) {

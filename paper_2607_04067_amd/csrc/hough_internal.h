@@ -26,6 +26,7 @@ struct GridArgs {
     float safe_r2;       // u^2 + v^2 below this: every vote of the hit is in range
     uint32_t threshold;
     int32_t rho_window;
+    int32_t periodic;    // theta-periodic 3x3 test (HOUGH_FLAG_THETA_PERIODIC)
 };
 
 // Launch shape of the fused batch kernel (chosen by the host; see plan_batch()).

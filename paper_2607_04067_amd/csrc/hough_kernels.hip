@@ -57,22 +57,32 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-lane constants of the columns a lane owns in the current tile.
+// Per-lane constants of the columns a lane owns in the current tile.  On a theta-periodic grid
+// the halo column left of column 0 is column n_theta - 1 and the one right of column
+// n_theta - 1 is column 0, both with rho reversed: such a lane votes with that column's own
+// constants into row n_rho - 1 - k, i.e. with a negative row stride from the top row (rs, rb:
+// row stride and base in bytes, used only by the periodic kernels).
 template <int G>
 struct Cols {
     float C[G], S[G], B[G];
+    int rs[G], rb[G];
 };
 
-template <int G>
-__device__ __forceinline__ Cols<G> load_cols(const GridArgs &g, int first_col, int lane) {
+template <int G, bool PER = false>
+__device__ __forceinline__ Cols<G> load_cols(const GridArgs &g, int first_col, int lane, int stride,
+                                             const uint32_t *col) {
     Cols<G> cl;
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         const int j = first_col + 64 * q + lane;
         const bool in = (j >= 0) && (j < g.n_theta);
-        cl.C[q] = in ? g.C[j] : 0.0f;
-        cl.S[q] = in ? g.S[j] : 0.0f;
-        cl.B[q] = in ? g.Bf : g.nrho_f;     // out-of-grid lanes land in the dummy row
+        const bool wrap = PER && (j == -1 || j == g.n_theta);
+        const int jw = j < 0 ? g.n_theta - 1 : 0;
+        cl.C[q] = in ? g.C[j] : (wrap ? g.C[jw] : 0.0f);
+        cl.S[q] = in ? g.S[j] : (wrap ? g.S[jw] : 0.0f);
+        cl.B[q] = (in || wrap) ? g.Bf : g.nrho_f;   // out-of-grid lanes land in the dummy row
+        cl.rs[q] = 4 * (wrap ? -stride : stride);                                    // bytes
+        cl.rb[q] = 4 * (wrap ? (g.n_rho - 1) * stride + (int)col[q] : (int)col[q]);
     }
     return cl;
 }
@@ -134,25 +144,35 @@ __device__ __forceinline__ StageCount stage_hits(float2 *st, const float *x,
 }
 
 // Steps 2-3: sweep one staged hit through the lane's columns and vote.
-template <int G, bool P>
+// The lane's cell of row k in group q.  Periodic kernels use the per-lane row stride (a 24-bit
+// multiply-add, full rate) so that the reversed halo lanes need no other instruction.
+template <int G, bool P, bool PER = false>
+__device__ __forceinline__ uint32_t *cell_of(uint32_t *tile, int k, const Cols<G> &cl, const Lane<G, P> &ln,
+                                             int q) {
+    if (PER)
+        return reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(tile) + (__mul24(k, cl.rs[q]) + cl.rb[q]));
+    return &tile[k * Lane<G, P>::STRIDE + (int)ln.col[q]];
+}
+
+template <int G, bool P, bool PER = false>
 __device__ __forceinline__ void vote1(uint32_t *tile, float u, float v, const Cols<G> &cl,
                                       const Lane<G, P> &ln) {
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         const float w = __builtin_fmaf(v, cl.S[q], cl.B[q]);
         const float t = __builtin_fmaf(u, cl.C[q], w);
-        lds_add(&tile[(int)t * Lane<G, P>::STRIDE + ln.col[q]], ln.inc);
+        lds_add(cell_of<G, P, PER>(tile, (int)t, cl, ln, q), ln.inc);
     }
 }
 
 // Four staged hits, one vote each per column.
-template <int G, bool P>
+template <int G, bool P, bool PER = false>
 __device__ __forceinline__ void vote4(uint32_t *tile, const float4 &a, const float4 &b,
                                       const Cols<G> &cl, const Lane<G, P> &ln) {
-    vote1<G, P>(tile, a.x, a.y, cl, ln);
-    vote1<G, P>(tile, a.z, a.w, cl, ln);
-    vote1<G, P>(tile, b.x, b.y, cl, ln);
-    vote1<G, P>(tile, b.z, b.w, cl, ln);
+    vote1<G, P, PER>(tile, a.x, a.y, cl, ln);
+    vote1<G, P, PER>(tile, a.z, a.w, cl, ln);
+    vote1<G, P, PER>(tile, b.x, b.y, cl, ln);
+    vote1<G, P, PER>(tile, b.z, b.w, cl, ln);
 }
 
 // Wait for every outstanding LDS operation of the wave (lgkmcnt(0), other counters untouched).
@@ -166,7 +186,7 @@ __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0
 // issued before the atomics of group c, and LDS operations complete in order, so the votes of
 // group c + 1 wait only for operations issued before the atomics of group c: a wave never
 // waits for its latest atomics.  The fences keep the compiler from reordering the groups.
-template <int G, bool P>
+template <int G, bool P, bool PER = false>
 __device__ __forceinline__ void vote_staged(uint32_t *tile, const float2 *st, StageCount n,
                                             const Cols<G> &cl, const Lane<G, P> &ln, float nrho_f) {
     const float4 *st4 = reinterpret_cast<const float4 *>(st);
@@ -178,35 +198,35 @@ __device__ __forceinline__ void vote_staged(uint32_t *tile, const float2 *st, St
         for (; c + 2 < n4; c += 2) {
             const float4 a1 = st4[2 * c + 2], b1 = st4[2 * c + 3];
             sched_fence();
-            vote4<G, P>(tile, a0, b0, cl, ln);
+            vote4<G, P, PER>(tile, a0, b0, cl, ln);
             sched_fence();
             a0 = st4[2 * c + 4];
             b0 = st4[2 * c + 5];
             sched_fence();
-            vote4<G, P>(tile, a1, b1, cl, ln);
+            vote4<G, P, PER>(tile, a1, b1, cl, ln);
             sched_fence();
         }
-        vote4<G, P>(tile, a0, b0, cl, ln);
+        vote4<G, P, PER>(tile, a0, b0, cl, ln);
         if (c + 1 < n4) {
             const float4 a1 = st4[2 * c + 2], b1 = st4[2 * c + 3];
-            vote4<G, P>(tile, a1, b1, cl, ln);
+            vote4<G, P, PER>(tile, a1, b1, cl, ln);
         }
     }
-    for (uint32_t h = n4 * 4; h < n.safe; ++h) vote1<G, P>(tile, st[h].x, st[h].y, cl, ln);
+    for (uint32_t h = n4 * 4; h < n.safe; ++h) vote1<G, P, PER>(tile, st[h].x, st[h].y, cl, ln);
     for (uint32_t h = n.safe; h < n.total; ++h) {
         const float2 p = st[h];
 #pragma unroll
         for (int q = 0; q < G; ++q) {
             const float w = __builtin_fmaf(p.y, cl.S[q], cl.B[q]);
             const float t = __builtin_fmaf(p.x, cl.C[q], w);
-            if (t >= 0.0f && t < nrho_f) lds_add(&tile[(int)t * Lane<G, P>::STRIDE + ln.col[q]], ln.inc);
+            if (t >= 0.0f && t < nrho_f) lds_add(cell_of<G, P, PER>(tile, (int)t, cl, ln, q), ln.inc);
         }
     }
 }
 
 // Votes of hits [hb, he); returns the number of valid hits seen.  The next 64 hits are loaded
 // while the current ones vote.
-template <int G, bool P>
+template <int G, bool P, bool PER = false>
 __device__ uint32_t vote_range(uint32_t *tile, float2 *st, const float *x, const float *y,
                                uint32_t hb, uint32_t he, const Cols<G> &cl, const Lane<G, P> &ln,
                                const GridArgs &g, int lane, uint32_t &bad) {
@@ -220,7 +240,7 @@ __device__ uint32_t vote_range(uint32_t *tile, float2 *st, const float *x, const
         int slot;
         const StageCount n = stage_values(st, xi, yi, i < he, g, bad, slot);
         n_valid += n.total;
-        vote_staged<G, P>(tile, st, n, cl, ln, g.nrho_f);
+        vote_staged<G, P, PER>(tile, st, n, cl, ln, g.nrho_f);
         wave_sync();
     }
     return n_valid;
@@ -249,9 +269,13 @@ __device__ __forceinline__ uint32_t cell_or_zero(const uint32_t *tile, int k, in
     return (k >= 0 && k < n_rho) ? ln.count(d) : 0u;
 }
 
-template <bool CHECK, int G, bool P>
+// WRAP (theta-periodic grid, first and last tile): the halo column beside column 0 is column
+// n_theta - 1 and follows it in raster order, the one beside column n_theta - 1 is column 0 and
+// precedes it, so for those two lanes the strict and the non-strict side trade places.
+template <bool CHECK, int G, bool P, bool WRAP = false>
 __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_rho, uint32_t T,
-                                          const Lane<G, P> &ln, int lane, uint32_t *mask) {
+                                          const Lane<G, P> &ln, int lane, uint32_t *mask,
+                                          int first_col = 0, int n_theta = 0) {
     const int k0 = unit * kPeakRows;
     uint32_t Mp[G], Mc[G];
 #pragma unroll
@@ -295,8 +319,16 @@ __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_
                     const uint32_t x = __builtin_amdgcn_readlane(V[q + 1 < G ? q + 1 : 0], 0);
                     VR = lane == 63 ? x : VR;
                 }
-                const uint32_t before = max(VL, Mp[q]);
-                const uint32_t after = max(VR, N[q][d]);
+                uint32_t before, after;
+                if (WRAP) {
+                    const int j = first_col + 64 * q + lane;
+                    const bool wl = j == 0, wr = j == n_theta - 1;
+                    before = max(max(wl ? 0u : VL, wr ? VR : 0u), Mp[q]);
+                    after = max(max(wl ? VL : 0u, wr ? 0u : VR), N[q][d]);
+                } else {
+                    before = max(VL, Mp[q]);
+                    after = max(VR, N[q][d]);
+                }
                 const uint32_t need = max(max(T, before + 1u), after);
                 mask[q] |= (uint32_t)((!CHECK || k < n_rho) && Mc[q] >= need) << (r0 + d);
             }
@@ -540,7 +572,7 @@ __global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__res
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int first = blockIdx.x * 64;
     const L ln(lane);
-    const Cols<1> cl = load_cols<1>(g, first, lane);
+    const Cols<1> cl = load_cols<1>(g, first, lane, L::STRIDE, ln.col);
     const int j = first + lane;
     const int kb = (int)((int64_t)g.n_rho * wave / NW), ke = (int)((int64_t)g.n_rho * (wave + 1) / NW);
     uint32_t bad = 0;
@@ -592,19 +624,26 @@ __global__ __launch_bounds__(NW * 64) void k_peaks(GridArgs g, const T *__restri
     for (int jb = 0; jb < g.n_theta; jb += NW) {
         for (int idx = threadIdx.x; idx < (NW + 2) * nr; idx += NW * 64) {
             const int r = idx / nr, k = idx - r * nr, jj = jb - 1 + r;
-            rows[idx] = (jj >= 0 && jj < g.n_theta) ? (uint32_t)acc[(size_t)jj * nr + k] : 0u;
+            uint32_t v = 0u;
+            if (jj >= 0 && jj < g.n_theta) v = (uint32_t)acc[(size_t)jj * nr + k];
+            else if (g.periodic && (jj == -1 || jj == g.n_theta))   // the other edge, rho reversed
+                v = (uint32_t)acc[(size_t)(jj < 0 ? g.n_theta - 1 : 0) * nr + (nr - 1 - k)];
+            rows[idx] = v;
         }
         __syncthreads();
         const int j = jb + wave;
         const uint32_t *up = rows + wave * nr, *mid = up + nr, *dn = mid + nr;
+        // on a periodic grid the row above column 0 is column n_theta - 1 (later in raster order)
+        // and the row below column n_theta - 1 is column 0 (earlier)
+        const bool up_later = g.periodic && j == 0, dn_earlier = g.periodic && j == g.n_theta - 1;
         uint32_t cnt = 0;
         auto is_peak = [&](int k) -> bool {
             const uint32_t c = mid[k];
             const uint32_t l = k > 0 ? 1u : 0u, r = k + 1 < nr ? 1u : 0u;
-            const uint32_t before = max(max(l ? up[k - 1] : 0u, up[k]),
-                                        max(r ? up[k + 1] : 0u, l ? mid[k - 1] : 0u));
-            const uint32_t after = max(max(r ? mid[k + 1] : 0u, l ? dn[k - 1] : 0u),
-                                       max(dn[k], r ? dn[k + 1] : 0u));
+            const uint32_t u3 = max(max(l ? up[k - 1] : 0u, up[k]), r ? up[k + 1] : 0u);
+            const uint32_t d3 = max(max(l ? dn[k - 1] : 0u, dn[k]), r ? dn[k + 1] : 0u);
+            const uint32_t before = max(max(up_later ? 0u : u3, dn_earlier ? d3 : 0u), l ? mid[k - 1] : 0u);
+            const uint32_t after = max(max(up_later ? u3 : 0u, dn_earlier ? 0u : d3), r ? mid[k + 1] : 0u);
             return c >= max(max(g.threshold, before + 1u), after);
         };
         if (j < g.n_theta) {
@@ -936,7 +975,7 @@ __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__r
 // queue[0] is the work counter and queue[1] counts workgroups that have left the loop; the
 // last one to leave (every pop has then happened) puts both back to zero for the next launch,
 // so a launch is a single kernel with no memset.
-template <int NW, int G>
+template <int NW, int G, bool PER>
 __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, BatchArgs a, int n_tiles, int nwords) {
     using L = Lane<G, true>;
     constexpr int TW = L::TW, ST = L::STRIDE, OUT = TW - 2, NT = NW * 64;
@@ -1010,16 +1049,23 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
         pd.on = false;
         for (int t = 0; t < n_tiles; ++t) {
             const int first = t * OUT - 1;      // grid column of lane 0 of group 0
-            const Cols<G> cl = load_cols<G>(g, first, lane);
-            const uint32_t nv = vote_range<G, true>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad);
+            const Cols<G> cl = load_cols<G, PER>(g, first, lane, ST, ln.col);
+            const uint32_t nv = vote_range<G, true, PER>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad);
             if (t == 0 && lane == 0 && nv) atomicAdd(&s_nvalid, nv);
             __syncthreads();
             for (int u = wave; u < 2 * nwords; u += NW) {
                 uint32_t m[G];
-                if (u >= 1 && (u + 1) * kPeakRows < g.n_rho)
+                const bool interior = u >= 1 && (u + 1) * kPeakRows < g.n_rho;
+                if (PER && (t == 0 || t == n_tiles - 1)) {
+                    if (interior)
+                        peak_rows<false, G, true, true>(tile, u, g.n_rho, g.threshold, ln, lane, m, first, g.n_theta);
+                    else
+                        peak_rows<true, G, true, true>(tile, u, g.n_rho, g.threshold, ln, lane, m, first, g.n_theta);
+                } else if (interior) {
                     peak_rows<false, G, true>(tile, u, g.n_rho, g.threshold, ln, lane, m);
-                else
+                } else {
                     peak_rows<true, G, true>(tile, u, g.n_rho, g.threshold, ln, lane, m);
+                }
                 uint16_t *pm16 = reinterpret_cast<uint16_t *>(pmask);
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
@@ -1196,8 +1242,12 @@ template <int NW, int G>
 static hipError_t launch_batch_t(const GridArgs &g, const BatchPlan &p, const BatchArgs &a,
                                  hipStream_t s) {
     const int nwords = (g.n_rho + 31) / 32;
-    hipLaunchKernelGGL((k_batch<NW, G>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
-                       p.n_tiles, nwords);
+    if (g.periodic)
+        hipLaunchKernelGGL((k_batch<NW, G, true>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
+                           p.n_tiles, nwords);
+    else
+        hipLaunchKernelGGL((k_batch<NW, G, false>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
+                           p.n_tiles, nwords);
     return hipGetLastError();
 }
 
@@ -1217,10 +1267,14 @@ hipError_t launch_batch(const GridArgs &g, const BatchPlan &p, const BatchArgs &
 
 template <int NW, int G>
 static int prepare_t(size_t lds, size_t) {
-    allow_lds(k_batch<NW, G>);
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<NW, G>, NW * 64, lds) != hipSuccess) return 0;
-    return n;
+    // both grid topologies: a context's plan serves whichever kernel its grid launches
+    allow_lds(k_batch<NW, G, false>);
+    allow_lds(k_batch<NW, G, true>);
+    int n = 0, m = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<NW, G, false>, NW * 64, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_batch<NW, G, true>, NW * 64, lds) != hipSuccess)
+        return 0;
+    return n < m ? n : m;
 }
 
 // Allow the plan's dynamic LDS for its kernel and return how many of its workgroups fit a CU

@@ -38,7 +38,11 @@ class hough_params(ctypes.Structure):
     _fields_ = [("n_theta", ctypes.c_int32), ("n_rho", ctypes.c_int32),
                 ("rho_min", ctypes.c_double), ("rho_max", ctypes.c_double),
                 ("acc_type", ctypes.c_int32), ("threshold", ctypes.c_int32),
-                ("rho_window", ctypes.c_int32), ("max_peaks", ctypes.c_int32)]
+                ("rho_window", ctypes.c_int32), ("max_peaks", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+FLAG_THETA_PERIODIC = 1
 
 
 _lib = None
@@ -148,11 +152,12 @@ class Context:
     """One configured (theta, rho) grid on the current GPU (wraps hough_ctx)."""
 
     def __init__(self, n_theta: int, n_rho: int, rho_min: float, rho_max: float, acc_type: str = "i32",
-                 threshold: int = 1, rho_window: int = 1, max_peaks: int = 0):
+                 threshold: int = 1, rho_window: int = 1, max_peaks: int = 0, periodic: bool = False):
         self._lib = load()
         self.params = hough_params(int(n_theta), int(n_rho), float(rho_min), float(rho_max),
                                    ACC_U16 if acc_type == "u16" else ACC_I32, int(threshold),
-                                   int(rho_window), int(max_peaks))
+                                   int(rho_window), int(max_peaks),
+                                   FLAG_THETA_PERIODIC if periodic else 0, 0)
         self.acc_type = acc_type
         self._ctx = ctypes.c_void_p()
         _check(self._lib.hough_config(ctypes.byref(self.params), ctypes.byref(self._ctx)), "hough_config")
@@ -160,10 +165,10 @@ class Context:
 
     @classmethod
     def for_workload(cls, wl, max_peaks: int = 4096, threshold: int | None = None,
-                     rho_window: int | None = None) -> "Context":
+                     rho_window: int | None = None, periodic: bool = False) -> "Context":
         return cls(wl.n_theta, wl.n_rho, wl.rho_min, wl.rho_max, wl.acc,
                    wl.threshold if threshold is None else threshold,
-                   wl.rho_window if rho_window is None else rho_window, max_peaks)
+                   wl.rho_window if rho_window is None else rho_window, max_peaks, periodic)
 
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx.value:

@@ -31,9 +31,12 @@ def test_library_exports_every_declared_function(hough_mod):
 
 
 def test_struct_layouts_match_header(hough_mod):
-    # hough_params: 2 x int32, 2 x double, 4 x int32 = 40 bytes; hough_peak: 8 bytes
-    assert ctypes.sizeof(hough_mod.hough_params) == 40
     text = open(os.path.join(ROOT, "include", "hough.h")).read()
+    # hough_params: 2 x int32, 2 x double, 6 x int32 = 48 bytes; hough_peak: 8 bytes
+    assert ctypes.sizeof(hough_mod.hough_params) == 48
+    params = re.sub(r"/\*.*?\*/", "", re.search(r"typedef struct hough_params \{(.*?)\}", text, re.S).group(1),
+                    flags=re.S)
+    assert re.findall(r"\b(?:int32_t|double)\s+(\w+)", params) == [n for n, _ in hough_mod.hough_params._fields_]
     peak = re.search(r"typedef struct hough_peak \{(.*?)\}", text, re.S).group(1)
     assert re.findall(r"(uint\d+_t)", peak) == ["uint16_t", "uint16_t", "uint32_t"]
     # hough_track: five doubles, int32 charge, uint32 n_hits = 48 bytes, as decode_tracks reads it

@@ -612,3 +612,66 @@ def test_track_params_parity(H, orc, name, finder):
         for i, f in enumerate(("a", "b", "radius", "pt", "phi_c")):
             np.testing.assert_allclose(got[f], ref[:, i], rtol=1e-12, atol=1e-9, err_msg=f)
     ctx.close()
+
+
+# --------------------------------------------------------------------- theta-periodic adjacency
+def _theta_pi_track(g, k):
+    """Circle whose line lies halfway between the last column and theta = pi (both edges vote)."""
+    import math
+    theta = math.pi - 0.5 * math.pi / g.n_theta
+    rho = g.rho_min + (k + 0.5) * (g.rho_max - g.rho_min) / g.n_rho
+    radius = 1.0 / (2.0 * rho)
+    radii = synth.layer_radii()
+    radii = radii[radii <= 2.0 * radius * (1 - 1e-9)]
+    px, py = synth.circle_points(theta, radius, radii)
+    return px.astype(np.float32), py.astype(np.float32)
+
+
+@pytest.mark.parametrize("n_theta,n_rho", [(360, 256), (62, 64), (63, 100), (2, 16), (125, 7), (720, 512)])
+def test_periodic_grid_plain_and_batch(H, orc, n_theta, n_rho):
+    import torch
+    lo, hi = -1 / 200, 1 / 200
+    g = orc.Grid(n_theta, n_rho, lo, hi)
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    ev = synth.make_events(wl, 6, n_events=3)
+    xs = [ev.event(e) for e in range(ev.n_events)]
+    if n_theta >= 100:
+        xs.append(_theta_pi_track(g, int(n_rho * 0.66)))
+    x = np.concatenate([a for a, _ in xs]); y = np.concatenate([b for _, b in xs])
+    offsets = np.zeros(len(xs) + 1, np.uint32)
+    offsets[1:] = np.cumsum([a.size for a, _ in xs])
+    for T in (3, 12):
+        ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, 1, 20000, periodic=True)
+        say(f"periodic grid {n_theta}x{n_rho} T={T}")
+        for e, (xe, ye) in enumerate(xs):                       # plain path
+            acc = ctx.vote(_t(xe), _t(ye))
+            pk, npk = ctx.peaks(acc, 20000)
+            torch.cuda.synchronize()
+            rj, rk, rc, n = orc.peaks(orc.vote(g, xe, ye), T, periodic=True)
+            assert int(npk.item()) == n, (e, T)
+            assert np.array_equal(H.decode_peaks(pk, n), np.stack([rj, rk, rc], 1).astype(np.int64))
+        for groups in (1, 2):                                   # fused batch path
+            try:
+                ctx.set_batch_plan(8, groups, 0)
+            except H.HoughError:
+                continue
+            xt, yt, ot = _t(x), _t(y), _t(offsets.astype(np.int32))
+            peaks, npk, keep, st = ctx.run_batch(xt, yt, ot)
+            torch.cuda.synchronize()
+            pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, offsets, threshold=T, rho_window=1, cap=20000,
+                                                    n_threads=8, periodic=True)
+            assert np.array_equal(npk.cpu().numpy()[:len(xs)].astype(np.int64), n_ref)
+            assert np.array_equal(keep.cpu().numpy()[:x.size], keep_ref)
+            p = peaks.cpu().numpy()
+            for e in range(len(xs)):
+                m = int(n_ref[e])
+                assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), (groups, e)
+        ctx.close()
+
+
+def test_periodic_needs_a_symmetric_range_and_two_columns(H):
+    with pytest.raises(H.HoughError):
+        H.Context(360, 256, -0.004, 0.005, "i32", 3, 1, 16, periodic=True)
+    with pytest.raises(H.HoughError):
+        H.Context(1, 256, -0.005, 0.005, "i32", 3, 1, 16, periodic=True)
+    H.Context(2, 256, -0.005, 0.005, "i32", 3, 1, 16, periodic=True).close()
