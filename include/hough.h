@@ -10,7 +10,9 @@
  *   4. threshold + 3x3 local-maximum peaks, returned in raster order            [Sec. II]
  *   5. the retention mask: a hit is kept when it lies within rho_window rho bins
  *      of a peak at the peak's own theta                                       [Sec. I, Sec. II]
- * An event is the point set of hit wire positions {(x_i, y_i)} of Sec. II.
+ * An event is the point set of hit wire positions {(x_i, y_i)} of Sec. II.  Beside them:
+ * the paper's own peak finder (relative threshold and iterative extraction, Sec. II) and the
+ * candidate circles / track parameters of a peak list (Eq. (2)).
  *
  * Exact rules (every result is an integer and is reproduced bit for bit by the CPU oracle):
  *   - theta_j = (j * pi) / n_theta in double (lower bin edge), j = 0 .. n_theta-1.
@@ -23,15 +25,18 @@
  *   - acc[j][k] = number of valid hits whose bin in column j is k.
  *   - (j, k) is a peak iff acc[j][k] >= threshold and, for each of its 8 neighbours inside the
  *     grid, acc[j][k] > neighbour when the neighbour comes first in raster order (smaller j,
- *     or equal j and smaller k) and acc[j][k] >= neighbour otherwise.  theta does not wrap.
+ *     or equal j and smaller k) and acc[j][k] >= neighbour otherwise.  theta does not wrap
+ *     unless the context asks for it (HOUGH_FLAG_THETA_PERIODIC).
  *   - keep_i = 1 iff hit i is valid and some peak (jp, kp) has hit i's bin in column jp in
  *     range with |bin - kp| <= rho_window.
  *
  * Memory and streams: every array argument is a DEVICE pointer owned by the caller (for
  * instance torch tensors' data pointers).  `stream` is a hipStream_t (NULL = the default
  * stream).  Calls are asynchronous: HOUGH_OK means "validated and enqueued".  A context owns its
- * constant tables and a small device workspace; calls that share a context must be ordered on
- * one stream (they share the workspace) and one host thread at a time may use a context.
+ * constant tables and a small device workspace on the device that was current when it was
+ * configured; calls must be made with that device current (HOUGH_EINVAL otherwise), calls
+ * that share a context must be ordered on one stream (they share the workspace) and one host
+ * thread at a time may use a context.
  * No call allocates device memory after hough_config, and none synchronises the device, so
  * the calls may be captured into a HIP graph.
  *

@@ -75,6 +75,12 @@ int default_plan(hough_ctx *c) {
     return HOUGH_OK;
 }
 
+// A context's tables and workspace live on the device it was configured on.
+bool on_device(const hough_ctx *c) {
+    int dev = -1;
+    return hipGetDevice(&dev) == hipSuccess && dev == c->device;
+}
+
 }  // namespace
 
 extern "C" {
@@ -221,6 +227,7 @@ int hough_set_batch_plan(hough_ctx *c, int32_t waves_per_group, int32_t column_g
 
 int hough_vote(hough_ctx *c, const float *x, const float *y, uint32_t n_hits, void *acc, void *stream) {
     if (!c || !acc) return HOUGH_EINVAL;
+    if (!on_device(c)) return HOUGH_EINVAL;
     if (n_hits && (!x || !y)) return HOUGH_EINVAL;
     if (c->p.acc_type == HOUGH_ACC_U16 && n_hits > 65535u) return HOUGH_EOVERFLOW;
     const hipError_t e = hough::launch_vote(c->g, x, y, n_hits, acc, c->p.acc_type, (hipStream_t)stream);
@@ -230,6 +237,7 @@ int hough_vote(hough_ctx *c, const float *x, const float *y, uint32_t n_hits, vo
 int hough_peaks(hough_ctx *c, const void *acc, hough_peak *peaks, uint32_t cap, uint32_t *n_peaks,
                 void *stream) {
     if (!c || !acc || !n_peaks || (cap && !peaks)) return HOUGH_EINVAL;
+    if (!on_device(c)) return HOUGH_EINVAL;
     if (((uintptr_t)peaks & 7u) != 0) return HOUGH_EINVAL;
     const hipError_t e = hough::launch_peaks(c->g, acc, c->p.acc_type, peaks, cap, n_peaks,
                                              (hipStream_t)stream);
@@ -240,6 +248,7 @@ int hough_peaks_iterative(hough_ctx *c, const void *acc, uint32_t frac_num, uint
                           int32_t r_theta, int32_t r_rho, hough_peak *peaks, uint32_t cap,
                           uint32_t *n_peaks, uint32_t *status, void *stream) {
     if (!c || !acc || !n_peaks || !status || (cap && !peaks)) return HOUGH_EINVAL;
+    if (!on_device(c)) return HOUGH_EINVAL;
     if (frac_den == 0 || r_theta < 0 || r_rho < 0) return HOUGH_EINVAL;
     if (((uintptr_t)peaks & 7u) != 0) return HOUGH_EINVAL;
     if (hough::peaks_iterative_lds_bytes() > c->lds_limit) return HOUGH_EDEVICE;
@@ -255,6 +264,7 @@ int hough_track_params(hough_ctx *c, const float *x, const float *y, uint32_t n_
                        const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
                        double b_tesla, hough_track *tracks, void *stream) {
     if (!c || !n_peaks || (cap && (!peaks || !tracks))) return HOUGH_EINVAL;
+    if (!on_device(c)) return HOUGH_EINVAL;
     if (n_hits && (!x || !y)) return HOUGH_EINVAL;
     if (((uintptr_t)peaks & 7u) != 0 || ((uintptr_t)tracks & 7u) != 0) return HOUGH_EINVAL;
     if (!isfinite(b_tesla)) return HOUGH_EINVAL;
@@ -267,6 +277,7 @@ int hough_retain(hough_ctx *c, const float *x, const float *y, uint32_t n_hits,
                  const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap, uint8_t *keep,
                  void *stream) {
     if (!c || !n_peaks || (cap && !peaks)) return HOUGH_EINVAL;
+    if (!on_device(c)) return HOUGH_EINVAL;
     if (n_hits && (!x || !y || !keep)) return HOUGH_EINVAL;
     if (((uintptr_t)peaks & 7u) != 0) return HOUGH_EINVAL;
     const hipError_t e = hough::launch_retain(c->g, x, y, n_hits, peaks, n_peaks, cap, keep,
@@ -279,6 +290,7 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
                             hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
                             void *stream) {
     if (!c) return HOUGH_EINVAL;
+    if (!on_device(c)) return HOUGH_EINVAL;
     if (n_events == 0) return HOUGH_OK;
     if (!x || !y || !offsets || !n_peaks || !keep || !status) return HOUGH_EINVAL;
     if (c->p.max_peaks > 0 && !peaks) return HOUGH_EINVAL;

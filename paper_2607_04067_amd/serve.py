@@ -99,13 +99,17 @@ def run(pools, trace: np.ndarray, n_streams: int = 8, max_batch_events: int = 25
 
 
 def summarize(trace: np.ndarray, res: np.ndarray, warmup_us: float = 0.0) -> dict:
-    """p50/p99 latency (done - scheduled arrival) and sustained rate over the measured window."""
+    """p50/p99 latency (done - scheduled arrival), its split into waiting for a launch and the
+    launch-to-results service time, and the sustained rate over the measured window."""
     sel = trace["arrival_us"] >= warmup_us
     if not sel.any():
         return {}
     lat = res["done_us"][sel] - trace["arrival_us"][sel]
+    wait = res["launch_us"][sel] - trace["arrival_us"][sel]
     span = (res["done_us"][sel].max() - trace["arrival_us"][sel].min()) / 1e6
     return {"requests": int(sel.sum()), "p50_us": round(float(np.percentile(lat, 50)), 1),
             "p99_us": round(float(np.percentile(lat, 99)), 1), "max_us": round(float(lat.max()), 1),
+            "p50_wait_us": round(float(np.percentile(wait, 50)), 1),
+            "p50_service_us": round(float(np.percentile(lat - wait, 50)), 1),
             "events_per_s": round(float(sel.sum() / span), 1) if span > 0 else None,
             "mean_batch": round(float(res["batch_events"][sel].mean()), 2)}
