@@ -47,6 +47,7 @@
 #ifndef HOUGH_H
 #define HOUGH_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -197,6 +198,23 @@ int hough_run_batch_gather(hough_ctx *ctx, const float *x, const float *y, const
                            const uint32_t *event_ids, const uint32_t *keep_offsets,
                            uint32_t n_events, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
                            uint32_t *status, void *stream);
+
+/* The latency form of hough_run_batch / hough_run_batch_gather: the same outputs (bit for bit),
+ * but each (event, theta tile) pair is a work item of its own, so the tiles of one event run on
+ * different workgroups at once and a small batch finishes sooner (each tile examines the hits
+ * the others have not kept yet, so a large batch finishes later than with hough_run_batch).
+ * event_ids and keep_offsets are both NULL (events are offsets' own, keep indexed like x) or
+ * both given (gather form).  workspace: device buffer of at least
+ * hough_split_workspace_bytes(ctx, n_events) bytes, 256-byte aligned, filled with zeros before
+ * its first use; every call leaves it zero again.  Calls sharing a workspace must be ordered. */
+int hough_run_batch_split(hough_ctx *ctx, const float *x, const float *y, const uint32_t *offsets,
+                          const uint32_t *event_ids, const uint32_t *keep_offsets, uint32_t n_events,
+                          hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes hough_run_batch_split needs for n_events events with the context's current
+ * launch shape (0 for a NULL context). */
+size_t hough_split_workspace_bytes(const hough_ctx *ctx, uint32_t n_events);
 
 /* Launch shape of hough_run_batch's fused kernel.  A theta tile is 64 * column_groups columns
  * (two of them halo columns shared with the neighbouring tiles); the hits of an event are split

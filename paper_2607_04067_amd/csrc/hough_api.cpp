@@ -288,7 +288,8 @@ int hough_retain(hough_ctx *c, const float *x, const float *y, uint32_t n_hits,
 static int run_batch_common(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,
                             const uint32_t *ids, const uint32_t *keep_offsets, uint32_t n_events,
                             hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
-                            void *stream) {
+                            void *stream, bool split = false, void *workspace = nullptr,
+                            size_t workspace_bytes = 0) {
     if (!c) return HOUGH_EINVAL;
     if (!on_device(c)) return HOUGH_EINVAL;
     if (n_events == 0) return HOUGH_OK;
@@ -312,7 +313,20 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     a.status = status;
     a.max_peaks = (uint32_t)c->p.max_peaks;
     a.queue = c->d_work;
-    const hipError_t e = hough::launch_batch(c->g, plan, a, (hipStream_t)stream);
+    hipError_t e;
+    if (split) {
+        hough::SplitArgs sp;
+        if (!hough::split_layout(c->p.n_theta, c->p.n_rho, c->plan.groups, n_events, workspace, workspace_bytes,
+                                 &sp))
+            return HOUGH_EINVAL;
+        const long items = (long)n_events * sp.n_tiles;
+        if (items >= (1L << 31)) return HOUGH_EINVAL;      // the work queue counts in 32 bits
+        long g2 = (long)c->plan.per_cu * c->n_cu;
+        plan.grid = (int)(g2 < items ? g2 : items);
+        e = hough::launch_batch_split(c->g, plan, a, sp, (hipStream_t)stream);
+    } else {
+        e = hough::launch_batch(c->g, plan, a, (hipStream_t)stream);
+    }
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
 }
 
@@ -330,6 +344,21 @@ int hough_run_batch_gather(hough_ctx *c, const float *x, const float *y, const u
     if (n_events && (!event_ids || !keep_offsets)) return HOUGH_EINVAL;
     return run_batch_common(c, x, y, offsets, event_ids, keep_offsets, n_events, peaks, n_peaks,
                             keep, status, stream);
+}
+
+size_t hough_split_workspace_bytes(const hough_ctx *c, uint32_t n_events) {
+    if (!c) return 0;
+    return hough::split_workspace_bytes(c->p.n_theta, c->p.n_rho, c->plan.groups, n_events);
+}
+
+int hough_run_batch_split(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,
+                          const uint32_t *event_ids, const uint32_t *keep_offsets, uint32_t n_events,
+                          hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
+                          void *workspace, size_t workspace_bytes, void *stream) {
+    if (n_events && ((event_ids == nullptr) != (keep_offsets == nullptr))) return HOUGH_EINVAL;
+    if (n_events && !workspace) return HOUGH_EINVAL;
+    return run_batch_common(c, x, y, offsets, event_ids, keep_offsets, n_events, peaks, n_peaks, keep,
+                            status, stream, true, workspace, workspace_bytes);
 }
 
 }  // extern "C"

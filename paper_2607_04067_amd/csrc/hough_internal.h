@@ -56,6 +56,22 @@ struct BatchArgs {
     uint32_t *queue;     // [2] work counter and exit counter (device, zero between launches)
 };
 
+// Workspace of the split form (one workgroup per theta tile of an event), laid out by
+// split_layout() in the caller's buffer.  Everything in it is zero between launches.
+struct SplitArgs {
+    uint32_t n_tiles;
+    uint32_t tile_cap;       // most peaks one tile can hold (no two peaks are 8-adjacent)
+    uint32_t *counts;        // [n_events * n_tiles] peaks listed by each tile
+    hough_peak *staged;      // [n_events * n_tiles * tile_cap] each tile's list, raster order
+    uint32_t *kept;          // [n_events * kSplitKeepWords] keep bits of each event's hits
+    uint32_t *done;          // [n_events] tiles finished; the last one merges
+    uint32_t *flags;         // [n_events] HOUGH_EV_* bits seen by the tiles
+};
+constexpr uint32_t kSplitKeepWords = (kMaxBatchHits + 31) / 32 + 1;
+size_t split_workspace_bytes(int n_theta, int n_rho, int groups, uint32_t n_events);
+bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *ws, size_t bytes,
+                  SplitArgs *out);
+
 // Launchers (hough_kernels.hip).  All return a hipError_t from the launch.
 hipError_t launch_vote(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                        void *acc, int acc_type, hipStream_t s);
@@ -65,6 +81,8 @@ hipError_t launch_retain(const GridArgs &g, const float *x, const float *y, uint
                          const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
                          uint8_t *keep, hipStream_t s);
 hipError_t launch_batch(const GridArgs &g, const BatchPlan &p, const BatchArgs &a, hipStream_t s);
+hipError_t launch_batch_split(const GridArgs &g, const BatchPlan &p, const BatchArgs &a,
+                              const SplitArgs &sp, hipStream_t s);
 
 // LDS needs and plans (hough_kernels.hip).
 size_t vote_lds_bytes(int n_rho);

@@ -1113,6 +1113,183 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
     }
 }
 
+// ------------------------------------------------------------ split batch path (latency form)
+// The same results as k_batch for batches small enough that latency matters more than
+// throughput: the work items are the (event, theta tile) pairs, so the tiles of one event run
+// on different workgroups at once.  A tile votes all of its event's hits, finds its peaks, lists
+// them in raster order into its own slot of the workspace, dilates them, and sets the keep bits
+// of the event's hits it keeps (skipping hits other tiles already kept).  The workgroup that
+// finishes an event's last tile merges: the tile lists in tile order (raster order) truncated
+// at max_peaks, the true count, the status and the keep bytes, and it leaves the event's part
+// of the workspace zero again.  Each tile re-examines the hits the others have not kept yet,
+// so retention costs more in total than in k_batch: the price of the shorter latency.
+
+// Step 5 of one tile in the split form: keep bits in global memory, shared by the tiles.
+template <int G>
+__device__ void retain_split(const uint32_t *dil, float2 *st, const float *x, const float *y,
+                             uint32_t *bits, uint32_t hb, uint32_t he, const Cols<G> &cl,
+                             const GridArgs &g, int lane) {
+    uint32_t unused = 0;
+    for (uint32_t base = hb; base < he; base += 64) {
+        const uint32_t i = base + lane;
+        const bool done = (i < he) && ((__hip_atomic_load(&bits[i >> 5], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT) >> (i & 31)) & 1u);
+        if (__ballot((i < he) && !done) == 0ull) continue;
+        int slot;
+        const StageCount n = stage_hits(st, x, y, base, he, done, g, lane, unused, slot);
+        const uint64_t kept = lookup_staged<G>(dil, st, n, cl, lane, g.nrho_f);
+        if (slot >= 0 && ((kept >> slot) & 1ull)) atomicOr(&bits[i >> 5], 1u << (i & 31));
+        wave_sync();
+    }
+}
+
+template <int NW, int G, bool PER>
+__global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArgs g, BatchArgs a, SplitArgs sp,
+                                                                         int nwords) {
+    using L = Lane<G, true>;
+    constexpr int TW = L::TW, ST = L::STRIDE, OUT = TW - 2, NT = NW * 64;
+    extern __shared__ __align__(16) uint32_t lds[];
+    uint32_t *tile = lds;                                                  // [(n_rho + 1) * ST]
+    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * ST);   // [NW * 64]
+    uint32_t *pmask = reinterpret_cast<uint32_t *>(stage + NW * 64);       // [nwords * TW]
+    uint32_t *dil = pmask + (size_t)nwords * TW;                           // [(nwords + 1) * TW]
+    __shared__ uint32_t s_item, s_flags, s_last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const L ln(lane);
+    const int tile_words4 = (g.n_rho + 1) * ST / 4;
+    const uint32_t T = sp.n_tiles;
+    const uint32_t n_items = a.n_events * T;
+
+    for (int i = threadIdx.x; i < tile_words4; i += NT)
+        reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = threadIdx.x; i < TW; i += NT) dil[nwords * TW + i] = 0u;
+
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_item = atomicAdd(a.queue, 1u);
+            s_flags = 0u;
+            s_last = 0u;
+        }
+        __syncthreads();
+        const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
+        if (item >= n_items) {
+            if (threadIdx.x == 0 && atomicAdd(a.queue + 1, 1u) == gridDim.x - 1u) {
+                __hip_atomic_store(a.queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(a.queue + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            break;
+        }
+        const uint32_t e = item / T, t = item - e * T;
+        const uint32_t pe_id = (uint32_t)__builtin_amdgcn_readfirstlane((int)(a.ids ? a.ids[e] : e));
+        const uint32_t h0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.offsets[pe_id]);
+        const uint32_t h1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.offsets[pe_id + 1]);
+        const bool malformed = h1 < h0;
+        const uint32_t H = malformed ? 0u : h1 - h0;
+        uint32_t *bits = sp.kept + (size_t)e * kSplitKeepWords;
+        if (malformed || H > kMaxBatchHits) {
+            if (threadIdx.x == 0 && t == 0) s_flags = HOUGH_EV_TOO_MANY_HITS;
+        } else if (H > 0) {
+            const uint32_t hb = (uint32_t)((uint64_t)H * wave / NW);
+            const uint32_t he = (uint32_t)((uint64_t)H * (wave + 1) / NW);
+            const float *xe = a.x + h0, *ye = a.y + h0;
+            uint32_t bad = 0;
+            const int first = (int)t * OUT - 1;
+            const Cols<G> cl = load_cols<G, PER>(g, first, lane, ST, ln.col);
+            vote_range<G, true, PER>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad);
+            if (t == 0 && __ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
+            __syncthreads();
+            for (int u = wave; u < 2 * nwords; u += NW) {
+                uint32_t m[G];
+                const bool interior = u >= 1 && (u + 1) * kPeakRows < g.n_rho;
+                if (PER && (t == 0 || t == T - 1)) {
+                    if (interior)
+                        peak_rows<false, G, true, true>(tile, u, g.n_rho, g.threshold, ln, lane, m, first, g.n_theta);
+                    else
+                        peak_rows<true, G, true, true>(tile, u, g.n_rho, g.threshold, ln, lane, m, first, g.n_theta);
+                } else if (interior) {
+                    peak_rows<false, G, true>(tile, u, g.n_rho, g.threshold, ln, lane, m);
+                } else {
+                    peak_rows<true, G, true>(tile, u, g.n_rho, g.threshold, ln, lane, m);
+                }
+                uint16_t *pm16 = reinterpret_cast<uint16_t *>(pmask);
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    const int c = 64 * q + lane;
+                    const bool out_col = (c >= 1) && (c <= TW - 2) && (first + c < g.n_theta);
+                    pm16[((u >> 1) * TW + c) * 2 + (u & 1)] = out_col ? (uint16_t)m[q] : (uint16_t)0;
+                }
+            }
+            if (g.rho_window >= 32) {
+#pragma unroll 1
+                for (int i = threadIdx.x; i < nwords * TW; i += NT) dil[i] = 0u;
+            }
+            __syncthreads();
+            hough_peak *slot = sp.staged + ((size_t)e * T + t) * sp.tile_cap;
+            const uint32_t np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, slot, sp.tile_cap,
+                                                         0u, ln, lane, wave, NW);
+            __syncthreads();
+            if (threadIdx.x == 0) sp.counts[(size_t)e * T + t] = np;
+#pragma unroll 1
+            for (int i = threadIdx.x; i < tile_words4; i += NT)
+                reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (np) retain_split<G>(dil, stage + wave * 64, xe, ye, bits, hb, he, cl, g, lane);
+        }
+        // publish this tile's results, then count it; the last tile of the event merges
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (s_flags) atomicOr(&sp.flags[e], s_flags);
+            __threadfence();
+            s_last = atomicAdd(&sp.done[e], 1u) == T - 1u ? 1u : 0u;
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            if (threadIdx.x == 0) {               // exclusive prefix of the tile counts, in place
+                uint32_t run = 0;
+                for (uint32_t tt = 0; tt < T; ++tt) {
+                    const uint32_t c = __hip_atomic_load(&sp.counts[(size_t)e * T + tt], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    sp.counts[(size_t)e * T + tt] = run;
+                    run += c;
+                }
+                s_item = run;                     // the event's true peak count
+            }
+            __syncthreads();
+            const uint32_t total = s_item;
+            hough_peak *pe = a.peaks ? a.peaks + (size_t)e * a.max_peaks : nullptr;
+            const uint32_t cap = pe ? a.max_peaks : 0u;
+            for (uint32_t tt = 0; tt < T; ++tt) {
+                const uint32_t beg = sp.counts[(size_t)e * T + tt];
+                const uint32_t end = tt + 1 < T ? sp.counts[(size_t)e * T + tt + 1] : total;
+                uint2 *src = reinterpret_cast<uint2 *>(sp.staged + ((size_t)e * T + tt) * sp.tile_cap);
+                for (uint32_t i = threadIdx.x; i < end - beg; i += NT) {   // copy, then clear the slot
+                    if (beg + i < cap) reinterpret_cast<uint2 *>(pe)[beg + i] = src[i];
+                    src[i] = make_uint2(0u, 0u);
+                }
+            }
+            const uint32_t fl = __hip_atomic_load(&sp.flags[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!malformed) {                     // malformed offsets: touch nothing but the counters
+                uint8_t *ke = a.keep + (a.ids ? a.keep_offsets[e] : h0);
+                const bool skipped = H > kMaxBatchHits;
+                for (uint32_t i = threadIdx.x; i < H; i += NT)
+                    ke[i] = skipped ? (uint8_t)0 : (uint8_t)((bits[i >> 5] >> (i & 31)) & 1u);
+            }
+            __syncthreads();
+            // leave the event's workspace zero for the next launch
+            for (uint32_t i = threadIdx.x; i < (H + 31u) / 32u && i < kSplitKeepWords; i += NT) bits[i] = 0u;
+            for (uint32_t tt = threadIdx.x; tt < T; tt += NT) sp.counts[(size_t)e * T + tt] = 0u;
+            if (threadIdx.x == 0) {
+                a.n_peaks[e] = total;
+                a.status[e] = fl | (total > a.max_peaks ? HOUGH_EV_PEAKS_TRUNCATED : 0u);
+                sp.flags[e] = 0u;
+                sp.done[e] = 0u;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 constexpr int kVoteWaves = 16;
 constexpr int kPeakWaves = 16;
 constexpr int kRetainWaves = 8;
@@ -1266,15 +1443,90 @@ hipError_t launch_batch(const GridArgs &g, const BatchPlan &p, const BatchArgs &
 }
 
 template <int NW, int G>
+static hipError_t launch_split_t(const GridArgs &g, const BatchPlan &p, const BatchArgs &a,
+                                 const SplitArgs &sp, hipStream_t s) {
+    const int nwords = (g.n_rho + 31) / 32;
+    if (g.periodic)
+        hipLaunchKernelGGL((k_batch_split<NW, G, true>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a, sp,
+                           nwords);
+    else
+        hipLaunchKernelGGL((k_batch_split<NW, G, false>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a, sp,
+                           nwords);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_split(const GridArgs &g, const BatchPlan &p, const BatchArgs &a,
+                              const SplitArgs &sp, hipStream_t s) {
+    switch (p.waves * 10 + p.groups) {
+        case 41: return launch_split_t<4, 1>(g, p, a, sp, s);
+        case 42: return launch_split_t<4, 2>(g, p, a, sp, s);
+        case 61: return launch_split_t<6, 1>(g, p, a, sp, s);
+        case 62: return launch_split_t<6, 2>(g, p, a, sp, s);
+        case 81: return launch_split_t<8, 1>(g, p, a, sp, s);
+        case 82: return launch_split_t<8, 2>(g, p, a, sp, s);
+        case 161: return launch_split_t<16, 1>(g, p, a, sp, s);
+        case 162: return launch_split_t<16, 2>(g, p, a, sp, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Workspace layout of the split form; every section starts on a 256-byte boundary.
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static void split_sizes(int n_theta, int n_rho, int groups, uint32_t n_events, uint32_t *n_tiles,
+                        uint32_t *tile_cap, size_t off[6]) {
+    const uint32_t out_cols = 64u * (uint32_t)groups - 2u;
+    *n_tiles = ((uint32_t)n_theta + out_cols - 1u) / out_cols;
+    *tile_cap = ((out_cols + 1u) / 2u) * (((uint32_t)n_rho + 1u) / 2u);
+    const size_t E = n_events, T = *n_tiles;
+    off[0] = 0;                                                          // counts
+    off[1] = align256(off[0] + E * T * 4);                               // staged
+    off[2] = align256(off[1] + E * T * (size_t)(*tile_cap) * sizeof(hough_peak));   // kept
+    off[3] = align256(off[2] + E * kSplitKeepWords * 4);                 // done
+    off[4] = align256(off[3] + E * 4);                                   // flags
+    off[5] = align256(off[4] + E * 4);                                   // end
+}
+
+size_t split_workspace_bytes(int n_theta, int n_rho, int groups, uint32_t n_events) {
+    uint32_t T, cap;
+    size_t off[6];
+    split_sizes(n_theta, n_rho, groups, n_events, &T, &cap, off);
+    return off[5];
+}
+
+bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *ws, size_t bytes,
+                  SplitArgs *out) {
+    uint32_t T, cap;
+    size_t off[6];
+    split_sizes(n_theta, n_rho, groups, n_events, &T, &cap, off);
+    if (!ws || bytes < off[5] || ((uintptr_t)ws & 255u) != 0) return false;
+    char *b = static_cast<char *>(ws);
+    out->n_tiles = T;
+    out->tile_cap = cap;
+    out->counts = reinterpret_cast<uint32_t *>(b + off[0]);
+    out->staged = reinterpret_cast<hough_peak *>(b + off[1]);
+    out->kept = reinterpret_cast<uint32_t *>(b + off[2]);
+    out->done = reinterpret_cast<uint32_t *>(b + off[3]);
+    out->flags = reinterpret_cast<uint32_t *>(b + off[4]);
+    return true;
+}
+
+template <int NW, int G>
 static int prepare_t(size_t lds, size_t) {
-    // both grid topologies: a context's plan serves whichever kernel its grid launches
+    // both grid topologies and both forms: a context's plan serves whichever kernel it launches
     allow_lds(k_batch<NW, G, false>);
     allow_lds(k_batch<NW, G, true>);
-    int n = 0, m = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<NW, G, false>, NW * 64, lds) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_batch<NW, G, true>, NW * 64, lds) != hipSuccess)
+    allow_lds(k_batch_split<NW, G, false>);
+    allow_lds(k_batch_split<NW, G, true>);
+    int n[4] = {0, 0, 0, 0};
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[0], k_batch<NW, G, false>, NW * 64, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[1], k_batch<NW, G, true>, NW * 64, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[2], k_batch_split<NW, G, false>, NW * 64, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[3], k_batch_split<NW, G, true>, NW * 64, lds) != hipSuccess)
         return 0;
-    return n < m ? n : m;
+    int m = n[0];
+    for (int i = 1; i < 4; ++i) m = n[i] < m ? n[i] : m;
+    return m;
 }
 
 // Allow the plan's dynamic LDS for its kernel and return how many of its workgroups fit a CU

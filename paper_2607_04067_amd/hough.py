@@ -79,6 +79,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.hough_run_batch.restype = i32
     L.hough_run_batch_gather.argtypes = [vp, vp, vp, vp, vp, vp, u32, vp, vp, vp, vp, vp]
     L.hough_run_batch_gather.restype = i32
+    L.hough_run_batch_split.argtypes = [vp, vp, vp, vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.hough_run_batch_split.restype = i32
+    L.hough_split_workspace_bytes.argtypes = [vp, u32]
+    L.hough_split_workspace_bytes.restype = ctypes.c_size_t
     L.hough_get_batch_plan.argtypes = [vp, ctypes.POINTER(hough_batch_plan)]
     L.hough_get_batch_plan.restype = i32
     L.hough_set_batch_plan.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
@@ -317,6 +321,53 @@ class Context:
                "hough_run_batch")
         return peaks, n_peaks, keep, status
 
+
+    def split_workspace(self, n_events: int) -> torch.Tensor:
+        """A zero-filled device workspace for run_batch_split over up to n_events events."""
+        n = int(self._lib.hough_split_workspace_bytes(self._ctx, int(n_events)))
+        return torch.zeros(max(n, 256), dtype=torch.uint8, device="cuda")
+
+    def run_batch_split(self, x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor,
+                        workspace: torch.Tensor | None = None, peaks: torch.Tensor | None = None,
+                        n_peaks: torch.Tensor | None = None, keep: torch.Tensor | None = None,
+                        status: torch.Tensor | None = None, event_ids: torch.Tensor | None = None,
+                        keep_offsets: torch.Tensor | None = None, keep_size: int | None = None, stream=None):
+        """run_batch's (or, with event_ids and keep_offsets, run_batch_gather's) results, computed
+        with each event's theta tiles on separate workgroups (the latency form).
+        workspace: from split_workspace (kept zero between calls)."""
+        if (event_ids is None) != (keep_offsets is None):
+            raise ValueError("event_ids and keep_offsets go together")
+        E = offsets.numel() - 1 if event_ids is None else event_ids.numel()
+        mp = self.params.max_peaks
+        dev = offsets.device
+        if workspace is None:
+            workspace = self.split_workspace(E)
+        if peaks is None:
+            peaks = torch.zeros((max(E, 1), max(mp, 1), 2), dtype=torch.int32, device=dev)
+        if n_peaks is None:
+            n_peaks = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
+        if status is None:
+            status = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
+        if keep is None:
+            n_keep = x.numel() if event_ids is None else int(keep_size or 0)
+            keep = torch.zeros(max(n_keep, 1), dtype=torch.uint8, device=dev)
+        if event_ids is None:
+            po = _dev(offsets, torch.int32, "offsets", E + 1)
+            pi = pko = None
+        else:
+            po = _dev(offsets, torch.int32, "offsets")
+            pi = _dev(event_ids, torch.int32, "event_ids", E) if E else self._dummy.data_ptr()
+            pko = _dev(keep_offsets, torch.int32, "keep_offsets", E) if E else self._dummy.data_ptr()
+        pp = _dev(peaks, torch.int32, "peaks", 2 * E * mp) if mp > 0 else 0
+        pn = _dev(n_peaks, torch.int32, "n_peaks", E)
+        ps = _dev(status, torch.int32, "status", E)
+        pw = _dev(workspace, torch.uint8, "workspace")
+        pk = self._ptr_or_dummy(keep, torch.uint8, "keep")
+        px = self._ptr_or_dummy(x, torch.float32, "x")
+        py = self._ptr_or_dummy(y, torch.float32, "y")
+        _check(self._lib.hough_run_batch_split(self._ctx, px, py, po, pi, pko, E, pp, pn, pk, ps, pw,
+                                               workspace.numel(), _stream(stream)), "hough_run_batch_split")
+        return peaks, n_peaks, keep, status
 
     def run_batch_gather(self, x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, event_ids: torch.Tensor,
                          keep_offsets: torch.Tensor, peaks: torch.Tensor | None = None,

@@ -675,3 +675,56 @@ def test_periodic_needs_a_symmetric_range_and_two_columns(H):
     with pytest.raises(H.HoughError):
         H.Context(1, 256, -0.005, 0.005, "i32", 3, 1, 16, periodic=True)
     H.Context(2, 256, -0.005, 0.005, "i32", 3, 1, 16, periodic=True).close()
+
+
+# ------------------------------------------------------------ split form (one workgroup per tile)
+@pytest.mark.parametrize("name,n_events", [("plain-16ev-180x128", 16), ("paper-1000ev-360x256", 24),
+                                           ("dense-2000ev-720x512", 5), ("paper-1000ev-1000x1000", 4)])
+def test_split_form_equals_fused_form_and_oracle(H, orc, name, n_events):
+    import torch
+    wl = synth.WORKLOADS[name]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 8, n_events=n_events)
+    xt, yt, ot = H.to_device(ev)
+    for T, mp in [(wl.threshold, 20000), (max(wl.threshold, 30), 7)]:
+        ctx = H.Context.for_workload(wl, threshold=T, max_peaks=mp)
+        ws = ctx.split_workspace(ev.n_events)
+        ref = [t.clone() for t in ctx.run_batch(xt, yt, ot)]
+        for rep in range(2):                                   # the workspace comes back zero
+            out = ctx.run_batch_split(xt, yt, ot, ws)
+            torch.cuda.synchronize()
+            say(f"split {name} T={T} max_peaks={mp} rep={rep}")
+            assert all(torch.equal(a, b) for a, b in zip(ref, out)), (name, T, mp, rep)
+            assert int(ws.count_nonzero()) == 0
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, ev.x, ev.y, ev.offsets, threshold=T, rho_window=1,
+                                                cap=max(mp, 1), n_threads=8)
+        assert np.array_equal(out[1].cpu().numpy()[:ev.n_events].astype(np.int64), n_ref)
+        assert np.array_equal(out[2].cpu().numpy(), keep_ref)
+        ctx.close()
+
+
+def test_split_form_edge_events_plans_and_periodic(H, orc):
+    import torch
+    evs = _edge_events()
+    big = synth.random_hits(33000, seed=4)                      # beyond the batch limit
+    evs = evs + [big, (np.zeros(0, np.float32), np.zeros(0, np.float32))]
+    x = np.concatenate([a for a, _ in evs]).astype(np.float32)
+    y = np.concatenate([b for _, b in evs]).astype(np.float32)
+    offsets = np.zeros(len(evs) + 1, np.uint32)
+    offsets[1:] = np.cumsum([a.size for a, _ in evs])
+    xt, yt, ot = _t(x), _t(y), _t(offsets.astype(np.int32))
+    for periodic in (False, True):
+        ctx = H.Context(125, 100, -0.005, 0.005, "i32", 3, 1, 64, periodic=periodic)
+        for w, gr in [(8, 1), (4, 2), (16, 1)]:
+            try:
+                ctx.set_batch_plan(w, gr, 0)
+            except H.HoughError:
+                continue
+            say(f"split edges periodic={periodic} plan={w}x{gr}")
+            ref = [t.clone() for t in ctx.run_batch(xt, yt, ot)]
+            ws = ctx.split_workspace(len(evs))
+            out = ctx.run_batch_split(xt, yt, ot, ws)
+            torch.cuda.synchronize()
+            assert all(torch.equal(a, b) for a, b in zip(ref, out)), (periodic, w, gr)
+            assert int(ws.count_nonzero()) == 0
+        ctx.close()
