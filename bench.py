@@ -341,11 +341,13 @@ def serving(H, duration_s: float, warmup_s: float, plain_duration_s: float, pool
     sizes = [p.batch.n_events for p in pools]
     out = {"mix": "50/50 paper-1000ev-360x256 / dense-2000ev-720x512 generators",
            "pool_events": pool_events, "n_streams": 8, "max_batch_events": 256, "small_batch_events": 64,
+           "split_batch_events": 16,
            "latency": "results (n_peaks, status, keep) in host memory minus scheduled arrival",
            "served": {}, "plain": {}}
     for i, rate in enumerate(SERVE_RATES):
         tr = serve.poisson_trace(rate, warmup_s + duration_s, sizes, [0.5, 0.5], seed=100 + i)
-        res, _, _ = serve.run(pools, tr, n_streams=8, max_batch_events=256, max_batch_hits=1 << 21)
+        res, _, _ = serve.run(pools, tr, n_streams=8, max_batch_events=256, max_batch_hits=1 << 21,
+                              small_batch_events=64, split_batch_events=16)
         out["served"][str(rate)] = serve.summarize(tr, res, warmup_us=warmup_s * 1e6)
         log(f"served {rate}/s: {out['served'][str(rate)]}")
     for i, rate in enumerate(SERVE_RATES[:2]):

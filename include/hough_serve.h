@@ -20,7 +20,9 @@
  * private copies of the pools' contexts (same parameters and launch shape), made on entry.
  * Inside a batch the events are ordered largest first (the smallest fill the kernel's tail);
  * a batch's ids and keep offsets go to the device in one copy and its n_peaks, status and
- * keep bytes come back in one.
+ * keep bytes come back in one.  Small batches can take the split form (each stream slot then
+ * holds a zero-filled workspace for split_batch_events events), which trades total work for a
+ * shorter time per batch.
  *
  * With `plain` set, each request is instead processed alone by hough_vote, hough_peaks and
  * hough_retain (three launches, accumulator through HBM), one request per stream slot, under
@@ -55,6 +57,10 @@ typedef struct hough_serve_config {
     int32_t copy_peaks;             /* 1: bring the peak lists back as part of completion    */
     int32_t small_batch_events;     /* batches of at most this many events run with 16-wave
                                        workgroups (one event per CU finishes sooner); 0: never */
+    int32_t split_batch_events;     /* batches of at most this many events run through
+                                       hough_run_batch_split on the 16-wave shape (an event's
+                                       theta tiles on separate workgroups); 0: never          */
+    int32_t reserved;               /* 0                                                     */
     double max_wait_us;             /* hold a partial batch until its oldest event waited this
                                        long while a slot is free (0: launch at once)          */
 } hough_serve_config;

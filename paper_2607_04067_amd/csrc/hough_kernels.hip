@@ -1124,21 +1124,33 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
 // of the workspace zero again.  Each tile re-examines the hits the others have not kept yet,
 // so retention costs more in total than in k_batch: the price of the shorter latency.
 
-// Step 5 of one tile in the split form: keep bits in global memory, shared by the tiles.
+// Step 5 of one tile in the split form: keep bits in global memory, shared by the tiles.  A
+// wave tests 64 consecutive hits at a time and merges its kept bits into (at most three) words
+// before it touches global memory, so that the tiles' atomics stay few.
 template <int G>
 __device__ void retain_split(const uint32_t *dil, float2 *st, const float *x, const float *y,
                              uint32_t *bits, uint32_t hb, uint32_t he, const Cols<G> &cl,
                              const GridArgs &g, int lane) {
     uint32_t unused = 0;
+    float xn = 0.0f, yn = 0.0f;                       // the next 64 hits load while these are tested
+    if (hb + lane < he) { xn = x[hb + lane]; yn = y[hb + lane]; }
     for (uint32_t base = hb; base < he; base += 64) {
-        const uint32_t i = base + lane;
-        const bool done = (i < he) && ((__hip_atomic_load(&bits[i >> 5], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT) >> (i & 31)) & 1u);
-        if (__ballot((i < he) && !done) == 0ull) continue;
+        const float xi = xn, yi = yn;
+        const uint32_t nb = base + 64u + (uint32_t)lane;
+        if (nb < he) { xn = x[nb]; yn = y[nb]; }
         int slot;
-        const StageCount n = stage_hits(st, x, y, base, he, done, g, lane, unused, slot);
+        const StageCount n = stage_values(st, xi, yi, base + lane < he, g, unused, slot);
         const uint64_t kept = lookup_staged<G>(dil, st, n, cl, lane, g.nrho_f);
-        if (slot >= 0 && ((kept >> slot) & 1ull)) atomicOr(&bits[i >> 5], 1u << (i & 31));
+        const uint64_t m = __ballot(slot >= 0 && ((kept >> slot) & 1ull));   // bit l: hit base + l
+        const uint32_t sh = base & 31u;
+        if (m && lane < 3) {
+            uint64_t part;                                                    // bits of word base/32 + lane
+            if (lane == 0) part = m << sh;
+            else if (lane == 1) part = m >> (32u - sh);
+            else part = sh ? m >> (64u - sh) : 0ull;
+            part &= 0xffffffffull;
+            if (part) atomicOr(&bits[(base >> 5) + (uint32_t)lane], (uint32_t)part);
+        }
         wave_sync();
     }
 }
@@ -1245,29 +1257,40 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
         __syncthreads();
         if (s_last) {
             __threadfence();
-            if (threadIdx.x == 0) {               // exclusive prefix of the tile counts, in place
-                uint32_t run = 0;
-                for (uint32_t tt = 0; tt < T; ++tt) {
-                    const uint32_t c = __hip_atomic_load(&sp.counts[(size_t)e * T + tt], __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                    sp.counts[(size_t)e * T + tt] = run;
-                    run += c;
-                }
-                s_item = run;                     // the event's true peak count
-            }
-            __syncthreads();
-            const uint32_t total = s_item;
+            // the tile lists in tile order, 64 tiles at a time: wave 0 scans their counts into
+            // pref (LDS, free now), then every thread copies peaks and clears the slots
+            uint32_t *pref = pmask;
             hough_peak *pe = a.peaks ? a.peaks + (size_t)e * a.max_peaks : nullptr;
             const uint32_t cap = pe ? a.max_peaks : 0u;
-            for (uint32_t tt = 0; tt < T; ++tt) {
-                const uint32_t beg = sp.counts[(size_t)e * T + tt];
-                const uint32_t end = tt + 1 < T ? sp.counts[(size_t)e * T + tt + 1] : total;
-                uint2 *src = reinterpret_cast<uint2 *>(sp.staged + ((size_t)e * T + tt) * sp.tile_cap);
-                for (uint32_t i = threadIdx.x; i < end - beg; i += NT) {   // copy, then clear the slot
-                    if (beg + i < cap) reinterpret_cast<uint2 *>(pe)[beg + i] = src[i];
-                    src[i] = make_uint2(0u, 0u);
+            uint32_t run = 0;
+            for (uint32_t t0 = 0; t0 < T; t0 += 64) {
+                const uint32_t nt = T - t0 < 64u ? T - t0 : 64u;
+                if (wave == 0) {
+                    const uint32_t c = (uint32_t)lane < nt
+                        ? __hip_atomic_load(&sp.counts[(size_t)e * T + t0 + lane], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                        : 0u;
+                    const uint32_t incl = wave_inclusive_scan(c, lane);
+                    pref[lane] = run + incl - c;
+                    if (lane == 63) pref[64] = run + incl;
                 }
+                __syncthreads();
+                const uint32_t lo_i = pref[0], hi_i = pref[64];
+                for (uint32_t i = lo_i + threadIdx.x; i < hi_i; i += NT) {
+                    uint32_t lo = 0, hi = nt - 1;             // the last tile whose list starts at or before i
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi + 1) >> 1;
+                        if (pref[mid] <= i) lo = mid; else hi = mid - 1;
+                    }
+                    uint2 *src = reinterpret_cast<uint2 *>(sp.staged + ((size_t)e * T + t0 + lo) * sp.tile_cap) +
+                                 (i - pref[lo]);
+                    if (i < cap) reinterpret_cast<uint2 *>(pe)[i] = *src;
+                    *src = make_uint2(0u, 0u);
+                }
+                run = hi_i;
+                __syncthreads();                              // pref is rewritten by the next chunk
             }
+            const uint32_t total = run;                       // the event's true peak count
             const uint32_t fl = __hip_atomic_load(&sp.flags[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!malformed) {                     // malformed offsets: touch nothing but the counters
                 uint8_t *ke = a.keep + (a.ids ? a.keep_offsets[e] : h0);

@@ -34,6 +34,8 @@ struct Slot {
     uint8_t *d_out = nullptr;
     hough_peak *d_peaks = nullptr;
     void *d_acc = nullptr;
+    void *d_ws = nullptr;              // split-form workspace (zero between launches)
+    size_t ws_bytes = 0;
     uint32_t *h_in = nullptr;
     uint8_t *h_out = nullptr;
     hough_peak *h_peaks = nullptr;
@@ -54,6 +56,7 @@ struct Server {
         for (Slot &s : slots) {
             if (s.stream) (void)hipStreamSynchronize(s.stream);
             (void)hipFree(s.d_in); (void)hipFree(s.d_out); (void)hipFree(s.d_peaks); (void)hipFree(s.d_acc);
+            (void)hipFree(s.d_ws);
             (void)hipHostFree(s.h_in); (void)hipHostFree(s.h_out); (void)hipHostFree(s.h_peaks);
             if (s.done) (void)hipEventDestroy(s.done);
             if (s.stream) (void)hipStreamDestroy(s.stream);
@@ -96,7 +99,14 @@ struct Server {
                 if (hough_set_batch_plan(cs, 16, 1, 0) != HOUGH_OK &&
                     hough_set_batch_plan(cs, bp.waves_per_group, bp.column_groups, bp.groups_per_cu) != HOUGH_OK)
                     return HOUGH_EINVAL;
+                // every split launch leaves the workspace zero, so the kinds can share it
+                if (!cfg.plain && cfg.split_batch_events > 0)
+                    s.ws_bytes = std::max(s.ws_bytes,
+                                          hough_split_workspace_bytes(cs, (uint32_t)cfg.split_batch_events));
             }
+            if (s.ws_bytes && (hipMalloc(&s.d_ws, s.ws_bytes) != hipSuccess ||
+                               hipMemset(s.d_ws, 0, s.ws_bytes) != hipSuccess))
+                return HOUGH_ENOMEM;
         }
         return HOUGH_OK;
     }
@@ -113,7 +123,8 @@ extern "C" int hough_serve_run(const hough_serve_pool *pools, int32_t n_kinds, c
                                uint8_t *keep_out, hough_peak *peaks_out, uint32_t peaks_stride) {
     if (!pools || n_kinds < 1 || !cfg || (n_reqs && (!reqs || !res))) return HOUGH_EINVAL;
     if (cfg->n_streams < 1 || cfg->n_streams > 32 || cfg->max_batch_events < 1 || cfg->max_batch_hits < 1 ||
-        cfg->small_batch_events < 0 || !(cfg->max_wait_us >= 0.0))
+        cfg->small_batch_events < 0 || cfg->split_batch_events < 0 || cfg->reserved != 0 ||
+        !(cfg->max_wait_us >= 0.0))
         return HOUGH_EINVAL;
     if (peaks_out && !cfg->copy_peaks) return HOUGH_EINVAL;
 
@@ -233,9 +244,14 @@ extern "C" int hough_serve_run(const hough_serve_pool *pools, int32_t n_kinds, c
         if (!cfg->plain) {
             if (hipMemcpyAsync(sl.d_in, sl.h_in, n * 8u, hipMemcpyHostToDevice, s) != hipSuccess)
                 return HOUGH_EDEVICE;
-            hough_ctx *c = n <= (uint32_t)cfg->small_batch_events ? sl.ctx_small[(size_t)k] : sl.ctx[(size_t)k];
-            st = hough_run_batch_gather(c, kd.pool.x, kd.pool.y, kd.pool.offsets, d_ids, d_koff,
-                                        n, sl.d_peaks, d_npk, d_keep, d_status, s);
+            if (n <= (uint32_t)cfg->split_batch_events) {
+                st = hough_run_batch_split(sl.ctx_small[(size_t)k], kd.pool.x, kd.pool.y, kd.pool.offsets, d_ids,
+                                           d_koff, n, sl.d_peaks, d_npk, d_keep, d_status, sl.d_ws, sl.ws_bytes, s);
+            } else {
+                hough_ctx *c = n <= (uint32_t)cfg->small_batch_events ? sl.ctx_small[(size_t)k] : sl.ctx[(size_t)k];
+                st = hough_run_batch_gather(c, kd.pool.x, kd.pool.y, kd.pool.offsets, d_ids, d_koff,
+                                            n, sl.d_peaks, d_npk, d_keep, d_status, s);
+            }
         } else {
             const uint32_t h0 = kd.pool.host_offsets[h_ids[0]];
             st = hough_vote(sl.ctx[(size_t)k], kd.pool.x + h0, kd.pool.y + h0, hits, sl.d_acc, s);

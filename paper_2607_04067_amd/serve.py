@@ -23,7 +23,8 @@ class hough_serve_pool(ctypes.Structure):
 class hough_serve_config(ctypes.Structure):
     _fields_ = [("n_streams", ctypes.c_int32), ("max_batch_events", ctypes.c_int32),
                 ("max_batch_hits", ctypes.c_int32), ("plain", ctypes.c_int32), ("copy_peaks", ctypes.c_int32),
-                ("small_batch_events", ctypes.c_int32), ("max_wait_us", ctypes.c_double)]
+                ("small_batch_events", ctypes.c_int32), ("split_batch_events", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("max_wait_us", ctypes.c_double)]
 
 
 REQ_DTYPE = np.dtype([("arrival_us", "<f8"), ("kind", "<i4"), ("event", "<u4")])
@@ -74,12 +75,12 @@ def poisson_trace(rate_hz: float, duration_s: float, pool_sizes, mix, seed: int 
 def run(pools, trace: np.ndarray, n_streams: int = 8, max_batch_events: int = 256,
         max_batch_hits: int = 1 << 20, plain: bool = False, copy_peaks: bool = False,
         max_wait_us: float = 0.0, want_keep: bool = False, want_peaks: int = 0,
-        small_batch_events: int = 64):
+        small_batch_events: int = 64, split_batch_events: int = 16):
     """Run `trace` to completion; returns (results array, keep bytes or None, peaks or None)."""
     L = _lib()
     structs = (hough_serve_pool * len(pools))(*[p.struct() for p in pools])
     cfg = hough_serve_config(int(n_streams), int(max_batch_events), int(max_batch_hits), int(plain),
-                             int(copy_peaks or want_peaks > 0), int(small_batch_events), float(max_wait_us))
+                             int(copy_peaks or want_peaks > 0), int(small_batch_events), int(split_batch_events), 0, float(max_wait_us))
     trace = np.ascontiguousarray(trace, dtype=REQ_DTYPE)
     res = np.zeros(trace.size, RES_DTYPE)
     keep = peaks = None

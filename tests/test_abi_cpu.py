@@ -54,7 +54,7 @@ def test_serve_config_layout_matches_header():
                   flags=re.S)
     fields = re.findall(r"\b(int32_t|double)\s+(\w+);", body)
     assert [n for _, n in fields] == [n for n, _ in serve.hough_serve_config._fields_]
-    assert ctypes.sizeof(serve.hough_serve_config) == 32
+    assert ctypes.sizeof(serve.hough_serve_config) == 40
 
 
 def test_status_strings(hough_mod):

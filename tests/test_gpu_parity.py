@@ -439,6 +439,32 @@ def test_gather_batches_equal_plain_batches(H):
     ctx.close()
 
 
+
+def test_split_gather_batches_equal_gather_batches(H):
+    """The split form over pool indices gives run_batch_gather's results, bytes outside the
+    batch's keep ranges untouched, on a reused workspace."""
+    import torch
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    pool = synth.make_events(wl, 0, n_events=40)
+    ctx = H.Context.for_workload(wl, max_peaks=8192)
+    xt, yt, ot = H.to_device(pool)
+    ws = ctx.split_workspace(8)
+    for ids in (np.array([7, 3, 3, 39, 0, 21, 7, 12], np.int64), np.array([5, 38], np.int64)):
+        sub = pool.subset(ids)
+        koff = (sub.offsets[:-1] + 5).astype(np.int32)           # a 5-byte gap before the first event
+        n_keep = sub.n_hits + 9
+        ref = ctx.run_batch_gather(xt, yt, ot, _t(ids.astype(np.int32)), _t(koff), keep_size=n_keep,
+                                   keep=torch.full((n_keep,), 0xAB, dtype=torch.uint8, device="cuda"))
+        out = ctx.run_batch_split(xt, yt, ot, ws, event_ids=_t(ids.astype(np.int32)), keep_offsets=_t(koff),
+                                  keep=torch.full((n_keep,), 0xAB, dtype=torch.uint8, device="cuda"))
+        torch.cuda.synchronize()
+        say(f"split gather ids={ids.tolist()}")
+        assert all(torch.equal(a, b) for a, b in zip(ref, out))
+        assert int((out[2][:5] != 0xAB).sum()) == 0 and int((out[2][-4:] != 0xAB).sum()) == 0
+        assert int(ws.count_nonzero()) == 0
+    ctx.close()
+
+
 def _serve_pools(H, n_each=48):
     from paper_2607_04067_amd import serve
     pools = []
@@ -450,11 +476,13 @@ def _serve_pools(H, n_each=48):
     return pools
 
 
-@pytest.mark.parametrize("plain,small", [(False, 0), (False, 64), (True, 0)])
-def test_served_results_equal_results_alone(H, plain, small):
+@pytest.mark.parametrize("plain,small,split", [(False, 0, 0), (False, 64, 0), (False, 64, 4), (False, 0, 16),
+                                               (True, 0, 0)])
+def test_served_results_equal_results_alone(H, plain, small, split):
     """Each request's n_peaks, status, keep and peak list in the served mix (continuous
     batching over several streams, events reordered largest first inside a batch, small
-    batches on the 16-wave shape or not) equal the same event processed alone."""
+    batches on the 16-wave shape or in the split form or neither) equal the same event
+    processed alone."""
     import torch
     from paper_2607_04067_amd import serve
     pools = _serve_pools(H)
@@ -462,8 +490,9 @@ def test_served_results_equal_results_alone(H, plain, small):
                                 [p.batch.n_events for p in pools], [0.5, 0.5], seed=3)
     assert trace.size > 20
     res, keep, peaks = serve.run(pools, trace, n_streams=4, max_batch_events=16, max_batch_hits=40000,
-                                 plain=plain, want_keep=True, want_peaks=16384, small_batch_events=small)
-    say(f"served {trace.size} requests plain={plain}: {serve.summarize(trace, res)}")
+                                 plain=plain, want_keep=True, want_peaks=16384, small_batch_events=small,
+                                 split_batch_events=split)
+    say(f"served {trace.size} requests plain={plain} split={split}: {serve.summarize(trace, res)}")
     off = 0
     alone = {}
     for i, (k, e) in enumerate(zip(trace["kind"], trace["event"])):
