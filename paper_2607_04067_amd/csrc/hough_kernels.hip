@@ -431,39 +431,75 @@ __device__ __forceinline__ uint32_t lookup1(const uint32_t *dil, float u, float 
         const float w = __builtin_fmaf(v, cl.S[q], cl.B[q]);
         const float t = __builtin_fmaf(u, cl.C[q], w);
         if (!checked || (t >= 0.0f && t < nrho_f)) {
-            const int k = (int)t;
-            m |= dil[(k >> 5) * (64 * G) + 64 * q + lane] >> (k & 31);
+            const uint32_t k = (uint32_t)(int)t;
+            // word k / 32 of the column (a shift and one shift-add: the empty asm keeps the
+            // compiler from turning the pair into shift, mask and add), then bit k mod 32 (the
+            // bit-field extract takes its offset modulo 32)
+            uint32_t kw = k >> 5;
+            asm("" : "+v"(kw));
+            m |= __builtin_amdgcn_ubfe(dil[kw * (64u * G) + 64u * q + (uint32_t)lane], k, 1u);
         }
     }
-    return m & 1u;
+    return m;
+}
+
+// OR over the 64 lanes (DPP row shifts and row broadcasts, no LDS), returned wave-uniform.
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+    v |= __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // Look up the staged hits st[0 .. n.total) (the first n.safe need no range test), four at a
-// time so that their reads are in flight together.  Returns the mask of kept stage slots.
+// time so that their reads are in flight together.  Each lane gathers its own column's verdicts
+// as bits (hit h at bit h mod 32 of one of two words) and one OR across the wave at the end
+// turns them into the mask of kept stage slots.
 template <int G>
 __device__ __forceinline__ uint64_t lookup_staged(const uint32_t *dil, const float2 *st, StageCount n,
                                                   const Cols<G> &cl, int lane, float nrho_f) {
     const float4 *st4 = reinterpret_cast<const float4 *>(st);
-    uint64_t kept = 0;
+    uint32_t w[2] = {0u, 0u};
     uint32_t h = 0;
-    for (; h + 4 <= n.safe; h += 4) {
+    // hits h .. h+3 into bits h mod 32 .. of word `half` (h is a multiple of 4, so a group
+    // never straddles the two words)
+    auto four = [&](uint32_t &acc, uint32_t sh) {
         const float4 a = st4[h >> 1], b = st4[(h >> 1) + 1];
-        const uint32_t m0 = lookup1<G>(dil, a.x, a.y, false, cl, lane, nrho_f);
-        const uint32_t m1 = lookup1<G>(dil, a.z, a.w, false, cl, lane, nrho_f);
-        const uint32_t m2 = lookup1<G>(dil, b.x, b.y, false, cl, lane, nrho_f);
-        const uint32_t m3 = lookup1<G>(dil, b.z, b.w, false, cl, lane, nrho_f);
-        const uint64_t one = 1ull << h;
-        kept |= __ballot(m0 != 0u) ? one : 0ull;
-        kept |= __ballot(m1 != 0u) ? one << 1 : 0ull;
-        kept |= __ballot(m2 != 0u) ? one << 2 : 0ull;
-        kept |= __ballot(m3 != 0u) ? one << 3 : 0ull;
-    }
+        const float uu[4] = {a.x, a.z, b.x, b.z}, vv[4] = {a.y, a.w, b.y, b.w};
+        uint32_t kk[4][G], wd[4][G];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const float t = __builtin_fmaf(uu[i], cl.C[q], __builtin_fmaf(vv[i], cl.S[q], cl.B[q]));
+                kk[i][q] = (uint32_t)(int)t;
+                uint32_t kw = kk[i][q] >> 5;        // see lookup1
+                asm("" : "+v"(kw));
+                wd[i][q] = kw * (64u * G) + 64u * q + (uint32_t)lane;
+            }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < G; ++q) wd[i][q] = dil[wd[i][q]];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < G; ++q) acc |= __builtin_amdgcn_ubfe(wd[i][q], kk[i][q], 1u) << (sh + i);
+    };
+    for (; h + 4 <= n.safe && h < 32; h += 4) four(w[0], h);
+    for (; h + 4 <= n.safe; h += 4) four(w[1], h - 32);
     for (; h < n.total; ++h) {
         const float2 p = st[h];
         const uint32_t m = lookup1<G>(dil, p.x, p.y, h >= n.safe, cl, lane, nrho_f);
-        kept |= __ballot(m != 0u) ? (1ull << h) : 0ull;
+        if (h < 32) w[0] |= m << h; else w[1] |= m << (h - 32);
     }
-    return kept;
+    if (n.total == 0) return 0ull;
+    const uint32_t klo = wave_or(w[0]);
+    const uint32_t khi = n.total > 32 ? wave_or(w[1]) : 0u;
+    return ((uint64_t)khi << 32) | klo;
 }
 
 __device__ __forceinline__ uint64_t low_bits(uint32_t n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
