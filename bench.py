@@ -325,6 +325,114 @@ def end_to_end(H, ctx, wl, ev, reps: int = 10):
 SERVE_RATES = (50_000, 100_000, 200_000, 400_000)
 
 
+def _stage_times(H, ctx, sub, cap, reps):
+    """Mean times (ms) of one batch's stages on one stream: hits and offsets from pinned host
+    memory to HBM, the fused launch, n_peaks/status/keep back to pinned host memory, and the
+    three together.  Each stage is bracketed by its own HIP events; the mean of reps runs."""
+    import torch
+    E = sub.n_events
+    hx = torch.from_numpy(np.ascontiguousarray(sub.x)).pin_memory()
+    hy = torch.from_numpy(np.ascontiguousarray(sub.y)).pin_memory()
+    ho = torch.from_numpy(sub.offsets.astype(np.int32)).pin_memory()
+    dx, dy, do = (torch.empty_like(t, device="cuda") for t in (hx, hy, ho))
+    peaks = torch.zeros((E, cap, 2), dtype=torch.int32, device="cuda")
+    npk = torch.zeros(E, dtype=torch.int32, device="cuda")
+    keep = torch.zeros(max(sub.n_hits, 1), dtype=torch.uint8, device="cuda")
+    status = torch.zeros(E, dtype=torch.int32, device="cuda")
+    h_npk, h_st = torch.empty(E, dtype=torch.int32).pin_memory(), torch.empty(E, dtype=torch.int32).pin_memory()
+    h_keep = torch.empty(max(sub.n_hits, 1), dtype=torch.uint8).pin_memory()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    acc = np.zeros(4)
+    for r in range(reps + 1):
+        ev[0].record(stream)
+        dx.copy_(hx, non_blocking=True); dy.copy_(hy, non_blocking=True); do.copy_(ho, non_blocking=True)
+        ev[1].record(stream)
+        ctx.run_batch(dx, dy, do, peaks, npk, keep, status, stream)
+        ev[2].record(stream)
+        h_npk.copy_(npk, non_blocking=True); h_st.copy_(status, non_blocking=True)
+        h_keep.copy_(keep, non_blocking=True)
+        ev[3].record(stream)
+        ev[3].synchronize()
+        if r:                                   # the first run warms up
+            acc += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3]),
+                    ev[0].elapsed_time(ev[3])]
+    return [round(float(v), 4) for v in acc / reps]
+
+
+def _split_kernel_ms(H, wl, sub, cap, reps):
+    """Mean time (ms) of hough_run_batch_split over a resident batch, 16-wave workgroups (the
+    shape the serving loop gives small batches)."""
+    import torch
+    ctx = H.Context.for_workload(wl, max_peaks=cap)
+    try:
+        ctx.set_batch_plan(16, 1, 0)
+    except H.HoughError:
+        pass
+    x, y, off = H.to_device(sub)
+    ws = ctx.split_workspace(sub.n_events)
+    out = [t for t in ctx.run_batch_split(x, y, off, ws)]
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    total = 0.0
+    for _ in range(reps):
+        a.record(stream)
+        ctx.run_batch_split(x, y, off, ws, *out)
+        b.record(stream)
+        b.synchronize()
+        total += a.elapsed_time(b)
+    ctx.close()
+    return round(total / reps, 4)
+
+
+def sweeps(H, wl, ev, reps: int = 10, cpu_budget_s: float = 20.0):
+    """The paper's batch-scale and block-size studies, reshaped for this path (Sec. IV, Fig. 8
+    and Fig. 9): (1) runtime against the number of events, GPU end to end (PCIe both ways) and
+    kernel only, beside the CPU oracle on the host cores while it fits the budget; (2) per-stage
+    times (transfer in, fused kernel, transfer back) against the workgroup size, at the
+    1,000-event scale.  Every point is the mean of `reps` runs, as in the paper."""
+    from oracle import oracle
+    cap = MAX_PEAKS[wl.name]
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1))
+    out = {"events": [], "block": [], "reps": reps, "workload": wl.name,
+           "cpu": f"oracle, OpenMP over events, {threads} threads"}
+    ctx = H.Context.for_workload(wl, max_peaks=cap)
+    spent, per_event = 0.0, 0.0
+    for n in (1, 10, 100, 1000, 10000):
+        idx = np.arange(n) % ev.n_events              # past the generated events: repeated ones
+        sub = ev.subset(idx)
+        h2d, kern, d2h, total = _stage_times(H, ctx, sub, cap, reps)
+        row = {"events": n, "gpu_e2e_ms": total, "gpu_kernel_ms": kern, "h2d_ms": h2d, "d2h_ms": d2h}
+        if spent + per_event * n * threads < cpu_budget_s:
+            t0 = time.perf_counter()
+            oracle.run_batch(wl, sub.x, sub.y, sub.offsets, cap=cap, n_threads=threads)
+            dt = time.perf_counter() - t0
+            spent += dt * threads
+            per_event = dt / n
+            row["cpu_ms"] = round(dt * 1e3, 3)
+            row["speedup_e2e"] = round(dt * 1e3 / total, 1)
+        if n <= 100:                                  # small batches: the split (latency) form
+            row["gpu_kernel_split_ms"] = _split_kernel_ms(H, wl, sub, cap, reps)
+        log(f"sweep events {row}")
+        out["events"].append(row)
+    sub = ev.subset(np.arange(min(1000, ev.n_events)))
+    for waves in (4, 6, 8, 16):
+        for groups in (1, 2):
+            try:
+                ctx.set_batch_plan(waves, groups, 0)
+            except H.HoughError:
+                continue
+            h2d, kern, d2h, total = _stage_times(H, ctx, sub, cap, reps)
+            plan = ctx.batch_plan
+            row = {"threads_per_workgroup": 64 * waves, "column_groups": groups,
+                   "workgroups_per_cu": plan["groups_per_cu"], "h2d_ms": h2d, "kernel_ms": kern,
+                   "d2h_ms": d2h, "total_ms": total}
+            log(f"sweep block {row}")
+            out["block"].append(row)
+    ctx.close()
+    return out
+
+
 def serving(H, duration_s: float, warmup_s: float, plain_duration_s: float, pool_events: int = 8192):
     """Open-loop Poisson arrivals of a 50/50 mix of the 1000-event-workload and dense-workload
     generators (pools of `pool_events` each, seed 0) through the native serving loop: served
@@ -374,6 +482,8 @@ def main(argv=None):
     ap.add_argument("--no-e2e", action="store_true", help="skip the PCIe-inclusive measurement")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="measured seconds of arrivals per served rate (after 1 s of warm-up)")
+    ap.add_argument("--sweeps", action="store_true",
+                    help="add the runtime-vs-events and stage-times-vs-workgroup-size studies")
     ap.add_argument("--copy-reference-mb", type=int, default=0,
                     help="also time a plain device copy of this many MiB (HBM reference for counters)")
     args = ap.parse_args(argv)
@@ -471,6 +581,8 @@ def main(argv=None):
     }
     if tuned is not None:
         out["autotune_ms"] = tuned["ms"]
+    if args.sweeps:
+        out["sweeps"] = sweeps(H, wl, ev)
     if args.copy_reference_mb:
         n = args.copy_reference_mb << 20
         src = torch.empty(n, dtype=torch.uint8, device="cuda")
