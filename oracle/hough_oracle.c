@@ -40,6 +40,9 @@
  *     |k_i(jp) - kp| <= rho_window, k_i(jp) computed with the bin rule above.
  *   - the paper's own peak finder (relative threshold, then iterative extraction with
  *     neighbourhood suppression) is oracle_peaks_iterative; its readings are stated there.
+ *   - optional duplicate suppression (curlers fire the same wires on every turn): a hit whose
+ *     coordinates are bit-identical to an earlier hit of its event casts no votes; retention
+ *     still judges every copy by its coordinates (oracle_vote_dedup).
  */
 #include <float.h>
 #include <math.h>
@@ -114,6 +117,43 @@ void oracle_vote(int n_theta, int n_rho, const float *C, const float *S, float B
             if (k >= 0) acc[(size_t)j * n_rho + k] += 1;
         }
     }
+}
+
+/* Duplicate hits (a multi-turn track fires the same wire again): first[i] = 1 iff no earlier
+ * hit of the list has bit-identical coordinates, by direct comparison with every earlier hit. */
+void oracle_first_copies(const float *x, const float *y, long n_hits, uint8_t *first)
+{
+    for (long i = 0; i < n_hits; ++i) {
+        uint32_t xi, yi;
+        memcpy(&xi, &x[i], 4);
+        memcpy(&yi, &y[i], 4);
+        first[i] = 1;
+        for (long j = 0; j < i; ++j) {
+            uint32_t xj, yj;
+            memcpy(&xj, &x[j], 4);
+            memcpy(&yj, &y[j], 4);
+            if (xi == xj && yi == yj) { first[i] = 0; break; }
+        }
+    }
+}
+
+/* Voting with each distinct hit counted once: only the first copy of a hit votes. */
+void oracle_vote_dedup(int n_theta, int n_rho, const float *C, const float *S, float Bf,
+                       const float *x, const float *y, long n_hits, int32_t *acc)
+{
+    uint8_t *first = (uint8_t *)malloc(n_hits > 0 ? (size_t)n_hits : 1);
+    memset(acc, 0, sizeof(int32_t) * (size_t)n_theta * (size_t)n_rho);
+    if (!first) return;
+    oracle_first_copies(x, y, n_hits, first);
+    for (long i = 0; i < n_hits; ++i) {
+        float u, v;
+        if (!first[i] || !oracle_conformal(x[i], y[i], &u, &v)) continue;
+        for (int j = 0; j < n_theta; ++j) {
+            int k = oracle_rho_bin(u, v, C[j], S[j], Bf, n_rho);
+            if (k >= 0) acc[(size_t)j * n_rho + k] += 1;
+        }
+    }
+    free(first);
 }
 
 /* Is cell (j,k) a peak?  Threshold plus the 3x3 local-maximum test with the raster tie rule. */
@@ -307,6 +347,8 @@ void oracle_track_params(int n_theta, int n_rho, double rho_min, double rho_max,
 /*
  * Whole hot path over CSR-packed events: per event vote, find all peaks, keep hits near any
  * of them, and return the first `cap` peaks of each event (raster order) with the true count.
+ * dedup != 0: only the first copy of bit-identical hits votes (every copy is still retained or
+ * not by its coordinates).
  * Events are independent (Sec. III), so they are spread over n_threads OpenMP threads; each
  * event is still computed by the plain single-event routines above.
  * peaks_out holds cap triples (j, k, count) per event.  Returns 0, or -1 on allocation failure.
@@ -314,7 +356,7 @@ void oracle_track_params(int n_theta, int n_rho, double rho_min, double rho_max,
 int oracle_run_batch(int n_theta, int n_rho, double rho_min, double rho_max, int threshold,
                      int rho_window, const float *x, const float *y, const uint32_t *offsets,
                      long n_events, long cap, int32_t *peaks_out, int64_t *n_peaks_out,
-                     uint8_t *keep, int n_threads, int periodic)
+                     uint8_t *keep, int n_threads, int periodic, int dedup)
 {
     float *C = (float *)malloc(sizeof(float) * (size_t)n_theta);
     float *S = (float *)malloc(sizeof(float) * (size_t)n_theta);
@@ -336,7 +378,10 @@ int oracle_run_batch(int n_theta, int n_rho, double rho_min, double rho_max, int
 #pragma omp atomic write
             failed = 1;
         } else {
-            oracle_vote(n_theta, n_rho, C, S, Bf, x + a, y + a, h, acc);
+            if (dedup)
+                oracle_vote_dedup(n_theta, n_rho, C, S, Bf, x + a, y + a, h, acc);
+            else
+                oracle_vote(n_theta, n_rho, C, S, Bf, x + a, y + a, h, acc);
             long np = oracle_peaks_mode(acc, n_theta, n_rho, threshold, periodic, pj, pk, pc, max_p);
             oracle_retain(n_rho, C, S, Bf, rho_window, x + a, y + a, h, pj, pk, np, keep + a);
             n_peaks_out[e] = np;

@@ -82,7 +82,9 @@ def lib():
                                     _i32p, _i32p, c_long, _u8p]
         L.oracle_retain.restype = None
         L.oracle_run_batch.argtypes = [c_int, c_int, c_double, c_double, c_int, c_int, _f32p, _f32p,
-                                       _u32p, c_long, c_long, _i32p, _i64p, _u8p, c_int, c_int]
+                                       _u32p, c_long, c_long, _i32p, _i64p, _u8p, c_int, c_int, c_int]
+        L.oracle_first_copies.argtypes = [_f32p, _f32p, c_long, _u8p]
+        L.oracle_vote_dedup.argtypes = [c_int, c_int, _f32p, _f32p, c_float, _f32p, _f32p, c_long, _i32p]
         L.oracle_run_batch.restype = c_int
         L.oracle_max_threads.argtypes = []
         L.oracle_max_threads.restype = c_int
@@ -137,6 +139,25 @@ def vote(g: Grid, x, y) -> np.ndarray:
     x, y = _f32(x), _f32(y)
     acc = np.zeros((g.n_theta, g.n_rho), np.int32)
     lib().oracle_vote(g.n_theta, g.n_rho, g.C, g.S, float(g.B), x, y, x.size, acc)
+    return acc
+
+
+def first_copies(x, y) -> np.ndarray:
+    """uint8 per hit: 1 iff no earlier hit has bit-identical (x, y) (duplicate suppression)."""
+    x, y = _f32(x), _f32(y)
+    first = np.zeros(max(x.size, 1), np.uint8)
+    lib().oracle_first_copies(x if x.size else np.zeros(1, np.float32),
+                              y if y.size else np.zeros(1, np.float32), x.size, first)
+    return first[:x.size]
+
+
+def vote_dedup(g: Grid, x, y) -> np.ndarray:
+    """Accumulator with only the first copy of bit-identical hits voting."""
+    x, y = _f32(x), _f32(y)
+    acc = np.zeros((g.n_theta, g.n_rho), np.int32)
+    lib().oracle_vote_dedup(g.n_theta, g.n_rho, g.C, g.S, float(g.B),
+                            x if x.size else np.zeros(1, np.float32),
+                            y if y.size else np.zeros(1, np.float32), x.size, acc)
     return acc
 
 
@@ -201,8 +222,9 @@ def retain(g: Grid, x, y, pj, pk, rho_window: int = 1) -> np.ndarray:
 
 
 def run_batch(wl_or_grid, x, y, offsets, threshold: int | None = None, rho_window: int | None = None,
-              cap: int = 4096, n_threads: int = 1, periodic: bool = False):
-    """Whole path over CSR events.  Returns (peaks[E, cap, 3] as (j, k, count), n_peaks[E], keep[H])."""
+              cap: int = 4096, n_threads: int = 1, periodic: bool = False, dedup: bool = False):
+    """Whole path over CSR events.  Returns (peaks[E, cap, 3] as (j, k, count), n_peaks[E], keep[H]).
+    dedup: only the first copy of bit-identical hits of an event votes."""
     if isinstance(wl_or_grid, Grid):
         g = wl_or_grid
         if threshold is None or rho_window is None:
@@ -220,7 +242,8 @@ def run_batch(wl_or_grid, x, y, offsets, threshold: int | None = None, rho_windo
     keep = np.zeros(max(x.size, 1), np.uint8)
     rc = lib().oracle_run_batch(g.n_theta, g.n_rho, g.rho_min, g.rho_max, int(threshold), int(rho_window),
                                 x if x.size else np.zeros(1, np.float32), y if y.size else np.zeros(1, np.float32),
-                                offsets, E, int(cap), out, n_peaks, keep, int(n_threads), int(bool(periodic)))
+                                offsets, E, int(cap), out, n_peaks, keep, int(n_threads), int(bool(periodic)),
+                                int(bool(dedup)))
     if rc != 0:
         raise MemoryError("oracle_run_batch failed")
     return out[:E], n_peaks[:E], keep[:x.size]

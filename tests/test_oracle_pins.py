@@ -655,3 +655,86 @@ def test_periodic_single_track_at_theta_pi_has_one_peak(orc):
         assert list(zip(pj.tolist(), pk.tolist())) == [(0, g.n_rho - 1 - k), (g.n_theta - 1, k)]
         assert pc[0] == pc[1]
         assert list(zip(qj.tolist(), qk.tolist())) == [(0, g.n_rho - 1 - k)]
+
+
+# ----------------------------------------------------------------- duplicate suppression
+def _bits(x, y):
+    return np.stack([np.asarray(x, np.float32).view(np.uint32), np.asarray(y, np.float32).view(np.uint32)], 1)
+
+
+def test_first_copies_match_a_set_of_seen_bit_patterns(orc):
+    """Brute force with a Python set over bit patterns; -0.0 and 0.0 are different hits, two
+    NaNs with the same payload are the same hit."""
+    rng = np.random.default_rng(21)
+    x, y = synth.random_hits(300, seed=22)
+    pick = rng.integers(0, 300, 200)
+    x = np.concatenate([x, x[pick], np.float32([0.0, -0.0, np.nan, np.nan, 5.0])])
+    y = np.concatenate([y, y[pick], np.float32([1.0, 1.0, 2.0, 2.0, 5.0])])
+    perm = rng.permutation(x.size)
+    x, y = x[perm], y[perm]
+    seen, want = set(), []
+    for bx, by in _bits(x, y):
+        key = (int(bx), int(by))
+        want.append(0 if key in seen else 1)
+        seen.add(key)
+    got = orc.first_copies(x, y)
+    assert np.array_equal(got, np.array(want, np.uint8))
+    assert int(got.sum()) == len(seen)
+
+
+def test_dedup_vote_equals_voting_the_distinct_hits(orc):
+    """np.unique over the bit patterns gives the distinct hits; voting them once each is the
+    deduplicated accumulator, and a hit repeated r times adds r-1 to every cell it votes in."""
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 5, n_events=4)
+    for e in range(4):
+        x, y = ev.event(e)
+        uniq = np.unique(_bits(x, y), axis=0)
+        xu, yu = uniq[:, 0].view(np.float32), uniq[:, 1].view(np.float32)
+        acc_d = orc.vote_dedup(g, x, y)
+        assert np.array_equal(acc_d, orc.vote(g, xu, yu))
+    x, y = synth.random_hits(50, seed=3)
+    reps = np.arange(50) % 4 + 1
+    xr, yr = np.repeat(x, reps), np.repeat(y, reps)
+    acc_plain, acc_d = orc.vote(g, xr, yr), orc.vote_dedup(g, xr, yr)
+    extra = sum((r - 1) * orc.vote(g, x[i:i + 1], y[i:i + 1]) for i, r in enumerate(reps))
+    assert np.array_equal(acc_plain - acc_d, extra)
+    assert np.array_equal(acc_d, orc.vote(g, x, y))
+
+
+def test_dedup_batch_peaks_and_keep(orc):
+    """The deduplicated batch: peaks of the distinct hits' accumulator, and each copy kept iff
+    its coordinates are within the window of one of those peaks (equal to its first copy)."""
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 6, n_events=3)
+    x = np.concatenate([ev.x, ev.x[:500]])          # the first event's hits once more at the end
+    y = np.concatenate([ev.y, ev.y[:500]])
+    off = ev.offsets.copy()
+    off[-1] += 500
+    pk, n, keep = orc.run_batch(g, x, y, off, threshold=30, rho_window=1, cap=20000, dedup=True)
+    pk0, n0, keep0 = orc.run_batch(g, x, y, off, threshold=30, rho_window=1, cap=20000)
+    for e in range(3):
+        a, b = int(off[e]), int(off[e + 1])
+        xe, ye = x[a:b], y[a:b]
+        acc = orc.vote_dedup(g, xe, ye)
+        pj, pkk, pc, m = orc.peaks(acc, 30)
+        assert n[e] == m and np.array_equal(pk[e, :m], np.stack([pj, pkk, pc], 1))
+        ref = orc.retain(g, xe, ye, pj, pkk, 1)
+        assert np.array_equal(keep[a:b], ref)
+        first = orc.first_copies(xe, ye)
+        assert first.sum() < xe.size or e < 2
+        if first.all():                              # events without duplicates are unchanged
+            assert n[e] == n0[e] and np.array_equal(keep[a:b], keep0[a:b])
+        else:                                        # the copies raised some counts
+            assert not np.array_equal(orc.vote(g, xe, ye), acc)
+    a = int(off[2])
+    tail = keep[int(off[3]) - 500:int(off[3])]
+    lookup = {}
+    for i in range(a, int(off[3]) - 500):
+        lookup.setdefault((x[i].tobytes(), y[i].tobytes()), keep[i])
+    for i, kv in enumerate(tail):
+        j = int(off[3]) - 500 + i
+        if (x[j].tobytes(), y[j].tobytes()) in lookup:
+            assert kv == lookup[(x[j].tobytes(), y[j].tobytes())]
