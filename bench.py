@@ -482,6 +482,8 @@ def main(argv=None):
     ap.add_argument("--no-e2e", action="store_true", help="skip the PCIe-inclusive measurement")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="measured seconds of arrivals per served rate (after 1 s of warm-up)")
+    ap.add_argument("--dedup", action="store_true",
+                    help="suppress duplicate hits (HOUGH_FLAG_DEDUP: one more launch per step)")
     ap.add_argument("--sweeps", action="store_true",
                     help="add the runtime-vs-events and stage-times-vs-workgroup-size studies")
     ap.add_argument("--copy-reference-mb", type=int, default=0,
@@ -499,7 +501,7 @@ def main(argv=None):
     log(f"generating {wl.n_events} events of {wl.name}")
     ev = synth.make_events(wl, 0)
     votes = ev.n_hits * wl.n_theta
-    ctx = H.Context.for_workload(wl, max_peaks=MAX_PEAKS[wl.name])
+    ctx = H.Context.for_workload(wl, max_peaks=MAX_PEAKS[wl.name], dedup=args.dedup)
     xt, yt, ot = H.to_device(ev)
     E = ev.n_events
     peaks = torch.zeros((E, MAX_PEAKS[wl.name], 2), dtype=torch.int32, device="cuda")
@@ -550,7 +552,7 @@ def main(argv=None):
     stored = int(np.minimum(npk.cpu().numpy().astype(np.int64), cap).sum())
     # algorithmic HBM bytes per launch: x, y and offsets in; keep, peak records, n_peaks, status out
     algo_bytes = 8 * ev.n_hits + 4 * (E + 1) + ev.n_hits + 8 * stored + 8 * E
-    prof = profiled_traffic(wl.name, ctx.batch_plan)
+    prof = None if args.dedup else profiled_traffic(wl.name, ctx.batch_plan)   # counters: plain launch only
     out = {
         "metric": METRIC, "value": round(events_per_s, 1), "unit": "events/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -559,7 +561,8 @@ def main(argv=None):
         "config": {"workload": wl.name, "events": E, "hits": ev.n_hits, "n_theta": wl.n_theta,
                    "n_rho": wl.n_rho, "threshold": wl.threshold, "rho_window": wl.rho_window,
                    "max_peaks": MAX_PEAKS[wl.name],
-                   "path": "hough_run_batch (one fused launch)" + (" in a HIP graph" if args.graph else ""),
+                   "path": ("hough_run_batch (" + ("duplicate pass + fused launch" if args.dedup else "one fused launch")
+                            + ")" + (" in a HIP graph" if args.graph else "")),
                    "plan": ctx.batch_plan},
         "gvotes_per_s": round(votes / (ms_per_step / 1e3) / 1e9, 2),
         "kernel_ms": round(kern_ms, 4),

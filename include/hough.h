@@ -71,6 +71,8 @@ extern "C" {
 #define HOUGH_EV_TOO_MANY_CANDIDATES 8u  /* hough_peaks_iterative: more cells reach the
                                         threshold than hough_max_iterative_candidates(); no
                                         peak was listed and n_peaks is zero                    */
+#define HOUGH_EV_DEDUP_SKIPPED   16u /* HOUGH_FLAG_DEDUP: the event has more hits than
+                                        hough_max_dedup_hits(), so every hit voted            */
 
 /* The (theta, rho) grid and the peak / retention parameters (Sec. II). */
 typedef struct hough_params {
@@ -92,6 +94,17 @@ typedef struct hough_params {
  * border from row k + dk lands on row n_rho - 1 - (k + dk)); raster order still decides ties.
  * Needs n_theta >= 2.  The iterative finder's suppression window does not wrap. */
 #define HOUGH_FLAG_THETA_PERIODIC 1
+
+/* hough_params.flags: duplicate suppression on the batch path (hough_run_batch,
+ * hough_run_batch_gather, hough_run_batch_split).  A track that curls through the chamber
+ * several times fires the same wires on every turn, so an event can hold the same wire
+ * position more than once.  With this flag a hit whose (x, y) is bit-identical to an earlier
+ * hit of its event casts no votes; every copy is still retained, or not, by its coordinates
+ * (so all copies get the same keep byte).  Events with more than hough_max_dedup_hits() hits
+ * vote every hit and get HOUGH_EV_DEDUP_SKIPPED.  A batch call then makes one more kernel
+ * launch before the fused one, and it writes the events' keep bytes in both.  hough_vote
+ * rejects a context with this flag (HOUGH_EINVAL): the per-event path has no such pass. */
+#define HOUGH_FLAG_DEDUP 2
 
 /* One peak: grid cell and its count.  8 bytes, no padding. */
 typedef struct hough_peak {
@@ -211,6 +224,9 @@ int hough_run_batch_split(hough_ctx *ctx, const float *x, const float *y, const 
                           const uint32_t *event_ids, const uint32_t *keep_offsets, uint32_t n_events,
                           hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* Largest event (hits) whose duplicates HOUGH_FLAG_DEDUP suppresses. */
+uint32_t hough_max_dedup_hits(void);
 
 /* Workspace bytes hough_run_batch_split needs for n_events events with the context's current
  * launch shape (0 for a NULL context). */

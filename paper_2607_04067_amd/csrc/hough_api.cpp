@@ -115,7 +115,8 @@ int hough_config(const hough_params *p, hough_ctx **out) {
     if (!isfinite(p->rho_min) || !isfinite(p->rho_max) || !(p->rho_max > p->rho_min)) return HOUGH_EINVAL;
     if (p->acc_type != HOUGH_ACC_U16 && p->acc_type != HOUGH_ACC_I32) return HOUGH_EINVAL;
     if (p->threshold < 1 || p->rho_window < 0 || p->max_peaks < 0) return HOUGH_EINVAL;
-    if ((p->flags & ~HOUGH_FLAG_THETA_PERIODIC) != 0 || p->reserved != 0) return HOUGH_EINVAL;
+    if ((p->flags & ~(HOUGH_FLAG_THETA_PERIODIC | HOUGH_FLAG_DEDUP)) != 0 || p->reserved != 0)
+        return HOUGH_EINVAL;
     if ((p->flags & HOUGH_FLAG_THETA_PERIODIC) && (p->n_theta < 2 || p->rho_min != -p->rho_max))
         return HOUGH_EINVAL;
     const double A = (double)p->n_rho / (p->rho_max - p->rho_min);
@@ -175,6 +176,7 @@ int hough_config(const hough_params *p, hough_ctx **out) {
     g.threshold = (uint32_t)p->threshold;
     g.rho_window = p->rho_window < p->n_rho ? p->rho_window : p->n_rho;
     g.periodic = (p->flags & HOUGH_FLAG_THETA_PERIODIC) ? 1 : 0;
+    g.dedup = (p->flags & HOUGH_FLAG_DEDUP) ? 1 : 0;
 
     rc = default_plan(c);
     if (rc != HOUGH_OK) {
@@ -227,6 +229,7 @@ int hough_set_batch_plan(hough_ctx *c, int32_t waves_per_group, int32_t column_g
 
 int hough_vote(hough_ctx *c, const float *x, const float *y, uint32_t n_hits, void *acc, void *stream) {
     if (!c || !acc) return HOUGH_EINVAL;
+    if (c->p.flags & HOUGH_FLAG_DEDUP) return HOUGH_EINVAL;      // no duplicate pass on this path
     if (!on_device(c)) return HOUGH_EINVAL;
     if (n_hits && (!x || !y)) return HOUGH_EINVAL;
     if (c->p.acc_type == HOUGH_ACC_U16 && n_hits > 65535u) return HOUGH_EOVERFLOW;
@@ -313,9 +316,8 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     a.status = status;
     a.max_peaks = (uint32_t)c->p.max_peaks;
     a.queue = c->d_work;
-    hipError_t e;
+    hough::SplitArgs sp;
     if (split) {
-        hough::SplitArgs sp;
         if (!hough::split_layout(c->p.n_theta, c->p.n_rho, c->plan.groups, n_events, workspace, workspace_bytes,
                                  &sp))
             return HOUGH_EINVAL;
@@ -323,10 +325,12 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
         if (items >= (1L << 31)) return HOUGH_EINVAL;      // the work queue counts in 32 bits
         long g2 = (long)c->plan.per_cu * c->n_cu;
         plan.grid = (int)(g2 < items ? g2 : items);
-        e = hough::launch_batch_split(c->g, plan, a, sp, (hipStream_t)stream);
-    } else {
-        e = hough::launch_batch(c->g, plan, a, (hipStream_t)stream);
     }
+    hipError_t e = hipSuccess;
+    if (c->g.dedup) e = hough::launch_dedup(a, (hipStream_t)stream);   // marks later copies in keep
+    if (e == hipSuccess)
+        e = split ? hough::launch_batch_split(c->g, plan, a, sp, (hipStream_t)stream)
+                  : hough::launch_batch(c->g, plan, a, (hipStream_t)stream);
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
 }
 
@@ -345,6 +349,8 @@ int hough_run_batch_gather(hough_ctx *c, const float *x, const float *y, const u
     return run_batch_common(c, x, y, offsets, event_ids, keep_offsets, n_events, peaks, n_peaks,
                             keep, status, stream);
 }
+
+uint32_t hough_max_dedup_hits(void) { return hough::kDedupMaxHits; }
 
 size_t hough_split_workspace_bytes(const hough_ctx *c, uint32_t n_events) {
     if (!c) return 0;

@@ -14,6 +14,13 @@ constexpr int kWave = 64;
 // Largest event of the fused batch kernel: a count then fits a packed 16-bit LDS counter, and
 // each wave's keep flags fit a few registers (at most 8192 hits per wave, 64 per lane).
 constexpr uint32_t kMaxBatchHits = 32767;
+// Largest event whose duplicate hits the batch path suppresses: its hash table (twice as many
+// 32-bit slots as hits, rounded up to a power of two) fits 64 KB of LDS.
+constexpr uint32_t kDedupMaxHits = 8192;
+constexpr uint32_t kDedupSlots = 2 * kDedupMaxHits;
+// Under duplicate suppression a keep byte carries two bits until its event is finished: bit 0
+// is the kept flag, bit 1 (this value) marks a later copy of a hit (set by the duplicate pass).
+constexpr uint8_t kKeepDuplicate = 2;
 
 // Grid constants as the kernels see them.
 struct GridArgs {
@@ -27,6 +34,7 @@ struct GridArgs {
     uint32_t threshold;
     int32_t rho_window;
     int32_t periodic;    // theta-periodic 3x3 test (HOUGH_FLAG_THETA_PERIODIC)
+    int32_t dedup;       // later copies of a hit do not vote (HOUGH_FLAG_DEDUP)
 };
 
 // Launch shape of the fused batch kernel (chosen by the host; see plan_batch()).
@@ -73,6 +81,10 @@ bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *w
                   SplitArgs *out);
 
 // Launchers (hough_kernels.hip).  All return a hipError_t from the launch.
+// Duplicate pass of the batch path: writes every keep byte of each well-formed event of at
+// most kMaxBatchHits hits, kKeepDuplicate for a later copy of a hit and 0 otherwise (all 0 for
+// events above kDedupMaxHits).
+hipError_t launch_dedup(const BatchArgs &a, hipStream_t s);
 hipError_t launch_vote(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                        void *acc, int acc_type, hipStream_t s);
 hipError_t launch_peaks(const GridArgs &g, const void *acc, int acc_type, hough_peak *peaks,

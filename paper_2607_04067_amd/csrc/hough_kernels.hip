@@ -36,6 +36,12 @@ __device__ __forceinline__ bool conformal(float x, float y, float &u, float &v) 
     return ok;
 }
 
+// The validity part of the map alone (no division).
+__device__ __forceinline__ bool valid_hit(float x, float y) {
+    const float r2 = __builtin_fmaf(x, x, y * y);
+    return (r2 > 0.0f) && (r2 <= FLT_MAX);
+}
+
 // True when every column's t lies strictly inside (0, n_rho).  |rho| <= sqrt(u^2 + v^2) for
 // every theta, so u^2 + v^2 below safe_r2 (set on the host with slack for the rounding of this
 // sum and of t) keeps every vote of the hit in range.
@@ -225,11 +231,12 @@ __device__ __forceinline__ void vote_staged(uint32_t *tile, const float2 *st, St
 }
 
 // Votes of hits [hb, he); returns the number of valid hits seen.  The next 64 hits are loaded
-// while the current ones vote.
+// while the current ones vote.  dup (duplicate suppression, else null): the event's keep bytes
+// as the duplicate pass left them; a later copy of a hit is counted as valid but not staged.
 template <int G, bool P, bool PER = false>
 __device__ uint32_t vote_range(uint32_t *tile, float2 *st, const float *x, const float *y,
                                uint32_t hb, uint32_t he, const Cols<G> &cl, const Lane<G, P> &ln,
-                               const GridArgs &g, int lane, uint32_t &bad) {
+                               const GridArgs &g, int lane, uint32_t &bad, const uint8_t *dup = nullptr) {
     uint32_t n_valid = 0;
     float xn = 0.0f, yn = 0.0f;
     if (hb + lane < he) { xn = x[hb + lane]; yn = y[hb + lane]; }
@@ -237,8 +244,14 @@ __device__ uint32_t vote_range(uint32_t *tile, float2 *st, const float *x, const
         const uint32_t i = base + lane;
         const float xi = xn, yi = yn;
         if (i + 64 < he) { xn = x[i + 64]; yn = y[i + 64]; }
+        bool live = i < he;
+        if (dup) {
+            const bool copy = live && (dup[i] & kKeepDuplicate) != 0;
+            n_valid += (uint32_t)__popcll(__ballot(copy && valid_hit(xi, yi)));
+            live = live && !copy;
+        }
         int slot;
-        const StageCount n = stage_values(st, xi, yi, i < he, g, bad, slot);
+        const StageCount n = stage_values(st, xi, yi, live, g, bad, slot);
         n_valid += n.total;
         vote_staged<G, P, PER>(tile, st, n, cl, ln, g.nrho_f);
         wave_sync();
@@ -505,8 +518,9 @@ __device__ __forceinline__ uint64_t lookup_staged(const uint32_t *dil, const flo
 __device__ __forceinline__ uint64_t low_bits(uint32_t n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
 
 // Hits of a wave's range that are valid and not yet kept, once there are at most 64 of them:
-// lane l holds one entry (an event-local hit index) while bit l of `live` is set.  Later tiles
-// look up only these instead of mapping the whole range again.
+// lane l holds one entry (an event-local hit index, bit 31 set for a later copy of a hit under
+// duplicate suppression) while bit l of `live` is set.  Later tiles look up only these instead
+// of mapping the whole range again.
 struct Pending {
     uint32_t idx;
     uint64_t live;   // wave-uniform
@@ -524,13 +538,14 @@ __device__ void build_pending(Pending &pd, float2 *st, const float *x, const flo
     uint32_t n = 0;
     for (uint32_t base = hb; base < he; base += 64) {
         const uint32_t i = base + lane;
-        const bool cand = (i < he) && ke[i] == 0u;
+        const uint32_t kv = (i < he) ? ke[i] : 1u;
+        const bool cand = (i < he) && !(kv & 1u);
         float xi = 0.0f, yi = 0.0f;
         if (cand) { xi = x[i]; yi = y[i]; }
         float u, v;
         const bool ok = conformal(xi, yi, u, v) && cand;
         const uint64_t b = __ballot(ok);
-        if (ok) st32[n + mbcnt(b)] = i;
+        if (ok) st32[n + mbcnt(b)] = i | ((kv & (uint32_t)kKeepDuplicate) << 30);
         n += (uint32_t)__popcll(b);
     }
     wave_sync();
@@ -549,16 +564,17 @@ __device__ uint32_t retain_pending(Pending &pd, const uint32_t *dil, float2 *st,
     if (pd.live == 0ull) return 0u;
     const bool me = (pd.live >> lane) & 1ull;
     const uint32_t pos = mbcnt(pd.live);
+    const uint32_t idx = pd.idx & 0x7fffffffu;
     if (me) {
         float u, v;
-        (void)conformal(x[pd.idx], y[pd.idx], u, v);
+        (void)conformal(x[idx], y[idx], u, v);
         st[pos] = make_float2(u, v);
     }
     wave_sync();
     const uint64_t kept = lookup_staged<G>(dil, st, StageCount{0u, (uint32_t)__popcll(pd.live)}, cl,
                                            lane, g.nrho_f);
     const bool k_me = me && ((kept >> pos) & 1ull);
-    if (k_me) ke[pd.idx] = 1u;
+    if (k_me) ke[idx] = (uint8_t)(1u | ((pd.idx >> 30) & (uint32_t)kKeepDuplicate));
     const uint64_t kept_lanes = __ballot(k_me);
     pd.live &= ~kept_lanes;
     wave_sync();
@@ -577,12 +593,13 @@ __device__ uint32_t retain_range(const uint32_t *dil, float2 *st, const float *x
     left = 0;
     for (uint32_t base = hb; base < he; base += 64) {
         const uint32_t i = base + lane;
-        const bool done = (i < he) && ke[i] != 0u;
+        const uint32_t kv = (i < he) ? ke[i] : 1u;
+        const bool done = (i < he) && (kv & 1u);
         if (__ballot((i < he) && !done) == 0ull) continue;      // whole chunk already kept
         int slot;
         const StageCount n = stage_hits(st, x, y, base, he, done, g, lane, unused, slot);
         const uint64_t kept = lookup_staged<G>(dil, st, n, cl, lane, g.nrho_f);
-        if (slot >= 0 && ((kept >> slot) & 1ull)) ke[i] = 1u;
+        if (slot >= 0 && ((kept >> slot) & 1ull)) ke[i] = (uint8_t)(kv | 1u);
         const uint32_t nk = (uint32_t)__popcll(kept);
         newly += nk;
         left += n.total - nk;
@@ -1077,8 +1094,13 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
         const uint32_t cap = pe ? a.max_peaks : 0u;
         uint32_t bad = 0;
         uint8_t *ke = a.keep + (a.ids ? (uint32_t)__builtin_amdgcn_readfirstlane((int)a.keep_offsets[e]) : h0);
+        // with duplicate suppression the duplicate pass has written every keep byte already
+        if (!g.dedup) {
 #pragma unroll 1
-        for (uint32_t i = hb + lane; i < he; i += 64) ke[i] = 0u;
+            for (uint32_t i = hb + lane; i < he; i += 64) ke[i] = 0u;
+        } else if (H > kDedupMaxHits && threadIdx.x == 0) {
+            atomicOr(&s_flags, HOUGH_EV_DEDUP_SKIPPED);
+        }
         Pending pd;
         pd.idx = 0u;
         pd.live = 0ull;
@@ -1086,7 +1108,8 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
         for (int t = 0; t < n_tiles; ++t) {
             const int first = t * OUT - 1;      // grid column of lane 0 of group 0
             const Cols<G> cl = load_cols<G, PER>(g, first, lane, ST, ln.col);
-            const uint32_t nv = vote_range<G, true, PER>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad);
+            const uint32_t nv = vote_range<G, true, PER>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad,
+                                                         g.dedup ? ke : nullptr);
             if (t == 0 && lane == 0 && nv) atomicAdd(&s_nvalid, nv);
             __syncthreads();
             for (int u = wave; u < 2 * nwords; u += NW) {
@@ -1139,6 +1162,13 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             __syncthreads();
         }
         if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
+        if (g.dedup) {                       // drop the later-copy bit, leaving the kept bit
+#pragma unroll 1
+            for (uint32_t i = hb + lane; i < he; i += 64) {
+                const uint32_t v = ke[i];
+                if (v & kKeepDuplicate) ke[i] = (uint8_t)(v & 1u);
+            }
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             const uint32_t np = s_npeaks;
@@ -1234,16 +1264,19 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
         const bool malformed = h1 < h0;
         const uint32_t H = malformed ? 0u : h1 - h0;
         uint32_t *bits = sp.kept + (size_t)e * kSplitKeepWords;
+        uint8_t *ke = a.keep + (a.ids ? (uint32_t)__builtin_amdgcn_readfirstlane((int)a.keep_offsets[e]) : h0);
         if (malformed || H > kMaxBatchHits) {
             if (threadIdx.x == 0 && t == 0) s_flags = HOUGH_EV_TOO_MANY_HITS;
         } else if (H > 0) {
+            if (g.dedup && H > kDedupMaxHits && threadIdx.x == 0 && t == 0) atomicOr(&s_flags, HOUGH_EV_DEDUP_SKIPPED);
             const uint32_t hb = (uint32_t)((uint64_t)H * wave / NW);
             const uint32_t he = (uint32_t)((uint64_t)H * (wave + 1) / NW);
             const float *xe = a.x + h0, *ye = a.y + h0;
             uint32_t bad = 0;
             const int first = (int)t * OUT - 1;
             const Cols<G> cl = load_cols<G, PER>(g, first, lane, ST, ln.col);
-            vote_range<G, true, PER>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad);
+            vote_range<G, true, PER>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad,
+                                     g.dedup ? ke : nullptr);
             if (t == 0 && __ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
             __syncthreads();
             for (int u = wave; u < 2 * nwords; u += NW) {
@@ -1329,7 +1362,6 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
             const uint32_t total = run;                       // the event's true peak count
             const uint32_t fl = __hip_atomic_load(&sp.flags[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!malformed) {                     // malformed offsets: touch nothing but the counters
-                uint8_t *ke = a.keep + (a.ids ? a.keep_offsets[e] : h0);
                 const bool skipped = H > kMaxBatchHits;
                 for (uint32_t i = threadIdx.x; i < H; i += NT)
                     ke[i] = skipped ? (uint8_t)0 : (uint8_t)((bits[i >> 5] >> (i & 31)) & 1u);
@@ -1346,6 +1378,71 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
             }
         }
         __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ duplicate pass (HOUGH_FLAG_DEDUP)
+// One workgroup per event.  Open addressing in LDS keyed by the bits of (x, y): every slot ends
+// holding the smallest event-local index of its key (compare-and-swap into an empty slot, atomic
+// min into a slot of the same key), so after the inserts a hit is a later copy iff the slot of
+// its key holds another index.  The table has at least twice as many slots as hits, so every
+// probe sequence meets its key or an empty slot; entries never empty again, so a lookup finds
+// its key before any empty slot.  The probe loops are bounded by the table size all the same.
+constexpr int kDedupThreads = 512;
+constexpr uint32_t kEmptySlot = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t dedup_hash(uint32_t kx, uint32_t ky) {
+    uint32_t h = kx * 0x9e3779b1u;
+    h ^= ky + 0x7f4a7c15u + (h << 6) + (h >> 2);
+    h *= 0x85ebca6bu;
+    return h ^ (h >> 16);
+}
+
+__global__ __launch_bounds__(kDedupThreads) void k_dedup(BatchArgs a) {
+    __shared__ uint32_t tab[kDedupSlots];
+    const uint32_t e = blockIdx.x;
+    const uint32_t pe_id = a.ids ? a.ids[e] : e;
+    const uint32_t h0 = a.offsets[pe_id], h1 = a.offsets[pe_id + 1];
+    if (h1 < h0) return;                                   // malformed: the batch kernel flags it
+    const uint32_t H = h1 - h0;
+    if (H == 0 || H > kMaxBatchHits) return;               // too many: the batch kernel zeroes keep
+    uint8_t *ke = a.keep + (a.ids ? a.keep_offsets[e] : h0);
+    const uint32_t *xb = reinterpret_cast<const uint32_t *>(a.x) + h0;
+    const uint32_t *yb = reinterpret_cast<const uint32_t *>(a.y) + h0;
+    if (H > kDedupMaxHits) {                               // every hit votes
+        for (uint32_t i = threadIdx.x; i < H; i += kDedupThreads) ke[i] = 0u;
+        return;
+    }
+    uint32_t slots = 64;
+    while (slots < 2 * H) slots <<= 1;                     // <= kDedupSlots
+    const uint32_t mask = slots - 1;
+    for (uint32_t q = threadIdx.x; q < slots; q += kDedupThreads) tab[q] = kEmptySlot;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < H; i += kDedupThreads) {
+        const uint32_t kx = xb[i], ky = yb[i];
+        uint32_t q = dedup_hash(kx, ky) & mask;
+        for (uint32_t probe = 0; probe < slots; ++probe, q = (q + 1) & mask) {
+            const uint32_t cur = atomicCAS(&tab[q], kEmptySlot, i);
+            if (cur == kEmptySlot) break;                  // first of its key so far
+            if (cur < H && xb[cur] == kx && yb[cur] == ky) {
+                atomicMin(&tab[q], i);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < H; i += kDedupThreads) {
+        const uint32_t kx = xb[i], ky = yb[i];
+        uint32_t q = dedup_hash(kx, ky) & mask, first = i;
+        for (uint32_t probe = 0; probe < slots; ++probe, q = (q + 1) & mask) {
+            const uint32_t cur = tab[q];
+            if (cur >= H) break;                           // cannot happen (see above)
+            if (xb[cur] == kx && yb[cur] == ky) {
+                first = cur;
+                break;
+            }
+        }
+        ke[i] = first != i ? kKeepDuplicate : (uint8_t)0;
     }
 }
 
@@ -1393,6 +1490,12 @@ int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, 
     p.grid = 0;
     *out = p;
     return 0;
+}
+
+hipError_t launch_dedup(const BatchArgs &a, hipStream_t s) {
+    if (a.n_events == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dedup, dim3(a.n_events), dim3(kDedupThreads), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_vote(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,

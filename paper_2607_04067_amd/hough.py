@@ -21,6 +21,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "hough.h")
 HOUGH_OK, HOUGH_EINVAL, HOUGH_ENOMEM, HOUGH_EOVERFLOW, HOUGH_EDEVICE = 0, -1, -2, -3, -4
 ACC_U16, ACC_I32 = 1, 2
 EV_PEAKS_TRUNCATED, EV_INVALID_HITS, EV_TOO_MANY_HITS, EV_TOO_MANY_CANDIDATES = 1, 2, 4, 8
+EV_DEDUP_SKIPPED = 16
 
 
 class HoughError(RuntimeError):
@@ -43,6 +44,7 @@ class hough_params(ctypes.Structure):
 
 
 FLAG_THETA_PERIODIC = 1
+FLAG_DEDUP = 2
 
 
 _lib = None
@@ -73,6 +75,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.hough_track_params.restype = i32
     L.hough_max_iterative_candidates.argtypes = []
     L.hough_max_iterative_candidates.restype = u32
+    L.hough_max_dedup_hits.argtypes = []
+    L.hough_max_dedup_hits.restype = u32
     L.hough_retain.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp]
     L.hough_retain.restype = i32
     L.hough_run_batch.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp]
@@ -156,12 +160,13 @@ class Context:
     """One configured (theta, rho) grid on the current GPU (wraps hough_ctx)."""
 
     def __init__(self, n_theta: int, n_rho: int, rho_min: float, rho_max: float, acc_type: str = "i32",
-                 threshold: int = 1, rho_window: int = 1, max_peaks: int = 0, periodic: bool = False):
+                 threshold: int = 1, rho_window: int = 1, max_peaks: int = 0, periodic: bool = False,
+                 dedup: bool = False):
         self._lib = load()
         self.params = hough_params(int(n_theta), int(n_rho), float(rho_min), float(rho_max),
                                    ACC_U16 if acc_type == "u16" else ACC_I32, int(threshold),
                                    int(rho_window), int(max_peaks),
-                                   FLAG_THETA_PERIODIC if periodic else 0, 0)
+                                   (FLAG_THETA_PERIODIC if periodic else 0) | (FLAG_DEDUP if dedup else 0), 0)
         self.acc_type = acc_type
         self._ctx = ctypes.c_void_p()
         _check(self._lib.hough_config(ctypes.byref(self.params), ctypes.byref(self._ctx)), "hough_config")
@@ -169,10 +174,10 @@ class Context:
 
     @classmethod
     def for_workload(cls, wl, max_peaks: int = 4096, threshold: int | None = None,
-                     rho_window: int | None = None, periodic: bool = False) -> "Context":
+                     rho_window: int | None = None, periodic: bool = False, dedup: bool = False) -> "Context":
         return cls(wl.n_theta, wl.n_rho, wl.rho_min, wl.rho_max, wl.acc,
                    wl.threshold if threshold is None else threshold,
-                   wl.rho_window if rho_window is None else rho_window, max_peaks, periodic)
+                   wl.rho_window if rho_window is None else rho_window, max_peaks, periodic, dedup)
 
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx.value:

@@ -757,3 +757,114 @@ def test_split_form_edge_events_plans_and_periodic(H, orc):
             assert all(torch.equal(a, b) for a, b in zip(ref, out)), (periodic, w, gr)
             assert int(ws.count_nonzero()) == 0
         ctx.close()
+
+
+# ------------------------------------------------------------ duplicate suppression (HOUGH_FLAG_DEDUP)
+def _dup_events():
+    """Events built around repeated hits: real curler events, every hit three times (interleaved
+    and in runs), one hit many times, NaN copies, -0.0 beside 0.0, and an event above the
+    duplicate pass's limit."""
+    rng = np.random.default_rng(31)
+    evs = []
+    ev = synth.make_events("paper-1000ev-360x256", 9, n_events=3)
+    evs += [ev.event(e) for e in range(3)]
+    x, y = synth.random_hits(400, seed=32)
+    evs.append((np.tile(x, 3), np.tile(y, 3)))
+    evs.append((np.repeat(x, 3), np.repeat(y, 3)))
+    evs.append((np.full(50, 300.0, np.float32), np.full(50, -250.0, np.float32)))
+    xs, ys = synth.random_hits(100, seed=33)
+    xs = np.concatenate([xs, np.float32([np.nan, np.nan, 0.0, -0.0, 0.0])])
+    ys = np.concatenate([ys, np.float32([1.0, 1.0, 350.0, 350.0, 350.0])])
+    perm = rng.permutation(xs.size)
+    evs.append((xs[perm], ys[perm]))
+    evs.append((np.zeros(0, np.float32), np.zeros(0, np.float32)))
+    evs.append((np.float32([250.0]), np.float32([400.0])))
+    big_x, big_y = synth.random_hits(9000, seed=34)            # above the duplicate pass's limit
+    evs.append((np.concatenate([big_x, big_x[:100]]), np.concatenate([big_y, big_y[:100]])))
+    dense = synth.make_events("dense-2000ev-720x512", 9, n_events=1)
+    evs.append(dense.event(0))
+    x = np.concatenate([a for a, _ in evs]).astype(np.float32)
+    y = np.concatenate([b for _, b in evs]).astype(np.float32)
+    off = np.zeros(len(evs) + 1, np.uint32)
+    off[1:] = np.cumsum([a.size for a, _ in evs])
+    return x, y, off
+
+
+@pytest.mark.parametrize("n_theta,n_rho,lo,hi,T", [(360, 256, -1 / 200, 1 / 200, 10), (180, 128, -1 / 200, 1 / 200, 8),
+                                                   (720, 512, -1 / 200, 1 / 200, 12), (125, 100, -0.005, 0.005, 3)])
+def test_dedup_batch_parity_with_oracle(H, orc, n_theta, n_rho, lo, hi, T):
+    import torch
+    g = orc.Grid(n_theta, n_rho, lo, hi)
+    x, y, off = _dup_events()
+    limit = int(H.load().hough_max_dedup_hits())
+    sizes = np.diff(off.astype(np.int64))
+    xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
+    for periodic in (False, True):
+        ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, 1, 20000, periodic=periodic, dedup=True)
+        say(f"dedup {n_theta}x{n_rho} T={T} periodic={periodic}")
+        pk, npk, keep, st = ctx.run_batch(xt, yt, ot)
+        torch.cuda.synchronize()
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=T, rho_window=1, cap=20000, n_threads=8,
+                                                periodic=periodic, dedup=True)
+        pk_all, n_all, keep_all = orc.run_batch(g, x, y, off, threshold=T, rho_window=1, cap=20000, n_threads=8,
+                                                periodic=periodic)
+        big = sizes > limit
+        n_want = np.where(big, n_all, n_ref)
+        npk = npk.cpu().numpy()[:len(sizes)].astype(np.int64)
+        assert np.array_equal(npk, n_want)
+        keep_np = keep.cpu().numpy()
+        p = pk.cpu().numpy()
+        for e in range(len(sizes)):
+            a, b = int(off[e]), int(off[e + 1])
+            want_keep = keep_all[a:b] if big[e] else keep_ref[a:b]
+            assert np.array_equal(keep_np[a:b], want_keep), e
+            m = int(min(n_want[e], 20000))
+            want = (pk_all if big[e] else pk_ref)[e, :m]
+            assert np.array_equal(H.decode_peaks(p[e], m), want.astype(np.int64)), e
+        stn = st.cpu().numpy()[:len(sizes)]
+        assert np.array_equal((stn & H.EV_DEDUP_SKIPPED) != 0, big)
+        assert int(keep_np.max()) <= 1
+        # the split form and the gather form agree with the fused kernel
+        ws = ctx.split_workspace(len(sizes))
+        out = ctx.run_batch_split(xt, yt, ot, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(out[1][:len(sizes)].cpu(), torch.from_numpy(npk.astype(np.int32)))
+        assert torch.equal(out[3], st) and torch.equal(out[2], keep)
+        ids = np.array([6, 0, 3, 3, 10], np.int64)
+        koff = np.concatenate([[0], np.cumsum(sizes[ids])[:-1]]).astype(np.int32)
+        gk = ctx.run_batch_gather(xt, yt, ot, _t(ids.astype(np.int32)), _t(koff), keep_size=int(sizes[ids].sum()))
+        torch.cuda.synchronize()
+        for j, e in enumerate(ids):
+            a, b = int(off[e]), int(off[e + 1])
+            assert np.array_equal(gk[2].cpu().numpy()[koff[j]:koff[j] + (b - a)], keep_np[a:b])
+            assert int(gk[1][j]) == int(npk[e])
+        ctx.close()
+
+
+def test_dedup_workloads_equal_oracle(H, orc):
+    """Real events (curlers fire the same wires on every turn) on every workload grid."""
+    import torch
+    for name, n in [("paper-1000ev-360x256", 24), ("dense-2000ev-720x512", 4), ("paper-1000ev-1000x1000", 4),
+                    ("plain-16ev-180x128", 16)]:
+        wl = synth.WORKLOADS[name]
+        g = orc.Grid.of(wl)
+        ev = synth.make_events(wl, 12, n_events=n)
+        ctx = H.Context.for_workload(wl, max_peaks=20000, threshold=max(wl.threshold, 20), dedup=True)
+        say(f"dedup workload {name}")
+        xt, yt, ot = H.to_device(ev)
+        pk, npk, keep, st = ctx.run_batch(xt, yt, ot)
+        torch.cuda.synchronize()
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, ev.x, ev.y, ev.offsets, threshold=max(wl.threshold, 20),
+                                                rho_window=1, cap=20000, n_threads=8, dedup=True)
+        assert np.array_equal(npk.cpu().numpy()[:n].astype(np.int64), n_ref)
+        assert np.array_equal(keep.cpu().numpy(), keep_ref)
+        assert int(st.cpu().numpy()[:n].max()) == 0
+        ctx.close()
+
+
+def test_dedup_context_rejected_by_the_per_event_vote(H):
+    ctx = H.Context(180, 128, -0.005, 0.005, "i32", 8, 1, 64, dedup=True)
+    x, y = synth.random_hits(10, seed=1)
+    with pytest.raises(H.HoughError):
+        ctx.vote(_t(x), _t(y))
+    ctx.close()
