@@ -319,6 +319,7 @@ def end_to_end(H, ctx, wl, ev, reps: int = 10):
         ms = float(np.median(times))
         out[key] = {"ms": round(ms, 4), "events_per_s": round(E / (ms / 1e3), 1)}
     out["with_peak_buffer"]["d2h_peak_bytes"] = E * cap * 8
+
     return out
 
 
