@@ -868,3 +868,56 @@ def test_dedup_context_rejected_by_the_per_event_vote(H):
     with pytest.raises(H.HoughError):
         ctx.vote(_t(x), _t(y))
     ctx.close()
+
+
+def test_random_configurations(H, orc):
+    """Seeded random grids, ranges, thresholds, windows, capacities and options against the
+    oracle: fused and split forms, bit for bit."""
+    import torch
+    rng = np.random.default_rng(2024)
+    pool = synth.make_events("paper-1000ev-360x256", 17, n_events=6)
+    for case in range(20):
+        n_theta = int(rng.integers(1, 420))
+        n_rho = int(rng.integers(1, 600))
+        periodic = bool(rng.random() < 0.3) and n_theta >= 2
+        if periodic:
+            hi = float(rng.uniform(0.001, 0.008)); lo = -hi
+        else:
+            lo = float(rng.uniform(-0.008, 0.002)); hi = lo + float(rng.uniform(0.0005, 0.012))
+        T = int(rng.integers(1, 30))
+        W = int(rng.choice([0, 1, 2, 5, 31, 33]))
+        cap = int(rng.choice([0, 1, 7, 300, 5000]))
+        dedup = bool(rng.random() < 0.3)
+        evs = [pool.event(int(e)) for e in rng.integers(0, 6, 3)]
+        evs.append(synth.random_hits(int(rng.integers(0, 700)), seed=case, r_lo=120.0, r_hi=900.0))
+        x = np.concatenate([a for a, _ in evs]).astype(np.float32)
+        y = np.concatenate([b for _, b in evs]).astype(np.float32)
+        off = np.zeros(len(evs) + 1, np.uint32)
+        off[1:] = np.cumsum([a.size for a, _ in evs])
+        g = orc.Grid(n_theta, n_rho, lo, hi)
+        try:
+            ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, W, cap, periodic=periodic, dedup=dedup)
+        except H.HoughError:
+            continue                                   # beyond the LDS limit for n_rho
+        say(f"random case {case}: {n_theta}x{n_rho} [{lo:.4f},{hi:.4f}) T={T} W={W} cap={cap} "
+            f"periodic={periodic} dedup={dedup}")
+        xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
+        pk, npk, keep, st = (t.clone() for t in ctx.run_batch(xt, yt, ot))
+        ws = ctx.split_workspace(len(evs))
+        sp = ctx.run_batch_split(xt, yt, ot, ws)
+        torch.cuda.synchronize()
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=T, rho_window=W, cap=max(cap, 1),
+                                                n_threads=8, periodic=periodic, dedup=dedup)
+        E = len(evs)
+        assert np.array_equal(npk.cpu().numpy()[:E].astype(np.int64), n_ref), case
+        assert np.array_equal(keep.cpu().numpy(), keep_ref), case
+        assert np.array_equal((st.cpu().numpy()[:E] & H.EV_PEAKS_TRUNCATED) != 0, n_ref > cap), case
+        p = pk.cpu().numpy()
+        for e in range(E):
+            m = int(min(n_ref[e], cap))
+            if m:
+                assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), (case, e)
+        assert torch.equal(sp[1], npk) and torch.equal(sp[2], keep) and torch.equal(sp[3], st), case
+        if cap:
+            assert torch.equal(sp[0], pk), case
+        ctx.close()
