@@ -225,6 +225,26 @@ int hough_run_batch_split(hough_ctx *ctx, const float *x, const float *y, const 
                           hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
                           void *workspace, size_t workspace_bytes, void *stream);
 
+/* The paper's peak finder over a batch of CSR events (as hough_run_batch takes them): steps
+ * 1-3 into one 16-bit accumulator per event in `workspace` (device, 256-byte aligned, at least
+ * hough_iterative_workspace_bytes(ctx, n_events) bytes, contents not preserved), then
+ * hough_peaks_iterative's finder per event (same frac, r_theta, r_rho and threshold floor),
+ * then retention (as hough_retain) with each event's first min(n_peaks, max_peaks) peaks.
+ * peaks (device): max_peaks records per event, in extraction order; n_peaks[e] the true count;
+ * keep[offsets[0] .. offsets[n_events]] one byte per hit; status[e] the HOUGH_EV_* bits
+ * (HOUGH_EV_TOO_MANY_CANDIDATES: no peak listed, nothing kept).  Events above
+ * hough_max_batch_hits() hits are skipped as in hough_run_batch; HOUGH_FLAG_DEDUP applies.
+ * Four kernel launches per call.  Accumulators go through HBM (n_theta * n_rho * 2 bytes per
+ * event), so this is the per-event path's work done for the whole batch at once, not the fused
+ * kernel. */
+int hough_run_batch_iterative(hough_ctx *ctx, const float *x, const float *y, const uint32_t *offsets,
+                              uint32_t n_events, uint32_t frac_num, uint32_t frac_den, int32_t r_theta,
+                              int32_t r_rho, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
+                              uint32_t *status, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes hough_run_batch_iterative needs for n_events events (0 for a NULL context). */
+size_t hough_iterative_workspace_bytes(const hough_ctx *ctx, uint32_t n_events);
+
 /* Largest event (hits) whose duplicates HOUGH_FLAG_DEDUP suppresses. */
 uint32_t hough_max_dedup_hits(void);
 

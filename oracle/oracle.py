@@ -249,5 +249,28 @@ def run_batch(wl_or_grid, x, y, offsets, threshold: int | None = None, rho_windo
     return out[:E], n_peaks[:E], keep[:x.size]
 
 
+def run_batch_iterative(g: Grid, x, y, offsets, t_abs: int, frac: tuple[int, int], r_theta: int, r_rho: int,
+                        rho_window: int, cap: int, dedup: bool = False):
+    """The paper's finder over CSR events, one event at a time: vote (only first copies with
+    dedup), iterative extraction (Sec. II, reading of the relative threshold and suppression),
+    then retention with the event's first min(n, cap) peaks.  Returns (peaks[E, cap, 3] as
+    (j, k, count) in extraction order, n[E], keep[H])."""
+    x, y = _f32(x), _f32(y)
+    offsets = np.asarray(offsets, np.int64)
+    E = offsets.size - 1
+    out = np.zeros((max(E, 1), max(cap, 1), 3), np.int32)
+    n = np.zeros(max(E, 1), np.int64)
+    keep = np.zeros(max(x.size, 1), np.uint8)
+    for e in range(E):
+        a, b = int(offsets[e]), int(offsets[e + 1])
+        acc = vote_dedup(g, x[a:b], y[a:b]) if dedup else vote(g, x[a:b], y[a:b])
+        pj, pk, pc, m = peaks_iterative(acc, t_abs, frac, r_theta, r_rho, cap=max(cap, 1))
+        k = min(m, cap)
+        n[e] = m
+        out[e, :k] = np.stack([pj[:k], pk[:k], pc[:k]], 1)
+        keep[a:b] = retain(g, x[a:b], y[a:b], pj[:k], pk[:k], rho_window)
+    return out[:E], n[:E], keep[:x.size]
+
+
 def max_threads() -> int:
     return int(lib().oracle_max_threads())

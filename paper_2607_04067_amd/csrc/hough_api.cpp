@@ -263,6 +263,42 @@ int hough_peaks_iterative(hough_ctx *c, const void *acc, uint32_t frac_num, uint
 
 uint32_t hough_max_iterative_candidates(void) { return 16384u; }
 
+size_t hough_iterative_workspace_bytes(const hough_ctx *c, uint32_t n_events) {
+    if (!c) return 0;
+    return (size_t)n_events * (size_t)c->p.n_theta * (size_t)c->p.n_rho * sizeof(uint16_t);
+}
+
+int hough_run_batch_iterative(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,
+                              uint32_t n_events, uint32_t frac_num, uint32_t frac_den, int32_t r_theta,
+                              int32_t r_rho, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
+                              uint32_t *status, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!c) return HOUGH_EINVAL;
+    if (!on_device(c)) return HOUGH_EINVAL;
+    if (frac_den == 0 || r_theta < 0 || r_rho < 0) return HOUGH_EINVAL;
+    if (n_events == 0) return HOUGH_OK;
+    if (!x || !y || !offsets || !n_peaks || !keep || !status || !workspace) return HOUGH_EINVAL;
+    if (c->p.max_peaks > 0 && !peaks) return HOUGH_EINVAL;
+    if (((uintptr_t)peaks & 7u) != 0 || ((uintptr_t)workspace & 255u) != 0) return HOUGH_EINVAL;
+    if (workspace_bytes < hough_iterative_workspace_bytes(c, n_events)) return HOUGH_EINVAL;
+    if (hough::peaks_iterative_lds_bytes() > c->lds_limit) return HOUGH_EDEVICE;
+    hough::BatchArgs a;
+    a.x = x;
+    a.y = y;
+    a.offsets = offsets;
+    a.ids = nullptr;
+    a.keep_offsets = nullptr;
+    a.n_events = n_events;
+    a.peaks = c->p.max_peaks > 0 ? peaks : nullptr;
+    a.n_peaks = n_peaks;
+    a.keep = keep;
+    a.status = status;
+    a.max_peaks = (uint32_t)c->p.max_peaks;
+    a.queue = nullptr;
+    const hipError_t e = hough::launch_batch_iterative(c->g, a, static_cast<uint16_t *>(workspace), frac_num,
+                                                       frac_den, r_theta, r_rho, (hipStream_t)stream);
+    return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
+}
+
 int hough_track_params(hough_ctx *c, const float *x, const float *y, uint32_t n_hits,
                        const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
                        double b_tesla, hough_track *tracks, void *stream) {

@@ -85,6 +85,10 @@ bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *w
 // most kMaxBatchHits hits, kKeepDuplicate for a later copy of a hit and 0 otherwise (all 0 for
 // events above kDedupMaxHits).
 hipError_t launch_dedup(const BatchArgs &a, hipStream_t s);
+// The iterative finder over a CSR batch (a.ids must be null): acc holds n_events accumulators
+// of n_theta * n_rho 16-bit cells.
+hipError_t launch_batch_iterative(const GridArgs &g, const BatchArgs &a, uint16_t *acc, uint32_t frac_num,
+                                  uint32_t frac_den, int r_theta, int r_rho, hipStream_t s);
 hipError_t launch_vote(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                        void *acc, int acc_type, hipStream_t s);
 hipError_t launch_peaks(const GridArgs &g, const void *acc, int acc_type, hough_peak *peaks,

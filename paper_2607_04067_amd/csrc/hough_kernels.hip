@@ -614,16 +614,16 @@ __device__ uint32_t retain_range(const uint32_t *dil, float2 *st, const float *x
 // count then fits 16 bits); each chunk's tile is written out (first chunk) or added (later
 // chunks) to acc, each element by the one thread that owns it.
 template <int NW>
-__global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__restrict__ x,
-                                                  const float *__restrict__ y, uint32_t n_hits,
-                                                  void *acc, int acc_type) {
+__device__ uint32_t vote_group_to_acc(const GridArgs &g, const float *__restrict__ x,
+                                      const float *__restrict__ y, uint32_t n_hits, void *acc,
+                                      int acc_type, int group, const uint8_t *dup) {
     using L = Lane<1, true>;
     constexpr uint32_t kChunk = 65535u;
     extern __shared__ __align__(16) uint32_t lds[];
     uint32_t *tile = lds;                                                  // [(n_rho + 1) * 32]
     float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * L::STRIDE);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int first = blockIdx.x * 64;
+    const int first = group * 64;
     const L ln(lane);
     const Cols<1> cl = load_cols<1>(g, first, lane, L::STRIDE, ln.col);
     const int j = first + lane;
@@ -637,7 +637,7 @@ __global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__res
         __syncthreads();
         const uint32_t hb = c0 + (uint32_t)((uint64_t)(c1 - c0) * wave / NW);
         const uint32_t he = c0 + (uint32_t)((uint64_t)(c1 - c0) * (wave + 1) / NW);
-        vote_range<1, true>(tile, stage + wave * 64, x, y, hb, he, cl, ln, g, lane, bad);
+        vote_range<1, true>(tile, stage + wave * 64, x, y, hb, he, cl, ln, g, lane, bad, dup);
         __syncthreads();
         // write-out: lane = column (theta row of acc), wave = a slice of rho
         if (j < g.n_theta) {
@@ -658,6 +658,45 @@ __global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__res
         __syncthreads();
         c0 = c1;
     } while (c0 < n_hits);
+    return bad;
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__restrict__ x,
+                                                  const float *__restrict__ y, uint32_t n_hits,
+                                                  void *acc, int acc_type) {
+    (void)vote_group_to_acc<NW>(g, x, y, n_hits, acc, acc_type, (int)blockIdx.x, nullptr);
+}
+
+// Steps 1-3 for a batch of CSR events into per-event 16-bit accumulators (the iterative
+// finder's batch form): workgroup (event, 64-column group).  Group 0 writes the event's status
+// (invalid hits, too many hits, duplicate pass skipped); the later kernels OR into it.  An event
+// above kMaxBatchHits hits, or with malformed offsets, gets no accumulator.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_vote_batch(GridArgs g, const float *__restrict__ x,
+                                                        const float *__restrict__ y,
+                                                        const uint32_t *__restrict__ offsets,
+                                                        uint16_t *acc, const uint8_t *keep,
+                                                        uint32_t *status) {
+    const uint32_t e = blockIdx.x;
+    const uint32_t h0 = offsets[e], h1 = offsets[e + 1];
+    const bool ok = h1 >= h0 && h1 - h0 <= kMaxBatchHits;
+    if (!ok) {
+        if (blockIdx.y == 0 && threadIdx.x == 0) status[e] = HOUGH_EV_TOO_MANY_HITS;
+        return;
+    }
+    const uint32_t H = h1 - h0;
+    const size_t cells = (size_t)g.n_theta * (size_t)g.n_rho;
+    const uint32_t bad = vote_group_to_acc<NW>(g, x + h0, y + h0, H, acc + (size_t)e * cells, HOUGH_ACC_U16,
+                                               (int)blockIdx.y, g.dedup ? keep + h0 : nullptr);
+    __shared__ uint32_t s_bad;
+    if (threadIdx.x == 0) s_bad = 0u;
+    __syncthreads();
+    if (bad) s_bad = 1u;
+    __syncthreads();
+    if (blockIdx.y == 0 && threadIdx.x == 0)
+        status[e] = (s_bad ? HOUGH_EV_INVALID_HITS : 0u) |
+                    (g.dedup && H > kDedupMaxHits ? HOUGH_EV_DEDUP_SKIPPED : 0u);
 }
 
 // hough_peaks: one workgroup; rows are staged NW at a time (plus one halo row on each side)
@@ -751,12 +790,16 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return v;
 }
 
+// offsets (batch form, else null): workgroup e takes event e's accumulator at acc + e * cells,
+// writes its list at out + e * cap, n_peaks[e], and ORs its bits into status[e] (which the
+// batch vote wrote), adding HOUGH_EV_PEAKS_TRUNCATED; events the vote skipped get no peaks.
 template <typename T>
 __global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, const T *__restrict__ acc,
                                                                 uint32_t frac_num, uint32_t frac_den,
                                                                 int r_theta, int r_rho, hough_peak *out,
                                                                 uint32_t cap, uint32_t *n_peaks,
-                                                                uint32_t *status) {
+                                                                uint32_t *status,
+                                                                const uint32_t *offsets = nullptr) {
     extern __shared__ __align__(16) uint64_t keys[];            // [kIterCandidates]
     __shared__ uint32_t s_red[kIterWaves];
     __shared__ uint32_t s_nc, s_nk;
@@ -764,6 +807,19 @@ __global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, cons
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t nr = (uint32_t)g.n_rho;
     const uint32_t cells = (uint32_t)g.n_theta * nr;
+    const bool batch = offsets != nullptr;
+    if (batch) {
+        const uint32_t e = blockIdx.x;
+        acc += (size_t)e * cells;
+        out = out ? out + (size_t)e * cap : nullptr;
+        n_peaks += e;
+        status += e;
+        const uint32_t h0 = offsets[e], h1 = offsets[e + 1];
+        if (h1 < h0 || h1 - h0 > kMaxBatchHits) {              // no accumulator was written
+            if (tid == 0) *n_peaks = 0u;
+            return;
+        }
+    }
     const uint32_t floor_t = g.threshold;
     if (tid == 0) { s_nc = 0u; s_nk = 0u; }
     __syncthreads();
@@ -852,7 +908,10 @@ __global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, cons
     __syncthreads();
     const uint32_t nc = s_nk;
     if (nc > kIterCandidates) {
-        if (tid == 0) { *n_peaks = 0u; *status = HOUGH_EV_TOO_MANY_CANDIDATES; }
+        if (tid == 0) {
+            *n_peaks = 0u;
+            *status = (batch ? *status : 0u) | HOUGH_EV_TOO_MANY_CANDIDATES;
+        }
         return;
     }
     // bitonic sort, descending, over the next power of two
@@ -903,7 +962,10 @@ __global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, cons
         }
         wave_sync();
     }
-    if (lane == 0) { *n_peaks = taken; *status = 0u; }
+    if (lane == 0) {
+        *n_peaks = taken;
+        *status = batch ? (*status | (taken > cap ? HOUGH_EV_PEAKS_TRUNCATED : 0u)) : 0u;
+    }
 }
 
 // hough_track_params: one wave per peak.  The lanes sweep the event's hits 64 at a time and
@@ -964,18 +1026,40 @@ __global__ __launch_bounds__(kTrackWaves * 64) void k_track_params(GridArgs g, c
 // hough_retain: one thread per hit.  Peak rows are processed in blocks that fit LDS: for
 // each block a dilated bitmap (bit k of row j set iff a peak (j, k') has |k - k'| <= W) is
 // built from the peak list, then every unkept hit looks up its own bin in each peak row.
+// offsets (batch form, else null): workgroup (e, b) covers hits b*NW*64 ... of event e, with
+// event e's peak list at peaks + e * cap and n_peaks[e]; the keep bytes of an event the vote
+// skipped for its size are zeroed (malformed offsets: nothing is touched).
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__restrict__ x,
                                                     const float *__restrict__ y, uint32_t n_hits,
                                                     const hough_peak *__restrict__ peaks,
                                                     const uint32_t *n_peaks, uint32_t cap,
-                                                    uint8_t *keep, int rows_per_block) {
+                                                    uint8_t *keep, int rows_per_block,
+                                                    const uint32_t *offsets = nullptr) {
     extern __shared__ __align__(16) uint32_t lds[];
     const int words = (g.n_rho + 31) / 32;
     uint32_t *dil = lds;                                   // [rows_per_block * words]
     uint32_t *rowany = dil + (size_t)rows_per_block * words;   // [rows_per_block]
+    uint32_t blk = blockIdx.x;
+    if (offsets) {
+        const uint32_t e = blockIdx.x;
+        blk = blockIdx.y;
+        const uint32_t h0 = offsets[e], h1 = offsets[e + 1];
+        if (h1 < h0) return;
+        if (h1 - h0 > kMaxBatchHits) {
+            for (uint32_t i = h0 + blk * (NW * 64) + threadIdx.x; i < h1; i += gridDim.y * (NW * 64)) keep[i] = 0u;
+            return;
+        }
+        if (blk * (uint32_t)(NW * 64) >= h1 - h0) return;
+        x += h0;
+        y += h0;
+        keep += h0;
+        n_hits = h1 - h0;
+        peaks += (size_t)e * cap;
+        n_peaks += e;
+    }
     const uint32_t np = min(*n_peaks, cap);
-    const uint32_t i = blockIdx.x * (NW * 64) + threadIdx.x;
+    const uint32_t i = blk * (NW * 64) + threadIdx.x;
     const bool in = i < n_hits;
     float u = 0.0f, v = 0.0f;
     bool valid = false;
@@ -1575,6 +1659,51 @@ hipError_t launch_retain(const GridArgs &g, const float *x, const float *y, uint
     hipLaunchKernelGGL(k_retain<kRetainWaves>, dim3(blocks), dim3(kRetainWaves * 64), lds, s, g, x, y,
                        n_hits, peaks, n_peaks, cap, keep, rows);
     return hipGetLastError();
+}
+
+// The iterative finder's batch form: (duplicate pass), vote into per-event 16-bit accumulators,
+// the finder, and retention with each event's first `cap` peaks, four launches for the batch.
+hipError_t launch_batch_iterative(const GridArgs &g, const BatchArgs &a, uint16_t *acc, uint32_t frac_num,
+                                  uint32_t frac_den, int r_theta, int r_rho, hipStream_t s) {
+    if (a.n_events == 0) return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (g.dedup) {
+        e = launch_dedup(a, s);
+        if (e != hipSuccess) return e;
+    }
+    {
+        const size_t lds = vote_lds_bytes(g.n_rho);
+        static const bool lds_ok = (allow_lds(k_vote_batch<kVoteWaves>), true);
+        (void)lds_ok;
+        const int groups = (g.n_theta + 63) / 64;
+        hipLaunchKernelGGL(k_vote_batch<kVoteWaves>, dim3(a.n_events, groups), dim3(kVoteWaves * 64), lds, s, g,
+                           a.x, a.y, a.offsets, acc, a.keep, a.status);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+        const size_t lds = (size_t)kIterCandidates * sizeof(uint64_t);
+        static const bool lds_ok = (allow_lds(k_peaks_iter<uint16_t>), true);
+        (void)lds_ok;
+        hipLaunchKernelGGL((k_peaks_iter<uint16_t>), dim3(a.n_events), dim3(kIterWaves * 64), lds, s, g,
+                           static_cast<const uint16_t *>(acc), frac_num, frac_den, r_theta, r_rho, a.peaks,
+                           a.max_peaks, a.n_peaks, a.status, a.offsets);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+        const int words = (g.n_rho + 31) / 32;
+        const size_t budget = 60 * 1024;
+        int rows = (int)(budget / ((size_t)words * 4 + 4));
+        if (rows > g.n_theta) rows = g.n_theta;
+        if (rows < 1) rows = 1;
+        const size_t lds = (size_t)rows * words * 4 + (size_t)rows * 4;
+        static const bool lds_ok = (allow_lds(k_retain<kRetainWaves>), true);
+        (void)lds_ok;
+        const uint32_t blocks = (kMaxBatchHits + kRetainWaves * 64 - 1) / (kRetainWaves * 64);
+        hipLaunchKernelGGL(k_retain<kRetainWaves>, dim3(a.n_events, blocks), dim3(kRetainWaves * 64), lds, s, g,
+                           a.x, a.y, 0u, a.peaks, a.n_peaks, a.max_peaks, a.keep, rows, a.offsets);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 template <int NW, int G>

@@ -77,6 +77,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.hough_max_iterative_candidates.restype = u32
     L.hough_max_dedup_hits.argtypes = []
     L.hough_max_dedup_hits.restype = u32
+    L.hough_iterative_workspace_bytes.argtypes = [vp, u32]
+    L.hough_iterative_workspace_bytes.restype = ctypes.c_size_t
+    L.hough_run_batch_iterative.argtypes = [vp, vp, vp, vp, u32, u32, u32, ctypes.c_int32, ctypes.c_int32,
+                                            vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.hough_run_batch_iterative.restype = i32
     L.hough_retain.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp]
     L.hough_retain.restype = i32
     L.hough_run_batch.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp, vp, vp]
@@ -326,6 +331,45 @@ class Context:
                "hough_run_batch")
         return peaks, n_peaks, keep, status
 
+
+    def iterative_workspace(self, n_events: int) -> torch.Tensor:
+        """Device workspace for run_batch_iterative over up to n_events events."""
+        n = int(self._lib.hough_iterative_workspace_bytes(self._ctx, int(n_events)))
+        return torch.empty(max(n, 256), dtype=torch.uint8, device="cuda")
+
+    def run_batch_iterative(self, x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, frac=(1, 2),
+                            r_theta: int = 5, r_rho: int = 5, workspace: torch.Tensor | None = None,
+                            peaks: torch.Tensor | None = None, n_peaks: torch.Tensor | None = None,
+                            keep: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None):
+        """The paper's peak finder over CSR events (hough_run_batch_iterative).  Returns (peaks
+        int32 [E, max_peaks, 2] in extraction order, n_peaks int32 [E], keep uint8 [H],
+        status int32 [E])."""
+        E = offsets.numel() - 1
+        mp = self.params.max_peaks
+        dev = offsets.device
+        if workspace is None:
+            workspace = self.iterative_workspace(E)
+        if peaks is None:
+            peaks = torch.zeros((max(E, 1), max(mp, 1), 2), dtype=torch.int32, device=dev)
+        if n_peaks is None:
+            n_peaks = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
+        if status is None:
+            status = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
+        if keep is None:
+            keep = torch.zeros(x.numel(), dtype=torch.uint8, device=dev)
+        po = _dev(offsets, torch.int32, "offsets", E + 1)
+        pp = _dev(peaks, torch.int32, "peaks", 2 * E * mp) if mp > 0 else 0
+        pn = _dev(n_peaks, torch.int32, "n_peaks", E)
+        ps = _dev(status, torch.int32, "status", E)
+        pw = _dev(workspace, torch.uint8, "workspace")
+        pk = self._ptr_or_dummy(keep, torch.uint8, "keep")
+        px = self._ptr_or_dummy(x, torch.float32, "x")
+        py = self._ptr_or_dummy(y, torch.float32, "y")
+        _check(self._lib.hough_run_batch_iterative(self._ctx, px, py, po, E, int(frac[0]), int(frac[1]),
+                                                   int(r_theta), int(r_rho), pp, pn, pk, ps, pw,
+                                                   workspace.numel(), _stream(stream)),
+               "hough_run_batch_iterative")
+        return peaks, n_peaks, keep, status
 
     def split_workspace(self, n_events: int) -> torch.Tensor:
         """A zero-filled device workspace for run_batch_split over up to n_events events."""

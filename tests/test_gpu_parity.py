@@ -876,6 +876,7 @@ def test_random_configurations(H, orc):
     import torch
     rng = np.random.default_rng(2024)
     pool = synth.make_events("paper-1000ev-360x256", 17, n_events=6)
+    ran = 0
     for case in range(20):
         n_theta = int(rng.integers(1, 420))
         n_rho = int(rng.integers(1, 600))
@@ -920,4 +921,86 @@ def test_random_configurations(H, orc):
         assert torch.equal(sp[1], npk) and torch.equal(sp[2], keep) and torch.equal(sp[3], st), case
         if cap:
             assert torch.equal(sp[0], pk), case
+        ctx.close()
+        ran += 1
+    assert ran >= 15
+
+
+# ------------------------------------------------------------ the paper's finder over a batch
+def _check_batch_iterative(H, orc, ctx, g, x, y, off, T, W, frac, rt, rr, cap, dedup=False):
+    import torch
+    xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
+    pk, npk, keep, st = ctx.run_batch_iterative(xt, yt, ot, frac, rt, rr)
+    torch.cuda.synchronize()
+    E = len(off) - 1
+    pk_ref, n_ref, keep_ref = orc.run_batch_iterative(g, x, y, off, T, frac, rt, rr, W, cap, dedup=dedup)
+    limit = int(H.load().hough_max_iterative_candidates())
+    npk, st, keep, p = npk.cpu().numpy()[:E], st.cpu().numpy()[:E], keep.cpu().numpy(), pk.cpu().numpy()
+    n_over = 0
+    for e in range(E):
+        a, b = int(off[e]), int(off[e + 1])
+        if b - a > ctx.max_batch_hits:
+            assert st[e] & H.EV_TOO_MANY_HITS and npk[e] == 0 and not keep[a:b].any()
+            continue
+        acc = orc.vote_dedup(g, x[a:b], y[a:b]) if dedup else orc.vote(g, x[a:b], y[a:b])
+        thr = max(T, -(-int(acc.max()) * frac[0] // frac[1]))
+        if int((acc >= thr).sum()) > limit:
+            n_over += 1
+            assert st[e] & H.EV_TOO_MANY_CANDIDATES and npk[e] == 0 and not keep[a:b].any(), e
+            continue
+        assert npk[e] == n_ref[e], e
+        m = int(min(n_ref[e], cap))
+        if m:
+            assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), e
+        assert np.array_equal(keep[a:b], keep_ref[a:b]), e
+        assert bool(st[e] & H.EV_PEAKS_TRUNCATED) == (n_ref[e] > cap), e
+        assert not st[e] & H.EV_TOO_MANY_CANDIDATES
+    return n_over
+
+
+@pytest.mark.parametrize("name,n_events,frac,rt,rr", [("paper-1000ev-360x256", 24, (1, 2), 5, 5),
+                                                      ("paper-1000ev-360x256", 12, (1, 3), 2, 3),
+                                                      ("dense-2000ev-720x512", 4, (1, 2), 5, 5),
+                                                      ("paper-1000ev-1000x1000", 4, (1, 2), 5, 5),
+                                                      ("plain-16ev-180x128", 16, (2, 3), 1, 1)])
+def test_batch_iterative_parity(H, orc, name, n_events, frac, rt, rr):
+    wl = synth.WORKLOADS[name]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 14, n_events=n_events)
+    floor_t = max(wl.threshold, 20) if name == "paper-1000ev-1000x1000" else wl.threshold
+    for cap, W, dedup in [(4096, 1, False), (3, 2, False), (4096, 1, True)]:
+        say(f"batch iterative {name} frac={frac} r={rt},{rr} cap={cap} W={W} dedup={dedup}")
+        ctx = H.Context.for_workload(wl, max_peaks=cap, threshold=floor_t, rho_window=W, dedup=dedup)
+        _check_batch_iterative(H, orc, ctx, g, ev.x, ev.y, ev.offsets, floor_t, W, frac, rt, rr, cap, dedup)
+        ctx.close()
+
+
+def test_batch_iterative_edge_events_and_per_event_path(H, orc):
+    """Edge events (empty, one hit, invalid hits, out of range, too many hits), a threshold so
+    low that some events overflow the candidate limit, and equality with the per-event path."""
+    import torch
+    evs = _edge_events() + [synth.random_hits(33000, seed=4)]
+    x = np.concatenate([a for a, _ in evs]).astype(np.float32)
+    y = np.concatenate([b for _, b in evs]).astype(np.float32)
+    off = np.zeros(len(evs) + 1, np.uint32)
+    off[1:] = np.cumsum([a.size for a, _ in evs])
+    for T, frac in [(3, (1, 2)), (1, (0, 1))]:
+        ctx = H.Context(200, 128, -0.005, 0.005, "i32", T, 1, 256)
+        g = orc.Grid(200, 128, -0.005, 0.005)
+        say(f"batch iterative edges T={T} frac={frac}")
+        n_over = _check_batch_iterative(H, orc, ctx, g, x, y, off, T, 1, frac, 3, 3, 256)
+        if frac == (0, 1):
+            assert n_over >= 1
+        # the per-event path gives the same lists for every event that fits
+        xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
+        pk, npk, keep, st = ctx.run_batch_iterative(xt, yt, ot, frac, 3, 3)
+        torch.cuda.synchronize()
+        for e in range(len(evs) - 1):
+            a, b = int(off[e]), int(off[e + 1])
+            acc = ctx.vote(_t(x[a:b]), _t(y[a:b]))
+            p1, n1, s1 = ctx.peaks_iterative(acc, 256, frac, 3, 3)
+            torch.cuda.synchronize()
+            assert int(n1.item()) == int(npk[e]) and int(s1.item()) == int(st[e]) & H.EV_TOO_MANY_CANDIDATES, e
+            m = min(int(n1.item()), 256)
+            assert torch.equal(p1[:m], pk[e, :m]), e
         ctx.close()
