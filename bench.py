@@ -194,14 +194,37 @@ def iterative_path(H, wl, ev, n_events: int = 200, frac=(1, 2), r_theta: int = 5
     ctx.close()
     k = keep.cpu().numpy()
     lab = sub.labels
-    return {"finder": f"relative threshold {frac[0]}/{frac[1]} of the maximum (floor {wl.threshold}), "
-                      f"suppression window +-{r_theta} theta x +-{r_rho} rho bins",
-            "events": sub.n_events, "ms_per_event": round(dt / sub.n_events * 1e3, 4),
-            "events_per_s": round(sub.n_events / dt, 1),
-            "peaks_per_event": round(float(npk.float().mean().item()), 2),
-            "flagged": int((st.cpu().numpy() != 0).sum()),
-            "R_c": round(float(k.mean()), 4) if k.size else None,
-            "R_s": round(float(k[lab >= 0].mean()), 4) if (lab >= 0).any() else None}
+    out = {"finder": f"relative threshold {frac[0]}/{frac[1]} of the maximum (floor {wl.threshold}), "
+                     f"suppression window +-{r_theta} theta x +-{r_rho} rho bins",
+           "events": sub.n_events, "ms_per_event": round(dt / sub.n_events * 1e3, 4),
+           "events_per_s": round(sub.n_events / dt, 1),
+           "peaks_per_event": round(float(npk.float().mean().item()), 2),
+           "flagged": int((st.cpu().numpy() != 0).sum()),
+           "R_c": round(float(k.mean()), 4) if k.size else None,
+           "R_s": round(float(k[lab >= 0].mean()), 4) if (lab >= 0).any() else None}
+
+    # the same finder over the whole batch at once (hough_run_batch_iterative: four launches)
+    bctx = H.Context.for_workload(wl, max_peaks=cap)
+    bx, by, bo = H.to_device(ev)
+    ws = bctx.iterative_workspace(ev.n_events)
+    res = bctx.run_batch_iterative(bx, by, bo, frac, r_theta, r_rho, ws)
+    times = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        bctx.run_batch_iterative(bx, by, bo, frac, r_theta, r_rho, ws, *res)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    kb = res[2].cpu().numpy()
+    out["batch"] = {"events": ev.n_events, "ms": round(ms, 4), "events_per_s": round(ev.n_events / (ms / 1e3), 1),
+                    "workspace_bytes": int(ws.numel()),
+                    "flagged": int((res[3].cpu().numpy()[:ev.n_events] != 0).sum()),
+                    "R_c": round(float(kb.mean()), 4) if kb.size else None,
+                    "R_s": round(float(kb[ev.labels >= 0].mean()), 4) if (ev.labels >= 0).any() else None}
+    bctx.close()
+    return out
 
 
 PT_BINS = (0.05, 0.2, 0.5, 1.0, 1.5)
