@@ -613,6 +613,10 @@ __device__ uint32_t retain_range(const uint32_t *dil, float2 *st, const float *x
 // Counters are packed two per dword, so the hits go through in chunks of at most 65,535 (a
 // count then fits 16 bits); each chunk's tile is written out (first chunk) or added (later
 // chunks) to acc, each element by the one thread that owns it.
+// Internal accumulator form of the iterative finder's batch path: 16-bit cells stored rho-major
+// (acc[k * n_theta + j]), so that the write-out of a tile row is one contiguous run per wave.
+constexpr int kAccU16RhoMajor = 3;
+
 template <int NW>
 __device__ uint32_t vote_group_to_acc(const GridArgs &g, const float *__restrict__ x,
                                       const float *__restrict__ y, uint32_t n_hits, void *acc,
@@ -641,7 +645,14 @@ __device__ uint32_t vote_group_to_acc(const GridArgs &g, const float *__restrict
         __syncthreads();
         // write-out: lane = column (theta row of acc), wave = a slice of rho
         if (j < g.n_theta) {
-            if (acc_type == HOUGH_ACC_U16) {
+            if (acc_type == kAccU16RhoMajor) {         // acc[k][j]: a wave stores 64 adjacent cells
+                uint16_t *col = static_cast<uint16_t *>(acc) + j;
+                for (int k = kb; k < ke; ++k) {
+                    const uint32_t v = ln.count(tile[k * L::STRIDE + ln.col[0]]);
+                    uint16_t *cell = col + (size_t)k * g.n_theta;
+                    *cell = (uint16_t)(c0 ? *cell + v : v);
+                }
+            } else if (acc_type == HOUGH_ACC_U16) {
                 uint16_t *row = static_cast<uint16_t *>(acc) + (size_t)j * g.n_rho;
                 for (int k = kb; k < ke; ++k) {
                     const uint32_t v = ln.count(tile[k * L::STRIDE + ln.col[0]]);
@@ -687,7 +698,7 @@ __global__ __launch_bounds__(NW * 64) void k_vote_batch(GridArgs g, const float 
     }
     const uint32_t H = h1 - h0;
     const size_t cells = (size_t)g.n_theta * (size_t)g.n_rho;
-    const uint32_t bad = vote_group_to_acc<NW>(g, x + h0, y + h0, H, acc + (size_t)e * cells, HOUGH_ACC_U16,
+    const uint32_t bad = vote_group_to_acc<NW>(g, x + h0, y + h0, H, acc + (size_t)e * cells, kAccU16RhoMajor,
                                                (int)blockIdx.y, g.dedup ? keep + h0 : nullptr);
     __shared__ uint32_t s_bad;
     if (threadIdx.x == 0) s_bad = 0u;
@@ -790,7 +801,7 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return v;
 }
 
-// offsets (batch form, else null): workgroup e takes event e's accumulator at acc + e * cells,
+// offsets (batch form, else null): workgroup e takes event e's accumulator (rho-major) at acc + e * cells,
 // writes its list at out + e * cap, n_peaks[e], and ORs its bits into status[e] (which the
 // batch vote wrote), adding HOUGH_EV_PEAKS_TRUNCATED; events the vote skipped get no peaks.
 template <typename T>
@@ -808,6 +819,13 @@ __global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, cons
     const uint32_t nr = (uint32_t)g.n_rho;
     const uint32_t cells = (uint32_t)g.n_theta * nr;
     const bool batch = offsets != nullptr;
+    // the batch form stores rho-major (see kAccU16RhoMajor); keys always hold raster indices
+    const uint32_t nt = (uint32_t)g.n_theta;
+    auto raster = [&](uint32_t c) -> uint32_t {
+        if (!batch) return c;
+        const uint32_t k = c / nt;
+        return (c - k * nt) * nr + k;
+    };
     if (batch) {
         const uint32_t e = blockIdx.x;
         acc += (size_t)e * cells;
@@ -845,7 +863,7 @@ __global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, cons
                 if (lane == 0) off = atomicAdd(&s_nc, (uint32_t)__popcll(b));
                 off = (uint32_t)__shfl((int)off, 0, 64);
                 const uint32_t pos = off + mbcnt(b);
-                if (p && pos < kIterCandidates) keys[pos] = ((uint64_t)v[r] << 32) | (uint64_t)(~c);
+                if (p && pos < kIterCandidates) keys[pos] = ((uint64_t)v[r] << 32) | (uint64_t)(~raster(c));
             }
         }
     }
@@ -900,7 +918,7 @@ __global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, cons
                     if (lane == 0) off = atomicAdd(&s_nk, (uint32_t)__popcll(b));
                     off = (uint32_t)__shfl((int)off, 0, 64);
                     const uint32_t pos = off + mbcnt(b);
-                    if (p && pos < kIterCandidates) keys[pos] = ((uint64_t)v[r] << 32) | (uint64_t)(~c);
+                    if (p && pos < kIterCandidates) keys[pos] = ((uint64_t)v[r] << 32) | (uint64_t)(~raster(c));
                 }
             }
         }
