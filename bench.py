@@ -38,6 +38,10 @@ VALU_LANE_OPS_PER_S = N_CU * LANES_PER_CU_CLK * CLOCK_HZ          # 39.3 T 32-bi
 OPS_PER_VOTE = 4      # 2 FMA (rho), 1 float->int (bin), 1 index (cell address); the +1 is on the LDS
 VOTE_PEAK_PER_S = VALU_LANE_OPS_PER_S / OPS_PER_VOTE              # 9.83 T votes/s
 HBM_PEAK_GBS = 8000.0
+# LDS atomic ceiling: an isolated ds_add_u32 loop (distinct banks, no return) sustains about 12.9
+# lanes per clock per CU on MI355X, 256 CUs x 2.4 GHz x 12.9 = 7.9 T lane-updates/s
+LDS_ATOMIC_LANES_PER_CU_CLK = 12.9
+LDS_ATOMIC_CEILING_PER_S = N_CU * CLOCK_HZ * LDS_ATOMIC_LANES_PER_CU_CLK
 
 
 def log(*a):
@@ -71,6 +75,22 @@ def profiled_traffic(workload: str, plan):
     if rec.get("source") != kernel_source_id() or rec.get("plan") != cur:
         return None
     return rec
+
+
+def lds_atomic_rate(ev, plan, wl, kern_ms: float) -> dict:
+    """LDS vote atomics the fused kernel issues per launch (each valid hit updates every lane's
+    column of every theta tile, halo and out-of-grid lanes included: 64 * column_groups lanes per
+    tile) per second of kernel time, against the measured LDS atomic ceiling."""
+    x64, y64 = ev.x.astype(np.float32), ev.y.astype(np.float32)
+    r2 = x64 * x64 + y64 * y64
+    valid = int(np.count_nonzero((r2 > 0) & np.isfinite(r2)))
+    lanes_per_tile = 64 * plan["column_groups"]
+    tiles = -(-wl.n_theta // (lanes_per_tile - 2))
+    lanes = valid * tiles * lanes_per_tile
+    rate = lanes / (kern_ms / 1e3)
+    return {"lane_updates_per_launch": lanes, "achieved_per_s": round(rate / 1e12, 3), "unit": "T/s",
+            "ceiling_per_s": round(LDS_ATOMIC_CEILING_PER_S / 1e12, 3),
+            "frac": round(rate / LDS_ATOMIC_CEILING_PER_S, 4)}
 
 
 def cpu_model() -> str:
@@ -598,7 +618,8 @@ def main(argv=None):
                      "kernel": "k_batch",
                      "algorithmic_bytes": algo_bytes,
                      "hbm_algorithmic_gbs": round(algo_bytes / (kern_ms / 1e3) / 1e9, 2),
-                     "hbm_frac": round(algo_bytes / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+                     "hbm_frac": round(algo_bytes / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "lds_atomic": lds_atomic_rate(ev, ctx.batch_plan, wl, kern_ms)},
         "retention": {"R_c": round(float(keep_np.mean()), 4) if keep_np.size else None,
                       "R_s": round(float(keep_np[labels >= 0].mean()), 4) if (labels >= 0).any() else None,
                       "peaks_per_event": round(float(npk.float().mean().item()), 1),
