@@ -465,27 +465,28 @@ def test_split_gather_batches_equal_gather_batches(H):
     ctx.close()
 
 
-def _serve_pools(H, n_each=48):
+def _serve_pools(H, n_each=48, dedup=False):
     from paper_2607_04067_amd import serve
     pools = []
     for name in ("paper-1000ev-360x256", "dense-2000ev-720x512"):
         wl = synth.WORKLOADS[name]
         ev = synth.make_events(wl, 7, n_events=n_each)
-        ctx = H.Context.for_workload(wl, max_peaks=16384)
+        ctx = H.Context.for_workload(wl, max_peaks=16384, dedup=dedup)
         pools.append(serve.Pool(ctx, ev))
     return pools
 
 
-@pytest.mark.parametrize("plain,small,split", [(False, 0, 0), (False, 64, 0), (False, 64, 4), (False, 0, 16),
-                                               (True, 0, 0)])
-def test_served_results_equal_results_alone(H, plain, small, split):
+@pytest.mark.parametrize("plain,small,split,dedup", [(False, 0, 0, False), (False, 64, 0, False),
+                                                     (False, 64, 4, False), (False, 0, 16, False),
+                                                     (False, 64, 8, True), (True, 0, 0, False)])
+def test_served_results_equal_results_alone(H, plain, small, split, dedup):
     """Each request's n_peaks, status, keep and peak list in the served mix (continuous
     batching over several streams, events reordered largest first inside a batch, small
-    batches on the 16-wave shape or in the split form or neither) equal the same event
-    processed alone."""
+    batches on the 16-wave shape or in the split form or neither, duplicate suppression on
+    or off) equal the same event processed alone."""
     import torch
     from paper_2607_04067_amd import serve
-    pools = _serve_pools(H)
+    pools = _serve_pools(H, dedup=dedup)
     trace = serve.poisson_trace(2e5 if not plain else 2e4, 0.002 if not plain else 0.004,
                                 [p.batch.n_events for p in pools], [0.5, 0.5], seed=3)
     assert trace.size > 20
