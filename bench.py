@@ -48,12 +48,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_of(text: str) -> str:
+    """Source text without // comments, trailing blanks and blank lines (what compiles)."""
+    out = []
+    for line in text.splitlines():
+        code = line.split("//", 1)[0].rstrip()
+        if code:
+            out.append(code)
+    return "\n".join(out)
+
+
 def kernel_source_id() -> str:
-    """Short hash of the kernel sources; profile records carry the one they were taken with."""
+    """Short hash of the kernel sources' code; profile records carry the one they were taken
+    with, so a change of comments alone does not retire them."""
     h = hashlib.sha256()
     for f in ("hough_kernels.hip", "hough_internal.h"):
-        with open(os.path.join(ROOT, "paper_2607_04067_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2607_04067_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_of(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,9 +1,10 @@
 // HIP kernels of libhough.so (gfx950 / CDNA4, wave64).
 //
-// Layout shared by every kernel that votes: a theta tile of TW = 64*G columns lives in LDS as
-// tile[k * TW + c] (rho-major, one 32-bit counter per cell).  Lane l of a wave owns column
-// c = 64*q + l of group q, so the 64 atomics one ds_add_u32 issues for one hit land in 64
-// consecutive dwords of one row slice: distinct banks, never the same address.  Hits are
+// Layout shared by every kernel that votes: a theta tile of TW = 64*G columns lives in LDS
+// rho-major, one row of the tile per rho bin, two 16-bit counters per dword (see Lane below).
+// Lane l of a wave owns column c = 64*q + l of group q, so the 64 atomics one ds_add_u32
+// issues for one hit land in 32 consecutive dwords of one row, the two lanes of a dword in
+// different halves of the wave: no bank conflict, never the same address.  Hits are
 // wave-uniform: a wave maps 64 hits at a time (one per lane), compacts the valid ones into a
 // per-wave LDS stage with ballot/mbcnt, then every lane sweeps its own column over the staged
 // hits (the theta sweep of Sec. III: one column = one parallel task, hits streamed through it).
@@ -582,8 +583,9 @@ __device__ uint32_t retain_pending(Pending &pd, const uint32_t *dil, float2 *st,
 }
 
 // Step 5 over the whole range [hb, he): every unkept valid hit is mapped again, staged and
-// looked up; each lane writes the keep byte of its own hit when its stage slot was kept (the
-// event's keep bytes were cleared when it started, and only this lane touches them).  Returns
+// looked up; each lane sets the kept bit of its own hit's keep byte when its stage slot was
+// kept (the event's keep bytes were cleared, or written by the duplicate pass, when it
+// started, and only this lane touches them).  Returns
 // the number of hits newly kept; `left` receives how many valid hits remain unkept.
 template <int G>
 __device__ uint32_t retain_range(const uint32_t *dil, float2 *st, const float *x,
@@ -609,14 +611,15 @@ __device__ uint32_t retain_range(const uint32_t *dil, float2 *st, const float *x
 }
 
 // ------------------------------------------------------------------------ plain path
-// hough_vote: one workgroup per 64-column group, all hits of the event swept through it.
-// Counters are packed two per dword, so the hits go through in chunks of at most 65,535 (a
-// count then fits 16 bits); each chunk's tile is written out (first chunk) or added (later
-// chunks) to acc, each element by the one thread that owns it.
 // Internal accumulator form of the iterative finder's batch path: 16-bit cells stored rho-major
 // (acc[k * n_theta + j]), so that the write-out of a tile row is one contiguous run per wave.
 constexpr int kAccU16RhoMajor = 3;
 
+// Steps 1-3 of one event into one 64-column group of acc, by one workgroup: all hits of the
+// event are swept through the group's tile.  Counters are packed two per dword, so the hits go
+// through in chunks of at most 65,535 (a count then fits 16 bits); each chunk's tile is written
+// out (first chunk) or added (later chunks) to acc, each element by the one thread that owns
+// it.  dup as for vote_range.  Returns this thread's invalid-hit flag.
 template <int NW>
 __device__ uint32_t vote_group_to_acc(const GridArgs &g, const float *__restrict__ x,
                                       const float *__restrict__ y, uint32_t n_hits, void *acc,
@@ -672,6 +675,7 @@ __device__ uint32_t vote_group_to_acc(const GridArgs &g, const float *__restrict
     return bad;
 }
 
+// hough_vote: one workgroup per 64-column group.
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__restrict__ x,
                                                   const float *__restrict__ y, uint32_t n_hits,
@@ -1125,8 +1129,9 @@ __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__r
 // theta tiles are processed in order: vote, find peaks, list + dilate, then retain while the
 // tile is cleared for the next one.  Counters are packed two per dword (an event has at most
 // kMaxBatchHits hits, so a count fits 16 bits).  Wave w owns hits [hb, he) of the event for
-// voting and retention, and keeps their keep flags in registers until the event is done.
-// Retention is skipped for the rest of the event once every valid hit is kept.
+// voting and retention and writes their keep bytes itself (each lane those of its own hits,
+// the pending list aside).  Retention is skipped for the rest of the event once every valid
+// hit is kept.
 // queue[0] is the work counter and queue[1] counts workgroups that have left the loop; the
 // last one to leave (every pop has then happened) puts both back to zero for the next launch,
 // so a launch is a single kernel with no memset.
@@ -1286,11 +1291,12 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
 // throughput: the work items are the (event, theta tile) pairs, so the tiles of one event run
 // on different workgroups at once.  A tile votes all of its event's hits, finds its peaks, lists
 // them in raster order into its own slot of the workspace, dilates them, and sets the keep bits
-// of the event's hits it keeps (skipping hits other tiles already kept).  The workgroup that
-// finishes an event's last tile merges: the tile lists in tile order (raster order) truncated
-// at max_peaks, the true count, the status and the keep bytes, and it leaves the event's part
-// of the workspace zero again.  Each tile re-examines the hits the others have not kept yet,
-// so retention costs more in total than in k_batch: the price of the shorter latency.
+// of the event's hits it keeps.  The workgroup that finishes an event's last tile merges: the
+// tile lists in tile order (raster order) truncated at max_peaks, the true count, the status
+// and the keep bytes, and it leaves the event's part of the workspace zero again.  Every tile
+// examines all of the event's hits, so retention costs more in total than in k_batch, and
+// each publish and merge is an agent-scope release or acquire: the price of the shorter
+// latency.
 
 // Step 5 of one tile in the split form: keep bits in global memory, shared by the tiles.  A
 // wave tests 64 consecutive hits at a time and merges its kept bits into (at most three) words
