@@ -13,7 +13,8 @@ struct hough_ctx {
     hough_params p;
     int device;
     float *d_tables;        // C[n_theta] then S[n_theta]
-    uint32_t *d_work;       // [0]: work counter of the fused kernel
+    uint32_t *d_work;       // [0], [1]: work and exit counters of the fused kernels; from [64]:
+                            // hough_peaks' per-block peak counts
     hough::GridArgs g;
     hough::BatchPlan plan;
     size_t lds_limit;
@@ -154,13 +155,15 @@ int hough_config(const hough_params *p, hough_ctx **out) {
         delete c;
         return HOUGH_ENOMEM;
     }
-    if (hipMalloc(&c->d_work, 256) != hipSuccess) {
+    const size_t work_bytes = 256 + 4 * (size_t)((p->n_theta + hough::kPeakRowsPerBlock - 1) /
+                                                 hough::kPeakRowsPerBlock);
+    if (hipMalloc(&c->d_work, work_bytes) != hipSuccess) {
         (void)hipFree(c->d_tables);
         delete c;
         return HOUGH_ENOMEM;
     }
     if (hipMemcpy(c->d_tables, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(c->d_work, 0, 256) != hipSuccess) {
+        hipMemset(c->d_work, 0, work_bytes) != hipSuccess) {
         hough_destroy(c);
         return HOUGH_EDEVICE;
     }
@@ -242,7 +245,7 @@ int hough_peaks(hough_ctx *c, const void *acc, hough_peak *peaks, uint32_t cap, 
     if (!c || !acc || !n_peaks || (cap && !peaks)) return HOUGH_EINVAL;
     if (!on_device(c)) return HOUGH_EINVAL;
     if (((uintptr_t)peaks & 7u) != 0) return HOUGH_EINVAL;
-    const hipError_t e = hough::launch_peaks(c->g, acc, c->p.acc_type, peaks, cap, n_peaks,
+    const hipError_t e = hough::launch_peaks(c->g, acc, c->p.acc_type, peaks, cap, n_peaks, c->d_work + 64,
                                              (hipStream_t)stream);
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
 }

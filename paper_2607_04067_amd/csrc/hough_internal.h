@@ -91,8 +91,10 @@ hipError_t launch_batch_iterative(const GridArgs &g, const BatchArgs &a, uint16_
                                   uint32_t frac_den, int r_theta, int r_rho, hipStream_t s);
 hipError_t launch_vote(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                        void *acc, int acc_type, hipStream_t s);
+// counts: ceil(n_theta / kPeakRowsPerBlock) counters of device scratch (the context's).
+constexpr int kPeakRowsPerBlock = 16;
 hipError_t launch_peaks(const GridArgs &g, const void *acc, int acc_type, hough_peak *peaks,
-                        uint32_t cap, uint32_t *n_peaks, hipStream_t s);
+                        uint32_t cap, uint32_t *n_peaks, uint32_t *counts, hipStream_t s);
 hipError_t launch_retain(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                          const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
                          uint8_t *keep, hipStream_t s);

@@ -714,76 +714,95 @@ __global__ __launch_bounds__(NW * 64) void k_vote_batch(GridArgs g, const float 
                     (g.dedup && H > kDedupMaxHits ? HOUGH_EV_DEDUP_SKIPPED : 0u);
 }
 
-// hough_peaks: one workgroup; rows are staged NW at a time (plus one halo row on each side)
-// and each wave tests one row, lanes over rho.  Counts are prefix-summed across waves so the
-// list is written in raster order.
-template <int NW, typename T>
+// hough_peaks: workgroup b tests theta rows [NW*b, NW*b + NW), staged in LDS with one halo row
+// on each side, one wave per row, lanes over rho.  Two launches: the first writes each block's
+// peak count to counts[b]; the second lists each block's peaks at the sum of the earlier blocks'
+// counts plus the earlier waves' (raster order), and block 0 writes the total.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+    return v;
+}
+
+template <int NW, typename T, bool WRITE>
 __global__ __launch_bounds__(NW * 64) void k_peaks(GridArgs g, const T *__restrict__ acc,
                                                    hough_peak *out, uint32_t cap,
-                                                   uint32_t *n_peaks) {
+                                                   uint32_t *n_peaks, uint32_t *counts) {
     extern __shared__ __align__(16) uint32_t lds[];
     uint32_t *rows = lds;   // [(NW + 2) * n_rho], buffer row r holds grid row jb - 1 + r
     __shared__ uint32_t s_cnt[NW];
-    __shared__ uint32_t s_total;
+    __shared__ uint32_t s_base;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nr = g.n_rho;
-    if (threadIdx.x == 0) s_total = 0;
-    for (int jb = 0; jb < g.n_theta; jb += NW) {
-        for (int idx = threadIdx.x; idx < (NW + 2) * nr; idx += NW * 64) {
-            const int r = idx / nr, k = idx - r * nr, jj = jb - 1 + r;
-            uint32_t v = 0u;
-            if (jj >= 0 && jj < g.n_theta) v = (uint32_t)acc[(size_t)jj * nr + k];
-            else if (g.periodic && (jj == -1 || jj == g.n_theta))   // the other edge, rho reversed
-                v = (uint32_t)acc[(size_t)(jj < 0 ? g.n_theta - 1 : 0) * nr + (nr - 1 - k)];
-            rows[idx] = v;
-        }
-        __syncthreads();
-        const int j = jb + wave;
-        const uint32_t *up = rows + wave * nr, *mid = up + nr, *dn = mid + nr;
-        // on a periodic grid the row above column 0 is column n_theta - 1 (later in raster order)
-        // and the row below column n_theta - 1 is column 0 (earlier)
-        const bool up_later = g.periodic && j == 0, dn_earlier = g.periodic && j == g.n_theta - 1;
-        uint32_t cnt = 0;
-        auto is_peak = [&](int k) -> bool {
-            const uint32_t c = mid[k];
-            const uint32_t l = k > 0 ? 1u : 0u, r = k + 1 < nr ? 1u : 0u;
-            const uint32_t u3 = max(max(l ? up[k - 1] : 0u, up[k]), r ? up[k + 1] : 0u);
-            const uint32_t d3 = max(max(l ? dn[k - 1] : 0u, dn[k]), r ? dn[k + 1] : 0u);
-            const uint32_t before = max(max(up_later ? 0u : u3, dn_earlier ? d3 : 0u), l ? mid[k - 1] : 0u);
-            const uint32_t after = max(max(up_later ? u3 : 0u, dn_earlier ? 0u : d3), r ? mid[k + 1] : 0u);
-            return c >= max(max(g.threshold, before + 1u), after);
-        };
-        if (j < g.n_theta) {
-            for (int kc = 0; kc < nr; kc += 64) {
-                const int k = kc + lane;
-                cnt += (uint32_t)__popcll(__ballot(k < nr && is_peak(k)));
-            }
-        }
-        if (lane == 0) s_cnt[wave] = cnt;
-        __syncthreads();
-        uint32_t base = s_total;
-        for (int w = 0; w < wave; ++w) base += s_cnt[w];
-        if (j < g.n_theta) {
-            for (int kc = 0; kc < nr; kc += 64) {
-                const int k = kc + lane;
-                const bool p = k < nr && is_peak(k);
-                const uint64_t m = __ballot(p);
-                if (p) {
-                    const uint32_t idx = base + mbcnt(m);
-                    if (idx < cap) store_peak(out + idx, (uint32_t)j, (uint32_t)k, mid[k]);
-                }
-                base += (uint32_t)__popcll(m);
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t s = 0;
-            for (int w = 0; w < NW; ++w) s += s_cnt[w];
-            s_total += s;
-        }
-        __syncthreads();
+    const int jb = (int)blockIdx.x * NW;
+    for (int idx = threadIdx.x; idx < (NW + 2) * nr; idx += NW * 64) {
+        const int r = idx / nr, k = idx - r * nr, jj = jb - 1 + r;
+        uint32_t v = 0u;
+        if (jj >= 0 && jj < g.n_theta) v = (uint32_t)acc[(size_t)jj * nr + k];
+        else if (g.periodic && (jj == -1 || jj == g.n_theta))   // the other edge, rho reversed
+            v = (uint32_t)acc[(size_t)(jj < 0 ? g.n_theta - 1 : 0) * nr + (nr - 1 - k)];
+        rows[idx] = v;
     }
-    if (threadIdx.x == 0) *n_peaks = s_total;
+    if (WRITE && wave == 0) {                     // peaks of the earlier blocks, and of all
+        uint32_t before = 0, all = 0;
+        for (uint32_t q = (uint32_t)lane; q < gridDim.x; q += 64) {
+            const uint32_t c = counts[q];
+            all += c;
+            if (q < blockIdx.x) before += c;
+        }
+        before = wave_sum(before);
+        all = wave_sum(all);
+        if (lane == 0) {
+            s_base = before;
+            if (blockIdx.x == 0) *n_peaks = all;
+        }
+    }
+    __syncthreads();
+    const int j = jb + wave;
+    const uint32_t *up = rows + wave * nr, *mid = up + nr, *dn = mid + nr;
+    // on a periodic grid the row above column 0 is column n_theta - 1 (later in raster order)
+    // and the row below column n_theta - 1 is column 0 (earlier)
+    const bool up_later = g.periodic && j == 0, dn_earlier = g.periodic && j == g.n_theta - 1;
+    auto is_peak = [&](int k) -> bool {
+        const uint32_t c = mid[k];
+        const uint32_t l = k > 0 ? 1u : 0u, r = k + 1 < nr ? 1u : 0u;
+        const uint32_t u3 = max(max(l ? up[k - 1] : 0u, up[k]), r ? up[k + 1] : 0u);
+        const uint32_t d3 = max(max(l ? dn[k - 1] : 0u, dn[k]), r ? dn[k + 1] : 0u);
+        const uint32_t before = max(max(up_later ? 0u : u3, dn_earlier ? d3 : 0u), l ? mid[k - 1] : 0u);
+        const uint32_t after = max(max(up_later ? u3 : 0u, dn_earlier ? 0u : d3), r ? mid[k + 1] : 0u);
+        return c >= max(max(g.threshold, before + 1u), after);
+    };
+    uint32_t cnt = 0;
+    if (j < g.n_theta) {
+        for (int kc = 0; kc < nr; kc += 64) {
+            const int k = kc + lane;
+            cnt += (uint32_t)__popcll(__ballot(k < nr && is_peak(k)));
+        }
+    }
+    if (lane == 0) s_cnt[wave] = cnt;
+    __syncthreads();
+    if (!WRITE) {
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < NW; ++w) t += s_cnt[w];
+            counts[blockIdx.x] = t;
+        }
+        return;
+    }
+    uint32_t base = s_base;
+    for (int w = 0; w < wave; ++w) base += s_cnt[w];
+    if (j < g.n_theta) {
+        for (int kc = 0; kc < nr; kc += 64) {
+            const int k = kc + lane;
+            const bool p = k < nr && is_peak(k);
+            const uint64_t m = __ballot(p);
+            if (p) {
+                const uint32_t idx = base + mbcnt(m);
+                if (idx < cap) store_peak(out + idx, (uint32_t)j, (uint32_t)k, mid[k]);
+            }
+            base += (uint32_t)__popcll(m);
+        }
+    }
 }
 
 // hough_peaks_iterative: the paper's peak finder (relative threshold, then iterative
@@ -1045,9 +1064,11 @@ __global__ __launch_bounds__(kTrackWaves * 64) void k_track_params(GridArgs g, c
     }
 }
 
-// hough_retain: one thread per hit.  Peak rows are processed in blocks that fit LDS: for
-// each block a dilated bitmap (bit k of row j set iff a peak (j, k') has |k - k'| <= W) is
-// built from the peak list, then every unkept hit looks up its own bin in each peak row.
+// hough_retain: workgroup b takes hits b*NW*64 ..., 64 per wave, mapped and staged once.  The
+// theta rows are processed in blocks that fit LDS: for each block the dilated peak bits (bit k
+// of row j set iff a peak (j, k') has |k - k'| <= W) are built from the peak list, stored as
+// [64-row group][word][row in group], and every wave looks its staged hits up 64 rows at a time
+// with lane = row, exactly as the fused kernel looks them up in its tile's columns.
 // offsets (batch form, else null): workgroup (e, b) covers hits b*NW*64 ... of event e, with
 // event e's peak list at peaks + e * cap and n_peaks[e]; the keep bytes of an event the vote
 // skipped for its size are zeroed (malformed offsets: nothing is touched).
@@ -1060,8 +1081,9 @@ __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__r
                                                     const uint32_t *offsets = nullptr) {
     extern __shared__ __align__(16) uint32_t lds[];
     const int words = (g.n_rho + 31) / 32;
-    uint32_t *dil = lds;                                   // [rows_per_block * words]
-    uint32_t *rowany = dil + (size_t)rows_per_block * words;   // [rows_per_block]
+    float2 *stage = reinterpret_cast<float2 *>(lds);              // [NW * 64]
+    uint32_t *dil = lds + 2 * NW * 64;                             // [rows_per_block / 64][words][64]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t blk = blockIdx.x;
     if (offsets) {
         const uint32_t e = blockIdx.x;
@@ -1081,16 +1103,17 @@ __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__r
         n_peaks += e;
     }
     const uint32_t np = min(*n_peaks, cap);
-    const uint32_t i = blk * (NW * 64) + threadIdx.x;
-    const bool in = i < n_hits;
-    float u = 0.0f, v = 0.0f;
-    bool valid = false;
-    if (in) valid = conformal(x[i], y[i], u, v);
-    uint32_t kept = 0;
+    const uint32_t base = blk * (NW * 64) + (uint32_t)wave * 64u;
+    const uint32_t i = base + (uint32_t)lane;
+    float2 *st = stage + wave * 64;
+    uint32_t unused = 0;
+    int slot;
+    const StageCount n = stage_hits(st, x, y, base, n_hits, false, g, lane, unused, slot);
+    uint64_t kept = 0;
     for (int ja = 0; ja < g.n_theta; ja += rows_per_block) {
         const int nrow = min(rows_per_block, g.n_theta - ja);
-        for (int t = threadIdx.x; t < nrow * words; t += NW * 64) dil[t] = 0u;
-        for (int t = threadIdx.x; t < nrow; t += NW * 64) rowany[t] = 0u;
+        const int ngroups = (nrow + 63) / 64;
+        for (int t = threadIdx.x; t < ngroups * words * 64; t += NW * 64) dil[t] = 0u;
         __syncthreads();
         for (uint32_t p = threadIdx.x; p < np; p += NW * 64) {
             const uint2 pk = reinterpret_cast<const uint2 *>(peaks)[p];
@@ -1098,30 +1121,28 @@ __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__r
             if (j < ja || j >= ja + nrow || k >= g.n_rho) continue;
             const int lo = k - g.rho_window > 0 ? k - g.rho_window : 0;
             const int hi = k + g.rho_window < g.n_rho - 1 ? k + g.rho_window : g.n_rho - 1;
-            uint32_t *row = dil + (size_t)(j - ja) * words;
+            const int r = j - ja;
+            uint32_t *col = dil + (size_t)(r >> 6) * words * 64 + (r & 63);
             for (int wd = lo >> 5; wd <= (hi >> 5); ++wd) {
                 const int a = max(lo, wd * 32) - wd * 32, b = min(hi, wd * 32 + 31) - wd * 32;
                 const uint32_t m = (b == 31 ? 0xffffffffu : ((1u << (b + 1)) - 1u)) & ~((1u << a) - 1u);
-                __hip_atomic_fetch_or(&row[wd], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_or(&col[wd * 64], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            rowany[j - ja] = 1u;
         }
         __syncthreads();
-        if (valid && !kept) {
-            for (int r = 0; r < nrow; ++r) {
-                if (!rowany[r]) continue;
-                const int j = ja + r;
-                const float w = __builtin_fmaf(v, g.S[j], g.Bf);
-                const float t = __builtin_fmaf(u, g.C[j], w);
-                if (t >= 0.0f && t < g.nrho_f) {
-                    const int k = (int)t;
-                    if ((dil[(size_t)r * words + (k >> 5)] >> (k & 31)) & 1u) { kept = 1; break; }
-                }
-            }
+        for (int q = 0; q < ngroups; ++q) {
+            // lane = theta row ja + 64q + lane; rows past the grid look up a zero word of row 0
+            const int j = ja + 64 * q + lane;
+            Cols<1> cl;
+            const bool row_in = j < g.n_theta;
+            cl.C[0] = row_in ? g.C[j] : 0.0f;
+            cl.S[0] = row_in ? g.S[j] : 0.0f;
+            cl.B[0] = row_in ? g.Bf : 0.0f;
+            kept |= lookup_staged<1>(dil + (size_t)q * words * 64, st, n, cl, lane, g.nrho_f);
         }
         __syncthreads();
     }
-    if (in) keep[i] = (uint8_t)kept;
+    if (i < n_hits) keep[i] = (slot >= 0 && ((kept >> slot) & 1ull)) ? 1u : 0u;
 }
 
 // ------------------------------------------------------------------------ fused batch path
@@ -1554,9 +1575,25 @@ __global__ __launch_bounds__(kDedupThreads) void k_dedup(BatchArgs a) {
     }
 }
 
-constexpr int kVoteWaves = 16;
-constexpr int kPeakWaves = 16;
+// hough_retain's LDS: the wave stages, then the dilated bits of a block of theta rows (a whole
+// number of 64-row groups, at most 60 KB of them).
 constexpr int kRetainWaves = 8;
+int retain_rows_per_block(const GridArgs &g) {
+    const size_t words = (size_t)(g.n_rho + 31) / 32;
+    const size_t budget = 60 * 1024;
+    int groups = (int)(budget / (words * 64 * 4));
+    const int need = (g.n_theta + 63) / 64;
+    if (groups > need) groups = need;
+    if (groups < 1) groups = 1;
+    return groups * 64;
+}
+size_t retain_lds_bytes(const GridArgs &g, int rows) {
+    const size_t words = (size_t)(g.n_rho + 31) / 32;
+    return (size_t)kRetainWaves * 64 * sizeof(float2) + (size_t)(rows / 64) * words * 64 * 4;
+}
+
+constexpr int kVoteWaves = 16;
+constexpr int kPeakWaves = kPeakRowsPerBlock;
 
 // The dynamic-LDS limit is a per-kernel, process-wide attribute: every kernel is allowed the
 // device maximum (less room for its static LDS) so that contexts with different grids, possibly
@@ -1618,18 +1655,27 @@ hipError_t launch_vote(const GridArgs &g, const float *x, const float *y, uint32
 }
 
 hipError_t launch_peaks(const GridArgs &g, const void *acc, int acc_type, hough_peak *peaks,
-                        uint32_t cap, uint32_t *n_peaks, hipStream_t s) {
+                        uint32_t cap, uint32_t *n_peaks, uint32_t *counts, hipStream_t s) {
     const size_t lds = peaks_lds_bytes(g.n_rho);
+    const int blocks = (g.n_theta + kPeakWaves - 1) / kPeakWaves;
     if (acc_type == HOUGH_ACC_U16) {
-        static const bool lds_ok = (allow_lds(k_peaks<kPeakWaves, uint16_t>), true);
+        static const bool lds_ok = (allow_lds(k_peaks<kPeakWaves, uint16_t, false>),
+                                    allow_lds(k_peaks<kPeakWaves, uint16_t, true>), true);
         (void)lds_ok;
-        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint16_t>), dim3(1), dim3(kPeakWaves * 64), lds, s, g,
-                           static_cast<const uint16_t *>(acc), peaks, cap, n_peaks);
+        const uint16_t *a = static_cast<const uint16_t *>(acc);
+        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint16_t, false>), dim3(blocks), dim3(kPeakWaves * 64), lds, s, g,
+                           a, peaks, cap, n_peaks, counts);
+        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint16_t, true>), dim3(blocks), dim3(kPeakWaves * 64), lds, s, g,
+                           a, peaks, cap, n_peaks, counts);
     } else {
-        static const bool lds_ok = (allow_lds(k_peaks<kPeakWaves, uint32_t>), true);
+        static const bool lds_ok = (allow_lds(k_peaks<kPeakWaves, uint32_t, false>),
+                                    allow_lds(k_peaks<kPeakWaves, uint32_t, true>), true);
         (void)lds_ok;
-        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint32_t>), dim3(1), dim3(kPeakWaves * 64), lds, s, g,
-                           static_cast<const uint32_t *>(acc), peaks, cap, n_peaks);
+        const uint32_t *a = static_cast<const uint32_t *>(acc);
+        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint32_t, false>), dim3(blocks), dim3(kPeakWaves * 64), lds, s, g,
+                           a, peaks, cap, n_peaks, counts);
+        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint32_t, true>), dim3(blocks), dim3(kPeakWaves * 64), lds, s, g,
+                           a, peaks, cap, n_peaks, counts);
     }
     return hipGetLastError();
 }
@@ -1671,12 +1717,8 @@ hipError_t launch_retain(const GridArgs &g, const float *x, const float *y, uint
                          const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
                          uint8_t *keep, hipStream_t s) {
     if (n_hits == 0) return hipSuccess;
-    const int words = (g.n_rho + 31) / 32;
-    const size_t budget = 60 * 1024;
-    int rows = (int)(budget / ((size_t)words * 4 + 4));
-    if (rows > g.n_theta) rows = g.n_theta;
-    if (rows < 1) rows = 1;
-    const size_t lds = (size_t)rows * words * 4 + (size_t)rows * 4;
+    const int rows = retain_rows_per_block(g);
+    const size_t lds = retain_lds_bytes(g, rows);
     static const bool lds_ok = (allow_lds(k_retain<kRetainWaves>), true);
     (void)lds_ok;
     const int blocks = (int)((n_hits + kRetainWaves * 64 - 1) / (kRetainWaves * 64));
@@ -1714,12 +1756,8 @@ hipError_t launch_batch_iterative(const GridArgs &g, const BatchArgs &a, uint16_
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {
-        const int words = (g.n_rho + 31) / 32;
-        const size_t budget = 60 * 1024;
-        int rows = (int)(budget / ((size_t)words * 4 + 4));
-        if (rows > g.n_theta) rows = g.n_theta;
-        if (rows < 1) rows = 1;
-        const size_t lds = (size_t)rows * words * 4 + (size_t)rows * 4;
+        const int rows = retain_rows_per_block(g);
+        const size_t lds = retain_lds_bytes(g, rows);
         static const bool lds_ok = (allow_lds(k_retain<kRetainWaves>), true);
         (void)lds_ok;
         const uint32_t blocks = (kMaxBatchHits + kRetainWaves * 64 - 1) / (kRetainWaves * 64);
