@@ -200,6 +200,16 @@ int hough_run_batch(hough_ctx *ctx, const float *x, const float *y, const uint32
                     uint32_t n_events, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
                     uint32_t *status, void *stream);
 
+/* hough_run_batch with a per-event threshold relative to the event's largest count, the form
+ * of threshold the paper gives its peak finder (Sec. II):
+ *     thr_e = max(threshold of the context, ceil(max_e * frac_num / frac_den)),
+ * with max_e the largest cell of event e's accumulator (integer arithmetic), then the same 3x3
+ * test, listing and retention.  The fused kernel votes every tile twice (once for max_e), so a
+ * call costs up to about 1.5 launches of hough_run_batch.  frac_den == 0: HOUGH_EINVAL. */
+int hough_run_batch_relative(hough_ctx *ctx, const float *x, const float *y, const uint32_t *offsets,
+                             uint32_t n_events, uint32_t frac_num, uint32_t frac_den, hough_peak *peaks,
+                             uint32_t *n_peaks, uint8_t *keep, uint32_t *status, void *stream);
+
 /* hough_run_batch over a chosen subset of a resident event pool (Sec. III batches, as formed by
  * a server from arriving events).  x, y, offsets describe the pool exactly as for
  * hough_run_batch; batch event e is pool event event_ids[e] (device array of n_events pool

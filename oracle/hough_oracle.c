@@ -348,7 +348,8 @@ void oracle_track_params(int n_theta, int n_rho, double rho_min, double rho_max,
  * Whole hot path over CSR-packed events: per event vote, find all peaks, keep hits near any
  * of them, and return the first `cap` peaks of each event (raster order) with the true count.
  * dedup != 0: only the first copy of bit-identical hits votes (every copy is still retained or
- * not by its coordinates).
+ * not by its coordinates).  frac_den > 0: each event's threshold is
+ * max(threshold, ceil(its largest count * frac_num / frac_den)), the relative form of Sec. II.
  * Events are independent (Sec. III), so they are spread over n_threads OpenMP threads; each
  * event is still computed by the plain single-event routines above.
  * peaks_out holds cap triples (j, k, count) per event.  Returns 0, or -1 on allocation failure.
@@ -356,7 +357,7 @@ void oracle_track_params(int n_theta, int n_rho, double rho_min, double rho_max,
 int oracle_run_batch(int n_theta, int n_rho, double rho_min, double rho_max, int threshold,
                      int rho_window, const float *x, const float *y, const uint32_t *offsets,
                      long n_events, long cap, int32_t *peaks_out, int64_t *n_peaks_out,
-                     uint8_t *keep, int n_threads, int periodic, int dedup)
+                     uint8_t *keep, int n_threads, int periodic, int dedup, int frac_num, int frac_den)
 {
     float *C = (float *)malloc(sizeof(float) * (size_t)n_theta);
     float *S = (float *)malloc(sizeof(float) * (size_t)n_theta);
@@ -382,7 +383,15 @@ int oracle_run_batch(int n_theta, int n_rho, double rho_min, double rho_max, int
                 oracle_vote_dedup(n_theta, n_rho, C, S, Bf, x + a, y + a, h, acc);
             else
                 oracle_vote(n_theta, n_rho, C, S, Bf, x + a, y + a, h, acc);
-            long np = oracle_peaks_mode(acc, n_theta, n_rho, threshold, periodic, pj, pk, pc, max_p);
+            int thr = threshold;
+            if (frac_den > 0) {            /* relative threshold: max(T, ceil(max * num / den)) */
+                int32_t mx = 0;
+                for (long c = 0; c < max_p; ++c)
+                    if (acc[c] > mx) mx = acc[c];
+                const int64_t rel = ((int64_t)mx * frac_num + frac_den - 1) / frac_den;
+                thr = rel > thr ? (int)(rel > 0x7fffffff ? 0x7fffffff : rel) : thr;
+            }
+            long np = oracle_peaks_mode(acc, n_theta, n_rho, thr, periodic, pj, pk, pc, max_p);
             oracle_retain(n_rho, C, S, Bf, rho_window, x + a, y + a, h, pj, pk, np, keep + a);
             n_peaks_out[e] = np;
             for (long p = 0; p < np && p < cap; ++p) {

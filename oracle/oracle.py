@@ -82,7 +82,8 @@ def lib():
                                     _i32p, _i32p, c_long, _u8p]
         L.oracle_retain.restype = None
         L.oracle_run_batch.argtypes = [c_int, c_int, c_double, c_double, c_int, c_int, _f32p, _f32p,
-                                       _u32p, c_long, c_long, _i32p, _i64p, _u8p, c_int, c_int, c_int]
+                                       _u32p, c_long, c_long, _i32p, _i64p, _u8p, c_int, c_int, c_int, c_int,
+                                       c_int]
         L.oracle_first_copies.argtypes = [_f32p, _f32p, c_long, _u8p]
         L.oracle_vote_dedup.argtypes = [c_int, c_int, _f32p, _f32p, c_float, _f32p, _f32p, c_long, _i32p]
         L.oracle_run_batch.restype = c_int
@@ -222,9 +223,11 @@ def retain(g: Grid, x, y, pj, pk, rho_window: int = 1) -> np.ndarray:
 
 
 def run_batch(wl_or_grid, x, y, offsets, threshold: int | None = None, rho_window: int | None = None,
-              cap: int = 4096, n_threads: int = 1, periodic: bool = False, dedup: bool = False):
+              cap: int = 4096, n_threads: int = 1, periodic: bool = False, dedup: bool = False,
+              frac: tuple[int, int] | None = None):
     """Whole path over CSR events.  Returns (peaks[E, cap, 3] as (j, k, count), n_peaks[E], keep[H]).
-    dedup: only the first copy of bit-identical hits of an event votes."""
+    dedup: only the first copy of bit-identical hits of an event votes.  frac=(num, den): each
+    event's threshold is max(threshold, ceil(its largest count * num / den))."""
     if isinstance(wl_or_grid, Grid):
         g = wl_or_grid
         if threshold is None or rho_window is None:
@@ -243,7 +246,7 @@ def run_batch(wl_or_grid, x, y, offsets, threshold: int | None = None, rho_windo
     rc = lib().oracle_run_batch(g.n_theta, g.n_rho, g.rho_min, g.rho_max, int(threshold), int(rho_window),
                                 x if x.size else np.zeros(1, np.float32), y if y.size else np.zeros(1, np.float32),
                                 offsets, E, int(cap), out, n_peaks, keep, int(n_threads), int(bool(periodic)),
-                                int(bool(dedup)))
+                                int(bool(dedup)), int(frac[0]) if frac else 0, int(frac[1]) if frac else 0)
     if rc != 0:
         raise MemoryError("oracle_run_batch failed")
     return out[:E], n_peaks[:E], keep[:x.size]

@@ -297,6 +297,8 @@ int hough_run_batch_iterative(hough_ctx *c, const float *x, const float *y, cons
     a.status = status;
     a.max_peaks = (uint32_t)c->p.max_peaks;
     a.queue = nullptr;
+    a.frac_num = 0;
+    a.frac_den = 0;
     const hipError_t e = hough::launch_batch_iterative(c->g, a, static_cast<uint16_t *>(workspace), frac_num,
                                                        frac_den, r_theta, r_rho, (hipStream_t)stream);
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
@@ -331,7 +333,7 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
                             const uint32_t *ids, const uint32_t *keep_offsets, uint32_t n_events,
                             hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
                             void *stream, bool split = false, void *workspace = nullptr,
-                            size_t workspace_bytes = 0) {
+                            size_t workspace_bytes = 0, uint32_t frac_num = 0, uint32_t frac_den = 0) {
     if (!c) return HOUGH_EINVAL;
     if (!on_device(c)) return HOUGH_EINVAL;
     if (n_events == 0) return HOUGH_OK;
@@ -355,6 +357,8 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     a.status = status;
     a.max_peaks = (uint32_t)c->p.max_peaks;
     a.queue = c->d_work;
+    a.frac_num = frac_num;
+    a.frac_den = frac_den;
     hough::SplitArgs sp;
     if (split) {
         if (!hough::split_layout(c->p.n_theta, c->p.n_rho, c->plan.groups, n_events, workspace, workspace_bytes,
@@ -378,6 +382,14 @@ int hough_run_batch(hough_ctx *c, const float *x, const float *y, const uint32_t
                     uint32_t *status, void *stream) {
     return run_batch_common(c, x, y, offsets, nullptr, nullptr, n_events, peaks, n_peaks, keep,
                             status, stream);
+}
+
+int hough_run_batch_relative(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,
+                             uint32_t n_events, uint32_t frac_num, uint32_t frac_den, hough_peak *peaks,
+                             uint32_t *n_peaks, uint8_t *keep, uint32_t *status, void *stream) {
+    if (frac_den == 0) return HOUGH_EINVAL;
+    return run_batch_common(c, x, y, offsets, nullptr, nullptr, n_events, peaks, n_peaks, keep, status, stream,
+                            false, nullptr, 0, frac_num, frac_den);
 }
 
 int hough_run_batch_gather(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,

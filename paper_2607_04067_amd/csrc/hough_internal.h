@@ -62,6 +62,8 @@ struct BatchArgs {
     uint32_t *status;
     uint32_t max_peaks;
     uint32_t *queue;     // [2] work counter and exit counter (device, zero between launches)
+    uint32_t frac_num;   // fused kernel: frac_den != 0 takes each event's threshold as
+    uint32_t frac_den;   // max(threshold, ceil(event maximum * frac_num / frac_den))
 };
 
 // Workspace of the split form (one workgroup per theta tile of an event), laid out by

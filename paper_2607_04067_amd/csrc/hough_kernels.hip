@@ -1165,7 +1165,7 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
     float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * ST);   // [NW * 64]
     uint32_t *pmask = reinterpret_cast<uint32_t *>(stage + NW * 64);       // [nwords * TW]
     uint32_t *dil = pmask + (size_t)nwords * TW;                           // [(nwords + 1) * TW]
-    __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept;
+    __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept, s_max;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const L ln(lane);
     const int tile_words4 = (g.n_rho + 1) * ST / 4;
@@ -1183,6 +1183,7 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             s_flags = 0u;
             s_nvalid = 0u;
             s_nkept = 0u;
+            s_max = 0u;
         }
         __syncthreads();
         // wave-uniform values live in scalar registers
@@ -1229,6 +1230,33 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
         } else if (H > kDedupMaxHits && threadIdx.x == 0) {
             atomicOr(&s_flags, HOUGH_EV_DEDUP_SKIPPED);
         }
+        uint32_t thr = g.threshold;
+        if (a.frac_den) {
+            // relative threshold: a first pass votes every tile only to find the event's
+            // largest count (rows 0 .. n_rho-1: the dummy row is not part of the grid)
+            uint32_t mloc = 0, bad0 = 0;
+#pragma unroll 1
+            for (int t = 0; t < n_tiles; ++t) {
+                const Cols<G> cl = load_cols<G, PER>(g, t * OUT - 1, lane, ST, ln.col);
+                (void)vote_range<G, true, PER>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad0,
+                                               g.dedup ? ke : nullptr);
+                __syncthreads();
+#pragma unroll 1
+                for (int i = threadIdx.x; i < g.n_rho * ST; i += NT) {
+                    const uint32_t d = tile[i];
+                    mloc = max(mloc, max(d & 0xffffu, d >> 16));
+                    tile[i] = 0u;
+                }
+                for (int i = g.n_rho * ST + threadIdx.x; i < (g.n_rho + 1) * ST; i += NT) tile[i] = 0u;
+                __syncthreads();
+            }
+            mloc = wave_max(mloc);
+            if (lane == 0) atomicMax(&s_max, mloc);
+            __syncthreads();
+            const uint64_t rel = ((uint64_t)s_max * a.frac_num + a.frac_den - 1u) / a.frac_den;
+            thr = (uint32_t)__builtin_amdgcn_readfirstlane(
+                (int)min<uint64_t>(max<uint64_t>(rel, g.threshold), 0x7fffffffull));
+        }
         Pending pd;
         pd.idx = 0u;
         pd.live = 0ull;
@@ -1245,13 +1273,13 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
                 const bool interior = u >= 1 && (u + 1) * kPeakRows < g.n_rho;
                 if (PER && (t == 0 || t == n_tiles - 1)) {
                     if (interior)
-                        peak_rows<false, G, true, true>(tile, u, g.n_rho, g.threshold, ln, lane, m, first, g.n_theta);
+                        peak_rows<false, G, true, true>(tile, u, g.n_rho, thr, ln, lane, m, first, g.n_theta);
                     else
-                        peak_rows<true, G, true, true>(tile, u, g.n_rho, g.threshold, ln, lane, m, first, g.n_theta);
+                        peak_rows<true, G, true, true>(tile, u, g.n_rho, thr, ln, lane, m, first, g.n_theta);
                 } else if (interior) {
-                    peak_rows<false, G, true>(tile, u, g.n_rho, g.threshold, ln, lane, m);
+                    peak_rows<false, G, true>(tile, u, g.n_rho, thr, ln, lane, m);
                 } else {
-                    peak_rows<true, G, true>(tile, u, g.n_rho, g.threshold, ln, lane, m);
+                    peak_rows<true, G, true>(tile, u, g.n_rho, thr, ln, lane, m);
                 }
                 uint16_t *pm16 = reinterpret_cast<uint16_t *>(pmask);
 #pragma unroll

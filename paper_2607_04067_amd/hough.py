@@ -77,6 +77,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.hough_max_iterative_candidates.restype = u32
     L.hough_max_dedup_hits.argtypes = []
     L.hough_max_dedup_hits.restype = u32
+    L.hough_run_batch_relative.argtypes = [vp, vp, vp, vp, u32, u32, u32, vp, vp, vp, vp, vp]
+    L.hough_run_batch_relative.restype = i32
     L.hough_iterative_workspace_bytes.argtypes = [vp, u32]
     L.hough_iterative_workspace_bytes.restype = ctypes.c_size_t
     L.hough_run_batch_iterative.argtypes = [vp, vp, vp, vp, u32, u32, u32, ctypes.c_int32, ctypes.c_int32,
@@ -306,8 +308,9 @@ class Context:
     # ----------------------------------------------------------------- fused batch
     def run_batch(self, x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, peaks: torch.Tensor | None = None,
                   n_peaks: torch.Tensor | None = None, keep: torch.Tensor | None = None,
-                  status: torch.Tensor | None = None, stream=None):
-        """Whole path over CSR events.  offsets: int32 [E+1] (uint32 values).
+                  status: torch.Tensor | None = None, stream=None, frac=None):
+        """Whole path over CSR events.  offsets: int32 [E+1] (uint32 values).  frac=(num, den):
+        each event's threshold relative to its largest count (hough_run_batch_relative).
         Returns (peaks int32 [E, max_peaks, 2], n_peaks int32 [E], keep uint8 [H], status int32 [E])."""
         E = offsets.numel() - 1
         mp = self.params.max_peaks
@@ -327,8 +330,12 @@ class Context:
         pk = self._ptr_or_dummy(keep, torch.uint8, "keep")
         px = self._ptr_or_dummy(x, torch.float32, "x")
         py = self._ptr_or_dummy(y, torch.float32, "y")
-        _check(self._lib.hough_run_batch(self._ctx, px, py, po, E, pp, pn, pk, ps, _stream(stream)),
-               "hough_run_batch")
+        if frac is None:
+            _check(self._lib.hough_run_batch(self._ctx, px, py, po, E, pp, pn, pk, ps, _stream(stream)),
+                   "hough_run_batch")
+        else:
+            _check(self._lib.hough_run_batch_relative(self._ctx, px, py, po, E, int(frac[0]), int(frac[1]),
+                                                      pp, pn, pk, ps, _stream(stream)), "hough_run_batch_relative")
         return peaks, n_peaks, keep, status
 
 

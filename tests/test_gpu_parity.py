@@ -890,6 +890,7 @@ def test_random_configurations(H, orc):
         W = int(rng.choice([0, 1, 2, 5, 31, 33]))
         cap = int(rng.choice([0, 1, 7, 300, 5000]))
         dedup = bool(rng.random() < 0.3)
+        frac = [None, (1, 2), (1, 4)][int(rng.integers(0, 3))]
         evs = [pool.event(int(e)) for e in rng.integers(0, 6, 3)]
         evs.append(synth.random_hits(int(rng.integers(0, 700)), seed=case, r_lo=120.0, r_hi=900.0))
         x = np.concatenate([a for a, _ in evs]).astype(np.float32)
@@ -902,8 +903,18 @@ def test_random_configurations(H, orc):
         except H.HoughError:
             continue                                   # beyond the LDS limit for n_rho
         say(f"random case {case}: {n_theta}x{n_rho} [{lo:.4f},{hi:.4f}) T={T} W={W} cap={cap} "
-            f"periodic={periodic} dedup={dedup}")
+            f"periodic={periodic} dedup={dedup} frac={frac}")
         xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
+        if frac is not None:                           # the relative threshold has no split form
+            pk, npk, keep, st = ctx.run_batch(xt, yt, ot, frac=frac)
+            torch.cuda.synchronize()
+            pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=T, rho_window=W, cap=max(cap, 1),
+                                                    n_threads=8, periodic=periodic, dedup=dedup, frac=frac)
+            assert np.array_equal(npk.cpu().numpy()[:len(evs)].astype(np.int64), n_ref), case
+            assert np.array_equal(keep.cpu().numpy(), keep_ref), case
+            ctx.close()
+            ran += 1
+            continue
         pk, npk, keep, st = (t.clone() for t in ctx.run_batch(xt, yt, ot))
         ws = ctx.split_workspace(len(evs))
         sp = ctx.run_batch_split(xt, yt, ot, ws)
@@ -1005,3 +1016,56 @@ def test_batch_iterative_edge_events_and_per_event_path(H, orc):
             m = min(int(n1.item()), 256)
             assert torch.equal(p1[:m], pk[e, :m]), e
         ctx.close()
+
+
+# ------------------------------------------------------------ relative threshold on the fused path
+@pytest.mark.parametrize("name,n_events", [("paper-1000ev-360x256", 24), ("dense-2000ev-720x512", 4),
+                                           ("paper-1000ev-1000x1000", 4), ("plain-16ev-180x128", 16)])
+def test_relative_threshold_parity(H, orc, name, n_events):
+    import torch
+    wl = synth.WORKLOADS[name]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 15, n_events=n_events)
+    xt, yt, ot = H.to_device(ev)
+    for frac, periodic, dedup, cap in [((1, 2), False, False, 20000), ((1, 3), True, False, 20000),
+                                       ((2, 3), False, True, 20000), ((1, 2), False, False, 5)]:
+        say(f"relative {name} frac={frac} periodic={periodic} dedup={dedup} cap={cap}")
+        ctx = H.Context.for_workload(wl, max_peaks=cap, periodic=periodic, dedup=dedup)
+        pk, npk, keep, st = ctx.run_batch(xt, yt, ot, frac=frac)
+        torch.cuda.synchronize()
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, ev.x, ev.y, ev.offsets, threshold=wl.threshold, rho_window=1,
+                                                cap=cap, n_threads=8, periodic=periodic, dedup=dedup, frac=frac)
+        assert np.array_equal(npk.cpu().numpy()[:n_events].astype(np.int64), n_ref)
+        assert np.array_equal(keep.cpu().numpy(), keep_ref)
+        p = pk.cpu().numpy()
+        for e in range(n_events):
+            m = int(min(n_ref[e], cap))
+            assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), e
+        assert np.array_equal((st.cpu().numpy()[:n_events] & H.EV_PEAKS_TRUNCATED) != 0, n_ref > cap)
+        ctx.close()
+
+
+def test_relative_threshold_edge_events(H, orc):
+    import torch
+    evs = _edge_events() + [synth.random_hits(33000, seed=4)]
+    x = np.concatenate([a for a, _ in evs]).astype(np.float32)
+    y = np.concatenate([b for _, b in evs]).astype(np.float32)
+    off = np.zeros(len(evs) + 1, np.uint32)
+    off[1:] = np.cumsum([a.size for a, _ in evs])
+    g = orc.Grid(125, 100, -0.005, 0.005)
+    ctx = H.Context(125, 100, -0.005, 0.005, "i32", 2, 1, 4096)
+    for frac in [(1, 2), (0, 1), (1, 1), (7, 5)]:
+        pk, npk, keep, st = ctx.run_batch(_t(x), _t(y), _t(off.astype(np.int32)), frac=frac)
+        torch.cuda.synchronize()
+        E = len(evs)
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=2, rho_window=1, cap=4096, frac=frac)
+        npk = npk.cpu().numpy()[:E]
+        assert st.cpu().numpy()[E - 1] & H.EV_TOO_MANY_HITS and npk[E - 1] == 0
+        assert np.array_equal(npk[:E - 1].astype(np.int64), n_ref[:E - 1]), frac
+        a = int(off[E - 1])
+        assert np.array_equal(keep.cpu().numpy()[:a], keep_ref[:a]), frac
+        if frac == (7, 5):
+            assert npk[:E - 1].sum() == 0                  # the threshold exceeds every count
+    with pytest.raises(H.HoughError):
+        ctx.run_batch(_t(x), _t(y), _t(off.astype(np.int32)), frac=(1, 0))
+    ctx.close()

@@ -738,3 +738,46 @@ def test_dedup_batch_peaks_and_keep(orc):
         j = int(off[3]) - 500 + i
         if (x[j].tobytes(), y[j].tobytes()) in lookup:
             assert kv == lookup[(x[j].tobytes(), y[j].tobytes())]
+
+
+# ------------------------------------------------------------- relative threshold (Sec. II)
+def test_relative_threshold_batch(orc):
+    """Each event's threshold is max(T, ceil(max * num / den)) with exact integer ceiling
+    (checked here with Python integers); frac = 0/1 leaves the absolute threshold."""
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 8, n_events=4)
+    pk0, n0, keep0 = orc.run_batch(g, ev.x, ev.y, ev.offsets, threshold=10, rho_window=1, cap=20000)
+    pkz, nz, keepz = orc.run_batch(g, ev.x, ev.y, ev.offsets, threshold=10, rho_window=1, cap=20000, frac=(0, 1))
+    assert np.array_equal(n0, nz) and np.array_equal(keep0, keepz) and np.array_equal(pk0, pkz)
+    for frac in [(1, 2), (1, 3), (2, 3)]:
+        pk, n, keep = orc.run_batch(g, ev.x, ev.y, ev.offsets, threshold=10, rho_window=1, cap=20000, frac=frac)
+        for e in range(4):
+            x, y = ev.event(e)
+            acc = orc.vote(g, x, y)
+            m = int(acc.max())
+            thr = max(10, -(-m * frac[0] // frac[1]))
+            pj, pkk, pc, cnt = orc.peaks(acc, thr)
+            assert n[e] == cnt
+            assert np.array_equal(pk[e, :cnt], np.stack([pj, pkk, pc], 1))
+            a, b = int(ev.offsets[e]), int(ev.offsets[e + 1])
+            assert np.array_equal(keep[a:b], orc.retain(g, x, y, pj, pkk, 1))
+            assert np.all(pc >= thr) and cnt <= n0[e]
+
+
+def test_relative_threshold_single_track(orc):
+    """A noiseless track through one cell's centre (count N there) plus noise whose cells stay
+    below N/2: with frac 1/2 the threshold is ceil(N/2) and the track's cell is a peak."""
+    g = orc.Grid(180, 128, -1 / 200, 1 / 200)
+    R, a = 300.0, 0.7
+    radii = np.linspace(200.0, 590.0, 41)
+    x, y = synth.circle_points(a, R, radii)
+    xn, yn = synth.random_hits(15, seed=4)
+    xs = np.concatenate([x.astype(np.float32), xn]); ys = np.concatenate([y.astype(np.float32), yn])
+    off = np.array([0, xs.size], np.uint32)
+    acc = orc.vote(g, xs, ys)
+    m = int(acc.max())
+    assert m >= 40
+    pk, n, keep = orc.run_batch(g, xs, ys, off, threshold=1, rho_window=1, cap=1000, frac=(1, 2))
+    assert np.all(pk[0, :n[0], 2] >= -(-m // 2))
+    assert m in pk[0, :n[0], 2]
