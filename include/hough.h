@@ -195,7 +195,9 @@ int hough_retain(hough_ctx *ctx, const float *x, const float *y, uint32_t n_hits
  * peaks: n_events * max_peaks entries; event e's peaks go to peaks[e * max_peaks ...] in raster
  * order, truncated at max_peaks.  n_peaks[e]: the true peak count.  keep: offsets[n_events]
  * bytes (indexed like x), computed from ALL peaks of the event even when the list is
- * truncated.  status[e]: HOUGH_EV_* bits.  n_events == 0 is valid. */
+ * truncated.  status[e]: HOUGH_EV_* bits.  n_events == 0 is valid.  A batch of more events
+ * than the kernel has resident workgroups (and at most 65,536 events) is preceded by a small
+ * launch that schedules the events largest first; no result depends on the schedule. */
 int hough_run_batch(hough_ctx *ctx, const float *x, const float *y, const uint32_t *offsets,
                     uint32_t n_events, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
                     uint32_t *status, void *stream);

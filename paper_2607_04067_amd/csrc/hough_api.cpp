@@ -15,6 +15,7 @@ struct hough_ctx {
     float *d_tables;        // C[n_theta] then S[n_theta]
     uint32_t *d_work;       // [0], [1]: work and exit counters of the fused kernels; from [64]:
                             // hough_peaks' per-block peak counts
+    uint32_t *d_order;      // [kOrderMaxEvents] the fused kernel's largest-first schedule
     hough::GridArgs g;
     hough::BatchPlan plan;
     size_t lds_limit;
@@ -162,6 +163,12 @@ int hough_config(const hough_params *p, hough_ctx **out) {
         delete c;
         return HOUGH_ENOMEM;
     }
+    if (hipMalloc(&c->d_order, sizeof(uint32_t) * hough::kOrderMaxEvents) != hipSuccess) {
+        (void)hipFree(c->d_work);
+        (void)hipFree(c->d_tables);
+        delete c;
+        return HOUGH_ENOMEM;
+    }
     if (hipMemcpy(c->d_tables, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->d_work, 0, work_bytes) != hipSuccess) {
         hough_destroy(c);
@@ -194,6 +201,7 @@ void hough_destroy(hough_ctx *c) {
     if (!c) return;
     if (c->d_tables) (void)hipFree(c->d_tables);
     if (c->d_work) (void)hipFree(c->d_work);
+    if (c->d_order) (void)hipFree(c->d_order);
     delete c;
 }
 
@@ -284,7 +292,7 @@ int hough_run_batch_iterative(hough_ctx *c, const float *x, const float *y, cons
     if (((uintptr_t)peaks & 7u) != 0 || ((uintptr_t)workspace & 255u) != 0) return HOUGH_EINVAL;
     if (workspace_bytes < hough_iterative_workspace_bytes(c, n_events)) return HOUGH_EINVAL;
     if (hough::peaks_iterative_lds_bytes() > c->lds_limit) return HOUGH_EDEVICE;
-    hough::BatchArgs a;
+    hough::BatchArgs a{};
     a.x = x;
     a.y = y;
     a.offsets = offsets;
@@ -296,6 +304,7 @@ int hough_run_batch_iterative(hough_ctx *c, const float *x, const float *y, cons
     a.keep = keep;
     a.status = status;
     a.max_peaks = (uint32_t)c->p.max_peaks;
+    a.order = nullptr;
     a.queue = nullptr;
     a.frac_num = 0;
     a.frac_den = 0;
@@ -344,7 +353,7 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     long grid = (long)plan.per_cu * c->n_cu;
     if (grid > (long)n_events) grid = n_events;
     plan.grid = (int)grid;
-    hough::BatchArgs a;
+    hough::BatchArgs a{};
     a.x = x;
     a.y = y;
     a.offsets = offsets;
@@ -356,6 +365,7 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     a.keep = keep;
     a.status = status;
     a.max_peaks = (uint32_t)c->p.max_peaks;
+    a.order = nullptr;
     a.queue = c->d_work;
     a.frac_num = frac_num;
     a.frac_den = frac_den;
@@ -371,6 +381,12 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     }
     hipError_t e = hipSuccess;
     if (c->g.dedup) e = hough::launch_dedup(a, (hipStream_t)stream);   // marks later copies in keep
+    // more events than resident workgroups: take them largest first, so that the batch does not
+    // end waiting for a large event begun last (a gathered batch keeps the caller's order)
+    if (e == hipSuccess && !split && !ids && n_events > (uint32_t)plan.grid && n_events <= hough::kOrderMaxEvents) {
+        e = hough::launch_order(offsets, n_events, c->d_order, (hipStream_t)stream);
+        a.order = c->d_order;
+    }
     if (e == hipSuccess)
         e = split ? hough::launch_batch_split(c->g, plan, a, sp, (hipStream_t)stream)
                   : hough::launch_batch(c->g, plan, a, (hipStream_t)stream);

@@ -61,6 +61,7 @@ struct BatchArgs {
     uint8_t *keep;
     uint32_t *status;
     uint32_t max_peaks;
+    const uint32_t *order;          // null, or the batch event taken at each queue position
     uint32_t *queue;     // [2] work counter and exit counter (device, zero between launches)
     uint32_t frac_num;   // fused kernel: frac_den != 0 takes each event's threshold as
     uint32_t frac_den;   // max(threshold, ceil(event maximum * frac_num / frac_den))
@@ -82,7 +83,16 @@ size_t split_workspace_bytes(int n_theta, int n_rho, int groups, uint32_t n_even
 bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *ws, size_t bytes,
                   SplitArgs *out);
 
+// Largest-first schedule of the fused kernel: for batches of more events than resident
+// workgroups (and at most kOrderMaxEvents of them) a one-workgroup pass sorts the events by
+// hit count, largest first, in size classes of 1/64 of an octave, so that the last events
+// taken from the work queue are the small ones.  Which workgroup runs an event never changes
+// its results.
+constexpr uint32_t kOrderMaxEvents = 1u << 16;
+
 // Launchers (hough_kernels.hip).  All return a hipError_t from the launch.
+// order[0 .. n_events) := the events of offsets (CSR, n_events + 1 entries) largest first.
+hipError_t launch_order(const uint32_t *offsets, uint32_t n_events, uint32_t *order, hipStream_t s);
 // Duplicate pass of the batch path: writes every keep byte of each well-formed event of at
 // most kMaxBatchHits hits, kKeepDuplicate for a later copy of a hit and 0 otherwise (all 0 for
 // events above kDedupMaxHits).

@@ -1178,7 +1178,8 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
 
     for (;;) {
         if (threadIdx.x == 0) {
-            s_event = atomicAdd(a.queue, 1u);
+            const uint32_t q = atomicAdd(a.queue, 1u);
+            s_event = (a.order && q < a.n_events) ? a.order[q] : q;
             s_npeaks = 0u;
             s_flags = 0u;
             s_nvalid = 0u;
@@ -1548,6 +1549,49 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
 constexpr int kDedupThreads = 512;
 constexpr uint32_t kEmptySlot = 0xffffffffu;
 
+// ------------------------------------------------------------------ largest-first schedule
+// Size class of an event of H hits, non-decreasing in H: H itself below 64, else the octave
+// of H and its next six bits (classes of 1/64 of an octave), at most 1727.  Malformed events
+// (offsets decreasing) count as empty.
+__device__ __forceinline__ uint32_t size_class(const uint32_t *offsets, uint32_t e) {
+    const uint32_t h0 = offsets[e], h1 = offsets[e + 1];
+    const uint32_t H = h1 >= h0 ? h1 - h0 : 0u;
+    if (H < 64u) return H;
+    const uint32_t lg = 31u - (uint32_t)__builtin_clz(H);
+    return ((lg - 5u) << 6) | ((H >> (lg - 6u)) & 63u);
+}
+
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderClasses = 2048;
+
+// One workgroup: count the events of each size class, turn the counts into the first queue
+// position of each class (largest class first) and scatter the event indices there.  Within a
+// class the order is whatever the LDS atomics give.
+__global__ __launch_bounds__(kOrderThreads) void k_order(const uint32_t *__restrict__ offsets, uint32_t n_events,
+                                                          uint32_t *__restrict__ order) {
+    __shared__ uint32_t cnt[kOrderClasses];
+    for (int i = threadIdx.x; i < kOrderClasses; i += kOrderThreads) cnt[i] = 0u;
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < n_events; e += kOrderThreads)
+        atomicAdd(&cnt[kOrderClasses - 1 - size_class(offsets, e)], 1u);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        uint32_t c[kOrderClasses / 64], sum = 0;
+#pragma unroll
+        for (int i = 0; i < kOrderClasses / 64; ++i) { c[i] = cnt[lane * (kOrderClasses / 64) + i]; sum += c[i]; }
+        uint32_t start = wave_inclusive_scan(sum, lane) - sum;
+#pragma unroll
+        for (int i = 0; i < kOrderClasses / 64; ++i) {
+            cnt[lane * (kOrderClasses / 64) + i] = start;
+            start += c[i];
+        }
+    }
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < n_events; e += kOrderThreads)
+        order[atomicAdd(&cnt[kOrderClasses - 1 - size_class(offsets, e)], 1u)] = e;
+}
+
 __device__ __forceinline__ uint32_t dedup_hash(uint32_t kx, uint32_t ky) {
     uint32_t h = kx * 0x9e3779b1u;
     h ^= ky + 0x7f4a7c15u + (h << 6) + (h >> 2);
@@ -1663,6 +1707,12 @@ int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, 
     p.grid = 0;
     *out = p;
     return 0;
+}
+
+hipError_t launch_order(const uint32_t *offsets, uint32_t n_events, uint32_t *order, hipStream_t s) {
+    if (n_events == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_order, dim3(1), dim3(kOrderThreads), 0, s, offsets, n_events, order);
+    return hipGetLastError();
 }
 
 hipError_t launch_dedup(const BatchArgs &a, hipStream_t s) {

@@ -416,6 +416,46 @@ def test_run_batch_in_hip_graph(H):
     ctx.close()
 
 
+def test_largest_first_schedule_keeps_results(H, orc):
+    """A batch of more events than resident workgroups is taken largest first (up to 65,536
+    events, in index order beyond): every event's results equal the oracle's, and those of the
+    same events gathered in index order."""
+    import torch
+    wl = synth.WORKLOADS["batch-10000ev-360x256"]
+    g = orc.Grid.of(wl)
+    pool = synth.make_events(wl, 0, n_events=400)
+    rng = np.random.default_rng(5)
+    xs, ys, offs = [], [], [0]
+    for e in range(pool.n_events):                   # sizes from empty to whole events
+        x, y = pool.event(e)
+        n = int(rng.integers(0, x.size + 1)) if e % 3 else x.size
+        xs.append(x[:n]); ys.append(y[:n]); offs.append(offs[-1] + n)
+    x = np.concatenate(xs); y = np.concatenate(ys); offs = np.array(offs, np.uint32)
+    for per_cu in (1, 0):
+        say(f"largest first: 400 events, {per_cu or 'all'} workgroups per CU")
+        ctx = H.Context.for_workload(wl, max_peaks=4096)
+        if per_cu:
+            ctx.set_batch_plan(8, 1, per_cu)
+        _batch_check(H, orc, ctx, g, wl.threshold, wl.rho_window, x, y, offs, 4096)
+        xt, yt, ot = _t(x), _t(y), _t(offs.astype(np.int32))
+        r = ctx.run_batch(xt, yt, ot)
+        ids = _t(np.arange(400, dtype=np.int32))
+        gth = ctx.run_batch_gather(xt, yt, ot, ids, _t(offs[:-1].astype(np.int32)), keep_size=x.size)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(r, gth))
+        ctx.close()
+    # beyond 65,536 events: tiny events and a few large ones, in index order
+    n_ev = 65536 + 300
+    sizes = rng.integers(0, 4, n_ev)
+    sizes[::997] = 600
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
+    x, y = synth.random_hits(int(offs[-1]), seed=9, r_lo=200, r_hi=810)
+    say(f"index order: {n_ev} events, {x.size} hits")
+    ctx = H.Context.for_workload(wl, max_peaks=64)
+    _batch_check(H, orc, ctx, g, wl.threshold, wl.rho_window, x, y, offs, 64)
+    ctx.close()
+
+
 def test_gather_batches_equal_plain_batches(H):
     """A batch formed from pool indices (repeats allowed, keep at batch-local offsets) gives the
     same per-event results as a CSR batch of the same events."""
