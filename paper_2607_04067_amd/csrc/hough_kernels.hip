@@ -375,12 +375,17 @@ __device__ __forceinline__ void store_peak(hough_peak *out, uint32_t j, uint32_t
 // column).  It also writes the dilated words dil[wd * TW + c]: bit b set iff a peak of column c
 // lies within rho_window rows of row 32*wd + b.  For rho_window < 32 a word follows from the
 // peak words above and below it; wider windows OR the row range of every peak into dil (which
-// the peak phase cleared).  Returns the tile's peak count.
+// the peak phase cleared).  tpk (optional): when the tile has at most kTilePeaks peaks, all of
+// them in raster order, each with its column's C and S (and its row as the bits of z), for the
+// retention of tiles with few peaks.  Returns the tile's peak count.
+constexpr uint32_t kTilePeaks = 64;
+
 template <int G, bool P>
 __device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask, uint32_t *dil,
                                     int nwords, int first_col, const GridArgs &g, hough_peak *out,
                                     uint32_t cap, uint32_t base, const Lane<G, P> &ln, int lane,
-                                    int wave, int n_waves) {
+                                    int wave, int n_waves, float4 *tpk = nullptr,
+                                    const Cols<G> *cl = nullptr) {
     constexpr int TW = 64 * G, ST = Lane<G, P>::STRIDE;
     const int W = g.rho_window;
     uint32_t colbase[G];
@@ -394,6 +399,7 @@ __device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask,
         carry += __shfl(incl, 63, 64);
     }
     if (carry == 0u) return 0u;
+    const bool rec = tpk != nullptr && carry <= kTilePeaks;   // then every local index fits
     for (int wd = wave; wd < nwords; wd += n_waves) {
 #pragma unroll
         for (int q = 0; q < G; ++q) {
@@ -417,6 +423,7 @@ __device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask,
                 const int k = wd * 32 + b;
                 const uint32_t cv = ln.count(tile[k * ST + ln.col[q]]);
                 if (idx < cap) store_peak(out + idx, j, (uint32_t)k, cv);
+                if (rec) tpk[idx - base] = make_float4(cl->C[q], cl->S[q], __uint_as_float((uint32_t)k), 0.0f);
                 ++idx;
                 if (W >= 32) {
                     const int lo = k - W > 0 ? k - W : 0;
@@ -606,6 +613,63 @@ __device__ uint32_t retain_range(const uint32_t *dil, float2 *st, const float *x
         newly += nk;
         left += n.total - nk;
         wave_sync();
+    }
+    return newly;
+}
+
+// Step 5 on a tile with at most kTilePeaks peaks, one lane per hit: hit (u, v) is kept by
+// peak (column j, row k) when its own bin in column j (the vote's arithmetic, in range) is
+// within rho_window of k, which is what a lookup of the dilated words tests; here it costs
+// one step per peak for 64 hits instead of one step per hit for the tile's columns.
+__device__ __forceinline__ bool kept_by_peaks(const float4 *tpk, uint32_t np, float u, float v,
+                                              const GridArgs &g) {
+    bool kept = false;
+#pragma unroll 4
+    for (uint32_t p = 0; p < np; ++p) {
+        const float4 P = tpk[p];                       // the same address in every lane
+        const float t = __builtin_fmaf(u, P.x, __builtin_fmaf(v, P.y, g.Bf));
+        const int d = (int)t - (int)__float_as_uint(P.z);
+        kept |= (t >= 0.0f) && (t < g.nrho_f) && (d <= g.rho_window) && (d >= -g.rho_window);
+    }
+    return kept;
+}
+
+// retain_pending with the tile's peak list.
+__device__ uint32_t retain_pending_peaks(Pending &pd, const float4 *tpk, uint32_t np, const float *x,
+                                         const float *y, uint8_t *ke, const GridArgs &g, int lane) {
+    if (pd.live == 0ull) return 0u;
+    const bool me = (pd.live >> lane) & 1ull;
+    const uint32_t idx = pd.idx & 0x7fffffffu;
+    bool kept = false;
+    if (me) {
+        float u, v;
+        (void)conformal(x[idx], y[idx], u, v);
+        kept = kept_by_peaks(tpk, np, u, v, g);
+    }
+    if (kept) ke[idx] = (uint8_t)(1u | ((pd.idx >> 30) & (uint32_t)kKeepDuplicate));
+    const uint64_t kept_lanes = __ballot(kept);
+    pd.live &= ~kept_lanes;
+    return (uint32_t)__popcll(kept_lanes);
+}
+
+// retain_range with the tile's peak list: each lane maps and tests its own unkept hit.
+__device__ uint32_t retain_range_peaks(const float4 *tpk, uint32_t np, const float *x, const float *y,
+                                       uint8_t *ke, uint32_t hb, uint32_t he, const GridArgs &g, int lane,
+                                       uint32_t &left) {
+    uint32_t newly = 0;
+    left = 0;
+    for (uint32_t base = hb; base < he; base += 64) {
+        const uint32_t i = base + lane;
+        const uint32_t kv = (i < he) ? ke[i] : 1u;
+        const bool cand = (i < he) && !(kv & 1u);
+        if (__ballot(cand) == 0ull) continue;            // whole chunk already kept
+        float u = 0.0f, v = 0.0f;
+        bool valid = false, kept = false;
+        if (cand) valid = conformal(x[i], y[i], u, v);
+        if (valid) kept = kept_by_peaks(tpk, np, u, v, g);
+        if (kept) ke[i] = (uint8_t)(kv | 1u);
+        newly += (uint32_t)__popcll(__ballot(kept));
+        left += (uint32_t)__popcll(__ballot(valid && !kept));
     }
     return newly;
 }
@@ -1156,7 +1220,10 @@ __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__r
 // queue[0] is the work counter and queue[1] counts workgroups that have left the loop; the
 // last one to leave (every pop has then happened) puts both back to zero for the next launch,
 // so a launch is a single kernel with no memset.
-template <int NW, int G, bool PER>
+// SP: tiles with at most kTilePeaks peaks list them for the peak-list retention (the plan's
+// choice for sparse grids and the relative threshold; compiled out otherwise, where it only
+// costs).
+template <int NW, int G, bool PER, bool SP>
 __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, BatchArgs a, int n_tiles, int nwords) {
     using L = Lane<G, true>;
     constexpr int TW = L::TW, ST = L::STRIDE, OUT = TW - 2, NT = NW * 64;
@@ -1165,6 +1232,7 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
     float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * ST);   // [NW * 64]
     uint32_t *pmask = reinterpret_cast<uint32_t *>(stage + NW * 64);       // [nwords * TW]
     uint32_t *dil = pmask + (size_t)nwords * TW;                           // [(nwords + 1) * TW]
+    float4 *tpk = reinterpret_cast<float4 *>(dil + (size_t)(nwords + 1) * TW);   // [kTilePeaks]
     __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept, s_max;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const L ln(lane);
@@ -1262,6 +1330,7 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
         pd.idx = 0u;
         pd.live = 0ull;
         pd.on = false;
+        uint32_t unkept = he - hb;           // this wave's unkept hits after its last full pass
         for (int t = 0; t < n_tiles; ++t) {
             const int first = t * OUT - 1;      // grid column of lane 0 of group 0
             const Cols<G> cl = load_cols<G, PER>(g, first, lane, ST, ln.col);
@@ -1296,8 +1365,13 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             }
             __syncthreads();
             const uint32_t base = s_npeaks;
-            const uint32_t np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, pe, cap, base,
-                                                         ln, lane, wave, NW);
+            uint32_t np;
+            if constexpr (SP)
+                np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, pe, cap, base, ln, lane, wave,
+                                              NW, tpk, &cl);
+            else
+                np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, pe, cap, base, ln, lane, wave,
+                                              NW);
             __syncthreads();
             if (threadIdx.x == 0) s_npeaks = base + np;
             // the counts are dead: clear the tile for the next one while retention reads dil
@@ -1305,13 +1379,23 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             for (int i = threadIdx.x; i < tile_words4; i += NT)
                 reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
             if (np && s_nkept < s_nvalid) {
+                // Few peaks: test each hit against the peak list (about 9 instructions per peak
+                // for a chunk of 64 hits, kept or not) where that beats looking the unkept hits
+                // up in every column's dilated words (about 7 per unkept hit, plus staging).
+                const bool few = SP && np <= kTilePeaks;
                 uint32_t newly;
                 if (pd.on) {
-                    newly = retain_pending<G>(pd, dil, stage + wave * 64, xe, ye, ke, cl, g, lane);
+                    const uint32_t n = (uint32_t)__popcll(pd.live);
+                    newly = (few && np * 9u < n * 7u + 10u)
+                                ? retain_pending_peaks(pd, tpk, np, xe, ye, ke, g, lane)
+                                : retain_pending<G>(pd, dil, stage + wave * 64, xe, ye, ke, cl, g, lane);
                 } else {
                     uint32_t left = 0;
-                    newly = retain_range<G>(dil, stage + wave * 64, xe, ye, ke, hb, he, cl, g, lane,
-                                            left);
+                    const uint32_t chunks = (he - hb + 63u) >> 6;
+                    newly = (few && np * 9u * chunks < unkept * 7u + chunks * 10u)
+                                ? retain_range_peaks(tpk, np, xe, ye, ke, hb, he, g, lane, left)
+                                : retain_range<G>(dil, stage + wave * 64, xe, ye, ke, hb, he, cl, g, lane, left);
+                    if (SP) unkept = left;
                     if (left <= 64u) build_pending(pd, stage + wave * 64, xe, ye, ke, hb, he, lane);
                 }
                 if (lane == 0 && newly) atomicAdd(&s_nkept, newly);
@@ -1691,7 +1775,7 @@ size_t peaks_lds_bytes(int n_rho) { return (size_t)(kPeakWaves + 2) * n_rho * 4 
 size_t batch_lds_bytes(int n_rho, int waves, int groups) {
     const size_t tw = 64u * groups, nwords = (size_t)(n_rho + 31) / 32;
     return (size_t)(n_rho + 1) * (tw / 2) * 4 + (size_t)waves * kStageBytes + nwords * tw * 4 +
-           (nwords + 1) * tw * 4;
+           (nwords + 1) * tw * 4 + kTilePeaks * sizeof(float4);
 }
 
 int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out) {
@@ -1703,6 +1787,7 @@ int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, 
     p.out_cols = p.tile_cols - 2;
     p.n_tiles = (n_theta + p.out_cols - 1) / p.out_cols;
     p.lds_bytes = batch_lds_bytes(n_rho, waves, groups);
+    p.sparse = n_rho >= kSparseRhoRows ? 1 : 0;
     if (p.lds_bytes + 256 > lds_limit) return -1;      // room for the kernel's static LDS
     p.grid = 0;
     *out = p;
@@ -1846,16 +1931,25 @@ hipError_t launch_batch_iterative(const GridArgs &g, const BatchArgs &a, uint16_
     return e;
 }
 
+template <int NW, int G, bool SP>
+static void launch_batch_sp(const GridArgs &g, const BatchPlan &p, const BatchArgs &a, hipStream_t s) {
+    const int nwords = (g.n_rho + 31) / 32;
+    if (g.periodic)
+        hipLaunchKernelGGL((k_batch<NW, G, true, SP>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
+                           p.n_tiles, nwords);
+    else
+        hipLaunchKernelGGL((k_batch<NW, G, false, SP>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
+                           p.n_tiles, nwords);
+}
+
 template <int NW, int G>
 static hipError_t launch_batch_t(const GridArgs &g, const BatchPlan &p, const BatchArgs &a,
                                  hipStream_t s) {
-    const int nwords = (g.n_rho + 31) / 32;
-    if (g.periodic)
-        hipLaunchKernelGGL((k_batch<NW, G, true>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
-                           p.n_tiles, nwords);
+    // a relative threshold leaves few peaks per tile whatever the grid
+    if (p.sparse || a.frac_den != 0u)
+        launch_batch_sp<NW, G, true>(g, p, a, s);
     else
-        hipLaunchKernelGGL((k_batch<NW, G, false>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
-                           p.n_tiles, nwords);
+        launch_batch_sp<NW, G, false>(g, p, a, s);
     return hipGetLastError();
 }
 
@@ -1945,18 +2039,22 @@ bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *w
 template <int NW, int G>
 static int prepare_t(size_t lds, size_t) {
     // both grid topologies and both forms: a context's plan serves whichever kernel it launches
-    allow_lds(k_batch<NW, G, false>);
-    allow_lds(k_batch<NW, G, true>);
+    allow_lds(k_batch<NW, G, false, false>);
+    allow_lds(k_batch<NW, G, true, false>);
+    allow_lds(k_batch<NW, G, false, true>);
+    allow_lds(k_batch<NW, G, true, true>);
     allow_lds(k_batch_split<NW, G, false>);
     allow_lds(k_batch_split<NW, G, true>);
-    int n[4] = {0, 0, 0, 0};
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[0], k_batch<NW, G, false>, NW * 64, lds) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[1], k_batch<NW, G, true>, NW * 64, lds) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[2], k_batch_split<NW, G, false>, NW * 64, lds) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[3], k_batch_split<NW, G, true>, NW * 64, lds) != hipSuccess)
+    int n[6] = {0, 0, 0, 0, 0, 0};
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[0], k_batch<NW, G, false, false>, NW * 64, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[1], k_batch<NW, G, true, false>, NW * 64, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[2], k_batch<NW, G, false, true>, NW * 64, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[3], k_batch<NW, G, true, true>, NW * 64, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[4], k_batch_split<NW, G, false>, NW * 64, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[5], k_batch_split<NW, G, true>, NW * 64, lds) != hipSuccess)
         return 0;
     int m = n[0];
-    for (int i = 1; i < 4; ++i) m = n[i] < m ? n[i] : m;
+    for (int i = 1; i < 6; ++i) m = n[i] < m ? n[i] : m;
     return m;
 }
 

@@ -697,7 +697,8 @@ def _theta_pi_track(g, k):
     return px.astype(np.float32), py.astype(np.float32)
 
 
-@pytest.mark.parametrize("n_theta,n_rho", [(360, 256), (62, 64), (63, 100), (2, 16), (125, 7), (720, 512)])
+@pytest.mark.parametrize("n_theta,n_rho", [(360, 256), (62, 64), (63, 100), (2, 16), (125, 7), (720, 512),
+                                           (100, 800), (360, 1000)])
 def test_periodic_grid_plain_and_batch(H, orc, n_theta, n_rho):
     import torch
     lo, hi = -1 / 200, 1 / 200
@@ -832,7 +833,8 @@ def _dup_events():
 
 
 @pytest.mark.parametrize("n_theta,n_rho,lo,hi,T", [(360, 256, -1 / 200, 1 / 200, 10), (180, 128, -1 / 200, 1 / 200, 8),
-                                                   (720, 512, -1 / 200, 1 / 200, 12), (125, 100, -0.005, 0.005, 3)])
+                                                   (720, 512, -1 / 200, 1 / 200, 12), (125, 100, -0.005, 0.005, 3),
+                                                   (360, 1000, -1 / 100, 1 / 100, 20)])
 def test_dedup_batch_parity_with_oracle(H, orc, n_theta, n_rho, lo, hi, T):
     import torch
     g = orc.Grid(n_theta, n_rho, lo, hi)
@@ -920,7 +922,7 @@ def test_random_configurations(H, orc):
     ran = 0
     for case in range(20):
         n_theta = int(rng.integers(1, 420))
-        n_rho = int(rng.integers(1, 600))
+        n_rho = int(rng.integers(1, 1100))
         periodic = bool(rng.random() < 0.3) and n_theta >= 2
         if periodic:
             hi = float(rng.uniform(0.001, 0.008)); lo = -hi
