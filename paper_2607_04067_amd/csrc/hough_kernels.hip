@@ -375,7 +375,8 @@ __device__ __forceinline__ void store_peak(hough_peak *out, uint32_t j, uint32_t
 // column).  It also writes the dilated words dil[wd * TW + c]: bit b set iff a peak of column c
 // lies within rho_window rows of row 32*wd + b.  For rho_window < 32 a word follows from the
 // peak words above and below it; wider windows OR the row range of every peak into dil (which
-// the peak phase cleared).  tpk (optional): when the tile has at most kTilePeaks peaks, all of
+// the peak phase cleared).  colcnt (optional): each column's peak count, summed by the peak
+// phase (else counted here from pmask).  tpk (optional): when the tile has at most kTilePeaks peaks, all of
 // them in raster order, each with its column's C and S (and its row as the bits of z), for the
 // retention of tiles with few peaks.  Returns the tile's peak count.
 constexpr uint32_t kTilePeaks = 64;
@@ -385,7 +386,7 @@ __device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask,
                                     int nwords, int first_col, const GridArgs &g, hough_peak *out,
                                     uint32_t cap, uint32_t base, const Lane<G, P> &ln, int lane,
                                     int wave, int n_waves, float4 *tpk = nullptr,
-                                    const Cols<G> *cl = nullptr) {
+                                    const Cols<G> *cl = nullptr, const uint32_t *colcnt = nullptr) {
     constexpr int TW = 64 * G, ST = Lane<G, P>::STRIDE;
     const int W = g.rho_window;
     uint32_t colbase[G];
@@ -393,7 +394,10 @@ __device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask,
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         uint32_t tot = 0;
-        for (int w = 0; w < nwords; ++w) tot += __popc(pmask[w * TW + 64 * q + lane]);
+        if (colcnt)
+            tot = colcnt[64 * q + lane];
+        else
+            for (int w = 0; w < nwords; ++w) tot += __popc(pmask[w * TW + 64 * q + lane]);
         const uint32_t incl = wave_inclusive_scan(tot, lane);
         colbase[q] = carry + incl - tot;
         carry += __shfl(incl, 63, 64);
@@ -1233,6 +1237,7 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
     uint32_t *pmask = reinterpret_cast<uint32_t *>(stage + NW * 64);       // [nwords * TW]
     uint32_t *dil = pmask + (size_t)nwords * TW;                           // [(nwords + 1) * TW]
     float4 *tpk = reinterpret_cast<float4 *>(dil + (size_t)(nwords + 1) * TW);   // [kTilePeaks]
+    uint32_t *colcnt = reinterpret_cast<uint32_t *>(tpk + kTilePeaks);            // [TW] peaks per column
     __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept, s_max;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const L ln(lane);
@@ -1243,6 +1248,7 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
     for (int i = threadIdx.x; i < tile_words4; i += NT)
         reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
     for (int i = threadIdx.x; i < TW; i += NT) dil[nwords * TW + i] = 0u;
+    for (int i = threadIdx.x; i < TW; i += NT) colcnt[i] = 0u;   // zero again after each listing
 
     for (;;) {
         if (threadIdx.x == 0) {
@@ -1357,6 +1363,7 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
                     const int c = 64 * q + lane;
                     const bool out_col = (c >= 1) && (c <= TW - 2) && (first + c < g.n_theta);
                     pm16[((u >> 1) * TW + c) * 2 + (u & 1)] = out_col ? (uint16_t)m[q] : (uint16_t)0;
+                    if (out_col && m[q]) atomicAdd(&colcnt[c], (uint32_t)__popc(m[q]));
                 }
             }
             if (g.rho_window >= 32) {
@@ -1368,12 +1375,13 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             uint32_t np;
             if constexpr (SP)
                 np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, pe, cap, base, ln, lane, wave,
-                                              NW, tpk, &cl);
+                                              NW, tpk, &cl, colcnt);
             else
                 np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, pe, cap, base, ln, lane, wave,
-                                              NW);
+                                              NW, nullptr, nullptr, colcnt);
             __syncthreads();
             if (threadIdx.x == 0) s_npeaks = base + np;
+            for (int i = threadIdx.x; i < TW; i += NT) colcnt[i] = 0u;
             // the counts are dead: clear the tile for the next one while retention reads dil
 #pragma unroll 1
             for (int i = threadIdx.x; i < tile_words4; i += NT)
@@ -1775,7 +1783,7 @@ size_t peaks_lds_bytes(int n_rho) { return (size_t)(kPeakWaves + 2) * n_rho * 4 
 size_t batch_lds_bytes(int n_rho, int waves, int groups) {
     const size_t tw = 64u * groups, nwords = (size_t)(n_rho + 31) / 32;
     return (size_t)(n_rho + 1) * (tw / 2) * 4 + (size_t)waves * kStageBytes + nwords * tw * 4 +
-           (nwords + 1) * tw * 4 + kTilePeaks * sizeof(float4);
+           (nwords + 1) * tw * 4 + kTilePeaks * sizeof(float4) + tw * 4;
 }
 
 int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out) {
