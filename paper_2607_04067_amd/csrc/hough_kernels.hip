@@ -286,7 +286,8 @@ __device__ __forceinline__ uint32_t cell_or_zero(const uint32_t *tile, int k, in
 // WRAP (theta-periodic grid, first and last tile): the halo column beside column 0 is column
 // n_theta - 1 and follows it in raster order, the one beside column n_theta - 1 is column 0 and
 // precedes it, so for those two lanes the strict and the non-strict side trade places.
-template <bool CHECK, int G, bool P, bool WRAP = false>
+// UNROLL: issue the reads of all four 4-row blocks together (for kernels with the registers).
+template <bool CHECK, int G, bool P, bool WRAP = false, bool UNROLL = false>
 __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_rho, uint32_t T,
                                           const Lane<G, P> &ln, int lane, uint32_t *mask,
                                           int first_col = 0, int n_theta = 0) {
@@ -298,8 +299,7 @@ __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_
         Mc[q] = cell_or_zero<CHECK, G, P>(tile, k0, n_rho, ln, q);
         mask[q] = 0u;
     }
-#pragma unroll 1
-    for (int r0 = 0; r0 < kPeakRows; r0 += 4) {
+    auto block = [&](int r0) {
         uint32_t N[G][4];
 #pragma unroll
         for (int d = 0; d < 4; ++d)
@@ -313,7 +313,7 @@ __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_
         if (__ballot(bm >= T) == 0ull) {
 #pragma unroll
             for (int q = 0; q < G; ++q) { Mp[q] = N[q][2]; Mc[q] = N[q][3]; }
-            continue;
+            return;
         }
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
@@ -349,6 +349,13 @@ __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_
 #pragma unroll
             for (int q = 0; q < G; ++q) { Mp[q] = Mc[q]; Mc[q] = N[q][d]; }
         }
+    };
+    if constexpr (UNROLL) {
+#pragma unroll
+        for (int r0 = 0; r0 < kPeakRows; r0 += 4) block(r0);
+    } else {
+#pragma unroll 1
+        for (int r0 = 0; r0 < kPeakRows; r0 += 4) block(r0);
     }
 }
 
@@ -1228,7 +1235,7 @@ __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__r
 // choice for sparse grids and the relative threshold; compiled out otherwise, where it only
 // costs).
 template <int NW, int G, bool PER, bool SP>
-__global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, BatchArgs a, int n_tiles, int nwords) {
+__global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_batch(GridArgs g, BatchArgs a, int n_tiles, int nwords) {
     using L = Lane<G, true>;
     constexpr int TW = L::TW, ST = L::STRIDE, OUT = TW - 2, NT = NW * 64;
     extern __shared__ __align__(16) uint32_t lds[];
@@ -1347,15 +1354,16 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch(GridArgs g, B
             for (int u = wave; u < 2 * nwords; u += NW) {
                 uint32_t m[G];
                 const bool interior = u >= 1 && (u + 1) * kPeakRows < g.n_rho;
+                constexpr bool UR = NW == 16;      // launch bound of 4 waves per SIMD: registers to spare
                 if (PER && (t == 0 || t == n_tiles - 1)) {
                     if (interior)
-                        peak_rows<false, G, true, true>(tile, u, g.n_rho, thr, ln, lane, m, first, g.n_theta);
+                        peak_rows<false, G, true, true, UR>(tile, u, g.n_rho, thr, ln, lane, m, first, g.n_theta);
                     else
-                        peak_rows<true, G, true, true>(tile, u, g.n_rho, thr, ln, lane, m, first, g.n_theta);
+                        peak_rows<true, G, true, true, UR>(tile, u, g.n_rho, thr, ln, lane, m, first, g.n_theta);
                 } else if (interior) {
-                    peak_rows<false, G, true>(tile, u, g.n_rho, thr, ln, lane, m);
+                    peak_rows<false, G, true, false, UR>(tile, u, g.n_rho, thr, ln, lane, m);
                 } else {
-                    peak_rows<true, G, true>(tile, u, g.n_rho, thr, ln, lane, m);
+                    peak_rows<true, G, true, false, UR>(tile, u, g.n_rho, thr, ln, lane, m);
                 }
                 uint16_t *pm16 = reinterpret_cast<uint16_t *>(pmask);
 #pragma unroll
