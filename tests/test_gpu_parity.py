@@ -389,13 +389,15 @@ def test_autotune_keeps_results(H, tmp_path):
     ctx.close()
 
 
-def test_run_batch_in_hip_graph(H):
+@pytest.mark.parametrize("n_events,n_other", [(200, 50), (1000, 800)])
+def test_run_batch_in_hip_graph(H, n_events, n_other):
     """Capture one hough_run_batch in a graph; every replay (with eager work in between) must
-    reproduce the eager result."""
+    reproduce the eager result.  With more events than workgroup slots the graph holds the
+    schedule pass too, and the eager batches in between rewrite the context's schedule."""
     import torch
     wl = synth.WORKLOADS["batch-10000ev-360x256"]
-    ev = synth.make_events(wl, 0, n_events=200)
-    other = synth.make_events(wl, 5, n_events=50)
+    ev = synth.make_events(wl, 0, n_events=n_events)
+    other = synth.make_events(wl, 5, n_events=n_other)
     ctx = H.Context.for_workload(wl, max_peaks=8192)
     xt, yt, ot = H.to_device(ev)
     xo, yo, oo = H.to_device(other)
