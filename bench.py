@@ -494,7 +494,7 @@ def sweeps(H, wl, ev, reps: int = 10, cpu_budget_s: float = 20.0):
         log(f"sweep events {row}")
         out["events"].append(row)
     sub = ev.subset(np.arange(min(1000, ev.n_events)))
-    for waves in (4, 6, 8, 16):
+    for waves in (4, 6, 8, 12, 16):
         for groups in (1, 2):
             try:
                 ctx.set_batch_plan(waves, groups, 0)

@@ -269,7 +269,7 @@ size_t hough_split_workspace_bytes(const hough_ctx *ctx, uint32_t n_events);
  * over waves_per_group waves of a workgroup; groups_per_cu workgroups run on each compute unit.
  * The schedule changes speed only, never results. */
 typedef struct hough_batch_plan {
-    int32_t waves_per_group;   /* 4, 6, 8 or 16                                        */
+    int32_t waves_per_group;   /* 4, 6, 8, 12 or 16                                    */
     int32_t column_groups;     /* 1 or 2                                               */
     int32_t groups_per_cu;     /* workgroups launched per CU (<= what fits)            */
     int32_t lds_bytes;         /* LDS per workgroup (read-only)                        */

@@ -15,7 +15,7 @@ import os
 
 import torch
 
-CANDIDATES = [(w, g, n) for w in (4, 6, 8, 16) for g in (1, 2) for n in (0, 1, 2, 3)]
+CANDIDATES = [(w, g, n) for w in (4, 6, 8, 12, 16) for g in (1, 2) for n in (0, 1, 2, 3)]
 DEFAULT_CACHE = os.environ.get("HOUGH_TUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "hough_batch_plans.json"))
 

@@ -1795,7 +1795,7 @@ size_t batch_lds_bytes(int n_rho, int waves, int groups) {
 }
 
 int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out) {
-    if (!(waves == 4 || waves == 6 || waves == 8 || waves == 16) || !(groups == 1 || groups == 2)) return -1;
+    if (!(waves == 4 || waves == 6 || waves == 8 || waves == 12 || waves == 16) || !(groups == 1 || groups == 2)) return -1;
     BatchPlan p{};
     p.waves = waves;
     p.groups = groups;
@@ -1977,6 +1977,8 @@ hipError_t launch_batch(const GridArgs &g, const BatchPlan &p, const BatchArgs &
         case 62: return launch_batch_t<6, 2>(g, p, a, s);
         case 81: return launch_batch_t<8, 1>(g, p, a, s);
         case 82: return launch_batch_t<8, 2>(g, p, a, s);
+        case 121: return launch_batch_t<12, 1>(g, p, a, s);
+        case 122: return launch_batch_t<12, 2>(g, p, a, s);
         case 161: return launch_batch_t<16, 1>(g, p, a, s);
         case 162: return launch_batch_t<16, 2>(g, p, a, s);
         default: return hipErrorInvalidValue;
@@ -2005,6 +2007,8 @@ hipError_t launch_batch_split(const GridArgs &g, const BatchPlan &p, const Batch
         case 62: return launch_split_t<6, 2>(g, p, a, sp, s);
         case 81: return launch_split_t<8, 1>(g, p, a, sp, s);
         case 82: return launch_split_t<8, 2>(g, p, a, sp, s);
+        case 121: return launch_split_t<12, 1>(g, p, a, sp, s);
+        case 122: return launch_split_t<12, 2>(g, p, a, sp, s);
         case 161: return launch_split_t<16, 1>(g, p, a, sp, s);
         case 162: return launch_split_t<16, 2>(g, p, a, sp, s);
         default: return hipErrorInvalidValue;
@@ -2084,6 +2088,8 @@ int prepare_batch(const BatchPlan &p, size_t lds_limit) {
         case 62: return prepare_t<6, 2>(p.lds_bytes, lds_limit);
         case 81: return prepare_t<8, 1>(p.lds_bytes, lds_limit);
         case 82: return prepare_t<8, 2>(p.lds_bytes, lds_limit);
+        case 121: return prepare_t<12, 1>(p.lds_bytes, lds_limit);
+        case 122: return prepare_t<12, 2>(p.lds_bytes, lds_limit);
         case 161: return prepare_t<16, 1>(p.lds_bytes, lds_limit);
         case 162: return prepare_t<16, 2>(p.lds_bytes, lds_limit);
         default: return 0;

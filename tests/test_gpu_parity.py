@@ -355,8 +355,8 @@ def test_every_launch_plan_gives_identical_results(H):
         xt, yt, ot = H.to_device(ev)
         ref = [t.clone() for t in ctx.run_batch(xt, yt, ot)]
         tried = 0
-        for w, gr, gpc in [(4, 1, 0), (4, 2, 0), (6, 1, 0), (6, 2, 0), (8, 1, 0), (8, 2, 0), (16, 1, 0),
-                           (16, 2, 0), (8, 1, 1), (6, 1, 3)]:
+        for w, gr, gpc in [(4, 1, 0), (4, 2, 0), (6, 1, 0), (6, 2, 0), (8, 1, 0), (8, 2, 0), (12, 1, 0),
+                           (12, 2, 0), (16, 1, 0), (16, 2, 0), (8, 1, 1), (6, 1, 3)]:
             try:
                 ctx.set_batch_plan(w, gr, gpc)
             except H.HoughError:
