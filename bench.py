@@ -349,6 +349,32 @@ def relative_threshold(H, ctx, xt, yt, ot, peaks, npk, keep, status, ev, stream,
             "R_s": round(float(k[lab >= 0].mean()), 4) if (lab >= 0).any() else None}
 
 
+def periodic_grid(H, wl, ev, xt, yt, ot, stream, reps: int = 10):
+    """The fused path on the same grid with the theta-periodic 3x3 test (HOUGH_FLAG_THETA_PERIODIC):
+    kernel time (HIP events, median), peaks and mask."""
+    import torch
+    ctx = H.Context.for_workload(wl, max_peaks=MAX_PEAKS[wl.name], periodic=True)
+    outs = ctx.run_batch(xt, yt, ot, stream=stream)
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ctx.run_batch(xt, yt, ot, *outs, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    npk, k = outs[1], outs[2].cpu().numpy()
+    lab = ev.labels
+    out = {"kernel_ms": round(ms, 4), "events_per_s": round(ev.n_events / (ms / 1e3), 1),
+           "peaks_per_event": round(float(npk.float().mean().item()), 2),
+           "R_c": round(float(k.mean()), 4) if k.size else None,
+           "R_s": round(float(k[lab >= 0].mean()), 4) if (lab >= 0).any() else None,
+           "plan": ctx.batch_plan}
+    ctx.close()
+    return out
+
+
 def end_to_end(H, ctx, wl, ev, reps: int = 10):
     """PCIe-inclusive rate of the batch path: hits and offsets from pinned host memory to HBM,
     one fused launch, then n_peaks, status and keep (and, in the second figure, the whole
@@ -563,7 +589,8 @@ def main(argv=None):
     ap.add_argument("--dedup", action="store_true",
                     help="suppress duplicate hits (HOUGH_FLAG_DEDUP: one more launch per step)")
     ap.add_argument("--no-relative", action="store_true",
-                    help="skip the relative-threshold measurement (its launches share the fused kernel's name)")
+                    help="skip the relative-threshold and periodic-grid measurements (their launches share "
+                         "the fused kernel's name)")
     ap.add_argument("--sweeps", action="store_true",
                     help="add the runtime-vs-events and stage-times-vs-workgroup-size studies")
     ap.add_argument("--copy-reference-mb", type=int, default=0,
@@ -665,6 +692,7 @@ def main(argv=None):
     }
     if not args.no_relative:
         out["relative_threshold"] = relative_threshold(H, ctx, xt, yt, ot, peaks, npk, keep, status, ev, stream)
+        out["periodic_grid"] = periodic_grid(H, wl, ev, xt, yt, ot, stream)
     if tuned is not None:
         out["autotune_ms"] = tuned["ms"]
     if args.sweeps:
