@@ -1699,6 +1699,14 @@ __device__ __forceinline__ uint32_t dedup_hash(uint32_t kx, uint32_t ky) {
     return h ^ (h >> 16);
 }
 
+// Slot word: the index of the first copy seen so far (low kDedupIdxBits) under 18 bits of the
+// key's hash, so that a probe that meets another key's slot is settled in LDS; only equal
+// fingerprints read the two hits back to compare the keys.  Among entries of one key the high
+// bits are equal, so an atomic minimum over the word is one over the index.
+constexpr uint32_t kDedupIdxBits = 14;
+constexpr uint32_t kDedupIdxMask = (1u << kDedupIdxBits) - 1u;
+static_assert(kDedupMaxHits <= kDedupIdxMask, "hit indices must fit below the fingerprint");
+
 __global__ __launch_bounds__(kDedupThreads) void k_dedup(BatchArgs a) {
     __shared__ uint32_t tab[kDedupSlots];
     const uint32_t e = blockIdx.x;
@@ -1721,25 +1729,35 @@ __global__ __launch_bounds__(kDedupThreads) void k_dedup(BatchArgs a) {
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < H; i += kDedupThreads) {
         const uint32_t kx = xb[i], ky = yb[i];
-        uint32_t q = dedup_hash(kx, ky) & mask;
+        const uint32_t hsh = dedup_hash(kx, ky);
+        const uint32_t fp = hsh >> kDedupIdxBits, word = (fp << kDedupIdxBits) | i;
+        uint32_t q = hsh & mask;
         for (uint32_t probe = 0; probe < slots; ++probe, q = (q + 1) & mask) {
-            const uint32_t cur = atomicCAS(&tab[q], kEmptySlot, i);
+            const uint32_t cur = atomicCAS(&tab[q], kEmptySlot, word);
             if (cur == kEmptySlot) break;                  // first of its key so far
-            if (cur < H && xb[cur] == kx && yb[cur] == ky) {
-                atomicMin(&tab[q], i);
-                break;
+            if ((cur >> kDedupIdxBits) == fp) {
+                const uint32_t j = cur & kDedupIdxMask;
+                if (xb[j] == kx && yb[j] == ky) {
+                    atomicMin(&tab[q], word);
+                    break;
+                }
             }
         }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < H; i += kDedupThreads) {
         const uint32_t kx = xb[i], ky = yb[i];
-        uint32_t q = dedup_hash(kx, ky) & mask, first = i;
+        const uint32_t hsh = dedup_hash(kx, ky);
+        const uint32_t fp = hsh >> kDedupIdxBits;
+        uint32_t q = hsh & mask, first = i;
         for (uint32_t probe = 0; probe < slots; ++probe, q = (q + 1) & mask) {
             const uint32_t cur = tab[q];
-            if (cur >= H) break;                           // cannot happen (see above)
-            if (xb[cur] == kx && yb[cur] == ky) {
-                first = cur;
+            if (cur == kEmptySlot) break;                  // cannot happen: every key was inserted
+            if ((cur >> kDedupIdxBits) != fp) continue;
+            const uint32_t j = cur & kDedupIdxMask;
+            if (j == i) break;                             // its own slot: the first copy
+            if (xb[j] == kx && yb[j] == ky) {
+                first = j;
                 break;
             }
         }
