@@ -1,12 +1,16 @@
 """Benchmark of the conformal Hough hot path on one MI355X.
 
 A step is one pass of the whole path (conformal map, theta sweep and vote, 3x3 peaks, retention
-mask) over one batch of synthetic drift-chamber events already resident in HBM, done by one
-launch of the fused batch kernel (hough_run_batch).  Prints one JSON line.
+mask) over one batch of synthetic drift-chamber events already resident in HBM: one
+hough_run_batch (the largest-first schedule pass and the persistent fused kernel), captured once
+in a HIP graph and replayed, with the launch shape picked by the autotuner before timing.
+Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline] [--no-plain]
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-graph] [--no-tune]
+                  [--plan W,G,C] [--no-cpu-baseline] [--no-plain] [--no-serve] ...
 
-The default workload is 1,000 events on a 360 x 256 grid (threshold 10, +-1 rho bin window).
+The default workload is the batching configuration: 10,000 events of uneven size (1-12 tracks,
+noise occupancy U(2%, 25%)) on a 360 x 256 grid, threshold 10, +-1 rho bin window.
 """
 from __future__ import annotations
 
@@ -26,7 +30,7 @@ if ROOT not in sys.path:
 from paper_2607_04067_amd import synth  # noqa: E402
 
 METRIC = "events/s + Gvotes/s on 1 MI355X; p50/p99 event latency, served vs plain"
-DEFAULT_WORKLOAD = "paper-1000ev-360x256"
+DEFAULT_WORKLOAD = "batch-10000ev-360x256"
 # Per-event capacity of the peak list; every event of these workloads fits (no truncation).
 MAX_PEAKS = {"plain-16ev-180x128": 1024, "paper-1000ev-360x256": 8192,
              "batch-10000ev-360x256": 8192, "dense-2000ev-720x512": 16384,
@@ -38,10 +42,8 @@ VALU_LANE_OPS_PER_S = N_CU * LANES_PER_CU_CLK * CLOCK_HZ          # 39.3 T 32-bi
 OPS_PER_VOTE = 4      # 2 FMA (rho), 1 float->int (bin), 1 index (cell address); the +1 is on the LDS
 VOTE_PEAK_PER_S = VALU_LANE_OPS_PER_S / OPS_PER_VOTE              # 9.83 T votes/s
 HBM_PEAK_GBS = 8000.0
-# LDS atomic ceiling: an isolated ds_add_u32 loop (distinct banks, no return) sustains about 12.9
-# lanes per clock per CU on MI355X, 256 CUs x 2.4 GHz x 12.9 = 7.9 T lane-updates/s
-LDS_ATOMIC_LANES_PER_CU_CLK = 12.9
-LDS_ATOMIC_CEILING_PER_S = N_CU * CLOCK_HZ * LDS_ATOMIC_LANES_PER_CU_CLK
+FP32_PEAK_TFLOPS = 157.3   # MI355X published vector fp32 peak
+FLOPS_PER_VOTE = 4         # the two fmas of the bin, 2 flops each
 
 
 def log(*a):
@@ -88,7 +90,44 @@ def profiled_traffic(workload: str, plan):
     return rec
 
 
-def lds_atomic_rate(ev, plan, wl, kern_ms: float) -> dict:
+def lds_atomic_ceiling(reps: int = 3) -> dict:
+    """The LDS atomic rate of the vote's access pattern over the whole chip, measured here and now
+    with libhough_probe.so (ds_add_u32, lane l on dword 32 * row + (l & 31), 16-bit halves, rows
+    changing every instruction, nothing else in the loop): lane-updates per second, the best of
+    a few occupancies, each the median of `reps` launches timed with HIP events."""
+    import ctypes
+    import torch
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_2607_04067_amd", "libhough_probe.so"))
+    L.hough_probe_lds_add.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.hough_probe_lds_add.restype = ctypes.c_int
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    stream = torch.cuda.current_stream()
+    rows = []
+    for waves, per_cu in ((8, 3), (8, 4), (16, 2), (4, 8)):
+        blocks, iters = n_cu * per_cu, 4096
+        sink = torch.zeros(blocks, dtype=torch.int32, device="cuda")
+        if L.hough_probe_lds_add(blocks, waves, iters, sink.data_ptr(), stream.cuda_stream) != 0:
+            raise RuntimeError("hough_probe_lds_add failed")
+        times = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            L.hough_probe_lds_add(blocks, waves, iters, sink.data_ptr(), stream.cuda_stream)
+            b.record(stream)
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = float(np.median(times))
+        lanes = blocks * waves * 64 * iters * 8
+        rows.append({"waves_per_group": waves, "groups_per_cu": per_cu, "ms": round(ms, 4),
+                     "lane_updates_per_s": lanes / (ms / 1e3)})
+    best = max(rows, key=lambda r: r["lane_updates_per_s"])
+    return {"lane_updates_per_s": best["lane_updates_per_s"],
+            "lanes_per_clk_per_cu": round(best["lane_updates_per_s"] / (n_cu * CLOCK_HZ), 2),
+            "probe": "libhough_probe.so ds_add_u32 loop, best of " + ", ".join(
+                f"{r['waves_per_group']}x{r['groups_per_cu']}: {r['lane_updates_per_s'] / 1e12:.2f} T/s" for r in rows)}
+
+
+def lds_atomic_rate(ev, plan, wl, kern_ms: float, ceiling_per_s: float) -> dict:
     """LDS vote atomics the fused kernel issues per launch (each valid hit updates every lane's
     column of every theta tile, halo and out-of-grid lanes included: 64 * column_groups lanes per
     tile) per second of kernel time, against the measured LDS atomic ceiling."""
@@ -100,8 +139,8 @@ def lds_atomic_rate(ev, plan, wl, kern_ms: float) -> dict:
     lanes = valid * tiles * lanes_per_tile
     rate = lanes / (kern_ms / 1e3)
     return {"lane_updates_per_launch": lanes, "achieved_per_s": round(rate / 1e12, 3), "unit": "T/s",
-            "ceiling_per_s": round(LDS_ATOMIC_CEILING_PER_S / 1e12, 3),
-            "frac": round(rate / LDS_ATOMIC_CEILING_PER_S, 4)}
+            "ceiling_per_s": round(ceiling_per_s / 1e12, 3),
+            "frac": round(rate / ceiling_per_s, 4)}
 
 
 def cpu_model() -> str:
@@ -115,41 +154,40 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(wl, ev, budget_s: float = 20.0, max_runs: int = 10):
-    """The CPU oracle, as it stands, on the host cores over a bounded sample: the median of up to
-    max_runs runs (OpenMP over events on up to 16 threads) and one run on one core."""
+def cpu_baseline(wl, ev, budget_s: float = 20.0, runs: int = 10):
+    """The CPU oracle, as it stands, on the host cores: a bounded sample of the workload (the
+    first n events, n sized so that the `runs` timed runs cost about budget_s of CPU time in
+    all), run `runs` times with OpenMP over events on up to 16 threads (the machine's CPU share for
+    one GPU) and reported as the median, then once on one core."""
     from oracle import oracle
     avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     threads = max(1, min(16, avail))
     cap = MAX_PEAKS[wl.name]
-    # size the sample from a one-thread probe so that one run costs about budget_s / 2 of CPU time
-    probe = ev.subset(np.arange(min(8, ev.n_events)))
+    # one-thread probe of the per-event cost
+    probe = ev.subset(np.arange(min(16, ev.n_events)))
     t0 = time.perf_counter()
     oracle.run_batch(wl, probe.x, probe.y, probe.offsets, cap=cap, n_threads=1)
     per_event = (time.perf_counter() - t0) / probe.n_events
-    n = int(min(ev.n_events, max(threads, 0.5 * budget_s / max(per_event, 1e-6))))
+    n = int(min(ev.n_events, max(threads, budget_s / runs / max(per_event, 1e-6))))
     sample = ev.subset(np.arange(n))
-    times, spent = [], 0.0
-    while len(times) < max_runs and (not times or spent + times[0] * threads <= budget_s):
+    oracle.run_batch(wl, sample.x, sample.y, sample.offsets, cap=cap, n_threads=threads)   # warm-up
+    times = []
+    for _ in range(runs):
         t0 = time.perf_counter()
         oracle.run_batch(wl, sample.x, sample.y, sample.offsets, cap=cap, n_threads=threads)
         times.append(time.perf_counter() - t0)
-        spent += times[-1] * threads
     dt = float(np.median(times))
     votes = sample.n_hits * wl.n_theta
-    # the same oracle on one core, over a smaller sample (about a tenth of the budget)
-    n1 = int(min(n, max(1, 0.1 * budget_s / max(per_event, 1e-6))))
-    one = ev.subset(np.arange(n1))
     t0 = time.perf_counter()
-    oracle.run_batch(wl, one.x, one.y, one.offsets, cap=cap, n_threads=1)
+    oracle.run_batch(wl, sample.x, sample.y, sample.offsets, cap=cap, n_threads=1)
     dt1 = time.perf_counter() - t0
     return {"value": round(n / dt, 2), "unit": "events/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} of {ev.n_events} events of {wl.name} (whole path, all peaks), "
-                      f"median of {len(times)} runs",
+                      f"median of {runs} runs after one warm-up",
             "cpu": cpu_model(), "host_cpus": avail,
             "gvotes_per_s": round(votes / dt / 1e9, 4), "seconds": round(dt, 4),
-            "one_core": {"events_per_s": round(n1 / dt1, 2), "sample_events": n1,
-                         "seconds": round(dt1, 3)}}
+            "one_core": {"events_per_s": round(n / dt1, 2), "sample_events": n, "seconds": round(dt1, 3),
+                         "gvotes_per_s": round(votes / dt1 / 1e9, 4)}}
 
 
 def plain_path(H, wl, ev, n_events: int = 200):
@@ -580,8 +618,13 @@ def main(argv=None):
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(synth.WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--tune", action="store_true", help="autotune the fused kernel's launch shape first")
-    ap.add_argument("--graph", action="store_true", help="capture one step in a HIP graph and replay it")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's default launch shape instead of autotuning it before timing")
+    ap.add_argument("--plan", default=None,
+                    help="W,G,C: run this launch shape (waves per workgroup, column groups, workgroups per CU) "
+                         "instead of tuning")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch each step eagerly instead of replaying it from a HIP graph")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-e2e", action="store_true", help="skip the PCIe-inclusive measurement")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -617,14 +660,17 @@ def main(argv=None):
     status = torch.zeros(E, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
     tuned = None
-    if args.tune:
+    if args.plan:
+        ctx.set_batch_plan(*(int(v) for v in args.plan.split(",")))
+    elif not args.no_tune:
         from paper_2607_04067_amd import autotune
         log("autotuning the launch shape")
         tuned = autotune.tune(ctx, xt, yt, ot, (peaks, npk, keep, status),
                               mean_hits=ev.n_hits / max(E, 1), cache=None)
+        log(f"tuned plan {ctx.batch_plan}")
 
     step = lambda: ctx.run_batch(xt, yt, ot, peaks, npk, keep, status, stream)
-    if args.graph:
+    if not args.no_graph:
         graph = torch.cuda.CUDAGraph()
         step()
         torch.cuda.synchronize()
@@ -660,6 +706,13 @@ def main(argv=None):
     # algorithmic HBM bytes per launch: x, y and offsets in; keep, peak records, n_peaks, status out
     algo_bytes = 8 * ev.n_hits + 4 * (E + 1) + ev.n_hits + 8 * stored + 8 * E
     prof = None if args.dedup else profiled_traffic(wl.name, ctx.batch_plan)   # counters: plain launch only
+    ceiling = lds_atomic_ceiling()
+    lds_peak = ceiling["lane_updates_per_s"] / 1e9            # Gvote/s: one LDS lane-update per vote at least
+    fp32 = achieved * 1e9 * FLOPS_PER_VOTE / 1e12
+    plan = ctx.batch_plan
+    path = ("hough_run_batch: " + ("duplicate pass, " if args.dedup else "")
+            + ("largest-first schedule pass + " if E > plan["groups_per_cu"] * N_CU else "")
+            + "persistent fused kernel" + ("" if args.no_graph else ", captured once in a HIP graph and replayed"))
     out = {
         "metric": METRIC, "value": round(events_per_s, 1), "unit": "events/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -667,22 +720,29 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": wl.name, "events": E, "hits": ev.n_hits, "n_theta": wl.n_theta,
                    "n_rho": wl.n_rho, "threshold": wl.threshold, "rho_window": wl.rho_window,
-                   "max_peaks": MAX_PEAKS[wl.name],
-                   "path": ("hough_run_batch (" + ("duplicate pass + fused launch" if args.dedup else "one fused launch")
-                            + ")" + (" in a HIP graph" if args.graph else "")),
-                   "plan": ctx.batch_plan},
+                   "max_peaks": MAX_PEAKS[wl.name], "path": path, "plan": plan,
+                   "plan_source": "fixed by --plan" if args.plan else ("library default" if args.no_tune
+                                                                       else "autotuned before timing")},
         "gvotes_per_s": round(votes / (ms_per_step / 1e3) / 1e9, 2),
         "kernel_ms": round(kern_ms, 4),
         "kernel_ms_median": round(float(np.median(kern_times)), 4),
-        "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": round(VOTE_PEAK_PER_S / 1e9, 1),
-                     "unit": "Gvote/s", "frac": round(achieved / (VOTE_PEAK_PER_S / 1e9), 4),
+        "kernel_ms_span": "HIP events on the launch stream around each step (schedule pass + fused kernel)",
+        "roofline": {"bound": "lds_atomic", "achieved": round(achieved, 1), "peak": round(lds_peak, 1),
+                     "unit": "Gvote/s", "frac": round(achieved / lds_peak, 4),
                      "traffic": prof["traffic_bytes"] if prof else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": "k_batch",
+                     "peak_source": ceiling["probe"],
+                     "lds_lanes_per_clk_per_cu": ceiling["lanes_per_clk_per_cu"],
+                     "fp32": {"achieved_tflops": round(fp32, 2), "peak_tflops": FP32_PEAK_TFLOPS,
+                              "frac": round(fp32 / FP32_PEAK_TFLOPS, 4),
+                              "flops_per_vote": FLOPS_PER_VOTE},
+                     "valu_issue": {"peak_gvote_s": round(VOTE_PEAK_PER_S / 1e9, 1), "ops_per_vote": OPS_PER_VOTE,
+                                    "frac": round(achieved / (VOTE_PEAK_PER_S / 1e9), 4)},
                      "algorithmic_bytes": algo_bytes,
                      "hbm_algorithmic_gbs": round(algo_bytes / (kern_ms / 1e3) / 1e9, 2),
                      "hbm_frac": round(algo_bytes / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "lds_atomic": lds_atomic_rate(ev, ctx.batch_plan, wl, kern_ms)},
+                     "lds_atomic": lds_atomic_rate(ev, plan, wl, kern_ms, ceiling["lane_updates_per_s"])},
         "retention": {"R_c": round(float(keep_np.mean()), 4) if keep_np.size else None,
                       "R_s": round(float(keep_np[labels >= 0].mean()), 4) if (labels >= 0).any() else None,
                       "peaks_per_event": round(float(npk.float().mean().item()), 1),
@@ -695,6 +755,7 @@ def main(argv=None):
         out["periodic_grid"] = periodic_grid(H, wl, ev, xt, yt, ot, stream)
     if tuned is not None:
         out["autotune_ms"] = tuned["ms"]
+        out["autotune_pick"] = tuned["plan"]
     if args.sweeps:
         out["sweeps"] = sweeps(H, wl, ev)
     if args.copy_reference_mb:

@@ -68,9 +68,7 @@ extern "C" {
 #define HOUGH_EV_INVALID_HITS    2u  /* the event contains invalid hits (they were ignored)     */
 #define HOUGH_EV_TOO_MANY_HITS   4u  /* more hits than hough_max_batch_hits(): event skipped,
                                         its n_peaks and keep are written as zero               */
-#define HOUGH_EV_TOO_MANY_CANDIDATES 8u  /* hough_peaks_iterative: more cells reach the
-                                        threshold than hough_max_iterative_candidates(); no
-                                        peak was listed and n_peaks is zero                    */
+/* 8u: unused */
 #define HOUGH_EV_DEDUP_SKIPPED   16u /* HOUGH_FLAG_DEDUP: the event has more hits than
                                         hough_max_dedup_hits(), so every hit voted            */
 
@@ -148,10 +146,11 @@ int hough_peaks(hough_ctx *ctx, const void *acc, hough_peak *peaks, uint32_t cap
  * then iterative extraction: the largest remaining cell at or above thr (the first in raster
  * order among equal counts) becomes a peak and every cell within r_theta theta bins and r_rho
  * rho bins of it (clipped at the grid edges, theta does not wrap) is suppressed; repeat until
- * no cell reaches thr.  acc as written by hough_vote.  The first min(count, cap) peaks, in
- * extraction order, go to peaks; *n_peaks (device) receives the count; *status (device)
- * receives 0, or HOUGH_EV_TOO_MANY_CANDIDATES when more than hough_max_iterative_candidates()
- * cells reach thr (then *n_peaks is 0).  HOUGH_EINVAL for frac_den == 0 or a negative radius. */
+ * no cell reaches thr.  Every cell at or above thr takes part, however many there are (the
+ * kernel walks them in chunks of its LDS key buffer).  acc as written by hough_vote.  The first
+ * min(count, cap) peaks, in extraction order, go to peaks; *n_peaks (device) receives the
+ * count; *status (device) receives 0, or HOUGH_EV_PEAKS_TRUNCATED when the count exceeds cap.
+ * HOUGH_EINVAL for frac_den == 0 or a negative radius. */
 int hough_peaks_iterative(hough_ctx *ctx, const void *acc, uint32_t frac_num, uint32_t frac_den,
                           int32_t r_theta, int32_t r_rho, hough_peak *peaks, uint32_t cap,
                           uint32_t *n_peaks, uint32_t *status, void *stream);
@@ -177,9 +176,6 @@ typedef struct hough_track {
 int hough_track_params(hough_ctx *ctx, const float *x, const float *y, uint32_t n_hits,
                        const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
                        double b_tesla, hough_track *tracks, void *stream);
-
-/* Largest number of cells at or above the threshold hough_peaks_iterative handles. */
-uint32_t hough_max_iterative_candidates(void);
 
 /* Step 5 for one event (Sec. I, Sec. II): keep[i] = 1 iff hit i is within rho_window rho bins
  * of one of the peaks peaks[0 .. min(*n_peaks, cap)-1] (n_peaks is a device pointer, as
@@ -243,9 +239,9 @@ int hough_run_batch_split(hough_ctx *ctx, const float *x, const float *y, const 
  * hough_peaks_iterative's finder per event (same frac, r_theta, r_rho and threshold floor),
  * then retention (as hough_retain) with each event's first min(n_peaks, max_peaks) peaks.
  * peaks (device): max_peaks records per event, in extraction order; n_peaks[e] the true count;
- * keep[offsets[0] .. offsets[n_events]] one byte per hit; status[e] the HOUGH_EV_* bits
- * (HOUGH_EV_TOO_MANY_CANDIDATES: no peak listed, nothing kept).  Events above
- * hough_max_batch_hits() hits are skipped as in hough_run_batch; HOUGH_FLAG_DEDUP applies.
+ * keep[offsets[0] .. offsets[n_events]] one byte per hit; status[e] the HOUGH_EV_* bits.
+ * Events above hough_max_batch_hits() hits are skipped as in hough_run_batch;
+ * HOUGH_FLAG_DEDUP applies.
  * Four kernel launches per call.  Accumulators go through HBM (n_theta * n_rho * 2 bytes per
  * event), so this is the per-event path's work done for the whole batch at once, not the fused
  * kernel. */
@@ -254,7 +250,9 @@ int hough_run_batch_iterative(hough_ctx *ctx, const float *x, const float *y, co
                               int32_t r_rho, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
                               uint32_t *status, void *workspace, size_t workspace_bytes, void *stream);
 
-/* Workspace bytes hough_run_batch_iterative needs for n_events events (0 for a NULL context). */
+/* Workspace bytes hough_run_batch_iterative needs for n_events events: the 16-bit accumulators
+ * and, on grids whose suppression bitmap does not fit on chip beside the finder's key buffer,
+ * one bitmap (one bit per cell) per event (0 for a NULL context). */
 size_t hough_iterative_workspace_bytes(const hough_ctx *ctx, uint32_t n_events);
 
 /* Largest event (hits) whose duplicates HOUGH_FLAG_DEDUP suppresses. */

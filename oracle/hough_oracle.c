@@ -272,6 +272,61 @@ long oracle_peaks_iterative(const int32_t *acc, int n_theta, int n_rho, int t_ab
     return n;
 }
 
+/*
+ * The same extraction as oracle_peaks_iterative in its order form, for accumulators where the
+ * step-by-step rescan would take too long (many cells at or above the threshold and many
+ * peaks).  The cells at or above the threshold are sorted by count descending, then raster
+ * index ascending, and visited in that order: a cell that no earlier peak's window covers
+ * becomes a peak and covers its own window.  Step by step, the extraction takes among the cells
+ * still available the first one in this order; a cell visited here while covered was covered
+ * by a peak taken before it, and a cell never becomes available again, so the two forms take
+ * the same cells in the same order.  Arguments and result as for oracle_peaks_iterative.
+ */
+static int oracle_key_desc(const void *a, const void *b)
+{
+    const uint64_t ka = *(const uint64_t *)a, kb = *(const uint64_t *)b;
+    return ka < kb ? 1 : (ka > kb ? -1 : 0);
+}
+
+long oracle_peaks_iterative_sorted(const int32_t *acc, int n_theta, int n_rho, int t_abs,
+                                   int frac_num, int frac_den, int r_theta, int r_rho,
+                                   int32_t *pj, int32_t *pk, int32_t *pc, long cap)
+{
+    const size_t cells = (size_t)n_theta * (size_t)n_rho;
+    int32_t max_count = 0;
+    for (size_t c = 0; c < cells; ++c)
+        if (acc[c] > max_count) max_count = acc[c];
+    const int64_t rel = ((int64_t)max_count * frac_num + frac_den - 1) / frac_den;
+    const int64_t thr = rel > t_abs ? rel : t_abs;
+    size_t n_cand = 0;
+    for (size_t c = 0; c < cells; ++c)
+        if (acc[c] >= thr) ++n_cand;
+    /* key: count in the high half, the raster index counted down in the low half */
+    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (n_cand ? n_cand : 1));
+    uint8_t *gone = (uint8_t *)calloc(cells ? cells : 1, 1);
+    if (!keys || !gone) { free(keys); free(gone); return -1; }
+    size_t m = 0;
+    for (size_t c = 0; c < cells; ++c)
+        if (acc[c] >= thr) keys[m++] = ((uint64_t)(uint32_t)acc[c] << 32) | (uint64_t)(0xffffffffu - (uint32_t)c);
+    qsort(keys, n_cand, sizeof(uint64_t), oracle_key_desc);
+    long n = 0;
+    for (size_t i = 0; i < n_cand; ++i) {
+        const size_t c = 0xffffffffu - (uint32_t)keys[i];
+        if (gone[c]) continue;
+        const int j = (int)(c / n_rho), k = (int)(c % n_rho);
+        if (n < cap) { pj[n] = j; pk[n] = k; pc[n] = acc[c]; }
+        ++n;
+        for (int jj = j - r_theta; jj <= j + r_theta; ++jj) {
+            if (jj < 0 || jj >= n_theta) continue;
+            for (int kk = k - r_rho; kk <= k + r_rho; ++kk)
+                if (kk >= 0 && kk < n_rho) gone[(size_t)jj * n_rho + kk] = 1;
+        }
+    }
+    free(keys);
+    free(gone);
+    return n;
+}
+
 /* Retention mask: keep_i = 1 iff hit i is within rho_window bins of a peak at the peak's theta. */
 void oracle_retain(int n_rho, const float *C, const float *S, float Bf, int rho_window,
                    const float *x, const float *y, long n_hits,
@@ -395,6 +450,66 @@ int oracle_run_batch(int n_theta, int n_rho, double rho_min, double rho_max, int
             oracle_retain(n_rho, C, S, Bf, rho_window, x + a, y + a, h, pj, pk, np, keep + a);
             n_peaks_out[e] = np;
             for (long p = 0; p < np && p < cap; ++p) {
+                peaks_out[(e * cap + p) * 3 + 0] = pj[p];
+                peaks_out[(e * cap + p) * 3 + 1] = pk[p];
+                peaks_out[(e * cap + p) * 3 + 2] = pc[p];
+            }
+        }
+        free(acc); free(pj); free(pk); free(pc);
+    }
+    free(C); free(S);
+    return failed ? -1 : 0;
+}
+
+/*
+ * The paper's finder over CSR-packed events, one event at a time: vote (only first copies of
+ * duplicate hits with dedup != 0), the iterative extraction in its order form
+ * (oracle_peaks_iterative_sorted), then retention against the event's first min(n, cap) peaks
+ * (the peaks a caller receives).  Events are independent, so they are spread over n_threads
+ * OpenMP threads.  peaks_out holds cap triples (j, k, count) per event in extraction order;
+ * n_peaks_out the true counts.  Returns 0, or -1 on allocation failure.
+ */
+int oracle_run_batch_iterative(int n_theta, int n_rho, double rho_min, double rho_max, int t_abs,
+                               int frac_num, int frac_den, int r_theta, int r_rho, int rho_window,
+                               const float *x, const float *y, const uint32_t *offsets, long n_events,
+                               long cap, int32_t *peaks_out, int64_t *n_peaks_out, uint8_t *keep,
+                               int n_threads, int dedup)
+{
+    float *C = (float *)malloc(sizeof(float) * (size_t)n_theta);
+    float *S = (float *)malloc(sizeof(float) * (size_t)n_theta);
+    float Bf;
+    int failed = 0;
+    if (!C || !S || oracle_tables(n_theta, n_rho, rho_min, rho_max, C, S, &Bf) != 0) {
+        free(C); free(S); return -1;
+    }
+    if (n_threads < 1) n_threads = 1;
+    const long room = cap > 0 ? cap : 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads)
+    for (long e = 0; e < n_events; ++e) {
+        long a = offsets[e], h = (long)offsets[e + 1] - (long)offsets[e];
+        int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n_theta * (size_t)n_rho);
+        int32_t *pj = (int32_t *)malloc(sizeof(int32_t) * (size_t)room);
+        int32_t *pk = (int32_t *)malloc(sizeof(int32_t) * (size_t)room);
+        int32_t *pc = (int32_t *)malloc(sizeof(int32_t) * (size_t)room);
+        if (!acc || !pj || !pk || !pc) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+            if (dedup)
+                oracle_vote_dedup(n_theta, n_rho, C, S, Bf, x + a, y + a, h, acc);
+            else
+                oracle_vote(n_theta, n_rho, C, S, Bf, x + a, y + a, h, acc);
+            long np = oracle_peaks_iterative_sorted(acc, n_theta, n_rho, t_abs, frac_num, frac_den, r_theta,
+                                                    r_rho, pj, pk, pc, cap);
+            if (np < 0) {
+#pragma omp atomic write
+                failed = 1;
+                np = 0;
+            }
+            const long listed = np < cap ? np : cap;
+            oracle_retain(n_rho, C, S, Bf, rho_window, x + a, y + a, h, pj, pk, listed, keep + a);
+            n_peaks_out[e] = np;
+            for (long p = 0; p < listed; ++p) {
                 peaks_out[(e * cap + p) * 3 + 0] = pj[p];
                 peaks_out[(e * cap + p) * 3 + 1] = pk[p];
                 peaks_out[(e * cap + p) * 3 + 2] = pc[p];

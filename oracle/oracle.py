@@ -74,6 +74,12 @@ def lib():
         L.oracle_peaks_iterative.argtypes = [_i32p, c_int, c_int, c_int, c_int, c_int, c_int, c_int,
                                              _i32p, _i32p, _i32p, c_long]
         L.oracle_peaks_iterative.restype = c_long
+        L.oracle_peaks_iterative_sorted.argtypes = L.oracle_peaks_iterative.argtypes
+        L.oracle_peaks_iterative_sorted.restype = c_long
+        L.oracle_run_batch_iterative.argtypes = [c_int, c_int, c_double, c_double, c_int, c_int, c_int, c_int,
+                                                 c_int, c_int, _f32p, _f32p, _u32p, c_long, c_long, _i32p, _i64p,
+                                                 _u8p, c_int, c_int]
+        L.oracle_run_batch_iterative.restype = c_int
         _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
         L.oracle_track_params.argtypes = [c_int, c_int, c_double, c_double, _f32p, _f32p, c_float, c_int,
                                           c_double, _f32p, _f32p, c_long, _i32p, _i32p, c_long, _f64p]
@@ -175,17 +181,18 @@ def peaks(acc: np.ndarray, threshold: int, cap: int | None = None, periodic: boo
 
 
 def peaks_iterative(acc: np.ndarray, t_abs: int, frac: tuple[int, int], r_theta: int, r_rho: int,
-                    cap: int | None = None):
+                    cap: int | None = None, sorted_form: bool = False):
     """The paper's peak finder (Sec. II): threshold max(t_abs, ceil(max * frac)), then the
     largest remaining cell (raster-first among equals) is taken and its (2 r_theta + 1) x
     (2 r_rho + 1) neighbourhood suppressed, repeatedly.  (j, k, count) in extraction order and
-    the true count."""
+    the true count.  sorted_form: the same extraction computed by one walk over the sorted
+    candidates (oracle_peaks_iterative_sorted), for accumulators with many candidates and peaks."""
     acc = np.ascontiguousarray(acc, dtype=np.int32)
     nt, nr = acc.shape
     cap = nt * nr if cap is None else int(cap)
     pj = np.zeros(max(cap, 1), np.int32); pk = np.zeros_like(pj); pc = np.zeros_like(pj)
-    n = int(lib().oracle_peaks_iterative(acc, nt, nr, int(t_abs), int(frac[0]), int(frac[1]),
-                                         int(r_theta), int(r_rho), pj, pk, pc, cap))
+    f = lib().oracle_peaks_iterative_sorted if sorted_form else lib().oracle_peaks_iterative
+    n = int(f(acc, nt, nr, int(t_abs), int(frac[0]), int(frac[1]), int(r_theta), int(r_rho), pj, pk, pc, cap))
     if n < 0:
         raise MemoryError("oracle_peaks_iterative")
     m = min(n, cap)
@@ -272,6 +279,26 @@ def run_batch_iterative(g: Grid, x, y, offsets, t_abs: int, frac: tuple[int, int
         n[e] = m
         out[e, :k] = np.stack([pj[:k], pk[:k], pc[:k]], 1)
         keep[a:b] = retain(g, x[a:b], y[a:b], pj[:k], pk[:k], rho_window)
+    return out[:E], n[:E], keep[:x.size]
+
+
+def run_batch_iterative_fast(g: Grid, x, y, offsets, t_abs: int, frac: tuple[int, int], r_theta: int,
+                             r_rho: int, rho_window: int, cap: int, dedup: bool = False, n_threads: int = 1):
+    """run_batch_iterative computed in C over n_threads OpenMP threads, with the finder in its
+    order form; the same results (a CPU test compares the two)."""
+    x, y = _f32(x), _f32(y)
+    offsets = np.ascontiguousarray(offsets, np.uint32)
+    E = offsets.size - 1
+    out = np.zeros((max(E, 1), max(cap, 1), 3), np.int32)
+    n = np.zeros(max(E, 1), np.int64)
+    keep = np.zeros(max(x.size, 1), np.uint8)
+    rc = lib().oracle_run_batch_iterative(g.n_theta, g.n_rho, g.rho_min, g.rho_max, int(t_abs), int(frac[0]),
+                                          int(frac[1]), int(r_theta), int(r_rho), int(rho_window),
+                                          x if x.size else np.zeros(1, np.float32),
+                                          y if y.size else np.zeros(1, np.float32), offsets, E, int(cap), out, n,
+                                          keep, int(n_threads), int(bool(dedup)))
+    if rc != 0:
+        raise MemoryError("oracle_run_batch_iterative failed")
     return out[:E], n[:E], keep[:x.size]
 
 

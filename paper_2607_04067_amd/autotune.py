@@ -4,7 +4,9 @@ The schedule space is the theta-tile width (64 * column_groups columns) times th
 event's hits over the waves of a workgroup (waves_per_group) times the number of workgroups
 launched per CU (up to what fits; fewer can divide a small batch more evenly over the grid).
 Every candidate is timed on the caller's resident batch with HIP
-events and the fastest is kept.  Results are cached in a JSON file keyed by device, grid and a
+events; the three fastest are timed again with more launches, and the fastest of those is kept
+unless the context's own shape is within `keep_margin` of it (then the default stays, so that
+run-to-run noise does not flip the shape).  Results are cached in a JSON file keyed by device, grid and a
 hits-per-event bucket, so that a later context with the same key starts from the tuned shape.
 The schedule never changes results, only speed.
 """
@@ -48,7 +50,7 @@ def time_plan(ctx, args, reps: int = 5) -> float:
 
 
 def tune(ctx, x, y, offsets, outputs, mean_hits: float, cache: str | None = DEFAULT_CACHE,
-         reps: int = 5, force: bool = False) -> dict:
+         reps: int = 5, force: bool = False, keep_margin: float = 0.02) -> dict:
     """Pick the fastest launch shape for this context on the given resident batch.
 
     outputs = (peaks, n_peaks, keep, status) buffers as accepted by Context.run_batch.
@@ -60,6 +62,8 @@ def tune(ctx, x, y, offsets, outputs, mean_hits: float, cache: str | None = DEFA
         ctx.set_batch_plan(*table[key]["plan"])
         return table[key]
     args = (x, y, offsets, *outputs)
+    d = ctx.batch_plan
+    default = f"{d['waves_per_group']}x{d['column_groups']}x{d['groups_per_cu']}"
     results = {}
     for w, g, n in CANDIDATES:
         try:
@@ -69,10 +73,19 @@ def tune(ctx, x, y, offsets, outputs, mean_hits: float, cache: str | None = DEFA
         key_c = f"{w}x{g}x{n or ctx.batch_plan['groups_per_cu']}"
         if key_c not in results:
             results[key_c] = round(time_plan(ctx, args, reps), 5)
-    best = min(results, key=results.get)
+    finalists = sorted(results, key=results.get)[:3]
+    if default in results and default not in finalists:
+        finalists.append(default)
+    final = {}
+    for key_c in finalists:
+        ctx.set_batch_plan(*(int(v) for v in key_c.split("x")))
+        final[key_c] = round(time_plan(ctx, args, 4 * reps), 5)
+    best = min(final, key=final.get)
+    if default in final and final[default] <= final[best] * (1.0 + keep_margin):
+        best = default
     w, g, n = (int(v) for v in best.split("x"))
     ctx.set_batch_plan(w, g, n)
-    entry = {"plan": [w, g, n], "ms": results}
+    entry = {"plan": [w, g, n], "ms": results, "final_ms": final, "default": default}
     if cache:
         table[key] = entry
         os.makedirs(os.path.dirname(cache) or ".", exist_ok=True)

@@ -1,4 +1,7 @@
-"""Build libhough.so (HIP, gfx950) in-tree with hipcc.
+"""Build the package's HIP libraries (gfx950) in-tree with hipcc.
+
+libhough.so        the C ABI of include/hough.h and include/hough_serve.h (the product);
+libhough_probe.so  a measurement probe (the LDS atomic rate of the vote's access pattern).
 
 Flags that matter for exactness: -ffp-contract=off (only the explicit fmaf calls fuse),
 correctly rounded single-precision division, denormals kept (no flush-to-zero) and no
@@ -14,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhough.so")
 SOURCES = ["hough_kernels.hip", "hough_api.cpp", "hough_serve.cpp"]
+PROBE_LIB = os.path.join(HERE, "libhough_probe.so")
+PROBE_SOURCES = ["hough_probe.hip"]
 ARCH = os.environ.get("HOUGH_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -32,10 +37,9 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(out: str = LIB, verbose: bool = False) -> str:
-    """Compile every HIP source into `out` (always recompiles)."""
+def _compile(sources, out: str, extra=(), verbose: bool = False) -> str:
     tmp = out + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+    cmd = [hipcc(), *HIPCC_FLAGS, *extra, *[os.path.join(CSRC, s) for s in sources], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -43,5 +47,19 @@ def build(out: str = LIB, verbose: bool = False) -> str:
     return out
 
 
+def build(out: str = LIB, verbose: bool = False) -> str:
+    """Compile the product library into `out` (always recompiles)."""
+    return _compile(SOURCES, out, verbose=verbose)
+
+
+def build_probe(out: str = PROBE_LIB, verbose: bool = False) -> str:
+    """Compile the measurement probe library (always recompiles)."""
+    return _compile(PROBE_SOURCES, out, verbose=verbose)
+
+
+def build_all(verbose: bool = False) -> list[str]:
+    return [build(verbose=verbose), build_probe(verbose=verbose)]
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build_all(verbose="-v" in sys.argv))

@@ -16,6 +16,9 @@ struct hough_ctx {
     uint32_t *d_work;       // [0], [1]: work and exit counters of the fused kernels; from [64]:
                             // hough_peaks' per-block peak counts
     uint32_t *d_order;      // [kOrderMaxEvents] the fused kernel's largest-first schedule
+    uint32_t *d_iter_bm;    // the iterative finder's suppression bitmap when it does not fit LDS
+    hough::IterPlan iter1;  // the iterative finder on one event (hough_peaks_iterative)
+    hough::IterPlan iterb;  // ... over a batch (hough_run_batch_iterative), two workgroups per CU
     hough::GridArgs g;
     hough::BatchPlan plan;
     size_t lds_limit;
@@ -122,6 +125,7 @@ int hough_config(const hough_params *p, hough_ctx **out) {
         return HOUGH_EINVAL;
     if ((p->flags & HOUGH_FLAG_THETA_PERIODIC) && (p->n_theta < 2 || p->rho_min != -p->rho_max))
         return HOUGH_EINVAL;
+    if ((int64_t)p->n_theta * (int64_t)p->n_rho > (int64_t)INT32_MAX) return HOUGH_EINVAL;   // 32-bit cell indices
     const double A = (double)p->n_rho / (p->rho_max - p->rho_min);
     const double B = -p->rho_min * A;
     if (!isfinite(A) || !isfinite(B) || !(fabs(A) < 1e30) || !(fabs(B) < 1e30)) return HOUGH_EINVAL;
@@ -170,6 +174,12 @@ int hough_config(const hough_params *p, hough_ctx **out) {
         delete c;
         return HOUGH_ENOMEM;
     }
+    c->iter1 = hough::plan_iterative(p->n_theta, p->n_rho, limit, 1);
+    c->iterb = hough::plan_iterative(p->n_theta, p->n_rho, limit, 2);
+    if (c->iter1.gbm && hipMalloc(&c->d_iter_bm, c->iter1.bm_bytes) != hipSuccess) {
+        hough_destroy(c);
+        return HOUGH_ENOMEM;
+    }
     if (hipMemcpy(c->d_tables, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->d_work, 0, work_bytes) != hipSuccess) {
         hough_destroy(c);
@@ -203,6 +213,7 @@ void hough_destroy(hough_ctx *c) {
     if (c->d_tables) (void)hipFree(c->d_tables);
     if (c->d_work) (void)hipFree(c->d_work);
     if (c->d_order) (void)hipFree(c->d_order);
+    if (c->d_iter_bm) (void)hipFree(c->d_iter_bm);
     delete c;
 }
 
@@ -266,18 +277,23 @@ int hough_peaks_iterative(hough_ctx *c, const void *acc, uint32_t frac_num, uint
     if (!on_device(c)) return HOUGH_EINVAL;
     if (frac_den == 0 || r_theta < 0 || r_rho < 0) return HOUGH_EINVAL;
     if (((uintptr_t)peaks & 7u) != 0) return HOUGH_EINVAL;
-    if (hough::peaks_iterative_lds_bytes() > c->lds_limit) return HOUGH_EDEVICE;
+    // a window wider than the grid suppresses what the grid's width does
+    r_theta = r_theta < c->p.n_theta ? r_theta : c->p.n_theta;
+    r_rho = r_rho < c->p.n_rho ? r_rho : c->p.n_rho;
     const hipError_t e = hough::launch_peaks_iterative(c->g, acc, c->p.acc_type, frac_num, frac_den,
-                                                       r_theta, r_rho, peaks, cap, n_peaks, status,
-                                                       (hipStream_t)stream);
+                                                       r_theta, r_rho, peaks, cap, n_peaks, status, c->iter1,
+                                                       c->d_iter_bm, (hipStream_t)stream);
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
 }
 
-uint32_t hough_max_iterative_candidates(void) { return 16384u; }
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Workspace of hough_run_batch_iterative: the events' 16-bit accumulators, then (when the
+// finder's bitmap does not fit LDS) one suppression bitmap per event.
 size_t hough_iterative_workspace_bytes(const hough_ctx *c, uint32_t n_events) {
     if (!c) return 0;
-    return (size_t)n_events * (size_t)c->p.n_theta * (size_t)c->p.n_rho * sizeof(uint16_t);
+    const size_t acc = align256((size_t)n_events * (size_t)c->p.n_theta * (size_t)c->p.n_rho * sizeof(uint16_t));
+    return acc + (c->iterb.gbm ? (size_t)n_events * c->iterb.bm_bytes : 0);
 }
 
 int hough_run_batch_iterative(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,
@@ -292,7 +308,10 @@ int hough_run_batch_iterative(hough_ctx *c, const float *x, const float *y, cons
     if (c->p.max_peaks > 0 && !peaks) return HOUGH_EINVAL;
     if (((uintptr_t)peaks & 7u) != 0 || ((uintptr_t)workspace & 255u) != 0) return HOUGH_EINVAL;
     if (workspace_bytes < hough_iterative_workspace_bytes(c, n_events)) return HOUGH_EINVAL;
-    if (hough::peaks_iterative_lds_bytes() > c->lds_limit) return HOUGH_EDEVICE;
+    r_theta = r_theta < c->p.n_theta ? r_theta : c->p.n_theta;
+    r_rho = r_rho < c->p.n_rho ? r_rho : c->p.n_rho;
+    const size_t acc_bytes = align256((size_t)n_events * (size_t)c->p.n_theta * (size_t)c->p.n_rho * sizeof(uint16_t));
+    uint32_t *gbm = c->iterb.gbm ? reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + acc_bytes) : nullptr;
     hough::BatchArgs a{};
     a.x = x;
     a.y = y;
@@ -310,7 +329,7 @@ int hough_run_batch_iterative(hough_ctx *c, const float *x, const float *y, cons
     a.frac_num = 0;
     a.frac_den = 0;
     const hipError_t e = hough::launch_batch_iterative(c->g, a, static_cast<uint16_t *>(workspace), frac_num,
-                                                       frac_den, r_theta, r_rho, (hipStream_t)stream);
+                                                       frac_den, r_theta, r_rho, c->iterb, gbm, (hipStream_t)stream);
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
 }
 

@@ -103,10 +103,21 @@ hipError_t launch_order(const uint32_t *offsets, uint32_t n_events, uint32_t *or
 // most kMaxBatchHits hits, kKeepDuplicate for a later copy of a hit and 0 otherwise (all 0 for
 // events above kDedupMaxHits).
 hipError_t launch_dedup(const BatchArgs &a, hipStream_t s);
+// Launch shape of the iterative finder: `keys` candidate keys per chunk in LDS, and its
+// suppression bitmap (bm_bytes per event) in LDS after them (gbm 0) or in device memory (gbm 1).
+struct IterPlan {
+    uint32_t keys;
+    int gbm;
+    size_t lds_bytes;    // dynamic LDS per workgroup
+    size_t bm_bytes;     // bitmap bytes of one event (one bit per cell, whole 32-bit words)
+};
+// per_cu: workgroups per CU the plan should leave room for (the batch form runs one per event).
+IterPlan plan_iterative(int n_theta, int n_rho, size_t lds_limit, int per_cu);
 // The iterative finder over a CSR batch (a.ids must be null): acc holds n_events accumulators
-// of n_theta * n_rho 16-bit cells.
+// of n_theta * n_rho 16-bit cells; gbm (ip.gbm): n_events bitmaps of ip.bm_bytes.
 hipError_t launch_batch_iterative(const GridArgs &g, const BatchArgs &a, uint16_t *acc, uint32_t frac_num,
-                                  uint32_t frac_den, int r_theta, int r_rho, hipStream_t s);
+                                  uint32_t frac_den, int r_theta, int r_rho, const IterPlan &ip, uint32_t *gbm,
+                                  hipStream_t s);
 hipError_t launch_vote(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                        void *acc, int acc_type, hipStream_t s);
 // counts: ceil(n_theta / kPeakRowsPerBlock) counters of device scratch (the context's).
@@ -123,14 +134,14 @@ hipError_t launch_batch_split(const GridArgs &g, const BatchPlan &p, const Batch
 // LDS needs and plans (hough_kernels.hip).
 size_t vote_lds_bytes(int n_rho);
 size_t peaks_lds_bytes(int n_rho);
-size_t peaks_iterative_lds_bytes();
 hipError_t launch_track_params(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                                const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
                                double rho_min, double rho_max, double b_tesla, hough_track *out,
                                hipStream_t s);
 hipError_t launch_peaks_iterative(const GridArgs &g, const void *acc, int acc_type, uint32_t frac_num,
                                   uint32_t frac_den, int r_theta, int r_rho, hough_peak *peaks,
-                                  uint32_t cap, uint32_t *n_peaks, uint32_t *status, hipStream_t s);
+                                  uint32_t cap, uint32_t *n_peaks, uint32_t *status, const IterPlan &ip,
+                                  uint32_t *gbm, hipStream_t s);
 size_t batch_lds_bytes(int n_rho, int waves, int groups);
 int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out);
 int prepare_batch(const BatchPlan &p, size_t lds_limit);

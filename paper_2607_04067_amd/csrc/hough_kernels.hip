@@ -880,18 +880,24 @@ __global__ __launch_bounds__(NW * 64) void k_peaks(GridArgs g, const T *__restri
     }
 }
 
-// hough_peaks_iterative: the paper's peak finder (relative threshold, then iterative
-// extraction with neighbourhood suppression) for one event, in one workgroup.  The cells at or
-// above the threshold are gathered into LDS as 64-bit keys (count << 32 | ~raster index), sorted
-// descending (larger count first, then earlier in raster order), and wave 0 takes each key that
-// no earlier taken cell suppresses: the choices of the step-by-step extraction, since
-// suppression depends only on the cells already taken.  Wave 0 works 64 keys at a time: a key
-// dies if an earlier taken cell covers it; the first live key of the group is taken and kills
-// the later ones it covers, until none is live.  Taken cells are written back over the keys
-// already consumed.  More than kIterCandidates cells at or above the threshold: status gets
-// HOUGH_EV_TOO_MANY_CANDIDATES and no peak is listed.
-constexpr uint32_t kIterCandidates = 16384;
+// hough_peaks_iterative: the paper's peak finder (relative threshold, then iterative extraction
+// with neighbourhood suppression) for one event, in one workgroup of kIterWaves waves.
+//
+// A cell at or above the threshold is a candidate, keyed count << 32 | ~(raster index).  The
+// step-by-step extraction takes the candidates in descending key order (larger count first, then
+// earlier in raster order) and passes over those an earlier taken cell suppresses: suppression
+// depends only on the cells already taken.  The kernel does exactly that in chunks.  A chunk is
+// the next run of the sorted candidates that fits the LDS key buffer (K keys): its key range
+// comes from a histogram of the remaining candidates' counts (and, when one count alone has more
+// than K candidates, of their raster indices); it is gathered, sorted (bitonic, descending) and
+// walked in order by wave 0, 64 keys at a time, against a suppression bitmap of the whole grid
+// (one bit per cell, raster-indexed, set for every cell within r_theta columns and r_rho rows of
+// a taken cell).  Candidates the bitmap covers are left out of later chunks.  The bitmap lives in
+// LDS after the keys when it fits (GBM false), else in device memory (GBM true).
 constexpr int kIterWaves = 16;
+constexpr uint32_t kIterThreads = kIterWaves * 64;
+constexpr uint32_t kIterMaxKeys = 16384;     // 128 KB of LDS
+constexpr uint32_t kIterMinKeys = 1024;
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 #pragma unroll
@@ -899,26 +905,125 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return v;
 }
 
-// offsets (batch form, else null): workgroup e takes event e's accumulator (rho-major) at acc + e * cells,
-// writes its list at out + e * cap, n_peaks[e], and ORs its bits into status[e] (which the
-// batch vote wrote), adding HOUGH_EV_PEAKS_TRUNCATED; events the vote skipped get no peaks.
-template <typename T>
-__global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, const T *__restrict__ acc,
-                                                                uint32_t frac_num, uint32_t frac_den,
-                                                                int r_theta, int r_rho, hough_peak *out,
-                                                                uint32_t cap, uint32_t *n_peaks,
-                                                                uint32_t *status,
-                                                                const uint32_t *offsets = nullptr) {
-    extern __shared__ __align__(16) uint64_t keys[];            // [kIterCandidates]
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+// The suppression bitmap: every access comes from the event's own workgroup, so workgroup-scope
+// atomics order the marks of wave 0 against the later reads of every wave (LDS or device memory).
+__device__ __forceinline__ bool bm_test(const uint32_t *bm, uint32_t r) {
+    const uint32_t w = __hip_atomic_load(bm + (r >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return (w >> (r & 31)) & 1u;
+}
+
+// Set the bits of every cell within r_theta columns and r_rho rows of (jf, kf), clipped at the
+// grid edges: per column one raster run jj * n_rho + [k0, k1], a few words each; the 64 lanes
+// take the (column, word) pairs.
+__device__ void mark_window(uint32_t *bm, int jf, int kf, int r_theta, int r_rho, int n_theta, int n_rho,
+                            uint32_t lane) {
+    const int j0 = max(jf - r_theta, 0), j1 = min(jf + r_theta, n_theta - 1);
+    const int k0 = max(kf - r_rho, 0), k1 = min(kf + r_rho, n_rho - 1);
+    const uint32_t per = (uint32_t)((k1 - k0) >> 5) + 2u;          // words one column can touch
+    const uint32_t units = (uint32_t)(j1 - j0 + 1) * per;
+    for (uint32_t u = lane; u < units; u += 64) {
+        const uint32_t col = (uint32_t)j0 + u / per, slot = u % per;
+        const uint32_t a = col * (uint32_t)n_rho + (uint32_t)k0, e = col * (uint32_t)n_rho + (uint32_t)k1;
+        const uint32_t w = (a >> 5) + slot;
+        if (w > (e >> 5)) continue;
+        const uint32_t lo = w == (a >> 5) ? (a & 31u) : 0u, hi = w == (e >> 5) ? (e & 31u) : 31u;
+        const uint32_t bits = (hi == 31u ? ~0u : ((1u << (hi + 1u)) - 1u)) & ~((1u << lo) - 1u);
+        __hip_atomic_fetch_or(bm + w, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+// Every cell of an accumulator of `cells` cells, eight loads in flight per lane: f(c, v, in) for
+// storage index c, count v, and in = c < cells.  Every lane calls f the same number of times per
+// wave, so f may use wave-wide operations.
+template <typename T, typename F>
+__device__ __forceinline__ void for_cells(const T *acc, uint32_t cells, F &&f) {
+    constexpr int U = 8;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint32_t base = wave * 64u; base < cells; base += U * kIterThreads) {
+        uint32_t v[U];
+#pragma unroll
+        for (int r = 0; r < U; ++r) {
+            const uint32_t c = base + (uint32_t)r * kIterThreads + lane;
+            v[r] = c < cells ? (uint32_t)acc[c] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < U; ++r) {
+            const uint32_t c = base + (uint32_t)r * kIterThreads + lane;
+            f(c, v[r], c < cells);
+        }
+    }
+}
+
+// Append `key` for the lanes where p holds, at positions taken from the LDS counter *cnt (one
+// atomic per wave); positions at or past `room` are counted but not stored.
+__device__ __forceinline__ void append_key(uint64_t *keys, uint32_t *cnt, uint32_t room, bool p, uint64_t key,
+                                           uint32_t lane) {
+    const uint64_t b = __ballot(p);
+    if (!b) return;
+    uint32_t off = 0;
+    if (lane == 0) off = atomicAdd(cnt, (uint32_t)__popcll(b));
+    off = (uint32_t)__shfl((int)off, 0, 64);
+    const uint32_t pos = off + mbcnt(b);
+    if (p && pos < room) keys[pos] = key;
+}
+
+// Wave 0 reads hist[0 .. nb) in processing order (from bin nb - 1 down when `top`, else from bin
+// 0 up) and returns, through *m, the number of leading bins whose counts sum to at most `room`
+// and, through *first, the position of the first non-empty bin (nb when all are empty).  nb is a
+// multiple of 64.
+__device__ void hist_fit(const uint32_t *hist, uint32_t nb, bool top, uint32_t room, uint32_t lane, uint32_t *m,
+                         uint32_t *first) {
+    const uint32_t per = nb / 64u, q0 = lane * per;
+    uint32_t s = 0, f = nb;
+    for (uint32_t q = q0; q < q0 + per; ++q) {
+        const uint32_t h = hist[top ? nb - 1u - q : q];
+        if (h && f == nb) f = q;
+        s += h;
+    }
+    const uint32_t incl = wave_inclusive_scan(s, (int)lane);
+    const uint64_t over = __ballot(incl > room);
+    uint32_t mm = nb;
+    if (over) {
+        const uint32_t cl = (uint32_t)__builtin_ctzll(over);
+        if (lane == cl) {
+            uint32_t run = incl - s;
+            for (uint32_t q = q0; q < q0 + per; ++q) {
+                run += hist[top ? nb - 1u - q : q];
+                if (run > room) { mm = q; break; }
+            }
+        }
+        mm = (uint32_t)__builtin_amdgcn_readlane((int)mm, (int)cl);
+    }
+    *m = mm;
+    *first = wave_min(f);
+}
+
+// offsets (batch form, else null): workgroup e takes event e's accumulator (rho-major 16-bit
+// cells) at acc + e * cells, writes its list at out + e * cap, n_peaks[e], and ORs
+// HOUGH_EV_PEAKS_TRUNCATED into status[e] (which the batch vote wrote); events the vote skipped
+// get no peaks.  K: keys in the LDS buffer (a power of two, kIterMinKeys .. kIterMaxKeys).
+// gbm (GBM): device bitmaps of bm_words words, one per workgroup.
+template <typename T, bool GBM>
+__global__ __launch_bounds__(kIterThreads) void k_peaks_iter(GridArgs g, const T *__restrict__ acc,
+                                                             uint32_t frac_num, uint32_t frac_den, int r_theta,
+                                                             int r_rho, hough_peak *out, uint32_t cap,
+                                                             uint32_t *n_peaks, uint32_t *status,
+                                                             const uint32_t *offsets, uint32_t K, uint32_t *gbm) {
+    extern __shared__ __align__(16) uint64_t keys[];       // [K]; the histograms reuse it as 2K words
+    uint32_t *hist = reinterpret_cast<uint32_t *>(keys);
     __shared__ uint32_t s_red[kIterWaves];
-    __shared__ uint32_t s_nc, s_nk;
-    constexpr int NT = kIterWaves * 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t nr = (uint32_t)g.n_rho;
-    const uint32_t cells = (uint32_t)g.n_theta * nr;
+    __shared__ uint32_t s_n, s_m, s_first, s_taken;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nr = (uint32_t)g.n_rho, nt = (uint32_t)g.n_theta;
+    const uint32_t cells = nt * nr, bm_words = (cells + 31u) / 32u, NB = 2u * K;
     const bool batch = offsets != nullptr;
-    // the batch form stores rho-major (see kAccU16RhoMajor); keys always hold raster indices
-    const uint32_t nt = (uint32_t)g.n_theta;
+    // the batch form stores rho-major (see kAccU16RhoMajor); keys and the bitmap use raster order
     auto raster = [&](uint32_t c) -> uint32_t {
         if (!batch) return c;
         const uint32_t k = c / nt;
@@ -936,35 +1041,20 @@ __global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, cons
             return;
         }
     }
-    const uint32_t floor_t = g.threshold;
-    if (tid == 0) { s_nc = 0u; s_nk = 0u; }
+    uint32_t *bm = GBM ? gbm + (batch ? (size_t)blockIdx.x * bm_words : (size_t)0)
+                       : reinterpret_cast<uint32_t *>(keys + K);
+    for (uint32_t w = tid; w < bm_words; w += kIterThreads) bm[w] = 0u;
+    if (tid == 0) { s_n = 0u; s_taken = 0u; }
     __syncthreads();
-    // pass 1: the global maximum, and every cell at or above the absolute floor while they fit
-    // (eight loads in flight per lane)
-    constexpr int U = 8;
+
+    // pass 1: the maximum, and the candidates of the absolute floor while they fit
+    const uint32_t floor_t = g.threshold;
     uint32_t m = 0;
-    for (uint32_t base = (uint32_t)wave * 64u; base < cells; base += U * NT) {
-        uint32_t v[U];
-#pragma unroll
-        for (int r = 0; r < U; ++r) {
-            const uint32_t c = base + (uint32_t)r * NT + lane;
-            v[r] = c < cells ? (uint32_t)acc[c] : 0u;
-        }
-#pragma unroll
-        for (int r = 0; r < U; ++r) {
-            const uint32_t c = base + (uint32_t)r * NT + lane;
-            m = max(m, v[r]);
-            const bool p = c < cells && v[r] >= floor_t;
-            const uint64_t b = __ballot(p);
-            if (b) {
-                uint32_t off = 0;
-                if (lane == 0) off = atomicAdd(&s_nc, (uint32_t)__popcll(b));
-                off = (uint32_t)__shfl((int)off, 0, 64);
-                const uint32_t pos = off + mbcnt(b);
-                if (p && pos < kIterCandidates) keys[pos] = ((uint64_t)v[r] << 32) | (uint64_t)(~raster(c));
-            }
-        }
-    }
+    for_cells(acc, cells, [&](uint32_t c, uint32_t v, bool in) {
+        m = max(m, v);
+        const bool p = in && v >= floor_t;
+        append_key(keys, &s_n, K, p, p ? ((uint64_t)v << 32) | (uint64_t)(~raster(c)) : 0ull, lane);
+    });
     m = wave_max(m);
     if (lane == 0) s_red[wave] = m;
     __syncthreads();
@@ -972,115 +1062,170 @@ __global__ __launch_bounds__(kIterWaves * 64) void k_peaks_iter(GridArgs g, cons
     for (int w = 0; w < kIterWaves; ++w) mx = max(mx, s_red[w]);
     const uint64_t rel = ((uint64_t)mx * frac_num + frac_den - 1u) / frac_den;
     const uint32_t thr = (uint32_t)min<uint64_t>(max<uint64_t>(rel, floor_t), 0xffffffffull);
-    const uint32_t n1 = s_nc;
+    const uint32_t n1 = s_n;
     __syncthreads();
-    // keep the keys that reach the relative threshold; if pass 1 overflowed, gather them again
-    if (n1 <= kIterCandidates) {
+
+    bool bounded = false;      // keys below `hi` are what is left once a chunk has been walked
+    uint64_t hi = 0;
+    bool have_chunk = false;
+    uint32_t n = 0;
+    uint64_t lo = 0;           // the chunk's lowest key (0: the chunk holds every candidate left)
+    if (n1 <= K) {
+        // every floor candidate is in LDS: keep those that reach thr, in place
         if (thr > floor_t) {
-            uint64_t mine[kIterCandidates / NT];
-#pragma unroll
-            for (int r = 0; r < (int)(kIterCandidates / NT); ++r) {
-                const uint32_t i = (uint32_t)tid + (uint32_t)r * NT;
-                mine[r] = i < n1 ? keys[i] : 0ull;
-            }
+            if (tid == 0) s_n = 0u;
             __syncthreads();
-#pragma unroll
-            for (int r = 0; r < (int)(kIterCandidates / NT); ++r) {
-                const bool p = (uint32_t)(mine[r] >> 32) >= thr && mine[r] != 0ull;
-                const uint64_t b = __ballot(p);
-                if (b) {
-                    uint32_t off = 0;
-                    if (lane == 0) off = atomicAdd(&s_nk, (uint32_t)__popcll(b));
-                    off = (uint32_t)__shfl((int)off, 0, 64);
-                    if (p) keys[off + mbcnt(b)] = mine[r];
-                }
-            }
-        } else if (tid == 0) {
-            s_nk = n1;
-        }
-    } else {
-        for (uint32_t base = (uint32_t)wave * 64u; base < cells; base += U * NT) {
-            uint32_t v[U];
-#pragma unroll
-            for (int r = 0; r < U; ++r) {
-                const uint32_t c = base + (uint32_t)r * NT + lane;
-                v[r] = c < cells ? (uint32_t)acc[c] : 0u;
-            }
-#pragma unroll
-            for (int r = 0; r < U; ++r) {
-                const uint32_t c = base + (uint32_t)r * NT + lane;
-                const bool p = c < cells && v[r] >= thr;
-                const uint64_t b = __ballot(p);
-                if (b) {
-                    uint32_t off = 0;
-                    if (lane == 0) off = atomicAdd(&s_nk, (uint32_t)__popcll(b));
-                    off = (uint32_t)__shfl((int)off, 0, 64);
-                    const uint32_t pos = off + mbcnt(b);
-                    if (p && pos < kIterCandidates) keys[pos] = ((uint64_t)v[r] << 32) | (uint64_t)(~raster(c));
-                }
+            for (uint32_t i0 = 0; i0 < n1; i0 += kIterThreads) {
+                const uint32_t i = i0 + tid;
+                const uint64_t key = i < n1 ? keys[i] : 0ull;
+                __syncthreads();
+                append_key(keys, &s_n, K, i < n1 && (uint32_t)(key >> 32) >= thr, key, lane);
+                __syncthreads();
             }
         }
+        n = s_n;
+        have_chunk = true;
     }
-    __syncthreads();
-    const uint32_t nc = s_nk;
-    if (nc > kIterCandidates) {
-        if (tid == 0) {
-            *n_peaks = 0u;
-            *status = (batch ? *status : 0u) | HOUGH_EV_TOO_MANY_CANDIDATES;
-        }
-        return;
-    }
-    // bitonic sort, descending, over the next power of two
-    uint32_t P = 1;
-    while (P < nc) P <<= 1;
-    for (uint32_t i = nc + tid; i < P; i += NT) keys[i] = 0ull;
-    __syncthreads();
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = tid; i < P; i += NT) {
-                const uint32_t ixj = i ^ j;
-                if (ixj > i) {
-                    const uint64_t a = keys[i], b = keys[ixj];
-                    const bool desc = (i & k) == 0u;
-                    if (desc ? (a < b) : (a > b)) { keys[i] = b; keys[ixj] = a; }
+    for (;;) {
+        if (!have_chunk) {
+            // the next chunk: the largest remaining keys whose number fits K
+            uint32_t vlo = thr, vhi = bounded ? (uint32_t)(hi >> 32) : mx;
+            bool none = vhi < vlo;
+            while (!none) {
+                const uint32_t w = (uint32_t)(((uint64_t)vhi - vlo + 1u + NB - 1u) / NB);
+                for (uint32_t b = tid; b < NB; b += kIterThreads) hist[b] = 0u;
+                __syncthreads();
+                for_cells(acc, cells, [&](uint32_t c, uint32_t v, bool in) {
+                    if (!in || v < vlo || v > vhi) return;
+                    const uint32_t r = raster(c);
+                    const uint64_t key = ((uint64_t)v << 32) | (uint64_t)(~r);
+                    if ((bounded && key >= hi) || bm_test(bm, r)) return;
+                    atomicAdd(&hist[(v - vlo) / w], 1u);
+                });
+                __syncthreads();
+                if (wave == 0) hist_fit(hist, NB, true, K, lane, &s_m, &s_first);
+                __syncthreads();
+                const uint32_t mb = s_m, fb = s_first;
+                __syncthreads();
+                if (fb == NB) { none = true; break; }                   // nothing left
+                if (mb > fb) {                                          // bins NB - mb .. NB - 1 fit
+                    lo = (uint64_t)(vlo + (NB - mb) * w) << 32;
+                    break;
                 }
+                const uint32_t bt = NB - 1u - fb;                       // the top non-empty bin, too full
+                if (w > 1u) {
+                    vhi = (uint32_t)min<uint64_t>((uint64_t)vhi, (uint64_t)vlo + (uint64_t)bt * w + w - 1u);
+                    vlo = vlo + bt * w;
+                    continue;
+                }
+                // one count vt has more than K candidates left: split them by raster index
+                const uint32_t vt = vlo + bt;
+                uint32_t rlo = (bounded && vt == (uint32_t)(hi >> 32)) ? ~(uint32_t)hi + 1u : 0u, rhi = cells - 1u;
+                for (;;) {
+                    const uint32_t wr = (uint32_t)(((uint64_t)rhi - rlo + 1u + NB - 1u) / NB);
+                    for (uint32_t b = tid; b < NB; b += kIterThreads) hist[b] = 0u;
+                    __syncthreads();
+                    for_cells(acc, cells, [&](uint32_t c, uint32_t v, bool in) {
+                        if (!in || v != vt) return;
+                        const uint32_t r = raster(c);
+                        if (r < rlo || r > rhi || bm_test(bm, r)) return;
+                        atomicAdd(&hist[(r - rlo) / wr], 1u);
+                    });
+                    __syncthreads();
+                    if (wave == 0) hist_fit(hist, NB, false, K, lane, &s_m, &s_first);
+                    __syncthreads();
+                    const uint32_t mr = s_m, fr = s_first;
+                    __syncthreads();
+                    if (mr > fr) {                                      // raster bins 0 .. mr - 1 fit
+                        const uint32_t r_end = (uint32_t)min<uint64_t>((uint64_t)rhi, (uint64_t)rlo + (uint64_t)mr * wr - 1u);
+                        lo = ((uint64_t)vt << 32) | (uint64_t)(~r_end);
+                        break;
+                    }
+                    rhi = (uint32_t)min<uint64_t>((uint64_t)rhi, (uint64_t)rlo + (uint64_t)fr * wr + wr - 1u);
+                    rlo = rlo + fr * wr;
+                }
+                break;
             }
+            if (none) break;
+            if (lo == ((uint64_t)thr << 32)) lo = 0;                    // every count down to thr
+            // gather the chunk: the remaining keys in [lo, hi)
+            if (tid == 0) s_n = 0u;
             __syncthreads();
+            for_cells(acc, cells, [&](uint32_t c, uint32_t v, bool in) {
+                bool p = in && v >= thr;
+                uint64_t key = 0;
+                if (p) {
+                    const uint32_t r = raster(c);
+                    key = ((uint64_t)v << 32) | (uint64_t)(~r);
+                    p = key >= lo && (!bounded || key < hi) && !bm_test(bm, r);
+                }
+                append_key(keys, &s_n, K, p, key, lane);
+            });
+            __syncthreads();
+            n = s_n;
         }
-    }
-    if (wave != 0) return;
-    // greedy extraction (wave 0): taken cells are stored as count << 32 | j << 16 | k
-    uint32_t taken = 0;
-    for (uint32_t base = 0; base < nc; base += 64) {
-        const uint32_t i = base + lane;
-        bool live = i < nc;
-        const uint64_t key = live ? keys[i] : 0ull;
-        const uint32_t c = ~(uint32_t)key, v = (uint32_t)(key >> 32);
-        const int j = live ? (int)(c / nr) : 0, k = live ? (int)(c - (uint32_t)j * nr) : 0;
-        wave_sync();
-        for (uint32_t a = 0; a < taken; ++a) {
-            const uint64_t t = keys[a];
-            const int ja = (int)((t >> 16) & 0xffffu), ka = (int)(t & 0xffffu);
-            live = live && !(abs(j - ja) <= r_theta && abs(k - ka) <= r_rho);
-        }
-        uint64_t b = __ballot(live);
-        while (b) {
-            const int f = __builtin_ctzll(b);
-            const int jf = __builtin_amdgcn_readlane(j, f), kf = __builtin_amdgcn_readlane(k, f);
-            const uint32_t vf = (uint32_t)__builtin_amdgcn_readlane((int)v, f);
-            if (lane == 0) {
-                keys[taken] = ((uint64_t)vf << 32) | ((uint64_t)jf << 16) | (uint64_t)kf;
-                if (taken < cap) store_peak(out + taken, (uint32_t)jf, (uint32_t)kf, vf);
+        have_chunk = false;
+        // bitonic sort, descending, over the next power of two (n <= K)
+        uint32_t P = 1;
+        while (P < n) P <<= 1;
+        for (uint32_t i = n + tid; i < P; i += kIterThreads) keys[i] = 0ull;
+        __syncthreads();
+        for (uint32_t k = 2; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = tid; i < P; i += kIterThreads) {
+                    const uint32_t ixj = i ^ j;
+                    if (ixj > i) {
+                        const uint64_t a = keys[i], b = keys[ixj];
+                        const bool desc = (i & k) == 0u;
+                        if (desc ? (a < b) : (a > b)) { keys[i] = b; keys[ixj] = a; }
+                    }
+                }
+                __syncthreads();
             }
-            ++taken;
-            live = live && lane != f && !(abs(j - jf) <= r_theta && abs(k - kf) <= r_rho);
-            b = __ballot(live);
         }
-        wave_sync();
+        // the walk (wave 0): a key the bitmap covers is passed over; within a group of 64 the
+        // first live key is taken and suppresses the later ones in its window; the group's taken
+        // cells then mark their windows for the keys after them
+        if (wave == 0) {
+            uint32_t taken = s_taken;
+            for (uint32_t base = 0; base < n; base += 64) {
+                const uint32_t i = base + lane;
+                bool live = i < n;
+                const uint64_t key = live ? keys[i] : 0ull;
+                const uint32_t r = ~(uint32_t)key, v = (uint32_t)(key >> 32);
+                const int j = live ? (int)(r / nr) : 0, k = live ? (int)(r - (uint32_t)j * nr) : 0;
+                live = live && !bm_test(bm, r);
+                uint64_t b = __ballot(live), took = 0;
+                while (b) {
+                    const int f = __builtin_ctzll(b);
+                    const int jf = __builtin_amdgcn_readlane(j, f), kf = __builtin_amdgcn_readlane(k, f);
+                    const uint32_t vf = (uint32_t)__builtin_amdgcn_readlane((int)v, f);
+                    if (lane == 0 && taken < cap) store_peak(out + taken, (uint32_t)jf, (uint32_t)kf, vf);
+                    ++taken;
+                    took |= 1ull << f;
+                    live = live && (int)lane != f && !(abs(j - jf) <= r_theta && abs(k - kf) <= r_rho);
+                    b = __ballot(live);
+                }
+                while (took) {
+                    const int f = __builtin_ctzll(took);
+                    took &= took - 1ull;
+                    mark_window(bm, __builtin_amdgcn_readlane(j, f), __builtin_amdgcn_readlane(k, f), r_theta,
+                                r_rho, (int)nt, (int)nr, lane);
+                }
+                wave_sync();
+            }
+            if (lane == 0) s_taken = taken;
+        }
+        __syncthreads();
+        if (lo == 0) break;                       // the chunk reached the lowest candidate
+        bounded = true;
+        hi = lo;
     }
-    if (lane == 0) {
+    if (tid == 0) {
+        const uint32_t taken = s_taken;
         *n_peaks = taken;
-        *status = batch ? (*status | (taken > cap ? HOUGH_EV_PEAKS_TRUNCATED : 0u)) : 0u;
+        const uint32_t tr = taken > cap ? HOUGH_EV_PEAKS_TRUNCATED : 0u;
+        *status = batch ? (*status | tr) : tr;
     }
 }
 
@@ -1877,27 +2022,69 @@ hipError_t launch_peaks(const GridArgs &g, const void *acc, int acc_type, hough_
     return hipGetLastError();
 }
 
-hipError_t launch_peaks_iterative(const GridArgs &g, const void *acc, int acc_type, uint32_t frac_num,
-                                  uint32_t frac_den, int r_theta, int r_rho, hough_peak *peaks,
-                                  uint32_t cap, uint32_t *n_peaks, uint32_t *status, hipStream_t s) {
-    const size_t lds = (size_t)kIterCandidates * sizeof(uint64_t);
-    if (acc_type == HOUGH_ACC_U16) {
-        static const bool lds_ok = (allow_lds(k_peaks_iter<uint16_t>), true);
-        (void)lds_ok;
-        hipLaunchKernelGGL((k_peaks_iter<uint16_t>), dim3(1), dim3(kIterWaves * 64), lds, s, g,
-                           static_cast<const uint16_t *>(acc), frac_num, frac_den, r_theta, r_rho,
-                           peaks, cap, n_peaks, status);
-    } else {
-        static const bool lds_ok = (allow_lds(k_peaks_iter<uint32_t>), true);
-        (void)lds_ok;
-        hipLaunchKernelGGL((k_peaks_iter<uint32_t>), dim3(1), dim3(kIterWaves * 64), lds, s, g,
-                           static_cast<const uint32_t *>(acc), frac_num, frac_den, r_theta, r_rho,
-                           peaks, cap, n_peaks, status);
+// Key buffer and bitmap placement of the iterative finder: the largest key buffer (a power of two
+// of kIterMinKeys .. kIterMaxKeys keys) that fits beside an LDS bitmap of the grid, with room for
+// `per_cu` workgroups per CU when that leaves at least 4096 keys, else one; a grid whose bitmap
+// does not fit beside kIterMinKeys keys keeps it in device memory.
+IterPlan plan_iterative(int n_theta, int n_rho, size_t lds_limit, int per_cu) {
+    IterPlan p{};
+    const size_t cells = (size_t)n_theta * (size_t)n_rho;
+    p.bm_bytes = (cells + 31) / 32 * 4;
+    const size_t room = lds_limit > 1024 ? lds_limit - 1024 : 0;      // static LDS and slack
+    const size_t bm_lds = (p.bm_bytes + 15) & ~(size_t)15;
+    for (int pc = per_cu; pc >= 1; --pc) {
+        const uint32_t min_keys = pc > 1 ? 4096u : kIterMinKeys;
+        for (uint32_t k = kIterMaxKeys; k >= min_keys; k >>= 1) {
+            if ((size_t)pc * ((size_t)k * 8 + bm_lds) <= room) {
+                p.keys = k;
+                p.gbm = 0;
+                p.lds_bytes = (size_t)k * 8 + bm_lds;
+                return p;
+            }
+        }
     }
-    return hipGetLastError();
+    for (uint32_t k = kIterMaxKeys; k >= kIterMinKeys; k >>= 1) {
+        if ((size_t)per_cu * (size_t)k * 8 <= room || k == kIterMinKeys) {
+            p.keys = k;
+            break;
+        }
+    }
+    p.gbm = 1;
+    p.lds_bytes = (size_t)p.keys * 8;
+    return p;
 }
 
-size_t peaks_iterative_lds_bytes() { return (size_t)kIterCandidates * sizeof(uint64_t) + 256; }
+template <typename T>
+static void launch_iter_t(const GridArgs &g, const T *acc, uint32_t frac_num, uint32_t frac_den, int r_theta,
+                          int r_rho, hough_peak *peaks, uint32_t cap, uint32_t *n_peaks, uint32_t *status,
+                          const uint32_t *offsets, uint32_t n_blocks, const IterPlan &ip, uint32_t *gbm,
+                          hipStream_t s) {
+    if (ip.gbm) {
+        static const bool lds_ok = (allow_lds(k_peaks_iter<T, true>), true);
+        (void)lds_ok;
+        hipLaunchKernelGGL((k_peaks_iter<T, true>), dim3(n_blocks), dim3(kIterThreads), ip.lds_bytes, s, g, acc,
+                           frac_num, frac_den, r_theta, r_rho, peaks, cap, n_peaks, status, offsets, ip.keys, gbm);
+    } else {
+        static const bool lds_ok = (allow_lds(k_peaks_iter<T, false>), true);
+        (void)lds_ok;
+        hipLaunchKernelGGL((k_peaks_iter<T, false>), dim3(n_blocks), dim3(kIterThreads), ip.lds_bytes, s, g, acc,
+                           frac_num, frac_den, r_theta, r_rho, peaks, cap, n_peaks, status, offsets, ip.keys,
+                           nullptr);
+    }
+}
+
+hipError_t launch_peaks_iterative(const GridArgs &g, const void *acc, int acc_type, uint32_t frac_num,
+                                  uint32_t frac_den, int r_theta, int r_rho, hough_peak *peaks,
+                                  uint32_t cap, uint32_t *n_peaks, uint32_t *status, const IterPlan &ip,
+                                  uint32_t *gbm, hipStream_t s) {
+    if (acc_type == HOUGH_ACC_U16)
+        launch_iter_t<uint16_t>(g, static_cast<const uint16_t *>(acc), frac_num, frac_den, r_theta, r_rho, peaks,
+                                cap, n_peaks, status, nullptr, 1u, ip, gbm, s);
+    else
+        launch_iter_t<uint32_t>(g, static_cast<const uint32_t *>(acc), frac_num, frac_den, r_theta, r_rho, peaks,
+                                cap, n_peaks, status, nullptr, 1u, ip, gbm, s);
+    return hipGetLastError();
+}
 
 hipError_t launch_track_params(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                                const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
@@ -1927,7 +2114,8 @@ hipError_t launch_retain(const GridArgs &g, const float *x, const float *y, uint
 // The iterative finder's batch form: (duplicate pass), vote into per-event 16-bit accumulators,
 // the finder, and retention with each event's first `cap` peaks, four launches for the batch.
 hipError_t launch_batch_iterative(const GridArgs &g, const BatchArgs &a, uint16_t *acc, uint32_t frac_num,
-                                  uint32_t frac_den, int r_theta, int r_rho, hipStream_t s) {
+                                  uint32_t frac_den, int r_theta, int r_rho, const IterPlan &ip, uint32_t *gbm,
+                                  hipStream_t s) {
     if (a.n_events == 0) return hipSuccess;
     hipError_t e = hipSuccess;
     if (g.dedup) {
@@ -1943,15 +2131,9 @@ hipError_t launch_batch_iterative(const GridArgs &g, const BatchArgs &a, uint16_
                            a.x, a.y, a.offsets, acc, a.keep, a.status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    {
-        const size_t lds = (size_t)kIterCandidates * sizeof(uint64_t);
-        static const bool lds_ok = (allow_lds(k_peaks_iter<uint16_t>), true);
-        (void)lds_ok;
-        hipLaunchKernelGGL((k_peaks_iter<uint16_t>), dim3(a.n_events), dim3(kIterWaves * 64), lds, s, g,
-                           static_cast<const uint16_t *>(acc), frac_num, frac_den, r_theta, r_rho, a.peaks,
-                           a.max_peaks, a.n_peaks, a.status, a.offsets);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    launch_iter_t<uint16_t>(g, acc, frac_num, frac_den, r_theta, r_rho, a.peaks, a.max_peaks, a.n_peaks, a.status,
+                            a.offsets, a.n_events, ip, gbm, s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         const int rows = retain_rows_per_block(g);
         const size_t lds = retain_lds_bytes(g, rows);

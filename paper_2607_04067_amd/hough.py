@@ -20,7 +20,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "hough.h")
 
 HOUGH_OK, HOUGH_EINVAL, HOUGH_ENOMEM, HOUGH_EOVERFLOW, HOUGH_EDEVICE = 0, -1, -2, -3, -4
 ACC_U16, ACC_I32 = 1, 2
-EV_PEAKS_TRUNCATED, EV_INVALID_HITS, EV_TOO_MANY_HITS, EV_TOO_MANY_CANDIDATES = 1, 2, 4, 8
+EV_PEAKS_TRUNCATED, EV_INVALID_HITS, EV_TOO_MANY_HITS = 1, 2, 4
 EV_DEDUP_SKIPPED = 16
 
 
@@ -73,8 +73,6 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.hough_peaks_iterative.restype = i32
     L.hough_track_params.argtypes = [vp, vp, vp, u32, vp, vp, u32, ctypes.c_double, vp, vp]
     L.hough_track_params.restype = i32
-    L.hough_max_iterative_candidates.argtypes = []
-    L.hough_max_iterative_candidates.restype = u32
     L.hough_max_dedup_hits.argtypes = []
     L.hough_max_dedup_hits.restype = u32
     L.hough_run_batch_relative.argtypes = [vp, vp, vp, vp, u32, u32, u32, vp, vp, vp, vp, vp]
@@ -134,6 +132,20 @@ def _dev(t: torch.Tensor, dtype, name: str, numel: int | None = None) -> int:
     if numel is not None and t.numel() < numel:
         raise ValueError(f"{name} needs at least {numel} elements, has {t.numel()}")
     return t.data_ptr()
+
+
+def _hits(x: torch.Tensor, y: torch.Tensor, keep: torch.Tensor | None = None, keep_needed: int | None = None) -> int:
+    """Number of hits of x and y, after checking that y holds as many as x and that keep (when
+    given) has room for keep_needed bytes (one per hit by default).  Raises ValueError before any
+    pointer reaches the library: a short buffer would be read or written out of bounds there."""
+    n = x.numel()
+    if y.numel() != n:
+        raise ValueError(f"x and y differ in length ({n} and {y.numel()})")
+    if keep is not None:
+        need = n if keep_needed is None else int(keep_needed)
+        if keep.numel() < need:
+            raise ValueError(f"keep needs at least {need} bytes, has {keep.numel()}")
+    return n
 
 
 def _stream(stream) -> int:
@@ -228,9 +240,7 @@ class Context:
     # ------------------------------------------------------------------ plain path
     def vote(self, x: torch.Tensor, y: torch.Tensor, acc: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """Accumulator [n_theta, n_rho] (int32, or int16 holding uint16 bits) of one event."""
-        n = x.numel()
-        if y.numel() != n:
-            raise ValueError("x and y differ in length")
+        n = _hits(x, y)
         dt = torch.int16 if self.acc_type == "u16" else torch.int32
         if acc is None:
             acc = torch.empty((self.n_theta, self.n_rho), dtype=dt, device=x.device)
@@ -280,6 +290,7 @@ class Context:
                      stream=None) -> torch.Tensor:
         """Candidate circles of the first min(n_peaks, cap) peaks: float64 [cap, 6] holding
         hough_track records (decode with decode_tracks)."""
+        _hits(x, y)
         if tracks is None:
             tracks = torch.zeros((max(cap, 1), 6), dtype=torch.float64, device=peaks.device)
         pt = _dev(tracks, torch.float64, "tracks", 6 * cap)
@@ -293,7 +304,7 @@ class Context:
 
     def retain(self, x: torch.Tensor, y: torch.Tensor, peaks: torch.Tensor, n_peaks: torch.Tensor, cap: int,
                keep: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        n = x.numel()
+        n = _hits(x, y, keep)
         if keep is None:
             keep = torch.empty(n, dtype=torch.uint8, device=x.device)
         pk = self._ptr_or_dummy(keep, torch.uint8, "keep")
@@ -312,6 +323,7 @@ class Context:
         """Whole path over CSR events.  offsets: int32 [E+1] (uint32 values).  frac=(num, den):
         each event's threshold relative to its largest count (hough_run_batch_relative).
         Returns (peaks int32 [E, max_peaks, 2], n_peaks int32 [E], keep uint8 [H], status int32 [E])."""
+        _hits(x, y, keep)
         E = offsets.numel() - 1
         mp = self.params.max_peaks
         dev = offsets.device
@@ -351,6 +363,7 @@ class Context:
         """The paper's peak finder over CSR events (hough_run_batch_iterative).  Returns (peaks
         int32 [E, max_peaks, 2] in extraction order, n_peaks int32 [E], keep uint8 [H],
         status int32 [E])."""
+        _hits(x, y, keep)
         E = offsets.numel() - 1
         mp = self.params.max_peaks
         dev = offsets.device
@@ -393,6 +406,7 @@ class Context:
         workspace: from split_workspace (kept zero between calls)."""
         if (event_ids is None) != (keep_offsets is None):
             raise ValueError("event_ids and keep_offsets go together")
+        _hits(x, y, keep, x.numel() if event_ids is None else keep_size)
         E = offsets.numel() - 1 if event_ids is None else event_ids.numel()
         mp = self.params.max_peaks
         dev = offsets.device
@@ -430,7 +444,9 @@ class Context:
                          n_peaks: torch.Tensor | None = None, keep: torch.Tensor | None = None,
                          status: torch.Tensor | None = None, keep_size: int | None = None, stream=None):
         """hough_run_batch over pool events `event_ids` (int32, uint32 values); event e's keep
-        bytes start at keep_offsets[e] (int32).  Returns (peaks, n_peaks, keep, status)."""
+        bytes start at keep_offsets[e] (int32).  keep_size: bytes of keep the batch writes (checked
+        against keep when both are given).  Returns (peaks, n_peaks, keep, status)."""
+        _hits(x, y, keep, keep_size)
         E = event_ids.numel()
         mp = self.params.max_peaks
         dev = offsets.device

@@ -59,7 +59,7 @@ def test_more_than_one_gpu_is_refused():
 
 
 @pytest.mark.parametrize("flag", ["--no-e2e", "--no-serve", "--no-plain", "--no-cpu-baseline",
-                                  "--copy-reference-mb", "--tune", "--graph"])
+                                  "--copy-reference-mb", "--no-tune", "--no-graph", "--plan"])
 def test_bench_flags_are_offered(flag, capsys):
     import bench
     with pytest.raises(SystemExit) as e:

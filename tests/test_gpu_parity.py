@@ -265,31 +265,41 @@ def test_determinism_and_batch_independence(H):
     ctx.close()
 
 
+def _host_threads() -> int:
+    import os
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
 @pytest.mark.parametrize("name", ["paper-1000ev-360x256", "batch-10000ev-360x256", "dense-2000ev-720x512",
                                   "paper-1000ev-1000x1000"])
-def test_full_size_sampled(H, orc, name):
-    """The whole workload in one launch (as timed by the benchmark); sampled events vs oracle."""
+def test_full_size_every_event(H, orc, name):
+    """The whole workload in one launch, as the benchmark times it; every event's peak list, true
+    count, status and keep bytes equal the oracle's (the oracle runs on all host cores)."""
     import torch
     from bench import MAX_PEAKS
     wl = synth.WORKLOADS[name]
-    g = orc.Grid.of(wl)
+    cap = MAX_PEAKS[name]
     ev = synth.make_events(wl, 0)
-    ctx = H.Context.for_workload(wl, max_peaks=MAX_PEAKS[name])
+    ctx = H.Context.for_workload(wl, max_peaks=cap)
     xt, yt, ot = H.to_device(ev)
-    say(f"full {name}: {ev.n_events} events, {ev.n_hits} hits")
+    say(f"full {name}: {ev.n_events} events, {ev.n_hits} hits, plan {ctx.batch_plan}")
     peaks, npk, keep, st = ctx.run_batch(xt, yt, ot)
     torch.cuda.synchronize()
-    npk = npk.cpu().numpy(); keep = keep.cpu().numpy(); st = st.cpu().numpy()
-    assert np.array_equal(st, np.where(npk > MAX_PEAKS[name], H.EV_PEAKS_TRUNCATED, 0))
-    sample = np.unique(np.linspace(0, ev.n_events - 1, 10).astype(int))
-    sub = ev.subset(sample)
-    pk_ref, n_ref, keep_ref = orc.run_batch(wl, sub.x, sub.y, sub.offsets, cap=MAX_PEAKS[name], n_threads=8)
-    for i, e in enumerate(sample):
-        a, b = int(ev.offsets[e]), int(ev.offsets[e + 1])
-        assert npk[e] == n_ref[i]
-        assert np.array_equal(keep[a:b], keep_ref[int(sub.offsets[i]):int(sub.offsets[i + 1])])
-        m = int(min(n_ref[i], MAX_PEAKS[name]))
-        assert np.array_equal(H.decode_peaks(peaks[e].cpu(), m), pk_ref[i, :m].astype(np.int64))
+    npk = npk.cpu().numpy().astype(np.int64)
+    keep = keep.cpu().numpy()
+    st = st.cpu().numpy()
+    peaks = peaks.cpu().numpy()
+    pk_ref, n_ref, keep_ref = orc.run_batch(wl, ev.x, ev.y, ev.offsets, cap=cap, n_threads=_host_threads())
+    assert np.array_equal(npk, n_ref)
+    assert np.array_equal(st, np.where(n_ref > cap, H.EV_PEAKS_TRUNCATED, 0))
+    assert np.array_equal(keep, keep_ref)
+    got = peaks.reshape(ev.n_events, cap, 2).view(np.uint32)
+    m = np.minimum(n_ref, cap)
+    slot = np.arange(cap)[None, :] < m[:, None]
+    assert np.array_equal(np.where(slot, got[:, :, 0] & 0xFFFF, 0), np.where(slot, pk_ref[:, :, 0], 0))
+    assert np.array_equal(np.where(slot, got[:, :, 0] >> 16, 0), np.where(slot, pk_ref[:, :, 1], 0))
+    assert np.array_equal(np.where(slot, got[:, :, 1], 0), np.where(slot, pk_ref[:, :, 2], 0))
     ctx.close()
 
 
@@ -564,33 +574,36 @@ def test_served_results_equal_results_alone(H, plain, small, split, dedup):
 
 # ----------------------------------------------------- the paper's iterative peak finder (plain path)
 def _iter_case(H, orc, ctx, g, x, y, floor_t, frac, rt, rr, cap=4096):
+    """hough_peaks_iterative on one event against the oracle (its order form, pinned against
+    the step-by-step extraction on the CPU): the list in extraction order, the true count and
+    the status, whatever the number of candidates."""
     import torch
     acc = ctx.vote(_t(x), _t(y))
     pk, npk, st = ctx.peaks_iterative(acc, cap, frac, rt, rr)
     torch.cuda.synchronize()
     acc_ref = orc.vote(g, x, y)
-    mx = int(acc_ref.max())
-    thr = max(floor_t, -(-mx * frac[0] // frac[1]))
-    over = int((acc_ref >= thr).sum()) > int(H.load().hough_max_iterative_candidates())
-    if over:
-        assert int(st.item()) == H.EV_TOO_MANY_CANDIDATES and int(npk.item()) == 0
-        return None
-    rj, rk, rc, n_ref = orc.peaks_iterative(acc_ref, floor_t, frac, rt, rr, cap)
-    assert int(st.item()) == 0
+    rj, rk, rc, n_ref = orc.peaks_iterative(acc_ref, floor_t, frac, rt, rr, max(cap, 1), sorted_form=True)
     assert int(npk.item()) == n_ref
+    assert int(st.item()) == (H.EV_PEAKS_TRUNCATED if n_ref > cap else 0)
     m = min(n_ref, cap)
     got = H.decode_peaks(pk, m)
-    want = np.stack([rj, rk, rc], 1).astype(np.int64)
+    want = np.stack([rj[:m], rk[:m], rc[:m]], 1).astype(np.int64)
     assert np.array_equal(got, want), (frac, rt, rr)
     return pk, npk, n_ref
 
 
-# (frac, r_theta, r_rho) per grid; the oracle rescans the grid for every peak it takes, so the
-# larger grids use fractions that keep the peak count moderate
+def _candidates(orc, g, x, y, floor_t, frac):
+    acc = orc.vote(g, x, y)
+    thr = max(floor_t, -(-int(acc.max()) * frac[0] // frac[1]))
+    return int((acc >= thr).sum())
+
+
+# (frac, r_theta, r_rho) per grid, the dense grid at half of the maximum among them (tens of
+# thousands of candidates: the finder walks them in several LDS chunks)
 ITER_SETTINGS = {
     "paper-1000ev-360x256": [((1, 2), 5, 5), ((1, 3), 2, 8), ((2, 3), 0, 0), ((0, 1), 1, 1),
                              ((1, 2), 40, 40), ((1, 4), 3, 0)],
-    "dense-2000ev-720x512": [((1, 2), 5, 5), ((2, 3), 0, 0), ((1, 2), 40, 40), ((1, 3), 3, 0)],
+    "dense-2000ev-720x512": [((1, 2), 5, 5), ((1, 2), 1, 1), ((2, 3), 0, 0), ((1, 2), 40, 40), ((1, 3), 3, 0)],
     "paper-1000ev-1000x1000": [((1, 2), 5, 5), ((2, 3), 0, 0), ((1, 2), 40, 40), ((2, 5), 3, 0)],
 }
 
@@ -599,38 +612,54 @@ ITER_SETTINGS = {
 def test_peaks_iterative_parity(H, orc, name):
     wl = synth.WORKLOADS[name]
     g = orc.Grid.of(wl)
-    ev = synth.make_events(wl, 0, n_events=2)
+    ev = synth.make_events(wl, 0, n_events=4 if name.startswith("dense") else 2)
     for floor_t in (wl.threshold, 2):
         ctx = H.Context.for_workload(wl, threshold=floor_t)
         for e in range(ev.n_events):
             x, y = ev.event(e)
             for frac, rt, rr in ITER_SETTINGS[name]:
-                say(f"iterative {name} floor={floor_t} event={e} frac={frac} window=({rt},{rr})")
+                say(f"iterative {name} floor={floor_t} event={e} frac={frac} window=({rt},{rr}) "
+                    f"candidates={_candidates(orc, g, x, y, floor_t, frac)}")
                 _iter_case(H, orc, ctx, g, x, y, floor_t, frac, rt, rr)
         ctx.close()
 
 
-def test_peaks_iterative_truncation_and_overflow(H, orc):
-    import torch
+def test_peaks_iterative_truncation_and_dense_candidates(H, orc):
     wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
     g = orc.Grid.of(wl)
     x, y = synth.make_events(wl, 0, n_events=1).event(0)
-    # floor 1: the first pass sees far more than the LDS holds, the relative threshold then
-    # leaves few cells, which a second pass over acc gathers
+    # floor 1: the first pass sees far more cells than the LDS key buffer holds, the relative
+    # threshold then leaves few, which one chunk gathers
     ctx = H.Context.for_workload(wl, threshold=1)
     acc_ref = orc.vote(g, x, y)
-    assert int((acc_ref >= 1).sum()) > int(H.load().hough_max_iterative_candidates())
-    out = _iter_case(H, orc, ctx, g, x, y, 1, (1, 2), 4, 4)
-    assert out is not None
-    _, _, n = out
+    assert int((acc_ref >= 1).sum()) > 16384
+    _, _, n = _iter_case(H, orc, ctx, g, x, y, 1, (1, 2), 4, 4)
     for cap in (0, 1, n - 1):
         _iter_case(H, orc, ctx, g, x, y, 1, (1, 2), 4, 4, cap=cap)
-    # a tiny relative threshold keeps too many cells: flagged, nothing listed
-    assert _iter_case(H, orc, ctx, g, x, y, 1, (1, 1000), 1, 1) is None
+    # a tiny relative threshold: every non-empty cell is a candidate (hundreds of thousands),
+    # many counts tie, and a small window takes tens of thousands of peaks
+    say(f"dense candidates: {_candidates(orc, g, x, y, 1, (1, 1000))}")
+    _iter_case(H, orc, ctx, g, x, y, 1, (1, 1000), 1, 1, cap=100000)
+    _iter_case(H, orc, ctx, g, x, y, 1, (0, 1), 0, 0, cap=50)
     with pytest.raises(H.HoughError):
         ctx.peaks_iterative(ctx.vote(_t(x), _t(y)), 16, (1, 0), 1, 1)      # frac_den == 0
     with pytest.raises(H.HoughError):
         ctx.peaks_iterative(ctx.vote(_t(x), _t(y)), 16, (1, 2), -1, 1)     # negative radius
+    ctx.close()
+
+
+def test_peaks_iterative_bitmap_in_device_memory(H, orc):
+    """A grid whose suppression bitmap does not fit LDS beside the smallest key buffer
+    (1200 x 1100 cells): the bitmap lives in device memory, per event and over a batch."""
+    g = orc.Grid(1200, 1100, -1 / 200, 1 / 200)
+    ev = synth.make_events(synth.WORKLOADS["paper-1000ev-360x256"], 5, n_events=3)
+    ctx = H.Context(1200, 1100, -1 / 200, 1 / 200, "i32", 3, 1, 20000)
+    for e in range(ev.n_events):
+        x, y = ev.event(e)
+        for frac, rt, rr in [((1, 2), 5, 5), ((1, 8), 2, 2), ((0, 1), 1, 1)]:
+            say(f"device bitmap event={e} frac={frac} candidates={_candidates(orc, g, x, y, 3, frac)}")
+            _iter_case(H, orc, ctx, g, x, y, 3, frac, rt, rr, cap=20000)
+    _check_batch_iterative(H, orc, ctx, g, ev.x, ev.y, ev.offsets, 3, 1, (1, 8), 2, 2, 20000)
     ctx.close()
 
 
@@ -984,25 +1013,20 @@ def test_random_configurations(H, orc):
 
 # ------------------------------------------------------------ the paper's finder over a batch
 def _check_batch_iterative(H, orc, ctx, g, x, y, off, T, W, frac, rt, rr, cap, dedup=False):
+    """hough_run_batch_iterative against the oracle's batch (every event, whatever its number of
+    candidates); events above the batch path's hit limit are skipped and flagged."""
     import torch
     xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
     pk, npk, keep, st = ctx.run_batch_iterative(xt, yt, ot, frac, rt, rr)
     torch.cuda.synchronize()
     E = len(off) - 1
-    pk_ref, n_ref, keep_ref = orc.run_batch_iterative(g, x, y, off, T, frac, rt, rr, W, cap, dedup=dedup)
-    limit = int(H.load().hough_max_iterative_candidates())
+    pk_ref, n_ref, keep_ref = orc.run_batch_iterative_fast(g, x, y, off, T, frac, rt, rr, W, cap, dedup=dedup,
+                                                           n_threads=_host_threads())
     npk, st, keep, p = npk.cpu().numpy()[:E], st.cpu().numpy()[:E], keep.cpu().numpy(), pk.cpu().numpy()
-    n_over = 0
     for e in range(E):
         a, b = int(off[e]), int(off[e + 1])
         if b - a > ctx.max_batch_hits:
             assert st[e] & H.EV_TOO_MANY_HITS and npk[e] == 0 and not keep[a:b].any()
-            continue
-        acc = orc.vote_dedup(g, x[a:b], y[a:b]) if dedup else orc.vote(g, x[a:b], y[a:b])
-        thr = max(T, -(-int(acc.max()) * frac[0] // frac[1]))
-        if int((acc >= thr).sum()) > limit:
-            n_over += 1
-            assert st[e] & H.EV_TOO_MANY_CANDIDATES and npk[e] == 0 and not keep[a:b].any(), e
             continue
         assert npk[e] == n_ref[e], e
         m = int(min(n_ref[e], cap))
@@ -1010,8 +1034,6 @@ def _check_batch_iterative(H, orc, ctx, g, x, y, off, T, W, frac, rt, rr, cap, d
             assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), e
         assert np.array_equal(keep[a:b], keep_ref[a:b]), e
         assert bool(st[e] & H.EV_PEAKS_TRUNCATED) == (n_ref[e] > cap), e
-        assert not st[e] & H.EV_TOO_MANY_CANDIDATES
-    return n_over
 
 
 @pytest.mark.parametrize("name,n_events,frac,rt,rr", [("paper-1000ev-360x256", 24, (1, 2), 5, 5),
@@ -1033,7 +1055,8 @@ def test_batch_iterative_parity(H, orc, name, n_events, frac, rt, rr):
 
 def test_batch_iterative_edge_events_and_per_event_path(H, orc):
     """Edge events (empty, one hit, invalid hits, out of range, too many hits), a threshold so
-    low that some events overflow the candidate limit, and equality with the per-event path."""
+    low that events have more candidates than one LDS chunk, and equality with the per-event
+    path."""
     import torch
     evs = _edge_events() + [synth.random_hits(33000, seed=4)]
     x = np.concatenate([a for a, _ in evs]).astype(np.float32)
@@ -1044,9 +1067,9 @@ def test_batch_iterative_edge_events_and_per_event_path(H, orc):
         ctx = H.Context(200, 128, -0.005, 0.005, "i32", T, 1, 256)
         g = orc.Grid(200, 128, -0.005, 0.005)
         say(f"batch iterative edges T={T} frac={frac}")
-        n_over = _check_batch_iterative(H, orc, ctx, g, x, y, off, T, 1, frac, 3, 3, 256)
+        _check_batch_iterative(H, orc, ctx, g, x, y, off, T, 1, frac, 3, 3, 256)
         if frac == (0, 1):
-            assert n_over >= 1
+            assert max(_candidates(orc, g, a, b, T, frac) for a, b in evs[:-1]) > 16384
         # the per-event path gives the same lists for every event that fits
         xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
         pk, npk, keep, st = ctx.run_batch_iterative(xt, yt, ot, frac, 3, 3)
@@ -1056,7 +1079,7 @@ def test_batch_iterative_edge_events_and_per_event_path(H, orc):
             acc = ctx.vote(_t(x[a:b]), _t(y[a:b]))
             p1, n1, s1 = ctx.peaks_iterative(acc, 256, frac, 3, 3)
             torch.cuda.synchronize()
-            assert int(n1.item()) == int(npk[e]) and int(s1.item()) == int(st[e]) & H.EV_TOO_MANY_CANDIDATES, e
+            assert int(n1.item()) == int(npk[e]) and int(s1.item()) == int(st[e]) & H.EV_PEAKS_TRUNCATED, e
             m = min(int(n1.item()), 256)
             assert torch.equal(p1[:m], pk[e, :m]), e
         ctx.close()

@@ -475,6 +475,90 @@ def test_iterative_peaks_equal_sorted_greedy_on_random_grids(orc):
         assert list(zip(pj.tolist(), pk.tolist(), pc.tolist())) == want, trial
 
 
+def test_iterative_sorted_form_equals_step_by_step(orc):
+    """The order form (one walk over the sorted candidates) takes the same cells in the same order
+    as the step-by-step extraction, on random grids of several count distributions, windows
+    (including 0 and wider than the grid), fractions and capacities."""
+    rng = np.random.default_rng(77)
+    for trial in range(200):
+        nt, nr = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+        kind = trial % 4
+        if kind == 0:
+            acc = rng.integers(0, int(rng.integers(1, 12)), size=(nt, nr))
+        elif kind == 1:                                   # few distinct counts: long ties
+            acc = rng.integers(0, 3, size=(nt, nr)) * int(rng.integers(1, 50))
+        elif kind == 2:                                   # a wide range of counts
+            acc = rng.integers(0, 5000, size=(nt, nr))
+        else:                                             # smooth blobs, as votes pile up around tracks
+            jj, kk = np.meshgrid(np.arange(nt), np.arange(nr), indexing="ij")
+            acc = np.zeros((nt, nr))
+            for _ in range(int(rng.integers(1, 6))):
+                cj, ck, h = rng.uniform(0, nt), rng.uniform(0, nr), rng.uniform(5, 60)
+                acc += h * np.exp(-((jj - cj) ** 2 + (kk - ck) ** 2) / rng.uniform(2, 30))
+            acc = np.floor(acc + rng.integers(0, 4, size=(nt, nr)))
+        acc = acc.astype(np.int32)
+        t_abs = int(rng.integers(1, 5))
+        frac = [(0, 1), (1, 2), (1, 3), (2, 3), (1, 1000)][trial % 5]
+        rt, rr = int(rng.integers(0, 6)), int(rng.integers(0, 6))
+        if trial % 17 == 0:
+            rt, rr = nt + 3, nr + 3
+        cap = [None, 1, 7][trial % 3]
+        a = orc.peaks_iterative(acc, t_abs, frac, rt, rr, cap=cap)
+        b = orc.peaks_iterative(acc, t_abs, frac, rt, rr, cap=cap, sorted_form=True)
+        assert a[3] == b[3], trial
+        for u, v in zip(a[:3], b[:3]):
+            assert np.array_equal(u, v), trial
+
+
+def test_iterative_sorted_form_equals_independent_sorted_greedy(orc):
+    rng = np.random.default_rng(78)
+    for trial in range(60):
+        nt, nr = int(rng.integers(1, 14)), int(rng.integers(1, 14))
+        acc = rng.integers(0, int(rng.integers(1, 12)), size=(nt, nr)).astype(np.int32)
+        t_abs = int(rng.integers(1, 4))
+        frac = (int(rng.integers(0, 4)), int(rng.integers(1, 5)))
+        rt, rr = int(rng.integers(0, 3)), int(rng.integers(0, 3))
+        pj, pk, pc, n = orc.peaks_iterative(acc, t_abs, frac, rt, rr, sorted_form=True)
+        assert list(zip(pj.tolist(), pk.tolist(), pc.tolist())) == _greedy_by_sorting(acc, t_abs, frac, rt, rr)
+
+
+def test_iterative_sorted_form_on_dense_events(orc):
+    """Events of the dense workload (720 x 512, 30% noise) at half of the maximum: tens of
+    thousands of cells reach the threshold; both forms agree."""
+    from paper_2607_04067_amd import synth
+    wl = synth.WORKLOADS["dense-2000ev-720x512"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 0, n_events=4)
+    for e in (2, 3):
+        x, y = ev.event(e)
+        acc = orc.vote(g, x, y)
+        thr = max(wl.threshold, -(-int(acc.max()) // 2))
+        assert int((acc >= thr).sum()) > 16384            # more than the GPU finder's largest key buffer
+        for rt, rr in ((5, 5), (1, 1)):
+            a = orc.peaks_iterative(acc, wl.threshold, (1, 2), rt, rr)
+            b = orc.peaks_iterative(acc, wl.threshold, (1, 2), rt, rr, sorted_form=True)
+            assert a[3] == b[3] and all(np.array_equal(u, v) for u, v in zip(a[:3], b[:3]))
+
+
+def test_batch_iterative_fast_equals_per_event_composition(orc):
+    """The threaded C batch (order form of the finder) equals the per-event Python composition
+    of vote, step-by-step extraction and retention, with and without duplicate suppression and
+    with a truncating capacity."""
+    from paper_2607_04067_amd import synth
+    wl = synth.WORKLOADS["paper-1000ev-360x256"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 3, n_events=6)
+    for cap, dedup, frac, rt, rr, W in [(4096, False, (1, 2), 5, 5, 1), (3, True, (1, 3), 2, 3, 2),
+                                        (0, False, (1, 2), 1, 1, 1)]:
+        a = orc.run_batch_iterative(g, ev.x, ev.y, ev.offsets, wl.threshold, frac, rt, rr, W, cap, dedup=dedup)
+        b = orc.run_batch_iterative_fast(g, ev.x, ev.y, ev.offsets, wl.threshold, frac, rt, rr, W, cap,
+                                         dedup=dedup, n_threads=4)
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+        for e in range(ev.n_events):
+            m = int(min(a[1][e], cap))
+            assert np.array_equal(a[0][e, :m], b[0][e, :m]), e
+
+
 def test_iterative_peaks_hand_built(orc):
     a = np.zeros((8, 10), np.int32)
     a[2, 3], a[2, 5], a[6, 9], a[0, 0] = 9, 8, 7, 4
