@@ -610,6 +610,61 @@ def serving(H, duration_s: float, warmup_s: float, plain_duration_s: float, pool
     return out
 
 
+PHASE_NAMES = ("pop", "setup", "vote", "peaks", "list", "retain", "finish")
+
+
+def phase_split(workload: str, plan=None, steps: int = 5) -> dict:
+    """Where a fused-kernel workgroup's time goes, from the instrumented build
+    (libhough_phases.so, include/hough_debug.h): per-phase shares of the workgroups' summed
+    time over `steps` launches, the mean workgroup's busy share of the kernel span, and the LDS
+    vote rate while voting (lane-updates per clock per CU, taking a CU's resident workgroups to
+    vote at the same time).  Must run in a process that has not loaded libhough.so."""
+    import ctypes
+    import torch
+    from paper_2607_04067_amd import build
+    from paper_2607_04067_amd import hough as H
+    L = H.load(build.PHASES_LIB)
+    L.hough_debug_phase_ticks.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    L.hough_debug_phase_ticks.restype = ctypes.c_int
+    wl = synth.WORKLOADS[workload]
+    ev = synth.make_events(wl, 0)
+    ctx = H.Context.for_workload(wl, max_peaks=MAX_PEAKS[wl.name])
+    if plan:
+        ctx.set_batch_plan(*plan)
+    xt, yt, ot = H.to_device(ev)
+    outs = ctx.run_batch(xt, yt, ot)
+    torch.cuda.synchronize()
+    ticks = (ctypes.c_uint64 * 9)()
+    khz = ctypes.c_uint32(0)
+    if L.hough_debug_phase_ticks(ticks, 9, 1, ctypes.byref(khz)) != 0:
+        raise RuntimeError("hough_debug_phase_ticks failed")
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        ctx.run_batch(xt, yt, ot, *outs, stream)
+    b.record(stream)
+    b.synchronize()
+    kern_ms = a.elapsed_time(b) / steps
+    if L.hough_debug_phase_ticks(ticks, 9, 1, ctypes.byref(khz)) != 0:
+        raise RuntimeError("hough_debug_phase_ticks failed")
+    t = [int(v) for v in ticks]
+    busy = sum(t[:7])
+    hz = khz.value * 1e3
+    p = ctx.batch_plan
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    grid = min(p["groups_per_cu"] * n_cu, ev.n_events)
+    lane_updates = t[8] * 64 * p["column_groups"]
+    vote_s = t[2] / hz
+    ctx.close()
+    return {"workload": workload, "plan": p, "steps": steps, "kernel_ms": round(kern_ms, 4),
+            "clock_khz": khz.value, "events": t[7] // steps,
+            "share": {n: round(t[i] / busy, 4) for i, n in enumerate(PHASE_NAMES)},
+            "workgroup_busy_share": round(busy / hz / (grid * steps * kern_ms / 1e3), 4),
+            "vote_lanes_per_clk_per_cu": round(lane_updates * p["groups_per_cu"] / vote_s / n_cu / CLOCK_HZ, 2),
+            "source": kernel_source_id()}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -636,6 +691,9 @@ def main(argv=None):
                          "the fused kernel's name)")
     ap.add_argument("--sweeps", action="store_true",
                     help="add the runtime-vs-events and stage-times-vs-workgroup-size studies")
+    ap.add_argument("--phases", default=None,
+                    help="comma-separated workloads: print the fused kernel's phase split from the "
+                         "instrumented build (libhough_phases.so) instead of the benchmark")
     ap.add_argument("--copy-reference-mb", type=int, default=0,
                     help="also time a plain device copy of this many MiB (HBM reference for counters)")
     args = ap.parse_args(argv)
@@ -643,6 +701,13 @@ def main(argv=None):
         print(f"bench.py measures one GPU only (the path is single-GPU; events shard across GPUs "
               f"with no exchange, see DESIGN.md); got --gpus {args.gpus}", file=sys.stderr)
         return 2
+
+    if args.phases:
+        plan = tuple(int(v) for v in args.plan.split(",")) if args.plan else None
+        for w in args.phases.split(","):
+            log(f"phase split of {w}")
+            print(json.dumps({"phases": phase_split(w, plan)}), flush=True)
+        return 0
 
     import torch
     from paper_2607_04067_amd import hough as H

@@ -46,12 +46,18 @@ _u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
 _u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
 
 
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
 def lib():
+    """The loaded oracle.  HOUGH_ORACLE_LIB names another build of the same source to load
+    instead (the sanitizer build of the tests)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        path = os.environ.get("HOUGH_ORACLE_LIB") or _LIB
+        if path == _LIB and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         c_int, c_long, c_double, c_float = ctypes.c_int, ctypes.c_long, ctypes.c_double, ctypes.c_float
         L.oracle_tables.argtypes = [c_int, c_int, c_double, c_double, _f32p, _f32p, ctypes.POINTER(c_float)]
         L.oracle_tables.restype = c_int

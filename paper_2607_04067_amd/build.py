@@ -1,7 +1,9 @@
 """Build the package's HIP libraries (gfx950) in-tree with hipcc.
 
 libhough.so        the C ABI of include/hough.h and include/hough_serve.h (the product);
-libhough_probe.so  a measurement probe (the LDS atomic rate of the vote's access pattern).
+libhough_probe.so  a measurement probe (the LDS atomic rate of the vote's access pattern);
+libhough_phases.so the product sources compiled with HOUGH_PHASE_TIMING: the fused kernel
+                   also times its phases (include/hough_debug.h).  Measurement only.
 
 Flags that matter for exactness: -ffp-contract=off (only the explicit fmaf calls fuse),
 correctly rounded single-precision division, denormals kept (no flush-to-zero) and no
@@ -57,8 +59,16 @@ def build_probe(out: str = PROBE_LIB, verbose: bool = False) -> str:
     return _compile(PROBE_SOURCES, out, verbose=verbose)
 
 
+PHASES_LIB = os.path.join(HERE, "libhough_phases.so")
+
+
+def build_phases(out: str = PHASES_LIB, verbose: bool = False) -> str:
+    """Compile the phase-timing build of the product sources (always recompiles)."""
+    return _compile(SOURCES, out, extra=("-DHOUGH_PHASE_TIMING",), verbose=verbose)
+
+
 def build_all(verbose: bool = False) -> list[str]:
-    return [build(verbose=verbose), build_probe(verbose=verbose)]
+    return [build(verbose=verbose), build_probe(verbose=verbose), build_phases(verbose=verbose)]
 
 
 if __name__ == "__main__":

@@ -89,6 +89,21 @@ size_t split_workspace_bytes(int n_theta, int n_rho, int groups, uint32_t n_even
 bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *ws, size_t bytes,
                   SplitArgs *out);
 
+// Phase slots of the instrumented build (HOUGH_PHASE_TIMING): clock ticks each workgroup of
+// the fused kernel spent per phase, summed over workgroups, plus two counts.
+enum PhaseSlot {
+    kPhasePop = 0,       // taking the next event (work counter, barrier)
+    kPhaseSetup,         // event set-up: keep bytes cleared, relative-threshold pass
+    kPhaseVote,          // steps 1-3 of a tile
+    kPhasePeaks,         // step 4: 3x3 test into peak bits
+    kPhaseList,          // listing and dilation
+    kPhaseRetain,        // step 5, and the tile cleared for the next one
+    kPhaseFinish,        // flags, n_peaks and status of the event
+    kPhaseEvents,        // count: events processed
+    kPhaseStagedHits,    // count: valid hits x theta tiles (each staged hit votes every tile column)
+    kPhaseSlots
+};
+
 // Largest-first schedule of the fused kernel: for batches of more events than resident
 // workgroups (and at most kOrderMaxEvents of them) a one-workgroup pass sorts the events by
 // hit count, largest first, in size classes of 1/64 of an octave, so that the last events

@@ -1379,6 +1379,43 @@ __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__r
 // SP: tiles with at most kTilePeaks peaks list them for the peak-list retention (the plan's
 // choice for sparse grids and the relative threshold; compiled out otherwise, where it only
 // costs).
+// Phase clock of the instrumented build (compiled with HOUGH_PHASE_TIMING; the product build
+// compiles it away): thread 0 of a workgroup reads the constant-rate clock after each workgroup
+// barrier and charges the interval to the phase that just ended; at exit it adds its totals to
+// a device array that hough_debug_phase_ticks reads.
+#ifdef HOUGH_PHASE_TIMING
+}  // namespace
+__device__ unsigned long long g_phase_ticks[kPhaseSlots];
+namespace {
+struct PhaseClock {
+    uint64_t last = 0, t[kPhaseSlots] = {};
+    __device__ __forceinline__ void start() {
+        if (threadIdx.x == 0) last = (uint64_t)wall_clock64();
+    }
+    __device__ __forceinline__ void mark(int i) {
+        if (threadIdx.x == 0) {
+            const uint64_t n = (uint64_t)wall_clock64();
+            t[i] += n - last;
+            last = n;
+        }
+    }
+    __device__ __forceinline__ void count(int i, uint64_t v) {
+        if (threadIdx.x == 0) t[i] += v;
+    }
+    __device__ __forceinline__ void flush() {
+        if (threadIdx.x == 0)
+            for (int i = 0; i < kPhaseSlots; ++i) atomicAdd(&g_phase_ticks[i], (unsigned long long)t[i]);
+    }
+};
+#else
+struct PhaseClock {
+    __device__ __forceinline__ void start() {}
+    __device__ __forceinline__ void mark(int) {}
+    __device__ __forceinline__ void count(int, uint64_t) {}
+    __device__ __forceinline__ void flush() {}
+};
+#endif
+
 template <int NW, int G, bool PER, bool SP>
 __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_batch(GridArgs g, BatchArgs a, int n_tiles, int nwords) {
     using L = Lane<G, true>;
@@ -1401,6 +1438,8 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
         reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
     for (int i = threadIdx.x; i < TW; i += NT) dil[nwords * TW + i] = 0u;
     for (int i = threadIdx.x; i < TW; i += NT) colcnt[i] = 0u;   // zero again after each listing
+    PhaseClock pc;
+    pc.start();
 
     for (;;) {
         if (threadIdx.x == 0) {
@@ -1413,9 +1452,11 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
             s_max = 0u;
         }
         __syncthreads();
+        pc.mark(kPhasePop);
         // wave-uniform values live in scalar registers
         const uint32_t e = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_event);
         if (e >= a.n_events) {
+            pc.flush();
             if (threadIdx.x == 0 && atomicAdd(a.queue + 1, 1u) == gridDim.x - 1u) {
                 __hip_atomic_store(a.queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(a.queue + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1484,6 +1525,8 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
             thr = (uint32_t)__builtin_amdgcn_readfirstlane(
                 (int)min<uint64_t>(max<uint64_t>(rel, g.threshold), 0x7fffffffull));
         }
+        pc.mark(kPhaseSetup);
+        pc.count(kPhaseEvents, 1u);
         Pending pd;
         pd.idx = 0u;
         pd.live = 0ull;
@@ -1496,6 +1539,8 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
                                                          g.dedup ? ke : nullptr);
             if (t == 0 && lane == 0 && nv) atomicAdd(&s_nvalid, nv);
             __syncthreads();
+            pc.mark(kPhaseVote);
+            if (t == 0) pc.count(kPhaseStagedHits, (uint64_t)s_nvalid * (uint64_t)n_tiles);
             for (int u = wave; u < 2 * nwords; u += NW) {
                 uint32_t m[G];
                 const bool interior = u >= 1 && (u + 1) * kPeakRows < g.n_rho;
@@ -1524,6 +1569,7 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
                 for (int i = threadIdx.x; i < nwords * TW; i += NT) dil[i] = 0u;
             }
             __syncthreads();
+            pc.mark(kPhasePeaks);
             const uint32_t base = s_npeaks;
             uint32_t np;
             if constexpr (SP)
@@ -1533,6 +1579,7 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
                 np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, pe, cap, base, ln, lane, wave,
                                               NW, nullptr, nullptr, colcnt);
             __syncthreads();
+            pc.mark(kPhaseList);
             if (threadIdx.x == 0) s_npeaks = base + np;
             for (int i = threadIdx.x; i < TW; i += NT) colcnt[i] = 0u;
             // the counts are dead: clear the tile for the next one while retention reads dil
@@ -1562,6 +1609,7 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
                 if (lane == 0 && newly) atomicAdd(&s_nkept, newly);
             }
             __syncthreads();
+            pc.mark(kPhaseRetain);
         }
         if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
         if (g.dedup) {                       // drop the later-copy bit, leaving the kept bit
@@ -1578,6 +1626,7 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
             a.status[e] = s_flags | (np > a.max_peaks ? HOUGH_EV_PEAKS_TRUNCATED : 0u);
         }
         __syncthreads();
+        pc.mark(kPhaseFinish);
     }
 }
 
@@ -2297,3 +2346,27 @@ int prepare_batch(const BatchPlan &p, size_t lds_limit) {
 }
 
 }  // namespace hough
+
+#ifdef HOUGH_PHASE_TIMING
+// include/hough_debug.h: read (and optionally clear) the phase totals of the instrumented build.
+extern "C" int hough_debug_phase_ticks(uint64_t *out, int32_t n, int32_t reset, uint32_t *clock_khz) {
+    if (!out || n < 1 || n > hough::kPhaseSlots) return HOUGH_EINVAL;
+    unsigned long long v[hough::kPhaseSlots] = {};
+    int dev = 0, khz = 0;
+    if (clock_khz && (hipGetDevice(&dev) != hipSuccess ||
+                      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess))
+        return HOUGH_EDEVICE;
+    if (clock_khz) *clock_khz = (uint32_t)khz;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpyFromSymbol(v, HIP_SYMBOL(hough::g_phase_ticks), sizeof(v)) != hipSuccess)
+        return HOUGH_EDEVICE;
+    for (int i = 0; i < n; ++i) out[i] = (uint64_t)v[i];
+    if (reset) {
+        const unsigned long long z[hough::kPhaseSlots] = {};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(hough::g_phase_ticks), z, sizeof(z)) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess)
+            return HOUGH_EDEVICE;
+    }
+    return HOUGH_OK;
+}
+#endif

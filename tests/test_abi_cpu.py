@@ -60,6 +60,37 @@ def test_serve_config_layout_matches_header():
 def test_status_strings(hough_mod):
     for code in (0, -1, -2, -3, -4):
         assert hough_mod.status_string(code) != "unknown status"
+    assert hough_mod.status_string(-6) == "unknown status"
+
+
+def test_config_reports_enomem_when_allocation_fails(hough_mod, monkeypatch):
+    """hough_config's allocation-failure path: with HOUGH_TEST_FAIL_ALLOC=1 a valid grid gets
+    HOUGH_ENOMEM and no context, before any device call (so this runs without a GPU).  Invalid
+    grids are still refused as HOUGH_EINVAL first."""
+    lib = hough_mod.load()
+    p = hough_mod.hough_params(360, 256, -0.005, 0.005, hough_mod.ACC_I32, 10, 1, 64, 0, 0)
+    bad = hough_mod.hough_params(360, 0, -0.005, 0.005, hough_mod.ACC_I32, 10, 1, 64, 0, 0)
+    ctx = ctypes.c_void_p(12345)
+    monkeypatch.setenv("HOUGH_TEST_FAIL_ALLOC", "1")
+    assert lib.hough_config(ctypes.byref(p), ctypes.byref(ctx)) == hough_mod.HOUGH_ENOMEM
+    assert not ctx.value
+    assert lib.hough_config(ctypes.byref(bad), ctypes.byref(ctx)) == hough_mod.HOUGH_EINVAL
+    assert lib.hough_config(None, ctypes.byref(ctx)) == hough_mod.HOUGH_EINVAL
+    lib.hough_destroy(None)                       # destroying nothing is a no-op
+
+
+def test_phase_timing_build_exports_its_hook_and_the_product_does_not(hough_mod):
+    """The instrumented build (libhough_phases.so) exports hough_debug_phase_ticks beside every
+    product function; libhough.so does not export it."""
+    from paper_2607_04067_amd import build
+    if not os.path.exists(build.PHASES_LIB):
+        build.build_phases()
+    phases = ctypes.CDLL(build.PHASES_LIB)
+    dbg = hough_mod.header_functions(os.path.join(ROOT, "include", "hough_debug.h"))
+    assert dbg == ["hough_debug_phase_ticks"]
+    for n in hough_mod.header_functions() + dbg:
+        assert hasattr(phases, n), n
+    assert not hasattr(hough_mod.load(), "hough_debug_phase_ticks")
 
 
 def test_peak_record_decoding(hough_mod):
