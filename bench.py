@@ -577,36 +577,50 @@ def sweeps(H, wl, ev, reps: int = 10, cpu_budget_s: float = 20.0):
 
 def serving(H, duration_s: float, warmup_s: float, plain_duration_s: float, pool_events: int = 8192):
     """Open-loop Poisson arrivals of a 50/50 mix of the 1000-event-workload and dense-workload
-    generators (pools of `pool_events` each, seed 0) through the native serving loop: served
-    (continuous batching, 8 streams) at each rate, and the plain per-event launch under the
-    same kind of trace (shorter, it saturates).  Latency = results in host memory - scheduled
-    arrival; warm-up arrivals are excluded."""
+    generators (pools of `pool_events` each, seed 0) through the native serving loop.  The
+    events' hits wait in host memory and each batch's hits go to the device when it is admitted
+    (one asynchronous copy per batch), so latency includes that transfer.  Served (continuous
+    batching, 8 streams) at each rate; the same with hits already resident in device memory at
+    one rate; and the plain per-event launch (its hits sent the same way) under the same kind of
+    trace (shorter, it saturates).  Latency = results in host memory - scheduled arrival;
+    warm-up arrivals are excluded."""
     from paper_2607_04067_amd import serve
-    pools = []
+    evs, ctxs = [], []
     for name in ("paper-1000ev-360x256", "dense-2000ev-720x512"):
         wl = synth.WORKLOADS[name]
         log(f"serving pool: {pool_events} events of {name}")
-        ev = synth.make_events(wl, 0, n_events=pool_events)
-        pools.append(serve.Pool(H.Context.for_workload(wl, max_peaks=MAX_PEAKS[name]), ev))
-    sizes = [p.batch.n_events for p in pools]
+        evs.append(synth.make_events(wl, 0, n_events=pool_events))
+        ctxs.append(H.Context.for_workload(wl, max_peaks=MAX_PEAKS[name]))
+    host = [serve.Pool(c, e, resident=False) for c, e in zip(ctxs, evs)]
+    sizes = [e.n_events for e in evs]
+    hits = sum(e.n_hits for e in evs)
     out = {"mix": "50/50 paper-1000ev-360x256 / dense-2000ev-720x512 generators",
-           "pool_events": pool_events, "n_streams": 8, "max_batch_events": 256, "small_batch_events": 64,
-           "split_batch_events": 16,
+           "pool_events": pool_events, "mean_hits": round(hits / sum(sizes), 1),
+           "n_streams": 8, "max_batch_events": 256, "small_batch_events": 64, "split_batch_events": 16,
+           "hits": "in host memory; each batch's offsets and hits sent in one async copy when admitted",
            "latency": "results (n_peaks, status, keep) in host memory minus scheduled arrival",
-           "served": {}, "plain": {}}
+           "served": {}, "served_resident": {}, "plain": {}}
+    cfg = dict(n_streams=8, max_batch_events=256, max_batch_hits=1 << 21, small_batch_events=64,
+               split_batch_events=16)
     for i, rate in enumerate(SERVE_RATES):
         tr = serve.poisson_trace(rate, warmup_s + duration_s, sizes, [0.5, 0.5], seed=100 + i)
-        res, _, _ = serve.run(pools, tr, n_streams=8, max_batch_events=256, max_batch_hits=1 << 21,
-                              small_batch_events=64, split_batch_events=16)
+        res, _, _ = serve.run(host, tr, **cfg)
         out["served"][str(rate)] = serve.summarize(tr, res, warmup_us=warmup_s * 1e6)
         log(f"served {rate}/s: {out['served'][str(rate)]}")
+    resident = [serve.Pool(c, e, resident=True) for c, e in zip(ctxs, evs)]
+    rate = SERVE_RATES[2]
+    tr = serve.poisson_trace(rate, warmup_s + duration_s / 2, sizes, [0.5, 0.5], seed=102)
+    res, _, _ = serve.run(resident, tr, **cfg)
+    out["served_resident"][str(rate)] = serve.summarize(tr, res, warmup_us=warmup_s * 1e6)
+    log(f"served (resident hits) {rate}/s: {out['served_resident'][str(rate)]}")
+    del resident
     for i, rate in enumerate(SERVE_RATES[:2]):
         tr = serve.poisson_trace(rate, plain_duration_s, sizes, [0.5, 0.5], seed=200 + i)
-        res, _, _ = serve.run(pools, tr, n_streams=8, plain=True)
+        res, _, _ = serve.run(host, tr, n_streams=8, plain=True, max_batch_hits=1 << 16)
         out["plain"][str(rate)] = serve.summarize(tr, res)
         log(f"plain {rate}/s: {out['plain'][str(rate)]}")
-    for p in pools:
-        p.ctx.close()
+    for c in ctxs:
+        c.close()
     return out
 
 
@@ -661,7 +675,8 @@ def phase_split(workload: str, plan=None, steps: int = 5) -> dict:
             "clock_khz": khz.value, "events": t[7] // steps,
             "share": {n: round(t[i] / busy, 4) for i, n in enumerate(PHASE_NAMES)},
             "workgroup_busy_share": round(busy / hz / (grid * steps * kern_ms / 1e3), 4),
-            "vote_lanes_per_clk_per_cu": round(lane_updates * p["groups_per_cu"] / vote_s / n_cu / CLOCK_HZ, 2),
+            # lane-updates per second of one voting workgroup, times the workgroups a CU holds
+            "vote_lanes_per_clk_per_cu": round(lane_updates / vote_s * p["groups_per_cu"] / CLOCK_HZ, 2),
             "source": kernel_source_id()}
 
 

@@ -66,8 +66,12 @@ extern "C" {
 /* Per-event status bits written by hough_run_batch. */
 #define HOUGH_EV_PEAKS_TRUNCATED 1u  /* more peaks than max_peaks; n_peaks holds the true count */
 #define HOUGH_EV_INVALID_HITS    2u  /* the event contains invalid hits (they were ignored)     */
-#define HOUGH_EV_TOO_MANY_HITS   4u  /* more hits than hough_max_batch_hits(): event skipped,
-                                        its n_peaks and keep are written as zero               */
+#define HOUGH_EV_TOO_MANY_HITS   4u  /* the event's offsets decrease (n_peaks written as zero,
+                                        nothing else touched), or (hough_run_batch_iterative
+                                        only) it has more than HOUGH_MAX_ITERATIVE_BATCH_HITS
+                                        hits: skipped, n_peaks and keep written as zero        */
+/* Largest event hough_run_batch_iterative processes (its accumulators hold 16-bit counts). */
+#define HOUGH_MAX_ITERATIVE_BATCH_HITS 32767u
 /* 8u: unused */
 #define HOUGH_EV_DEDUP_SKIPPED   16u /* HOUGH_FLAG_DEDUP: the event has more hits than
                                         hough_max_dedup_hits(), so every hit voted            */
@@ -75,7 +79,7 @@ extern "C" {
 /* The (theta, rho) grid and the peak / retention parameters (Sec. II). */
 typedef struct hough_params {
     int32_t n_theta;     /* theta bins on [0, pi), 1 .. 65535                                */
-    int32_t n_rho;       /* rho bins on [rho_min, rho_max), 1 .. hough_max_n_rho()           */
+    int32_t n_rho;       /* rho bins on [rho_min, rho_max), 1 .. hough_max_n_rho() (8192)    */
     double  rho_min;     /* lower rho edge (inverse length units of the hit coordinates)     */
     double  rho_max;     /* upper rho edge, > rho_min                                         */
     int32_t acc_type;    /* HOUGH_ACC_U16 or HOUGH_ACC_I32: element type of hough_vote's acc */
@@ -116,8 +120,10 @@ typedef struct hough_ctx hough_ctx;   /* opaque; owned by the library */
 /* Validate `p`, build the per-column constants C_j, S_j on the host (double libm cos/sin, each
  * rounded once to float) and upload them, and allocate the workspace on the current device.
  * On success *out receives a new context.  Returns HOUGH_EINVAL for a bad grid or parameter
- * (including a grid whose rho extent does not fit the on-chip accumulator tile),
- * HOUGH_ENOMEM / HOUGH_EDEVICE on allocation or copy failure. */
+ * (including n_rho above hough_max_n_rho()), HOUGH_ENOMEM / HOUGH_EDEVICE on allocation or
+ * copy failure.  The workspace includes the spill path's device-memory accumulators (see
+ * hough_run_batch): a few events' worth, or up to 256 MiB for a grid taller than the fused
+ * kernel's tile. */
 int hough_config(const hough_params *p, hough_ctx **out);
 
 /* Release a context (waits for nothing: the caller must have finished its work on it). */
@@ -193,7 +199,12 @@ int hough_retain(hough_ctx *ctx, const float *x, const float *y, uint32_t n_hits
  * bytes (indexed like x), computed from ALL peaks of the event even when the list is
  * truncated.  status[e]: HOUGH_EV_* bits.  n_events == 0 is valid.  A batch of more events
  * than the kernel has resident workgroups (and at most 65,536 events) is preceded by a small
- * launch that schedules the events largest first; no result depends on the schedule. */
+ * launch that schedules the events largest first; no result depends on the schedule.
+ * The fused kernel keeps an event's theta tile on chip, with 16-bit counts.  What it cannot
+ * hold -- events above 32,767 hits, or every event of a grid whose rho column is taller than
+ * its tile (hough_get_batch_plan then reports an all-zero shape) -- is computed by a spill
+ * launch after it, one event per workgroup with the accumulator in device memory (Sec. II,
+ * Sec. III), with the same results; on other grids that launch only scans the offsets. */
 int hough_run_batch(hough_ctx *ctx, const float *x, const float *y, const uint32_t *offsets,
                     uint32_t n_events, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
                     uint32_t *status, void *stream);
@@ -227,7 +238,8 @@ int hough_run_batch_gather(hough_ctx *ctx, const float *x, const float *y, const
  * event_ids and keep_offsets are both NULL (events are offsets' own, keep indexed like x) or
  * both given (gather form).  workspace: device buffer of at least
  * hough_split_workspace_bytes(ctx, n_events) bytes, 256-byte aligned, filled with zeros before
- * its first use; every call leaves it zero again.  Calls sharing a workspace must be ordered. */
+ * its first use (NULL when that size is 0); every call leaves it zero again.  Calls sharing a
+ * workspace must be ordered. */
 int hough_run_batch_split(hough_ctx *ctx, const float *x, const float *y, const uint32_t *offsets,
                           const uint32_t *event_ids, const uint32_t *keep_offsets, uint32_t n_events,
                           hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
@@ -240,7 +252,7 @@ int hough_run_batch_split(hough_ctx *ctx, const float *x, const float *y, const 
  * then retention (as hough_retain) with each event's first min(n_peaks, max_peaks) peaks.
  * peaks (device): max_peaks records per event, in extraction order; n_peaks[e] the true count;
  * keep[offsets[0] .. offsets[n_events]] one byte per hit; status[e] the HOUGH_EV_* bits.
- * Events above hough_max_batch_hits() hits are skipped as in hough_run_batch;
+ * Events above HOUGH_MAX_ITERATIVE_BATCH_HITS hits are skipped (HOUGH_EV_TOO_MANY_HITS);
  * HOUGH_FLAG_DEDUP applies.
  * Four kernel launches per call.  Accumulators go through HBM (n_theta * n_rho * 2 bytes per
  * event), so this is the per-event path's work done for the whole batch at once, not the fused
@@ -259,7 +271,8 @@ size_t hough_iterative_workspace_bytes(const hough_ctx *ctx, uint32_t n_events);
 uint32_t hough_max_dedup_hits(void);
 
 /* Workspace bytes hough_run_batch_split needs for n_events events with the context's current
- * launch shape (0 for a NULL context). */
+ * launch shape (0 for a NULL context, and for a grid without a fused kernel, whose batches need
+ * no workspace). */
 size_t hough_split_workspace_bytes(const hough_ctx *ctx, uint32_t n_events);
 
 /* Launch shape of hough_run_batch's fused kernel.  A theta tile is 64 * column_groups columns
@@ -273,19 +286,22 @@ typedef struct hough_batch_plan {
     int32_t lds_bytes;         /* LDS per workgroup (read-only)                        */
 } hough_batch_plan;
 
-/* The launch shape hough_run_batch currently uses (the library picks one at hough_config). */
+/* The launch shape hough_run_batch currently uses (the library picks one at hough_config); all
+ * zero when the grid's rho column does not fit the fused kernel's tile (every event spills). */
 int hough_get_batch_plan(const hough_ctx *ctx, hough_batch_plan *out);
 
 /* Select a launch shape (for autotuning).  groups_per_cu = 0 launches as many workgroups per CU
  * as fit; a positive value launches at most that many.  HOUGH_EINVAL if the combination is not
- * supported or does not fit the device; the context keeps its previous shape then. */
+ * supported or does not fit the device, or the grid has no fused kernel; the context keeps its
+ * previous shape then. */
 int hough_set_batch_plan(hough_ctx *ctx, int32_t waves_per_group, int32_t column_groups,
                          int32_t groups_per_cu);
 
-/* Largest number of hits per event hough_run_batch processes for this context. */
+/* Largest number of hits per event hough_run_batch processes for this context: every event
+ * (UINT32_MAX; larger events go through the spill path), 0 for a NULL context. */
 uint32_t hough_max_batch_hits(const hough_ctx *ctx);
 
-/* Largest n_rho hough_config accepts on the current device. */
+/* Largest n_rho hough_config accepts on the current device (8192 on MI355X). */
 int32_t hough_max_n_rho(void);
 
 /* Static description of a status code. */

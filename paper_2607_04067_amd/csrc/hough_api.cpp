@@ -20,7 +20,11 @@ struct hough_ctx {
     hough::IterPlan iter1;  // the iterative finder on one event (hough_peaks_iterative)
     hough::IterPlan iterb;  // ... over a batch (hough_run_batch_iterative), two workgroups per CU
     hough::GridArgs g;
-    hough::BatchPlan plan;
+    hough::BatchPlan plan;  // the fused kernel's launch shape (fused != 0)
+    int fused;              // 1: the fused kernel holds the grid's tile; 0: every batch event spills
+    uint32_t *d_spill;      // spill_wgs slices of spill_stride words (the spill path's accumulators)
+    size_t spill_stride;
+    int spill_wgs;
     size_t lds_limit;
     int n_cu;
 };
@@ -37,11 +41,34 @@ int lds_limit_bytes(int device, size_t *out) {
     return HOUGH_OK;
 }
 
+// Tallest rho axis the library takes: the per-event path's kernels need an LDS slab of at least
+// one row (hough_vote), three theta rows of the grid (hough_peaks) and one 64-row group of
+// dilated words (hough_retain); batches of grids whose column does not fit the fused kernel's
+// tile run through the spill path.
+constexpr int kMaxNRho = 8192;
+
 bool grid_fits(int n_rho, size_t limit) {
-    if (hough::vote_lds_bytes(n_rho) > limit) return false;
-    if (hough::peaks_lds_bytes(n_rho) > limit) return false;
+    if (n_rho > kMaxNRho) return false;
+    if (hough::vote_slab_rows(n_rho, limit) < 1) return false;
+    if (hough::peak_block_waves(n_rho, limit) < 2) return false;
+    const size_t words = (size_t)(n_rho + 31) / 32;
+    return 8 * 64 * 8 + words * 64 * 4 + 512 <= limit;     // hough_retain's stages and one row group
+}
+
+bool fused_fits(int n_rho, size_t limit) {
     hough::BatchPlan p;
     return hough::plan_batch(1, n_rho, 4, 1, limit, &p) == 0;
+}
+
+// Spill-path workgroups: enough to fill the chip within a 256 MiB budget where every event
+// spills, else a few for the rare events above the fused kernel's hit limit.
+constexpr size_t kSpillBudgetBytes = (size_t)256 << 20;
+int spill_workgroups(size_t stride_words, int n_cu, bool all) {
+    const size_t per = stride_words * 4;
+    size_t n = per ? kSpillBudgetBytes / per : 1;
+    if (!all && n > 4) n = 4;
+    if (n > (size_t)n_cu) n = (size_t)n_cu;
+    return n < 1 ? 1 : (int)n;
 }
 
 // Bound on u^2 + v^2 under which a hit's bin t = fma(u, C_j, fma(v, S_j, B)) lies strictly
@@ -161,8 +188,8 @@ int hough_config(const hough_params *p, hough_ctx **out) {
         delete c;
         return HOUGH_ENOMEM;
     }
-    const size_t work_bytes = 256 + 4 * (size_t)((p->n_theta + hough::kPeakRowsPerBlock - 1) /
-                                                 hough::kPeakRowsPerBlock);
+    const int peak_waves = hough::peak_block_waves(p->n_rho, limit);
+    const size_t work_bytes = 256 + 4 * (size_t)((p->n_theta + peak_waves - 1) / peak_waves);
     if (hipMalloc(&c->d_work, work_bytes) != hipSuccess) {
         (void)hipFree(c->d_tables);
         delete c;
@@ -177,6 +204,13 @@ int hough_config(const hough_params *p, hough_ctx **out) {
     c->iter1 = hough::plan_iterative(p->n_theta, p->n_rho, limit, 1);
     c->iterb = hough::plan_iterative(p->n_theta, p->n_rho, limit, 2);
     if (c->iter1.gbm && hipMalloc(&c->d_iter_bm, c->iter1.bm_bytes) != hipSuccess) {
+        hough_destroy(c);
+        return HOUGH_ENOMEM;
+    }
+    c->fused = fused_fits(p->n_rho, limit) ? 1 : 0;
+    c->spill_stride = hough::spill_stride(p->n_theta, p->n_rho);
+    c->spill_wgs = spill_workgroups(c->spill_stride, c->n_cu, !c->fused);
+    if (hipMalloc(&c->d_spill, c->spill_stride * 4 * (size_t)c->spill_wgs) != hipSuccess) {
         hough_destroy(c);
         return HOUGH_ENOMEM;
     }
@@ -198,8 +232,10 @@ int hough_config(const hough_params *p, hough_ctx **out) {
     g.rho_window = p->rho_window < p->n_rho ? p->rho_window : p->n_rho;
     g.periodic = (p->flags & HOUGH_FLAG_THETA_PERIODIC) ? 1 : 0;
     g.dedup = (p->flags & HOUGH_FLAG_DEDUP) ? 1 : 0;
+    g.vote_rows = hough::vote_slab_rows(p->n_rho, limit);
+    g.peak_waves = peak_waves;
 
-    rc = default_plan(c);
+    rc = c->fused ? default_plan(c) : HOUGH_OK;
     if (rc != HOUGH_OK) {
         hough_destroy(c);
         return rc;
@@ -214,6 +250,7 @@ void hough_destroy(hough_ctx *c) {
     if (c->d_work) (void)hipFree(c->d_work);
     if (c->d_order) (void)hipFree(c->d_order);
     if (c->d_iter_bm) (void)hipFree(c->d_iter_bm);
+    if (c->d_spill) (void)hipFree(c->d_spill);
     delete c;
 }
 
@@ -223,10 +260,14 @@ int hough_get_params(const hough_ctx *c, hough_params *out) {
     return HOUGH_OK;
 }
 
-uint32_t hough_max_batch_hits(const hough_ctx *c) { return c ? hough::kMaxBatchHits : 0u; }
+uint32_t hough_max_batch_hits(const hough_ctx *c) { return c ? UINT32_MAX : 0u; }
 
 int hough_get_batch_plan(const hough_ctx *c, hough_batch_plan *out) {
     if (!c || !out) return HOUGH_EINVAL;
+    if (!c->fused) {                      // no fused kernel for this grid: all zero
+        *out = hough_batch_plan{0, 0, 0, 0};
+        return HOUGH_OK;
+    }
     out->waves_per_group = c->plan.waves;
     out->column_groups = c->plan.groups;
     out->groups_per_cu = c->plan.per_cu;
@@ -236,7 +277,7 @@ int hough_get_batch_plan(const hough_ctx *c, hough_batch_plan *out) {
 
 int hough_set_batch_plan(hough_ctx *c, int32_t waves_per_group, int32_t column_groups,
                          int32_t groups_per_cu) {
-    if (!c || groups_per_cu < 0) return HOUGH_EINVAL;
+    if (!c || groups_per_cu < 0 || !c->fused) return HOUGH_EINVAL;
     hough::BatchPlan p;
     if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves_per_group, column_groups, c->lds_limit, &p) != 0)
         return HOUGH_EINVAL;
@@ -369,10 +410,6 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     if (!x || !y || !offsets || !n_peaks || !keep || !status) return HOUGH_EINVAL;
     if (c->p.max_peaks > 0 && !peaks) return HOUGH_EINVAL;
     if (((uintptr_t)peaks & 7u) != 0) return HOUGH_EINVAL;
-    hough::BatchPlan plan = c->plan;
-    long grid = (long)plan.per_cu * c->n_cu;
-    if (grid > (long)n_events) grid = n_events;
-    plan.grid = (int)grid;
     hough::BatchArgs a{};
     a.x = x;
     a.y = y;
@@ -389,6 +426,19 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     a.queue = c->d_work;
     a.frac_num = frac_num;
     a.frac_den = frac_den;
+    hough::SpillArgs spill{c->d_spill, c->spill_stride, c->d_work + 2, c->fused ? 0u : 1u};
+    hipError_t e = hipSuccess;
+    if (!c->fused) {
+        // the grid's column does not fit the fused kernel's tile: every event, in device memory
+        // (the split form gives the same results, so it takes the same path)
+        if (c->g.dedup) e = hough::launch_dedup(a, (hipStream_t)stream);
+        if (e == hipSuccess) e = hough::launch_spill(c->g, a, spill, c->spill_wgs, (hipStream_t)stream);
+        return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
+    }
+    hough::BatchPlan plan = c->plan;
+    long grid = (long)plan.per_cu * c->n_cu;
+    if (grid > (long)n_events) grid = n_events;
+    plan.grid = (int)grid;
     hough::SplitArgs sp;
     if (split) {
         if (!hough::split_layout(c->p.n_theta, c->p.n_rho, c->plan.groups, n_events, workspace, workspace_bytes,
@@ -399,7 +449,6 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
         long g2 = (long)c->plan.per_cu * c->n_cu;
         plan.grid = (int)(g2 < items ? g2 : items);
     }
-    hipError_t e = hipSuccess;
     if (c->g.dedup) e = hough::launch_dedup(a, (hipStream_t)stream);   // marks later copies in keep
     // more events than resident workgroups: take them largest first, so that the batch does not
     // end waiting for a large event begun last (a gathered batch keeps the caller's order)
@@ -410,6 +459,8 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     if (e == hipSuccess)
         e = split ? hough::launch_batch_split(c->g, plan, a, sp, (hipStream_t)stream)
                   : hough::launch_batch(c->g, plan, a, (hipStream_t)stream);
+    // events above the fused kernel's hit limit (flagged and skipped there), in device memory
+    if (e == hipSuccess) e = hough::launch_spill(c->g, a, spill, c->spill_wgs, (hipStream_t)stream);
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
 }
 
@@ -440,7 +491,7 @@ int hough_run_batch_gather(hough_ctx *c, const float *x, const float *y, const u
 uint32_t hough_max_dedup_hits(void) { return hough::kDedupMaxHits; }
 
 size_t hough_split_workspace_bytes(const hough_ctx *c, uint32_t n_events) {
-    if (!c) return 0;
+    if (!c || !c->fused) return 0;        // no fused kernel: the split form needs no workspace
     return hough::split_workspace_bytes(c->p.n_theta, c->p.n_rho, c->plan.groups, n_events);
 }
 
@@ -449,7 +500,7 @@ int hough_run_batch_split(hough_ctx *c, const float *x, const float *y, const ui
                           hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
                           void *workspace, size_t workspace_bytes, void *stream) {
     if (n_events && ((event_ids == nullptr) != (keep_offsets == nullptr))) return HOUGH_EINVAL;
-    if (n_events && !workspace) return HOUGH_EINVAL;
+    if (n_events && !workspace && hough_split_workspace_bytes(c, n_events) > 0) return HOUGH_EINVAL;
     return run_batch_common(c, x, y, offsets, event_ids, keep_offsets, n_events, peaks, n_peaks, keep,
                             status, stream, true, workspace, workspace_bytes);
 }

@@ -35,6 +35,8 @@ struct GridArgs {
     int32_t rho_window;
     int32_t periodic;    // theta-periodic 3x3 test (HOUGH_FLAG_THETA_PERIODIC)
     int32_t dedup;       // later copies of a hit do not vote (HOUGH_FLAG_DEDUP)
+    int32_t vote_rows;   // rho rows per LDS slab of hough_vote (n_rho when the column fits)
+    int32_t peak_waves;  // theta rows per workgroup of hough_peaks (16, 8, 4 or 2)
 };
 
 // Launch shape of the fused batch kernel (chosen by the host; see plan_batch()).
@@ -88,6 +90,21 @@ constexpr uint32_t kSplitKeepWords = (kMaxBatchHits + 31) / 32 + 1;
 size_t split_workspace_bytes(int n_theta, int n_rho, int groups, uint32_t n_events);
 bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *ws, size_t bytes,
                   SplitArgs *out);
+
+// Spill path of the batch entry points (k_spill): events processed one per workgroup with the
+// accumulator in device memory.  all = 1: every event (grids whose rho column does not fit the
+// fused kernel's tile); all = 0: only events above kMaxBatchHits (the fused and split kernels
+// flag and skip those).  Each workgroup owns `stride` 32-bit words of acc: its accumulator
+// (n_theta * n_rho), dilated retention bits (ceil(n_rho / 32) * n_theta) and column positions
+// (n_theta + 1).
+struct SpillArgs {
+    uint32_t *acc;
+    size_t stride;
+    uint32_t *queue;     // [2] work counter and exit counter (all = 1; zero between launches)
+    uint32_t all;
+};
+size_t spill_stride(int n_theta, int n_rho);
+hipError_t launch_spill(const GridArgs &g, const BatchArgs &a, const SpillArgs &sp, int n_wg, hipStream_t s);
 
 // Phase slots of the instrumented build (HOUGH_PHASE_TIMING): clock ticks each workgroup of
 // the fused kernel spent per phase, summed over workgroups, plus two counts.
@@ -147,8 +164,12 @@ hipError_t launch_batch_split(const GridArgs &g, const BatchPlan &p, const Batch
                               const SplitArgs &sp, hipStream_t s);
 
 // LDS needs and plans (hough_kernels.hip).
-size_t vote_lds_bytes(int n_rho);
-size_t peaks_lds_bytes(int n_rho);
+// LDS of hough_vote's workgroup for a slab of `rows` rho rows, and the tallest slab that fits.
+size_t vote_lds_bytes(int rows);
+int vote_slab_rows(int n_rho, size_t lds_limit);
+// LDS of hough_peaks' workgroup of `waves` theta rows, and the most rows that fit (0: none).
+size_t peaks_lds_bytes(int n_rho, int waves);
+int peak_block_waves(int n_rho, size_t lds_limit);
 hipError_t launch_track_params(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                                const hough_peak *peaks, const uint32_t *n_peaks, uint32_t cap,
                                double rho_min, double rho_max, double b_tesla, hough_track *out,

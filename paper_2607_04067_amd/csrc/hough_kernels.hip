@@ -690,56 +690,95 @@ __device__ uint32_t retain_range_peaks(const float4 *tpk, uint32_t np, const flo
 // (acc[k * n_theta + j]), so that the write-out of a tile row is one contiguous run per wave.
 constexpr int kAccU16RhoMajor = 3;
 
-// Steps 1-3 of one event into one 64-column group of acc, by one workgroup: all hits of the
-// event are swept through the group's tile.  Counters are packed two per dword, so the hits go
-// through in chunks of at most 65,535 (a count then fits 16 bits); each chunk's tile is written
-// out (first chunk) or added (later chunks) to acc, each element by the one thread that owns
-// it.  dup as for vote_range.  Returns this thread's invalid-hit flag.
+// Votes of hits [hb, he) into rows [r0, r1) of the lane's column only (a rho slab of the tile:
+// tile row k - r0 holds grid row k): every vote takes the range test r0 <= t < r1, which for an
+// integer r0 >= 0 is the same as r0 <= (int)t, so a vote lands exactly where the whole-grid rule
+// puts it, or is left to another slab.  Returns the number of valid hits seen.
+template <int NW>
+__device__ uint32_t vote_range_slab(uint32_t *tile, float2 *st, const float *x, const float *y, uint32_t hb,
+                                    uint32_t he, const Cols<1> &cl, const Lane<1, true> &ln, const GridArgs &g,
+                                    int lane, uint32_t &bad, const uint8_t *dup, int r0, int r1) {
+    const float lo_f = (float)r0, hi_f = (float)r1;
+    uint32_t n_valid = 0;
+    for (uint32_t base = hb; base < he; base += 64) {
+        const uint32_t i = base + lane;
+        bool live = i < he;
+        float xi = 0.0f, yi = 0.0f;
+        if (live) { xi = x[i]; yi = y[i]; }
+        if (dup) {
+            const bool copy = live && (dup[i] & kKeepDuplicate) != 0;
+            n_valid += (uint32_t)__popcll(__ballot(copy && valid_hit(xi, yi)));
+            live = live && !copy;
+        }
+        int slot;
+        const StageCount n = stage_values(st, xi, yi, live, g, bad, slot);
+        n_valid += n.total;
+        for (uint32_t h = 0; h < n.total; ++h) {
+            const float2 p = st[h];
+            const float t = __builtin_fmaf(p.x, cl.C[0], __builtin_fmaf(p.y, cl.S[0], cl.B[0]));
+            if (t >= lo_f && t < hi_f) lds_add(&tile[((int)t - r0) * Lane<1, true>::STRIDE + (int)ln.col[0]], ln.inc);
+        }
+        wave_sync();
+    }
+    return n_valid;
+}
+
+// Steps 1-3 of one event into one 64-column group of acc, rows [r0, r1) (the whole column, or a
+// rho slab of it when the column does not fit LDS), by one workgroup: all hits of the event are
+// swept through the group's tile.  Counters are packed two per dword, so the hits go through in
+// chunks of at most 65,535 (a count then fits 16 bits); each chunk's tile is written out (first
+// chunk) or added (later chunks) to acc, each element by the one thread that owns it.  dup as
+// for vote_range.  Returns this thread's invalid-hit flag.
 template <int NW>
 __device__ uint32_t vote_group_to_acc(const GridArgs &g, const float *__restrict__ x,
                                       const float *__restrict__ y, uint32_t n_hits, void *acc,
-                                      int acc_type, int group, const uint8_t *dup) {
+                                      int acc_type, int group, const uint8_t *dup, int r0, int r1) {
     using L = Lane<1, true>;
     constexpr uint32_t kChunk = 65535u;
     extern __shared__ __align__(16) uint32_t lds[];
-    uint32_t *tile = lds;                                                  // [(n_rho + 1) * 32]
-    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * L::STRIDE);
+    const bool whole = r0 == 0 && r1 == g.n_rho;
+    const int rows = r1 - r0;
+    uint32_t *tile = lds;                                                  // [(rows + 1) * 32]
+    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(rows + 1) * L::STRIDE);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int first = group * 64;
     const L ln(lane);
     const Cols<1> cl = load_cols<1>(g, first, lane, L::STRIDE, ln.col);
     const int j = first + lane;
-    const int kb = (int)((int64_t)g.n_rho * wave / NW), ke = (int)((int64_t)g.n_rho * (wave + 1) / NW);
+    const int kb = r0 + (int)((int64_t)rows * wave / NW), ke = r0 + (int)((int64_t)rows * (wave + 1) / NW);
     uint32_t bad = 0;
     uint32_t c0 = 0;
     do {
         const uint32_t c1 = n_hits - c0 > kChunk ? c0 + kChunk : n_hits;
-        for (int i = threadIdx.x; i < (g.n_rho + 1) * L::STRIDE / 4; i += NW * 64)
+        for (int i = threadIdx.x; i < (rows + 1) * L::STRIDE / 4; i += NW * 64)
             reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
         __syncthreads();
         const uint32_t hb = c0 + (uint32_t)((uint64_t)(c1 - c0) * wave / NW);
         const uint32_t he = c0 + (uint32_t)((uint64_t)(c1 - c0) * (wave + 1) / NW);
-        vote_range<1, true>(tile, stage + wave * 64, x, y, hb, he, cl, ln, g, lane, bad, dup);
+        if (whole)
+            vote_range<1, true>(tile, stage + wave * 64, x, y, hb, he, cl, ln, g, lane, bad, dup);
+        else
+            vote_range_slab<NW>(tile, stage + wave * 64, x, y, hb, he, cl, ln, g, lane, bad, dup, r0, r1);
         __syncthreads();
-        // write-out: lane = column (theta row of acc), wave = a slice of rho
+        // write-out: lane = column (theta row of acc), wave = a slice of the slab's rows
         if (j < g.n_theta) {
             if (acc_type == kAccU16RhoMajor) {         // acc[k][j]: a wave stores 64 adjacent cells
                 uint16_t *col = static_cast<uint16_t *>(acc) + j;
                 for (int k = kb; k < ke; ++k) {
-                    const uint32_t v = ln.count(tile[k * L::STRIDE + ln.col[0]]);
+                    const uint32_t v = ln.count(tile[(k - r0) * L::STRIDE + ln.col[0]]);
                     uint16_t *cell = col + (size_t)k * g.n_theta;
                     *cell = (uint16_t)(c0 ? *cell + v : v);
                 }
             } else if (acc_type == HOUGH_ACC_U16) {
                 uint16_t *row = static_cast<uint16_t *>(acc) + (size_t)j * g.n_rho;
                 for (int k = kb; k < ke; ++k) {
-                    const uint32_t v = ln.count(tile[k * L::STRIDE + ln.col[0]]);
+                    const uint32_t v = ln.count(tile[(k - r0) * L::STRIDE + ln.col[0]]);
                     row[k] = (uint16_t)(c0 ? row[k] + v : v);
                 }
             } else {
                 uint32_t *row = static_cast<uint32_t *>(acc) + (size_t)j * g.n_rho;
                 for (int k = kb; k < ke; ++k) {
-                    const uint32_t v = ln.count(tile[k * L::STRIDE + ln.col[0]]);
+                    const uint32_t v = ln.count(tile[(k - r0) * L::STRIDE + ln.col[0]]);
                     row[k] = c0 ? row[k] + v : v;
                 }
             }
@@ -750,41 +789,45 @@ __device__ uint32_t vote_group_to_acc(const GridArgs &g, const float *__restrict
     return bad;
 }
 
-// hough_vote: one workgroup per 64-column group.
+// hough_vote: workgroup (64-column group, rho slab of slab_rows rows).
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void k_vote(GridArgs g, const float *__restrict__ x,
                                                   const float *__restrict__ y, uint32_t n_hits,
-                                                  void *acc, int acc_type) {
-    (void)vote_group_to_acc<NW>(g, x, y, n_hits, acc, acc_type, (int)blockIdx.x, nullptr);
+                                                  void *acc, int acc_type, int slab_rows) {
+    const int r0 = (int)blockIdx.y * slab_rows, r1 = min(r0 + slab_rows, g.n_rho);
+    (void)vote_group_to_acc<NW>(g, x, y, n_hits, acc, acc_type, (int)blockIdx.x, nullptr, r0, r1);
 }
 
 // Steps 1-3 for a batch of CSR events into per-event 16-bit accumulators (the iterative
-// finder's batch form): workgroup (event, 64-column group).  Group 0 writes the event's status
-// (invalid hits, too many hits, duplicate pass skipped); the later kernels OR into it.  An event
-// above kMaxBatchHits hits, or with malformed offsets, gets no accumulator.
+// finder's batch form): workgroup (event, 64-column group, rho slab).  Workgroup (e, 0, 0) writes
+// the event's status (invalid hits, too many hits, duplicate pass skipped); the later kernels OR
+// into it.  An event above kMaxBatchHits hits, or with malformed offsets, gets no accumulator.
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void k_vote_batch(GridArgs g, const float *__restrict__ x,
                                                         const float *__restrict__ y,
                                                         const uint32_t *__restrict__ offsets,
                                                         uint16_t *acc, const uint8_t *keep,
-                                                        uint32_t *status) {
+                                                        uint32_t *status, int slab_rows) {
     const uint32_t e = blockIdx.x;
+    const bool first_wg = blockIdx.y == 0 && blockIdx.z == 0;
     const uint32_t h0 = offsets[e], h1 = offsets[e + 1];
     const bool ok = h1 >= h0 && h1 - h0 <= kMaxBatchHits;
     if (!ok) {
-        if (blockIdx.y == 0 && threadIdx.x == 0) status[e] = HOUGH_EV_TOO_MANY_HITS;
+        if (first_wg && threadIdx.x == 0) status[e] = HOUGH_EV_TOO_MANY_HITS;
         return;
     }
     const uint32_t H = h1 - h0;
     const size_t cells = (size_t)g.n_theta * (size_t)g.n_rho;
+    const int r0 = (int)blockIdx.z * slab_rows, r1 = min(r0 + slab_rows, g.n_rho);
     const uint32_t bad = vote_group_to_acc<NW>(g, x + h0, y + h0, H, acc + (size_t)e * cells, kAccU16RhoMajor,
-                                               (int)blockIdx.y, g.dedup ? keep + h0 : nullptr);
+                                               (int)blockIdx.y, g.dedup ? keep + h0 : nullptr, r0, r1);
     __shared__ uint32_t s_bad;
     if (threadIdx.x == 0) s_bad = 0u;
     __syncthreads();
     if (bad) s_bad = 1u;
     __syncthreads();
-    if (blockIdx.y == 0 && threadIdx.x == 0)
+    // every workgroup sees every hit of the event, so the first one's flags are the event's
+    if (first_wg && threadIdx.x == 0)
         status[e] = (s_bad ? HOUGH_EV_INVALID_HITS : 0u) |
                     (g.dedup && H > kDedupMaxHits ? HOUGH_EV_DEDUP_SKIPPED : 0u);
 }
@@ -1365,20 +1408,6 @@ __global__ __launch_bounds__(NW * 64) void k_retain(GridArgs g, const float *__r
     if (i < n_hits) keep[i] = (slot >= 0 && ((kept >> slot) & 1ull)) ? 1u : 0u;
 }
 
-// ------------------------------------------------------------------------ fused batch path
-// One workgroup processes one event at a time, taken from a global work counter; the event's
-// theta tiles are processed in order: vote, find peaks, list + dilate, then retain while the
-// tile is cleared for the next one.  Counters are packed two per dword (an event has at most
-// kMaxBatchHits hits, so a count fits 16 bits).  Wave w owns hits [hb, he) of the event for
-// voting and retention and writes their keep bytes itself (each lane those of its own hits,
-// the pending list aside).  Retention is skipped for the rest of the event once every valid
-// hit is kept.
-// queue[0] is the work counter and queue[1] counts workgroups that have left the loop; the
-// last one to leave (every pop has then happened) puts both back to zero for the next launch,
-// so a launch is a single kernel with no memset.
-// SP: tiles with at most kTilePeaks peaks list them for the peak-list retention (the plan's
-// choice for sparse grids and the relative threshold; compiled out otherwise, where it only
-// costs).
 // Phase clock of the instrumented build (compiled with HOUGH_PHASE_TIMING; the product build
 // compiles it away): thread 0 of a workgroup reads the constant-rate clock after each workgroup
 // barrier and charges the interval to the phase that just ended; at exit it adds its totals to
@@ -1416,6 +1445,20 @@ struct PhaseClock {
 };
 #endif
 
+// ------------------------------------------------------------------------ fused batch path
+// One workgroup processes one event at a time, taken from a global work counter; the event's
+// theta tiles are processed in order: vote, find peaks, list + dilate, then retain while the
+// tile is cleared for the next one.  Counters are packed two per dword (an event has at most
+// kMaxBatchHits hits, so a count fits 16 bits).  Wave w owns hits [hb, he) of the event for
+// voting and retention and writes their keep bytes itself (each lane those of its own hits,
+// the pending list aside).  Retention is skipped for the rest of the event once every valid
+// hit is kept.
+// queue[0] is the work counter and queue[1] counts workgroups that have left the loop; the
+// last one to leave (every pop has then happened) puts both back to zero for the next launch,
+// so a launch is a single kernel with no memset.
+// SP: tiles with at most kTilePeaks peaks list them for the peak-list retention (the plan's
+// choice for sparse grids and the relative threshold; compiled out otherwise, where it only
+// costs).
 template <int NW, int G, bool PER, bool SP>
 __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_batch(GridArgs g, BatchArgs a, int n_tiles, int nwords) {
     using L = Lane<G, true>;
@@ -1833,6 +1876,268 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
     }
 }
 
+// ------------------------------------------------------------ spill path (device-memory accumulator)
+// Events whose accumulator the fused kernel cannot hold on chip: every event of a grid whose rho
+// column is taller than the fused kernel's LDS tile, and events above kMaxBatchHits hits on any
+// grid (counts beyond 16 bits).  One workgroup processes one event at a time in device memory,
+// as the paper's own accumulator lives there (Sec. II, Sec. III):
+//   - a 32-bit accumulator stored rho-major, acc[k * n_theta + j], so that the 64 columns a wave
+//     votes for one hit land in a few cache lines (neighbouring columns' bins differ little);
+//     votes are device-scope atomic adds;
+//   - the 3x3 test slides a 3 x 3 window down each lane's column (lane = column), once to count
+//     each column's peaks and once to list them at their raster-order position, marking the
+//     dilated retention bits D[w * n_theta + j] (bit b: a peak of column j within rho_window rows
+//     of row 32w + b) of its own column as it goes;
+//   - retention maps every hit again (lane = hit) and looks its bin up in D column by column.
+// The work is a full pass over the grid per step, so this path is for what the fused kernel
+// cannot take, not a fast path.
+constexpr int kSpillWaves = 16;
+constexpr int kSpillThreads = kSpillWaves * 64;
+
+// Count of cell (column j, row k) of an event's accumulator, 0 outside the grid; on a
+// theta-periodic grid the column left of 0 is column n_theta - 1 and the column right of
+// n_theta - 1 is column 0, both with rho reversed.
+__device__ __forceinline__ uint32_t spill_cell(const uint32_t *acc, const GridArgs &g, int j, int k) {
+    if (g.periodic && (j == -1 || j == g.n_theta)) {
+        j = j < 0 ? g.n_theta - 1 : 0;
+        k = g.n_rho - 1 - k;
+    }
+    if (j < 0 || j >= g.n_theta || k < 0 || k >= g.n_rho) return 0u;
+    return acc[(size_t)k * g.n_theta + j];
+}
+
+// Release this workgroup's device-memory writes and atomics, then make everyone's visible to it.
+__device__ __forceinline__ void spill_sync() {
+    __threadfence();
+    __syncthreads();
+    __threadfence();
+}
+
+// One pass of step 4 over the lane's column j (all rows): calls f(k, count) for every peak.
+// Raster order: the column before (j - 1) and the row above come first, except that on a
+// periodic grid the wrapped column left of column 0 comes later and the one right of the last
+// column earlier.
+template <typename F>
+__device__ __forceinline__ void spill_column_peaks(const uint32_t *acc, const GridArgs &g, int j, uint32_t thr,
+                                                   F &&f) {
+    const bool left_later = g.periodic && j == 0, right_earlier = g.periodic && j == g.n_theta - 1;
+    // window rows k - 1, k, k + 1 of columns j - 1, j, j + 1
+    uint32_t l0 = 0u, c0 = 0u, r0 = 0u;
+    uint32_t l1 = spill_cell(acc, g, j - 1, 0), c1 = spill_cell(acc, g, j, 0), r1 = spill_cell(acc, g, j + 1, 0);
+#pragma unroll 1
+    for (int k = 0; k < g.n_rho; ++k) {
+        const uint32_t l2 = spill_cell(acc, g, j - 1, k + 1), c2 = spill_cell(acc, g, j, k + 1),
+                       r2 = spill_cell(acc, g, j + 1, k + 1);
+        if (c1 >= thr) {
+            const uint32_t lm = max(max(l0, l1), l2), rm = max(max(r0, r1), r2);
+            const uint32_t before = max(max(left_later ? 0u : lm, right_earlier ? rm : 0u), c0);
+            const uint32_t after = max(max(left_later ? lm : 0u, right_earlier ? 0u : rm), c2);
+            if (c1 >= max(before + 1u, after)) f(k, c1);
+        }
+        l0 = l1; l1 = l2;
+        c0 = c1; c1 = c2;
+        r0 = r1; r1 = r2;
+    }
+}
+
+__global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a, SpillArgs sp) {
+    __shared__ float2 stage[kSpillWaves][64];
+    __shared__ uint32_t s_event, s_flags, s_max, s_n, s_list[kSpillThreads], s_part[kSpillThreads];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t cells = (size_t)g.n_theta * (size_t)g.n_rho;
+    const int words = (g.n_rho + 31) / 32;
+    uint32_t *acc = sp.acc + (size_t)blockIdx.x * sp.stride;
+    uint32_t *dil = acc + cells;                          // [words][n_theta]
+    uint32_t *colpos = dil + (size_t)words * g.n_theta;   // [n_theta + 1]
+
+    // Every value that steers control flow around a barrier is wave-uniform (scalar), and an
+    // event that is skipped passes a barrier before it returns, as a processed one does at its
+    // end.  Without that barrier the compiler sends the lanes other than thread 0 straight
+    // from the return to the next event's first barrier (the counter read is thread 0's alone),
+    // so a wave splits: thread 0's lane waits to take the counter while the rest of the wave,
+    // and the other waves, go round the barriers again on the old event index.
+    auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
+    auto process = [&](uint32_t e) {
+        const uint32_t pe_id = uni(a.ids ? a.ids[e] : e);
+        const uint32_t h0 = uni(a.offsets[pe_id]), h1 = uni(a.offsets[pe_id + 1]);
+        if (h1 <= h0) {                      // malformed offsets: touch nothing but the counters
+            if (threadIdx.x == 0) { a.n_peaks[e] = 0u; a.status[e] = h1 < h0 ? HOUGH_EV_TOO_MANY_HITS : 0u; }
+            __syncthreads();
+            return;
+        }
+        const uint32_t H = h1 - h0;
+        uint8_t *ke = a.keep + (a.ids ? uni(a.keep_offsets[e]) : h0);
+        const float *xe = a.x + h0, *ye = a.y + h0;
+        // the duplicate pass marked later copies in the keep bytes of events up to kDedupMaxHits
+        const bool dup = g.dedup && H <= kDedupMaxHits;
+        if (threadIdx.x == 0) {
+            s_flags = (g.dedup && H > kDedupMaxHits) ? HOUGH_EV_DEDUP_SKIPPED : 0u;
+            s_max = 0u;
+        }
+        if (!dup)
+            for (uint32_t i = threadIdx.x; i < H; i += kSpillThreads) ke[i] = 0u;
+        for (size_t i = threadIdx.x; i < cells; i += kSpillThreads) acc[i] = 0u;
+        for (size_t i = threadIdx.x; i < (size_t)words * g.n_theta; i += kSpillThreads) dil[i] = 0u;
+        spill_sync();
+
+        // steps 1-3: wave w maps its slice of the hits, 64 at a time, and votes each valid hit
+        // (not a later copy) into every column, lane = column within groups of 64
+        uint32_t bad = 0;
+        const uint32_t hb = (uint32_t)((uint64_t)H * wave / kSpillWaves);
+        const uint32_t he = (uint32_t)((uint64_t)H * (wave + 1) / kSpillWaves);
+        for (uint32_t base = hb; base < he; base += 64) {
+            const uint32_t i = base + lane;
+            bool live = i < he;
+            if (live && dup && (ke[i] & kKeepDuplicate)) live = false;
+            float u = 0.0f, v = 0.0f;
+            const bool ok = conformal(live ? xe[i] : 0.0f, live ? ye[i] : 0.0f, u, v);
+            if (live && !ok) bad = 1u;
+            const uint64_t m = __ballot(live && ok);
+            if (live && ok) stage[wave][mbcnt(m)] = make_float2(u, v);
+            wave_sync();
+            const uint32_t n = (uint32_t)__popcll(m);
+            for (int j0 = 0; j0 < g.n_theta; j0 += 64) {
+                const int j = j0 + lane;
+                const bool in = j < g.n_theta;
+                const float C = in ? g.C[j] : 0.0f, S = in ? g.S[j] : 0.0f;
+#pragma unroll 4
+                for (uint32_t h = 0; h < n; ++h) {
+                    const float2 p = stage[wave][h];
+                    const float t = __builtin_fmaf(p.x, C, __builtin_fmaf(p.y, S, g.Bf));
+                    if (in && t >= 0.0f && t < g.nrho_f)
+                        __hip_atomic_fetch_add(acc + (size_t)(int)t * g.n_theta + j, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            wave_sync();
+        }
+        if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
+        spill_sync();
+
+        uint32_t thr = g.threshold;
+        if (a.frac_den) {                    // relative threshold: the event's largest count first
+            uint32_t m = 0;
+            for (size_t i = threadIdx.x; i < cells; i += kSpillThreads) m = max(m, acc[i]);
+            m = wave_max(m);
+            if (lane == 0) atomicMax(&s_max, m);
+            __syncthreads();
+            const uint64_t rel = ((uint64_t)uni(s_max) * a.frac_num + a.frac_den - 1u) / a.frac_den;
+            thr = (uint32_t)min<uint64_t>(max<uint64_t>(rel, g.threshold), 0x7fffffffull);
+        }
+
+        // step 4, first pass: each column's peak count
+        for (int j = threadIdx.x; j < g.n_theta; j += kSpillThreads) {
+            uint32_t c = 0;
+            spill_column_peaks(acc, g, j, thr, [&](int, uint32_t) { ++c; });
+            colpos[j] = c;
+        }
+        spill_sync();
+        // exclusive prefix over the columns (raster order is column-major): each thread sums a
+        // run of columns, the runs' totals are scanned, then each run is scanned again
+        const int per = (g.n_theta + kSpillThreads - 1) / kSpillThreads;
+        const int c0 = threadIdx.x * per, c1 = min(c0 + per, g.n_theta);
+        uint32_t part = 0;
+        for (int j = c0; j < c1; ++j) part += colpos[j];
+        s_part[threadIdx.x] = part;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t run = 0;
+            for (int t = 0; t < kSpillThreads; ++t) {
+                const uint32_t v = s_part[t];
+                s_part[t] = run;
+                run += v;
+            }
+            s_n = run;
+        }
+        __syncthreads();
+        uint32_t run = s_part[threadIdx.x];
+        for (int j = c0; j < c1; ++j) {
+            const uint32_t v = colpos[j];
+            colpos[j] = run;
+            run += v;
+        }
+        spill_sync();
+        // second pass: list each column's peaks in row order at its position, and mark the rows
+        // within rho_window of each peak in the column's dilated bits
+        hough_peak *pe = a.peaks ? a.peaks + (size_t)e * a.max_peaks : nullptr;
+        const uint32_t cap = pe ? a.max_peaks : 0u;
+        for (int j = threadIdx.x; j < g.n_theta; j += kSpillThreads) {
+            uint32_t pos = colpos[j];
+            spill_column_peaks(acc, g, j, thr, [&](int k, uint32_t c) {
+                if (pos < cap) store_peak(pe + pos, (uint32_t)j, (uint32_t)k, c);
+                ++pos;
+                const int lo = max(k - g.rho_window, 0), hi = min(k + g.rho_window, g.n_rho - 1);
+                for (int wd = lo >> 5; wd <= (hi >> 5); ++wd) {
+                    const int b0 = max(lo, wd * 32) - wd * 32, b1 = min(hi, wd * 32 + 31) - wd * 32;
+                    const uint32_t msk = (b1 == 31 ? 0xffffffffu : ((1u << (b1 + 1)) - 1u)) & ~((1u << b0) - 1u);
+                    uint32_t *w = dil + (size_t)wd * g.n_theta + j;   // this lane's column only
+                    *w |= msk;
+                }
+            });
+        }
+        spill_sync();
+
+        // step 5: lane = hit; a hit is kept once its bin in some column falls on a dilated bit
+        const uint32_t n_peaks = uni(s_n);
+        if (n_peaks > 0) {
+            for (uint32_t base = (uint32_t)wave * 64; base < H; base += kSpillThreads) {
+                const uint32_t i = base + lane;
+                float u = 0.0f, v = 0.0f;
+                bool want = i < H && conformal(xe[i], ye[i], u, v);
+                bool kept = false;
+                for (int j = 0; j < g.n_theta && __ballot(want && !kept); ++j) {
+                    const float t = __builtin_fmaf(u, g.C[j], __builtin_fmaf(v, g.S[j], g.Bf));
+                    if (want && !kept && t >= 0.0f && t < g.nrho_f) {
+                        const int k = (int)t;
+                        kept = (dil[(size_t)(k >> 5) * g.n_theta + j] >> (k & 31)) & 1u;
+                    }
+                }
+                if (i < H) ke[i] = kept ? 1u : 0u;
+            }
+        } else if (dup) {
+            for (uint32_t i = threadIdx.x; i < H; i += kSpillThreads) ke[i] = 0u;
+        }
+        spill_sync();
+        if (threadIdx.x == 0) {
+            a.n_peaks[e] = n_peaks;
+            a.status[e] = s_flags | (n_peaks > a.max_peaks ? HOUGH_EV_PEAKS_TRUNCATED : 0u);
+        }
+        __syncthreads();
+    };
+
+    if (sp.all) {
+        for (;;) {
+            if (threadIdx.x == 0) s_event = atomicAdd(sp.queue, 1u);
+            __syncthreads();
+            const uint32_t e = uni(s_event);
+            __syncthreads();
+            if (e >= a.n_events) break;
+            process(e);
+        }
+        if (threadIdx.x == 0 && atomicAdd(sp.queue + 1, 1u) == gridDim.x - 1u) {
+            __hip_atomic_store(sp.queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(sp.queue + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    // only the events above kMaxBatchHits: the workgroups split the batch into blocks of
+    // kSpillThreads events and pick those out of each block
+    for (uint32_t b0 = blockIdx.x * kSpillThreads; b0 < a.n_events; b0 += gridDim.x * kSpillThreads) {
+        if (threadIdx.x == 0) s_n = 0u;
+        __syncthreads();
+        const uint32_t e = b0 + threadIdx.x;
+        if (e < a.n_events) {
+            const uint32_t pe_id = a.ids ? a.ids[e] : e;
+            const uint32_t h0 = a.offsets[pe_id], h1 = a.offsets[pe_id + 1];
+            if (h1 >= h0 && h1 - h0 > kMaxBatchHits) s_list[atomicAdd(&s_n, 1u)] = e;
+        }
+        __syncthreads();
+        const uint32_t n = uni(s_n);
+        for (uint32_t p = 0; p < n; ++p) process(uni(s_list[p]));   // events are independent: any order
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------ duplicate pass (HOUGH_FLAG_DEDUP)
 // One workgroup per event.  Open addressing in LDS keyed by the bits of (x, y): every slot ends
 // holding the smallest event-local index of its key (compare-and-swap into an empty slot, atomic
@@ -1994,11 +2299,24 @@ void allow_lds(K kernel) {
 
 }  // namespace
 
-size_t vote_lds_bytes(int n_rho) {
-    return (size_t)(n_rho + 1) * 32 * 4 + (size_t)kVoteWaves * kStageBytes + 256;
+size_t vote_lds_bytes(int rows) {
+    return (size_t)(rows + 1) * 32 * 4 + (size_t)kVoteWaves * kStageBytes + 256;
 }
 
-size_t peaks_lds_bytes(int n_rho) { return (size_t)(kPeakWaves + 2) * n_rho * 4 + 256; }
+int vote_slab_rows(int n_rho, size_t lds_limit) {
+    const size_t fixed = (size_t)kVoteWaves * kStageBytes + 256 + 256;    // stages, slack, static LDS
+    if (lds_limit <= fixed + 2 * 128) return 0;
+    const long rows = (long)((lds_limit - fixed) / 128) - 1;
+    return (int)(rows < n_rho ? rows : n_rho);
+}
+
+size_t peaks_lds_bytes(int n_rho, int waves) { return (size_t)(waves + 2) * n_rho * 4 + 256; }
+
+int peak_block_waves(int n_rho, size_t lds_limit) {
+    for (int w = kPeakWaves; w >= 2; w >>= 1)
+        if (peaks_lds_bytes(n_rho, w) + 256 <= lds_limit) return w;
+    return 0;
+}
 
 size_t batch_lds_bytes(int n_rho, int waves, int groups) {
     const size_t tw = 64u * groups, nwords = (size_t)(n_rho + 31) / 32;
@@ -2028,6 +2346,18 @@ hipError_t launch_order(const uint32_t *offsets, uint32_t n_events, uint32_t *or
     return hipGetLastError();
 }
 
+size_t spill_stride(int n_theta, int n_rho) {
+    const size_t words = (size_t)(n_rho + 31) / 32;
+    const size_t n = (size_t)n_theta * n_rho + words * n_theta + n_theta + 1;
+    return (n + 63) & ~(size_t)63;                  // each workgroup's slice on a 256-byte boundary
+}
+
+hipError_t launch_spill(const GridArgs &g, const BatchArgs &a, const SpillArgs &sp, int n_wg, hipStream_t s) {
+    if (a.n_events == 0 || n_wg < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_spill, dim3(n_wg), dim3(kSpillThreads), 0, s, g, a, sp);
+    return hipGetLastError();
+}
+
 hipError_t launch_dedup(const BatchArgs &a, hipStream_t s) {
     if (a.n_events == 0) return hipSuccess;
     hipLaunchKernelGGL(k_dedup, dim3(a.n_events), dim3(kDedupThreads), 0, s, a);
@@ -2036,39 +2366,49 @@ hipError_t launch_dedup(const BatchArgs &a, hipStream_t s) {
 
 hipError_t launch_vote(const GridArgs &g, const float *x, const float *y, uint32_t n_hits,
                        void *acc, int acc_type, hipStream_t s) {
-    const size_t lds = vote_lds_bytes(g.n_rho);
+    if (g.vote_rows < 1) return hipErrorInvalidValue;
+    const size_t lds = vote_lds_bytes(g.vote_rows);
     static const bool lds_ok = (allow_lds(k_vote<kVoteWaves>), true);
     (void)lds_ok;
-    const int blocks = (g.n_theta + 63) / 64;
-    hipLaunchKernelGGL(k_vote<kVoteWaves>, dim3(blocks), dim3(kVoteWaves * 64), lds, s, g, x, y,
-                       n_hits, acc, acc_type);
+    const int groups = (g.n_theta + 63) / 64, slabs = (g.n_rho + g.vote_rows - 1) / g.vote_rows;
+    hipLaunchKernelGGL(k_vote<kVoteWaves>, dim3(groups, slabs), dim3(kVoteWaves * 64), lds, s, g, x, y,
+                       n_hits, acc, acc_type, g.vote_rows);
     return hipGetLastError();
 }
 
-hipError_t launch_peaks(const GridArgs &g, const void *acc, int acc_type, hough_peak *peaks,
-                        uint32_t cap, uint32_t *n_peaks, uint32_t *counts, hipStream_t s) {
-    const size_t lds = peaks_lds_bytes(g.n_rho);
-    const int blocks = (g.n_theta + kPeakWaves - 1) / kPeakWaves;
-    if (acc_type == HOUGH_ACC_U16) {
-        static const bool lds_ok = (allow_lds(k_peaks<kPeakWaves, uint16_t, false>),
-                                    allow_lds(k_peaks<kPeakWaves, uint16_t, true>), true);
-        (void)lds_ok;
-        const uint16_t *a = static_cast<const uint16_t *>(acc);
-        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint16_t, false>), dim3(blocks), dim3(kPeakWaves * 64), lds, s, g,
-                           a, peaks, cap, n_peaks, counts);
-        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint16_t, true>), dim3(blocks), dim3(kPeakWaves * 64), lds, s, g,
-                           a, peaks, cap, n_peaks, counts);
-    } else {
-        static const bool lds_ok = (allow_lds(k_peaks<kPeakWaves, uint32_t, false>),
-                                    allow_lds(k_peaks<kPeakWaves, uint32_t, true>), true);
-        (void)lds_ok;
-        const uint32_t *a = static_cast<const uint32_t *>(acc);
-        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint32_t, false>), dim3(blocks), dim3(kPeakWaves * 64), lds, s, g,
-                           a, peaks, cap, n_peaks, counts);
-        hipLaunchKernelGGL((k_peaks<kPeakWaves, uint32_t, true>), dim3(blocks), dim3(kPeakWaves * 64), lds, s, g,
-                           a, peaks, cap, n_peaks, counts);
+template <int NW, typename T>
+static void launch_peaks_t(const GridArgs &g, const T *acc, hough_peak *peaks, uint32_t cap, uint32_t *n_peaks,
+                           uint32_t *counts, hipStream_t s) {
+    static const bool lds_ok = (allow_lds(k_peaks<NW, T, false>), allow_lds(k_peaks<NW, T, true>), true);
+    (void)lds_ok;
+    const size_t lds = peaks_lds_bytes(g.n_rho, NW);
+    const int blocks = (g.n_theta + NW - 1) / NW;
+    hipLaunchKernelGGL((k_peaks<NW, T, false>), dim3(blocks), dim3(NW * 64), lds, s, g, acc, peaks, cap, n_peaks,
+                       counts);
+    hipLaunchKernelGGL((k_peaks<NW, T, true>), dim3(blocks), dim3(NW * 64), lds, s, g, acc, peaks, cap, n_peaks,
+                       counts);
+}
+
+template <typename T>
+static hipError_t launch_peaks_w(const GridArgs &g, const T *acc, hough_peak *peaks, uint32_t cap,
+                                 uint32_t *n_peaks, uint32_t *counts, hipStream_t s) {
+    switch (g.peak_waves) {
+        case 16: launch_peaks_t<16, T>(g, acc, peaks, cap, n_peaks, counts, s); break;
+        case 8: launch_peaks_t<8, T>(g, acc, peaks, cap, n_peaks, counts, s); break;
+        case 4: launch_peaks_t<4, T>(g, acc, peaks, cap, n_peaks, counts, s); break;
+        case 2: launch_peaks_t<2, T>(g, acc, peaks, cap, n_peaks, counts, s); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// hough_peaks: workgroups of g.peak_waves theta rows (fewer for tall grids, whose rows take
+// more LDS); counts holds one counter per workgroup.
+hipError_t launch_peaks(const GridArgs &g, const void *acc, int acc_type, hough_peak *peaks,
+                        uint32_t cap, uint32_t *n_peaks, uint32_t *counts, hipStream_t s) {
+    if (acc_type == HOUGH_ACC_U16)
+        return launch_peaks_w<uint16_t>(g, static_cast<const uint16_t *>(acc), peaks, cap, n_peaks, counts, s);
+    return launch_peaks_w<uint32_t>(g, static_cast<const uint32_t *>(acc), peaks, cap, n_peaks, counts, s);
 }
 
 // Key buffer and bitmap placement of the iterative finder: the largest key buffer (a power of two
@@ -2172,12 +2512,13 @@ hipError_t launch_batch_iterative(const GridArgs &g, const BatchArgs &a, uint16_
         if (e != hipSuccess) return e;
     }
     {
-        const size_t lds = vote_lds_bytes(g.n_rho);
+        if (g.vote_rows < 1) return hipErrorInvalidValue;
+        const size_t lds = vote_lds_bytes(g.vote_rows);
         static const bool lds_ok = (allow_lds(k_vote_batch<kVoteWaves>), true);
         (void)lds_ok;
-        const int groups = (g.n_theta + 63) / 64;
-        hipLaunchKernelGGL(k_vote_batch<kVoteWaves>, dim3(a.n_events, groups), dim3(kVoteWaves * 64), lds, s, g,
-                           a.x, a.y, a.offsets, acc, a.keep, a.status);
+        const int groups = (g.n_theta + 63) / 64, slabs = (g.n_rho + g.vote_rows - 1) / g.vote_rows;
+        hipLaunchKernelGGL(k_vote_batch<kVoteWaves>, dim3(a.n_events, groups, slabs), dim3(kVoteWaves * 64), lds,
+                           s, g, a.x, a.y, a.offsets, acc, a.keep, a.status, g.vote_rows);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     launch_iter_t<uint16_t>(g, acc, frac_num, frac_den, r_theta, r_rho, a.peaks, a.max_peaks, a.n_peaks, a.status,

@@ -404,8 +404,15 @@ class Context:
         """run_batch's (or, with event_ids and keep_offsets, run_batch_gather's) results, computed
         with each event's theta tiles on separate workgroups (the latency form).
         workspace: from split_workspace (kept zero between calls)."""
+        return self._split(x, y, offsets, workspace, peaks, n_peaks, keep, status, event_ids, keep_offsets,
+                           keep_size, stream)
+
+    def _split(self, x, y, offsets, workspace, peaks, n_peaks, keep, status, event_ids, keep_offsets,
+               keep_size, stream):
         if (event_ids is None) != (keep_offsets is None):
             raise ValueError("event_ids and keep_offsets go together")
+        if event_ids is not None and keep_size is None:
+            raise ValueError("the gather form needs keep_size (the keep bytes the batch writes)")
         _hits(x, y, keep, x.numel() if event_ids is None else keep_size)
         E = offsets.numel() - 1 if event_ids is None else event_ids.numel()
         mp = self.params.max_peaks
@@ -431,10 +438,10 @@ class Context:
         pp = _dev(peaks, torch.int32, "peaks", 2 * E * mp) if mp > 0 else 0
         pn = _dev(n_peaks, torch.int32, "n_peaks", E)
         ps = _dev(status, torch.int32, "status", E)
-        pw = _dev(workspace, torch.uint8, "workspace")
         pk = self._ptr_or_dummy(keep, torch.uint8, "keep")
         px = self._ptr_or_dummy(x, torch.float32, "x")
         py = self._ptr_or_dummy(y, torch.float32, "y")
+        pw = _dev(workspace, torch.uint8, "workspace")
         _check(self._lib.hough_run_batch_split(self._ctx, px, py, po, pi, pko, E, pp, pn, pk, ps, pw,
                                                workspace.numel(), _stream(stream)), "hough_run_batch_split")
         return peaks, n_peaks, keep, status
@@ -446,6 +453,8 @@ class Context:
         """hough_run_batch over pool events `event_ids` (int32, uint32 values); event e's keep
         bytes start at keep_offsets[e] (int32).  keep_size: bytes of keep the batch writes (checked
         against keep when both are given).  Returns (peaks, n_peaks, keep, status)."""
+        if keep_size is None:
+            raise ValueError("the gather form needs keep_size (the keep bytes the batch writes)")
         _hits(x, y, keep, keep_size)
         E = event_ids.numel()
         mp = self.params.max_peaks

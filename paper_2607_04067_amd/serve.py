@@ -1,9 +1,12 @@
 """Serving: an open-loop arrival trace run through the native request loop (hough_serve_run).
 
-Events of each kind sit in a device-resident CSR pool (one per grid).  A trace draws arrival
-times from a Poisson process and, per arrival, a kind (Bernoulli mix) and a pool event; the C++
-loop admits, batches, launches and completes them (see include/hough_serve.h).  This module only
-builds the inputs, calls the library and summarises the per-request timings.
+Events of each kind sit in a CSR pool (one per grid), either resident in device memory or in
+host memory (then each batch's hits are sent to the device when it is admitted).  A trace draws
+arrival times from a Poisson process and, per arrival, a kind (Bernoulli mix) and a pool event;
+the C++ loop admits, batches, launches and completes them (see include/hough_serve.h).
+simulate() replays the same scheduling against a cost model on a simulated clock
+(hough_serve_simulate), without a device.  This module only builds the inputs, calls the
+library and summarises the per-request timings.
 """
 from __future__ import annotations
 
@@ -17,7 +20,12 @@ from . import hough
 
 class hough_serve_pool(ctypes.Structure):
     _fields_ = [("ctx", ctypes.c_void_p), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
-                ("offsets", ctypes.c_void_p), ("host_offsets", ctypes.c_void_p), ("n_events", ctypes.c_uint32)]
+                ("offsets", ctypes.c_void_p), ("host_offsets", ctypes.c_void_p), ("n_events", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("host_x", ctypes.c_void_p), ("host_y", ctypes.c_void_p)]
+
+
+class hough_serve_model(ctypes.Structure):
+    _fields_ = [("fixed_us", ctypes.c_double), ("per_event_us", ctypes.c_double), ("per_hit_us", ctypes.c_double)]
 
 
 class hough_serve_config(ctypes.Structure):
@@ -29,7 +37,7 @@ class hough_serve_config(ctypes.Structure):
 
 REQ_DTYPE = np.dtype([("arrival_us", "<f8"), ("kind", "<i4"), ("event", "<u4")])
 RES_DTYPE = np.dtype([("launch_us", "<f8"), ("done_us", "<f8"), ("n_peaks", "<u4"), ("status", "<u4"),
-                      ("batch_events", "<u4"), ("pad", "<u4")])
+                      ("batch_events", "<u4"), ("slot", "<u4")])
 
 
 def _lib():
@@ -39,22 +47,37 @@ def _lib():
                                       ctypes.POINTER(hough_serve_config), ctypes.c_void_p, ctypes.c_uint32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
         L.hough_serve_run.restype = ctypes.c_int
+        L.hough_serve_simulate.argtypes = [ctypes.c_int32, ctypes.POINTER(hough_serve_config), ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(hough_serve_model),
+                                           ctypes.c_void_p]
+        L.hough_serve_simulate.restype = ctypes.c_int
         L._serve_ready = True
     return L
 
 
 class Pool:
-    """A resident event pool: device hits + offsets, a host copy of the offsets, and its context."""
+    """An event pool and its context.  resident=True: hits and offsets in device memory (the
+    loop sends only event indices); resident=False: hits in host memory, sent with each batch
+    (the host arrays are kept here so that they outlive the run)."""
 
-    def __init__(self, ctx: hough.Context, batch):
+    def __init__(self, ctx: hough.Context, batch, resident: bool = True):
         self.ctx = ctx
         self.batch = batch
-        self.x, self.y, self.offsets = hough.to_device(batch)
+        self.resident = resident
         self.host_offsets = np.ascontiguousarray(batch.offsets, dtype=np.uint32)
+        if resident:
+            self.x, self.y, self.offsets = hough.to_device(batch)
+        else:
+            self.host_x = np.ascontiguousarray(batch.x, dtype=np.float32)
+            self.host_y = np.ascontiguousarray(batch.y, dtype=np.float32)
 
     def struct(self) -> hough_serve_pool:
-        return hough_serve_pool(self.ctx._ctx.value, self.x.data_ptr(), self.y.data_ptr(),
-                                self.offsets.data_ptr(), self.host_offsets.ctypes.data, self.batch.n_events)
+        if self.resident:
+            return hough_serve_pool(self.ctx._ctx.value, self.x.data_ptr(), self.y.data_ptr(),
+                                    self.offsets.data_ptr(), self.host_offsets.ctypes.data, self.batch.n_events,
+                                    0, None, None)
+        return hough_serve_pool(self.ctx._ctx.value, None, None, None, self.host_offsets.ctypes.data,
+                                self.batch.n_events, 0, self.host_x.ctypes.data, self.host_y.ctypes.data)
 
 
 def poisson_trace(rate_hz: float, duration_s: float, pool_sizes, mix, seed: int = 0) -> np.ndarray:
@@ -99,6 +122,28 @@ def run(pools, trace: np.ndarray, n_streams: int = 8, max_batch_events: int = 25
     return res, keep, peaks
 
 
+def simulate(trace: np.ndarray, hits: np.ndarray, models, n_streams: int = 8, max_batch_events: int = 256,
+             max_batch_hits: int = 1 << 20, plain: bool = False, max_wait_us: float = 0.0,
+             small_batch_events: int = 0, split_batch_events: int = 0) -> np.ndarray:
+    """The serving loop's scheduling of `trace` on a simulated clock (hough_serve_simulate):
+    hits[i] is request i's event size, models[kind] = (fixed_us, per_event_us, per_hit_us) the
+    cost of a batch of that kind.  Returns the per-request results array (no device used)."""
+    L = _lib()
+    cfg = hough_serve_config(int(n_streams), int(max_batch_events), int(max_batch_hits), int(plain), 0,
+                             int(small_batch_events), int(split_batch_events), 0, float(max_wait_us))
+    trace = np.ascontiguousarray(trace, dtype=REQ_DTYPE)
+    hits = np.ascontiguousarray(hits, dtype=np.uint32)
+    if hits.size != trace.size:
+        raise ValueError("one hit count per request")
+    ms = (hough_serve_model * max(len(models), 1))(*[hough_serve_model(*map(float, m)) for m in models])
+    res = np.zeros(trace.size, RES_DTYPE)
+    rc = L.hough_serve_simulate(len(models), ctypes.byref(cfg), trace.ctypes.data, hits.ctypes.data, trace.size,
+                                ms, res.ctypes.data)
+    if rc != hough.HOUGH_OK:
+        raise hough.HoughError(rc, "hough_serve_simulate")
+    return res
+
+
 def summarize(trace: np.ndarray, res: np.ndarray, warmup_us: float = 0.0) -> dict:
     """p50/p99 latency (done - scheduled arrival), its split into waiting for a launch and the
     launch-to-results service time, and the sustained rate over the measured window."""
@@ -109,7 +154,8 @@ def summarize(trace: np.ndarray, res: np.ndarray, warmup_us: float = 0.0) -> dic
     wait = res["launch_us"][sel] - trace["arrival_us"][sel]
     span = (res["done_us"][sel].max() - trace["arrival_us"][sel].min()) / 1e6
     return {"requests": int(sel.sum()), "p50_us": round(float(np.percentile(lat, 50)), 1),
-            "p99_us": round(float(np.percentile(lat, 99)), 1), "max_us": round(float(lat.max()), 1),
+            "p99_us": round(float(np.percentile(lat, 99)), 1),
+            "p99_9_us": round(float(np.percentile(lat, 99.9)), 1), "max_us": round(float(lat.max()), 1),
             "p50_wait_us": round(float(np.percentile(wait, 50)), 1),
             "p50_service_us": round(float(np.percentile(lat - wait, 50)), 1),
             "events_per_s": round(float(sel.sum() / span), 1) if span > 0 else None,

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_function(hough_mod):
     names = hough_mod.header_functions()
     assert {"hough_config", "hough_vote", "hough_peaks", "hough_retain", "hough_run_batch"} <= set(names)
     serve = hough_mod.header_functions(os.path.join(ROOT, "include", "hough_serve.h"))
-    assert serve == ["hough_serve_run"]
+    assert serve == ["hough_serve_run", "hough_serve_simulate"]
     for n in names + serve:
         assert hasattr(lib, n), n
 

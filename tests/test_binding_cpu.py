@@ -51,7 +51,7 @@ def test_short_y_is_rejected_by_every_entry_point(H):
              lambda: ctx.run_batch_iterative(x, y, off),
              lambda: ctx.run_batch_split(x, y, off),
              lambda: ctx.run_batch_gather(x, y, off, torch.zeros(1, dtype=torch.int32),
-                                          torch.zeros(1, dtype=torch.int32))]
+                                          torch.zeros(1, dtype=torch.int32), keep_size=10)]
     for call in calls:
         with pytest.raises(ValueError, match="differ in length"):
             call()
@@ -75,6 +75,12 @@ def test_short_keep_is_rejected(H):
                                          keep_offsets=torch.zeros(1, dtype=torch.int32), keep_size=12)]
     for call in calls:
         with pytest.raises(ValueError, match="keep needs at least"):
+            call()
+    # the gather forms cannot check keep without being told how many bytes the batch writes
+    ids = torch.zeros(1, dtype=torch.int32)
+    for call in [lambda: ctx.run_batch_gather(x, y, off, ids, ids, keep=short),
+                 lambda: ctx.run_batch_split(x, y, off, keep=short, event_ids=ids, keep_offsets=ids)]:
+        with pytest.raises(ValueError, match="keep_size"):
             call()
 
 

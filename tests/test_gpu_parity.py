@@ -211,28 +211,111 @@ def test_u16_accumulator_and_overflow_guard(H, orc):
     ctx.close()
 
 
+FUSED_MAX_HITS = 32767          # largest event the fused kernel holds; larger ones spill
+ITERATIVE_MAX_HITS = 32767      # largest event of the iterative finder's batch form
+
+
 def test_large_events_in_batch(H, orc):
-    """Events up to the fused kernel's hit limit are exact; larger ones are flagged and zeroed."""
+    """Events up to the fused kernel's hit limit and beyond it (the spill path in device memory,
+    including counts beyond 16 bits) all equal the oracle, in one batch, plain and gathered."""
+    import torch
     g = orc.Grid(360, 256, -1 / 200, 1 / 200)
     ctx = H.Context(360, 256, -1 / 200, 1 / 200, "i32", 40, 1, 4096)
-    lim = ctx.max_batch_hits
-    x1, y1 = synth.random_hits(lim, seed=1, r_lo=200, r_hi=810)
-    x2, y2 = synth.random_hits(lim + 1, seed=2, r_lo=200, r_hi=810)
-    x3, y3 = synth.random_hits(50, seed=3, r_lo=200, r_hi=810)
-    xs = np.concatenate([x1, x2, x3]); ys = np.concatenate([y1, y2, y3])
-    offs = np.array([0, lim, 2 * lim + 1, 2 * lim + 51], np.uint32)
-    import torch
-    peaks, npk, keep, st = ctx.run_batch(_t(xs), _t(ys), _t(offs.astype(np.int32)))
+    lim = FUSED_MAX_HITS
+    sizes = [lim, lim + 1, 50, 70000, 0, 3]
+    parts = [synth.random_hits(n, seed=1 + i, r_lo=200, r_hi=810) for i, n in enumerate(sizes)]
+    xs = np.concatenate([a for a, _ in parts]).astype(np.float32)
+    ys = np.concatenate([b for _, b in parts]).astype(np.float32)
+    offs = np.zeros(len(sizes) + 1, np.uint32)
+    offs[1:] = np.cumsum(sizes)
+    say(f"large events {sizes}")
+    _batch_check(H, orc, ctx, g, 40, 1, xs, ys, offs, 4096)
+    # gathered, in another order, one of them twice
+    ids = np.array([3, 1, 5, 1, 0], np.int64)
+    koff = np.concatenate([[0], np.cumsum([sizes[i] for i in ids])[:-1]]).astype(np.int32)
+    n_keep = int(sum(sizes[i] for i in ids))
+    xt, yt, ot = _t(xs), _t(ys), _t(offs.astype(np.int32))
+    pk, npk, keep, st = ctx.run_batch_gather(xt, yt, ot, _t(ids.astype(np.int32)), _t(koff), keep_size=n_keep)
     torch.cuda.synchronize()
-    st = st.cpu().numpy(); npk = npk.cpu().numpy(); keep = keep.cpu().numpy()
-    assert st[1] == H.EV_TOO_MANY_HITS and npk[1] == 0 and not keep[lim:2 * lim + 1].any()
-    for e, (a, b) in [(0, (0, lim)), (2, (2 * lim + 1, 2 * lim + 51))]:
-        acc = orc.vote(g, xs[a:b], ys[a:b])
-        ref, n_ref = _oracle_peaks(orc, acc, 40)
-        assert npk[e] == n_ref and st[e] == (H.EV_PEAKS_TRUNCATED if n_ref > 4096 else 0)
-        m = min(n_ref, 4096)
-        assert np.array_equal(H.decode_peaks(peaks[e].cpu(), m), ref[:m])
-        assert np.array_equal(keep[a:b], orc.retain(g, xs[a:b], ys[a:b], ref[:, 0], ref[:, 1], 1))
+    pk_ref, n_ref, keep_ref = orc.run_batch(g, xs, ys, offs, threshold=40, rho_window=1, cap=4096)
+    npk, st, keep, pk = npk.cpu().numpy(), st.cpu().numpy(), keep.cpu().numpy(), pk.cpu().numpy()
+    for b, e in enumerate(ids):
+        assert npk[b] == n_ref[e] and st[b] == (H.EV_PEAKS_TRUNCATED if n_ref[e] > 4096 else 0), (b, e)
+        m = int(min(n_ref[e], 4096))
+        assert np.array_equal(H.decode_peaks(pk[b], m), pk_ref[e, :m].astype(np.int64)), (b, e)
+        assert np.array_equal(keep[koff[b]:koff[b] + sizes[e]], keep_ref[offs[e]:offs[e + 1]]), (b, e)
+    ctx.close()
+
+
+# grids whose rho column is taller than the fused kernel's LDS tile: the per-event path votes in
+# rho slabs and every batch form runs in device memory
+TALL_GRIDS = [(360, 2048, -1 / 200, 1 / 200, 10), (1000, 1500, -0.01, 0.01, 20), (97, 4099, -1 / 150, 1 / 150, 6)]
+
+
+@pytest.mark.parametrize("n_theta,n_rho,lo,hi,T", TALL_GRIDS)
+def test_tall_grids_equal_the_oracle(H, orc, n_theta, n_rho, lo, hi, T):
+    import torch
+    g = orc.Grid(n_theta, n_rho, lo, hi)
+    ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, 1, 8192)
+    assert ctx.batch_plan["waves_per_group"] == 0           # no fused tile: the spill path
+    ev = synth.make_events(synth.WORKLOADS["paper-1000ev-360x256"], 5, n_events=6)
+    evs = [ev.event(e) for e in range(ev.n_events)] + _edge_events()
+    x = np.concatenate([a for a, _ in evs]).astype(np.float32)
+    y = np.concatenate([b for _, b in evs]).astype(np.float32)
+    off = np.zeros(len(evs) + 1, np.uint32)
+    off[1:] = np.cumsum([a.size for a, _ in evs])
+    say(f"tall grid {n_theta}x{n_rho}: {len(evs)} events, {x.size} hits")
+    _batch_check(H, orc, ctx, g, T, 1, x, y, off, 8192)
+    # the per-event path: the accumulator (slab vote), the peak list and the keep mask
+    for e in range(min(3, ev.n_events)):
+        xe, ye = ev.event(e)
+        acc, peaks, npk, keep = _plain_event(H, ctx, xe, ye, 8192)
+        torch.cuda.synchronize()
+        acc_ref = orc.vote(g, xe, ye)
+        assert np.array_equal(acc.cpu().numpy().astype(np.int64), acc_ref.astype(np.int64)), e
+        ref, n_ref = _oracle_peaks(orc, acc_ref, T)
+        assert int(npk.item()) == n_ref
+        assert np.array_equal(H.decode_peaks(peaks, min(n_ref, 8192)), ref[:8192])
+        assert np.array_equal(keep.cpu().numpy(), orc.retain(g, xe, ye, ref[:, 0], ref[:, 1], 1))
+    # relative threshold and the split form take the same path
+    xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
+    E = len(evs)
+    pk, npk, keep, st = ctx.run_batch(xt, yt, ot, frac=(1, 2))
+    torch.cuda.synchronize()
+    pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=T, rho_window=1, cap=8192, frac=(1, 2))
+    assert np.array_equal(npk.cpu().numpy()[:E].astype(np.int64), n_ref)
+    assert np.array_equal(keep.cpu().numpy(), keep_ref)
+    sp = ctx.run_batch_split(xt, yt, ot)
+    plain = ctx.run_batch(xt, yt, ot)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(sp, plain))
+    ctx.close()
+
+
+@pytest.mark.parametrize("flags", ["periodic", "dedup"])
+def test_tall_grid_periodic_and_dedup(H, orc, flags):
+    import torch
+    n_theta, n_rho, lo, hi, T = 240, 1800, -1 / 200, 1 / 200, 8
+    g = orc.Grid(n_theta, n_rho, lo, hi)
+    ev = synth.make_events(synth.WORKLOADS["paper-1000ev-360x256"], 6, n_events=5)
+    x, y, off = ev.x, ev.y, ev.offsets
+    if flags == "periodic":
+        ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, 1, 8192, periodic=True)
+        pk, npk, keep, st = ctx.run_batch(_t(x), _t(y), _t(off.astype(np.int32)))
+        torch.cuda.synchronize()
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=T, rho_window=1, cap=8192, periodic=True)
+    else:
+        ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, 1, 8192, dedup=True)
+        pk, npk, keep, st = ctx.run_batch(_t(x), _t(y), _t(off.astype(np.int32)))
+        torch.cuda.synchronize()
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=T, rho_window=1, cap=8192, dedup=True)
+    E = ev.n_events
+    assert np.array_equal(npk.cpu().numpy()[:E].astype(np.int64), n_ref)
+    assert np.array_equal(keep.cpu().numpy(), keep_ref)
+    p = pk.cpu().numpy()
+    for e in range(E):
+        m = int(min(n_ref[e], 8192))
+        assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), e
     ctx.close()
 
 
@@ -508,7 +591,7 @@ def test_split_gather_batches_equal_gather_batches(H):
         ref = ctx.run_batch_gather(xt, yt, ot, _t(ids.astype(np.int32)), _t(koff), keep_size=n_keep,
                                    keep=torch.full((n_keep,), 0xAB, dtype=torch.uint8, device="cuda"))
         out = ctx.run_batch_split(xt, yt, ot, ws, event_ids=_t(ids.astype(np.int32)), keep_offsets=_t(koff),
-                                  keep=torch.full((n_keep,), 0xAB, dtype=torch.uint8, device="cuda"))
+                                  keep_size=n_keep, keep=torch.full((n_keep,), 0xAB, dtype=torch.uint8, device="cuda"))
         torch.cuda.synchronize()
         say(f"split gather ids={ids.tolist()}")
         assert all(torch.equal(a, b) for a, b in zip(ref, out))
@@ -517,35 +600,49 @@ def test_split_gather_batches_equal_gather_batches(H):
     ctx.close()
 
 
-def _serve_pools(H, n_each=48, dedup=False):
+def _serve_pools(H, n_each=48, dedup=False, resident=True, max_peaks=16384):
     from paper_2607_04067_amd import serve
     pools = []
     for name in ("paper-1000ev-360x256", "dense-2000ev-720x512"):
         wl = synth.WORKLOADS[name]
         ev = synth.make_events(wl, 7, n_events=n_each)
-        ctx = H.Context.for_workload(wl, max_peaks=16384, dedup=dedup)
-        pools.append(serve.Pool(ctx, ev))
+        ctx = H.Context.for_workload(wl, max_peaks=max_peaks, dedup=dedup)
+        pools.append(serve.Pool(ctx, ev, resident=resident))
     return pools
 
 
-@pytest.mark.parametrize("plain,small,split,dedup", [(False, 0, 0, False), (False, 64, 0, False),
-                                                     (False, 64, 4, False), (False, 0, 16, False),
-                                                     (False, 64, 8, True), (True, 0, 0, False)])
-def test_served_results_equal_results_alone(H, plain, small, split, dedup):
+# shape: (streams, events per batch, arena hits, arrival rate, seconds of arrivals, max_peaks)
+SERVE_SHAPES = {"small": (4, 16, 40000, 2e5, 0.002, 16384),
+                "bench": (8, 256, 1 << 21, 4e5, 0.003, 8192)}
+
+
+@pytest.mark.parametrize("plain,small,split,dedup,resident,shape", [
+    (False, 0, 0, False, True, "small"), (False, 64, 0, False, True, "small"),
+    (False, 64, 4, False, True, "small"), (False, 0, 16, False, True, "small"),
+    (False, 64, 8, True, True, "small"), (True, 0, 0, False, True, "small"),
+    (False, 0, 0, False, False, "small"), (False, 64, 8, True, False, "small"), (True, 0, 0, False, False, "small"),
+    (False, 64, 16, False, False, "bench"), (False, 64, 16, False, True, "bench")])
+def test_served_results_equal_results_alone(H, plain, small, split, dedup, resident, shape):
     """Each request's n_peaks, status, keep and peak list in the served mix (continuous
     batching over several streams, events reordered largest first inside a batch, small
     batches on the 16-wave shape or in the split form or neither, duplicate suppression on
-    or off) equal the same event processed alone."""
+    or off, hits resident on the device or sent with each batch, up to the benchmark's shape
+    of 8 streams and 256-event batches) equal the same event processed alone; requests were
+    batched together and batches on different streams overlapped in time."""
     import torch
     from paper_2607_04067_amd import serve
-    pools = _serve_pools(H, dedup=dedup)
-    trace = serve.poisson_trace(2e5 if not plain else 2e4, 0.002 if not plain else 0.004,
-                                [p.batch.n_events for p in pools], [0.5, 0.5], seed=3)
+    n_streams, max_events, arena, rate, secs, cap = SERVE_SHAPES[shape]
+    pools = _serve_pools(H, dedup=dedup, resident=resident, max_peaks=cap)
+    if plain:
+        rate, secs = 2e4, 0.004
+    trace = serve.poisson_trace(rate, secs, [p.batch.n_events for p in pools], [0.5, 0.5], seed=3)
     assert trace.size > 20
-    res, keep, peaks = serve.run(pools, trace, n_streams=4, max_batch_events=16, max_batch_hits=40000,
-                                 plain=plain, want_keep=True, want_peaks=16384, small_batch_events=small,
-                                 split_batch_events=split)
-    say(f"served {trace.size} requests plain={plain} split={split}: {serve.summarize(trace, res)}")
+    say(f"serving {trace.size} requests: plain={plain} small={small} split={split} dedup={dedup} "
+        f"resident={resident} shape={shape}")
+    res, keep, peaks = serve.run(pools, trace, n_streams=n_streams, max_batch_events=max_events,
+                                 max_batch_hits=arena, plain=plain, want_keep=True, want_peaks=cap,
+                                 small_batch_events=small, split_batch_events=split)
+    say(f"served: {serve.summarize(trace, res)}")
     off = 0
     alone = {}
     for i, (k, e) in enumerate(zip(trace["kind"], trace["event"])):
@@ -556,18 +653,29 @@ def test_served_results_equal_results_alone(H, plain, small, split, dedup):
             pk, n, kp, st = p.ctx.run_batch(xs, ys, os_)
             torch.cuda.synchronize()
             alone[(k, e)] = (int(n[0]), int(st[0]), kp.cpu().numpy()[:sub.n_hits].copy(),
-                             H.decode_peaks(pk[0], min(int(n[0]), 16384)))
+                             H.decode_peaks(pk[0], min(int(n[0]), cap)))
         n, st, kp, pl = alone[(k, e)]
         assert res["n_peaks"][i] == n
         if not plain:
             assert res["status"][i] == st
         h = kp.size
         assert np.array_equal(keep[off:off + h], kp), i
-        assert np.array_equal(H.decode_peaks(peaks[i], min(n, 16384)), pl), i
+        assert np.array_equal(H.decode_peaks(peaks[i], min(n, cap)), pl), i
         off += h
-    assert np.all(res["done_us"] >= trace["arrival_us"])
+    assert np.all(res["done_us"] >= res["launch_us"]) and np.all(res["launch_us"] >= trace["arrival_us"])
+    assert np.all(res["slot"] < n_streams)
     if not plain:
-        assert res["batch_events"].max() >= 1
+        assert res["batch_events"].max() > 1
+    # two requests on different streams were in flight at the same time
+    if n_streams > 1 and not plain:
+        order = np.argsort(res["launch_us"], kind="stable")
+        end_by_slot = {}
+        overlap = False
+        for j in order:
+            lo, s_j = float(res["launch_us"][j]), int(res["slot"][j])
+            overlap = overlap or any(end > lo for s_, end in end_by_slot.items() if s_ != s_j)
+            end_by_slot[s_j] = max(end_by_slot.get(s_j, 0.0), float(res["done_us"][j]))
+        assert overlap
     for p in pools:
         p.ctx.close()
 
@@ -1025,7 +1133,7 @@ def _check_batch_iterative(H, orc, ctx, g, x, y, off, T, W, frac, rt, rr, cap, d
     npk, st, keep, p = npk.cpu().numpy()[:E], st.cpu().numpy()[:E], keep.cpu().numpy(), pk.cpu().numpy()
     for e in range(E):
         a, b = int(off[e]), int(off[e + 1])
-        if b - a > ctx.max_batch_hits:
+        if b - a > ITERATIVE_MAX_HITS:
             assert st[e] & H.EV_TOO_MANY_HITS and npk[e] == 0 and not keep[a:b].any()
             continue
         assert npk[e] == n_ref[e], e
@@ -1127,10 +1235,9 @@ def test_relative_threshold_edge_events(H, orc):
         E = len(evs)
         pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=2, rho_window=1, cap=4096, frac=frac)
         npk = npk.cpu().numpy()[:E]
-        assert st.cpu().numpy()[E - 1] & H.EV_TOO_MANY_HITS and npk[E - 1] == 0
-        assert np.array_equal(npk[:E - 1].astype(np.int64), n_ref[:E - 1]), frac
-        a = int(off[E - 1])
-        assert np.array_equal(keep.cpu().numpy()[:a], keep_ref[:a]), frac
+        assert np.array_equal(npk.astype(np.int64), n_ref), frac        # the last event spills
+        assert np.array_equal(st.cpu().numpy()[:E] & H.EV_TOO_MANY_HITS, np.zeros(E, np.int32))
+        assert np.array_equal(keep.cpu().numpy(), keep_ref), frac
         if frac == (7, 5):
             assert npk[:E - 1].sum() == 0                  # the threshold exceeds every count
     with pytest.raises(H.HoughError):
