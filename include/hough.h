@@ -59,6 +59,7 @@ extern "C" {
 #define HOUGH_ENOMEM    (-2)   /* device or host allocation failed in hough_config            */
 #define HOUGH_EOVERFLOW (-3)   /* a count could exceed the output type (u16 accumulator)      */
 #define HOUGH_EDEVICE   (-4)   /* a HIP runtime call or kernel launch failed                  */
+#define HOUGH_ETOOLARGE (-5)   /* the batch needs more than the library's static scratch      */
 
 #define HOUGH_ACC_U16 1        /* accumulator cells are uint16_t (needs n_hits <= 65535)     */
 #define HOUGH_ACC_I32 2        /* accumulator cells are int32_t                               */
@@ -244,6 +245,21 @@ int hough_run_batch_split(hough_ctx *ctx, const float *x, const float *y, const 
                           const uint32_t *event_ids, const uint32_t *keep_offsets, uint32_t n_events,
                           hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): hough_run_batch_split with the library's own scratch
+ * in place of a caller workspace.  Same arguments (minus the workspace), outputs, asynchrony and
+ * errors; the call itself allocates nothing.  The scratch is one device array of
+ * HOUGH_STATIC_SCRATCH_BYTES per device, set up by hough_config on that device and held until
+ * the process ends; a batch whose hough_split_workspace_bytes exceeds it is refused with
+ * HOUGH_ETOOLARGE before anything is enqueued.  Every call on a device shares that device's
+ * array (each call leaves it zero), so calls that may overlap on one device -- on different
+ * streams, or from different host threads -- race and must be ordered by the caller. */
+#define HOUGH_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+int hough_run_batch_split_static(hough_ctx *ctx, const float *x, const float *y, const uint32_t *offsets,
+                                 const uint32_t *event_ids, const uint32_t *keep_offsets, uint32_t n_events,
+                                 hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
+                                 void *stream);
 
 /* The paper's peak finder over a batch of CSR events (as hough_run_batch takes them): steps
  * 1-3 into one 16-bit accumulator per event in `workspace` (device, 256-byte aligned, at least

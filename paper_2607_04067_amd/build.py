@@ -18,7 +18,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhough.so")
-SOURCES = ["hough_kernels.hip", "hough_api.cpp", "hough_serve.cpp"]
+SOURCES = ["hough_kernels.hip", "hough_scratch.hip", "hough_api.cpp", "hough_serve.cpp"]
 PROBE_LIB = os.path.join(HERE, "libhough_probe.so")
 PROBE_SOURCES = ["hough_probe.hip"]
 ARCH = os.environ.get("HOUGH_OFFLOAD_ARCH", "gfx950")

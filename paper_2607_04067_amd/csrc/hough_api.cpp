@@ -125,6 +125,7 @@ const char *hough_status_string(int status) {
         case HOUGH_ENOMEM: return "out of memory";
         case HOUGH_EOVERFLOW: return "count may overflow the accumulator type";
         case HOUGH_EDEVICE: return "HIP runtime or launch failure";
+        case HOUGH_ETOOLARGE: return "batch needs more than the library's static scratch";
         default: return "unknown status";
     }
 }
@@ -164,6 +165,7 @@ int hough_config(const hough_params *p, hough_ctx **out) {
     if (hipGetDevice(&dev) != hipSuccess) return HOUGH_EDEVICE;
     size_t limit = 0;
     int rc = lds_limit_bytes(dev, &limit);
+    if (rc == HOUGH_OK) rc = hough::scratch_init(dev);   // once per device
     if (rc != HOUGH_OK) return rc;
     if (!grid_fits(p->n_rho, limit)) return HOUGH_EINVAL;
 
@@ -503,6 +505,21 @@ int hough_run_batch_split(hough_ctx *c, const float *x, const float *y, const ui
     if (n_events && !workspace && hough_split_workspace_bytes(c, n_events) > 0) return HOUGH_EINVAL;
     return run_batch_common(c, x, y, offsets, event_ids, keep_offsets, n_events, peaks, n_peaks, keep,
                             status, stream, true, workspace, workspace_bytes);
+}
+
+int hough_run_batch_split_static(hough_ctx *c, const float *x, const float *y, const uint32_t *offsets,
+                                 const uint32_t *event_ids, const uint32_t *keep_offsets, uint32_t n_events,
+                                 hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep, uint32_t *status,
+                                 void *stream) {
+    if (!c) return HOUGH_EINVAL;
+    if (!on_device(c)) return HOUGH_EINVAL;
+    if (n_events && ((event_ids == nullptr) != (keep_offsets == nullptr))) return HOUGH_EINVAL;
+    const size_t need = hough_split_workspace_bytes(c, n_events);
+    if (need > hough::kStaticScratchBytes) return HOUGH_ETOOLARGE;
+    void *ws = hough::scratch_ptr(c->device);
+    if (!ws) return HOUGH_EDEVICE;
+    return run_batch_common(c, x, y, offsets, event_ids, keep_offsets, n_events, peaks, n_peaks, keep,
+                            status, stream, true, ws, hough::kStaticScratchBytes);
 }
 
 }  // extern "C"

@@ -106,6 +106,13 @@ struct SpillArgs {
 size_t spill_stride(int n_theta, int n_rho);
 hipError_t launch_spill(const GridArgs &g, const BatchArgs &a, const SpillArgs &sp, int n_wg, hipStream_t s);
 
+// Library-held scratch of hough_run_batch_split_static (hough_scratch.hip): one device array
+// per device, its address taken once per device by scratch_init (called from hough_config
+// with that device current).  Zero between calls, as the split form's workspace.
+constexpr size_t kStaticScratchBytes = HOUGH_STATIC_SCRATCH_BYTES;
+int scratch_init(int device);
+void *scratch_ptr(int device);
+
 // Phase slots of the instrumented build (HOUGH_PHASE_TIMING): clock ticks each workgroup of
 // the fused kernel spent per phase, summed over workgroups, plus two counts.
 enum PhaseSlot {

@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhough.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "hough.h")
 
-HOUGH_OK, HOUGH_EINVAL, HOUGH_ENOMEM, HOUGH_EOVERFLOW, HOUGH_EDEVICE = 0, -1, -2, -3, -4
+HOUGH_OK, HOUGH_EINVAL, HOUGH_ENOMEM, HOUGH_EOVERFLOW, HOUGH_EDEVICE, HOUGH_ETOOLARGE = 0, -1, -2, -3, -4, -5
+STATIC_SCRATCH_BYTES = 32 << 20     # HOUGH_STATIC_SCRATCH_BYTES
 ACC_U16, ACC_I32 = 1, 2
 EV_PEAKS_TRUNCATED, EV_INVALID_HITS, EV_TOO_MANY_HITS = 1, 2, 4
 EV_DEDUP_SKIPPED = 16
@@ -90,6 +91,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.hough_run_batch_gather.restype = i32
     L.hough_run_batch_split.argtypes = [vp, vp, vp, vp, vp, vp, u32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     L.hough_run_batch_split.restype = i32
+    L.hough_run_batch_split_static.argtypes = [vp, vp, vp, vp, vp, vp, u32, vp, vp, vp, vp, vp]
+    L.hough_run_batch_split_static.restype = i32
     L.hough_split_workspace_bytes.argtypes = [vp, u32]
     L.hough_split_workspace_bytes.restype = ctypes.c_size_t
     L.hough_get_batch_plan.argtypes = [vp, ctypes.POINTER(hough_batch_plan)]
@@ -405,10 +408,20 @@ class Context:
         with each event's theta tiles on separate workgroups (the latency form).
         workspace: from split_workspace (kept zero between calls)."""
         return self._split(x, y, offsets, workspace, peaks, n_peaks, keep, status, event_ids, keep_offsets,
-                           keep_size, stream)
+                           keep_size, stream, static=False)
+
+    def run_batch_split_static(self, x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor,
+                               peaks: torch.Tensor | None = None, n_peaks: torch.Tensor | None = None,
+                               keep: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                               event_ids: torch.Tensor | None = None, keep_offsets: torch.Tensor | None = None,
+                               keep_size: int | None = None, stream=None):
+        """run_batch_split on the library's static scratch (hough_run_batch_split_static): the
+        call allocates nothing when every output tensor is given."""
+        return self._split(x, y, offsets, None, peaks, n_peaks, keep, status, event_ids, keep_offsets,
+                           keep_size, stream, static=True)
 
     def _split(self, x, y, offsets, workspace, peaks, n_peaks, keep, status, event_ids, keep_offsets,
-               keep_size, stream):
+               keep_size, stream, static: bool):
         if (event_ids is None) != (keep_offsets is None):
             raise ValueError("event_ids and keep_offsets go together")
         if event_ids is not None and keep_size is None:
@@ -417,7 +430,7 @@ class Context:
         E = offsets.numel() - 1 if event_ids is None else event_ids.numel()
         mp = self.params.max_peaks
         dev = offsets.device
-        if workspace is None:
+        if workspace is None and not static:
             workspace = self.split_workspace(E)
         if peaks is None:
             peaks = torch.zeros((max(E, 1), max(mp, 1), 2), dtype=torch.int32, device=dev)
@@ -441,9 +454,13 @@ class Context:
         pk = self._ptr_or_dummy(keep, torch.uint8, "keep")
         px = self._ptr_or_dummy(x, torch.float32, "x")
         py = self._ptr_or_dummy(y, torch.float32, "y")
-        pw = _dev(workspace, torch.uint8, "workspace")
-        _check(self._lib.hough_run_batch_split(self._ctx, px, py, po, pi, pko, E, pp, pn, pk, ps, pw,
-                                               workspace.numel(), _stream(stream)), "hough_run_batch_split")
+        if static:
+            _check(self._lib.hough_run_batch_split_static(self._ctx, px, py, po, pi, pko, E, pp, pn, pk, ps,
+                                                          _stream(stream)), "hough_run_batch_split_static")
+        else:
+            pw = _dev(workspace, torch.uint8, "workspace")
+            _check(self._lib.hough_run_batch_split(self._ctx, px, py, po, pi, pko, E, pp, pn, pk, ps, pw,
+                                                   workspace.numel(), _stream(stream)), "hough_run_batch_split")
         return peaks, n_peaks, keep, status
 
     def run_batch_gather(self, x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, event_ids: torch.Tensor,

@@ -58,7 +58,7 @@ def test_serve_config_layout_matches_header():
 
 
 def test_status_strings(hough_mod):
-    for code in (0, -1, -2, -3, -4):
+    for code in (0, -1, -2, -3, -4, -5):
         assert hough_mod.status_string(code) != "unknown status"
     assert hough_mod.status_string(-6) == "unknown status"
 
@@ -77,6 +77,13 @@ def test_config_reports_enomem_when_allocation_fails(hough_mod, monkeypatch):
     assert lib.hough_config(ctypes.byref(bad), ctypes.byref(ctx)) == hough_mod.HOUGH_EINVAL
     assert lib.hough_config(None, ctypes.byref(ctx)) == hough_mod.HOUGH_EINVAL
     lib.hough_destroy(None)                       # destroying nothing is a no-op
+
+
+def test_static_scratch_limit_matches_header(hough_mod):
+    text = open(os.path.join(ROOT, "include", "hough.h")).read()
+    m = re.search(r"#define HOUGH_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == hough_mod.STATIC_SCRATCH_BYTES
+    assert re.search(r"#define HOUGH_ETOOLARGE \(-5\)", text) and hough_mod.HOUGH_ETOOLARGE == -5
 
 
 def test_phase_timing_build_exports_its_hook_and_the_product_does_not(hough_mod):
