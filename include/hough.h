@@ -300,6 +300,7 @@ typedef struct hough_batch_plan {
     int32_t column_groups;     /* 1 or 2                                               */
     int32_t groups_per_cu;     /* workgroups launched per CU (<= what fits)            */
     int32_t lds_bytes;         /* LDS per workgroup (read-only)                        */
+    int32_t window_rows;       /* rho rows of a windowed tile, 0 = whole column (read-only) */
 } hough_batch_plan;
 
 /* The launch shape hough_run_batch currently uses (the library picks one at hough_config); all
@@ -307,9 +308,14 @@ typedef struct hough_batch_plan {
 int hough_get_batch_plan(const hough_ctx *ctx, hough_batch_plan *out);
 
 /* Select a launch shape (for autotuning).  groups_per_cu = 0 launches as many workgroups per CU
- * as fit; a positive value launches at most that many.  HOUGH_EINVAL if the combination is not
- * supported or does not fit the device, or the grid has no fused kernel; the context keeps its
- * previous shape then. */
+ * as fit; a positive value launches at most that many.  A groups_per_cu above what a tile of the
+ * whole rho column allows selects a windowed tile (one column group, theta not periodic): the
+ * tallest whole number of 32-row words that lets that many workgroups share a CU.  Each event
+ * then gets the window of rows its hits can reach (they are bounded by the event's smallest
+ * x^2 + y^2, Eq. (1)); an event whose rows do not fit goes through the spill path, as do
+ * events above the fused kernel's hit limit.  The split forms always hold the whole column.
+ * HOUGH_EINVAL if the combination is not supported or does not fit the device, or the grid has
+ * no fused kernel; the context keeps its previous shape then. */
 int hough_set_batch_plan(hough_ctx *ctx, int32_t waves_per_group, int32_t column_groups,
                          int32_t groups_per_cu);
 

@@ -2,7 +2,9 @@
 
 The schedule space is the theta-tile width (64 * column_groups columns) times the split of an
 event's hits over the waves of a workgroup (waves_per_group) times the number of workgroups
-launched per CU (up to what fits; fewer can divide a small batch more evenly over the grid).
+launched per CU (up to what fits; fewer can divide a small batch more evenly over the grid;
+more than a whole rho column allows selects a windowed tile, which pays off where the events'
+hits reach only part of the rho range).
 Every candidate is timed on the caller's resident batch with HIP
 events; the three fastest are timed again with more launches, and the fastest of those is kept
 unless the context's own shape is within `keep_margin` of it (then the default stays, so that
@@ -36,11 +38,18 @@ def _load(path):
         return {}
 
 
-def time_plan(ctx, args, reps: int = 5) -> float:
-    """Mean milliseconds of one hough_run_batch over `reps` launches (after one warm-up)."""
+def time_plan(ctx, args, reps: int = 5, give_up_ms: float | None = None) -> float:
+    """Mean milliseconds of one hough_run_batch over `reps` launches (after one warm-up).  A
+    warm-up slower than `give_up_ms` is returned as it is (a windowed plan whose window the
+    batch's events do not fit sends them all through the slow spill path)."""
     stream = torch.cuda.current_stream()
-    ctx.run_batch(*args, stream=stream)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    ctx.run_batch(*args, stream=stream)
+    b.record(stream)
+    b.synchronize()
+    if give_up_ms is not None and a.elapsed_time(b) > give_up_ms:
+        return a.elapsed_time(b)
     a.record(stream)
     for _ in range(reps):
         ctx.run_batch(*args, stream=stream)
@@ -72,7 +81,8 @@ def tune(ctx, x, y, offsets, outputs, mean_hits: float, cache: str | None = DEFA
             continue
         key_c = f"{w}x{g}x{n or ctx.batch_plan['groups_per_cu']}"
         if key_c not in results:
-            results[key_c] = round(time_plan(ctx, args, reps), 5)
+            best = min(results.values(), default=None)
+            results[key_c] = round(time_plan(ctx, args, reps, give_up_ms=4.0 * best if best else None), 5)
     finalists = sorted(results, key=results.get)[:3]
     if default in results and default not in finalists:
         finalists.append(default)

@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -97,13 +98,13 @@ int default_plan(hough_ctx *c) {
     for (int wi = 0; wi < 5; ++wi) {
         hough::BatchPlan p;
         if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves_opts[wi], 1, c->lds_limit, &p) != 0) continue;
-        p.per_cu = hough::prepare_batch(p, c->lds_limit);
-        if (p.per_cu < 1) continue;
+        p.per_cu = hough::prepare_batch(&p);
+        if (p.per_cu < 1 || p.split_per_cu < 1) continue;
         const int score = p.per_cu * p.waves;
         if (score > best) { best = score; pick = p; }
     }
     if (best < 0) return HOUGH_EINVAL;
-    if (hough::prepare_batch(pick, c->lds_limit) < 1) return HOUGH_EDEVICE;
+    if (hough::prepare_batch(&pick) < 1) return HOUGH_EDEVICE;
     c->plan = pick;
     return HOUGH_OK;
 }
@@ -236,6 +237,13 @@ int hough_config(const hough_params *p, hough_ctx **out) {
     g.dedup = (p->flags & HOUGH_FLAG_DEDUP) ? 1 : 0;
     g.vote_rows = hough::vote_slab_rows(p->n_rho, limit);
     g.peak_waves = peak_waves;
+    // bounds for a windowed tile's rows: the largest |(C_j, S_j)| of the float tables and B
+    g.wA = 0.0;
+    for (int j = 0; j < p->n_theta; ++j) {
+        const double cj = tab[j], sj = tab[p->n_theta + j];
+        g.wA = std::max(g.wA, sqrt(cj * cj + sj * sj));
+    }
+    g.wB = (double)g.Bf;
 
     rc = c->fused ? default_plan(c) : HOUGH_OK;
     if (rc != HOUGH_OK) {
@@ -267,14 +275,32 @@ uint32_t hough_max_batch_hits(const hough_ctx *c) { return c ? UINT32_MAX : 0u; 
 int hough_get_batch_plan(const hough_ctx *c, hough_batch_plan *out) {
     if (!c || !out) return HOUGH_EINVAL;
     if (!c->fused) {                      // no fused kernel for this grid: all zero
-        *out = hough_batch_plan{0, 0, 0, 0};
+        *out = hough_batch_plan{0, 0, 0, 0, 0};
         return HOUGH_OK;
     }
     out->waves_per_group = c->plan.waves;
     out->column_groups = c->plan.groups;
     out->groups_per_cu = c->plan.per_cu;
     out->lds_bytes = (int32_t)c->plan.lds_bytes;
+    out->window_rows = c->plan.win;
     return HOUGH_OK;
+}
+
+// More workgroups per CU than a whole-column tile allows: the tallest windowed tile (a multiple
+// of 32 rows) that lets groups_per_cu of them share a CU, if any (one column group, theta not
+// periodic).  Events whose hits reach beyond the window go to the spill kernel.
+static int windowed_plan(const hough_ctx *c, int waves, int groups, int groups_per_cu, hough::BatchPlan *out) {
+    if (groups != 1 || c->g.periodic) return -1;
+    for (int win = ((c->p.n_rho - 1) / 32) * 32; win >= 32; win -= 32) {
+        hough::BatchPlan p;
+        if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves, groups, c->lds_limit, &p, win) != 0) continue;
+        p.per_cu = hough::prepare_batch(&p);
+        if (p.per_cu >= groups_per_cu && p.split_per_cu >= 1) {
+            *out = p;
+            return 0;
+        }
+    }
+    return -1;
 }
 
 int hough_set_batch_plan(hough_ctx *c, int32_t waves_per_group, int32_t column_groups,
@@ -283,9 +309,13 @@ int hough_set_batch_plan(hough_ctx *c, int32_t waves_per_group, int32_t column_g
     hough::BatchPlan p;
     if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves_per_group, column_groups, c->lds_limit, &p) != 0)
         return HOUGH_EINVAL;
-    p.per_cu = hough::prepare_batch(p, c->lds_limit);
-    if (p.per_cu < 1 || groups_per_cu > p.per_cu) {
-        (void)hough::prepare_batch(c->plan, c->lds_limit);
+    p.per_cu = hough::prepare_batch(&p);
+    if (p.per_cu >= 1 && p.split_per_cu >= 1 && groups_per_cu > p.per_cu &&
+        windowed_plan(c, waves_per_group, column_groups, groups_per_cu, &p) != 0)
+        p.per_cu = 0;
+    if (p.per_cu < 1 || p.split_per_cu < 1 || groups_per_cu > p.per_cu) {
+        hough::BatchPlan keep = c->plan;
+        (void)hough::prepare_batch(&keep);
         return HOUGH_EINVAL;
     }
     if (groups_per_cu > 0) p.per_cu = groups_per_cu;
@@ -448,7 +478,9 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
             return HOUGH_EINVAL;
         const long items = (long)n_events * sp.n_tiles;
         if (items >= (1L << 31)) return HOUGH_EINVAL;      // the work queue counts in 32 bits
-        long g2 = (long)c->plan.per_cu * c->n_cu;
+        // the split form holds the whole column, whatever window the fused kernel's plan has
+        const int per = c->plan.per_cu < c->plan.split_per_cu ? c->plan.per_cu : c->plan.split_per_cu;
+        long g2 = (long)per * c->n_cu;
         plan.grid = (int)(g2 < items ? g2 : items);
     }
     if (c->g.dedup) e = hough::launch_dedup(a, (hipStream_t)stream);   // marks later copies in keep

@@ -37,6 +37,7 @@ struct GridArgs {
     int32_t dedup;       // later copies of a hit do not vote (HOUGH_FLAG_DEDUP)
     int32_t vote_rows;   // rho rows per LDS slab of hough_vote (n_rho when the column fits)
     int32_t peak_waves;  // theta rows per workgroup of hough_peaks (16, 8, 4 or 2)
+    double wA, wB;       // A and B in double: the rho window of an event's hits (fused kernel)
 };
 
 // Launch shape of the fused batch kernel (chosen by the host; see plan_batch()).
@@ -50,7 +51,14 @@ struct BatchPlan {
     int per_cu;          // resident workgroups per CU (occupancy API)
     int grid;            // persistent workgroups
     int sparse;          // retention by peak list on tiles with few peaks (see kSparseRhoRows)
+    int win;             // rows of a windowed tile (0: the tile holds the whole rho column)
+    size_t split_lds_bytes;   // the split form's LDS (it always holds the whole column)
+    int split_per_cu;    // its resident workgroups per CU
 };
+// Status bit of an event the fused (or split) kernel leaves to the spill kernel launched after
+// it: more than kMaxBatchHits hits, or hits that reach beyond the rows of a windowed tile.  The
+// spill kernel replaces the event's status.
+constexpr uint32_t kStatusSpill = 0x80000000u;
 // Grids with at least this many rho rows take the fused kernel's peak-list retention on tiles
 // with few peaks (their votes spread over many rows, so a tile rarely has many peaks); so does
 // every relative-threshold launch.  Other launches run the kernel compiled without it, which
@@ -185,8 +193,9 @@ hipError_t launch_peaks_iterative(const GridArgs &g, const void *acc, int acc_ty
                                   uint32_t frac_den, int r_theta, int r_rho, hough_peak *peaks,
                                   uint32_t cap, uint32_t *n_peaks, uint32_t *status, const IterPlan &ip,
                                   uint32_t *gbm, hipStream_t s);
-size_t batch_lds_bytes(int n_rho, int waves, int groups);
-int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out);
-int prepare_batch(const BatchPlan &p, size_t lds_limit);
+// LDS of the fused kernel's workgroup: the whole column (win 0) or a window of win rows.
+size_t batch_lds_bytes(int n_rho, int waves, int groups, int win = 0);
+int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out, int win = 0);
+int prepare_batch(BatchPlan *p);
 
 }  // namespace hough

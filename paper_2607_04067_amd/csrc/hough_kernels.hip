@@ -18,6 +18,8 @@
 // the literal test 0 <= t < n_rho.
 #include <float.h>
 
+#include <algorithm>
+
 #include "hough_internal.h"
 
 namespace hough {
@@ -77,7 +79,7 @@ struct Cols {
 
 template <int G, bool PER = false>
 __device__ __forceinline__ Cols<G> load_cols(const GridArgs &g, int first_col, int lane, int stride,
-                                             const uint32_t *col) {
+                                             const uint32_t *col, float dummy_row = -1.0f) {
     Cols<G> cl;
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -87,7 +89,8 @@ __device__ __forceinline__ Cols<G> load_cols(const GridArgs &g, int first_col, i
         const int jw = j < 0 ? g.n_theta - 1 : 0;
         cl.C[q] = in ? g.C[j] : (wrap ? g.C[jw] : 0.0f);
         cl.S[q] = in ? g.S[j] : (wrap ? g.S[jw] : 0.0f);
-        cl.B[q] = (in || wrap) ? g.Bf : g.nrho_f;   // out-of-grid lanes land in the dummy row
+        // out-of-grid lanes land in the dummy row (row n_rho, or the row a windowed tile gives it)
+        cl.B[q] = (in || wrap) ? g.Bf : (dummy_row >= 0.0f ? dummy_row : g.nrho_f);
         cl.rs[q] = 4 * (wrap ? -stride : stride);                                    // bytes
         cl.rb[q] = 4 * (wrap ? (g.n_rho - 1) * stride + (int)col[q] : (int)col[q]);
     }
@@ -389,7 +392,7 @@ __device__ __forceinline__ void store_peak(hough_peak *out, uint32_t j, uint32_t
 constexpr uint32_t kTilePeaks = 64;
 
 template <int G, bool P>
-__device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask, uint32_t *dil,
+__device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask, uint32_t *dil, int w0,
                                     int nwords, int first_col, const GridArgs &g, hough_peak *out,
                                     uint32_t cap, uint32_t base, const Lane<G, P> &ln, int lane,
                                     int wave, int n_waves, float4 *tpk = nullptr,
@@ -404,21 +407,22 @@ __device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask,
         if (colcnt)
             tot = colcnt[64 * q + lane];
         else
-            for (int w = 0; w < nwords; ++w) tot += __popc(pmask[w * TW + 64 * q + lane]);
+            for (int w = w0; w < w0 + nwords; ++w) tot += __popc(pmask[w * TW + 64 * q + lane]);
         const uint32_t incl = wave_inclusive_scan(tot, lane);
         colbase[q] = carry + incl - tot;
         carry += __shfl(incl, 63, 64);
     }
     if (carry == 0u) return 0u;
     const bool rec = tpk != nullptr && carry <= kTilePeaks;   // then every local index fits
-    for (int wd = wave; wd < nwords; wd += n_waves) {
+    const int w1 = w0 + nwords;
+    for (int wd = w0 + wave; wd < w1; wd += n_waves) {
 #pragma unroll
         for (int q = 0; q < G; ++q) {
             const int c = 64 * q + lane;
             uint32_t m = pmask[wd * TW + c];
             if (W < 32) {
-                const uint32_t up = wd > 0 ? pmask[(wd - 1) * TW + c] : 0u;
-                const uint32_t dn = wd + 1 < nwords ? pmask[(wd + 1) * TW + c] : 0u;
+                const uint32_t up = wd > w0 ? pmask[(wd - 1) * TW + c] : 0u;
+                const uint32_t dn = wd + 1 < w1 ? pmask[(wd + 1) * TW + c] : 0u;
                 uint32_t d = m;
                 for (int sft = 1; sft <= W; ++sft)
                     d |= (m << sft) | (m >> sft) | (up >> (32 - sft)) | (dn << (32 - sft));
@@ -426,7 +430,7 @@ __device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask,
             }
             if (!m) continue;
             uint32_t idx = base + colbase[q];
-            for (int w = 0; w < wd; ++w) idx += __popc(pmask[w * TW + c]);
+            for (int w = w0; w < wd; ++w) idx += __popc(pmask[w * TW + c]);
             const uint32_t j = (uint32_t)(first_col + c);
             while (m) {
                 const int b = __builtin_ctz(m);
@@ -439,7 +443,8 @@ __device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask,
                 if (W >= 32) {
                     const int lo = k - W > 0 ? k - W : 0;
                     const int hi = k + W < g.n_rho - 1 ? k + W : g.n_rho - 1;
-                    for (int w = lo >> 5; w <= (hi >> 5); ++w) {
+                    // words outside [w0, w1) hold rows no hit of the event reaches
+                    for (int w = max(lo >> 5, w0); w <= min(hi >> 5, w1 - 1); ++w) {
                         const int a = max(lo, w * 32) - w * 32, e = min(hi, w * 32 + 31) - w * 32;
                         const uint32_t rm = (e == 31 ? ~0u : ((1u << (e + 1)) - 1u)) & ~((1u << a) - 1u);
                         __hip_atomic_fetch_or(&dil[w * TW + c], rm, __ATOMIC_RELAXED,
@@ -1459,27 +1464,46 @@ struct PhaseClock {
 // SP: tiles with at most kTilePeaks peaks list them for the peak-list retention (the plan's
 // choice for sparse grids and the relative threshold; compiled out otherwise, where it only
 // costs).
-template <int NW, int G, bool PER, bool SP>
-__global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_batch(GridArgs g, BatchArgs a, int n_tiles, int nwords) {
+// WIN: the tile holds a window of `win` rho rows (a multiple of 32) instead of the whole
+// column.  The hits of an event vote only into the rows their radius lets them reach (|rho| is at
+// most 1 / sqrt(x^2 + y^2) in every column), so each event is given the window [wb, wb + win)
+// (wb a multiple of 16) that covers those rows; the rows outside are zero, cannot hold a peak
+// and are never looked up.  Tile row r holds grid row wb - 1 + r: one zero halo row on each
+// side, then the out-of-grid columns' dummy row.  The peak and dilated words stay aligned to
+// the grid's 32-row words (those the window touches, plus one zero row), so retention looks
+// up grid rows exactly as without a window.  An event whose hits reach beyond the window is
+// left to the spill kernel (kStatusSpill).  A smaller tile lets more workgroups share a CU,
+// which is what the window is for: on the paper's grid (rho range twice the reach of hits at
+// 200 mm and beyond) half of the 1000 rows are enough.
+// Launch bounds: a windowed tile exists to fit two or three workgroups of at most 8 waves on a
+// CU, so 4 waves per SIMD are enough for it and leave it registers to spare.
+template <int NW, int G, bool PER, bool SP, bool WIN>
+__global__ __launch_bounds__(NW * 64, (NW == 16 || WIN) ? 4 : (G == 1 ? 6 : 4)) void k_batch(GridArgs g, BatchArgs a,
+                                                                                            int n_tiles, int nwords,
+                                                                                            int win) {
     using L = Lane<G, true>;
     constexpr int TW = L::TW, ST = L::STRIDE, OUT = TW - 2, NT = NW * 64;
+    static_assert(!WIN || (G == 1 && !PER), "windowed tiles: one column group, theta not periodic");
     extern __shared__ __align__(16) uint32_t lds[];
-    uint32_t *tile = lds;                                                  // [(n_rho + 1) * ST]
-    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)(g.n_rho + 1) * ST);   // [NW * 64]
-    uint32_t *pmask = reinterpret_cast<uint32_t *>(stage + NW * 64);       // [nwords * TW]
-    uint32_t *dil = pmask + (size_t)nwords * TW;                           // [(nwords + 1) * TW]
-    float4 *tpk = reinterpret_cast<float4 *>(dil + (size_t)(nwords + 1) * TW);   // [kTilePeaks]
+    // tile rows (dummy row included) and peak-word rows of the LDS layout
+    const int rows_t = WIN ? win + 3 : g.n_rho + 1;
+    const int nwp = WIN ? win / 32 + 1 : nwords;
+    uint32_t *tile = lds;                                                  // [rows_t * ST]
+    float2 *stage = reinterpret_cast<float2 *>(tile + (size_t)rows_t * ST);   // [NW * 64]
+    uint32_t *pmask = reinterpret_cast<uint32_t *>(stage + NW * 64);       // [nwp * TW]
+    uint32_t *dil = pmask + (size_t)nwp * TW;                              // [(nwp + 1) * TW]
+    float4 *tpk = reinterpret_cast<float4 *>(dil + (size_t)(nwp + 1) * TW);   // [kTilePeaks]
     uint32_t *colcnt = reinterpret_cast<uint32_t *>(tpk + kTilePeaks);            // [TW] peaks per column
-    __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept, s_max;
+    __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept, s_max, s_minr2, s_wb, s_fit;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const L ln(lane);
-    const int tile_words4 = (g.n_rho + 1) * ST / 4;
+    const int tile_words4 = rows_t * ST / 4;
 
     // the tile is all zero at the start of every tile; the dil row past the last word is read
     // by the out-of-grid columns' dummy row and stays zero
     for (int i = threadIdx.x; i < tile_words4; i += NT)
         reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
-    for (int i = threadIdx.x; i < TW; i += NT) dil[nwords * TW + i] = 0u;
+    for (int i = threadIdx.x; i < TW; i += NT) dil[nwp * TW + i] = 0u;
     for (int i = threadIdx.x; i < TW; i += NT) colcnt[i] = 0u;   // zero again after each listing
     PhaseClock pc;
     pc.start();
@@ -1493,6 +1517,7 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
             s_nvalid = 0u;
             s_nkept = 0u;
             s_max = 0u;
+            s_minr2 = __float_as_uint(FLT_MAX);
         }
         __syncthreads();
         pc.mark(kPhasePop);
@@ -1517,12 +1542,12 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
             continue;
         }
         const uint32_t H = h1 - h0;
-        if (H > kMaxBatchHits || H == 0u) {
+        if (H > kMaxBatchHits || H == 0u) {      // above the 16-bit counters: the spill kernel's
             uint8_t *ke = a.keep + (a.ids ? a.keep_offsets[e] : h0);
             for (uint32_t i = threadIdx.x; i < H; i += NT) ke[i] = 0u;
             if (threadIdx.x == 0) {
                 a.n_peaks[e] = 0u;
-                a.status[e] = H ? HOUGH_EV_TOO_MANY_HITS : 0u;
+                a.status[e] = H ? kStatusSpill : 0u;
             }
             __syncthreads();
             continue;
@@ -1541,6 +1566,51 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
         } else if (H > kDedupMaxHits && threadIdx.x == 0) {
             atomicOr(&s_flags, HOUGH_EV_DEDUP_SKIPPED);
         }
+        // the event's rho window: the smallest r2 = x^2 + y^2 among its valid hits (the same
+        // float expression as the map's) bounds every bin they vote into, |t - B| <= wA / sqrt(r2)
+        // with wA the largest |(C_j, S_j)|; the float map and the two fmas of t add a few 2^-24
+        // relative, far inside the 1e-6 and 1e-5 margins kept here.  Rows are floor(t), so the
+        // floors of the bounds are the first and last rows a vote can reach.
+        int wb = 0;
+        if constexpr (WIN) {
+            uint32_t mn = __float_as_uint(FLT_MAX);
+#pragma unroll 1
+            for (uint32_t i = hb + lane; i < he; i += 64) {
+                const float xi = xe[i], yi = ye[i];
+                const float r2 = __builtin_fmaf(xi, xi, yi * yi);
+                if (r2 > 0.0f && r2 <= FLT_MAX) mn = min(mn, __float_as_uint(r2));   // r2 > 0: bits order as values
+            }
+            mn = wave_min(mn);
+            if (lane == 0) atomicMin(&s_minr2, mn);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const double rmax = (1.0 + 1e-6) / sqrt((double)__uint_as_float(s_minr2));
+                const double span = g.wA * rmax, slack = 1e-5 * (fabs(g.wB) + span) + 1e-3;
+                const double lo = g.wB - span - slack, hi = g.wB + span + slack;
+                const double top = (double)(g.n_rho - 1);
+                const int klo = lo <= 0.0 ? 0 : (lo >= top ? g.n_rho - 1 : (int)lo);
+                const int khi = hi <= 0.0 ? 0 : (hi >= top ? g.n_rho - 1 : (int)hi);
+                const int b0 = (klo / 16) * 16;
+                s_wb = (uint32_t)b0;
+                s_fit = khi < b0 + win ? 1u : 0u;
+            }
+            __syncthreads();
+            wb = __builtin_amdgcn_readfirstlane((int)s_wb);
+            if (__builtin_amdgcn_readfirstlane((int)s_fit) == 0) {
+                // leave it to the spill kernel (its keep bytes are clear, or hold the duplicate
+                // pass's marks, which the spill kernel reads)
+                if (threadIdx.x == 0) { a.n_peaks[e] = 0u; a.status[e] = kStatusSpill; }
+                __syncthreads();
+                continue;
+            }
+        }
+        // grid row k of the window lives in tile row k - wb + 1; grid word w of the peak and
+        // dilated words in word row w - wb / 32
+        uint32_t *tile_w = WIN ? tile + (ptrdiff_t)(1 - wb) * ST : tile;
+        uint32_t *pmask_w = WIN ? pmask - (ptrdiff_t)(wb >> 5) * TW : pmask;
+        uint32_t *dil_w = WIN ? dil - (ptrdiff_t)(wb >> 5) * TW : dil;
+        const int w_lo = WIN ? (wb >> 5) : 0;
+        const float dummy_row = WIN ? (float)(wb + win + 1) : -1.0f;
         uint32_t thr = g.threshold;
         if (a.frac_den) {
             // relative threshold: a first pass votes every tile only to find the event's
@@ -1548,17 +1618,18 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
             uint32_t mloc = 0, bad0 = 0;
 #pragma unroll 1
             for (int t = 0; t < n_tiles; ++t) {
-                const Cols<G> cl = load_cols<G, PER>(g, t * OUT - 1, lane, ST, ln.col);
-                (void)vote_range<G, true, PER>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad0,
+                const Cols<G> cl = load_cols<G, PER>(g, t * OUT - 1, lane, ST, ln.col, dummy_row);
+                (void)vote_range<G, true, PER>(tile_w, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad0,
                                                g.dedup ? ke : nullptr);
                 __syncthreads();
+                // every tile row but the dummy one (a window's halo rows stay zero)
 #pragma unroll 1
-                for (int i = threadIdx.x; i < g.n_rho * ST; i += NT) {
+                for (int i = threadIdx.x; i < (rows_t - 1) * ST; i += NT) {
                     const uint32_t d = tile[i];
                     mloc = max(mloc, max(d & 0xffffu, d >> 16));
                     tile[i] = 0u;
                 }
-                for (int i = g.n_rho * ST + threadIdx.x; i < (g.n_rho + 1) * ST; i += NT) tile[i] = 0u;
+                for (int i = (rows_t - 1) * ST + threadIdx.x; i < rows_t * ST; i += NT) tile[i] = 0u;
                 __syncthreads();
             }
             mloc = wave_max(mloc);
@@ -1577,28 +1648,34 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
         uint32_t unkept = he - hb;           // this wave's unkept hits after its last full pass
         for (int t = 0; t < n_tiles; ++t) {
             const int first = t * OUT - 1;      // grid column of lane 0 of group 0
-            const Cols<G> cl = load_cols<G, PER>(g, first, lane, ST, ln.col);
-            const uint32_t nv = vote_range<G, true, PER>(tile, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane, bad,
-                                                         g.dedup ? ke : nullptr);
+            const Cols<G> cl = load_cols<G, PER>(g, first, lane, ST, ln.col, dummy_row);
+            const uint32_t nv = vote_range<G, true, PER>(tile_w, stage + wave * 64, xe, ye, hb, he, cl, ln, g, lane,
+                                                         bad, g.dedup ? ke : nullptr);
             if (t == 0 && lane == 0 && nv) atomicAdd(&s_nvalid, nv);
             __syncthreads();
             pc.mark(kPhaseVote);
             if (t == 0) pc.count(kPhaseStagedHits, (uint64_t)s_nvalid * (uint64_t)n_tiles);
-            for (int u = wave; u < 2 * nwords; u += NW) {
+            // 16-row units of grid rows; a windowed tile tests the units inside its window (the
+            // halo rows above and below are in the tile, so no unit needs bounds tests) and
+            // writes zero for the other halves of the words it touches
+            for (int u = 2 * w_lo + wave; u < 2 * (w_lo + nwp); u += NW) {
                 uint32_t m[G];
-                const bool interior = u >= 1 && (u + 1) * kPeakRows < g.n_rho;
-                constexpr bool UR = NW == 16;      // launch bound of 4 waves per SIMD: registers to spare
-                if (PER && (t == 0 || t == n_tiles - 1)) {
+                const bool interior = WIN || (u >= 1 && (u + 1) * kPeakRows < g.n_rho);
+                constexpr bool UR = NW == 16 || WIN;     // launch bound of 4 waves per SIMD: registers to spare
+                if (WIN && (u * kPeakRows < wb || (u + 1) * kPeakRows > wb + win)) {
+#pragma unroll
+                    for (int q = 0; q < G; ++q) m[q] = 0u;
+                } else if (PER && (t == 0 || t == n_tiles - 1)) {
                     if (interior)
                         peak_rows<false, G, true, true, UR>(tile, u, g.n_rho, thr, ln, lane, m, first, g.n_theta);
                     else
                         peak_rows<true, G, true, true, UR>(tile, u, g.n_rho, thr, ln, lane, m, first, g.n_theta);
                 } else if (interior) {
-                    peak_rows<false, G, true, false, UR>(tile, u, g.n_rho, thr, ln, lane, m);
+                    peak_rows<false, G, true, false, UR>(tile_w, u, g.n_rho, thr, ln, lane, m);
                 } else {
-                    peak_rows<true, G, true, false, UR>(tile, u, g.n_rho, thr, ln, lane, m);
+                    peak_rows<true, G, true, false, UR>(tile_w, u, g.n_rho, thr, ln, lane, m);
                 }
-                uint16_t *pm16 = reinterpret_cast<uint16_t *>(pmask);
+                uint16_t *pm16 = reinterpret_cast<uint16_t *>(pmask_w);
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
                     const int c = 64 * q + lane;
@@ -1609,18 +1686,18 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
             }
             if (g.rho_window >= 32) {
 #pragma unroll 1
-                for (int i = threadIdx.x; i < nwords * TW; i += NT) dil[i] = 0u;
+                for (int i = threadIdx.x; i < nwp * TW; i += NT) dil[i] = 0u;
             }
             __syncthreads();
             pc.mark(kPhasePeaks);
             const uint32_t base = s_npeaks;
             uint32_t np;
             if constexpr (SP)
-                np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, pe, cap, base, ln, lane, wave,
-                                              NW, tpk, &cl, colcnt);
+                np = emit_and_dilate<G, true>(tile_w, pmask_w, dil_w, w_lo, nwp, first, g, pe, cap, base, ln, lane,
+                                              wave, NW, tpk, &cl, colcnt);
             else
-                np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, pe, cap, base, ln, lane, wave,
-                                              NW, nullptr, nullptr, colcnt);
+                np = emit_and_dilate<G, true>(tile_w, pmask_w, dil_w, w_lo, nwp, first, g, pe, cap, base, ln, lane,
+                                              wave, NW, nullptr, nullptr, colcnt);
             __syncthreads();
             pc.mark(kPhaseList);
             if (threadIdx.x == 0) s_npeaks = base + np;
@@ -1639,13 +1716,13 @@ __global__ __launch_bounds__(NW * 64, NW == 16 ? 4 : (G == 1 ? 6 : 4)) void k_ba
                     const uint32_t n = (uint32_t)__popcll(pd.live);
                     newly = (few && np * 9u < n * 7u + 10u)
                                 ? retain_pending_peaks(pd, tpk, np, xe, ye, ke, g, lane)
-                                : retain_pending<G>(pd, dil, stage + wave * 64, xe, ye, ke, cl, g, lane);
+                                : retain_pending<G>(pd, dil_w, stage + wave * 64, xe, ye, ke, cl, g, lane);
                 } else {
                     uint32_t left = 0;
                     const uint32_t chunks = (he - hb + 63u) >> 6;
                     newly = (few && np * 9u * chunks < unkept * 7u + chunks * 10u)
                                 ? retain_range_peaks(tpk, np, xe, ye, ke, hb, he, g, lane, left)
-                                : retain_range<G>(dil, stage + wave * 64, xe, ye, ke, hb, he, cl, g, lane, left);
+                                : retain_range<G>(dil_w, stage + wave * 64, xe, ye, ke, hb, he, cl, g, lane, left);
                     if (SP) unkept = left;
                     if (left <= 64u) build_pending(pd, stage + wave * 64, xe, ye, ke, hb, he, lane);
                 }
@@ -1801,7 +1878,7 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
             }
             __syncthreads();
             hough_peak *slot = sp.staged + ((size_t)e * T + t) * sp.tile_cap;
-            const uint32_t np = emit_and_dilate<G, true>(tile, pmask, dil, nwords, first, g, slot, sp.tile_cap,
+            const uint32_t np = emit_and_dilate<G, true>(tile, pmask, dil, 0, nwords, first, g, slot, sp.tile_cap,
                                                          0u, ln, lane, wave, NW);
             __syncthreads();
             if (threadIdx.x == 0) sp.counts[(size_t)e * T + t] = np;
@@ -2120,8 +2197,8 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
         }
         return;
     }
-    // only the events above kMaxBatchHits: the workgroups split the batch into blocks of
-    // kSpillThreads events and pick those out of each block
+    // only the events the fused or split kernel left: the workgroups split the batch into blocks
+    // of kSpillThreads events and pick those out of each block
     for (uint32_t b0 = blockIdx.x * kSpillThreads; b0 < a.n_events; b0 += gridDim.x * kSpillThreads) {
         if (threadIdx.x == 0) s_n = 0u;
         __syncthreads();
@@ -2129,7 +2206,8 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
         if (e < a.n_events) {
             const uint32_t pe_id = a.ids ? a.ids[e] : e;
             const uint32_t h0 = a.offsets[pe_id], h1 = a.offsets[pe_id + 1];
-            if (h1 >= h0 && h1 - h0 > kMaxBatchHits) s_list[atomicAdd(&s_n, 1u)] = e;
+            // left here by the fused kernel (kStatusSpill), or by the split form (above its limit)
+            if ((a.status[e] & kStatusSpill) || (h1 >= h0 && h1 - h0 > kMaxBatchHits)) s_list[atomicAdd(&s_n, 1u)] = e;
         }
         __syncthreads();
         const uint32_t n = uni(s_n);
@@ -2318,23 +2396,33 @@ int peak_block_waves(int n_rho, size_t lds_limit) {
     return 0;
 }
 
-size_t batch_lds_bytes(int n_rho, int waves, int groups) {
-    const size_t tw = 64u * groups, nwords = (size_t)(n_rho + 31) / 32;
-    return (size_t)(n_rho + 1) * (tw / 2) * 4 + (size_t)waves * kStageBytes + nwords * tw * 4 +
-           (nwords + 1) * tw * 4 + kTilePeaks * sizeof(float4) + tw * 4;
+// The fused kernel's dynamic LDS: the packed tile with its dummy row (a windowed tile: `win`
+// rows, a zero halo row on each side and the dummy row), the wave stages, the peak and dilated
+// words, the tile's peak list and the per-column peak counts.
+size_t batch_lds_bytes(int n_rho, int waves, int groups, int win) {
+    const size_t tw = 64u * groups;
+    const size_t rows = win ? (size_t)win + 3 : (size_t)n_rho + 1;
+    const size_t nwords = win ? (size_t)win / 32 + 1 : (size_t)(n_rho + 31) / 32;
+    return rows * (tw / 2) * 4 + (size_t)waves * kStageBytes + nwords * tw * 4 + (nwords + 1) * tw * 4 +
+           kTilePeaks * sizeof(float4) + tw * 4;
 }
 
-int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out) {
+int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out, int win) {
     if (!(waves == 4 || waves == 6 || waves == 8 || waves == 12 || waves == 16) || !(groups == 1 || groups == 2)) return -1;
+    // a window is a whole number of 32-row words, one column group, shorter than the grid
+    if (win != 0 && (groups != 1 || win < 32 || win % 32 != 0 || win >= n_rho)) return -1;
     BatchPlan p{};
     p.waves = waves;
     p.groups = groups;
     p.tile_cols = 64 * groups;
     p.out_cols = p.tile_cols - 2;
     p.n_tiles = (n_theta + p.out_cols - 1) / p.out_cols;
-    p.lds_bytes = batch_lds_bytes(n_rho, waves, groups);
+    p.win = win;
+    p.lds_bytes = batch_lds_bytes(n_rho, waves, groups, win);
+    p.split_lds_bytes = batch_lds_bytes(n_rho, waves, groups, 0);
     p.sparse = n_rho >= kSparseRhoRows ? 1 : 0;
-    if (p.lds_bytes + 256 > lds_limit) return -1;      // room for the kernel's static LDS
+    // room for the kernel's static LDS; the split form always holds the whole column
+    if (p.lds_bytes + 256 > lds_limit || p.split_lds_bytes + 256 > lds_limit) return -1;
     p.grid = 0;
     *out = p;
     return 0;
@@ -2540,17 +2628,25 @@ hipError_t launch_batch_iterative(const GridArgs &g, const BatchArgs &a, uint16_
 template <int NW, int G, bool SP>
 static void launch_batch_sp(const GridArgs &g, const BatchPlan &p, const BatchArgs &a, hipStream_t s) {
     const int nwords = (g.n_rho + 31) / 32;
+    if constexpr (G == 1) {
+        if (p.win) {
+            hipLaunchKernelGGL((k_batch<NW, G, false, SP, true>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
+                               p.n_tiles, nwords, p.win);
+            return;
+        }
+    }
     if (g.periodic)
-        hipLaunchKernelGGL((k_batch<NW, G, true, SP>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
-                           p.n_tiles, nwords);
+        hipLaunchKernelGGL((k_batch<NW, G, true, SP, false>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
+                           p.n_tiles, nwords, 0);
     else
-        hipLaunchKernelGGL((k_batch<NW, G, false, SP>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
-                           p.n_tiles, nwords);
+        hipLaunchKernelGGL((k_batch<NW, G, false, SP, false>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a,
+                           p.n_tiles, nwords, 0);
 }
 
 template <int NW, int G>
 static hipError_t launch_batch_t(const GridArgs &g, const BatchPlan &p, const BatchArgs &a,
                                  hipStream_t s) {
+    if (p.win && (G != 1 || g.periodic)) return hipErrorInvalidValue;   // no such plan is made
     // a relative threshold leaves few peaks per tile whatever the grid
     if (p.sparse || a.frac_den != 0u)
         launch_batch_sp<NW, G, true>(g, p, a, s);
@@ -2580,11 +2676,11 @@ static hipError_t launch_split_t(const GridArgs &g, const BatchPlan &p, const Ba
                                  const SplitArgs &sp, hipStream_t s) {
     const int nwords = (g.n_rho + 31) / 32;
     if (g.periodic)
-        hipLaunchKernelGGL((k_batch_split<NW, G, true>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a, sp,
-                           nwords);
+        hipLaunchKernelGGL((k_batch_split<NW, G, true>), dim3(p.grid), dim3(NW * 64), p.split_lds_bytes, s, g, a,
+                           sp, nwords);
     else
-        hipLaunchKernelGGL((k_batch_split<NW, G, false>), dim3(p.grid), dim3(NW * 64), p.lds_bytes, s, g, a, sp,
-                           nwords);
+        hipLaunchKernelGGL((k_batch_split<NW, G, false>), dim3(p.grid), dim3(NW * 64), p.split_lds_bytes, s, g, a,
+                           sp, nwords);
     return hipGetLastError();
 }
 
@@ -2646,42 +2742,59 @@ bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *w
     return true;
 }
 
-template <int NW, int G>
-static int prepare_t(size_t lds, size_t) {
-    // both grid topologies and both forms: a context's plan serves whichever kernel it launches
-    allow_lds(k_batch<NW, G, false, false>);
-    allow_lds(k_batch<NW, G, true, false>);
-    allow_lds(k_batch<NW, G, false, true>);
-    allow_lds(k_batch<NW, G, true, true>);
-    allow_lds(k_batch_split<NW, G, false>);
-    allow_lds(k_batch_split<NW, G, true>);
-    int n[6] = {0, 0, 0, 0, 0, 0};
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[0], k_batch<NW, G, false, false>, NW * 64, lds) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[1], k_batch<NW, G, true, false>, NW * 64, lds) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[2], k_batch<NW, G, false, true>, NW * 64, lds) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[3], k_batch<NW, G, true, true>, NW * 64, lds) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[4], k_batch_split<NW, G, false>, NW * 64, lds) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n[5], k_batch_split<NW, G, true>, NW * 64, lds) != hipSuccess)
-        return 0;
-    int m = n[0];
-    for (int i = 1; i < 6; ++i) m = n[i] < m ? n[i] : m;
-    return m;
+template <typename K>
+static int occupancy(K kernel, int threads, size_t lds) {
+    int n = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, lds) == hipSuccess ? n : 0;
 }
 
-// Allow the plan's dynamic LDS for its kernel and return how many of its workgroups fit a CU
-// (0 if none).  Done once when a plan is chosen, so that launches make no other runtime calls.
-int prepare_batch(const BatchPlan &p, size_t lds_limit) {
-    switch (p.waves * 10 + p.groups) {
-        case 41: return prepare_t<4, 1>(p.lds_bytes, lds_limit);
-        case 42: return prepare_t<4, 2>(p.lds_bytes, lds_limit);
-        case 61: return prepare_t<6, 1>(p.lds_bytes, lds_limit);
-        case 62: return prepare_t<6, 2>(p.lds_bytes, lds_limit);
-        case 81: return prepare_t<8, 1>(p.lds_bytes, lds_limit);
-        case 82: return prepare_t<8, 2>(p.lds_bytes, lds_limit);
-        case 121: return prepare_t<12, 1>(p.lds_bytes, lds_limit);
-        case 122: return prepare_t<12, 2>(p.lds_bytes, lds_limit);
-        case 161: return prepare_t<16, 1>(p.lds_bytes, lds_limit);
-        case 162: return prepare_t<16, 2>(p.lds_bytes, lds_limit);
+template <int NW, int G>
+static int prepare_t(BatchPlan *p) {
+    // both grid topologies and both forms: a context's plan serves whichever kernel it launches
+    allow_lds(k_batch<NW, G, false, false, false>);
+    allow_lds(k_batch<NW, G, true, false, false>);
+    allow_lds(k_batch<NW, G, false, true, false>);
+    allow_lds(k_batch<NW, G, true, true, false>);
+    allow_lds(k_batch_split<NW, G, false>);
+    allow_lds(k_batch_split<NW, G, true>);
+    const int T = NW * 64;
+    const size_t full = p->split_lds_bytes;
+    int split = occupancy(k_batch_split<NW, G, false>, T, full);
+    split = std::min(split, occupancy(k_batch_split<NW, G, true>, T, full));
+    int fused = 0;
+    if constexpr (G == 1) {
+        if (p->win) {
+            allow_lds(k_batch<NW, 1, false, false, true>);
+            allow_lds(k_batch<NW, 1, false, true, true>);
+            fused = std::min(occupancy(k_batch<NW, 1, false, false, true>, T, p->lds_bytes),
+                             occupancy(k_batch<NW, 1, false, true, true>, T, p->lds_bytes));
+        }
+    }
+    if (!p->win) {
+        fused = std::min(occupancy(k_batch<NW, G, false, false, false>, T, full),
+                         occupancy(k_batch<NW, G, true, false, false>, T, full));
+        fused = std::min(fused, std::min(occupancy(k_batch<NW, G, false, true, false>, T, full),
+                                         occupancy(k_batch<NW, G, true, true, false>, T, full)));
+    }
+    p->split_per_cu = split;
+    return fused;
+}
+
+// Allow the plan's dynamic LDS for its kernels and return how many of the fused kernel's
+// workgroups fit a CU (0 if none; split_per_cu gets the split form's).  Done once when a plan is
+// chosen, so that launches make no other runtime calls.
+int prepare_batch(BatchPlan *p) {
+    switch (p->waves * 10 + p->groups) {
+        case 41: return prepare_t<4, 1>(p);
+        case 42: return prepare_t<4, 2>(p);
+        case 61: return prepare_t<6, 1>(p);
+        case 62: return prepare_t<6, 2>(p);
+        case 81: return prepare_t<8, 1>(p);
+        case 82: return prepare_t<8, 2>(p);
+        case 121: return prepare_t<12, 1>(p);
+        case 122: return prepare_t<12, 2>(p);
+        case 161: return prepare_t<16, 1>(p);
+        case 162: return prepare_t<16, 2>(p);
         default: return 0;
     }
 }

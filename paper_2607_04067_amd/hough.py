@@ -33,7 +33,7 @@ class HoughError(RuntimeError):
 
 class hough_batch_plan(ctypes.Structure):
     _fields_ = [("waves_per_group", ctypes.c_int32), ("column_groups", ctypes.c_int32),
-                ("groups_per_cu", ctypes.c_int32), ("lds_bytes", ctypes.c_int32)]
+                ("groups_per_cu", ctypes.c_int32), ("lds_bytes", ctypes.c_int32), ("window_rows", ctypes.c_int32)]
 
 
 class hough_params(ctypes.Structure):
@@ -229,7 +229,7 @@ class Context:
         p = hough_batch_plan()
         _check(self._lib.hough_get_batch_plan(self._ctx, ctypes.byref(p)), "hough_get_batch_plan")
         return {"waves_per_group": p.waves_per_group, "column_groups": p.column_groups,
-                "groups_per_cu": p.groups_per_cu, "lds_bytes": p.lds_bytes}
+                "groups_per_cu": p.groups_per_cu, "lds_bytes": p.lds_bytes, "window_rows": p.window_rows}
 
     def set_batch_plan(self, waves_per_group: int, column_groups: int, groups_per_cu: int = 0) -> None:
         _check(self._lib.hough_set_batch_plan(self._ctx, int(waves_per_group), int(column_groups),

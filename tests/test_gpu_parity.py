@@ -462,6 +462,114 @@ def test_every_launch_plan_gives_identical_results(H):
         ctx.close()
 
 
+def _paper_grid_events():
+    """Paper-grid workload events, then events whose hits reach beyond a 512-row window (radii
+    from 150 mm: the spill path), sit inside it at its edges, or need only a few rows."""
+    wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
+    ev = synth.make_events(wl, 9, n_events=8)
+    evs = [ev.event(e) for e in range(ev.n_events)] + _edge_events()
+    for seed, lo, hi in [(11, 700.0, 810.0), (12, 200.0, 200.5), (13, 450.0, 460.0)]:
+        evs.append(synth.random_hits(400, seed=seed, r_lo=lo, r_hi=hi))
+    # tracks plus hits at 120-190 mm: beyond any 512-row window, peaks and kept hits all the same
+    xr, yr = synth.random_hits(60, seed=14, r_lo=120.0, r_hi=190.0)
+    evs.insert(3, (np.concatenate([evs[0][0], xr]), np.concatenate([evs[0][1], yr])))
+    evs.insert(5, synth.random_hits(500, seed=15, r_lo=120.0, r_hi=810.0))
+    x = np.concatenate([a for a, _ in evs]).astype(np.float32)
+    y = np.concatenate([b for _, b in evs]).astype(np.float32)
+    off = np.zeros(len(evs) + 1, np.uint32)
+    off[1:] = np.cumsum([a.size for a, _ in evs])
+    return wl, x, y, off
+
+
+WINDOW_PLANS = [(8, 1, 2), (4, 1, 2), (6, 1, 2), (4, 1, 3)]
+
+
+def test_windowed_tile_plans_equal_the_oracle(H, orc):
+    """Plans with more workgroups per CU than a whole 1000-row column allows hold a window of
+    rows per event; every event (those whose rows do not fit go through the spill path) equals
+    the oracle, with fixed and relative thresholds, wide retention windows and gathered."""
+    import torch
+    wl, x, y, off = _paper_grid_events()
+    g = orc.Grid.of(wl)
+    E = len(off) - 1
+    xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
+    seen = 0
+    for W in (1, 40):
+        ctx = H.Context.for_workload(wl, rho_window=W, max_peaks=8192)
+        assert ctx.batch_plan["window_rows"] == 0                  # the default holds the column
+        for plan in WINDOW_PLANS:
+            try:
+                ctx.set_batch_plan(*plan)
+            except H.HoughError:
+                continue
+            bp = ctx.batch_plan
+            say(f"windowed plan {plan} W={W} -> {bp}")
+            assert bp["window_rows"] > 0 and bp["window_rows"] % 32 == 0 and bp["groups_per_cu"] == plan[2]
+            seen += 1
+            st = _batch_check(H, orc, ctx, g, wl.threshold, W, x, y, off, 8192)
+            assert np.all((st & ~(H.EV_INVALID_HITS | H.EV_PEAKS_TRUNCATED)) == 0), st
+            assert int(ctx.run_batch(xt, yt, ot)[1][3]) > 0      # the spilled event has peaks
+            pk, npk, keep, st = ctx.run_batch(xt, yt, ot, frac=(1, 2))
+            torch.cuda.synchronize()
+            pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=wl.threshold, rho_window=W, cap=8192,
+                                                    n_threads=8, frac=(1, 2))
+            assert np.array_equal(npk.cpu().numpy()[:E].astype(np.int64), n_ref)
+            assert np.array_equal(keep.cpu().numpy(), keep_ref)
+            p = pk.cpu().numpy()
+            for e in range(E):
+                m = int(min(n_ref[e], 8192))
+                assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), e
+            # gathered in reverse order, and the split form (whole column) beside it
+            sizes = np.diff(off.astype(np.int64))
+            ids = np.arange(E)[::-1].copy()
+            koff = np.concatenate([[0], np.cumsum(sizes[ids])[:-1]]).astype(np.int32)
+            plain = ctx.run_batch(xt, yt, ot)
+            gk = ctx.run_batch_gather(xt, yt, ot, _t(ids.astype(np.int32)), _t(koff), keep_size=int(sizes.sum()))
+            sp = ctx.run_batch_split(xt, yt, ot)
+            torch.cuda.synchronize()
+            assert all(torch.equal(a, b) for a, b in zip(sp, plain))
+            kp, kg = plain[2].cpu().numpy(), gk[2].cpu().numpy()
+            for j, e in enumerate(ids):
+                assert int(gk[1][j]) == int(plain[1][e]) and int(gk[3][j]) == int(plain[3][e]), e
+                assert np.array_equal(kg[koff[j]:koff[j] + sizes[e]], kp[off[e]:off[e + 1]]), e
+        ctx.close()
+    assert seen >= 2
+
+
+def test_windowed_tile_with_duplicate_suppression(H, orc):
+    import torch
+    wl, x, y, off = _paper_grid_events()
+    g = orc.Grid.of(wl)
+    E = len(off) - 1
+    ctx = H.Context.for_workload(wl, max_peaks=8192, dedup=True)
+    ctx.set_batch_plan(8, 1, 2)
+    assert ctx.batch_plan["window_rows"] > 0
+    pk, npk, keep, st = ctx.run_batch(_t(x), _t(y), _t(off.astype(np.int32)))
+    torch.cuda.synchronize()
+    pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=wl.threshold, rho_window=1, cap=8192,
+                                            n_threads=8, dedup=True)
+    assert np.array_equal(npk.cpu().numpy()[:E].astype(np.int64), n_ref)
+    assert np.array_equal(keep.cpu().numpy(), keep_ref)
+    p = pk.cpu().numpy()
+    for e in range(E):
+        m = int(min(n_ref[e], 8192))
+        assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), e
+    ctx.close()
+
+
+def test_windowed_plans_refused_where_no_window_helps(H):
+    # a periodic grid and two column groups have no windowed form; the context keeps its plan
+    wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
+    ctx = H.Context.for_workload(wl, periodic=True)
+    before = ctx.batch_plan
+    with pytest.raises(H.HoughError):
+        ctx.set_batch_plan(8, 1, 2)
+    with pytest.raises(H.HoughError):
+        ctx.set_batch_plan(8, 2, 2)
+    assert ctx.batch_plan == before
+    ctx.close()
+
+
 def test_autotune_keeps_results(H, tmp_path):
     import torch
     from paper_2607_04067_amd import autotune
