@@ -362,6 +362,27 @@ __device__ __forceinline__ void peak_rows(const uint32_t *tile, int unit, int n_
     }
 }
 
+// True when no count of the 16-row unit `unit` reaches T (then it holds no peak).  The unit's
+// rows are contiguous in the packed tile, so the wave reads them whole, 16 bytes per lane per
+// read, and takes the maximum of each lane's 16-bit counts: a few instructions where the 3x3
+// test reads and compares every row.
+template <int G>
+__device__ __forceinline__ bool unit_below(const uint32_t *tile, int unit, uint32_t T, int lane) {
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    constexpr int ST = Lane<G, true>::STRIDE, READS = ST * kPeakRows / 4 / 64;
+    const uint4 *p = reinterpret_cast<const uint4 *>(tile + unit * kPeakRows * ST) + lane;
+    u16x2 m = {0, 0};
+#pragma unroll
+    for (int i = 0; i < READS; ++i) {
+        const uint4 v = p[64 * i];
+        const u16x2 a = __builtin_elementwise_max(__builtin_bit_cast(u16x2, v.x), __builtin_bit_cast(u16x2, v.y));
+        const u16x2 b = __builtin_elementwise_max(__builtin_bit_cast(u16x2, v.z), __builtin_bit_cast(u16x2, v.w));
+        m = __builtin_elementwise_max(m, __builtin_elementwise_max(a, b));
+    }
+    const uint32_t mx = max((uint32_t)m.x, (uint32_t)m.y);
+    return __ballot(mx >= T) == 0ull;
+}
+
 // Inclusive prefix sum over the 64 lanes with DPP row shifts and row broadcasts (no LDS).
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int) {
     v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true);   // row_shr:1
@@ -524,7 +545,12 @@ __device__ __forceinline__ uint64_t lookup_staged(const uint32_t *dil, const flo
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int q = 0; q < G; ++q) acc |= __builtin_amdgcn_ubfe(wd[i][q], kk[i][q], 1u) << (sh + i);
+            for (int q = 0; q < G; ++q) {
+                // one shift-or per bit (the empty asm keeps the compiler from regrouping the ORs
+                // into separate shifts and three-input ORs)
+                acc |= __builtin_amdgcn_ubfe(wd[i][q], kk[i][q], 1u) << (sh + i);
+                asm("" : "+v"(acc));
+            }
     };
     for (; h + 4 <= n.safe && h < 32; h += 4) four(w[0], h);
     for (; h + 4 <= n.safe; h += 4) four(w[1], h - 32);
@@ -1646,6 +1672,9 @@ __global__ __launch_bounds__(NW * 64, (NW == 16 || WIN) ? 4 : (G == 1 ? 6 : 4)) 
         pd.live = 0ull;
         pd.on = false;
         uint32_t unkept = he - hb;           // this wave's unkept hits after its last full pass
+        // sparse event (under a quarter of the threshold per cell on average): most peak units
+        // hold no count that reaches it, so each unit is first tested whole (unit_below)
+        const bool sparse_ev = SP && (uint64_t)H * 4u < (uint64_t)thr * (uint32_t)g.n_rho;
         for (int t = 0; t < n_tiles; ++t) {
             const int first = t * OUT - 1;      // grid column of lane 0 of group 0
             const Cols<G> cl = load_cols<G, PER>(g, first, lane, ST, ln.col, dummy_row);
@@ -1662,7 +1691,8 @@ __global__ __launch_bounds__(NW * 64, (NW == 16 || WIN) ? 4 : (G == 1 ? 6 : 4)) 
                 uint32_t m[G];
                 const bool interior = WIN || (u >= 1 && (u + 1) * kPeakRows < g.n_rho);
                 constexpr bool UR = NW == 16 || WIN;     // launch bound of 4 waves per SIMD: registers to spare
-                if (WIN && (u * kPeakRows < wb || (u + 1) * kPeakRows > wb + win)) {
+                if ((WIN && (u * kPeakRows < wb || (u + 1) * kPeakRows > wb + win)) ||
+                    (sparse_ev && interior && !(PER && (t == 0 || t == n_tiles - 1)) && unit_below<G>(tile_w, u, thr, lane))) {
 #pragma unroll
                     for (int q = 0; q < G; ++q) m[q] = 0u;
                 } else if (PER && (t == 0 || t == n_tiles - 1)) {
