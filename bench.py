@@ -85,7 +85,8 @@ def profiled_traffic(workload: str, plan):
         return None
     rec = json.loads(text[start + 7:text.index("```", start + 7)])
     cur = [plan["waves_per_group"], plan["column_groups"], plan["groups_per_cu"]]
-    if rec.get("source") != kernel_source_id() or rec.get("plan") != cur:
+    if (rec.get("source") != kernel_source_id() or rec.get("plan") != cur
+            or rec.get("window_rows", 0) != plan.get("window_rows", 0)):
         return None
     return rec
 

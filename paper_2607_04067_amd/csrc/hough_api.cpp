@@ -459,6 +459,9 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     a.frac_num = frac_num;
     a.frac_den = frac_den;
     hough::SpillArgs spill{c->d_spill, c->spill_stride, c->d_work + 2, c->fused ? 0u : 1u};
+    // fused contexts: the fused (or split) kernel counts the events it leaves to the spill kernel
+    // in the spill kernel's first counter, so that the spill kernel skips its scan when none
+    a.spill_count = c->fused ? c->d_work + 2 : nullptr;
     hipError_t e = hipSuccess;
     if (!c->fused) {
         // the grid's column does not fit the fused kernel's tile: every event, in device memory

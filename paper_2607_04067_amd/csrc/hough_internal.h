@@ -81,6 +81,8 @@ struct BatchArgs {
     uint32_t *queue;     // [2] work counter and exit counter (device, zero between launches)
     uint32_t frac_num;   // fused kernel: frac_den != 0 takes each event's threshold as
     uint32_t frac_den;   // max(threshold, ceil(event maximum * frac_num / frac_den))
+    uint32_t *spill_count;   // null, or a counter of the events left to the spill kernel
+                             // (zero between launches; the spill kernel clears it)
 };
 
 // Workspace of the split form (one workgroup per theta tile of an event), laid out by

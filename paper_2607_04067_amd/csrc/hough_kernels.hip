@@ -1574,6 +1574,7 @@ __global__ __launch_bounds__(NW * 64, (NW == 16 || WIN) ? 4 : (G == 1 ? 6 : 4)) 
             if (threadIdx.x == 0) {
                 a.n_peaks[e] = 0u;
                 a.status[e] = H ? kStatusSpill : 0u;
+                if (H && a.spill_count) atomicAdd(a.spill_count, 1u);
             }
             __syncthreads();
             continue;
@@ -1625,7 +1626,11 @@ __global__ __launch_bounds__(NW * 64, (NW == 16 || WIN) ? 4 : (G == 1 ? 6 : 4)) 
             if (__builtin_amdgcn_readfirstlane((int)s_fit) == 0) {
                 // leave it to the spill kernel (its keep bytes are clear, or hold the duplicate
                 // pass's marks, which the spill kernel reads)
-                if (threadIdx.x == 0) { a.n_peaks[e] = 0u; a.status[e] = kStatusSpill; }
+                if (threadIdx.x == 0) {
+                    a.n_peaks[e] = 0u;
+                    a.status[e] = kStatusSpill;
+                    if (a.spill_count) atomicAdd(a.spill_count, 1u);
+                }
                 __syncthreads();
                 continue;
             }
@@ -1868,7 +1873,10 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
         uint32_t *bits = sp.kept + (size_t)e * kSplitKeepWords;
         uint8_t *ke = a.keep + (a.ids ? (uint32_t)__builtin_amdgcn_readfirstlane((int)a.keep_offsets[e]) : h0);
         if (malformed || H > kMaxBatchHits) {
-            if (threadIdx.x == 0 && t == 0) s_flags = HOUGH_EV_TOO_MANY_HITS;
+            if (threadIdx.x == 0 && t == 0) {
+                s_flags = HOUGH_EV_TOO_MANY_HITS;
+                if (!malformed && a.spill_count) atomicAdd(a.spill_count, 1u);
+            }
         } else if (H > 0) {
             if (g.dedup && H > kDedupMaxHits && threadIdx.x == 0 && t == 0) atomicOr(&s_flags, HOUGH_EV_DEDUP_SKIPPED);
             const uint32_t hb = (uint32_t)((uint64_t)H * wave / NW);
@@ -2227,9 +2235,14 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
         }
         return;
     }
-    // only the events the fused or split kernel left: the workgroups split the batch into blocks
-    // of kSpillThreads events and pick those out of each block
-    for (uint32_t b0 = blockIdx.x * kSpillThreads; b0 < a.n_events; b0 += gridDim.x * kSpillThreads) {
+    // only the events the fused or split kernel left (sp.queue[0] counts them; none: nothing to
+    // scan): the workgroups split the batch into blocks of kSpillThreads events and pick those
+    // out of each block.  The last workgroup to leave clears the count and its own exit counter.
+    if (threadIdx.x == 0) s_n = __hip_atomic_load(sp.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const bool any = uni(s_n) != 0u;
+    __syncthreads();
+    for (uint32_t b0 = blockIdx.x * kSpillThreads; any && b0 < a.n_events; b0 += gridDim.x * kSpillThreads) {
         if (threadIdx.x == 0) s_n = 0u;
         __syncthreads();
         const uint32_t e = b0 + threadIdx.x;
@@ -2243,6 +2256,10 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
         const uint32_t n = uni(s_n);
         for (uint32_t p = 0; p < n; ++p) process(uni(s_list[p]));   // events are independent: any order
         __syncthreads();
+    }
+    if (threadIdx.x == 0 && atomicAdd(sp.queue + 1, 1u) == gridDim.x - 1u) {
+        __hip_atomic_store(sp.queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(sp.queue + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

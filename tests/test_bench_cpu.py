@@ -38,13 +38,16 @@ def test_profile_records_are_consistent():
 def test_profiled_traffic_follows_source_and_plan():
     import bench
     for path, _, rec in _records():
-        plan = dict(zip(("waves_per_group", "column_groups", "groups_per_cu"), rec["plan"]))
+        plan = dict(zip(("waves_per_group", "column_groups", "groups_per_cu"), rec["plan"]),
+                    window_rows=rec.get("window_rows", 0))
         got = bench.profiled_traffic(rec["workload"], plan)
         if rec["source"] == bench.kernel_source_id():
             assert got is not None and got["traffic_bytes"] == rec["traffic_bytes"]
         else:
             assert got is None
         other = dict(plan, groups_per_cu=plan["groups_per_cu"] + 1)
+        assert bench.profiled_traffic(rec["workload"], other) is None
+        other = dict(plan, window_rows=plan["window_rows"] + 32)      # another tile height
         assert bench.profiled_traffic(rec["workload"], other) is None
     assert bench.profiled_traffic("no-such-workload", {"waves_per_group": 8, "column_groups": 1,
                                                        "groups_per_cu": 1}) is None
