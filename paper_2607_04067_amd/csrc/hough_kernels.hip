@@ -700,14 +700,20 @@ __device__ uint32_t retain_range_peaks(const float4 *tpk, uint32_t np, const flo
                                        uint32_t &left) {
     uint32_t newly = 0;
     left = 0;
+    // the keep bytes and hits of the next 64 are loaded while these are tested
+    uint32_t kn = 1u;
+    float xn = 0.0f, yn = 0.0f;
+    if (hb + lane < he) { kn = ke[hb + lane]; xn = x[hb + lane]; yn = y[hb + lane]; }
     for (uint32_t base = hb; base < he; base += 64) {
         const uint32_t i = base + lane;
-        const uint32_t kv = (i < he) ? ke[i] : 1u;
+        const uint32_t kv = kn;
+        const float xi = xn, yi = yn;
+        if (i + 64 < he) { kn = ke[i + 64]; xn = x[i + 64]; yn = y[i + 64]; }
         const bool cand = (i < he) && !(kv & 1u);
         if (__ballot(cand) == 0ull) continue;            // whole chunk already kept
         float u = 0.0f, v = 0.0f;
         bool valid = false, kept = false;
-        if (cand) valid = conformal(x[i], y[i], u, v);
+        if (cand) valid = conformal(xi, yi, u, v);
         if (valid) kept = kept_by_peaks(tpk, np, u, v, g);
         if (kept) ke[i] = (uint8_t)(kv | 1u);
         newly += (uint32_t)__popcll(__ballot(kept));

@@ -145,18 +145,31 @@ def simulate(trace: np.ndarray, hits: np.ndarray, models, n_streams: int = 8, ma
 
 
 def summarize(trace: np.ndarray, res: np.ndarray, warmup_us: float = 0.0) -> dict:
-    """p50/p99 latency (done - scheduled arrival), its split into waiting for a launch and the
-    launch-to-results service time, and the sustained rate over the measured window."""
+    """p50/p99/p99.9 latency (done - scheduled arrival), its split into waiting for a launch and
+    the launch-to-results service time, and the sustained rate over the measured window.  "tail"
+    describes the requests at or above the p99.9 latency: how much of their latency was waiting
+    and how much service, their batch sizes, and the arrival-time span they come from (one short
+    span: a single episode, such as a stall of the host loop; spread over the run: load)."""
     sel = trace["arrival_us"] >= warmup_us
     if not sel.any():
         return {}
-    lat = res["done_us"][sel] - trace["arrival_us"][sel]
-    wait = res["launch_us"][sel] - trace["arrival_us"][sel]
-    span = (res["done_us"][sel].max() - trace["arrival_us"][sel].min()) / 1e6
-    return {"requests": int(sel.sum()), "p50_us": round(float(np.percentile(lat, 50)), 1),
-            "p99_us": round(float(np.percentile(lat, 99)), 1),
-            "p99_9_us": round(float(np.percentile(lat, 99.9)), 1), "max_us": round(float(lat.max()), 1),
-            "p50_wait_us": round(float(np.percentile(wait, 50)), 1),
-            "p50_service_us": round(float(np.percentile(lat - wait, 50)), 1),
-            "events_per_s": round(float(sel.sum() / span), 1) if span > 0 else None,
-            "mean_batch": round(float(res["batch_events"][sel].mean()), 2)}
+    arr = trace["arrival_us"][sel]
+    lat = res["done_us"][sel] - arr
+    wait = res["launch_us"][sel] - arr
+    serv = lat - wait
+    span = (res["done_us"][sel].max() - arr.min()) / 1e6
+    r1 = lambda v: round(float(v), 1)
+    p999 = np.percentile(lat, 99.9)
+    t = lat >= p999
+    tail = {"requests": int(t.sum()), "mean_wait_us": r1(wait[t].mean()), "mean_service_us": r1(serv[t].mean()),
+            "mean_batch": round(float(res["batch_events"][sel][t].mean()), 2),
+            "arrival_ms": [r1(arr[t].min() / 1e3), r1(arr[t].max() / 1e3)],
+            "worst_arrival_ms": r1(arr[np.argmax(lat)] / 1e3)}
+    return {"requests": int(sel.sum()), "p50_us": r1(np.percentile(lat, 50)),
+            "p99_us": r1(np.percentile(lat, 99)), "p99_9_us": r1(p999), "max_us": r1(lat.max()),
+            "p50_wait_us": r1(np.percentile(wait, 50)), "p99_9_wait_us": r1(np.percentile(wait, 99.9)),
+            "max_wait_us": r1(wait.max()),
+            "p50_service_us": r1(np.percentile(serv, 50)), "p99_9_service_us": r1(np.percentile(serv, 99.9)),
+            "max_service_us": r1(serv.max()),
+            "events_per_s": r1(sel.sum() / span) if span > 0 else None,
+            "mean_batch": round(float(res["batch_events"][sel].mean()), 2), "tail": tail}

@@ -154,3 +154,23 @@ def test_invalid_traces_are_refused():
         serve.simulate(_trace([0.0], [0]), np.array([1]), m, n_streams=33)
     with pytest.raises(hough.HoughError):           # a batch that costs nothing
         serve.simulate(_trace([0.0], [0]), np.array([1]), [(0.0, 0.0, 0.0)])
+
+
+def test_summary_splits_the_tail_into_waiting_and_service():
+    """A simulated stall: one slot, steady arrivals, and a burst that queues behind one long
+    batch; the summary's tail is that episode, its latency mostly waiting."""
+    n = 2000
+    arr = np.arange(n) * 50.0
+    arr[1000:1040] = arr[1000]                       # a burst of 40 requests at once
+    tr = _trace(np.sort(arr), np.zeros(n, np.int64))
+    hits = np.full(n, 100)
+    res = serve.simulate(tr, hits, [(20.0, 30.0, 0.0)], n_streams=1, max_batch_events=4, max_batch_hits=1 << 20)
+    s = serve.summarize(tr, res)
+    assert s["requests"] == n and s["max_us"] >= s["p99_9_us"] >= s["p99_us"] >= s["p50_us"]
+    assert s["max_wait_us"] >= s["p99_9_wait_us"] and s["max_service_us"] >= s["p99_9_service_us"]
+    tail = s["tail"]
+    assert tail["requests"] >= 2
+    assert tail["mean_wait_us"] > tail["mean_service_us"]           # queued behind the burst
+    lo, hi = tail["arrival_ms"]
+    assert 49.0 <= lo <= hi <= 53.0                                   # the burst at 50 ms
+    assert 49.0 <= tail["worst_arrival_ms"] <= 53.0
