@@ -232,6 +232,17 @@ def plain_path(H, wl, ev, n_events: int = 200):
             "landed_vote_fraction": round(landed_frac, 5)}
 
 
+def flagged(H, status) -> int:
+    """Events with a status bit other than the peak buffer's truncation (which depends only on
+    the buffer the caller gives): invalid hits, refusals, skipped duplicate passes."""
+    return int(((np.asarray(status) & ~H.EV_PEAKS_TRUNCATED) != 0).sum())
+
+
+def truncated(H, status) -> int:
+    """Events with more peaks than the peak buffer holds (their counts are still the true ones)."""
+    return int(((np.asarray(status) & H.EV_PEAKS_TRUNCATED) != 0).sum())
+
+
 def iterative_path(H, wl, ev, n_events: int = 200, frac=(1, 2), r_theta: int = 5, r_rho: int = 5):
     """The paper's own peak finder on the per-event path: vote (accumulator in HBM), relative
     threshold + iterative extraction, retention against those peaks; three launches per event."""
@@ -239,7 +250,7 @@ def iterative_path(H, wl, ev, n_events: int = 200, frac=(1, 2), r_theta: int = 5
     ctx = H.Context.for_workload(wl)
     sub = ev.subset(np.arange(min(n_events, ev.n_events)))
     xt, yt, _ = H.to_device(sub)
-    cap = 1024
+    cap = MAX_PEAKS[wl.name]        # the batch path's peak buffer: truncation is the caller's choice
     dt_acc = torch.int16 if wl.acc == "u16" else torch.int32
     acc = torch.empty((wl.n_theta, wl.n_rho), dtype=dt_acc, device="cuda")
     peaks = torch.zeros((sub.n_events, cap, 2), dtype=torch.int32, device="cuda")
@@ -269,7 +280,8 @@ def iterative_path(H, wl, ev, n_events: int = 200, frac=(1, 2), r_theta: int = 5
            "events": sub.n_events, "ms_per_event": round(dt / sub.n_events * 1e3, 4),
            "events_per_s": round(sub.n_events / dt, 1),
            "peaks_per_event": round(float(npk.float().mean().item()), 2),
-           "flagged": int((st.cpu().numpy() != 0).sum()),
+           "flagged": flagged(H, st.cpu().numpy()), "truncated": truncated(H, st.cpu().numpy()),
+           "peak_buffer": cap,
            "R_c": round(float(k.mean()), 4) if k.size else None,
            "R_s": round(float(k[lab >= 0].mean()), 4) if (lab >= 0).any() else None}
 
@@ -290,7 +302,8 @@ def iterative_path(H, wl, ev, n_events: int = 200, frac=(1, 2), r_theta: int = 5
     kb = res[2].cpu().numpy()
     out["batch"] = {"events": ev.n_events, "ms": round(ms, 4), "events_per_s": round(ev.n_events / (ms / 1e3), 1),
                     "workspace_bytes": int(ws.numel()),
-                    "flagged": int((res[3].cpu().numpy()[:ev.n_events] != 0).sum()),
+                    "flagged": flagged(H, res[3].cpu().numpy()[:ev.n_events]),
+                    "truncated": truncated(H, res[3].cpu().numpy()[:ev.n_events]),
                     "R_c": round(float(kb.mean()), 4) if kb.size else None,
                     "R_s": round(float(kb[ev.labels >= 0].mean()), 4) if (ev.labels >= 0).any() else None}
     bctx.close()
