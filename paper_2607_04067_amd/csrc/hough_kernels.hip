@@ -417,7 +417,8 @@ __device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask,
                                     int nwords, int first_col, const GridArgs &g, hough_peak *out,
                                     uint32_t cap, uint32_t base, const Lane<G, P> &ln, int lane,
                                     int wave, int n_waves, float4 *tpk = nullptr,
-                                    const Cols<G> *cl = nullptr, const uint32_t *colcnt = nullptr) {
+                                    const Cols<G> *cl = nullptr, const uint32_t *colcnt = nullptr,
+                                    uint32_t *edge = nullptr) {
     constexpr int TW = 64 * G, ST = Lane<G, P>::STRIDE;
     const int W = g.rho_window;
     uint32_t colbase[G];
@@ -459,7 +460,10 @@ __device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask,
                 const int k = wd * 32 + b;
                 const uint32_t cv = ln.count(tile[k * ST + ln.col[q]]);
                 if (idx < cap) store_peak(out + idx, j, (uint32_t)k, cv);
-                if (rec) tpk[idx - base] = make_float4(cl->C[q], cl->S[q], __uint_as_float((uint32_t)k), 0.0f);
+                if (rec) {
+                    tpk[idx - base] = make_float4(cl->C[q], cl->S[q], __int_as_float(k - W), 0.0f);
+                    if (edge && (k <= W || k >= g.n_rho - W)) *edge = 1u;
+                }
                 ++idx;
                 if (W >= 32) {
                     const int lo = k - W > 0 ? k - W : 0;
@@ -662,40 +666,58 @@ __device__ uint32_t retain_range(const uint32_t *dil, float2 *st, const float *x
 // Step 5 on a tile with at most kTilePeaks peaks, one lane per hit: hit (u, v) is kept by
 // peak (column j, row k) when its own bin in column j (the vote's arithmetic, in range) is
 // within rho_window of k, which is what a lookup of the dilated words tests; here it costs
-// one step per peak for 64 hits instead of one step per hit for the tile's columns.
-__device__ __forceinline__ bool kept_by_peaks(const float4 *tpk, uint32_t np, float u, float v,
-                                              const GridArgs &g) {
-    bool kept = false;
-#pragma unroll 4
-    for (uint32_t p = 0; p < np; ++p) {
-        const float4 P = tpk[p];                       // the same address in every lane
+// one step per peak for 64 hits instead of one step per hit for the tile's columns.  The list
+// holds k - W (as int bits in z).  For a peak with W < k < N_rho - W the range test is implied:
+// a bin t outside [0, N_rho) truncates to an integer below 1 or at least N_rho, out of
+// [k - W, k + W]; so unless the tile has a peak nearer an edge (`edge`) a peak costs two fmas,
+// a conversion, a subtraction and one unsigned compare.  t is first clamped to [-2, N_rho + W + 2]
+// (one v_med3), which keeps the conversion defined and changes no verdict: a clamped bin lies
+// outside every peak's window either way.  Returns the mask of kept lanes among `valid`, and
+// stops once every valid lane is kept.
+__device__ __forceinline__ uint64_t kept_by_peaks(const float4 *tpk, uint32_t np, float u, float v, bool valid,
+                                                  bool edge, const GridArgs &g) {
+    const uint64_t want = __ballot(valid);
+    const uint32_t w2 = 2u * (uint32_t)g.rho_window;
+    const float hi = g.nrho_f + (float)g.rho_window + 2.0f;
+    uint64_t km = 0;
+    // one peak: its compares go straight into wave masks (scalar ORs and ANDs)
+    auto test = [&](const float4 &P) {
         const float t = __builtin_fmaf(u, P.x, __builtin_fmaf(v, P.y, g.Bf));
-        const int d = (int)t - (int)__float_as_uint(P.z);
-        kept |= (t >= 0.0f) && (t < g.nrho_f) && (d <= g.rho_window) && (d >= -g.rho_window);
+        const uint32_t dd = (uint32_t)(int)__builtin_amdgcn_fmed3f(t, -2.0f, hi) - __float_as_uint(P.z);
+        uint64_t m = __ballot(dd <= w2);
+        if (edge) m &= __ballot(t >= 0.0f) & __ballot(t < g.nrho_f);
+        km |= m;
+    };
+    uint32_t p = 0;
+    // four peaks at a time, their list reads issued together; done once every valid lane is kept
+    for (; p + 4 <= np; p += 4) {
+        float4 P[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) P[q] = tpk[p + q];       // the same address in every lane
+#pragma unroll
+        for (int q = 0; q < 4; ++q) test(P[q]);
+        if ((km & want) == want) return want;
     }
-    return kept;
+    for (; p < np; ++p) test(tpk[p]);
+    return km & want;
 }
 
 // retain_pending with the tile's peak list.
-__device__ uint32_t retain_pending_peaks(Pending &pd, const float4 *tpk, uint32_t np, const float *x,
+__device__ uint32_t retain_pending_peaks(Pending &pd, const float4 *tpk, uint32_t np, bool edge, const float *x,
                                          const float *y, uint8_t *ke, const GridArgs &g, int lane) {
     if (pd.live == 0ull) return 0u;
     const bool me = (pd.live >> lane) & 1ull;
     const uint32_t idx = pd.idx & 0x7fffffffu;
-    bool kept = false;
-    if (me) {
-        float u, v;
-        (void)conformal(x[idx], y[idx], u, v);
-        kept = kept_by_peaks(tpk, np, u, v, g);
-    }
-    if (kept) ke[idx] = (uint8_t)(1u | ((pd.idx >> 30) & (uint32_t)kKeepDuplicate));
-    const uint64_t kept_lanes = __ballot(kept);
+    float u = 0.0f, v = 0.0f;
+    if (me) (void)conformal(x[idx], y[idx], u, v);
+    const uint64_t kept_lanes = kept_by_peaks(tpk, np, u, v, me, edge, g);
+    if ((kept_lanes >> lane) & 1ull) ke[idx] = (uint8_t)(1u | ((pd.idx >> 30) & (uint32_t)kKeepDuplicate));
     pd.live &= ~kept_lanes;
     return (uint32_t)__popcll(kept_lanes);
 }
 
 // retain_range with the tile's peak list: each lane maps and tests its own unkept hit.
-__device__ uint32_t retain_range_peaks(const float4 *tpk, uint32_t np, const float *x, const float *y,
+__device__ uint32_t retain_range_peaks(const float4 *tpk, uint32_t np, bool edge, const float *x, const float *y,
                                        uint8_t *ke, uint32_t hb, uint32_t he, const GridArgs &g, int lane,
                                        uint32_t &left) {
     uint32_t newly = 0;
@@ -712,12 +734,13 @@ __device__ uint32_t retain_range_peaks(const float4 *tpk, uint32_t np, const flo
         const bool cand = (i < he) && !(kv & 1u);
         if (__ballot(cand) == 0ull) continue;            // whole chunk already kept
         float u = 0.0f, v = 0.0f;
-        bool valid = false, kept = false;
+        bool valid = false;
         if (cand) valid = conformal(xi, yi, u, v);
-        if (valid) kept = kept_by_peaks(tpk, np, u, v, g);
-        if (kept) ke[i] = (uint8_t)(kv | 1u);
-        newly += (uint32_t)__popcll(__ballot(kept));
-        left += (uint32_t)__popcll(__ballot(valid && !kept));
+        const uint64_t km = kept_by_peaks(tpk, np, u, v, valid, edge, g);
+        if ((km >> lane) & 1ull) ke[i] = (uint8_t)(kv | 1u);
+        const uint32_t nk = (uint32_t)__popcll(km);
+        newly += nk;
+        left += (uint32_t)__popcll(__ballot(valid)) - nk;
     }
     return newly;
 }
@@ -1526,7 +1549,7 @@ __global__ __launch_bounds__(NW * 64, (NW == 16 || WIN) ? 4 : (G == 1 ? 6 : 4)) 
     uint32_t *dil = pmask + (size_t)nwp * TW;                              // [(nwp + 1) * TW]
     float4 *tpk = reinterpret_cast<float4 *>(dil + (size_t)(nwp + 1) * TW);   // [kTilePeaks]
     uint32_t *colcnt = reinterpret_cast<uint32_t *>(tpk + kTilePeaks);            // [TW] peaks per column
-    __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept, s_max, s_minr2, s_wb, s_fit;
+    __shared__ uint32_t s_event, s_npeaks, s_flags, s_nvalid, s_nkept, s_max, s_minr2, s_wb, s_fit, s_edge;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const L ln(lane);
     const int tile_words4 = rows_t * ST / 4;
@@ -1729,13 +1752,14 @@ __global__ __launch_bounds__(NW * 64, (NW == 16 || WIN) ? 4 : (G == 1 ? 6 : 4)) 
 #pragma unroll 1
                 for (int i = threadIdx.x; i < nwp * TW; i += NT) dil[i] = 0u;
             }
+            if (SP && threadIdx.x == 0) s_edge = 0u;     // set by the listing for a peak near a rho edge
             __syncthreads();
             pc.mark(kPhasePeaks);
             const uint32_t base = s_npeaks;
             uint32_t np;
             if constexpr (SP)
                 np = emit_and_dilate<G, true>(tile_w, pmask_w, dil_w, w_lo, nwp, first, g, pe, cap, base, ln, lane,
-                                              wave, NW, tpk, &cl, colcnt);
+                                              wave, NW, tpk, &cl, colcnt, &s_edge);
             else
                 np = emit_and_dilate<G, true>(tile_w, pmask_w, dil_w, w_lo, nwp, first, g, pe, cap, base, ln, lane,
                                               wave, NW, nullptr, nullptr, colcnt);
@@ -1748,21 +1772,24 @@ __global__ __launch_bounds__(NW * 64, (NW == 16 || WIN) ? 4 : (G == 1 ? 6 : 4)) 
             for (int i = threadIdx.x; i < tile_words4; i += NT)
                 reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
             if (np && s_nkept < s_nvalid) {
-                // Few peaks: test each hit against the peak list (about 9 instructions per peak
-                // for a chunk of 64 hits, kept or not) where that beats looking the unkept hits
-                // up in every column's dilated words (about 7 per unkept hit, plus staging).
+                // Few peaks: test each hit against the peak list (about 5 instructions per peak
+                // for a chunk of 64 hits, kept or not; 9 when a peak lies near a rho edge) where
+                // that beats looking the unkept hits up in every column's dilated words (about 7
+                // per unkept hit, plus staging).
                 const bool few = SP && np <= kTilePeaks;
+                const bool edge = SP && s_edge != 0u;
+                const uint32_t cp = edge ? 9u : 5u;
                 uint32_t newly;
                 if (pd.on) {
                     const uint32_t n = (uint32_t)__popcll(pd.live);
-                    newly = (few && np * 9u < n * 7u + 10u)
-                                ? retain_pending_peaks(pd, tpk, np, xe, ye, ke, g, lane)
+                    newly = (few && np * cp < n * 7u + 10u)
+                                ? retain_pending_peaks(pd, tpk, np, edge, xe, ye, ke, g, lane)
                                 : retain_pending<G>(pd, dil_w, stage + wave * 64, xe, ye, ke, cl, g, lane);
                 } else {
                     uint32_t left = 0;
                     const uint32_t chunks = (he - hb + 63u) >> 6;
-                    newly = (few && np * 9u * chunks < unkept * 7u + chunks * 10u)
-                                ? retain_range_peaks(tpk, np, xe, ye, ke, hb, he, g, lane, left)
+                    newly = (few && np * cp * chunks < unkept * 7u + chunks * 10u)
+                                ? retain_range_peaks(tpk, np, edge, xe, ye, ke, hb, he, g, lane, left)
                                 : retain_range<G>(dil_w, stage + wave * 64, xe, ye, ke, hb, he, cl, g, lane, left);
                     if (SP) unkept = left;
                     if (left <= 64u) build_pending(pd, stage + wave * 64, xe, ye, ke, hb, he, lane);
