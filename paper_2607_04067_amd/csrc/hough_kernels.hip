@@ -411,6 +411,11 @@ __device__ __forceinline__ void store_peak(hough_peak *out, uint32_t j, uint32_t
 // them in raster order, each with its column's C and S (and its row as the bits of z), for the
 // retention of tiles with few peaks.  Returns the tile's peak count.
 constexpr uint32_t kTilePeaks = 64;
+// Deferred retention (sparse-grid kernels): a tile with at most kDeferTilePeaks peaks, all of
+// them in the caller's peak list, leaves its retention to a later pass over the event's hits
+// against the peak list itself, which then covers up to kDeferPeaks peaks of several tiles.
+constexpr uint32_t kDeferTilePeaks = 80;
+constexpr uint32_t kDeferPeaks = 256;
 
 template <int G, bool P>
 __device__ uint32_t emit_and_dilate(const uint32_t *tile, const uint32_t *pmask, uint32_t *dil, int w0,
@@ -1706,6 +1711,40 @@ __global__ __launch_bounds__(NW * 64, (NW == 16 || WIN) ? 4 : (G == 1 ? 6 : 4)) 
         pd.live = 0ull;
         pd.on = false;
         uint32_t unkept = he - hb;           // this wave's unkept hits after its last full pass
+        // Deferred retention: peaks [def0, def0 + defn) of the event's list still have to keep
+        // their hits.  flush() tests every unkept hit against them, 64 peaks at a time staged in
+        // the tile's peak list (wave 0 reads the records back, then every wave tests its own
+        // hits), and drops the pending lists (their entries may have been kept meanwhile).
+        // (only where the launch bound leaves registers for it: windowed and 16-wave kernels)
+        constexpr bool DEF = SP && (WIN || NW == 16);
+        uint32_t def0 = 0, defn = 0;
+        auto flush = [&]() {
+            for (uint32_t b = 0; b < defn; b += kTilePeaks) {
+                const uint32_t nb = min(kTilePeaks, defn - b);
+                if (wave == 0) {
+                    bool near = false;
+                    if ((uint32_t)lane < nb) {
+                        const uint64_t rec = __hip_atomic_load(
+                            reinterpret_cast<const uint64_t *>(pe + def0 + b + (uint32_t)lane), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+                        const int j = (int)(rec & 0xffffu), k = (int)((rec >> 16) & 0xffffu);
+                        tpk[lane] = make_float4(g.C[j], g.S[j], __int_as_float(k - g.rho_window), 0.0f);
+                        near = k <= g.rho_window || k >= g.n_rho - g.rho_window;
+                    }
+                    const uint64_t nm = __ballot(near);
+                    if (lane == 0) s_edge = nm ? 1u : 0u;
+                }
+                __syncthreads();
+                uint32_t left = 0;
+                const uint32_t newly = retain_range_peaks(tpk, nb, s_edge != 0u, xe, ye, ke, hb, he, g, lane, left);
+                if (lane == 0 && newly) atomicAdd(&s_nkept, newly);
+                unkept = left;
+                __syncthreads();
+            }
+            defn = 0;
+            pd.on = false;
+            pd.live = 0ull;
+        };
         // sparse event (under a quarter of the threshold per cell on average): most peak units
         // hold no count that reaches it, so each unit is first tested whole (unit_below)
         const bool sparse_ev = SP && (uint64_t)H * 4u < (uint64_t)thr * (uint32_t)g.n_rho;
@@ -1771,13 +1810,22 @@ __global__ __launch_bounds__(NW * 64, (NW == 16 || WIN) ? 4 : (G == 1 ? 6 : 4)) 
 #pragma unroll 1
             for (int i = threadIdx.x; i < tile_words4; i += NT)
                 reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (np && s_nkept < s_nvalid) {
+            if (DEF && np && s_nkept < s_nvalid && pe && np <= kDeferTilePeaks && base + np <= cap &&
+                defn + np <= kDeferPeaks) {
+                if (defn == 0) def0 = base;          // the deferred peaks stay contiguous
+                defn += np;
+            } else if (np && s_nkept < s_nvalid) {
                 // Few peaks: test each hit against the peak list (about 5 instructions per peak
                 // for a chunk of 64 hits, kept or not; 9 when a peak lies near a rho edge) where
                 // that beats looking the unkept hits up in every column's dilated words (about 7
-                // per unkept hit, plus staging).
-                const bool few = SP && np <= kTilePeaks;
+                // per unkept hit, plus staging).  A flush of deferred peaks reuses the list's
+                // storage, so after one this tile looks its hits up in the dilated words.
+                bool few = SP && np <= kTilePeaks;
                 const bool edge = SP && s_edge != 0u;
+                if (DEF && defn) {
+                    flush();
+                    few = false;
+                }
                 const uint32_t cp = edge ? 9u : 5u;
                 uint32_t newly;
                 if (pd.on) {
@@ -1797,6 +1845,10 @@ __global__ __launch_bounds__(NW * 64, (NW == 16 || WIN) ? 4 : (G == 1 ? 6 : 4)) 
                 if (lane == 0 && newly) atomicAdd(&s_nkept, newly);
             }
             __syncthreads();
+            pc.mark(kPhaseRetain);
+        }
+        if (DEF && defn) {
+            if (s_nkept < s_nvalid) flush();
             pc.mark(kPhaseRetain);
         }
         if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
