@@ -303,8 +303,12 @@ typedef struct hough_batch_plan {
     int32_t window_rows;       /* rho rows of a windowed tile, 0 = whole column (read-only) */
 } hough_batch_plan;
 
-/* The launch shape hough_run_batch currently uses (the library picks one at hough_config); all
- * zero when the grid's rho column does not fit the fused kernel's tile (every event spills). */
+/* The launch shape hough_run_batch currently uses (the library picks one at hough_config).  A
+ * grid whose whole rho column does not fit the fused kernel's tile gets a windowed tile (theta
+ * not periodic; window_rows > 0): each event whose hits reach only that many rows runs in the
+ * fused kernel, the others, and every event of the split forms, through the spill path.  All
+ * zero when there is no fused kernel for the grid (a periodic grid taller than the tile: every
+ * event spills). */
 int hough_get_batch_plan(const hough_ctx *ctx, hough_batch_plan *out);
 
 /* Select a launch shape (for autotuning).  groups_per_cu = 0 launches as many workgroups per CU

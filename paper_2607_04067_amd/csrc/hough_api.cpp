@@ -22,7 +22,9 @@ struct hough_ctx {
     hough::IterPlan iterb;  // ... over a batch (hough_run_batch_iterative), two workgroups per CU
     hough::GridArgs g;
     hough::BatchPlan plan;  // the fused kernel's launch shape (fused != 0)
-    int fused;              // 1: the fused kernel holds the grid's tile; 0: every batch event spills
+    int fused;              // 1: the fused kernel holds the grid's whole column (and windows of it);
+                            // 2: only windows of it (taller grids, theta not periodic; the split
+                            // form spills every event); 0: every batch event spills
     uint32_t *d_spill;      // spill_wgs slices of spill_stride words (the spill path's accumulators)
     size_t spill_stride;
     int spill_wgs;
@@ -101,6 +103,45 @@ int default_plan(hough_ctx *c) {
         p.per_cu = hough::prepare_batch(&p);
         if (p.per_cu < 1 || p.split_per_cu < 1) continue;
         const int score = p.per_cu * p.waves;
+        if (score > best) { best = score; pick = p; }
+    }
+    if (best < 0) return HOUGH_EINVAL;
+    if (hough::prepare_batch(&pick) < 1) return HOUGH_EDEVICE;
+    c->plan = pick;
+    return HOUGH_OK;
+}
+
+// The tallest windowed tile (a multiple of 32 rows) that lets groups_per_cu workgroups share a
+// CU, if any (one column group, theta not periodic): for more workgroups per CU than a
+// whole-column tile allows, and for grids taller than that tile.  Events whose hits reach
+// beyond the window go to the spill kernel.
+int windowed_plan(const hough_ctx *c, int waves, int groups, int groups_per_cu, hough::BatchPlan *out) {
+    if (groups != 1 || c->g.periodic) return -1;
+    const bool need_split = c->fused == 1;
+    for (int win = ((c->p.n_rho - 1) / 32) * 32; win >= 32; win -= 32) {
+        hough::BatchPlan p;
+        if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves, groups, c->lds_limit, &p, win, need_split) != 0)
+            continue;
+        p.per_cu = hough::prepare_batch(&p);
+        if (p.per_cu >= groups_per_cu && (!need_split || p.split_per_cu >= 1)) {
+            *out = p;
+            return 0;
+        }
+    }
+    return -1;
+}
+
+// Default launch shape where only windows of the column fit (fused == 2): the tallest window
+// with the most resident waves per CU (the most events fit, the rest spill); ties go to the
+// earlier candidate.
+int default_windowed_plan(hough_ctx *c) {
+    int best = -1;
+    hough::BatchPlan pick{};
+    const int waves_opts[5] = {16, 8, 12, 6, 4};
+    for (int wi = 0; wi < 5; ++wi) {
+        hough::BatchPlan p;
+        if (windowed_plan(c, waves_opts[wi], 1, 1, &p) != 0) continue;
+        const int score = p.win * 64 + p.per_cu * p.waves;
         if (score > best) { best = score; pick = p; }
     }
     if (best < 0) return HOUGH_EINVAL;
@@ -210,9 +251,9 @@ int hough_config(const hough_params *p, hough_ctx **out) {
         hough_destroy(c);
         return HOUGH_ENOMEM;
     }
-    c->fused = fused_fits(p->n_rho, limit) ? 1 : 0;
+    c->fused = fused_fits(p->n_rho, limit) ? 1 : ((p->flags & HOUGH_FLAG_THETA_PERIODIC) ? 0 : 2);
     c->spill_stride = hough::spill_stride(p->n_theta, p->n_rho);
-    c->spill_wgs = spill_workgroups(c->spill_stride, c->n_cu, !c->fused);
+    c->spill_wgs = spill_workgroups(c->spill_stride, c->n_cu, c->fused != 1);
     if (hipMalloc(&c->d_spill, c->spill_stride * 4 * (size_t)c->spill_wgs) != hipSuccess) {
         hough_destroy(c);
         return HOUGH_ENOMEM;
@@ -245,7 +286,7 @@ int hough_config(const hough_params *p, hough_ctx **out) {
     }
     g.wB = (double)g.Bf;
 
-    rc = c->fused ? default_plan(c) : HOUGH_OK;
+    rc = c->fused == 1 ? default_plan(c) : (c->fused == 2 ? default_windowed_plan(c) : HOUGH_OK);
     if (rc != HOUGH_OK) {
         hough_destroy(c);
         return rc;
@@ -286,34 +327,22 @@ int hough_get_batch_plan(const hough_ctx *c, hough_batch_plan *out) {
     return HOUGH_OK;
 }
 
-// More workgroups per CU than a whole-column tile allows: the tallest windowed tile (a multiple
-// of 32 rows) that lets groups_per_cu of them share a CU, if any (one column group, theta not
-// periodic).  Events whose hits reach beyond the window go to the spill kernel.
-static int windowed_plan(const hough_ctx *c, int waves, int groups, int groups_per_cu, hough::BatchPlan *out) {
-    if (groups != 1 || c->g.periodic) return -1;
-    for (int win = ((c->p.n_rho - 1) / 32) * 32; win >= 32; win -= 32) {
-        hough::BatchPlan p;
-        if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves, groups, c->lds_limit, &p, win) != 0) continue;
-        p.per_cu = hough::prepare_batch(&p);
-        if (p.per_cu >= groups_per_cu && p.split_per_cu >= 1) {
-            *out = p;
-            return 0;
-        }
-    }
-    return -1;
-}
-
 int hough_set_batch_plan(hough_ctx *c, int32_t waves_per_group, int32_t column_groups,
                          int32_t groups_per_cu) {
     if (!c || groups_per_cu < 0 || !c->fused) return HOUGH_EINVAL;
-    hough::BatchPlan p;
-    if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves_per_group, column_groups, c->lds_limit, &p) != 0)
-        return HOUGH_EINVAL;
-    p.per_cu = hough::prepare_batch(&p);
-    if (p.per_cu >= 1 && p.split_per_cu >= 1 && groups_per_cu > p.per_cu &&
-        windowed_plan(c, waves_per_group, column_groups, groups_per_cu, &p) != 0)
-        p.per_cu = 0;
-    if (p.per_cu < 1 || p.split_per_cu < 1 || groups_per_cu > p.per_cu) {
+    hough::BatchPlan p{};
+    if (c->fused == 1) {
+        if (hough::plan_batch(c->p.n_theta, c->p.n_rho, waves_per_group, column_groups, c->lds_limit, &p) != 0)
+            return HOUGH_EINVAL;
+        p.per_cu = hough::prepare_batch(&p);
+        if (p.per_cu >= 1 && p.split_per_cu >= 1 && groups_per_cu > p.per_cu &&
+            windowed_plan(c, waves_per_group, column_groups, groups_per_cu, &p) != 0)
+            p.per_cu = 0;
+        if (p.split_per_cu < 1) p.per_cu = 0;
+    } else if (windowed_plan(c, waves_per_group, column_groups, groups_per_cu > 0 ? groups_per_cu : 1, &p) != 0) {
+        p.per_cu = 0;                         // only windows of the column fit
+    }
+    if (p.per_cu < 1 || groups_per_cu > p.per_cu) {
         hough::BatchPlan keep = c->plan;
         (void)hough::prepare_batch(&keep);
         return HOUGH_EINVAL;
@@ -458,14 +487,15 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     a.queue = c->d_work;
     a.frac_num = frac_num;
     a.frac_den = frac_den;
-    hough::SpillArgs spill{c->d_spill, c->spill_stride, c->d_work + 2, c->fused ? 0u : 1u};
-    // fused contexts: the fused (or split) kernel counts the events it leaves to the spill kernel
-    // in the spill kernel's first counter, so that the spill kernel skips its scan when none
-    a.spill_count = c->fused ? c->d_work + 2 : nullptr;
+    // every event in device memory: no fused kernel for this grid, or the split form on a grid
+    // whose whole column does not fit it (the split form gives the same results)
+    const bool spill_all = !c->fused || (split && c->fused == 2);
+    hough::SpillArgs spill{c->d_spill, c->spill_stride, c->d_work + 2, spill_all ? 1u : 0u};
+    // otherwise the fused (or split) kernel counts the events it leaves to the spill kernel in
+    // the spill kernel's first counter, so that the spill kernel skips its scan when none
+    a.spill_count = spill_all ? nullptr : c->d_work + 2;
     hipError_t e = hipSuccess;
-    if (!c->fused) {
-        // the grid's column does not fit the fused kernel's tile: every event, in device memory
-        // (the split form gives the same results, so it takes the same path)
+    if (spill_all) {
         if (c->g.dedup) e = hough::launch_dedup(a, (hipStream_t)stream);
         if (e == hipSuccess) e = hough::launch_spill(c->g, a, spill, c->spill_wgs, (hipStream_t)stream);
         return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
@@ -528,7 +558,7 @@ int hough_run_batch_gather(hough_ctx *c, const float *x, const float *y, const u
 uint32_t hough_max_dedup_hits(void) { return hough::kDedupMaxHits; }
 
 size_t hough_split_workspace_bytes(const hough_ctx *c, uint32_t n_events) {
-    if (!c || !c->fused) return 0;        // no fused kernel: the split form needs no workspace
+    if (!c || c->fused != 1) return 0;    // the split form spills every event: no workspace
     return hough::split_workspace_bytes(c->p.n_theta, c->p.n_rho, c->plan.groups, n_events);
 }
 

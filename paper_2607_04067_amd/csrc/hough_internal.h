@@ -197,7 +197,8 @@ hipError_t launch_peaks_iterative(const GridArgs &g, const void *acc, int acc_ty
                                   uint32_t *gbm, hipStream_t s);
 // LDS of the fused kernel's workgroup: the whole column (win 0) or a window of win rows.
 size_t batch_lds_bytes(int n_rho, int waves, int groups, int win = 0);
-int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out, int win = 0);
+int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out, int win = 0,
+               bool need_split = true);
 int prepare_batch(BatchPlan *p);
 
 }  // namespace hough

@@ -2539,7 +2539,8 @@ size_t batch_lds_bytes(int n_rho, int waves, int groups, int win) {
            kTilePeaks * sizeof(float4) + tw * 4;
 }
 
-int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out, int win) {
+int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, BatchPlan *out, int win,
+               bool need_split) {
     if (!(waves == 4 || waves == 6 || waves == 8 || waves == 12 || waves == 16) || !(groups == 1 || groups == 2)) return -1;
     // a window is a whole number of 32-row words, one column group, shorter than the grid
     if (win != 0 && (groups != 1 || win < 32 || win % 32 != 0 || win >= n_rho)) return -1;
@@ -2553,8 +2554,9 @@ int plan_batch(int n_theta, int n_rho, int waves, int groups, size_t lds_limit, 
     p.lds_bytes = batch_lds_bytes(n_rho, waves, groups, win);
     p.split_lds_bytes = batch_lds_bytes(n_rho, waves, groups, 0);
     p.sparse = n_rho >= kSparseRhoRows ? 1 : 0;
-    // room for the kernel's static LDS; the split form always holds the whole column
-    if (p.lds_bytes + 256 > lds_limit || p.split_lds_bytes + 256 > lds_limit) return -1;
+    // room for the kernel's static LDS; the split form always holds the whole column (grids
+    // taller than that run their split calls through the spill kernel: need_split false)
+    if (p.lds_bytes + 256 > lds_limit || (need_split && p.split_lds_bytes + 256 > lds_limit)) return -1;
     p.grid = 0;
     *out = p;
     return 0;

@@ -248,7 +248,8 @@ def test_large_events_in_batch(H, orc):
 
 
 # grids whose rho column is taller than the fused kernel's LDS tile: the per-event path votes in
-# rho slabs and every batch form runs in device memory
+# rho slabs; the batch path holds a window of the column per event (events whose hits reach
+# beyond it, and every event of the split form, run in device memory)
 TALL_GRIDS = [(360, 2048, -1 / 200, 1 / 200, 10), (1000, 1500, -0.01, 0.01, 20), (97, 4099, -1 / 150, 1 / 150, 6)]
 
 
@@ -257,7 +258,8 @@ def test_tall_grids_equal_the_oracle(H, orc, n_theta, n_rho, lo, hi, T):
     import torch
     g = orc.Grid(n_theta, n_rho, lo, hi)
     ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, 1, 8192)
-    assert ctx.batch_plan["waves_per_group"] == 0           # no fused tile: the spill path
+    bp = ctx.batch_plan
+    assert bp["waves_per_group"] > 0 and 0 < bp["window_rows"] < n_rho   # windows of the column
     ev = synth.make_events(synth.WORKLOADS["paper-1000ev-360x256"], 5, n_events=6)
     evs = [ev.event(e) for e in range(ev.n_events)] + _edge_events()
     x = np.concatenate([a for a, _ in evs]).astype(np.float32)
@@ -289,6 +291,16 @@ def test_tall_grids_equal_the_oracle(H, orc, n_theta, n_rho, lo, hi, T):
     plain = ctx.run_batch(xt, yt, ot)
     torch.cuda.synchronize()
     assert all(torch.equal(a, b) for a, b in zip(sp, plain))
+    # two workgroups per CU (a shorter window: more events spill) gives the same results
+    try:
+        ctx.set_batch_plan(8, 1, 2)
+    except H.HoughError:
+        pass
+    else:
+        say(f"tall grid {n_theta}x{n_rho} plan {ctx.batch_plan}")
+        again = ctx.run_batch(xt, yt, ot)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(again, plain))
     ctx.close()
 
 
@@ -301,11 +313,13 @@ def test_tall_grid_periodic_and_dedup(H, orc, flags):
     x, y, off = ev.x, ev.y, ev.offsets
     if flags == "periodic":
         ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, 1, 8192, periodic=True)
+        assert ctx.batch_plan["waves_per_group"] == 0       # no windowed form: every event spills
         pk, npk, keep, st = ctx.run_batch(_t(x), _t(y), _t(off.astype(np.int32)))
         torch.cuda.synchronize()
         pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=T, rho_window=1, cap=8192, periodic=True)
     else:
         ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, 1, 8192, dedup=True)
+        assert ctx.batch_plan["window_rows"] > 0
         pk, npk, keep, st = ctx.run_batch(_t(x), _t(y), _t(off.astype(np.int32)))
         torch.cuda.synchronize()
         pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=T, rho_window=1, cap=8192, dedup=True)
