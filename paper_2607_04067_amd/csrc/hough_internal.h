@@ -110,7 +110,8 @@ bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *w
 struct SpillArgs {
     uint32_t *acc;
     size_t stride;
-    uint32_t *queue;     // [2] work counter and exit counter (all = 1; zero between launches)
+    uint32_t *queue;     // [3], zero between launches: all = 1: work and exit counters; all = 0:
+                         // the count of events left to it, the exit counter, the block counter
     uint32_t all;
 };
 size_t spill_stride(int n_theta, int n_rho);

@@ -2093,6 +2093,12 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
 // cannot take, not a fast path.
 constexpr int kSpillWaves = 16;
 constexpr int kSpillThreads = kSpillWaves * 64;
+constexpr uint32_t kSpillBlock = 4;      // events per counter pop when only some events spill
+
+// A cell of the accumulator, read past the L1 (the vote's atomics update it in L2).
+__device__ __forceinline__ uint32_t spill_load(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Count of cell (column j, row k) of an event's accumulator, 0 outside the grid; on a
 // theta-periodic grid the column left of 0 is column n_theta - 1 and the column right of
@@ -2103,14 +2109,19 @@ __device__ __forceinline__ uint32_t spill_cell(const uint32_t *acc, const GridAr
         k = g.n_rho - 1 - k;
     }
     if (j < 0 || j >= g.n_theta || k < 0 || k >= g.n_rho) return 0u;
-    return acc[(size_t)k * g.n_theta + j];
+    return spill_load(acc + (size_t)k * g.n_theta + j);
 }
 
-// Release this workgroup's device-memory writes and atomics, then make everyone's visible to it.
+// The spill kernel's device memory belongs to one workgroup, so workgroup scope orders it: the
+// release waits for this wave's stores and atomics, the barrier lines the waves up.  The waves
+// of a workgroup share one L1, which their plain stores go through; only the vote's atomics are
+// performed beyond it (in L2), so the accumulator is read with loads that bypass the L1
+// (spill_load).  (Agent-scope fences here wrote back the whole L2 at every barrier: with many
+// workgroups spilling at once that took most of the kernel's time.)
 __device__ __forceinline__ void spill_sync() {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // One pass of step 4 over the lane's column j (all rows): calls f(k, count) for every peak.
@@ -2217,7 +2228,7 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
         uint32_t thr = g.threshold;
         if (a.frac_den) {                    // relative threshold: the event's largest count first
             uint32_t m = 0;
-            for (size_t i = threadIdx.x; i < cells; i += kSpillThreads) m = max(m, acc[i]);
+            for (size_t i = threadIdx.x; i < cells; i += kSpillThreads) m = max(m, spill_load(acc + i));
             m = wave_max(m);
             if (lane == 0) atomicMax(&s_max, m);
             __syncthreads();
@@ -2321,17 +2332,24 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
         return;
     }
     // only the events the fused or split kernel left (sp.queue[0] counts them; none: nothing to
-    // scan): the workgroups split the batch into blocks of kSpillThreads events and pick those
-    // out of each block.  The last workgroup to leave clears the count and its own exit counter.
+    // scan): the workgroups take blocks of kSpillBlock events from a counter (sp.queue[2]) and
+    // process the left ones of each block, so that a batch whose events mostly spill (a window
+    // its events do not fit) keeps every workgroup busy.  The last workgroup to leave clears
+    // the count and both counters.
     if (threadIdx.x == 0) s_n = __hip_atomic_load(sp.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const bool any = uni(s_n) != 0u;
     __syncthreads();
-    for (uint32_t b0 = blockIdx.x * kSpillThreads; any && b0 < a.n_events; b0 += gridDim.x * kSpillThreads) {
-        if (threadIdx.x == 0) s_n = 0u;
+    while (any) {
+        if (threadIdx.x == 0) {
+            s_event = atomicAdd(sp.queue + 2, 1u);
+            s_n = 0u;
+        }
         __syncthreads();
+        const uint32_t b0 = uni(s_event) * kSpillBlock;
+        if (b0 >= a.n_events) break;                   // every thread leaves together
         const uint32_t e = b0 + threadIdx.x;
-        if (e < a.n_events) {
+        if (threadIdx.x < kSpillBlock && e < a.n_events) {
             const uint32_t pe_id = a.ids ? a.ids[e] : e;
             const uint32_t h0 = a.offsets[pe_id], h1 = a.offsets[pe_id + 1];
             // left here by the fused kernel (kStatusSpill), or by the split form (above its limit)
@@ -2344,6 +2362,7 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
     }
     if (threadIdx.x == 0 && atomicAdd(sp.queue + 1, 1u) == gridDim.x - 1u) {
         __hip_atomic_store(sp.queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(sp.queue + 2, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(sp.queue + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
