@@ -2124,19 +2124,23 @@ __device__ __forceinline__ void spill_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// One pass of step 4 over the lane's column j (all rows): calls f(k, count) for every peak.
-// Raster order: the column before (j - 1) and the row above come first, except that on a
-// periodic grid the wrapped column left of column 0 comes later and the one right of the last
-// column earlier.
+// One pass of step 4 over rows [32b, 32b + 32) of column j: calls f(k, count) for every peak,
+// in row order.  Raster order: the column before (j - 1) and the row above come first, except
+// that on a periodic grid the wrapped column left of column 0 comes later and the one right of
+// the last column earlier.  The blocks of all columns are independent work items, so the
+// workgroup's threads walk many of them at once (a thread walking a whole column waited on
+// its loads row after row).
 template <typename F>
-__device__ __forceinline__ void spill_column_peaks(const uint32_t *acc, const GridArgs &g, int j, uint32_t thr,
-                                                   F &&f) {
+__device__ __forceinline__ void spill_block_peaks(const uint32_t *acc, const GridArgs &g, int j, int b, uint32_t thr,
+                                                  F &&f) {
     const bool left_later = g.periodic && j == 0, right_earlier = g.periodic && j == g.n_theta - 1;
+    const int k0 = 32 * b, k1 = min(k0 + 32, g.n_rho);
     // window rows k - 1, k, k + 1 of columns j - 1, j, j + 1
-    uint32_t l0 = 0u, c0 = 0u, r0 = 0u;
-    uint32_t l1 = spill_cell(acc, g, j - 1, 0), c1 = spill_cell(acc, g, j, 0), r1 = spill_cell(acc, g, j + 1, 0);
-#pragma unroll 1
-    for (int k = 0; k < g.n_rho; ++k) {
+    uint32_t l0 = spill_cell(acc, g, j - 1, k0 - 1), c0 = spill_cell(acc, g, j, k0 - 1),
+             r0 = spill_cell(acc, g, j + 1, k0 - 1);
+    uint32_t l1 = spill_cell(acc, g, j - 1, k0), c1 = spill_cell(acc, g, j, k0), r1 = spill_cell(acc, g, j + 1, k0);
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k) {
         const uint32_t l2 = spill_cell(acc, g, j - 1, k + 1), c2 = spill_cell(acc, g, j, k + 1),
                        r2 = spill_cell(acc, g, j + 1, k + 1);
         if (c1 >= thr) {
@@ -2159,7 +2163,8 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
     const int words = (g.n_rho + 31) / 32;
     uint32_t *acc = sp.acc + (size_t)blockIdx.x * sp.stride;
     uint32_t *dil = acc + cells;                          // [words][n_theta]
-    uint32_t *colpos = dil + (size_t)words * g.n_theta;   // [n_theta + 1]
+    uint32_t *colpos = dil + (size_t)words * g.n_theta;   // [n_theta * words + 1] per (column, block)
+    const int n_items = g.n_theta * words;                // (column, 32-row block), column-major
 
     // Every value that steers control flow around a barrier is wave-uniform (scalar), and an
     // event that is skipped passes a barrier before it returns, as a processed one does at its
@@ -2236,17 +2241,21 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
             thr = (uint32_t)min<uint64_t>(max<uint64_t>(rel, g.threshold), 0x7fffffffull);
         }
 
-        // step 4, first pass: each column's peak count
-        for (int j = threadIdx.x; j < g.n_theta; j += kSpillThreads) {
+        // step 4, first pass: each (column, block)'s peak count.  Neighbouring threads take
+        // neighbouring columns of one block, so that a wave's loads of a row are one run of
+        // cells; the counts are stored column-major (raster order)
+        for (int it = threadIdx.x; it < n_items; it += kSpillThreads) {
+            const int b = it / g.n_theta, j = it - b * g.n_theta;
             uint32_t c = 0;
-            spill_column_peaks(acc, g, j, thr, [&](int, uint32_t) { ++c; });
-            colpos[j] = c;
+            spill_block_peaks(acc, g, j, b, thr, [&](int, uint32_t) { ++c; });
+            colpos[j * words + b] = c;
         }
         spill_sync();
-        // exclusive prefix over the columns (raster order is column-major): each thread sums a
-        // run of columns, the runs' totals are scanned, then each run is scanned again
-        const int per = (g.n_theta + kSpillThreads - 1) / kSpillThreads;
-        const int c0 = threadIdx.x * per, c1 = min(c0 + per, g.n_theta);
+        // exclusive prefix over the items (raster order is column-major, rows in order within a
+        // column): each thread sums a run of items, the runs' totals are scanned, then each run
+        // is scanned again
+        const int per = (n_items + kSpillThreads - 1) / kSpillThreads;
+        const int c0 = min((int)threadIdx.x * per, n_items), c1 = min(c0 + per, n_items);
         uint32_t part = 0;
         for (int j = c0; j < c1; ++j) part += colpos[j];
         s_part[threadIdx.x] = part;
@@ -2268,21 +2277,23 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
             run += v;
         }
         spill_sync();
-        // second pass: list each column's peaks in row order at its position, and mark the rows
-        // within rho_window of each peak in the column's dilated bits
+        // second pass: list each block's peaks in row order at its position, and mark the rows
+        // within rho_window of each peak in the column's dilated bits (words other blocks of the
+        // column may mark too: atomic ORs, in L2)
         hough_peak *pe = a.peaks ? a.peaks + (size_t)e * a.max_peaks : nullptr;
         const uint32_t cap = pe ? a.max_peaks : 0u;
-        for (int j = threadIdx.x; j < g.n_theta; j += kSpillThreads) {
-            uint32_t pos = colpos[j];
-            spill_column_peaks(acc, g, j, thr, [&](int k, uint32_t c) {
+        for (int it = threadIdx.x; it < n_items; it += kSpillThreads) {
+            const int b = it / g.n_theta, j = it - b * g.n_theta;
+            uint32_t pos = colpos[j * words + b];
+            spill_block_peaks(acc, g, j, b, thr, [&](int k, uint32_t c) {
                 if (pos < cap) store_peak(pe + pos, (uint32_t)j, (uint32_t)k, c);
                 ++pos;
                 const int lo = max(k - g.rho_window, 0), hi = min(k + g.rho_window, g.n_rho - 1);
                 for (int wd = lo >> 5; wd <= (hi >> 5); ++wd) {
                     const int b0 = max(lo, wd * 32) - wd * 32, b1 = min(hi, wd * 32 + 31) - wd * 32;
                     const uint32_t msk = (b1 == 31 ? 0xffffffffu : ((1u << (b1 + 1)) - 1u)) & ~((1u << b0) - 1u);
-                    uint32_t *w = dil + (size_t)wd * g.n_theta + j;   // this lane's column only
-                    *w |= msk;
+                    __hip_atomic_fetch_or(dil + (size_t)wd * g.n_theta + j, msk, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
                 }
             });
         }
@@ -2300,7 +2311,7 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
                     const float t = __builtin_fmaf(u, g.C[j], __builtin_fmaf(v, g.S[j], g.Bf));
                     if (want && !kept && t >= 0.0f && t < g.nrho_f) {
                         const int k = (int)t;
-                        kept = (dil[(size_t)(k >> 5) * g.n_theta + j] >> (k & 31)) & 1u;
+                        kept = (spill_load(dil + (size_t)(k >> 5) * g.n_theta + j) >> (k & 31)) & 1u;
                     }
                 }
                 if (i < H) ke[i] = kept ? 1u : 0u;
@@ -2589,7 +2600,8 @@ hipError_t launch_order(const uint32_t *offsets, uint32_t n_events, uint32_t *or
 
 size_t spill_stride(int n_theta, int n_rho) {
     const size_t words = (size_t)(n_rho + 31) / 32;
-    const size_t n = (size_t)n_theta * n_rho + words * n_theta + n_theta + 1;
+    // accumulator, dilated words, one peak count per (column, 32-row block) and its end
+    const size_t n = (size_t)n_theta * n_rho + words * n_theta + words * n_theta + 1;
     return (n + 63) & ~(size_t)63;                  // each workgroup's slice on a 256-byte boundary
 }
 
