@@ -571,6 +571,72 @@ def test_windowed_tile_with_duplicate_suppression(H, orc):
     ctx.close()
 
 
+@pytest.mark.parametrize("plan", [None, (8, 1, 2)])
+def test_deferred_retention_with_many_peaks_and_small_buffers(H, orc, plan):
+    """Low thresholds on the paper grid give tiles of more than 80 peaks among tiles of few, so
+    deferred peaks are flushed before a tile that retains on its own; small peak buffers stop
+    deferral once the buffer would not hold a tile's peaks.  Plain, duplicate-suppressed and
+    relative-threshold runs, whole-column (16-wave) and windowed plans."""
+    import torch
+    wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
+    g = orc.Grid.of(wl)
+    ev = synth.make_events(wl, 21, n_events=12)
+    xt, yt, ot = H.to_device(ev)
+    E = ev.n_events
+    for T, cap, dedup, frac in [(4, 20000, False, None), (6, 150, False, None), (8, 40, True, None),
+                                (20, 30, False, None), (3, 20000, False, (1, 4))]:
+        ctx = H.Context(wl.n_theta, wl.n_rho, wl.rho_min, wl.rho_max, "i32", T, 1, cap, dedup=dedup)
+        if plan:
+            ctx.set_batch_plan(*plan)
+        say(f"deferred T={T} cap={cap} dedup={dedup} frac={frac} plan={ctx.batch_plan}")
+        pk, npk, keep, st = ctx.run_batch(xt, yt, ot, frac=frac) if frac else ctx.run_batch(xt, yt, ot)
+        torch.cuda.synchronize()
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, ev.x, ev.y, ev.offsets, threshold=T, rho_window=1, cap=cap,
+                                                n_threads=8, dedup=dedup, frac=frac)
+        assert np.array_equal(npk.cpu().numpy()[:E].astype(np.int64), n_ref)
+        assert np.array_equal(keep.cpu().numpy(), keep_ref)
+        p = pk.cpu().numpy()
+        for e in range(E):
+            m = int(min(n_ref[e], cap))
+            assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), e
+        assert np.array_equal((st.cpu().numpy()[:E] & H.EV_PEAKS_TRUNCATED) != 0, n_ref > cap)
+        ctx.close()
+
+
+def test_spill_blocks_with_many_events_left(H, orc):
+    """A windowed plan whose window about half of 300 events do not fit: the spill kernel's
+    workgroups take the left events from blocks all over the batch; every event equals the
+    oracle, in order and gathered."""
+    import torch
+    wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
+    g = orc.Grid.of(wl)
+    rng = np.random.default_rng(5)
+    evs = []
+    for i in range(300):
+        r_lo = 150.0 if rng.random() < 0.5 else 260.0         # below 200 mm: beyond a 512-row window
+        evs.append(synth.random_hits(int(rng.integers(20, 400)), seed=1000 + i, r_lo=r_lo, r_hi=810.0))
+    x = np.concatenate([a for a, _ in evs]).astype(np.float32)
+    y = np.concatenate([b for _, b in evs]).astype(np.float32)
+    off = np.zeros(len(evs) + 1, np.uint32)
+    off[1:] = np.cumsum([a.size for a, _ in evs])
+    ctx = H.Context(wl.n_theta, wl.n_rho, wl.rho_min, wl.rho_max, "i32", 3, 1, 4096)
+    ctx.set_batch_plan(8, 1, 2)
+    assert ctx.batch_plan["window_rows"] == 512
+    _batch_check(H, orc, ctx, g, 3, 1, x, y, off, 4096)
+    sizes = np.diff(off.astype(np.int64))
+    ids = rng.permutation(len(evs))
+    koff = np.concatenate([[0], np.cumsum(sizes[ids])[:-1]]).astype(np.int32)
+    xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
+    plain = ctx.run_batch(xt, yt, ot)
+    gk = ctx.run_batch_gather(xt, yt, ot, _t(ids.astype(np.int32)), _t(koff), keep_size=int(sizes.sum()))
+    torch.cuda.synchronize()
+    kp, kg = plain[2].cpu().numpy(), gk[2].cpu().numpy()
+    for j, e in enumerate(ids):
+        assert int(gk[1][j]) == int(plain[1][e]) and int(gk[3][j]) == int(plain[3][e]), e
+        assert np.array_equal(kg[koff[j]:koff[j] + sizes[e]], kp[off[e]:off[e + 1]]), e
+    ctx.close()
+
+
 def test_windowed_plans_refused_where_no_window_helps(H):
     # a periodic grid and two column groups have no windowed form; the context keeps its plan
     wl = synth.WORKLOADS["paper-1000ev-1000x1000"]
