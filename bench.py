@@ -727,8 +727,8 @@ def main(argv=None):
                     help="also time a plain device copy of this many MiB (HBM reference for counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (the path is single-GPU; events shard across GPUs "
-              f"with no exchange, see DESIGN.md); got --gpus {args.gpus}", file=sys.stderr)
+        print(f"bench.py measures one GPU only (the path is single-GPU: events are independent, so "
+              f"a batch would shard across GPUs with no exchange); got --gpus {args.gpus}", file=sys.stderr)
         return 2
 
     if args.phases:
