@@ -2094,6 +2094,7 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
 constexpr int kSpillWaves = 16;
 constexpr int kSpillThreads = kSpillWaves * 64;
 constexpr uint32_t kSpillBlock = 4;      // events per counter pop when only some events spill
+constexpr int kSpillSlabRows = 1024;     // rho rows of the vote's LDS slab (128 KB of packed counts)
 
 // A cell of the accumulator, read past the L1 (the vote's atomics update it in L2).
 __device__ __forceinline__ uint32_t spill_load(const uint32_t *p) {
@@ -2156,6 +2157,7 @@ __device__ __forceinline__ void spill_block_peaks(const uint32_t *acc, const Gri
 }
 
 __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a, SpillArgs sp) {
+    extern __shared__ __align__(16) uint32_t spill_tile[];      // [slab_rows * 32] packed counts
     __shared__ float2 stage[kSpillWaves][64];
     __shared__ uint32_t s_event, s_flags, s_max, s_n, s_list[kSpillThreads], s_part[kSpillThreads];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -2192,40 +2194,45 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
         }
         if (!dup)
             for (uint32_t i = threadIdx.x; i < H; i += kSpillThreads) ke[i] = 0u;
-        for (size_t i = threadIdx.x; i < cells; i += kSpillThreads) acc[i] = 0u;
         for (size_t i = threadIdx.x; i < (size_t)words * g.n_theta; i += kSpillThreads) dil[i] = 0u;
         spill_sync();
 
-        // steps 1-3: wave w maps its slice of the hits, 64 at a time, and votes each valid hit
-        // (not a later copy) into every column, lane = column within groups of 64
+        // steps 1-3: the accumulator is built in LDS, one 64-column group and one rho slab of
+        // sp.slab_rows rows at a time, as packed 16-bit counts (so in chunks of at most 65,535
+        // hits), each wave mapping its slice of the chunk's hits and voting the valid ones (not
+        // later copies), lane = column; each chunk's slab is then written out (first chunk) or
+        // added (later chunks) to acc by the thread that owns the cell, a wave storing one row
+        // of 64 adjacent cells.  Every cell of acc is written, so acc needs no clearing.
         uint32_t bad = 0;
-        const uint32_t hb = (uint32_t)((uint64_t)H * wave / kSpillWaves);
-        const uint32_t he = (uint32_t)((uint64_t)H * (wave + 1) / kSpillWaves);
-        for (uint32_t base = hb; base < he; base += 64) {
-            const uint32_t i = base + lane;
-            bool live = i < he;
-            if (live && dup && (ke[i] & kKeepDuplicate)) live = false;
-            float u = 0.0f, v = 0.0f;
-            const bool ok = conformal(live ? xe[i] : 0.0f, live ? ye[i] : 0.0f, u, v);
-            if (live && !ok) bad = 1u;
-            const uint64_t m = __ballot(live && ok);
-            if (live && ok) stage[wave][mbcnt(m)] = make_float2(u, v);
-            wave_sync();
-            const uint32_t n = (uint32_t)__popcll(m);
+        {
+            constexpr uint32_t kChunk = 65535u;
+            const Lane<1, true> ln(lane);
             for (int j0 = 0; j0 < g.n_theta; j0 += 64) {
+                const Cols<1> cl = load_cols<1>(g, j0, lane, Lane<1, true>::STRIDE, ln.col);
                 const int j = j0 + lane;
-                const bool in = j < g.n_theta;
-                const float C = in ? g.C[j] : 0.0f, S = in ? g.S[j] : 0.0f;
-#pragma unroll 4
-                for (uint32_t h = 0; h < n; ++h) {
-                    const float2 p = stage[wave][h];
-                    const float t = __builtin_fmaf(p.x, C, __builtin_fmaf(p.y, S, g.Bf));
-                    if (in && t >= 0.0f && t < g.nrho_f)
-                        __hip_atomic_fetch_add(acc + (size_t)(int)t * g.n_theta + j, 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+                for (int r0 = 0; r0 < g.n_rho; r0 += sp.slab_rows) {
+                    const int r1 = min(r0 + sp.slab_rows, g.n_rho);
+                    for (uint32_t c0 = 0; c0 < H; c0 += kChunk) {
+                        const uint32_t c1 = H - c0 > kChunk ? c0 + kChunk : H;
+                        for (int i = threadIdx.x; i < (r1 - r0) * Lane<1, true>::STRIDE / 4; i += kSpillThreads)
+                            reinterpret_cast<uint4 *>(spill_tile)[i] = make_uint4(0u, 0u, 0u, 0u);
+                        __syncthreads();
+                        const uint32_t hb = c0 + (uint32_t)((uint64_t)(c1 - c0) * wave / kSpillWaves);
+                        const uint32_t he = c0 + (uint32_t)((uint64_t)(c1 - c0) * (wave + 1) / kSpillWaves);
+                        (void)vote_range_slab<kSpillWaves>(spill_tile, &stage[wave][0], xe, ye, hb, he, cl, ln, g, lane,
+                                                           bad, dup ? ke : nullptr, r0, r1);
+                        __syncthreads();
+                        if (j < g.n_theta) {
+                            for (int k = r0 + wave; k < r1; k += kSpillWaves) {
+                                const uint32_t v = ln.count(spill_tile[(k - r0) * Lane<1, true>::STRIDE + ln.col[0]]);
+                                uint32_t *cell = acc + (size_t)k * g.n_theta + j;
+                                *cell = c0 ? *cell + v : v;
+                            }
+                        }
+                        __syncthreads();
+                    }
                 }
             }
-            wave_sync();
         }
         if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
         spill_sync();
@@ -2299,23 +2306,37 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
         }
         spill_sync();
 
-        // step 5: lane = hit; a hit is kept once its bin in some column falls on a dilated bit
+        // step 5, one 64-column group at a time: the group's dilated words are staged in LDS
+        // (the vote's slab space), then each wave looks its hits, 64 at a time, up in every
+        // column of the group (lane = column, the fused kernel's lookup); a hit kept by one
+        // group is not looked up again.  Bit 0 of a keep byte is the verdict; a later copy's
+        // bit 1 (duplicate pass) is dropped at the end.
         const uint32_t n_peaks = uni(s_n);
         if (n_peaks > 0) {
-            for (uint32_t base = (uint32_t)wave * 64; base < H; base += kSpillThreads) {
-                const uint32_t i = base + lane;
-                float u = 0.0f, v = 0.0f;
-                bool want = i < H && conformal(xe[i], ye[i], u, v);
-                bool kept = false;
-                for (int j = 0; j < g.n_theta && __ballot(want && !kept); ++j) {
-                    const float t = __builtin_fmaf(u, g.C[j], __builtin_fmaf(v, g.S[j], g.Bf));
-                    if (want && !kept && t >= 0.0f && t < g.nrho_f) {
-                        const int k = (int)t;
-                        kept = (spill_load(dil + (size_t)(k >> 5) * g.n_theta + j) >> (k & 31)) & 1u;
-                    }
+            const Lane<1, true> ln(lane);
+            uint32_t unused = 0;
+            for (int j0 = 0; j0 < g.n_theta; j0 += 64) {
+                // [words + 1][64]: the extra zero row is where out-of-grid lanes look
+                for (int q = threadIdx.x; q < (words + 1) * 64; q += kSpillThreads) {
+                    const int w = q >> 6, c = j0 + (q & 63);
+                    spill_tile[q] = (w < words && c < g.n_theta) ? spill_load(dil + (size_t)w * g.n_theta + c) : 0u;
                 }
-                if (i < H) ke[i] = kept ? 1u : 0u;
+                __syncthreads();
+                const Cols<1> cl = load_cols<1>(g, j0, lane, Lane<1, true>::STRIDE, ln.col);
+                for (uint32_t base = (uint32_t)wave * 64; base < H; base += kSpillThreads) {
+                    const uint32_t i = base + lane;
+                    const uint32_t kv = i < H ? ke[i] : 1u;
+                    const bool done = i < H && (kv & 1u);
+                    if (__ballot(i < H && !done) == 0ull) continue;
+                    int slot;
+                    const StageCount n = stage_hits(&stage[wave][0], xe, ye, base, H, done, g, lane, unused, slot);
+                    const uint64_t kept = lookup_staged<1>(spill_tile, &stage[wave][0], n, cl, lane, g.nrho_f);
+                    if (slot >= 0 && ((kept >> slot) & 1ull)) ke[i] = (uint8_t)(kv | 1u);
+                    wave_sync();
+                }
+                __syncthreads();
             }
+            for (uint32_t i = threadIdx.x; i < H; i += kSpillThreads) ke[i] = (uint8_t)(ke[i] & 1u);
         } else if (dup) {
             for (uint32_t i = threadIdx.x; i < H; i += kSpillThreads) ke[i] = 0u;
         }
@@ -2607,7 +2628,18 @@ size_t spill_stride(int n_theta, int n_rho) {
 
 hipError_t launch_spill(const GridArgs &g, const BatchArgs &a, const SpillArgs &sp, int n_wg, hipStream_t s) {
     if (a.n_events == 0 || n_wg < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_spill, dim3(n_wg), dim3(kSpillThreads), 0, s, g, a, sp);
+    // the slab's dynamic LDS beside the kernel's 16 KB of static LDS (allow_lds's limit would
+    // not leave room for that)
+    static const hipError_t lds_ok = hipFuncSetAttribute(reinterpret_cast<const void *>(k_spill),
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                         kSpillSlabRows * 32 * (int)sizeof(uint32_t));
+    if (lds_ok != hipSuccess) return lds_ok;
+    SpillArgs s2 = sp;
+    s2.slab_rows = g.n_rho < kSpillSlabRows ? g.n_rho : kSpillSlabRows;
+    // the slab doubles as the retention step's [words + 1][64] dilated words
+    const size_t slab = (size_t)s2.slab_rows * 32u, dil_rows = ((size_t)(g.n_rho + 31) / 32 + 1) * 64u;
+    const size_t lds = (slab > dil_rows ? slab : dil_rows) * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_spill, dim3(n_wg), dim3(kSpillThreads), lds, s, g, a, s2);
     return hipGetLastError();
 }
 
