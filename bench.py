@@ -541,18 +541,22 @@ def _split_kernel_ms(H, wl, sub, cap, reps):
     return round(total / reps, 4)
 
 
-def sweeps(H, wl, ev, reps: int = 10, cpu_budget_s: float = 20.0):
+def sweeps(H, wl, ev, reps: int = 10, cpu_budget_s: float = 20.0, plan: dict | None = None):
     """The paper's batch-scale and block-size studies, reshaped for this path (Sec. IV, Fig. 8
     and Fig. 9): (1) runtime against the number of events, GPU end to end (PCIe both ways) and
     kernel only, beside the CPU oracle on the host cores while it fits the budget; (2) per-stage
     times (transfer in, fused kernel, transfer back) against the workgroup size, at the
-    1,000-event scale.  Every point is the mean of `reps` runs, as in the paper."""
+    1,000-event scale.  Every point is the mean of `reps` runs, as in the paper.  `plan` (a
+    batch_plan dict, the benchmark's own launch shape) is used for the events study."""
     from oracle import oracle
     cap = MAX_PEAKS[wl.name]
     threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1))
     out = {"events": [], "block": [], "reps": reps, "workload": wl.name,
            "cpu": f"oracle, OpenMP over events, {threads} threads"}
     ctx = H.Context.for_workload(wl, max_peaks=cap)
+    if plan is not None:
+        ctx.set_batch_plan(plan["waves_per_group"], plan["column_groups"], plan["groups_per_cu"])
+    out["plan"] = dict(ctx.batch_plan)
     spent, per_event = 0.0, 0.0
     for n in (1, 10, 100, 1000, 10000):
         idx = np.arange(n) % ev.n_events              # past the generated events: repeated ones
@@ -851,7 +855,7 @@ def main(argv=None):
         out["autotune_ms"] = tuned["ms"]
         out["autotune_pick"] = tuned["plan"]
     if args.sweeps:
-        out["sweeps"] = sweeps(H, wl, ev)
+        out["sweeps"] = sweeps(H, wl, ev, plan=ctx.batch_plan)
     if args.copy_reference_mb:
         n = args.copy_reference_mb << 20
         src = torch.empty(n, dtype=torch.uint8, device="cuda")
