@@ -123,8 +123,8 @@ typedef struct hough_ctx hough_ctx;   /* opaque; owned by the library */
  * On success *out receives a new context.  Returns HOUGH_EINVAL for a bad grid or parameter
  * (including n_rho above hough_max_n_rho()), HOUGH_ENOMEM / HOUGH_EDEVICE on allocation or
  * copy failure.  The workspace includes the spill path's device-memory accumulators (see
- * hough_run_batch): a few events' worth, or up to 256 MiB for a grid taller than the fused
- * kernel's tile. */
+ * hough_run_batch): a few events' worth, or for a grid taller than the fused kernel's tile one
+ * event's worth per CU up to 2 GiB (fewer where the device has not that much free). */
 int hough_config(const hough_params *p, hough_ctx **out);
 
 /* Release a context (waits for nothing: the caller must have finished its work on it). */

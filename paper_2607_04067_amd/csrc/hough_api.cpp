@@ -63,9 +63,11 @@ bool fused_fits(int n_rho, size_t limit) {
     return hough::plan_batch(1, n_rho, 4, 1, limit, &p) == 0;
 }
 
-// Spill-path workgroups: enough to fill the chip within a 256 MiB budget where every event
-// spills, else a few for the rare events above the fused kernel's hit limit.
-constexpr size_t kSpillBudgetBytes = (size_t)256 << 20;
+// Spill-path workgroups: one per CU within a 2 GiB budget where every event may spill (each
+// takes its own event, so the workgroup count is the path's parallelism: 1000 x 2000 bins with
+// 8.5 MB per slice gets 240 workgroups), else a few for the rare events above the fused
+// kernel's hit limit.
+constexpr size_t kSpillBudgetBytes = (size_t)2048 << 20;
 int spill_workgroups(size_t stride_words, int n_cu, bool all) {
     const size_t per = stride_words * 4;
     size_t n = per ? kSpillBudgetBytes / per : 1;
@@ -254,9 +256,15 @@ int hough_config(const hough_params *p, hough_ctx **out) {
     c->fused = fused_fits(p->n_rho, limit) ? 1 : ((p->flags & HOUGH_FLAG_THETA_PERIODIC) ? 0 : 2);
     c->spill_stride = hough::spill_stride(p->n_theta, p->n_rho);
     c->spill_wgs = spill_workgroups(c->spill_stride, c->n_cu, c->fused != 1);
-    if (hipMalloc(&c->d_spill, c->spill_stride * 4 * (size_t)c->spill_wgs) != hipSuccess) {
-        hough_destroy(c);
-        return HOUGH_ENOMEM;
+    // fewer slices where the device cannot spare the budget
+    while (hipMalloc(&c->d_spill, c->spill_stride * 4 * (size_t)c->spill_wgs) != hipSuccess) {
+        (void)hipGetLastError();             // clear the failed allocation's error
+        c->d_spill = nullptr;
+        if (c->spill_wgs == 1) {
+            hough_destroy(c);
+            return HOUGH_ENOMEM;
+        }
+        c->spill_wgs = (c->spill_wgs + 1) / 2;
     }
     if (hipMemcpy(c->d_tables, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->d_work, 0, work_bytes) != hipSuccess) {
