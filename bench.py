@@ -34,7 +34,7 @@ DEFAULT_WORKLOAD = "batch-10000ev-360x256"
 # Per-event capacity of the peak list; every event of these workloads fits (no truncation).
 MAX_PEAKS = {"plain-16ev-180x128": 1024, "paper-1000ev-360x256": 8192,
              "batch-10000ev-360x256": 8192, "dense-2000ev-720x512": 16384,
-             "paper-1000ev-1000x1000": 4096}
+             "paper-1000ev-1000x1000": 4096, "paper-1000ev-1000x2000": 4096}
 
 # MI355X: 256 CUs, 4 SIMD16 units each, 2.4 GHz peak engine clock.
 N_CU, LANES_PER_CU_CLK, CLOCK_HZ = 256, 64, 2.4e9

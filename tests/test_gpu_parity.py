@@ -368,26 +368,30 @@ def _host_threads() -> int:
     return max(1, min(16, n))
 
 
-@pytest.mark.parametrize("name", ["paper-1000ev-360x256", "batch-10000ev-360x256", "dense-2000ev-720x512",
-                                  "paper-1000ev-1000x1000"])
-def test_full_size_every_event(H, orc, name):
+@pytest.mark.parametrize("name,periodic", [("paper-1000ev-360x256", False), ("batch-10000ev-360x256", False),
+                                           ("dense-2000ev-720x512", False), ("paper-1000ev-1000x1000", False),
+                                           ("paper-1000ev-1000x2000", False), ("paper-1000ev-1000x2000", True)])
+def test_full_size_every_event(H, orc, name, periodic):
     """The whole workload in one launch, as the benchmark times it; every event's peak list, true
-    count, status and keep bytes equal the oracle's (the oracle runs on all host cores)."""
+    count, status and keep bytes equal the oracle's (the oracle runs on all host cores).  The
+    2000-row grid runs windowed tiles, and with the theta-periodic test the device-memory path
+    for every event."""
     import torch
     from bench import MAX_PEAKS
     wl = synth.WORKLOADS[name]
     cap = MAX_PEAKS[name]
     ev = synth.make_events(wl, 0)
-    ctx = H.Context.for_workload(wl, max_peaks=cap)
+    ctx = H.Context.for_workload(wl, max_peaks=cap, periodic=periodic)
     xt, yt, ot = H.to_device(ev)
-    say(f"full {name}: {ev.n_events} events, {ev.n_hits} hits, plan {ctx.batch_plan}")
+    say(f"full {name} periodic={periodic}: {ev.n_events} events, {ev.n_hits} hits, plan {ctx.batch_plan}")
     peaks, npk, keep, st = ctx.run_batch(xt, yt, ot)
     torch.cuda.synchronize()
     npk = npk.cpu().numpy().astype(np.int64)
     keep = keep.cpu().numpy()
     st = st.cpu().numpy()
     peaks = peaks.cpu().numpy()
-    pk_ref, n_ref, keep_ref = orc.run_batch(wl, ev.x, ev.y, ev.offsets, cap=cap, n_threads=_host_threads())
+    pk_ref, n_ref, keep_ref = orc.run_batch(wl, ev.x, ev.y, ev.offsets, cap=cap, n_threads=_host_threads(),
+                                            periodic=periodic)
     assert np.array_equal(npk, n_ref)
     assert np.array_equal(st, np.where(n_ref > cap, H.EV_PEAKS_TRUNCATED, 0))
     assert np.array_equal(keep, keep_ref)
