@@ -2169,6 +2169,7 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
     uint32_t *dil = acc + cells;                          // [words][n_theta]
     uint32_t *colpos = dil + (size_t)words * g.n_theta;   // [n_theta * words + 1] per (column, block)
     const int n_items = g.n_theta * words;                // (column, 32-row block), column-major
+    uint32_t *pmask = colpos + n_items + 1;               // [n_items]: each block's peak rows
 
     // Every value that steers control flow around a barrier is wave-uniform (scalar), and an
     // event that is skipped passes a barrier before it returns, as a processed one does at its
@@ -2250,14 +2251,17 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
             thr = (uint32_t)min<uint64_t>(max<uint64_t>(rel, g.threshold), 0x7fffffffull);
         }
 
-        // step 4, first pass: each (column, block)'s peak count.  Neighbouring threads take
-        // neighbouring columns of one block, so that a wave's loads of a row are one run of
-        // cells; the counts are stored column-major (raster order)
+        // step 4, first pass: each (column, block)'s peak rows as a bit mask, and their number.
+        // Neighbouring threads take neighbouring columns of one block, so that a wave's loads of
+        // a row are one run of cells; both are stored column-major (raster order).  The listing
+        // pass then reads only the peak cells (a second 3x3 walk read the whole accumulator
+        // again)
         for (int it = threadIdx.x; it < n_items; it += kSpillThreads) {
             const int b = it / g.n_theta, j = it - b * g.n_theta;
-            uint32_t c = 0;
-            spill_block_peaks(acc, g, j, b, thr, [&](int, uint32_t) { ++c; });
-            colpos[j * words + b] = c;
+            uint32_t m = 0;
+            spill_block_peaks(acc, g, j, b, thr, [&](int k, uint32_t) { m |= 1u << (k & 31); });
+            pmask[j * words + b] = m;
+            colpos[j * words + b] = (uint32_t)__popc(m);
         }
         spill_sync();
         // exclusive prefix over the items (raster order is column-major, rows in order within a
@@ -2286,16 +2290,18 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
             run += v;
         }
         spill_sync();
-        // second pass: list each block's peaks in row order at its position, and mark the rows
-        // within rho_window of each peak in the column's dilated bits (words other blocks of the
-        // column may mark too: atomic ORs, in L2)
+        // second pass (the same items on the same threads, so each reads its own mask): list
+        // each block's peaks in row order at its position, and mark the rows within rho_window
+        // of each peak in the column's dilated bits (words other blocks of the column may mark
+        // too: atomic ORs, in L2)
         hough_peak *pe = a.peaks ? a.peaks + (size_t)e * a.max_peaks : nullptr;
         const uint32_t cap = pe ? a.max_peaks : 0u;
         for (int it = threadIdx.x; it < n_items; it += kSpillThreads) {
             const int b = it / g.n_theta, j = it - b * g.n_theta;
             uint32_t pos = colpos[j * words + b];
-            spill_block_peaks(acc, g, j, b, thr, [&](int k, uint32_t c) {
-                if (pos < cap) store_peak(pe + pos, (uint32_t)j, (uint32_t)k, c);
+            for (uint32_t m = pmask[j * words + b]; m; m &= m - 1u) {
+                const int k = 32 * b + (__ffs(m) - 1);
+                if (pos < cap) store_peak(pe + pos, (uint32_t)j, (uint32_t)k, spill_load(acc + (size_t)k * g.n_theta + j));
                 ++pos;
                 const int lo = max(k - g.rho_window, 0), hi = min(k + g.rho_window, g.n_rho - 1);
                 for (int wd = lo >> 5; wd <= (hi >> 5); ++wd) {
@@ -2304,7 +2310,7 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
                     __hip_atomic_fetch_or(dil + (size_t)wd * g.n_theta + j, msk, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
                 }
-            });
+            }
         }
         spill_sync();
 
@@ -2623,8 +2629,9 @@ hipError_t launch_order(const uint32_t *offsets, uint32_t n_events, uint32_t *or
 
 size_t spill_stride(int n_theta, int n_rho) {
     const size_t words = (size_t)(n_rho + 31) / 32;
-    // accumulator, dilated words, one peak count per (column, 32-row block) and its end
-    const size_t n = (size_t)n_theta * n_rho + words * n_theta + words * n_theta + 1;
+    // accumulator, dilated words, one peak count per (column, 32-row block) and its end, one
+    // peak-row mask per (column, block)
+    const size_t n = (size_t)n_theta * n_rho + words * n_theta + words * n_theta + 1 + words * n_theta;
     return (n + 63) & ~(size_t)63;                  // each workgroup's slice on a 256-byte boundary
 }
 
