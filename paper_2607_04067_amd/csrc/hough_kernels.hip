@@ -2167,9 +2167,12 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
     const int words = (g.n_rho + 31) / 32;
     uint32_t *acc = sp.acc + (size_t)blockIdx.x * sp.stride;
     uint32_t *dil = acc + cells;                          // [words][n_theta]
-    uint32_t *colpos = dil + (size_t)words * g.n_theta;   // [n_theta * words + 1] per (column, block)
-    const int n_items = g.n_theta * words;                // (column, 32-row block), column-major
-    uint32_t *pmask = colpos + n_items + 1;               // [n_items]: each block's peak rows
+    // Work items are (column, 32-row block) pairs, item it = block it / n_theta of column
+    // it mod n_theta; the per-item arrays are stored in item order
+    const int n_items = g.n_theta * words;
+    uint32_t *pmask = dil + (size_t)words * g.n_theta;    // [n_items] each block's peak rows
+    uint32_t *colpos = pmask + n_items;                   // [n_items] its first peak's place in its column
+    uint32_t *colstart = colpos + n_items;                // [n_theta + 1] each column's first peak
 
     // Every value that steers control flow around a barrier is wave-uniform (scalar), and an
     // event that is skipped passes a barrier before it returns, as a processed one does at its
@@ -2251,26 +2254,36 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
             thr = (uint32_t)min<uint64_t>(max<uint64_t>(rel, g.threshold), 0x7fffffffull);
         }
 
-        // step 4, first pass: each (column, block)'s peak rows as a bit mask, and their number.
-        // Neighbouring threads take neighbouring columns of one block, so that a wave's loads of
-        // a row are one run of cells; both are stored column-major (raster order).  The listing
-        // pass then reads only the peak cells (a second 3x3 walk read the whole accumulator
-        // again)
+        // step 4, first pass: each item's peak rows as a bit mask.  Neighbouring threads take
+        // neighbouring columns of one block, so that a wave's loads of a row are one run of
+        // cells and its stores of the masks are too (stored column-major, every 4-byte store
+        // dirtied a line of its own: 2 GB more written per 1,000 events on 1000 x 2000).  The
+        // listing pass then reads only the peak cells (a second 3x3 walk read the whole
+        // accumulator again)
         for (int it = threadIdx.x; it < n_items; it += kSpillThreads) {
             const int b = it / g.n_theta, j = it - b * g.n_theta;
             uint32_t m = 0;
             spill_block_peaks(acc, g, j, b, thr, [&](int k, uint32_t) { m |= 1u << (k & 31); });
-            pmask[j * words + b] = m;
-            colpos[j * words + b] = (uint32_t)__popc(m);
+            pmask[it] = m;
         }
         spill_sync();
-        // exclusive prefix over the items (raster order is column-major, rows in order within a
-        // column): each thread sums a run of items, the runs' totals are scanned, then each run
-        // is scanned again
-        const int per = (n_items + kSpillThreads - 1) / kSpillThreads;
-        const int c0 = min((int)threadIdx.x * per, n_items), c1 = min(c0 + per, n_items);
+        // raster order is column-major with rows in order within a column: a thread per column
+        // places each block's peaks within the column (neighbouring threads, neighbouring
+        // columns: coalesced), then an exclusive prefix over the columns' totals (each thread
+        // sums a run of columns, the runs' totals are scanned, then each run is scanned again)
+        for (int j = threadIdx.x; j < g.n_theta; j += kSpillThreads) {
+            uint32_t in_col = 0;
+            for (int b = 0; b < words; ++b) {
+                colpos[b * g.n_theta + j] = in_col;
+                in_col += (uint32_t)__popc(pmask[b * g.n_theta + j]);
+            }
+            colstart[j] = in_col;
+        }
+        spill_sync();
+        const int per = (g.n_theta + kSpillThreads - 1) / kSpillThreads;
+        const int c0 = min((int)threadIdx.x * per, g.n_theta), c1 = min(c0 + per, g.n_theta);
         uint32_t part = 0;
-        for (int j = c0; j < c1; ++j) part += colpos[j];
+        for (int j = c0; j < c1; ++j) part += colstart[j];
         s_part[threadIdx.x] = part;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -2285,21 +2298,20 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
         __syncthreads();
         uint32_t run = s_part[threadIdx.x];
         for (int j = c0; j < c1; ++j) {
-            const uint32_t v = colpos[j];
-            colpos[j] = run;
+            const uint32_t v = colstart[j];
+            colstart[j] = run;
             run += v;
         }
         spill_sync();
-        // second pass (the same items on the same threads, so each reads its own mask): list
-        // each block's peaks in row order at its position, and mark the rows within rho_window
-        // of each peak in the column's dilated bits (words other blocks of the column may mark
-        // too: atomic ORs, in L2)
+        // second pass: list each block's peaks in row order at its position, and mark the rows
+        // within rho_window of each peak in the column's dilated bits (words other blocks of the
+        // column may mark too: atomic ORs, in L2)
         hough_peak *pe = a.peaks ? a.peaks + (size_t)e * a.max_peaks : nullptr;
         const uint32_t cap = pe ? a.max_peaks : 0u;
         for (int it = threadIdx.x; it < n_items; it += kSpillThreads) {
             const int b = it / g.n_theta, j = it - b * g.n_theta;
-            uint32_t pos = colpos[j * words + b];
-            for (uint32_t m = pmask[j * words + b]; m; m &= m - 1u) {
+            uint32_t pos = colstart[j] + colpos[it];
+            for (uint32_t m = pmask[it]; m; m &= m - 1u) {
                 const int k = 32 * b + (__ffs(m) - 1);
                 if (pos < cap) store_peak(pe + pos, (uint32_t)j, (uint32_t)k, spill_load(acc + (size_t)k * g.n_theta + j));
                 ++pos;
@@ -2629,9 +2641,9 @@ hipError_t launch_order(const uint32_t *offsets, uint32_t n_events, uint32_t *or
 
 size_t spill_stride(int n_theta, int n_rho) {
     const size_t words = (size_t)(n_rho + 31) / 32;
-    // accumulator, dilated words, one peak count per (column, 32-row block) and its end, one
-    // peak-row mask per (column, block)
-    const size_t n = (size_t)n_theta * n_rho + words * n_theta + words * n_theta + 1 + words * n_theta;
+    // accumulator, dilated words, per (column, 32-row block) a peak-row mask and the place of
+    // its first peak within the column, per column the place of its first peak (and the end)
+    const size_t n = (size_t)n_theta * n_rho + 3 * words * n_theta + n_theta + 1;
     return (n + 63) & ~(size_t)63;                  // each workgroup's slice on a 256-byte boundary
 }
 
