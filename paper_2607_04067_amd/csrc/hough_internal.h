@@ -113,7 +113,6 @@ struct SpillArgs {
     uint32_t *queue;     // [3], zero between launches: all = 1: work and exit counters; all = 0:
                          // the count of events left to it, the exit counter, the block counter
     uint32_t all;
-    int slab_rows;       // set by launch_spill: rho rows of the vote's LDS slab
 };
 size_t spill_stride(int n_theta, int n_rho);
 hipError_t launch_spill(const GridArgs &g, const BatchArgs &a, const SpillArgs &sp, int n_wg, hipStream_t s);

@@ -19,6 +19,7 @@
 #include <float.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "hough_internal.h"
 
@@ -2094,72 +2095,135 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
 constexpr int kSpillWaves = 16;
 constexpr int kSpillThreads = kSpillWaves * 64;
 constexpr uint32_t kSpillBlock = 4;      // events per counter pop when only some events spill
-constexpr int kSpillSlabRows = 1024;     // rho rows of the vote's LDS slab (128 KB of packed counts)
+constexpr int kSpillSlabDwords = 32768;  // the slab: 128 KB of dynamic LDS
+constexpr int kSpillOwnedPacked = 992;   // owned rows of a packed slab: 31 blocks + 2 halo rows <= 1,024
+constexpr int kSpillOwnedWide = 480;     // owned rows of a 32-bit slab: 15 blocks + 2 halo rows <= 512
 
-// A word of the accumulator or of the dilated bits, read past the L1 (the bits are ORed by
-// atomics in L2; the accumulator, stored by other waves of the workgroup, is read the same way:
-// plain loads through the L1 measured 2% faster, not worth a second rule).
+// A word of the dilated bits (ORed by atomics in L2) or a peak's count in the accumulator,
+// read past the L1.
 __device__ __forceinline__ uint32_t spill_load(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Count of cell (column j, row k) of an event's accumulator, 0 outside the grid; on a
-// theta-periodic grid the column left of 0 is column n_theta - 1 and the column right of
-// n_theta - 1 is column 0, both with rho reversed.
-__device__ __forceinline__ uint32_t spill_cell(const uint32_t *acc, const GridArgs &g, int j, int k) {
-    if (g.periodic && (j == -1 || j == g.n_theta)) {
-        j = j < 0 ? g.n_theta - 1 : 0;
-        k = g.n_rho - 1 - k;
-    }
-    if (j < 0 || j >= g.n_theta || k < 0 || k >= g.n_rho) return 0u;
-    return spill_load(acc + (size_t)k * g.n_theta + j);
 }
 
 // The spill kernel's device memory belongs to one workgroup, so workgroup scope orders it: the
 // release waits for this wave's stores and atomics, the barrier lines the waves up.  The waves
 // of a workgroup share one L1, which their plain stores go through; the dilation's atomic ORs
-// are performed beyond it (in L2), so the dilated bits, and the accumulator with them, are read
-// with loads that bypass the L1 (spill_load).  (Agent-scope fences here wrote back the whole L2 at every barrier: with many
-// workgroups spilling at once that took most of the kernel's time.)
+// are performed beyond it (in L2), so the dilated bits, and the peak counts with them, are read
+// with loads that bypass the L1 (spill_load).  (Agent-scope fences here wrote back the whole
+// L2 at every barrier: with many workgroups spilling at once that took most of the kernel's
+// time.)
 __device__ __forceinline__ void spill_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// One pass of step 4 over rows [32b, 32b + 32) of column j: calls f(k, count) for every peak,
-// in row order.  Raster order: the column before (j - 1) and the row above come first, except
-// that on a periodic grid the wrapped column left of column 0 comes later and the one right of
-// the last column earlier.  The blocks of all columns are independent work items, so the
-// workgroup's threads walk many of them at once (a thread walking a whole column waited on
-// its loads row after row).
-template <typename F>
-__device__ __forceinline__ void spill_block_peaks(const uint32_t *acc, const GridArgs &g, int j, int b, uint32_t thr,
-                                                  F &&f) {
+// The spill kernel's LDS slab: one group of up to 62 owned columns with a halo lane on each
+// side (lane l holds column first + l - 1; on a theta-periodic grid the halo beyond either edge
+// holds the wrapped column with rho reversed, as in the fused kernel) and owned rows [ro, ro1)
+// with one halo row on each side (slab row i holds grid row ro - 1 + i).  P: two 16-bit counts
+// per dword (events of at most 65,535 hits), else one 32-bit count per cell.
+template <bool P>
+struct SpillSlab {
+    const uint32_t *tile;
+    static constexpr int STRIDE = Lane<1, P>::STRIDE;      // dwords per slab row
+    __device__ __forceinline__ uint32_t count(int l, int i) const {
+        if (P) return (tile[i * STRIDE + (l & 31)] >> (16 * (l >> 5))) & 0xffffu;
+        return tile[i * STRIDE + l];
+    }
+};
+
+// Steps 1-3 into the slab: votes of hits [hb, he) by the whole-grid rule (bin k of the lane's
+// column, a wrapped halo lane taking row n_rho - 1 - k), kept when r0 <= k < r1, at slab row
+// k - base.  dup as for vote_range.
+template <bool P>
+__device__ void spill_vote_slab(uint32_t *tile, float2 *st, const float *x, const float *y, uint32_t hb,
+                                uint32_t he, const Cols<1> &cl, bool wrap, const GridArgs &g, int lane,
+                                uint32_t &bad, const uint8_t *dup, int r0, int r1, int base) {
+    const Lane<1, P> ln(lane);
+    for (uint32_t b0 = hb; b0 < he; b0 += 64) {
+        const uint32_t i = b0 + lane;
+        bool live = i < he;
+        float xi = 0.0f, yi = 0.0f;
+        if (live) { xi = x[i]; yi = y[i]; }
+        if (dup && live && (dup[i] & kKeepDuplicate)) live = false;
+        int slot;
+        const StageCount n = stage_values(st, xi, yi, live, g, bad, slot);
+        for (uint32_t h = 0; h < n.total; ++h) {
+            const float2 p = st[h];
+            const float t = __builtin_fmaf(p.x, cl.C[0], __builtin_fmaf(p.y, cl.S[0], cl.B[0]));
+            if (t >= 0.0f && t < g.nrho_f) {
+                const int k = wrap ? g.n_rho - 1 - (int)t : (int)t;
+                if (k >= r0 && k < r1) lds_add(&tile[(k - base) * Lane<1, P>::STRIDE + (int)ln.col[0]], ln.inc);
+            }
+        }
+        wave_sync();
+    }
+}
+
+// Step 4 on rows [k0, k1) of slab lane l (owned column j): bit k - k0 of the result is set iff
+// cell (j, k) is a peak, and each peak's count is stored to acc for the listing pass.  Raster
+// order: the column before (j - 1) and the row above come first, except that on a periodic
+// grid the wrapped column left of column 0 comes later and the one right of the last column
+// earlier; rows outside the grid are the slab's zero halo rows.
+template <bool P>
+__device__ uint32_t spill_slab_peaks(const SpillSlab<P> &s, int l, int j, int k0, int k1, int base,
+                                     uint32_t thr, const GridArgs &g, uint32_t *acc) {
     const bool left_later = g.periodic && j == 0, right_earlier = g.periodic && j == g.n_theta - 1;
-    const int k0 = 32 * b, k1 = min(k0 + 32, g.n_rho);
-    // window rows k - 1, k, k + 1 of columns j - 1, j, j + 1
-    uint32_t l0 = spill_cell(acc, g, j - 1, k0 - 1), c0 = spill_cell(acc, g, j, k0 - 1),
-             r0 = spill_cell(acc, g, j + 1, k0 - 1);
-    uint32_t l1 = spill_cell(acc, g, j - 1, k0), c1 = spill_cell(acc, g, j, k0), r1 = spill_cell(acc, g, j + 1, k0);
-#pragma unroll 4
-    for (int k = k0; k < k1; ++k) {
-        const uint32_t l2 = spill_cell(acc, g, j - 1, k + 1), c2 = spill_cell(acc, g, j, k + 1),
-                       r2 = spill_cell(acc, g, j + 1, k + 1);
+    int i = k0 - base;
+    uint32_t l0 = s.count(l - 1, i - 1), c0 = s.count(l, i - 1), r0 = s.count(l + 1, i - 1);
+    uint32_t l1 = s.count(l - 1, i), c1 = s.count(l, i), r1 = s.count(l + 1, i);
+    uint32_t m = 0;
+    for (int k = k0; k < k1; ++k, ++i) {
+        const uint32_t l2 = s.count(l - 1, i + 1), c2 = s.count(l, i + 1), r2 = s.count(l + 1, i + 1);
         if (c1 >= thr) {
             const uint32_t lm = max(max(l0, l1), l2), rm = max(max(r0, r1), r2);
             const uint32_t before = max(max(left_later ? 0u : lm, right_earlier ? rm : 0u), c0);
             const uint32_t after = max(max(left_later ? lm : 0u, right_earlier ? 0u : rm), c2);
-            if (c1 >= max(before + 1u, after)) f(k, c1);
+            if (c1 >= max(before + 1u, after)) {
+                m |= 1u << (k - k0);
+                acc[(size_t)k * g.n_theta + j] = c1;
+            }
         }
         l0 = l1; l1 = l2;
         c0 = c1; c1 = c2;
         r0 = r1; r1 = r2;
     }
+    return m;
+}
+
+// Every (group, slab) of the grid in turn: clear the slab, vote the event's hits into it (wave
+// w maps its slice of the hits), then f(slab, first owned column, ro, ro1, base) between
+// barriers.
+template <bool P, typename F>
+__device__ void spill_for_slabs(uint32_t *tile, float2 *st, const float *x, const float *y, uint32_t H,
+                                const GridArgs &g, int lane, int wave, uint32_t &bad, const uint8_t *dup, F &&f) {
+    constexpr int owned = P ? kSpillOwnedPacked : kSpillOwnedWide;
+    constexpr int stride = Lane<1, P>::STRIDE;
+    const Lane<1, P> ln(lane);
+    const uint32_t hb = (uint32_t)((uint64_t)H * wave / kSpillWaves);
+    const uint32_t he = (uint32_t)((uint64_t)H * (wave + 1) / kSpillWaves);
+    for (int jo = 0; jo < g.n_theta; jo += 62) {
+        const int j = jo - 1 + lane;
+        const bool wrap = g.periodic && (j == -1 || j == g.n_theta);
+        const Cols<1> cl = g.periodic ? load_cols<1, true>(g, jo - 1, lane, stride, ln.col)
+                                      : load_cols<1, false>(g, jo - 1, lane, stride, ln.col);
+        for (int ro = 0; ro < g.n_rho; ro += owned) {
+            const int ro1 = min(ro + owned, g.n_rho), base = ro - 1, rows = ro1 - ro + 2;
+            for (int i = threadIdx.x; i < rows * stride / 4; i += kSpillThreads)
+                reinterpret_cast<uint4 *>(tile)[i] = make_uint4(0u, 0u, 0u, 0u);
+            __syncthreads();
+            spill_vote_slab<P>(tile, st, x, y, hb, he, cl, wrap, g, lane, bad, dup, max(ro - 1, 0),
+                               min(ro1 + 1, g.n_rho), base);
+            __syncthreads();
+            f(SpillSlab<P>{tile}, jo, ro, ro1, base);
+            __syncthreads();
+        }
+    }
 }
 
 __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a, SpillArgs sp) {
-    extern __shared__ __align__(16) uint32_t spill_tile[];      // [slab_rows * 32] packed counts
+    extern __shared__ __align__(16) uint32_t spill_tile[];      // [kSpillSlabDwords]
     __shared__ float2 stage[kSpillWaves][64];
     __shared__ uint32_t s_event, s_flags, s_max, s_n, s_list[kSpillThreads], s_part[kSpillThreads];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -2203,69 +2267,44 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
         for (size_t i = threadIdx.x; i < (size_t)words * g.n_theta; i += kSpillThreads) dil[i] = 0u;
         spill_sync();
 
-        // steps 1-3: the accumulator is built in LDS, one 64-column group and one rho slab of
-        // sp.slab_rows rows at a time, as packed 16-bit counts (so in chunks of at most 65,535
-        // hits), each wave mapping its slice of the chunk's hits and voting the valid ones (not
-        // later copies), lane = column; each chunk's slab is then written out (first chunk) or
-        // added (later chunks) to acc by the thread that owns the cell, a wave storing one row
-        // of 64 adjacent cells.  Every cell of acc is written, so acc needs no clearing.
+        // steps 1-4 on chip, one slab at a time: vote, then the 3x3 test of every owned cell,
+        // giving each (column, 32-row block) item its peak rows as a bit mask (stored in item
+        // order: neighbouring threads take neighbouring columns) and each peak's count in acc.
+        // Only peak cells reach device memory (writing the whole accumulator out and walking it
+        // there was three quarters of the path's time).  The relative threshold needs the
+        // event's largest count first: one more round of votes.
         uint32_t bad = 0;
-        {
-            constexpr uint32_t kChunk = 65535u;
-            const Lane<1, true> ln(lane);
-            for (int j0 = 0; j0 < g.n_theta; j0 += 64) {
-                const Cols<1> cl = load_cols<1>(g, j0, lane, Lane<1, true>::STRIDE, ln.col);
-                const int j = j0 + lane;
-                for (int r0 = 0; r0 < g.n_rho; r0 += sp.slab_rows) {
-                    const int r1 = min(r0 + sp.slab_rows, g.n_rho);
-                    for (uint32_t c0 = 0; c0 < H; c0 += kChunk) {
-                        const uint32_t c1 = H - c0 > kChunk ? c0 + kChunk : H;
-                        for (int i = threadIdx.x; i < (r1 - r0) * Lane<1, true>::STRIDE / 4; i += kSpillThreads)
-                            reinterpret_cast<uint4 *>(spill_tile)[i] = make_uint4(0u, 0u, 0u, 0u);
-                        __syncthreads();
-                        const uint32_t hb = c0 + (uint32_t)((uint64_t)(c1 - c0) * wave / kSpillWaves);
-                        const uint32_t he = c0 + (uint32_t)((uint64_t)(c1 - c0) * (wave + 1) / kSpillWaves);
-                        (void)vote_range_slab<kSpillWaves>(spill_tile, &stage[wave][0], xe, ye, hb, he, cl, ln, g, lane,
-                                                           bad, dup ? ke : nullptr, r0, r1);
-                        __syncthreads();
-                        if (j < g.n_theta) {
-                            for (int k = r0 + wave; k < r1; k += kSpillWaves) {
-                                const uint32_t v = ln.count(spill_tile[(k - r0) * Lane<1, true>::STRIDE + ln.col[0]]);
-                                uint32_t *cell = acc + (size_t)k * g.n_theta + j;
-                                *cell = c0 ? *cell + v : v;
-                            }
-                        }
-                        __syncthreads();
-                    }
-                }
-            }
-        }
-        if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
-        spill_sync();
-
         uint32_t thr = g.threshold;
-        if (a.frac_den) {                    // relative threshold: the event's largest count first
-            uint32_t m = 0;
-            for (size_t i = threadIdx.x; i < cells; i += kSpillThreads) m = max(m, spill_load(acc + i));
-            m = wave_max(m);
-            if (lane == 0) atomicMax(&s_max, m);
-            __syncthreads();
-            const uint64_t rel = ((uint64_t)uni(s_max) * a.frac_num + a.frac_den - 1u) / a.frac_den;
-            thr = (uint32_t)min<uint64_t>(max<uint64_t>(rel, g.threshold), 0x7fffffffull);
-        }
-
-        // step 4, first pass: each item's peak rows as a bit mask.  Neighbouring threads take
-        // neighbouring columns of one block, so that a wave's loads of a row are one run of
-        // cells and its stores of the masks are too (stored column-major, every 4-byte store
-        // dirtied a line of its own: 2 GB more written per 1,000 events on 1000 x 2000).  The
-        // listing pass then reads only the peak cells (a second 3x3 walk read the whole
-        // accumulator again)
-        for (int it = threadIdx.x; it < n_items; it += kSpillThreads) {
-            const int b = it / g.n_theta, j = it - b * g.n_theta;
-            uint32_t m = 0;
-            spill_block_peaks(acc, g, j, b, thr, [&](int k, uint32_t) { m |= 1u << (k & 31); });
-            pmask[it] = m;
-        }
+        const uint8_t *dupk = dup ? ke : nullptr;
+        auto slabs = [&](auto packed) {
+            constexpr bool P = decltype(packed)::value;
+            if (a.frac_den) {
+                spill_for_slabs<P>(spill_tile, &stage[wave][0], xe, ye, H, g, lane, wave, bad, dupk,
+                                   [&](const SpillSlab<P> &sl, int, int ro, int ro1, int) {
+                    uint32_t m = 0;
+                    for (int i = threadIdx.x; i < (ro1 - ro + 2) * SpillSlab<P>::STRIDE; i += kSpillThreads) {
+                        const uint32_t v = sl.tile[i];
+                        m = max(m, P ? max(v & 0xffffu, v >> 16) : v);
+                    }
+                    m = wave_max(m);
+                    if (lane == 0) atomicMax(&s_max, m);
+                });
+                const uint64_t rel = ((uint64_t)uni(s_max) * a.frac_num + a.frac_den - 1u) / a.frac_den;
+                thr = (uint32_t)min<uint64_t>(max<uint64_t>(rel, g.threshold), 0x7fffffffull);
+            }
+            spill_for_slabs<P>(spill_tile, &stage[wave][0], xe, ye, H, g, lane, wave, bad, dupk,
+                               [&](const SpillSlab<P> &sl, int jo, int ro, int ro1, int base) {
+                const int nl = min(62, g.n_theta - jo), nb = (ro1 - ro + 31) / 32;
+                for (int t = threadIdx.x; t < nl * nb; t += kSpillThreads) {
+                    const int bs = t / nl, l = 1 + (t - bs * nl), j = jo + l - 1;
+                    const int k0 = ro + 32 * bs, k1 = min(k0 + 32, ro1);
+                    pmask[(k0 >> 5) * g.n_theta + j] = spill_slab_peaks<P>(sl, l, j, k0, k1, base, thr, g, acc);
+                }
+            });
+        };
+        if (H <= 65535u) slabs(std::true_type{});
+        else slabs(std::false_type{});
+        if (__ballot(bad != 0u) && lane == 0) atomicOr(&s_flags, HOUGH_EV_INVALID_HITS);
         spill_sync();
         // raster order is column-major with rows in order within a column: a thread per column
         // places each block's peaks within the column (neighbouring threads, neighbouring
@@ -2650,17 +2689,14 @@ size_t spill_stride(int n_theta, int n_rho) {
 hipError_t launch_spill(const GridArgs &g, const BatchArgs &a, const SpillArgs &sp, int n_wg, hipStream_t s) {
     if (a.n_events == 0 || n_wg < 1) return hipSuccess;
     // the slab's dynamic LDS beside the kernel's 16 KB of static LDS (allow_lds's limit would
-    // not leave room for that)
+    // not leave room for that); the slab doubles as the retention step's [words + 1][64]
+    // dilated words (at most 257 * 64 dwords)
+    constexpr int kBytes = kSpillSlabDwords * (int)sizeof(uint32_t);
     static const hipError_t lds_ok = hipFuncSetAttribute(reinterpret_cast<const void *>(k_spill),
-                                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                         kSpillSlabRows * 32 * (int)sizeof(uint32_t));
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, kBytes);
     if (lds_ok != hipSuccess) return lds_ok;
-    SpillArgs s2 = sp;
-    s2.slab_rows = g.n_rho < kSpillSlabRows ? g.n_rho : kSpillSlabRows;
-    // the slab doubles as the retention step's [words + 1][64] dilated words
-    const size_t slab = (size_t)s2.slab_rows * 32u, dil_rows = ((size_t)(g.n_rho + 31) / 32 + 1) * 64u;
-    const size_t lds = (slab > dil_rows ? slab : dil_rows) * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_spill, dim3(n_wg), dim3(kSpillThreads), lds, s, g, a, s2);
+    if (((size_t)(g.n_rho + 31) / 32 + 1) * 64u > (size_t)kSpillSlabDwords) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_spill, dim3(n_wg), dim3(kSpillThreads), (size_t)kBytes, s, g, a, sp);
     return hipGetLastError();
 }
 
