@@ -137,14 +137,24 @@ int windowed_plan(const hough_ctx *c, int waves, int groups, int groups_per_cu, 
 // with the most resident waves per CU (the most events fit, the rest spill); ties go to the
 // earlier candidate.
 int default_windowed_plan(hough_ctx *c) {
+    const int waves_opts[5] = {16, 8, 12, 6, 4};
+    hough::BatchPlan cand[5];
+    bool ok[5];
+    int tallest = 0;
+    for (int wi = 0; wi < 5; ++wi) {
+        ok[wi] = windowed_plan(c, waves_opts[wi], 1, 1, &cand[wi]) == 0;
+        if (ok[wi] && cand[wi].win > tallest) tallest = cand[wi].win;
+    }
+    // the most resident waves among the windows within one 32-row step of the tallest (a
+    // window only has to hold the rows an event's hits reach; on 1000 x 2000 bins 16 waves
+    // with 1,056 rows ran 0.72 ms per 1,000 events against 0.86 for 8 waves with 1,088),
+    // then the taller window
     int best = -1;
     hough::BatchPlan pick{};
-    const int waves_opts[5] = {16, 8, 12, 6, 4};
     for (int wi = 0; wi < 5; ++wi) {
-        hough::BatchPlan p;
-        if (windowed_plan(c, waves_opts[wi], 1, 1, &p) != 0) continue;
-        const int score = p.win * 64 + p.per_cu * p.waves;
-        if (score > best) { best = score; pick = p; }
+        if (!ok[wi] || cand[wi].win < tallest - 32) continue;
+        const int score = cand[wi].per_cu * cand[wi].waves * 65536 + cand[wi].win;
+        if (score > best) { best = score; pick = cand[wi]; }
     }
     if (best < 0) return HOUGH_EINVAL;
     if (hough::prepare_batch(&pick) < 1) return HOUGH_EDEVICE;
