@@ -304,6 +304,60 @@ def test_tall_grids_equal_the_oracle(H, orc, n_theta, n_rho, lo, hi, T):
     ctx.close()
 
 
+def _stacked_events(seed: int, sizes_at_least):
+    """Events made of whole paper-workload events stacked until each reaches its size (tracks
+    and noise, as many as fit), then one plain event and an empty one."""
+    ev = synth.make_events(synth.WORKLOADS["paper-1000ev-360x256"], seed, n_events=120)
+    xs, ys, sizes, e = [], [], [], 0
+    for need in sizes_at_least:
+        bx, by = [], []
+        while sum(a.size for a in bx) < need:
+            a, b = ev.event(e)
+            bx.append(a)
+            by.append(b)
+            e += 1
+        xs += bx
+        ys += by
+        sizes.append(sum(a.size for a in bx))
+    a, b = ev.event(e)
+    xs.append(a)
+    ys.append(b)
+    sizes += [a.size, 0]
+    off = np.zeros(len(sizes) + 1, np.uint32)
+    off[1:] = np.cumsum(sizes)
+    return np.concatenate(xs).astype(np.float32), np.concatenate(ys).astype(np.float32), off
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_spill_slabs_of_large_events_on_a_tall_grid(H, orc, periodic):
+    """The spill path's slabs in both forms and over several slabs per column: events above
+    65,535 hits (32-bit counts, 480 owned rows a slab) and between 32,768 and 65,535 (packed, 992
+    rows) on 130 x 1200 bins (three column groups, two or three slabs), beside a plain event and
+    an empty one; plain and theta-periodic grids, absolute and relative threshold, W = 2: every
+    event's peaks, count, status and keep bytes equal the oracle's."""
+    import torch
+    n_theta, n_rho, lo, hi, T, W, cap = 130, 1200, -1 / 200, 1 / 200, 40, 2, 8192
+    g = orc.Grid(n_theta, n_rho, lo, hi)
+    ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, W, cap, periodic=periodic)
+    x, y, off = _stacked_events(11, [65536, 32768])
+    E = off.size - 1
+    say(f"spill slabs periodic={periodic}: sizes {np.diff(off).tolist()}")
+    xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
+    for frac in (None, (1, 2)):
+        pk, npk, keep, st = ctx.run_batch(xt, yt, ot, frac=frac)
+        torch.cuda.synchronize()
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=T, rho_window=W, cap=cap, n_threads=8,
+                                                periodic=periodic, frac=frac)
+        assert np.array_equal(npk.cpu().numpy()[:E].astype(np.int64), n_ref), frac
+        assert np.array_equal(st.cpu().numpy()[:E], np.where(n_ref > cap, H.EV_PEAKS_TRUNCATED, 0)), frac
+        assert np.array_equal(keep.cpu().numpy()[:x.size], keep_ref), frac
+        p = pk.cpu().numpy()
+        for e in range(E):
+            m = int(min(n_ref[e], cap))
+            assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), (frac, e)
+    ctx.close()
+
+
 @pytest.mark.parametrize("flags", ["periodic", "dedup"])
 def test_tall_grid_periodic_and_dedup(H, orc, flags):
     import torch
