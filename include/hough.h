@@ -122,9 +122,10 @@ typedef struct hough_ctx hough_ctx;   /* opaque; owned by the library */
  * rounded once to float) and upload them, and allocate the workspace on the current device.
  * On success *out receives a new context.  Returns HOUGH_EINVAL for a bad grid or parameter
  * (including n_rho above hough_max_n_rho()), HOUGH_ENOMEM / HOUGH_EDEVICE on allocation or
- * copy failure.  The workspace includes the spill path's device-memory accumulators (see
- * hough_run_batch): a few events' worth, or for a grid taller than the fused kernel's tile one
- * event's worth per CU up to 2 GiB (fewer where the device has not that much free). */
+ * copy failure.  The workspace includes the spill path's per-event slices (peak counts, peak
+ * masks and places, dilated bits: about 4 bytes per grid cell; see hough_run_batch): a few
+ * events' worth, or for a grid taller than the fused kernel's tile one event's worth per CU up
+ * to 2 GiB (fewer where the device has not that much free). */
 int hough_config(const hough_params *p, hough_ctx **out);
 
 /* Release a context (waits for nothing: the caller must have finished its work on it). */
@@ -202,10 +203,11 @@ int hough_retain(hough_ctx *ctx, const float *x, const float *y, uint32_t n_hits
  * than the kernel has resident workgroups (and at most 65,536 events) is preceded by a small
  * launch that schedules the events largest first; no result depends on the schedule.
  * The fused kernel keeps an event's theta tile on chip, with 16-bit counts.  What it cannot
- * hold -- events above 32,767 hits, or every event of a grid whose rho column is taller than
- * its tile (hough_get_batch_plan then reports an all-zero shape) -- is computed by a spill
- * launch after it, one event per workgroup with the accumulator in device memory (Sec. II,
- * Sec. III), with the same results; on other grids that launch only scans the offsets. */
+ * hold -- events above 32,767 hits, events whose hits reach beyond a windowed tile, and every
+ * event of a theta-periodic grid whose rho column is taller than its tile (hough_get_batch_plan
+ * then reports an all-zero shape) -- is computed by a spill launch after it, one event per
+ * workgroup, its accumulator swept through on-chip rho slabs (Sec. II, Sec. III), with the
+ * same results; when the fused kernel leaves it nothing, that launch returns at once. */
 int hough_run_batch(hough_ctx *ctx, const float *x, const float *y, const uint32_t *offsets,
                     uint32_t n_events, hough_peak *peaks, uint32_t *n_peaks, uint8_t *keep,
                     uint32_t *status, void *stream);

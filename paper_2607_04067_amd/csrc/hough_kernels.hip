@@ -2077,21 +2077,23 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
     }
 }
 
-// ------------------------------------------------------------ spill path (device-memory accumulator)
-// Events whose accumulator the fused kernel cannot hold on chip: every event of a grid whose rho
-// column is taller than the fused kernel's LDS tile, and events above kMaxBatchHits hits on any
-// grid (counts beyond 16 bits).  One workgroup processes one event at a time in device memory,
-// as the paper's own accumulator lives there (Sec. II, Sec. III):
-//   - a 32-bit accumulator stored rho-major, acc[k * n_theta + j], so that the 64 columns a wave
-//     votes for one hit land in a few cache lines (neighbouring columns' bins differ little);
-//     votes are device-scope atomic adds;
-//   - the 3x3 test slides a 3 x 3 window down each lane's column (lane = column), once to count
-//     each column's peaks and once to list them at their raster-order position, marking the
-//     dilated retention bits D[w * n_theta + j] (bit b: a peak of column j within rho_window rows
-//     of row 32w + b) of its own column as it goes;
-//   - retention maps every hit again (lane = hit) and looks its bin up in D column by column.
-// The work is a full pass over the grid per step, so this path is for what the fused kernel
-// cannot take, not a fast path.
+// ------------------------------------------------------------ spill path (rho slabs)
+// Events whose accumulator the fused kernel cannot hold on chip: every event of a theta-periodic
+// grid whose rho column is taller than the fused kernel's LDS tile, events whose hits reach
+// beyond a windowed tile, every event of the split forms on such grids, and events above
+// kMaxBatchHits hits on any grid (counts beyond 16 bits).  One workgroup processes one event at
+// a time:
+//   - steps 1-4 one slab at a time in LDS (62 owned columns with halo lanes by up to 992 owned
+//     rows with halo rows; 32-bit counts and 480 rows for events above 65,535 hits): vote, then
+//     the 3x3 test of every owned cell, which leaves each (column, 32-row block) its peak rows
+//     as a bit mask and each peak's count in device memory; the accumulator stays on chip;
+//   - a thread per column places each block's peaks within its column, a scan over the columns
+//     gives raster order, and the listing pass writes the peaks and marks the dilated retention
+//     bits D[w * n_theta + j] (bit b: a peak of column j within rho_window rows of row 32w + b);
+//   - retention stages one 64-column group of D in LDS at a time and looks the event's hits up
+//     in it, lane = column.
+// Every (group, slab) maps all of the event's hits again, so this path is for what the fused
+// kernel cannot take, not a fast path.
 constexpr int kSpillWaves = 16;
 constexpr int kSpillThreads = kSpillWaves * 64;
 constexpr uint32_t kSpillBlock = 4;      // events per counter pop when only some events spill
