@@ -123,7 +123,7 @@ typedef struct hough_ctx hough_ctx;   /* opaque; owned by the library */
  * On success *out receives a new context.  Returns HOUGH_EINVAL for a bad grid or parameter
  * (including n_rho above hough_max_n_rho()), HOUGH_ENOMEM / HOUGH_EDEVICE on allocation or
  * copy failure.  The workspace includes the spill path's per-event slices (peak counts, peak
- * masks and places, dilated bits: about 4 bytes per grid cell; see hough_run_batch): a few
+ * masks and places, dilated bits: about 2.4 bytes per grid cell; see hough_run_batch): a few
  * events' worth, or for a grid taller than the fused kernel's tile one event's worth per CU up
  * to 2 GiB (fewer where the device has not that much free). */
 int hough_config(const hough_params *p, hough_ctx **out);

@@ -65,8 +65,8 @@ bool fused_fits(int n_rho, size_t limit) {
 
 // Spill-path workgroups: one per CU within a 2 GiB budget where every event may spill (each
 // takes its own event, so the workgroup count is the path's parallelism: 1000 x 2000 bins with
-// 8.8 MB per slice gets 245 workgroups), else a few for the rare events above the fused
-// kernel's hit limit.
+// 4.8 MB per slice get one per CU), else a few for the rare events above the fused kernel's hit
+// limit.
 constexpr size_t kSpillBudgetBytes = (size_t)2048 << 20;
 int spill_workgroups(size_t stride_words, int n_cu, bool all) {
     const size_t per = stride_words * 4;

@@ -108,7 +108,7 @@ bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *w
 // (n_theta * n_rho), dilated retention bits (ceil(n_rho / 32) * n_theta) and column positions
 // (n_theta + 1).
 struct SpillArgs {
-    uint32_t *acc;
+    uint32_t *work;      // one slice of `stride` words per workgroup (spill_stride)
     size_t stride;
     uint32_t *queue;     // [3], zero between launches: all = 1: work and exit counters; all = 0:
                          // the count of events left to it, the exit counter, the block counter

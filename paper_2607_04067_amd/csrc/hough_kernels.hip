@@ -2164,13 +2164,15 @@ __device__ void spill_vote_slab(uint32_t *tile, float2 *st, const float *x, cons
 }
 
 // Step 4 on rows [k0, k1) of slab lane l (owned column j): bit k - k0 of the result is set iff
-// cell (j, k) is a peak, and each peak's count is stored to acc for the listing pass.  Raster
+// cell (j, k) is a peak, and the i-th peak's count is stored to pc[i] for the listing pass (a
+// block holds at most 16 peaks: of two vertically adjacent cells the later one must exceed the
+// earlier, the earlier must not fall below the later, so not both are peaks).  Raster
 // order: the column before (j - 1) and the row above come first, except that on a periodic
 // grid the wrapped column left of column 0 comes later and the one right of the last column
 // earlier; rows outside the grid are the slab's zero halo rows.
 template <bool P>
 __device__ uint32_t spill_slab_peaks(const SpillSlab<P> &s, int l, int j, int k0, int k1, int base,
-                                     uint32_t thr, const GridArgs &g, uint32_t *acc) {
+                                     uint32_t thr, const GridArgs &g, uint32_t *pc) {
     const bool left_later = g.periodic && j == 0, right_earlier = g.periodic && j == g.n_theta - 1;
     int i = k0 - base;
     uint32_t l0 = s.count(l - 1, i - 1), c0 = s.count(l, i - 1), r0 = s.count(l + 1, i - 1);
@@ -2183,8 +2185,8 @@ __device__ uint32_t spill_slab_peaks(const SpillSlab<P> &s, int l, int j, int k0
             const uint32_t before = max(max(left_later ? 0u : lm, right_earlier ? rm : 0u), c0);
             const uint32_t after = max(max(left_later ? lm : 0u, right_earlier ? 0u : rm), c2);
             if (c1 >= max(before + 1u, after)) {
+                pc[__popc(m)] = c1;
                 m |= 1u << (k - k0);
-                acc[(size_t)k * g.n_theta + j] = c1;
             }
         }
         l0 = l1; l1 = l2;
@@ -2229,16 +2231,15 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
     __shared__ float2 stage[kSpillWaves][64];
     __shared__ uint32_t s_event, s_flags, s_max, s_n, s_list[kSpillThreads], s_part[kSpillThreads];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const size_t cells = (size_t)g.n_theta * (size_t)g.n_rho;
     const int words = (g.n_rho + 31) / 32;
-    uint32_t *acc = sp.acc + (size_t)blockIdx.x * sp.stride;
-    uint32_t *dil = acc + cells;                          // [words][n_theta]
+    uint32_t *dil = sp.work + (size_t)blockIdx.x * sp.stride;   // [words][n_theta]
     // Work items are (column, 32-row block) pairs, item it = block it / n_theta of column
     // it mod n_theta; the per-item arrays are stored in item order
     const int n_items = g.n_theta * words;
     uint32_t *pmask = dil + (size_t)words * g.n_theta;    // [n_items] each block's peak rows
     uint32_t *colpos = pmask + n_items;                   // [n_items] its first peak's place in its column
     uint32_t *colstart = colpos + n_items;                // [n_theta + 1] each column's first peak
+    uint32_t *pcount = colstart + g.n_theta + 1;          // [n_items][16] its peaks' counts
 
     // Every value that steers control flow around a barrier is wave-uniform (scalar), and an
     // event that is skipped passes a barrier before it returns, as a processed one does at its
@@ -2271,7 +2272,7 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
 
         // steps 1-4 on chip, one slab at a time: vote, then the 3x3 test of every owned cell,
         // giving each (column, 32-row block) item its peak rows as a bit mask (stored in item
-        // order: neighbouring threads take neighbouring columns) and each peak's count in acc.
+        // order: neighbouring threads take neighbouring columns) and its peaks' counts.
         // Only peak cells reach device memory (writing the whole accumulator out and walking it
         // there was three quarters of the path's time).  The relative threshold needs the
         // event's largest count first: one more round of votes.
@@ -2300,7 +2301,8 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
                 for (int t = threadIdx.x; t < nl * nb; t += kSpillThreads) {
                     const int bs = t / nl, l = 1 + (t - bs * nl), j = jo + l - 1;
                     const int k0 = ro + 32 * bs, k1 = min(k0 + 32, ro1);
-                    pmask[(k0 >> 5) * g.n_theta + j] = spill_slab_peaks<P>(sl, l, j, k0, k1, base, thr, g, acc);
+                    const int it = (k0 >> 5) * g.n_theta + j;
+                    pmask[it] = spill_slab_peaks<P>(sl, l, j, k0, k1, base, thr, g, pcount + (size_t)it * 16);
                 }
             });
         };
@@ -2352,10 +2354,13 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(GridArgs g, BatchArgs a
         for (int it = threadIdx.x; it < n_items; it += kSpillThreads) {
             const int b = it / g.n_theta, j = it - b * g.n_theta;
             uint32_t pos = colstart[j] + colpos[it];
+            const uint32_t *pc = pcount + (size_t)it * 16;
+            uint32_t r = 0;
             for (uint32_t m = pmask[it]; m; m &= m - 1u) {
                 const int k = 32 * b + (__ffs(m) - 1);
-                if (pos < cap) store_peak(pe + pos, (uint32_t)j, (uint32_t)k, spill_load(acc + (size_t)k * g.n_theta + j));
+                if (pos < cap) store_peak(pe + pos, (uint32_t)j, (uint32_t)k, spill_load(pc + r));
                 ++pos;
+                ++r;
                 const int lo = max(k - g.rho_window, 0), hi = min(k + g.rho_window, g.n_rho - 1);
                 for (int wd = lo >> 5; wd <= (hi >> 5); ++wd) {
                     const int b0 = max(lo, wd * 32) - wd * 32, b1 = min(hi, wd * 32 + 31) - wd * 32;
@@ -2682,9 +2687,10 @@ hipError_t launch_order(const uint32_t *offsets, uint32_t n_events, uint32_t *or
 
 size_t spill_stride(int n_theta, int n_rho) {
     const size_t words = (size_t)(n_rho + 31) / 32;
-    // accumulator, dilated words, per (column, 32-row block) a peak-row mask and the place of
-    // its first peak within the column, per column the place of its first peak (and the end)
-    const size_t n = (size_t)n_theta * n_rho + 3 * words * n_theta + n_theta + 1;
+    // dilated words, per (column, 32-row block) a peak-row mask and the place of its first peak
+    // within the column, per column the place of its first peak (and the end), per (column,
+    // block) the counts of its at most 16 peaks
+    const size_t n = 3 * words * n_theta + n_theta + 1 + 16 * words * n_theta;
     return (n + 63) & ~(size_t)63;                  // each workgroup's slice on a 256-byte boundary
 }
 
