@@ -80,7 +80,7 @@ WORKLOADS: dict[str, Workload] = {w.name: w for w in [
     Workload("paper-1000ev-1000x1000", 1000, (2, 8), (0.05, 1.5), (0.10, 0.10), 1000, 1000, "i32", 20,
              rho_min=-0.01, rho_max=0.01, salt=2),
     # the same events on a rho axis twice as fine (2000 rows: taller than a whole-column tile
-    # on chip, so windowed tiles, and the device-memory path on a theta-periodic grid); a bin
+    # on chip, so windowed tiles, and the spill path on a theta-periodic grid); a bin
     # half as tall collects fewer votes, and threshold 14 gives about the peak count (95 per
     # event) that 20 gives on the 1000-row grid (110)
     Workload("paper-1000ev-1000x2000", 1000, (2, 8), (0.05, 1.5), (0.10, 0.10), 1000, 2000, "i32", 14,

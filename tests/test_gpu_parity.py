@@ -216,8 +216,8 @@ ITERATIVE_MAX_HITS = 32767      # largest event of the iterative finder's batch 
 
 
 def test_large_events_in_batch(H, orc):
-    """Events up to the fused kernel's hit limit and beyond it (the spill path in device memory,
-    including counts beyond 16 bits) all equal the oracle, in one batch, plain and gathered."""
+    """Events up to the fused kernel's hit limit and beyond it (the spill path, including counts
+    beyond 16 bits) all equal the oracle, in one batch, plain and gathered."""
     import torch
     g = orc.Grid(360, 256, -1 / 200, 1 / 200)
     ctx = H.Context(360, 256, -1 / 200, 1 / 200, "i32", 40, 1, 4096)
@@ -249,7 +249,7 @@ def test_large_events_in_batch(H, orc):
 
 # grids whose rho column is taller than the fused kernel's LDS tile: the per-event path votes in
 # rho slabs; the batch path holds a window of the column per event (events whose hits reach
-# beyond it, and every event of the split form, run in device memory)
+# beyond it, and every event of the split form, run through the spill path)
 TALL_GRIDS = [(360, 2048, -1 / 200, 1 / 200, 10), (1000, 1500, -0.01, 0.01, 20), (97, 4099, -1 / 150, 1 / 150, 6)]
 
 
@@ -428,7 +428,7 @@ def _host_threads() -> int:
 def test_full_size_every_event(H, orc, name, periodic):
     """The whole workload in one launch, as the benchmark times it; every event's peak list, true
     count, status and keep bytes equal the oracle's (the oracle runs on all host cores).  The
-    2000-row grid runs windowed tiles, and with the theta-periodic test the device-memory path
+    2000-row grid runs windowed tiles, and with the theta-periodic test the spill path
     for every event."""
     import torch
     from bench import MAX_PEAKS
