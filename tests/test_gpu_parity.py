@@ -328,6 +328,42 @@ def _stacked_events(seed: int, sizes_at_least):
     return np.concatenate(xs).astype(np.float32), np.concatenate(ys).astype(np.float32), off
 
 
+@pytest.mark.parametrize("n_theta,n_rho,lo,hi,T,W", [(2, 1250, -1 / 200, 1 / 200, 3, 3),
+                                                     (63, 1300, -0.0048, 0.0048, 6, 1),
+                                                     (125, 2100, -1 / 195, 1 / 195, 5, 2)])
+def test_spill_slabs_on_narrow_periodic_grids(H, orc, n_theta, n_rho, lo, hi, T, W):
+    """Theta-periodic grids taller than a tile, so every event goes through the spill path's
+    slabs: with 2 columns (both halo lanes wrap onto the two owned ones), 63 (the wrapped right
+    halo falls in a second group of one owned column) and 125 (three groups, the last with one
+    owned column), the edge events, absolute and relative threshold (a periodic grid's rho
+    range is symmetric: the wrap reverses rho)."""
+    import torch
+    g = orc.Grid(n_theta, n_rho, lo, hi)
+    ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, W, 4096, periodic=True)
+    assert ctx.batch_plan["waves_per_group"] == 0
+    ev = synth.make_events(synth.WORKLOADS["paper-1000ev-360x256"], 9, n_events=4)
+    evs = [ev.event(e) for e in range(ev.n_events)] + _edge_events()
+    x = np.concatenate([a for a, _ in evs]).astype(np.float32)
+    y = np.concatenate([b for _, b in evs]).astype(np.float32)
+    off = np.zeros(len(evs) + 1, np.uint32)
+    off[1:] = np.cumsum([a.size for a, _ in evs])
+    E = len(evs)
+    say(f"narrow periodic {n_theta}x{n_rho}: {E} events, {x.size} hits")
+    xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
+    for frac in (None, (1, 3)):
+        pk, npk, keep, st = ctx.run_batch(xt, yt, ot, frac=frac)
+        torch.cuda.synchronize()
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=T, rho_window=W, cap=4096, periodic=True,
+                                                frac=frac)
+        assert np.array_equal(npk.cpu().numpy()[:E].astype(np.int64), n_ref), frac
+        assert np.array_equal(keep.cpu().numpy()[:x.size], keep_ref), frac
+        p = pk.cpu().numpy()
+        for e in range(E):
+            m = int(min(n_ref[e], 4096))
+            assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), (frac, e)
+    ctx.close()
+
+
 @pytest.mark.parametrize("periodic", [False, True])
 def test_spill_slabs_of_large_events_on_a_tall_grid(H, orc, periodic):
     """The spill path's slabs in both forms and over several slabs per column: events above
