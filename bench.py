@@ -401,6 +401,56 @@ def relative_threshold(H, ctx, xt, yt, ot, peaks, npk, keep, status, ev, stream,
             "R_s": round(float(k[lab >= 0].mean()), 4) if (lab >= 0).any() else None}
 
 
+SECONDARY_WORKLOADS = ["plain-16ev-180x128", "paper-1000ev-360x256", "dense-2000ev-720x512",
+                       "paper-1000ev-1000x1000"]
+
+
+def secondary(H, names, ceiling: dict, tune: bool, reps: int = 20) -> dict:
+    """The other configurations beside the headline, each on its own resident batch: the
+    launch shape autotuned on it (or the library default), then `reps` launches of
+    hough_run_batch timed with HIP events on the launch stream (mean), the LDS-atomic and
+    published-fp32 fractions as in the headline's roofline, and the profiled HBM traffic where
+    a summary for that workload and shape exists."""
+    import torch
+    lds_peak = ceiling["lane_updates_per_s"] / 1e9
+    out = {}
+    for name in names:
+        wl = synth.WORKLOADS[name]
+        ev = synth.make_events(wl, 0)
+        cap = MAX_PEAKS[name]
+        ctx = H.Context.for_workload(wl, max_peaks=cap)
+        xt, yt, ot = H.to_device(ev)
+        bufs = ctx.run_batch(xt, yt, ot)
+        if tune:
+            from paper_2607_04067_amd import autotune
+            autotune.tune(ctx, xt, yt, ot, bufs, mean_hits=ev.n_hits / max(ev.n_events, 1), cache=None)
+        stream = torch.cuda.current_stream()
+        for _ in range(3):
+            ctx.run_batch(xt, yt, ot, *bufs, stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            ctx.run_batch(xt, yt, ot, *bufs, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / reps
+        plan = ctx.batch_plan
+        gv = ev.n_hits * wl.n_theta / (ms / 1e3) / 1e9
+        prof = profiled_traffic(name, plan)
+        out[name] = {"events": ev.n_events, "hits": ev.n_hits, "plan": plan,
+                     "plan_source": "autotuned" if tune else "library default",
+                     "kernel_ms": round(ms, 4), "events_per_s": round(ev.n_events / (ms / 1e3), 1),
+                     "gvotes_per_s": round(gv, 1), "frac": round(gv / lds_peak, 4),
+                     "lds_atomic_frac": lds_atomic_rate(ev, plan, wl, ms, ceiling["lane_updates_per_s"])["frac"],
+                     "fp32_frac": round(gv * 1e9 * FLOPS_PER_VOTE / 1e12 / FP32_PEAK_TFLOPS, 4),
+                     "traffic": prof["traffic_bytes"] if prof else None,
+                     "peaks_per_event": round(float(bufs[1].float().mean().item()), 1)}
+        log(f"secondary {name}: {out[name]['kernel_ms']} ms, plan {plan}")
+        ctx.close()
+        del xt, yt, ot, bufs
+    return out
+
+
 def periodic_grid(H, wl, ev, xt, yt, ot, stream, reps: int = 10):
     """The fused path on the same grid with the theta-periodic 3x3 test (HOUGH_FLAG_THETA_PERIODIC):
     kernel time (HIP events, median), peaks and mask."""
@@ -719,6 +769,9 @@ def main(argv=None):
                     help="measured seconds of arrivals per served rate (after 1 s of warm-up)")
     ap.add_argument("--dedup", action="store_true",
                     help="suppress duplicate hits (HOUGH_FLAG_DEDUP: one more launch per step)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the other configurations' kernel times (the 16-event, 1,000-event, dense "
+                         "and paper-grid workloads)")
     ap.add_argument("--no-relative", action="store_true",
                     help="skip the relative-threshold and periodic-grid measurements (their launches share "
                          "the fused kernel's name)")
@@ -848,6 +901,9 @@ def main(argv=None):
         "paper_context": "paper: 1,000 simulated events in 0.14 s end to end (7,143 events/s) on an "
                          "RTX 5060 Ti with a 1000x1000 grid; different data, grid and GPU",
     }
+    if not args.no_secondary:
+        out["secondary"] = secondary(H, [w for w in SECONDARY_WORKLOADS if w != wl.name], ceiling,
+                                     tune=not args.no_tune)
     if not args.no_relative:
         out["relative_threshold"] = relative_threshold(H, ctx, xt, yt, ot, peaks, npk, keep, status, ev, stream)
         out["periodic_grid"] = periodic_grid(H, wl, ev, xt, yt, ot, stream)
