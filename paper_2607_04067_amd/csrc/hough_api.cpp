@@ -505,8 +505,8 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     a.queue = c->d_work;
     a.frac_num = frac_num;
     a.frac_den = frac_den;
-    // every event in device memory: no fused kernel for this grid, or the split form on a grid
-    // whose whole column does not fit it (the split form gives the same results)
+    // every event through the spill path: no fused kernel for this grid, or the split form on a
+    // grid whose whole column does not fit it (the split form gives the same results)
     const bool spill_all = !c->fused || (split && c->fused == 2);
     hough::SpillArgs spill{c->d_spill, c->spill_stride, c->d_work + 2, spill_all ? 1u : 0u};
     // otherwise the fused (or split) kernel counts the events it leaves to the spill kernel in
@@ -544,7 +544,8 @@ static int run_batch_common(hough_ctx *c, const float *x, const float *y, const 
     if (e == hipSuccess)
         e = split ? hough::launch_batch_split(c->g, plan, a, sp, (hipStream_t)stream)
                   : hough::launch_batch(c->g, plan, a, (hipStream_t)stream);
-    // events above the fused kernel's hit limit (flagged and skipped there), in device memory
+    // events above the fused kernel's hit limit or beyond its window (flagged and skipped there),
+    // through the spill path
     if (e == hipSuccess) e = hough::launch_spill(c->g, a, spill, c->spill_wgs, (hipStream_t)stream);
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
 }

@@ -101,12 +101,13 @@ size_t split_workspace_bytes(int n_theta, int n_rho, int groups, uint32_t n_even
 bool split_layout(int n_theta, int n_rho, int groups, uint32_t n_events, void *ws, size_t bytes,
                   SplitArgs *out);
 
-// Spill path of the batch entry points (k_spill): events processed one per workgroup with the
-// accumulator in device memory.  all = 1: every event (grids whose rho column does not fit the
-// fused kernel's tile); all = 0: only events above kMaxBatchHits (the fused and split kernels
-// flag and skip those).  Each workgroup owns `stride` 32-bit words of acc: its accumulator
-// (n_theta * n_rho), dilated retention bits (ceil(n_rho / 32) * n_theta) and column positions
-// (n_theta + 1).
+// Spill path of the batch entry points (k_spill): events processed one per workgroup, the
+// accumulator swept through rho slabs in LDS.  all = 1: every event (no fused kernel for the
+// grid, or the split form on a grid whose column does not fit its tile); all = 0: the events
+// the fused or split kernel flagged (kStatusSpill: above kMaxBatchHits hits, or beyond a
+// windowed tile) and skipped.  Each workgroup owns `stride` 32-bit words of `work`: dilated
+// retention bits (ceil(n_rho / 32) * n_theta), per (column, 32-row block) a peak-row mask and
+// a place, per column a first place (n_theta + 1), and per block 16 peak counts.
 struct SpillArgs {
     uint32_t *work;      // one slice of `stride` words per workgroup (spill_stride)
     size_t stride;
