@@ -2083,8 +2083,8 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
 // beyond a windowed tile, every event of the split forms on such grids, and events above
 // kMaxBatchHits hits on any grid (counts beyond 16 bits).  One workgroup processes one event at
 // a time:
-//   - steps 1-4 one slab at a time in LDS (62 owned columns with halo lanes by up to 992 owned
-//     rows with halo rows; 32-bit counts and 480 rows for events above 65,535 hits): vote, then
+//   - steps 1-4 one slab at a time in LDS (62 owned columns with halo lanes by up to 1,120 owned
+//     rows with halo rows; 32-bit counts and 544 rows for events above 65,535 hits): vote, then
 //     the 3x3 test of every owned cell, which leaves each (column, 32-row block) its peak rows
 //     as a bit mask and each peak's count in device memory; the accumulator stays on chip;
 //   - a thread per column places each block's peaks within its column, a scan over the columns
@@ -2097,9 +2097,12 @@ __global__ __launch_bounds__(NW * 64, G == 1 ? 6 : 4) void k_batch_split(GridArg
 constexpr int kSpillWaves = 16;
 constexpr int kSpillThreads = kSpillWaves * 64;
 constexpr uint32_t kSpillBlock = 4;      // events per counter pop when only some events spill
-constexpr int kSpillSlabDwords = 32768;  // the slab: 128 KB of dynamic LDS
-constexpr int kSpillOwnedPacked = 992;   // owned rows of a packed slab: 31 blocks + 2 halo rows <= 1,024
-constexpr int kSpillOwnedWide = 480;     // owned rows of a 32-bit slab: 15 blocks + 2 halo rows <= 512
+// the slab: 143 KB of dynamic LDS, what the CU's 160 KB leave beside the kernel's static LDS
+// (slabs of 1,024 rows split a 2,000-row column into three, 3.4 against 4.1 ms per 1,000
+// events on 1000 x 2000 bins)
+constexpr int kSpillSlabDwords = 36608;
+constexpr int kSpillOwnedPacked = 1120;  // owned rows of a packed slab: 35 blocks + 2 halo rows <= 1,144
+constexpr int kSpillOwnedWide = 544;     // owned rows of a 32-bit slab: 17 blocks + 2 halo rows <= 572
 
 // A word of the dilated bits (ORed by atomics in L2) or a peak's count in the accumulator,
 // read past the L1.
@@ -2151,6 +2154,7 @@ __device__ void spill_vote_slab(uint32_t *tile, float2 *st, const float *x, cons
         if (dup && live && (dup[i] & kKeepDuplicate)) live = false;
         int slot;
         const StageCount n = stage_values(st, xi, yi, live, g, bad, slot);
+#pragma unroll 4
         for (uint32_t h = 0; h < n.total; ++h) {
             const float2 p = st[h];
             const float t = __builtin_fmaf(p.x, cl.C[0], __builtin_fmaf(p.y, cl.S[0], cl.B[0]));
