@@ -69,3 +69,21 @@ def test_bench_flags_are_offered(flag, capsys):
         bench.main(["--help"])
     assert e.value.code == 0
     assert flag in capsys.readouterr().out
+
+
+def test_every_workload_has_a_peak_buffer_and_the_secondary_list_is_known():
+    import bench
+    from paper_2607_04067_amd import synth
+    assert set(bench.MAX_PEAKS) == set(synth.WORKLOADS)
+    assert bench.DEFAULT_WORKLOAD in synth.WORKLOADS
+    assert set(bench.SECONDARY_WORKLOADS) <= set(synth.WORKLOADS)
+    assert len(set(bench.SECONDARY_WORKLOADS)) == len(bench.SECONDARY_WORKLOADS)
+
+
+def test_profile_commands_leave_out_the_secondary_section():
+    """The other configurations launch the same kernels: a profiled command must skip them, or
+    their launches would mix into the summary's kernel statistics."""
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if "rocprofv3" in line and "bench.py" in line and "--phases" not in line:
+                assert "--no-secondary" in line, (path, line)
