@@ -365,6 +365,37 @@ def test_spill_slabs_on_narrow_periodic_grids(H, orc, n_theta, n_rho, lo, hi, T,
 
 
 @pytest.mark.parametrize("periodic", [False, True])
+def test_tall_grid_dedup_with_relative_threshold(H, orc, periodic):
+    """Duplicate suppression and the relative threshold together on a grid taller than a tile:
+    windowed tiles (plain) or the spill path's two rounds of slab votes (theta-periodic), both
+    skipping the later copies the duplicate pass marked."""
+    import torch
+    n_theta, n_rho, lo, hi, T, W = 150, 1400, -1 / 200, 1 / 200, 4, 1
+    g = orc.Grid(n_theta, n_rho, lo, hi)
+    ctx = H.Context(n_theta, n_rho, lo, hi, "i32", T, W, 4096, periodic=periodic, dedup=True)
+    ev = synth.make_events(synth.WORKLOADS["paper-1000ev-360x256"], 13, n_events=5)
+    evs = [ev.event(e) for e in range(ev.n_events)] + _edge_events()
+    x = np.concatenate([a for a, _ in evs]).astype(np.float32)
+    y = np.concatenate([b for _, b in evs]).astype(np.float32)
+    off = np.zeros(len(evs) + 1, np.uint32)
+    off[1:] = np.cumsum([a.size for a, _ in evs])
+    E = len(evs)
+    xt, yt, ot = _t(x), _t(y), _t(off.astype(np.int32))
+    for frac in (None, (1, 2)):
+        pk, npk, keep, st = ctx.run_batch(xt, yt, ot, frac=frac)
+        torch.cuda.synchronize()
+        pk_ref, n_ref, keep_ref = orc.run_batch(g, x, y, off, threshold=T, rho_window=W, cap=4096, periodic=periodic,
+                                                dedup=True, frac=frac)
+        assert np.array_equal(npk.cpu().numpy()[:E].astype(np.int64), n_ref), frac
+        assert np.array_equal(keep.cpu().numpy()[:x.size], keep_ref), frac
+        p = pk.cpu().numpy()
+        for e in range(E):
+            m = int(min(n_ref[e], 4096))
+            assert np.array_equal(H.decode_peaks(p[e], m), pk_ref[e, :m].astype(np.int64)), (frac, e)
+    ctx.close()
+
+
+@pytest.mark.parametrize("periodic", [False, True])
 def test_spill_slabs_of_large_events_on_a_tall_grid(H, orc, periodic):
     """The spill path's slabs in both forms and over several slabs per column: events above
     65,535 hits (32-bit counts, 480 owned rows a slab) and between 32,768 and 65,535 (packed, 992
